@@ -1,0 +1,169 @@
+"""Multigrid V-cycle with the additive Schwarz smoother (oracle).
+
+Follows Algorithm 1 of the paper (the recursive V-cycle MGV: exact solve on the
+coarsest level; nu1 pre-smoothing steps U <- U + S^{-1}(F - K U); restriction
+G = R (F - K U); coarse correction from Delta U = 0; prolongation
+U <- U + P Delta U; nu2 post-smoothing steps), the additive Schwarz smoother
+S^{-1} = eta sum_i E_i^T K_i^{-1} E_i (equation ASM), and the solution
+protocol of the numerical-results section (repeat V-cycles; additional cycles
+are additional calls).
+
+The coarsest-level solve uses the global zero-mean pressure multiplier of the
+paper's footnote: the bordered system [[K_0, e], [e^T, 0]] with e = [0; w_0].
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .spaces import Discretization
+from .assemble import assemble, load_vector, pressure_integrals
+from .refine import prolongation, galerkin
+from .patches import build_patches, local_inverses
+
+
+class Level:
+    def __init__(self, disc, K):
+        self.disc = disc
+        self.K = K
+        self.w = pressure_integrals(disc)
+        self.P = None        # prolongation from this level to the next finer one (None on the finest)
+        self.patches = None
+        self.groups = None
+        self.coarse_inv = None
+
+
+class Hierarchy:
+    """Levels 0 (coarsest) .. L-1 (finest); K on the finest level is
+    assembled, coarser ones are Galerkin products."""
+
+    def __init__(self, d, n_elem, k, n_levels, nu, sigma, advection=None):
+        assert n_elem % (2 ** (n_levels - 1)) == 0
+        self.d, self.k, self.L = d, k, n_levels
+        self.nu, self.sigma = nu, sigma
+        finest = Discretization(d, n_elem, k)
+        mats = assemble(finest, nu, sigma, advection)
+        levels = [Level(finest, mats["K"])]
+        self.A, self.B = mats["A"], mats["B"]
+        for _ in range(n_levels - 1):
+            fine = levels[0]
+            coarse_disc = Discretization(d, fine.disc.N // 2, k)
+            P = prolongation(coarse_disc, fine.disc)
+            Kc = galerkin(fine.K, P)
+            lv = Level(coarse_disc, Kc)
+            lv.P = P
+            levels.insert(0, lv)
+        self.levels = levels
+        for l, lv in enumerate(levels):
+            if l == 0:
+                n = lv.disc.n
+                e = np.concatenate([np.zeros(lv.disc.n_v), lv.w])
+                bord = np.zeros((n + 1, n + 1))
+                bord[:n, :n] = lv.K.toarray()
+                bord[:n, n] = e
+                bord[n, :n] = e
+                lv.coarse_inv = np.linalg.inv(bord)[:n, :n]
+            else:
+                lv.patches = build_patches(lv.disc)
+                lv.groups = local_inverses(lv.K, lv.patches, lv.w, lv.disc.n_v)
+
+    @property
+    def finest(self):
+        return self.levels[-1]
+
+
+def schwarz_correction(level, r):
+    """sum_i E_i^T M_i E_i r  (the sum in equation ASM, before eta)."""
+    out = np.zeros_like(r)
+    for ids, I, M in level.groups:
+        delta = np.einsum("mij,mj->mi", M, r[I])
+        out += np.bincount(I.ravel(), weights=delta.ravel(), minlength=r.size)
+    return out
+
+
+def smooth(level, U, F, eta):
+    """One additive Schwarz step U <- U + eta sum_i E_i^T K_i^{-1} E_i (F - K U)."""
+    r = F - level.K @ U
+    return U + eta * schwarz_correction(level, r)
+
+
+def mgv(h, l, U, F, nu1, nu2, eta):
+    """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l.
+    Returns the updated U (the paper updates U in place)."""
+    lv = h.levels[l]
+    if l == 0:
+        return lv.coarse_inv @ F
+    for _ in range(nu1):
+        U = smooth(lv, U, F, eta[l])
+    P = h.levels[l - 1].P
+    G = P.T @ (F - lv.K @ U)
+    dU = np.zeros(h.levels[l - 1].disc.n)
+    dU = mgv(h, l - 1, dU, G, nu1, nu2, eta)
+    U = U + P @ dU
+    for _ in range(nu2):
+        U = smooth(lv, U, F, eta[l])
+    return U
+
+
+# Fixed additive-Schwarz damping per (dimension, pressure degree k).  Read
+# literally (local zero-mean pressure, plain sum of equation ASM), the smoothed
+# operator S^{-1} K has its largest eigenvalues on pressure modes, because the
+# local pressure corrections of all subdomains holding a pressure function are
+# summed (4 subdomains in the 2D interior, 12 in 3D, up to 9 / 24 / 81 near the
+# boundary): about 4.94 (2D, k=1), 9.01 (2D, k=2), 24.1 (3D, k=1) and 80.0
+# (3D, k=2).  The paper's eta = 0.5 is then unstable, so the fixed damping is
+# taken below 2 / lambda_max, at the best value of a V(2,2) sweep.
+DEFAULT_ETA = {(2, 1): 0.35, (2, 2): 0.2, (3, 1): 0.07, (3, 2): 0.02}
+
+
+def default_eta(d, k):
+    return DEFAULT_ETA[(d, k)]
+
+
+def eta_levels(h, eta):
+    """Per-level damping array indexed by level (entry 0 unused)."""
+    if eta is None:
+        eta = default_eta(h.d, h.k)
+    if np.isscalar(eta):
+        return [float(eta)] * h.L
+    eta = list(eta)
+    assert len(eta) == h.L - 1, "one damping per smoothed level, finest first"
+    # given finest -> coarsest; level l = L-1 .. 1
+    out = [0.0] * h.L
+    for i, e in enumerate(eta):
+        out[h.L - 1 - i] = float(e)
+    return out
+
+
+def vcycles(h, U, F, m, nu1=2, nu2=2, eta=None):
+    et = eta_levels(h, eta)
+    for _ in range(m):
+        U = mgv(h, h.L - 1, U, F, nu1, nu2, et)
+    return U
+
+
+def residual_norm(h, U, F):
+    return float(np.linalg.norm(F - h.finest.K @ U))
+
+
+def normalize_pressure(h, U):
+    """p <- p - (w^T p) * 1, so that the discrete pressure has zero integral
+    (the basis is a partition of unity and |Omega| = 1)."""
+    lv = h.finest
+    U = U.copy()
+    nv = lv.disc.n_v
+    U[nv:] -= lv.w @ U[nv:]
+    return U
+
+
+def solve(h, F, tol=1e-8, U0=None, nu1=2, nu2=2, eta=None, max_cycles=200):
+    """Repeat V-cycles until ||F - K U||_2 <= tol ||F||_2 (starting residual
+    included), then normalize the pressure.  Returns (U, history)."""
+    U = np.zeros_like(F) if U0 is None else U0.copy()
+    et = eta_levels(h, eta)
+    fn = np.linalg.norm(F)
+    hist = [residual_norm(h, U, F)]
+    cycles = 0
+    while hist[-1] > tol * fn and cycles < max_cycles:
+        U = mgv(h, h.L - 1, U, F, nu1, nu2, et)
+        cycles += 1
+        hist.append(residual_norm(h, U, F))
+    return normalize_pressure(h, U), np.array(hist)

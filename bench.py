@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the divergence-conforming multigrid solver on one MI355X.
+
+Workload (synthetic, seeded): 2D generalized Stokes on the unit square,
+pressure degree k=2 (velocity S^{3,2} x S^{2,3}), 256x256 elements, 6 grids
+(256 .. 8), nu = 1, sigma in {1e-2, 1, 1e2, 1e4}, load vector of the
+manufactured solution u = curl(sin^2(pi x) sin^2(pi y)), p = sin(2 pi x)
+sin(2 pi y).  One step solves all four problems from U = 0 to relative
+residual 1e-8 with V(2,2) cycles; inputs are resident in HBM before timing.
+
+Prints one JSON line: metric, value (DOF/s over the whole step, DOFs =
+dim V_h + dim Q_h), roofline of the dominant kernel (finest-grid residual
+SpMV), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF/s solved to 1e-8 rel. residual; learned+FP32-refined vs plain FP64 GPU"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stokes2d_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1705_09282_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the finest residual kernel from the committed
+    rocprofv3 counter runs, or None if missing or taken on other kernel code."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(tol):
+    """The oracle as it stands, on one of the four problems (sigma = 1), one
+    full solve to tol from U = 0; setup excluded as for the GPU."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    import workloads
+    from oracle.multigrid import Hierarchy, solve
+    from oracle.assemble import load_vector
+    from oracle.manufactured import forcing
+    cfg = workloads.stokes2d(1.0)
+    with threadpool_limits(1):
+        h = Hierarchy(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"])
+        F = load_vector(h.finest.disc, forcing(cfg["d"], cfg["nu"], cfg["sigma"]))
+        t0 = time.perf_counter()
+        U, hist = solve(h, F, tol=tol)
+        dt = time.perf_counter() - t0
+    dofs = h.finest.disc.dofs()
+    return {"value": dofs / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": "sigma=1 problem only (1 of 4): one full FP64 oracle solve to 1e-8 from U=0, "
+                      "256x256, k=2, 6 grids, V(2,2), setup excluded, BLAS limited to 1 thread",
+            "seconds": dt, "cycles": len(hist) - 1}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-elem", type=int, default=256)
+    ap.add_argument("--levels", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
+              f"single device and has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_1705_09282_amd.dfmg import Solver
+
+    dev = torch.device("cuda:0")
+    probs = []
+    t_setup = time.perf_counter()
+    for sigma in workloads.STOKES2D_SIGMAS:
+        cfg = workloads.stokes2d(sigma, N=args.n_elem, L=args.levels)
+        s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"]).bind(dev)
+        F = torch.tensor(s.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        z = s.sizes()
+        probs.append((sigma, s, F, U, z))
+    setup_s = time.perf_counter() - t_setup
+    dofs = sum(z["n"] - 1 for *_, z in probs)
+    print(f"[bench] setup of {len(probs)} problems: {setup_s:.1f} s, DOFs/step {dofs}", file=sys.stderr, flush=True)
+
+    def step():
+        out = []
+        for sigma, s, F, U, z in probs:
+            U.zero_()
+            out.append(s.solve(F, U, tol=args.tol))
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        stats = step()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
+
+    cycles = [st["cycles"] for st in stats]
+    divs = [s.div_norm(U) for _, s, _, U, _ in probs]
+    value = args.steps * dofs / T
+
+    # roofline of the dominant kernel: finest-grid residual of the sigma = 1 problem
+    _, s1, F1, U1, z1 = probs[1]
+    r = torch.empty_like(F1)
+    ms = s1.time_residual(args.levels - 1, F1, U1, r, reps=200)
+    alg_bytes = 8 * z1["nnz"] + 3 * 8 * z1["n"]
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
+                        f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, V(2,2) additive Schwarz, "
+                        f"tol {args.tol:g}, U0=0",
+            "path": "plain FP64 V-cycles",
+            "dofs_per_step": dofs,
+            "cycles_per_sigma": cycles,
+            "vcycles_per_s": args.steps * sum(cycles) / T,
+            "div_norm_per_sigma": divs,
+            "setup_s": setup_s,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmv<2,2> (finest-grid residual r = F - K U)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.tol)
+    for _, s, _, _, _ in probs:
+        s.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

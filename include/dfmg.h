@@ -1,0 +1,191 @@
+/*
+ * dfmg -- divergence-free geometric multigrid for isogeometric compatible
+ * (divergence-conforming B-spline) discretizations of the generalized Stokes
+ * and Oseen problems on MI355X (gfx950).
+ *
+ * Method: Coley, Benzaken, Evans, "A geometric multigrid method for
+ * isogeometric compatible discretizations of the generalized Stokes and Oseen
+ * problems" (arXiv:1705.09282).  The problem statement (weak form with Nitsche
+ * no-slip and strong no-penetration, block system K U = F) is the paper's
+ * section on spatial discretization; the spaces are its compatible B-spline
+ * spaces; the solver is its Algorithm 1 (V-cycle) with the additive Schwarz
+ * smoother of equation ASM on subdomains that are supports of streamfunction
+ * (2D) / vector-potential (3D) basis functions.
+ *
+ * Conventions (all entry points):
+ *  - Return value 0 = success, negative = error (DFMG_E*).  The message of the
+ *    last error on the calling thread is returned by dfmg_last_error().
+ *    No C++ exception crosses this interface.
+ *  - "host" pointers are CPU memory owned by the caller; "device" pointers are
+ *    HIP device memory owned by the caller.  The library owns only its context
+ *    (host memory) and the internal HIP stream and graph it creates at bind.
+ *  - Vectors are FP64 in canonical DOF order [u_0 | u_1 (| u_2) | p]; inside a
+ *    block the tensor multi-index runs x fastest.  Velocity component c has
+ *    B-spline degree k+1 in direction c and k in the others, with the two end
+ *    functions in direction c removed (strong v.n = 0); the pressure block keeps
+ *    all (N+k)^d functions of degree k.  Level n_levels-1 is the finest grid.
+ *  - Device work is ordered on the stream given to dfmg_bind; calls that
+ *    return numbers to the host (solve, norms) synchronize that stream.
+ *  - A context is not thread-safe; different contexts are independent.
+ */
+#ifndef DFMG_H
+#define DFMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DFMG_OK 0
+#define DFMG_EINVAL (-1)   /* invalid argument or size */
+#define DFMG_ENOMEM (-2)   /* workspace too small / host allocation failed */
+#define DFMG_EHIP (-3)     /* HIP runtime error; message carries hipGetErrorString */
+#define DFMG_ENOTCONV (-4) /* max_cycles reached; U holds the last iterate */
+#define DFMG_EDIVERGED (-5)/* NaN/Inf or residual growth; U holds the last iterate */
+#define DFMG_ESTATE (-6)   /* call out of order (e.g. vcycle before bind) */
+
+typedef struct dfmg_ctx dfmg_ctx;
+
+/* Unit square (dim 2) or cube (dim 3) split into n_elem^dim equal elements on
+ * the finest grid; n_levels nested grids obtained by halving, so n_elem must be
+ * divisible by 2^(n_levels-1) (coarsest grid n_elem / 2^(n_levels-1) >= 1). */
+typedef struct {
+    int dim;
+    int n_elem;
+    int n_levels;
+} dfmg_grid;
+
+/* Advection field of the generalized Oseen problem (paper, weak form).
+ * kind 0: none (generalized Stokes).
+ * kind 1: 2D rigid rotation a = c * (-(y - 1/2), x - 1/2). */
+typedef struct {
+    int kind;
+    double c;
+} dfmg_advection;
+
+/* Solver options.  dfmg_default_options fills: nu1 = nu2 = 2, eta = 0 (use the
+ * stable fixed damping for (dim, k): 0.35 for 2D k=1, 0.2 for 2D k=2, 0.07 for
+ * 3D k=1, 0.02 for 3D k=2), precision 0, smoother 0, max_cycles 200,
+ * use_graph 1, cycles_per_check 1. */
+typedef struct {
+    int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
+    int nu2;              /* post-smoothing steps per level                     */
+    double eta;           /* fixed additive-Schwarz damping; <= 0: default      */
+    int precision;        /* 0: FP64 V-cycles                                   */
+    int smoother;         /* 0 auto, 1 gather (owner computes), 2 coloured scatter */
+    int max_cycles;       /* solve: cycle limit (ENOTCONV beyond)               */
+    int use_graph;        /* 1: replay the V-cycle as a captured hipGraph       */
+    int cycles_per_check; /* solve: V-cycles launched between host checks       */
+} dfmg_options;
+
+#define DFMG_MAX_HISTORY 512
+
+typedef struct {
+    int cycles;           /* V-cycles applied                                   */
+    int converged;        /* 1 if ||F - K U||_2 <= tol ||F||_2                  */
+    int status;           /* return code of the solve                           */
+    double res0;          /* ||F - K U_0||_2                                    */
+    double res_final;     /* residual norm at exit                              */
+    double rho;           /* (res_final / res0)^(1/cycles)                      */
+    double fnorm;         /* ||F||_2                                            */
+    double solve_seconds; /* wall time of the solve (host clock, stream synced) */
+    int n_history;
+    double history[DFMG_MAX_HISTORY]; /* residual norm at the start of each cycle */
+} dfmg_stats;
+
+void dfmg_default_options(dfmg_options *opt);
+
+/* Host-side setup of the whole hierarchy (section on nested complexes and
+ * Galerkin coarse operators K_l = R K_{l+1} P, subdomains of the Schwarz
+ * smoother, prefactored local saddle-point inverses, coarse-grid inverse).
+ * k in {1, 2} is the pressure degree (the paper's p = k + 1), nu > 0,
+ * sigma >= 0.  opt may be NULL (defaults).  On success *out owns host memory
+ * released by dfmg_destroy.  Errors: EINVAL. */
+int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma,
+               const dfmg_advection *adv, const dfmg_options *opt, dfmg_ctx **out);
+
+void dfmg_destroy(dfmg_ctx *ctx);
+
+/* Device bytes the caller must provide to dfmg_bind. */
+int dfmg_workspace_bytes(const dfmg_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory (>= dfmg_workspace_bytes, 256-byte aligned)
+ * and the caller's HIP stream (NULL = default stream); uploads the hierarchy
+ * and synchronizes.  The workspace must stay valid until dfmg_destroy.
+ * Errors: EINVAL, ENOMEM (too small), EHIP. */
+int dfmg_bind(dfmg_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Sizes of level `level` (0 = coarsest).  Any output pointer may be NULL.
+ * n_patch is 0 on level 0 (exact solve there).  nnz counts the non-zero
+ * entries of K_level. */
+int dfmg_sizes(const dfmg_ctx *ctx, int level, int64_t *n_vel, int64_t *n_pres,
+               int64_t *n_patch, int64_t *nnz);
+
+/* Set one damping per smoothed level, finest first (n = n_levels - 1 values in
+ * (0, 1)); replaces the fixed damping for later cycles. */
+int dfmg_set_eta(dfmg_ctx *ctx, const double *eta_host, int n);
+
+/* ncycles applications of Algorithm 1 on the finest level: U <- MGV(U, F).
+ * F_dev, U_dev: device, length n of the finest level; U is read and written.
+ * Stream-ordered, no host synchronization.  Errors: ESTATE, EINVAL, EHIP. */
+int dfmg_vcycle(dfmg_ctx *ctx, const double *F_dev, double *U_dev, int ncycles);
+
+/* Repeat V-cycles from U (device, in/out) until ||F - K U||_2 <= tol ||F||_2
+ * (numerical-results protocol, relative to ||F||), then shift the pressure to
+ * zero mean.  st may be NULL.  Errors: ENOTCONV, EDIVERGED, ESTATE, EHIP. */
+int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, dfmg_stats *st);
+
+/* ||F - K U||_2 on the finest level (device inputs, host output). */
+int dfmg_residual_norm(dfmg_ctx *ctx, const double *F_dev, const double *U_dev, double *out);
+
+/* ||div u_h||_{L2(Omega)} of the velocity part of U (lemma of the section on
+ * the Stokes complex: zero for an exactly divergence-free field). */
+int dfmg_div_norm(dfmg_ctx *ctx, const double *U_dev, double *out);
+
+/* ---- Level-wise kernels (device pointers), for parity checks of each step ----
+ * residual:  r = F - K_level U                       (Algorithm 1, residual)
+ * smooth:    nsteps x  U <- U + eta_l sum_i E_i^T M_i E_i (F - K_level U)
+ *            (equation ASM; M_i the bordered local inverse)
+ * restrict:  G = R_level r,   R_level = P_{level-1}^T   (level >= 1)
+ * prolong:   U += P_{level-1} dU                       (level >= 1)
+ * coarse:    dU = K_0^{-1} G with zero-mean pressure (bordered inverse) */
+int dfmg_level_residual(dfmg_ctx *ctx, int level, const double *F_dev, const double *U_dev, double *r_dev);
+int dfmg_level_smooth(dfmg_ctx *ctx, int level, const double *F_dev, double *U_dev, int nsteps);
+int dfmg_level_restrict(dfmg_ctx *ctx, int level, const double *r_dev, double *G_dev);
+int dfmg_level_prolong_add(dfmg_ctx *ctx, int level, const double *dU_dev, double *U_dev);
+int dfmg_coarse_solve(dfmg_ctx *ctx, const double *G_dev, double *dU_dev);
+
+/* Average duration in milliseconds of the residual kernel r = F - K_level U
+ * over `reps` back-to-back launches on the library's stream, timed with HIP
+ * events recorded on that stream (device inputs; synchronizes). */
+int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const double *U_dev, double *r_dev,
+                       int reps, double *ms_out);
+
+/* ---- Host exports for bit-exact index-map parity and value parity ----
+ * CSR of K_level (explicit zeros dropped): rowptr[n+1], col[nnz], val[nnz]. */
+int dfmg_export_matrix(const dfmg_ctx *ctx, int level, int64_t *rowptr, int32_t *col, double *val);
+/* Subdomains of level >= 1: ptr[n_patch+1], dofs[ptr[n_patch]] (ascending
+ * global DOF indices per subdomain), color[n_patch] (DOF-disjoint colours).
+ * dfmg_patch_total gives ptr[n_patch]. */
+int dfmg_patch_total(const dfmg_ctx *ctx, int level, int64_t *total);
+int dfmg_export_patches(const dfmg_ctx *ctx, int level, int64_t *ptr, int32_t *dofs, int32_t *color);
+/* Prolongation P_{level-1} (rows: level, cols: level-1) as CSR; nnz via
+ * dfmg_prolongation_nnz. */
+int dfmg_prolongation_nnz(const dfmg_ctx *ctx, int level, int64_t *nnz);
+int dfmg_export_prolongation(const dfmg_ctx *ctx, int level, int64_t *rowptr, int32_t *col, double *val);
+
+/* Load vector F = [l(N^v_i); 0] (host output, length n of the finest level) for
+ * the manufactured solution u = curl psi, psi = sin^2(pi x) sin^2(pi y) (2D) or
+ * psi = (g, 0, g), g = sin^2(pi x) sin^2(pi y) sin^2(pi z) (3D), with pressure
+ * prod_j sin(2 pi x_j), forcing f = sigma u - nu Lap u + grad p + (a . grad) u,
+ * by Gauss quadrature with k+3 points per direction per element. */
+int dfmg_manufactured_rhs(const dfmg_ctx *ctx, double *F_host);
+
+const char *dfmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFMG_H */

@@ -1,0 +1,831 @@
+// Host-side hierarchy construction.  See setup.hpp for the storage layout.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+#include <utility>
+
+namespace dfmg {
+
+// ---------------------------------------------------------------- B-splines
+
+std::vector<double> open_knots(int N, int q) {
+    std::vector<double> kn;
+    kn.reserve(N + 2 * q + 1);
+    for (int i = 0; i <= q; ++i) kn.push_back(0.0);
+    for (int e = 1; e < N; ++e) kn.push_back((double)e / N);
+    for (int i = 0; i <= q; ++i) kn.push_back(1.0);
+    return kn;
+}
+
+// Triangular evaluation of the Cox-de Boor recursion restricted to span s.
+void span_basis(const std::vector<double> &kn, int q, int s, double x, double *val, double *der) {
+    double cur[8], prev[8], lower[8];
+    cur[0] = 1.0;
+    for (int p = 1; p <= q; ++p) {
+        for (int m = 0; m < p; ++m) prev[m] = cur[m];  // degree p-1, functions s-p+1+m
+        if (p == q)
+            for (int m = 0; m < p; ++m) lower[m] = prev[m];
+        for (int m = 0; m <= p; ++m) {
+            const int i = s - p + m;
+            double v = 0.0;
+            if (m >= 1) {
+                const double d1 = kn[i + p] - kn[i];
+                if (d1 > 0) v += (x - kn[i]) / d1 * prev[m - 1];
+            }
+            if (m <= p - 1) {
+                const double d2 = kn[i + p + 1] - kn[i + 1];
+                if (d2 > 0) v += (kn[i + p + 1] - x) / d2 * prev[m];
+            }
+            cur[m] = v;
+        }
+    }
+    for (int m = 0; m <= q; ++m) val[m] = cur[m];
+    if (!der) return;
+    if (q == 0) {
+        der[0] = 0.0;
+        return;
+    }
+    for (int m = 0; m <= q; ++m) {
+        const int i = s - q + m;
+        double v = 0.0;
+        if (m >= 1) {
+            const double d1 = kn[i + q] - kn[i];
+            if (d1 > 0) v += q / d1 * lower[m - 1];
+        }
+        if (m <= q - 1) {
+            const double d2 = kn[i + q + 1] - kn[i + 1];
+            if (d2 > 0) v -= q / d2 * lower[m];
+        }
+        der[m] = v;
+    }
+}
+
+void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w) {
+    t.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double p0 = 1.0, p1 = z, dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            p0 = 1.0;
+            p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = (n == 1) ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        p0 = 1.0;
+        p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = (n == 1) ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+        t[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Sparse row: (column, value) pairs.
+using SRow = std::vector<std::pair<int, double>>;
+
+static SRow combine(double a, const SRow &x, double b, const SRow &y) {
+    SRow out;
+    size_t i = 0, j = 0;
+    while (i < x.size() || j < y.size()) {
+        if (j >= y.size() || (i < x.size() && x[i].first < y[j].first)) {
+            out.push_back({x[i].first, a * x[i].second});
+            ++i;
+        } else if (i >= x.size() || y[j].first < x[i].first) {
+            out.push_back({y[j].first, b * y[j].second});
+            ++j;
+        } else {
+            out.push_back({x[i].first, a * x[i].second + b * y[j].second});
+            ++i;
+            ++j;
+        }
+    }
+    return out;
+}
+
+// Boehm's algorithm: inserting knot t into span s (kn[s] <= t < kn[s+1]) maps
+// control points P to Q with Q_i = P_i (i <= s-q), Q_i = P_{i-1} (i > s) and
+// Q_i = a_i P_i + (1 - a_i) P_{i-1}, a_i = (t - kn[i]) / (kn[i+q] - kn[i]),
+// otherwise.  Composing the insertions of all midpoints gives the map A from
+// coarse to fine coefficients; the basis relation is its transpose.
+Mat1 refinement_matrix(int Nc, int q) {
+    std::vector<double> kn = open_knots(Nc, q);
+    const int nc = Nc + q;
+    std::vector<SRow> A(nc);
+    for (int i = 0; i < nc; ++i) A[i] = {{i, 1.0}};
+    for (int m = 0; m < Nc; ++m) {
+        const double t = (2.0 * m + 1.0) / (2.0 * Nc);
+        int s = q;
+        while (!(kn[s] <= t && t < kn[s + 1])) ++s;
+        const int n = (int)kn.size() - q - 1;
+        std::vector<SRow> B(n + 1);
+        for (int i = 0; i <= n; ++i) {
+            if (i <= s - q) {
+                B[i] = A[i];
+            } else if (i >= s + 1) {
+                B[i] = A[i - 1];
+            } else {
+                const double al = (t - kn[i]) / (kn[i + q] - kn[i]);
+                B[i] = combine(al, A[i], 1.0 - al, A[i - 1]);
+            }
+        }
+        A.swap(B);
+        kn.insert(kn.begin() + s + 1, t);
+    }
+    const int nf = 2 * Nc + q;
+    Mat1 T;
+    T.init(nc, nf);
+    for (int j = 0; j < nf; ++j)
+        for (auto &e : A[j])
+            if (std::fabs(e.second) > 1e-14) T(e.first, j) = e.second;
+    return T;
+}
+
+// Xc = Tr X Tc^T
+static Mat1 rap(const Mat1 &Tr, const Mat1 &X, const Mat1 &Tc) {
+    std::vector<SRow> rr(Tr.nr), rc(Tc.nr);
+    for (int i = 0; i < Tr.nr; ++i)
+        for (int a = 0; a < Tr.nc; ++a)
+            if (Tr(i, a) != 0.0) rr[i].push_back({a, Tr(i, a)});
+    for (int i = 0; i < Tc.nr; ++i)
+        for (int a = 0; a < Tc.nc; ++a)
+            if (Tc(i, a) != 0.0) rc[i].push_back({a, Tc(i, a)});
+    Mat1 Y;
+    Y.init(X.nr, Tc.nr);
+    for (int j = 0; j < Tc.nr; ++j)
+        for (auto &e : rc[j])
+            for (int a = 0; a < X.nr; ++a) {
+                const double x = X(a, e.first);
+                if (x != 0.0) Y(a, j) += x * e.second;
+            }
+    Mat1 Xc;
+    Xc.init(Tr.nr, Tc.nr);
+    for (int i = 0; i < Tr.nr; ++i)
+        for (auto &e : rr[i])
+            for (int j = 0; j < Tc.nr; ++j) {
+                const double y = Y(e.first, j);
+                if (y != 0.0) Xc(i, j) += e.second * y;
+            }
+    return Xc;
+}
+
+// ---------------------------------------------------------- 1D factor matrices
+
+static void fine_factors(const Problem &pb, Factors &F) {
+    const int N = pb.N, k = pb.k, nq = k + 3;
+    const double h = 1.0 / N, CI = 4.0 * k;
+    std::vector<double> t, wt;
+    gauss_legendre(nq, t, wt);
+    F.N = N;
+    double v[8], dv[8], v0[8];
+    for (int a = 0; a < 2; ++a) {
+        const int q = k + a, n = N + q;
+        const auto kn = open_knots(N, q);
+        F.mass[a].init(n, n);
+        F.stiff[a].init(n, n);
+        F.dcol[a].init(n, n);
+        F.xmass[a].init(n, n);
+        F.nit[a].init(n, n);
+        for (int e = 0; e < N; ++e)
+            for (int g = 0; g < nq; ++g) {
+                const double x = (e + 0.5 * (t[g] + 1.0)) * h, wq = 0.5 * h * wt[g];
+                span_basis(kn, q, e + q, x, v, dv);
+                for (int m1 = 0; m1 <= q; ++m1)
+                    for (int m2 = 0; m2 <= q; ++m2) {
+                        const int i = e + m1, j = e + m2;
+                        F.mass[a](i, j) += wq * v[m1] * v[m2];
+                        F.stiff[a](i, j) += wq * dv[m1] * dv[m2];
+                        F.dcol[a](i, j) += wq * v[m1] * dv[m2];
+                        F.xmass[a](i, j) += wq * (x - 0.5) * v[m1] * v[m2];
+                    }
+            }
+        // Nitsche boundary terms at both ends: -n (N_i N_j' + N_i' N_j) + C_I/h N_i N_j
+        for (int side = 0; side < 2; ++side) {
+            const double x = side, nrm = side ? 1.0 : -1.0;
+            const int s = side ? q + N - 1 : q;
+            span_basis(kn, q, s, x, v, dv);
+            for (int m1 = 0; m1 <= q; ++m1)
+                for (int m2 = 0; m2 <= q; ++m2)
+                    F.nit[a](s - q + m1, s - q + m2) +=
+                        -nrm * (v[m1] * dv[m2] + dv[m1] * v[m2]) + CI / h * v[m1] * v[m2];
+        }
+    }
+    const auto kn1 = open_knots(N, k + 1), kn0 = open_knots(N, k);
+    F.grad.init(N + k + 1, N + k);
+    for (int e = 0; e < N; ++e)
+        for (int g = 0; g < nq; ++g) {
+            const double x = (e + 0.5 * (t[g] + 1.0)) * h, wq = 0.5 * h * wt[g];
+            span_basis(kn1, k + 1, e + k + 1, x, v, dv);
+            span_basis(kn0, k, e + k, x, v0, nullptr);
+            for (int m1 = 0; m1 <= k + 1; ++m1)
+                for (int m2 = 0; m2 <= k; ++m2) F.grad(e + m1, e + m2) += wq * dv[m1] * v0[m2];
+        }
+}
+
+static void coarse_factors(const Factors &Ff, int k, Factors &Fc) {
+    const int Nc = Ff.N / 2;
+    Fc.N = Nc;
+    Mat1 T[2] = {refinement_matrix(Nc, k), refinement_matrix(Nc, k + 1)};
+    for (int a = 0; a < 2; ++a) {
+        Fc.mass[a] = rap(T[a], Ff.mass[a], T[a]);
+        Fc.stiff[a] = rap(T[a], Ff.stiff[a], T[a]);
+        Fc.dcol[a] = rap(T[a], Ff.dcol[a], T[a]);
+        Fc.xmass[a] = rap(T[a], Ff.xmass[a], T[a]);
+        Fc.nit[a] = rap(T[a], Ff.nit[a], T[a]);
+    }
+    Fc.grad = rap(T[1], Ff.grad, T[0]);
+}
+
+// ----------------------------------------------------------- operator terms
+
+struct FRef {
+    const Mat1 *m = nullptr;
+    bool tr = false;
+    double get(int i, int j) const { return tr ? (*m)(j, i) : (*m)(i, j); }
+};
+struct Term {
+    double coef;
+    FRef f[3];
+};
+
+static std::vector<Term> make_terms(const Problem &pb, const Factors &F, int R, int C) {
+    const int d = pb.d;
+    std::vector<Term> T;
+    auto idx = [&](int comp, int dir) { return (comp < d && dir == comp) ? 1 : 0; };
+    if (R < d && C == R) {
+        const int c = R;
+        Term t{pb.sigma, {}};
+        for (int j = 0; j < d; ++j) t.f[j] = {&F.mass[idx(c, j)], false};
+        T.push_back(t);
+        for (int e = 0; e < d; ++e) {
+            Term s{pb.nu, {}}, n{pb.nu, {}};
+            for (int j = 0; j < d; ++j) {
+                s.f[j] = {j == e ? &F.stiff[idx(c, j)] : &F.mass[idx(c, j)], false};
+                n.f[j] = {j == e ? &F.nit[idx(c, j)] : &F.mass[idx(c, j)], false};
+            }
+            T.push_back(s);
+            T.push_back(n);
+        }
+        if (pb.adv_kind == 1 && d == 2) {
+            // a = c (-(y - 1/2), x - 1/2):  (v_c, a_x d_x u_c) + (v_c, a_y d_y u_c)
+            Term ax{-pb.adv_c, {}}, ay{pb.adv_c, {}};
+            ax.f[0] = {&F.dcol[idx(c, 0)], false};
+            ax.f[1] = {&F.xmass[idx(c, 1)], false};
+            ay.f[0] = {&F.xmass[idx(c, 0)], false};
+            ay.f[1] = {&F.dcol[idx(c, 1)], false};
+            T.push_back(ax);
+            T.push_back(ay);
+        }
+    } else if (R < d && C == d) {
+        Term t{-1.0, {}};  // -B
+        for (int j = 0; j < d; ++j) t.f[j] = {j == R ? &F.grad : &F.mass[0], false};
+        T.push_back(t);
+    } else if (R == d && C < d) {
+        Term t{1.0, {}};  // B^T
+        for (int j = 0; j < d; ++j) t.f[j] = {j == C ? &F.grad : &F.mass[0], j == C};
+        T.push_back(t);
+    }
+    return T;
+}
+
+// ------------------------------------------------------------ level storage
+
+static void level_geometry(const Problem &pb, int N, HostLevel &L) {
+    const int d = pb.d, k = pb.k;
+    BlockGeom G{d, k};
+    L.N = N;
+    L.nblk = d + 1;
+    L.off[0] = 0;
+    for (int R = 0; R <= d; ++R) {
+        int64_t rows = 1;
+        for (int j = 0; j < 3; ++j) {
+            L.nb[R][j] = (j < d) ? N + k - G.s(R, j) : 1;
+            rows *= L.nb[R][j];
+        }
+        L.off[R + 1] = L.off[R] + rows;
+    }
+    L.n = L.off[d + 1];
+    L.n_v = L.off[d];
+    L.n_q = L.n - L.n_v;
+}
+
+static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
+    const int d = pb.d;
+    BlockGeom G{d, pb.k};
+    int64_t tot = 0;
+    for (int R = 0; R <= d; ++R) {
+        int ns = 0;
+        for (int C = 0; C <= d; ++C)
+            if (G.coupled(R, C)) {
+                int w = 1;
+                for (int j = 0; j < d; ++j) w *= G.width(R, C, j);
+                ns += w;
+            }
+        L.nslots[R] = ns;
+        L.val_off[R] = tot;
+        tot += (L.off[R + 1] - L.off[R]) * ns;
+    }
+    L.val_off[d + 1] = tot;
+    L.val.assign(tot, 0.0);
+    for (int R = 0; R <= d; ++R) {
+        const int64_t rows = L.off[R + 1] - L.off[R];
+        int slot0 = 0;
+        for (int C = 0; C <= d; ++C) {
+            if (!G.coupled(R, C)) continue;
+            const auto terms = make_terms(pb, F, R, C);
+            int W[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
+            for (int j = 0; j < d; ++j) {
+                W[j] = G.width(R, C, j);
+                lo[j] = G.lo(R, C, j);
+            }
+            for (int64_t li = 0; li < rows; ++li) {
+                int is[3];
+                int64_t t = li;
+                for (int j = 0; j < 3; ++j) {
+                    is[j] = (int)(t % L.nb[R][j]);
+                    t /= L.nb[R][j];
+                }
+                int slot = slot0;
+                for (int o2 = 0; o2 < W[2]; ++o2)
+                    for (int o1 = 0; o1 < W[1]; ++o1)
+                        for (int o0 = 0; o0 < W[0]; ++o0, ++slot) {
+                            const int o[3] = {o0, o1, o2};
+                            bool ok = true;
+                            int itrue[3], jtrue[3];
+                            for (int j = 0; j < d; ++j) {
+                                const int js = is[j] + lo[j] + o[j];
+                                if (js < 0 || js >= L.nb[C][j]) ok = false;
+                                itrue[j] = is[j] + G.s(R, j);
+                                jtrue[j] = js + G.s(C, j);
+                            }
+                            if (!ok) continue;
+                            double v = 0.0;
+                            for (auto &tm : terms) {
+                                double p = tm.coef;
+                                for (int j = 0; j < d; ++j) p *= tm.f[j].get(itrue[j], jtrue[j]);
+                                v += p;
+                            }
+                            L.val[L.val_off[R] + (int64_t)slot * rows + li] = v;
+                        }
+            }
+            int w = 1;
+            for (int j = 0; j < d; ++j) w *= W[j];
+            slot0 += w;
+        }
+    }
+}
+
+static int block_of(const HostLevel &L, int64_t g) {
+    int R = 0;
+    while (R + 1 < L.nblk && g >= L.off[R + 1]) ++R;
+    return R;
+}
+
+static double entry(const Problem &pb, const HostLevel &L, int64_t grow, int64_t gcol) {
+    const int d = pb.d;
+    BlockGeom G{d, pb.k};
+    const int R = block_of(L, grow), C = block_of(L, gcol);
+    if (!G.coupled(R, C)) return 0.0;
+    int64_t a = grow - L.off[R], b = gcol - L.off[C];
+    const int64_t rows = L.off[R + 1] - L.off[R];
+    int slot = 0;
+    for (int C2 = 0; C2 < C; ++C2)
+        if (G.coupled(R, C2)) {
+            int w = 1;
+            for (int j = 0; j < d; ++j) w *= G.width(R, C2, j);
+            slot += w;
+        }
+    int o[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    for (int j = 0; j < 3; ++j) {
+        const int is = (int)(a % L.nb[R][j]), js = (int)(b % L.nb[C][j]);
+        a /= L.nb[R][j];
+        b /= L.nb[C][j];
+        if (j < d) {
+            W[j] = G.width(R, C, j);
+            o[j] = js - is - G.lo(R, C, j);
+            if (o[j] < 0 || o[j] >= W[j]) return 0.0;
+        }
+    }
+    slot += (o[2] * W[1] + o[1]) * W[0] + o[0];
+    return L.val[L.val_off[R] + (int64_t)slot * rows + (grow - L.off[R])];
+}
+
+double level_entry(const Hierarchy &H, int level, int64_t grow, int64_t gcol) {
+    return entry(H.pb, H.lv[level], grow, gcol);
+}
+
+// ------------------------------------------------------------- dense solves
+
+// Inverse of an n x n matrix by Gaussian elimination with partial pivoting.
+static void invert(int n, std::vector<double> &A, std::vector<double> &Ainv) {
+    Ainv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + i] = 1.0;
+    double scale = 0.0;
+    for (double x : A) scale = std::max(scale, std::fabs(x));
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)p * n + c])) p = r;
+        if (std::fabs(A[(size_t)p * n + c]) <= 1e-13 * scale) throw std::runtime_error("singular local system");
+        if (p != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[(size_t)p * n + j], A[(size_t)c * n + j]);
+                std::swap(Ainv[(size_t)p * n + j], Ainv[(size_t)c * n + j]);
+            }
+        const double inv = 1.0 / A[(size_t)c * n + c];
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[(size_t)r * n + c] * inv;
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[(size_t)r * n + j] -= f * A[(size_t)c * n + j];
+                Ainv[(size_t)r * n + j] -= f * Ainv[(size_t)c * n + j];
+            }
+        }
+    }
+    for (int r = 0; r < n; ++r) {
+        const double inv = 1.0 / A[(size_t)r * n + r];
+        for (int j = 0; j < n; ++j) Ainv[(size_t)r * n + j] *= inv;
+    }
+}
+
+// Leading n x n block of inv([[K_sub, e], [e^T, 0]]).
+static void bordered_inverse(const Problem &pb, const HostLevel &L, const int32_t *dofs, int n, double *out) {
+    const int m = n + 1;
+    std::vector<double> A((size_t)m * m, 0.0), Ai;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) A[(size_t)a * m + b] = entry(pb, L, dofs[a], dofs[b]);
+    for (int a = 0; a < n; ++a) {
+        const double e = dofs[a] >= L.n_v ? L.w[dofs[a] - L.n_v] : 0.0;
+        A[(size_t)a * m + n] = e;
+        A[(size_t)n * m + a] = e;
+    }
+    invert(m, A, Ai);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) out[(size_t)a * n + b] = Ai[(size_t)a * m + b];
+}
+
+// ---------------------------------------------------------------- subdomains
+
+static void build_patches(const Problem &pb, HostLevel &L) {
+    const int d = pb.d, k = pb.k, N = L.N;
+    BlockGeom G{d, k};
+    // potential blocks: degree and true index range per direction
+    struct PB {
+        int q[3], lo[3], hi[3];
+    };
+    std::vector<PB> pots;
+    if (d == 2) {
+        PB p{};
+        for (int j = 0; j < 3; ++j) {
+            p.q[j] = (j < d) ? k + 1 : 0;
+            p.lo[j] = (j < d) ? 1 : 0;
+            p.hi[j] = (j < d) ? N + k : 1;
+        }
+        pots.push_back(p);
+    } else {
+        for (int o = 0; o < 3; ++o) {
+            PB p{};
+            for (int j = 0; j < 3; ++j) {
+                p.q[j] = (j == o) ? k : k + 1;
+                p.lo[j] = (j == o) ? 0 : 1;
+                p.hi[j] = (j == o) ? N + k : N + k;
+            }
+            pots.push_back(p);
+        }
+    }
+    L.pptr.assign(1, 0);
+    L.pdofs.clear();
+    L.color.clear();
+    for (int o = 0; o < (int)pots.size(); ++o) {
+        const PB &p = pots[o];
+        for (int a2 = p.lo[2]; a2 < p.hi[2]; ++a2)
+            for (int a1 = p.lo[1]; a1 < p.hi[1]; ++a1)
+                for (int a0 = p.lo[0]; a0 < p.hi[0]; ++a0) {
+                    const int a[3] = {a0, a1, a2};
+                    int e0[3] = {0, 0, 0}, e1[3] = {0, 0, 0};
+                    for (int j = 0; j < d; ++j) {
+                        e0[j] = std::max(0, a[j] - p.q[j]);
+                        e1[j] = std::min(N - 1, a[j]);
+                    }
+                    for (int b = 0; b <= d; ++b) {
+                        int r0[3] = {0, 0, 0}, r1[3] = {0, 0, 0};  // stored index range, inclusive
+                        bool empty = false;
+                        for (int j = 0; j < 3; ++j) {
+                            if (j >= d) continue;
+                            const int q = G.q(b, j), s = G.s(b, j);
+                            const int lo = s, hi = N + k + (q - k) - s;  // true kept range [lo, hi)
+                            int first = -1, last = -2;
+                            for (int i = std::max(lo, e0[j]); i < std::min(hi, e1[j] + q + 1); ++i) {
+                                const bool in = std::max(0, i - q) >= e0[j] && std::min(N - 1, i) <= e1[j];
+                                if (in) {
+                                    if (first < 0) first = i;
+                                    last = i;
+                                }
+                            }
+                            if (first < 0) {
+                                empty = true;
+                                break;
+                            }
+                            r0[j] = first - s;
+                            r1[j] = last - s;
+                        }
+                        if (empty) continue;
+                        for (int i2 = r0[2]; i2 <= r1[2]; ++i2)
+                            for (int i1 = r0[1]; i1 <= r1[1]; ++i1)
+                                for (int i0 = r0[0]; i0 <= r1[0]; ++i0)
+                                    L.pdofs.push_back((int32_t)(L.off[b] + i0 +
+                                                                (int64_t)L.nb[b][0] * (i1 + (int64_t)L.nb[b][1] * i2)));
+                    }
+                    L.pptr.push_back((int32_t)L.pdofs.size());
+                    int col = o;
+                    for (int j = 0; j < d; ++j) col = col * (k + 1) + a[j] % (k + 1);
+                    L.color.push_back(col);
+                }
+    }
+    L.n_patch = (int64_t)L.pptr.size() - 1;
+    // local inverses
+    L.moff.resize(L.n_patch);
+    int64_t tot = 0;
+    L.max_patch = 0;
+    for (int64_t i = 0; i < L.n_patch; ++i) {
+        const int n = L.pptr[i + 1] - L.pptr[i];
+        L.moff[i] = (int32_t)tot;
+        tot += (int64_t)n * n;
+        L.max_patch = std::max(L.max_patch, n);
+    }
+    if (tot > INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
+    if (L.max_patch > 1023) throw std::runtime_error("subdomain with more than 1023 DOFs");
+    if (L.n_patch >= (1 << 22)) throw std::runtime_error("more than 2^22 subdomains");
+    L.M.assign(tot, 0.0);
+    for (int64_t i = 0; i < L.n_patch; ++i) {
+        const int n = L.pptr[i + 1] - L.pptr[i];
+        bordered_inverse(pb, L, &L.pdofs[L.pptr[i]], n, &L.M[L.moff[i]]);
+    }
+    // inverse map: for each DOF the (patch, local row) pairs, patch ascending,
+    // packed as patch << 10 | row
+    L.inv_ptr.assign(L.n + 1, 0);
+    for (int32_t g : L.pdofs) L.inv_ptr[g + 1]++;
+    for (int64_t g = 0; g < L.n; ++g) L.inv_ptr[g + 1] += L.inv_ptr[g];
+    L.inv_ent.assign(L.pdofs.size(), 0);
+    std::vector<int32_t> fillp(L.inv_ptr.begin(), L.inv_ptr.end() - 1);
+    for (int64_t i = 0; i < L.n_patch; ++i)
+        for (int r = 0; r < L.pptr[i + 1] - L.pptr[i]; ++r) {
+            const int32_t g = L.pdofs[L.pptr[i] + r];
+            L.inv_ent[fillp[g]++] = (int32_t)((i << 10) | r);
+        }
+    // colour lists
+    int ncol = 0;
+    for (int c : L.color) ncol = std::max(ncol, c + 1);
+    L.col_ptr.assign(ncol + 1, 0);
+    for (int c : L.color) L.col_ptr[c + 1]++;
+    for (int c = 0; c < ncol; ++c) L.col_ptr[c + 1] += L.col_ptr[c];
+    L.col_list.assign(L.n_patch, 0);
+    std::vector<int32_t> fc(L.col_ptr.begin(), L.col_ptr.end() - 1);
+    for (int64_t i = 0; i < L.n_patch; ++i) L.col_list[fc[L.color[i]]++] = (int32_t)i;
+}
+
+// -------------------------------------------------------------- prolongation
+
+static void build_prolongation(const Problem &pb, const HostLevel &C, HostLevel &F) {
+    const int d = pb.d, k = pb.k;
+    BlockGeom G{d, k};
+    Mat1 T[2] = {refinement_matrix(C.N, k), refinement_matrix(C.N, k + 1)};
+    F.P_rp.assign(1, 0);
+    F.P_ci.clear();
+    F.P_v.clear();
+    for (int b = 0; b <= d; ++b) {
+        // per direction: for each fine stored index, list of (coarse stored index, value)
+        std::vector<std::vector<std::pair<int, double>>> lists[3];
+        for (int j = 0; j < 3; ++j) {
+            lists[j].resize(F.nb[b][j]);
+            if (j >= d) {
+                lists[j][0] = {{0, 1.0}};
+                continue;
+            }
+            const int q = G.q(b, j), s = G.s(b, j);
+            const Mat1 &Tq = T[q - k];
+            for (int is = 0; is < F.nb[b][j]; ++is)
+                for (int jc = 0; jc < C.nb[b][j]; ++jc) {
+                    const double v = Tq(jc + s, is + s);
+                    if (v != 0.0) lists[j][is].push_back({jc, v});
+                }
+        }
+        for (int i2 = 0; i2 < F.nb[b][2]; ++i2)
+            for (int i1 = 0; i1 < F.nb[b][1]; ++i1)
+                for (int i0 = 0; i0 < F.nb[b][0]; ++i0) {
+                    for (auto &z : lists[2][i2])
+                        for (auto &y : lists[1][i1])
+                            for (auto &x : lists[0][i0]) {
+                                F.P_ci.push_back((int32_t)(C.off[b] + x.first +
+                                                           (int64_t)C.nb[b][0] * (y.first + (int64_t)C.nb[b][1] * z.first)));
+                                F.P_v.push_back(x.second * y.second * z.second);
+                            }
+                    F.P_rp.push_back((int32_t)F.P_ci.size());
+                }
+    }
+    // transpose
+    F.R_rp.assign(C.n + 1, 0);
+    for (int32_t c : F.P_ci) F.R_rp[c + 1]++;
+    for (int64_t i = 0; i < C.n; ++i) F.R_rp[i + 1] += F.R_rp[i];
+    F.R_ci.assign(F.P_ci.size(), 0);
+    F.R_v.assign(F.P_ci.size(), 0.0);
+    std::vector<int32_t> fp(F.R_rp.begin(), F.R_rp.end() - 1);
+    for (int64_t r = 0; r < F.n; ++r)
+        for (int32_t e = F.P_rp[r]; e < F.P_rp[r + 1]; ++e) {
+            const int32_t c = F.P_ci[e];
+            F.R_ci[fp[c]] = (int32_t)r;
+            F.R_v[fp[c]] = F.P_v[e];
+            fp[c]++;
+        }
+}
+
+static void pressure_integrals(const Problem &pb, HostLevel &L) {
+    const int d = pb.d, k = pb.k;
+    const auto kn = open_knots(L.N, k);
+    const int n1 = L.N + k;
+    std::vector<double> w1(n1);
+    for (int j = 0; j < n1; ++j) w1[j] = (kn[j + k + 1] - kn[j]) / (k + 1);
+    L.w.assign(L.n_q, 0.0);
+    for (int64_t g = 0; g < L.n_q; ++g) {
+        int64_t t = g;
+        double v = 1.0;
+        for (int j = 0; j < d; ++j) {
+            v *= w1[t % n1];
+            t /= n1;
+        }
+        L.w[g] = v;
+    }
+}
+
+void build_hierarchy(const Problem &pb, Hierarchy &H) {
+    if (pb.d != 2 && pb.d != 3) throw std::runtime_error("dim must be 2 or 3");
+    if (pb.k != 1 && pb.k != 2) throw std::runtime_error("k must be 1 or 2");
+    if (pb.L < 1 || pb.N < 1) throw std::runtime_error("n_elem and n_levels must be positive");
+    if (pb.N % (1 << (pb.L - 1)) != 0) throw std::runtime_error("n_elem must be divisible by 2^(n_levels-1)");
+    if (!(pb.nu > 0.0) || !(pb.sigma >= 0.0)) throw std::runtime_error("need nu > 0 and sigma >= 0");
+    if (pb.adv_kind != 0 && !(pb.adv_kind == 1 && pb.d == 2)) throw std::runtime_error("advection kind 1 needs dim 2");
+    H.pb = pb;
+    const int L = pb.L;
+    H.fac.assign(L, Factors());
+    H.lv.assign(L, HostLevel());
+    fine_factors(pb, H.fac[L - 1]);
+    for (int l = L - 2; l >= 0; --l) coarse_factors(H.fac[l + 1], pb.k, H.fac[l]);
+    for (int l = 0; l < L; ++l) {
+        level_geometry(pb, H.fac[l].N, H.lv[l]);
+        fill_matrix(pb, H.fac[l], H.lv[l]);
+        pressure_integrals(pb, H.lv[l]);
+    }
+    for (int l = 1; l < L; ++l) {
+        build_patches(pb, H.lv[l]);
+        build_prolongation(pb, H.lv[l - 1], H.lv[l]);
+    }
+    {
+        HostLevel &C = H.lv[0];
+        const int n = (int)C.n;
+        std::vector<int32_t> all(n);
+        for (int i = 0; i < n; ++i) all[i] = i;
+        C.Kinv.assign((size_t)n * n, 0.0);
+        bordered_inverse(pb, C, all.data(), n, C.Kinv.data());
+    }
+    // divergence norm data (finest grid)
+    {
+        const int k = pb.k, q = k + 1;
+        const auto kn = open_knots(pb.N, q);
+        const int n = pb.N + q;
+        H.dcoef.assign(n, 0.0);
+        for (int j = 0; j < n; ++j) {
+            const double den = kn[j + q] - kn[j];
+            H.dcoef[j] = den > 0 ? q / den : 0.0;
+        }
+        const Mat1 &Mq = H.fac[L - 1].mass[0];
+        const int nq1 = pb.N + k, w = 2 * k + 1;
+        H.pmass.assign((size_t)nq1 * w, 0.0);
+        for (int i = 0; i < nq1; ++i)
+            for (int o = -k; o <= k; ++o)
+                if (i + o >= 0 && i + o < nq1) H.pmass[(size_t)i * w + o + k] = Mq(i, i + o);
+    }
+    const double table[2][2] = {{0.35, 0.2}, {0.07, 0.02}};
+    H.default_eta = table[pb.d - 2][pb.k - 1];
+}
+
+// ------------------------------------------------------- manufactured forcing
+
+static double sder(int n, double t) {
+    const double pi = M_PI;
+    switch (n) {
+        case 0: return std::sin(pi * t) * std::sin(pi * t);
+        case 1: return pi * std::sin(2 * pi * t);
+        case 2: return 2 * pi * pi * std::cos(2 * pi * t);
+        case 3: return -4 * pi * pi * pi * std::sin(2 * pi * t);
+    }
+    return 0.0;
+}
+
+// f = sigma u - nu Lap u + grad p + (a . grad) u at x for u = curl psi above.
+static void forcing(const Problem &pb, const double *x, double *f) {
+    const int d = pb.d;
+    const double pi = M_PI;
+    // velocity components as sums of c * prod_j s^{(n_j)}(x_j)
+    struct T {
+        double c;
+        int n[3];
+    };
+    std::vector<std::vector<T>> U;
+    if (d == 2) {
+        U = {{{1.0, {0, 1, 0}}}, {{-1.0, {1, 0, 0}}}};
+    } else {
+        U = {{{1.0, {0, 1, 0}}}, {{1.0, {0, 0, 1}}, {-1.0, {1, 0, 0}}}, {{-1.0, {0, 1, 0}}}};
+    }
+    auto ev = [&](const std::vector<T> &terms, int dj, int dn) {
+        double s = 0.0;
+        for (auto &t : terms) {
+            double p = t.c;
+            for (int j = 0; j < d; ++j) p *= sder(t.n[j] + (j == dj ? dn : 0), x[j]);
+            s += p;
+        }
+        return s;
+    };
+    double a[3] = {0, 0, 0};
+    if (pb.adv_kind == 1) {
+        a[0] = -pb.adv_c * (x[1] - 0.5);
+        a[1] = pb.adv_c * (x[0] - 0.5);
+    }
+    for (int c = 0; c < d; ++c) {
+        double lap = 0.0, adv = 0.0;
+        for (int j = 0; j < d; ++j) {
+            lap += ev(U[c], j, 2);
+            adv += a[j] * ev(U[c], j, 1);
+        }
+        double gp = 2 * pi;
+        for (int j = 0; j < d; ++j) gp *= (j == c) ? std::cos(2 * pi * x[j]) : std::sin(2 * pi * x[j]);
+        f[c] = pb.sigma * ev(U[c], -1, 0) - pb.nu * lap + gp + adv;
+    }
+}
+
+void manufactured_rhs(const Hierarchy &H, double *F) {
+    const Problem &pb = H.pb;
+    const HostLevel &L = H.lv[pb.L - 1];
+    const int d = pb.d, k = pb.k, N = pb.N, nq = k + 3;
+    BlockGeom G{d, k};
+    std::vector<double> t, wt;
+    gauss_legendre(nq, t, wt);
+    std::fill(F, F + L.n, 0.0);
+    const auto kn0 = open_knots(N, k), kn1 = open_knots(N, k + 1);
+    const double h = 1.0 / N;
+    const int E2 = d == 3 ? N : 1, G2 = d == 3 ? nq : 1;
+    double val[3][2][8];  // [dir][degree index][m]
+    for (int e2 = 0; e2 < E2; ++e2)
+        for (int e1 = 0; e1 < N; ++e1)
+            for (int e0 = 0; e0 < N; ++e0)
+                for (int g2 = 0; g2 < G2; ++g2)
+                    for (int g1 = 0; g1 < nq; ++g1)
+                        for (int g0 = 0; g0 < nq; ++g0) {
+                            const int e[3] = {e0, e1, e2}, g[3] = {g0, g1, g2};
+                            double x[3] = {0, 0, 0}, wq = 1.0;
+                            for (int j = 0; j < d; ++j) {
+                                x[j] = (e[j] + 0.5 * (t[g[j]] + 1.0)) * h;
+                                wq *= 0.5 * h * wt[g[j]];
+                                span_basis(kn0, k, e[j] + k, x[j], val[j][0], nullptr);
+                                span_basis(kn1, k + 1, e[j] + k + 1, x[j], val[j][1], nullptr);
+                            }
+                            double f[3];
+                            forcing(pb, x, f);
+                            for (int c = 0; c < d; ++c) {
+                                int qd[3] = {0, 0, 0};
+                                for (int j = 0; j < d; ++j) qd[j] = G.q(c, j) - k;
+                                const int m2max = d == 3 ? k + qd[2] : 0;
+                                for (int m2 = 0; m2 <= m2max; ++m2)
+                                    for (int m1 = 0; m1 <= k + qd[1]; ++m1)
+                                        for (int m0 = 0; m0 <= k + qd[0]; ++m0) {
+                                            const int m[3] = {m0, m1, m2};
+                                            int64_t idx = 0, stride = 1;
+                                            bool ok = true;
+                                            double phi = 1.0;
+                                            for (int j = 0; j < d; ++j) {
+                                                const int is = e[j] + m[j] - G.s(c, j);
+                                                if (is < 0 || is >= L.nb[c][j]) ok = false;
+                                                idx += is * stride;
+                                                stride *= L.nb[c][j];
+                                                phi *= val[j][qd[j]][m[j]];
+                                            }
+                                            if (ok) F[L.off[c] + idx] += wq * f[c] * phi;
+                                        }
+                            }
+                        }
+}
+
+}  // namespace dfmg

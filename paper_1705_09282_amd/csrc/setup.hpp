@@ -1,0 +1,112 @@
+// Host-side construction of the multigrid hierarchy for the divergence-
+// conforming B-spline discretization of generalized Stokes / Oseen problems
+// on the unit square or cube.
+//
+// The fine-grid operator is a sum of tensor products of 1D factor matrices
+// (mass, stiffness, first-derivative, (x - 1/2)-weighted mass, Nitsche
+// boundary terms, and the derivative coupling of degree k+1 and k splines), so
+// the Galerkin coarse operators K_l = R K_{l+1} P of the paper's nested
+// hierarchy are obtained exactly by applying the 1D refinement matrices to
+// every factor.  Matrices are stored in a "stencil ELL" layout: for each row
+// block (velocity component or pressure) and each coupled column block, every
+// row holds the full box of tensor offsets in which two B-splines can overlap,
+// values only (column indices follow from the offset), slot-major so that
+// consecutive rows are consecutive in memory.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dfmg {
+
+struct Mat1 {
+    int nr = 0, nc = 0;
+    std::vector<double> a;
+    void init(int r, int c) { nr = r; nc = c; a.assign((size_t)r * c, 0.0); }
+    double &operator()(int i, int j) { return a[(size_t)i * nc + j]; }
+    double operator()(int i, int j) const { return a[(size_t)i * nc + j]; }
+};
+
+// Open uniform knot vector of degree q on n elements of [0, 1].
+std::vector<double> open_knots(int n_elem, int q);
+
+// Values (and first derivatives) of the q+1 B-splines of degree q that are
+// non-zero on knot span s, at x; val[j] belongs to function s-q+j.
+void span_basis(const std::vector<double> &kn, int q, int s, double x, double *val, double *der);
+
+// Gauss-Legendre nodes and weights on [-1, 1].
+void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w);
+
+// Refinement matrix T (n_coarse x n_fine) by Boehm knot insertion of every
+// element midpoint: coarse N_i = sum_j T_ij fine N_j.
+Mat1 refinement_matrix(int n_coarse_elem, int q);
+
+// 1D factor matrices on one grid; index 0 = degree k, 1 = degree k+1.
+struct Factors {
+    int N = 0;
+    Mat1 mass[2], stiff[2], dcol[2], xmass[2], nit[2];
+    Mat1 grad;  // integral of (N^{k+1}_i)' N^k_j
+};
+
+struct Problem {
+    int d = 2, N = 0, L = 1, k = 1;
+    double nu = 1.0, sigma = 1.0;
+    int adv_kind = 0;
+    double adv_c = 0.0;
+};
+
+struct HostLevel {
+    int N = 0;
+    int nblk = 0;              // d + 1 blocks
+    int nb[4][3] = {};         // stored count per block per direction
+    int64_t off[5] = {};       // block offsets, off[nblk] = n
+    int64_t n = 0, n_v = 0, n_q = 0;
+    // stencil ELL: values of row block R at val[val_off[R] + slot * rows(R) + row]
+    std::vector<double> val;
+    int64_t val_off[5] = {};
+    int nslots[4] = {};
+    std::vector<double> w;     // pressure basis integrals
+    // subdomains (levels >= 1)
+    int64_t n_patch = 0;
+    std::vector<int32_t> pptr, pdofs, color, moff, inv_ptr, inv_ent;
+    std::vector<double> M;     // local inverses, row-major n_i x n_i at moff
+    std::vector<int32_t> col_ptr, col_list;
+    int max_patch = 0;
+    // prolongation from level-1 (CSR, rows = this level) and restriction
+    std::vector<int32_t> P_rp, P_ci, R_rp, R_ci;
+    std::vector<double> P_v, R_v;
+    // coarse level: leading n x n block of the bordered inverse
+    std::vector<double> Kinv;
+};
+
+struct Hierarchy {
+    Problem pb;
+    std::vector<Factors> fac;
+    std::vector<HostLevel> lv;
+    // divergence-norm data on the finest grid
+    std::vector<double> dcoef;     // derivative coefficients of degree k+1 splines
+    std::vector<double> pmass;     // 1D pressure mass band (n_q1 x (2k+1))
+    double default_eta = 0.2;
+};
+
+// Build everything.  Throws std::runtime_error on invalid input.
+void build_hierarchy(const Problem &pb, Hierarchy &H);
+
+// Stencil-ELL helpers shared by setup and export.
+struct BlockGeom {
+    int d, k;
+    int q(int R, int dir) const { return (R < d && dir == R) ? k + 1 : k; }
+    int s(int R, int dir) const { return (R < d && dir == R) ? 1 : 0; }
+    int lo(int R, int C, int dir) const { return s(R, dir) - s(C, dir) - q(R, dir); }
+    int width(int R, int C, int dir) const { return q(R, dir) + q(C, dir) + 1; }
+    bool coupled(int R, int C) const { return (R < d) ? (C == R || C == d) : (C < d); }
+};
+
+// Entry K(g_row, g_col) of a level (0 if outside the stored pattern).
+double level_entry(const Hierarchy &H, int level, int64_t grow, int64_t gcol);
+
+// Manufactured load vector on the finest grid.
+void manufactured_rhs(const Hierarchy &H, double *F);
+
+}  // namespace dfmg

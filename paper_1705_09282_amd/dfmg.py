@@ -1,0 +1,282 @@
+"""Python binding of libdfmg.so (the C-ABI declared in include/dfmg.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies device memory (the workspace, F and U) and the
+stream.  The library must have been built (``python -m
+paper_1705_09282_amd.build``); importing this module without it raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfmg.so")
+
+c_int, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_dblp = ctypes.POINTER(ctypes.c_double)
+
+MAX_HISTORY = 512
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EDIVERGED", -6: "ESTATE"}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n_elem", c_int), ("n_levels", c_int)]
+
+
+class Advection(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("c", c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", c_int), ("nu2", c_int), ("eta", c_double), ("precision", c_int),
+                ("smoother", c_int), ("max_cycles", c_int), ("use_graph", c_int),
+                ("cycles_per_check", c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("cycles", c_int), ("converged", c_int), ("status", c_int), ("res0", c_double),
+                ("res_final", c_double), ("rho", c_double), ("fnorm", c_double),
+                ("solve_seconds", c_double), ("n_history", c_int),
+                ("history", c_double * MAX_HISTORY)]
+
+    def as_dict(self):
+        return {"cycles": self.cycles, "converged": bool(self.converged), "status": self.status,
+                "res0": self.res0, "res_final": self.res_final, "rho": self.rho, "fnorm": self.fnorm,
+                "solve_seconds": self.solve_seconds,
+                "history": [self.history[i] for i in range(self.n_history)]}
+
+
+# (name, restype, argtypes) of every exported entry point
+SIGNATURES = [
+    ("dfmg_default_options", None, [ctypes.POINTER(Options)]),
+    ("dfmg_setup", c_int, [ctypes.POINTER(Grid), c_int, c_double, c_double, ctypes.POINTER(Advection),
+                           ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    ("dfmg_destroy", None, [c_void_p]),
+    ("dfmg_workspace_bytes", c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
+    ("dfmg_bind", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("dfmg_sizes", c_int, [c_void_p, c_int, c_i64p, c_i64p, c_i64p, c_i64p]),
+    ("dfmg_set_eta", c_int, [c_void_p, c_dblp, c_int]),
+    ("dfmg_vcycle", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("dfmg_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
+    ("dfmg_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
+    ("dfmg_div_norm", c_int, [c_void_p, c_void_p, c_dblp]),
+    ("dfmg_level_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    ("dfmg_level_smooth", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
+    ("dfmg_level_restrict", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    ("dfmg_level_prolong_add", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    ("dfmg_coarse_solve", c_int, [c_void_p, c_void_p, c_void_p]),
+    ("dfmg_time_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_dblp]),
+    ("dfmg_export_matrix", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
+    ("dfmg_patch_total", c_int, [c_void_p, c_int, c_i64p]),
+    ("dfmg_export_patches", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_i32p]),
+    ("dfmg_prolongation_nnz", c_int, [c_void_p, c_int, c_i64p]),
+    ("dfmg_export_prolongation", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
+    ("dfmg_manufactured_rhs", c_int, [c_void_p, c_dblp]),
+    ("dfmg_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_09282_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DfmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise DfmgError(code, lib().dfmg_last_error().decode())
+    return code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev(t, n):
+    """Device pointer of a contiguous FP64 torch tensor of n entries on the GPU."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+def default_options(**kw):
+    o = Options()
+    lib().dfmg_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """Hierarchy for one problem: unit square (dim 2) or cube (dim 3),
+    n_elem elements per direction on the finest of n_levels grids, pressure
+    degree k, viscosity nu, reaction sigma, rotation advection speed c."""
+
+    def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, **options):
+        self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
+        g = Grid(dim, n_elem, n_levels)
+        adv = Advection(1 if c != 0.0 else 0, c)
+        opt = default_options(**options)
+        ctx = c_void_p()
+        _check(lib().dfmg_setup(ctypes.byref(g), k, nu, sigma, ctypes.byref(adv), ctypes.byref(opt),
+                                ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._ws = None
+        self._sizes = {}
+
+    # ---------------------------------------------------------------- host
+    def sizes(self, level=None):
+        level = self.n_levels - 1 if level is None else level
+        if level in self._sizes:
+            return dict(self._sizes[level])
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().dfmg_sizes(self._ctx, level, *[ctypes.byref(x) for x in v]))
+        nv, nq, npatch, nnz = (x.value for x in v)
+        self._sizes[level] = {"n_vel": nv, "n_pres": nq, "n": nv + nq, "n_patch": npatch, "nnz": nnz}
+        return dict(self._sizes[level])
+
+    @property
+    def n(self):
+        return self.sizes()["n"]
+
+    def _nlev(self, level):
+        if not 0 <= level < self.n_levels:
+            raise ValueError("level out of range")
+        return self.sizes(level)["n"]
+
+    def export_matrix(self, level):
+        s = self.sizes(level)
+        rp = np.zeros(s["n"] + 1, np.int64)
+        col = np.zeros(s["nnz"], np.int32)
+        val = np.zeros(s["nnz"], np.float64)
+        _check(lib().dfmg_export_matrix(self._ctx, level, _ptr(rp, ctypes.c_int64), _ptr(col, ctypes.c_int32),
+                                        _ptr(val, ctypes.c_double)))
+        return rp, col, val
+
+    def export_patches(self, level):
+        s = self.sizes(level)
+        tot = ctypes.c_int64()
+        _check(lib().dfmg_patch_total(self._ctx, level, ctypes.byref(tot)))
+        ptr = np.zeros(s["n_patch"] + 1, np.int64)
+        dofs = np.zeros(tot.value, np.int32)
+        color = np.zeros(s["n_patch"], np.int32)
+        _check(lib().dfmg_export_patches(self._ctx, level, _ptr(ptr, ctypes.c_int64), _ptr(dofs, ctypes.c_int32),
+                                         _ptr(color, ctypes.c_int32)))
+        return ptr, dofs, color
+
+    def export_prolongation(self, level):
+        s = self.sizes(level)
+        nnz = ctypes.c_int64()
+        _check(lib().dfmg_prolongation_nnz(self._ctx, level, ctypes.byref(nnz)))
+        rp = np.zeros(s["n"] + 1, np.int64)
+        col = np.zeros(nnz.value, np.int32)
+        val = np.zeros(nnz.value, np.float64)
+        _check(lib().dfmg_export_prolongation(self._ctx, level, _ptr(rp, ctypes.c_int64),
+                                              _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double)))
+        return rp, col, val
+
+    def manufactured_rhs(self):
+        F = np.zeros(self.n, np.float64)
+        _check(lib().dfmg_manufactured_rhs(self._ctx, _ptr(F, ctypes.c_double)))
+        return F
+
+    def workspace_bytes(self):
+        b = c_size_t()
+        _check(lib().dfmg_workspace_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    # -------------------------------------------------------------- device
+    def bind(self, device="cuda"):
+        import torch
+        nbytes = self.workspace_bytes()
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        stream = torch.cuda.current_stream(self._ws.device).cuda_stream
+        _check(lib().dfmg_bind(self._ctx, c_void_p(aligned), nbytes, c_void_p(stream)))
+        return self
+
+    def set_eta(self, etas):
+        a = np.ascontiguousarray(etas, dtype=np.float64)
+        _check(lib().dfmg_set_eta(self._ctx, _ptr(a, ctypes.c_double), int(a.size)))
+
+    def vcycle(self, F, U, ncycles=1):
+        n = self.n
+        _check(lib().dfmg_vcycle(self._ctx, _dev(F, n), _dev(U, n), int(ncycles)))
+
+    def solve(self, F, U, tol=1e-8, raise_on_error=True):
+        st = Stats()
+        n = self.n
+        code = lib().dfmg_solve(self._ctx, _dev(F, n), _dev(U, n), float(tol), ctypes.byref(st))
+        if raise_on_error:
+            _check(code)
+        return st.as_dict()
+
+    def residual_norm(self, F, U):
+        out = c_double()
+        n = self.n
+        _check(lib().dfmg_residual_norm(self._ctx, _dev(F, n), _dev(U, n), ctypes.byref(out)))
+        return out.value
+
+    def div_norm(self, U):
+        out = c_double()
+        _check(lib().dfmg_div_norm(self._ctx, _dev(U, self.n), ctypes.byref(out)))
+        return out.value
+
+    def level_residual(self, level, F, U, r):
+        n = self._nlev(level)
+        _check(lib().dfmg_level_residual(self._ctx, level, _dev(F, n), _dev(U, n), _dev(r, n)))
+
+    def level_smooth(self, level, F, U, nsteps=1):
+        n = self._nlev(level)
+        _check(lib().dfmg_level_smooth(self._ctx, level, _dev(F, n), _dev(U, n), int(nsteps)))
+
+    def level_restrict(self, level, r, G):
+        _check(lib().dfmg_level_restrict(self._ctx, level, _dev(r, self._nlev(level)), _dev(G, self._nlev(level - 1))))
+
+    def level_prolong_add(self, level, dU, U):
+        _check(lib().dfmg_level_prolong_add(self._ctx, level, _dev(dU, self._nlev(level - 1)), _dev(U, self._nlev(level))))
+
+    def time_residual(self, level, F, U, r, reps=50):
+        out = c_double()
+        n = self._nlev(level)
+        _check(lib().dfmg_time_residual(self._ctx, level, _dev(F, n), _dev(U, n), _dev(r, n), int(reps), ctypes.byref(out)))
+        return out.value
+
+    def coarse_solve(self, G, dU):
+        n = self._nlev(0)
+        _check(lib().dfmg_coarse_solve(self._ctx, _dev(G, n), _dev(dU, n)))
+
+    def close(self):
+        if self._ctx:
+            lib().dfmg_destroy(self._ctx)
+            self._ctx = c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -117,7 +117,9 @@ def test_solve_matches_oracle(cfg):
     Ug = host(Ud)
     nv = h.finest.disc.n_v
     assert st["converged"] and st["cycles"] == len(hist) - 1
-    np.testing.assert_allclose(st["history"], hist, rtol=1e-9)
+    # residual norms: same values up to the rounding of two summation orders,
+    # ~1e-16 * ||F|| absolute, which dominates near the tolerance
+    np.testing.assert_allclose(st["history"], hist, rtol=1e-9, atol=1e-13 * hist[0])
     assert rel_l2(Ug[:nv], Uo[:nv]) < 1e-10
     assert rel_l2(Ug[nv:], Uo[nv:]) < 1e-9
     assert residual_norm(h, Ug, F) <= 1.0000001e-8 * np.linalg.norm(F)

@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF/s solved to 1e-8 rel. residual; learned+FP32-refined vs plain FP64 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stokes2d_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1705_09282_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1705_09282_amd", "csrc", "spmv.hip")
 
 
 def kernel_hash():
@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-elem", type=int, default=256)
     ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run a plain device copy of MB megabytes (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -87,11 +89,21 @@ def main():
     from paper_1705_09282_amd.dfmg import Solver
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {3} copies of {n * 8} bytes", file=sys.stderr, flush=True)
+        del src, dst
     probs = []
     t_setup = time.perf_counter()
     for sigma in workloads.STOKES2D_SIGMAS:
         cfg = workloads.stokes2d(sigma, N=args.n_elem, L=args.levels)
         s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"]).bind(dev)
+        tuning = s.autotune(reps=20)
         F = torch.tensor(s.manufactured_rhs(), device=dev)
         U = torch.zeros_like(F)
         z = s.sizes()
@@ -153,6 +165,7 @@ def main():
             "vcycles_per_s": args.steps * sum(cycles) / T,
             "div_norm_per_sigma": divs,
             "setup_s": setup_s,
+            "tuning_last_problem": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
         },
         "roofline": {
             "bound": "hbm",

@@ -68,7 +68,7 @@ typedef struct {
 /* Solver options.  dfmg_default_options fills: nu1 = nu2 = 2, eta = 0 (use the
  * stable fixed damping for (dim, k): 0.35 for 2D k=1, 0.2 for 2D k=2, 0.07 for
  * 3D k=1, 0.02 for 3D k=2), precision 0, smoother 0, max_cycles 200,
- * use_graph 1, cycles_per_check 1. */
+ * use_graph 1, cycles_per_check 1, share_inverses 1. */
 typedef struct {
     int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
     int nu2;              /* post-smoothing steps per level                     */
@@ -78,6 +78,8 @@ typedef struct {
     int max_cycles;       /* solve: cycle limit (ENOTCONV beyond)               */
     int use_graph;        /* 1: replay the V-cycle as a captured hipGraph       */
     int cycles_per_check; /* solve: V-cycles launched between host checks       */
+    int share_inverses;   /* 1: subdomains with equal local systems (to 1e-14)
+                             share one stored inverse; 0: one per subdomain     */
 } dfmg_options;
 
 #define DFMG_MAX_HISTORY 512
@@ -162,6 +164,22 @@ int dfmg_coarse_solve(dfmg_ctx *ctx, const double *G_dev, double *dU_dev);
  * events recorded on that stream (device inputs; synchronizes). */
 int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const double *U_dev, double *r_dev,
                        int reps, double *ms_out);
+
+/* ---- Kernel variants per level (the autotuner's search space) ----
+ * lpr[l]:      lanes of a wavefront per matrix row in the residual kernel of
+ *              level l (1, 2 or 4);
+ * smoother[l]: 1 = subdomain-parallel local solves + per-DOF gather of the
+ *              corrections, 2 = one launch per DOF-disjoint colour with plain
+ *              read-modify-write scatter (no atomics); ignored on level 0.
+ * Arrays have n_levels entries.  Results do not depend on lpr; the two
+ * smoother forms differ only in summation order. */
+int dfmg_get_tuning(const dfmg_ctx *ctx, int *lpr, int *smoother);
+int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
+/* Time every variant of every level on the device (reps launches each, HIP
+ * events on the library stream) and keep the fastest; ms_out (nullable,
+ * 2 * n_levels entries) receives the best residual and smoother times.
+ * Requires dfmg_bind.  Leaves the solver state unchanged. */
+int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
 
 /* ---- Host exports for bit-exact index-map parity and value parity ----
  * CSR of K_level (explicit zeros dropped): rowptr[n+1], col[nnz], val[nnz]. */

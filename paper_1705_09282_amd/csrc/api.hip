@@ -38,7 +38,9 @@ struct ArgError : std::runtime_error {
 struct DevLevel {
     double *val = nullptr;
     double *U = nullptr, *F = nullptr, *r = nullptr;
-    int32_t *pptr = nullptr, *pdofs = nullptr, *moff = nullptr, *inv_ptr = nullptr, *inv_ent = nullptr;
+    int32_t *pptr = nullptr, *pdofs = nullptr, *moff = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr;
+    int4 *ent_info = nullptr;
+    double *delta = nullptr;
     int32_t *col_list = nullptr;
     double *M = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
@@ -79,6 +81,7 @@ struct dfmg_ctx {
     hipGraphExec_t graph = nullptr;
     bool graph_norm = false;
     std::vector<int> smoother;  // per level: 1 gather, 2 colour
+    std::vector<int> lpr;       // per level: lanes per row of the residual kernel
     std::vector<double> eta_host;
 };
 
@@ -120,7 +123,7 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.F = A.take<double>(h.n);
         v.r = A.take<double>(h.n);
         nmax = std::max(nmax, h.n);
-        maxblocks = std::max(maxblocks, blocks_for(h.n));
+        maxblocks = std::max(maxblocks, spmv_blocks(h.n, 4));
         v.val = A.take<double>(h.val.size());
         if (l == 0) {
             v.Kinv = A.take<double>(h.Kinv.size());
@@ -130,7 +133,9 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.pdofs = A.take<int32_t>(h.pdofs.size());
         v.moff = A.take<int32_t>(h.moff.size());
         v.inv_ptr = A.take<int32_t>(h.inv_ptr.size());
-        v.inv_ent = A.take<int32_t>(h.inv_ent.size());
+        v.inv_pos = A.take<int32_t>(h.inv_pos.size());
+        v.ent_info = A.take<int4>(h.pdofs.size());
+        v.delta = A.take<double>(h.pdofs.size());
         v.col_list = A.take<int32_t>(h.col_list.size());
         v.M = A.take<double>(h.M.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
@@ -170,7 +175,7 @@ SpmvArgs spmv_args(dfmg_ctx *c, int l, const double *F, const double *U, double 
     for (int R = 0; R < 4; ++R)
         for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
     a.n = (int)h.n;
-    a.nblocks = blocks_for(h.n);
+    a.nblocks = spmv_blocks(h.n, c->lpr[l]);
     a.F = F;
     a.U = U;
     a.r = r;
@@ -179,8 +184,11 @@ SpmvArgs spmv_args(dfmg_ctx *c, int l, const double *F, const double *U, double 
     return a;
 }
 
-void spmv(dfmg_ctx *c, int l, const double *F, const double *U, double *r, double *partial, const int *stop) {
-    launch_spmv(c->H.pb.d, c->H.pb.k, spmv_args(c, l, F, U, r, partial, stop), c->s);
+// r = F - K_l U; returns the number of per-block partial sums written
+int spmv(dfmg_ctx *c, int l, const double *F, const double *U, double *r, double *partial, const int *stop) {
+    const SpmvArgs a = spmv_args(c, l, F, U, r, partial, stop);
+    launch_spmv(c->H.pb.d, c->H.pb.k, c->lpr[l], a, c->s);
+    return a.nblocks;
 }
 
 // eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l.
@@ -190,7 +198,10 @@ void schwarz(dfmg_ctx *c, int l, const double *r, double *U, bool assign, const 
     PatchArgs a{};
     a.n = (int)h.n;
     a.inv_ptr = v.inv_ptr;
-    a.inv_ent = v.inv_ent;
+    a.inv_pos = v.inv_pos;
+    a.ent_info = v.ent_info;
+    a.delta = v.delta;
+    a.nent = (int)h.pdofs.size();
     a.pptr = v.pptr;
     a.pdofs = v.pdofs;
     a.moff = v.moff;
@@ -234,9 +245,8 @@ void cycle_body(dfmg_ctx *c, bool norm) {
     if (L == 1) {
         DevLevel &v = c->dl[0];
         if (norm) {
-            spmv(c, 0, v.F, v.U, v.r, c->partial, stop);
-            launch_check(blocks_for(c->H.lv[0].n), c->partial, c->hist, c->counter, c->stop, c->thresh2,
-                         DFMG_MAX_HISTORY, c->s);
+            const int np = spmv(c, 0, v.F, v.U, v.r, c->partial, stop);
+            launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
         }
         coarse(c, v.F, v.r, stop);  // exact solve of K U = F
         launch_copy(c->H.lv[0].n, v.r, v.U, stop, c->s);
@@ -253,10 +263,9 @@ void cycle_body(dfmg_ctx *c, bool norm) {
                 zero = false;
                 continue;
             }
-            spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            const int np = spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
             if (first_res) {
-                launch_check(blocks_for(h.n), c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY,
-                             c->s);
+                launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
                 first_res = false;
             }
             schwarz(c, l, v.r, v.U, false, stop);
@@ -265,10 +274,9 @@ void cycle_body(dfmg_ctx *c, bool norm) {
             launch_fill(h.n, v.U, 0.0, stop, c->s);
             restrict_to(c, l, v.F, c->dl[l - 1].F, stop);
         } else {
-            spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            const int np = spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
             if (first_res)
-                launch_check(blocks_for(h.n), c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY,
-                             c->s);
+                launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
             restrict_to(c, l, v.r, c->dl[l - 1].F, stop);
         }
     }
@@ -340,6 +348,7 @@ void dfmg_default_options(dfmg_options *o) {
     o->max_cycles = 200;
     o->use_graph = 1;
     o->cycles_per_check = 1;
+    o->share_inverses = 1;
 }
 
 const char *dfmg_last_error(void) { return g_err.c_str(); }
@@ -369,6 +378,7 @@ int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma, const dfmg
         if (o.precision != 0) throw ArgError("precision must be 0");
         if (o.smoother < 0 || o.smoother > 2) throw ArgError("smoother must be 0, 1 or 2");
         if (o.eta >= 1.0) throw ArgError("eta must be < 1");
+        pb.share_inverses = o.share_inverses != 0;
         auto *c = new dfmg_ctx();
         try {
             build_hierarchy(pb, c->H);
@@ -381,6 +391,11 @@ int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma, const dfmg
         c->eta_host.assign(pb.L, eta0);
         c->eta_host[0] = 0.0;
         c->smoother.assign(pb.L, o.smoother == 2 ? 2 : 1);
+        c->lpr.assign(pb.L, 1);
+        for (int l = 0; l < pb.L; ++l) {
+            const int64_t n = c->H.lv[l].n;
+            c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
+        }
         *out = c;
     });
 }
@@ -437,7 +452,17 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.pdofs, h.pdofs, s);
             up(v.moff, h.moff, s);
             up(v.inv_ptr, h.inv_ptr, s);
-            up(v.inv_ent, h.inv_ent, s);
+            up(v.inv_pos, h.inv_pos, s);
+            {
+                std::vector<int4> info(h.pdofs.size());
+                for (int64_t p = 0; p < h.n_patch; ++p) {
+                    const int nn = h.pptr[p + 1] - h.pptr[p];
+                    for (int m = 0; m < nn; ++m)
+                        info[h.pptr[p] + m] = make_int4(h.moff[p] + m * nn, h.pptr[p], nn, 0);
+                }
+                up(v.ent_info, info, s);
+                HIPCHK(hipStreamSynchronize(s));  // info is a local host buffer
+            }
             up(v.col_list, h.col_list, s);
             up(v.M, h.M, s);
             up(v.P_rp, h.P_rp, s);
@@ -515,8 +540,7 @@ int dfmg_residual_norm(dfmg_ctx *c, const double *F, const double *U, double *ou
     return guarded([&] {
         enter(c);
         const int L = c->H.pb.L;
-        const int nb = blocks_for(c->H.lv[L - 1].n);
-        spmv(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
+        const int nb = spmv(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
         launch_reduce(nb, c->partial, c->scal, 1.0, c->s);
         *out = std::sqrt(read_scalar(c, c->scal));
         leave(c);
@@ -587,8 +611,8 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         }
         if (!stopv) {
             // limit reached: measure the residual of the last iterate
-            spmv(c, L - 1, v.F, v.U, v.r, c->partial, nullptr);
-            launch_check(nb, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
+            const int np = spmv(c, L - 1, v.F, v.U, v.r, c->partial, nullptr);
+            launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
             int hv[2];
             HIPCHK(hipMemcpyAsync(&hv[0], c->counter, sizeof(int), hipMemcpyDeviceToHost, c->s));
             HIPCHK(hipMemcpyAsync(&hv[1], c->stop, sizeof(int), hipMemcpyDeviceToHost, c->s));
@@ -697,6 +721,95 @@ int dfmg_coarse_solve(dfmg_ctx *c, const double *G, double *dU) {
     return guarded([&] {
         enter(c);
         coarse(c, G, dU, nullptr);
+        leave(c);
+    });
+}
+
+int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
+    if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
+    for (int l = 0; l < c->H.pb.L; ++l) {
+        lpr[l] = c->lpr[l];
+        smoother[l] = c->smoother[l];
+    }
+    return DFMG_OK;
+}
+
+int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
+    if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
+    for (int l = 0; l < c->H.pb.L; ++l)
+        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] == 1 || smoother[l] == 2))
+            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1 or 2");
+    return guarded([&] {
+        for (int l = 0; l < c->H.pb.L; ++l) {
+            c->lpr[l] = lpr[l];
+            c->smoother[l] = smoother[l];
+        }
+        if (c->graph) {
+            HIPCHK(hipGraphExecDestroy(c->graph));
+            c->graph = nullptr;
+        }
+    });
+}
+
+int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
+    if (!c || reps < 1) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        enter(c);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto timed = [&](auto &&fn) {
+            fn();  // warm
+            HIPCHK(hipEventRecord(e0, c->s));
+            for (int i = 0; i < reps; ++i) fn();
+            HIPCHK(hipEventRecord(e1, c->s));
+            HIPCHK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, e0, e1));
+            return (double)t / reps;
+        };
+        const int L = c->H.pb.L;
+        for (int l = 0; l < L; ++l) {
+            DevLevel &v = c->dl[l];
+            double best = 1e30;
+            int bl = c->lpr[l];
+            for (int lp : {1, 2, 4}) {
+                c->lpr[l] = lp;
+                const double t = timed([&] { spmv(c, l, v.F, v.U, v.r, nullptr, nullptr); });
+                if (t < best) {
+                    best = t;
+                    bl = lp;
+                }
+            }
+            c->lpr[l] = bl;
+            if (ms_out) ms_out[2 * l] = best;
+            if (l == 0) {
+                if (ms_out) ms_out[1] = 0.0;
+                continue;
+            }
+            double bests = 1e30;
+            int bs = c->smoother[l];
+            for (int sm : {1, 2}) {
+                c->smoother[l] = sm;
+                const double t = timed([&] { schwarz(c, l, v.r, v.U, false, nullptr); });
+                if (t < bests) {
+                    bests = t;
+                    bs = sm;
+                }
+            }
+            c->smoother[l] = bs;
+            if (ms_out) ms_out[2 * l + 1] = bests;
+            // the timing runs added corrections to U_l: restore the state the
+            // cycle expects (internal U is reloaded or reset by every cycle)
+            launch_fill(c->H.lv[l].n, v.U, 0.0, nullptr, c->s);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (c->graph) {
+            HIPCHK(hipGraphExecDestroy(c->graph));
+            c->graph = nullptr;
+        }
+        HIPCHK(hipStreamSynchronize(c->s));
         leave(c);
     });
 }

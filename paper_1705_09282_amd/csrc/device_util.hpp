@@ -1,0 +1,35 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace dfmg {
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2.  Remapping the hardware block id so that each XCD works
+// on one contiguous eighth of the rows keeps neighbouring rows (which share
+// most of the vector entries a stencil row reads) in the same L2.
+__device__ __forceinline__ int xcd_block(int hw, int grid) {
+    const int per = grid >> 3;  // grid is a multiple of 8
+    return (hw & 7) * per + (hw >> 3);
+}
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// Sum over the block (wave shuffles, then the waves in a fixed order); the
+// result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+}  // namespace dfmg

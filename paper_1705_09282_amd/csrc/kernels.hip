@@ -1,157 +1,69 @@
 // HIP kernels of the additive-Schwarz V-cycle (gfx950, wave64).
-#include "kernels.hpp"
+#include "device_util.hpp"
 
 namespace dfmg {
 
-// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
-// with a private L2.  Remapping the hardware block id so that each XCD works
-// on one contiguous eighth of the rows keeps neighbouring rows (which share
-// most of the vector entries a stencil row reads) in the same L2.
-__device__ __forceinline__ int xcd_block(int hw, int grid) {
-    const int per = grid >> 3;  // grid is a multiple of 8
-    return (hw & 7) * per + (hw >> 3);
-}
-
-template <int D, int K>
-struct Geo {
-    __host__ __device__ static constexpr int q(int R, int dir) { return (R < D && dir == R) ? K + 1 : K; }
-    __host__ __device__ static constexpr int s(int R, int dir) { return (R < D && dir == R) ? 1 : 0; }
-    __host__ __device__ static constexpr int lo(int R, int C, int dir) {
-        return dir < D ? s(R, dir) - s(C, dir) - q(R, dir) : 0;
-    }
-    __host__ __device__ static constexpr int w(int R, int C, int dir) {
-        return dir < D ? q(R, dir) + q(C, dir) + 1 : 1;
-    }
-};
-
-__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
-
-// Contribution of column block C to row (i0, i1, i2) of row block R.  Slots
-// outside the grid hold 0 and read a clamped (valid) vector entry.
-template <int D, int K, int R, int C>
-__device__ __forceinline__ double block_dot(const SpmvArgs &a, int i0, int i1, int i2, const double *&vp,
-                                            int64_t stride) {
-    using G = Geo<D, K>;
-    constexpr int W0 = G::w(R, C, 0), W1 = G::w(R, C, 1), W2 = G::w(R, C, 2);
-    constexpr int L0 = G::lo(R, C, 0), L1 = G::lo(R, C, 1), L2 = G::lo(R, C, 2);
-    const double *Uc = a.U + a.off[C];
-    const int n0 = a.nb[C][0], n1 = a.nb[C][1], n2 = a.nb[C][2];
-    double acc = 0.0;
-#pragma unroll
-    for (int o2 = 0; o2 < W2; ++o2) {
-        const int j2 = (D == 3) ? clampi(i2 + L2 + o2, 0, n2 - 1) : 0;
-#pragma unroll
-        for (int o1 = 0; o1 < W1; ++o1) {
-            const int j1 = clampi(i1 + L1 + o1, 0, n1 - 1);
-            const double *urow = Uc + ((int64_t)j2 * n1 + j1) * n0;
-#pragma unroll
-            for (int o0 = 0; o0 < W0; ++o0) {
-                const int j0 = clampi(i0 + L0 + o0, 0, n0 - 1);
-                acc = fma(*vp, urow[j0], acc);
-                vp += stride;
-            }
-        }
-    }
-    return acc;
-}
-
-template <int D, int K, int R>
-__device__ __forceinline__ double row_dot(const SpmvArgs &a, int li) {
-    const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
-    const int i0 = li % nb0;
-    const int t = li / nb0;
-    const int i1 = t % nb1;
-    const int i2 = t / nb1;
-    const int64_t stride = a.off[R + 1] - a.off[R];
-    const double *vp = a.val + a.val_off[R] + li;
-    double acc;
-    if constexpr (R < D) {
-        acc = block_dot<D, K, R, R>(a, i0, i1, i2, vp, stride);
-        acc += block_dot<D, K, R, D>(a, i0, i1, i2, vp, stride);
-    } else {
-        acc = block_dot<D, K, R, 0>(a, i0, i1, i2, vp, stride);
-        acc += block_dot<D, K, R, 1>(a, i0, i1, i2, vp, stride);
-        if constexpr (D == 3) acc += block_dot<D, K, R, 2>(a, i0, i1, i2, vp, stride);
-    }
-    return acc;
-}
-
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    // wave reduction then across the 4 waves, fixed order
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) sh[wv] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
-    return s;
-}
-
-// r = F - K U, optionally with per-block partial sums of r^2.
-template <int D, int K>
-__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
-    if (a.stop && *a.stop) return;
+// Additive Schwarz, step 1: local solves.  Thread t owns entry t of the
+// subdomain-major correction buffer, i.e. local row m of subdomain p with
+// t = pptr[p] + m, and computes delta_t = (M_p E_p r)_m.
+__global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgs a) {
+    const int halt = a.stop ? *a.stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int g = b * kBlock + threadIdx.x;
-    double rr = 0.0;
-    if (b < a.nblocks && g < a.n) {
-        double acc;
-        if (g < a.off[1]) {
-            acc = row_dot<D, K, 0>(a, g);
-        } else if (g < a.off[2]) {
-            acc = row_dot<D, K, 1>(a, g - (int)a.off[1]);
-        } else if (D == 3 && g < a.off[3]) {
-            acc = row_dot<D, K, (D == 3 ? 2 : 1)>(a, g - (int)a.off[2]);
-        } else {
-            acc = row_dot<D, K, D>(a, g - (int)a.off[D]);
+    const int t = b * kBlock + threadIdx.x;
+    if (t >= a.nent) return;
+    // descriptor of entry t: offset of its row of M, first entry of its
+    // subdomain, subdomain size
+    const int4 info = a.ent_info[t];
+    const double *m = a.M + info.x;
+    const int32_t *dofs = a.pdofs + info.y;
+    const int nn = info.z;
+    // chunks of 8 independent gathers; the tail is padded with zero
+    // coefficients on a valid index, which leaves the sum unchanged
+    double acc = 0.0;
+    for (int c = 0; c < nn; c += 8) {
+        int d[8];
+        double mv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool ok = c + u < nn;
+            d[u] = dofs[ok ? c + u : c];
+            mv[u] = ok ? m[c + u] : 0.0;
         }
-        const double v = a.F[g] - acc;
-        a.r[g] = v;
-        rr = v * v;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rv[u] = a.r[d[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
     }
-    if (a.partial) {
-        __shared__ double sh[kBlock / 64];
-        const double s = block_sum(rr, sh);
-        if (threadIdx.x == 0 && b < a.nblocks) a.partial[b] = s;
-    }
+    if (!halt) a.delta[t] = acc;
 }
 
-void launch_spmv(int d, int k, const SpmvArgs &a, hipStream_t s) {
-    const int grid = padded_grid(a.nblocks);
-    if (d == 2 && k == 1) hipLaunchKernelGGL((k_spmv<2, 1>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (d == 2 && k == 2) hipLaunchKernelGGL((k_spmv<2, 2>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (d == 3 && k == 1) hipLaunchKernelGGL((k_spmv<3, 1>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_spmv<3, 2>), dim3(grid), dim3(kBlock), 0, s, a);
-}
-
-// Additive Schwarz update, owner-computes form: DOF j gathers, from every
-// subdomain i that holds it at local row m, the row m of M_i E_i r, so
-// U_j += eta * sum_i (E_i^T M_i E_i r)_j with no atomics and a fixed order.
-__global__ __launch_bounds__(kBlock) void k_schwarz_gather(PatchArgs a) {
-    if (a.stop && *a.stop) return;
+// Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
+// subdomain holding DOF j (fixed order, no atomics).
+__global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgs a) {
+    const int halt = a.stop ? *a.stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     if (j >= a.n) return;
-    double acc = 0.0;
-    const int e1 = a.inv_ptr[j + 1];
-    for (int e = a.inv_ptr[j]; e < e1; ++e) {
-        const int ent = a.inv_ent[e];
-        const int p = ent >> 10, row = ent & 1023;
-        const int base = a.pptr[p];
-        const int nn = a.pptr[p + 1] - base;
-        const double *m = a.M + a.moff[p] + row * nn;
-        const int32_t *dofs = a.pdofs + base;
-        for (int c = 0; c < nn; ++c) acc = fma(m[c], a.r[dofs[c]], acc);
-    }
     const double eta = *a.eta;
-    a.U[j] = a.assign ? eta * acc : fma(eta, acc, a.U[j]);
+    const double u = a.assign ? 0.0 : a.U[j];
+    double acc = 0.0;
+    const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
+    for (int e = e0; e < e1; e += 4) {
+        int pos[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pos[v] = a.inv_pos[e + v < e1 ? e + v : e];
+        double dv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dv[v] = a.delta[pos[v]];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : 0.0;
+    }
+    if (!halt) a.U[j] = fma(eta, acc, u);
 }
 
 void launch_schwarz_gather(const PatchArgs &a, hipStream_t s) {
-    const int grid = padded_grid(blocks_for(a.n));
-    hipLaunchKernelGGL(k_schwarz_gather, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_patch_solve, dim3(padded_grid(blocks_for(a.nent))), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dof_update, dim3(padded_grid(blocks_for(a.n))), dim3(kBlock), 0, s, a);
 }
 
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
@@ -183,13 +95,28 @@ void launch_schwarz_colour(const PatchArgs &a, const int32_t *list, int np, hipS
 // y = (add ? y : 0) + A x for a CSR matrix (restriction and prolongation).
 __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, const int32_t *ci, const double *v,
                                                 const double *x, double *y, int add, const int *stop) {
-    if (stop && *stop) return;
+    const int halt = stop ? *stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
+    const double y0 = add ? y[i] : 0.0;
     double acc = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) acc = fma(v[e], x[ci[e]], acc);
-    y[i] = add ? y[i] + acc : acc;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0; e < e1; e += 4) {
+        int col[4];
+        double w[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = e + u < e1;
+            col[u] = ci[ok ? e + u : e];
+            w[u] = ok ? v[e + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[col[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(w[u], xv[u], acc);
+    }
+    if (!halt) y[i] = y0 + acc;
 }
 
 void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const double *v, const double *x, double *y,

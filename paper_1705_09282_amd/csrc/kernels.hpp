@@ -29,7 +29,10 @@ struct SpmvArgs {
 
 struct PatchArgs {
     int n;              // DOFs of the level
-    const int32_t *inv_ptr, *inv_ent, *pptr, *pdofs, *moff;
+    int nent;           // entries of all subdomains (sum of their sizes)
+    const int32_t *inv_ptr, *inv_pos, *pptr, *pdofs, *moff;
+    const int4 *ent_info;  // per entry: (M row offset, subdomain start, subdomain size, 0)
+    double *delta;      // per-entry local corrections
     const double *M;
     const double *r;
     double *U;
@@ -38,7 +41,9 @@ struct PatchArgs {
     const int *stop;
 };
 
-void launch_spmv(int d, int k, const SpmvArgs &a, hipStream_t s);
+void launch_spmv(int d, int k, int lpr, const SpmvArgs &a, hipStream_t s);
+// blocks of the residual kernel with lpr lanes per row
+inline int spmv_blocks(int64_t n, int lpr) { return (int)((n * lpr + 255) / 256); }
 void launch_schwarz_gather(const PatchArgs &a, hipStream_t s);
 void launch_schwarz_colour(const PatchArgs &a, const int32_t *list, int np, hipStream_t s);
 void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const double *v, const double *x, double *y,

@@ -462,10 +462,12 @@ static void invert(int n, std::vector<double> &A, std::vector<double> &Ainv) {
     }
 }
 
-// Leading n x n block of inv([[K_sub, e], [e^T, 0]]).
-static void bordered_inverse(const Problem &pb, const HostLevel &L, const int32_t *dofs, int n, double *out) {
+// Bordered local system [[K_sub, e], [e^T, 0]], e = integrals of the local
+// pressure functions (zero on velocity rows): row-major (n+1) x (n+1).
+static void bordered_system(const Problem &pb, const HostLevel &L, const int32_t *dofs, int n,
+                            std::vector<double> &A) {
     const int m = n + 1;
-    std::vector<double> A((size_t)m * m, 0.0), Ai;
+    A.assign((size_t)m * m, 0.0);
     for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) A[(size_t)a * m + b] = entry(pb, L, dofs[a], dofs[b]);
     for (int a = 0; a < n; ++a) {
@@ -473,6 +475,13 @@ static void bordered_inverse(const Problem &pb, const HostLevel &L, const int32_
         A[(size_t)a * m + n] = e;
         A[(size_t)n * m + a] = e;
     }
+}
+
+// Leading n x n block of inv([[K_sub, e], [e^T, 0]]).
+static void bordered_inverse(const Problem &pb, const HostLevel &L, const int32_t *dofs, int n, double *out) {
+    const int m = n + 1;
+    std::vector<double> A, Ai;
+    bordered_system(pb, L, dofs, n, A);
     invert(m, A, Ai);
     for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) out[(size_t)a * n + b] = Ai[(size_t)a * m + b];
@@ -480,7 +489,7 @@ static void bordered_inverse(const Problem &pb, const HostLevel &L, const int32_
 
 // ---------------------------------------------------------------- subdomains
 
-static void build_patches(const Problem &pb, HostLevel &L) {
+static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     const int d = pb.d, k = pb.k, N = L.N;
     BlockGeom G{d, k};
     // potential blocks: degree and true index range per direction
@@ -557,36 +566,67 @@ static void build_patches(const Problem &pb, HostLevel &L) {
                 }
     }
     L.n_patch = (int64_t)L.pptr.size() - 1;
-    // local inverses
+    // local inverses; subdomains whose bordered local systems agree to
+    // rounding (translates of one another on a uniform grid with constant
+    // coefficients) share one stored inverse
     L.moff.resize(L.n_patch);
-    int64_t tot = 0;
     L.max_patch = 0;
+    L.M.clear();
+    struct Cls {
+        int n;
+        int32_t off;
+        std::vector<double> A;
+    };
+    std::vector<Cls> classes;
+    std::vector<std::vector<int>> bucket(1 << 16);
+    std::vector<double> A, Ainv;
     for (int64_t i = 0; i < L.n_patch; ++i) {
         const int n = L.pptr[i + 1] - L.pptr[i];
-        L.moff[i] = (int32_t)tot;
-        tot += (int64_t)n * n;
         L.max_patch = std::max(L.max_patch, n);
+        bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, A);
+        double scale = 0.0;
+        for (double x : A) scale = std::max(scale, std::fabs(x));
+        int found = -1;
+        uint64_t hsh = (uint64_t)n * 1469598103934665603ull;
+        if (share) {
+            // hash of a coarse quantization: equal matrices land in one bucket
+            for (double x : A) hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / scale * 4096.0)) * 1099511628211ull;
+            for (int c : bucket[hsh & 0xffff]) {
+                const Cls &C = classes[c];
+                if (C.n != n) continue;
+                double dmax = 0.0;
+                for (size_t t = 0; t < A.size(); ++t) dmax = std::max(dmax, std::fabs(A[t] - C.A[t]));
+                if (dmax <= 1e-14 * scale) {
+                    found = c;
+                    break;
+                }
+            }
+        }
+        if (found < 0) {
+            invert(n + 1, A, Ainv);  // A is overwritten by the elimination
+            Cls C;
+            C.n = n;
+            C.off = (int32_t)L.M.size();
+            bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, C.A);
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) L.M.push_back(Ainv[(size_t)a * (n + 1) + b]);
+            if (L.M.size() > (size_t)INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
+            found = (int)classes.size();
+            if (share) bucket[hsh & 0xffff].push_back(found);
+            classes.push_back(std::move(C));
+        }
+        L.moff[i] = classes[found].off;
     }
-    if (tot > INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
-    if (L.max_patch > 1023) throw std::runtime_error("subdomain with more than 1023 DOFs");
-    if (L.n_patch >= (1 << 22)) throw std::runtime_error("more than 2^22 subdomains");
-    L.M.assign(tot, 0.0);
-    for (int64_t i = 0; i < L.n_patch; ++i) {
-        const int n = L.pptr[i + 1] - L.pptr[i];
-        bordered_inverse(pb, L, &L.pdofs[L.pptr[i]], n, &L.M[L.moff[i]]);
-    }
-    // inverse map: for each DOF the (patch, local row) pairs, patch ascending,
-    // packed as patch << 10 | row
+    L.n_class = (int64_t)classes.size();
+    // inverse map: for each DOF the delta positions of its (patch, row)
+    // entries, patch ascending
     L.inv_ptr.assign(L.n + 1, 0);
     for (int32_t g : L.pdofs) L.inv_ptr[g + 1]++;
     for (int64_t g = 0; g < L.n; ++g) L.inv_ptr[g + 1] += L.inv_ptr[g];
-    L.inv_ent.assign(L.pdofs.size(), 0);
+    L.inv_pos.assign(L.pdofs.size(), 0);
     std::vector<int32_t> fillp(L.inv_ptr.begin(), L.inv_ptr.end() - 1);
     for (int64_t i = 0; i < L.n_patch; ++i)
-        for (int r = 0; r < L.pptr[i + 1] - L.pptr[i]; ++r) {
-            const int32_t g = L.pdofs[L.pptr[i] + r];
-            L.inv_ent[fillp[g]++] = (int32_t)((i << 10) | r);
-        }
+        for (int32_t t = L.pptr[i]; t < L.pptr[i + 1]; ++t) L.inv_pos[fillp[L.pdofs[t]]++] = t;
     // colour lists
     int ncol = 0;
     for (int c : L.color) ncol = std::max(ncol, c + 1);
@@ -690,7 +730,7 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         pressure_integrals(pb, H.lv[l]);
     }
     for (int l = 1; l < L; ++l) {
-        build_patches(pb, H.lv[l]);
+        build_patches(pb, H.lv[l], pb.share_inverses);
         build_prolongation(pb, H.lv[l - 1], H.lv[l]);
     }
     {

@@ -54,6 +54,7 @@ struct Problem {
     double nu = 1.0, sigma = 1.0;
     int adv_kind = 0;
     double adv_c = 0.0;
+    bool share_inverses = true;
 };
 
 struct HostLevel {
@@ -69,8 +70,9 @@ struct HostLevel {
     std::vector<double> w;     // pressure basis integrals
     // subdomains (levels >= 1)
     int64_t n_patch = 0;
-    std::vector<int32_t> pptr, pdofs, color, moff, inv_ptr, inv_ent;
+    std::vector<int32_t> pptr, pdofs, color, moff, inv_ptr, inv_pos;
     std::vector<double> M;     // local inverses, row-major n_i x n_i at moff
+    int64_t n_class = 0;       // distinct stored inverses
     std::vector<int32_t> col_ptr, col_list;
     int max_patch = 0;
     // prolongation from level-1 (CSR, rows = this level) and restriction

@@ -33,7 +33,7 @@ class Advection(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nu1", c_int), ("nu2", c_int), ("eta", c_double), ("precision", c_int),
                 ("smoother", c_int), ("max_cycles", c_int), ("use_graph", c_int),
-                ("cycles_per_check", c_int)]
+                ("cycles_per_check", c_int), ("share_inverses", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -69,6 +69,9 @@ SIGNATURES = [
     ("dfmg_level_prolong_add", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("dfmg_coarse_solve", c_int, [c_void_p, c_void_p, c_void_p]),
     ("dfmg_time_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_dblp]),
+    ("dfmg_get_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
+    ("dfmg_set_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
+    ("dfmg_autotune", c_int, [c_void_p, c_int, c_dblp]),
     ("dfmg_export_matrix", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_patch_total", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_patches", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_i32p]),
@@ -264,6 +267,49 @@ class Solver:
         n = self._nlev(level)
         _check(lib().dfmg_time_residual(self._ctx, level, _dev(F, n), _dev(U, n), _dev(r, n), int(reps), ctypes.byref(out)))
         return out.value
+
+    def get_tuning(self):
+        lpr = np.zeros(self.n_levels, np.int32)
+        sm = np.zeros(self.n_levels, np.int32)
+        _check(lib().dfmg_get_tuning(self._ctx, _ptr(lpr, ctypes.c_int32), _ptr(sm, ctypes.c_int32)))
+        return {"lpr": lpr.tolist(), "smoother": sm.tolist()}
+
+    def set_tuning(self, lpr, smoother):
+        lpr = np.ascontiguousarray(lpr, dtype=np.int32)
+        sm = np.ascontiguousarray(smoother, dtype=np.int32)
+        if lpr.size != self.n_levels or sm.size != self.n_levels:
+            raise ValueError("one entry per level")
+        _check(lib().dfmg_set_tuning(self._ctx, _ptr(lpr, ctypes.c_int32), _ptr(sm, ctypes.c_int32)))
+
+    def autotune(self, reps=20, cache=None, key=None):
+        """Pick the fastest kernel variant per level by timing on the device.
+        With ``cache`` (a JSON file path) and ``key``, a stored choice is
+        reused instead of timing, and a new choice is stored."""
+        import json
+        if cache and key and os.path.exists(cache):
+            try:
+                stored = json.load(open(cache)).get(key)
+            except ValueError:
+                stored = None
+            if stored:
+                self.set_tuning(stored["lpr"], stored["smoother"])
+                return dict(stored, cached=True)
+        ms = np.zeros(2 * self.n_levels)
+        _check(lib().dfmg_autotune(self._ctx, int(reps), _ptr(ms, ctypes.c_double)))
+        out = self.get_tuning()
+        out["ms"] = ms.tolist()
+        if cache and key:
+            data = {}
+            if os.path.exists(cache):
+                try:
+                    data = json.load(open(cache))
+                except ValueError:
+                    data = {}
+            data[key] = {"lpr": out["lpr"], "smoother": out["smoother"], "ms": out["ms"]}
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1)
+        out["cached"] = False
+        return out
 
     def coarse_solve(self, G, dU):
         n = self._nlev(0)

@@ -90,7 +90,8 @@ def test_level_kernels(d, N, k, L, c):
 
 
 @pytest.mark.parametrize("d,N,k,L,c", CASES)
-@pytest.mark.parametrize("opt", [{}, {"use_graph": 0}, {"smoother": 2}, {"nu1": 1, "nu2": 3}, {"nu1": 0, "nu2": 2}])
+@pytest.mark.parametrize("opt", [{}, {"use_graph": 0}, {"smoother": 2}, {"nu1": 1, "nu2": 3}, {"nu1": 0, "nu2": 2},
+                                 {"share_inverses": 0}])
 def test_vcycles_match_oracle(d, N, k, L, c, opt):
     s, h, F = make(d, N, k, L, nu=0.5, sigma=4.0, c=c, **opt)
     U0 = divfree_start(h, 31)
@@ -104,6 +105,40 @@ def test_vcycles_match_oracle(d, N, k, L, c, opt):
     scale = l2_norm_velocity(h.finest.disc, Ug)
     assert div_norm(h.finest.disc, Ug) < 1e-11 * scale
     assert s.div_norm(Ud) < 1e-11 * scale
+    s.close()
+
+
+@pytest.mark.parametrize("d,N,k,L", [(2, 32, 2, 4), (3, 8, 1, 3), (2, 16, 1, 3)])
+@pytest.mark.parametrize("lpr,sm", [(1, 1), (2, 2), (4, 1), (2, 1), (4, 2)])
+def test_kernel_variants_match_oracle(d, N, k, L, lpr, sm):
+    """Every (lanes per row, smoother form) variant gives the oracle's cycles."""
+    s, h, F = make(d, N, k, L, nu=0.5, sigma=4.0)
+    s.set_tuning([lpr] * L, [sm] * L)
+    U0 = divfree_start(h, 17)
+    Ud = dev(U0)
+    s.vcycle(dev(F), Ud, 2)
+    Uo = vcycles(h, U0, F, 2)
+    nv = h.finest.disc.n_v
+    assert rel_l2(host(Ud)[:nv], Uo[:nv]) < 1e-10
+    r = dev(np.zeros(h.finest.disc.n))
+    s.level_residual(L - 1, dev(F), dev(U0), r)
+    assert relerr(host(r), F - h.finest.K @ U0) < 1e-12
+    s.close()
+
+
+def test_autotune_keeps_results_and_picks_fastest(tmp_path):
+    s, h, F = make(2, 64, 2, 4)
+    U0 = divfree_start(h, 5)
+    ref = dev(U0)
+    s.vcycle(dev(F), ref, 2)
+    out = s.autotune(reps=10, cache=str(tmp_path / "tune.json"), key="t")
+    assert not out["cached"] and len(out["lpr"]) == 4
+    Ud = dev(U0)
+    s.vcycle(dev(F), Ud, 2)
+    nv = h.finest.disc.n_v
+    assert rel_l2(host(Ud)[:nv], host(ref)[:nv]) < 1e-12
+    again = s.autotune(reps=10, cache=str(tmp_path / "tune.json"), key="t")
+    assert again["cached"] and again["lpr"] == out["lpr"]
     s.close()
 
 

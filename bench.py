@@ -98,44 +98,64 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: {3} copies of {n * 8} bytes", file=sys.stderr, flush=True)
         del src, dst
-    probs = []
+    def make_problems(precision):
+        probs = []
+        for sigma in workloads.STOKES2D_SIGMAS:
+            cfg = workloads.stokes2d(sigma, N=args.n_elem, L=args.levels)
+            s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"],
+                       precision=precision).bind(dev)
+            tuning = s.autotune(reps=20)
+            F = torch.tensor(s.manufactured_rhs(), device=dev)
+            U = torch.zeros_like(F)
+            probs.append((sigma, s, F, U, s.sizes(), tuning))
+        return probs
+
+    def run(probs):
+        """warm-up, then the timed steps; returns (seconds, stats of the last step)"""
+        def step():
+            out = []
+            for sigma, s, F, U, z, _ in probs:
+                U.zero_()
+                out.append(s.solve(F, U, tol=args.tol))
+            return out
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for _ in range(args.steps):
+            stats = step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, stats
+
     t_setup = time.perf_counter()
-    for sigma in workloads.STOKES2D_SIGMAS:
-        cfg = workloads.stokes2d(sigma, N=args.n_elem, L=args.levels)
-        s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"]).bind(dev)
-        tuning = s.autotune(reps=20)
-        F = torch.tensor(s.manufactured_rhs(), device=dev)
-        U = torch.zeros_like(F)
-        z = s.sizes()
-        probs.append((sigma, s, F, U, z))
+    plain = make_problems(0)
+    mixed = make_problems(1)
     setup_s = time.perf_counter() - t_setup
-    dofs = sum(z["n"] - 1 for *_, z in probs)
-    print(f"[bench] setup of {len(probs)} problems: {setup_s:.1f} s, DOFs/step {dofs}", file=sys.stderr, flush=True)
+    dofs = sum(z["n"] - 1 for *_, z, _ in plain)
+    print(f"[bench] setup of 2x{len(plain)} problems: {setup_s:.1f} s, DOFs/step {dofs}", file=sys.stderr, flush=True)
 
-    def step():
-        out = []
-        for sigma, s, F, U, z in probs:
-            U.zero_()
-            out.append(s.solve(F, U, tol=args.tol))
-        return out
+    T64, stats64 = run(plain)
+    print(f"[bench] plain FP64: {args.steps} steps in {T64:.3f} s", file=sys.stderr, flush=True)
+    T, stats = run(mixed)
+    print(f"[bench] FP32-refined: {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        stats = step()
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
-
+    # error of the refined solutions against the plain FP64 solutions of the same step
+    import numpy as np
+    errs = []
+    for (_, _, _, U64, z, _), (_, _, _, U32, _, _) in zip(plain, mixed):
+        nv = z["n_vel"]
+        a, b = U32[:nv].double(), U64[:nv].double()
+        errs.append(float(torch.linalg.norm(a - b) / torch.linalg.norm(b)))
     cycles = [st["cycles"] for st in stats]
-    divs = [s.div_norm(U) for _, s, _, U, _ in probs]
+    divs = [s.div_norm(U) for _, s, _, U, _, _ in mixed]
     value = args.steps * dofs / T
+    value64 = args.steps * dofs / T64
+    probs = plain
+    tuning = plain[-1][5]
 
     # roofline of the dominant kernel: finest-grid residual of the sigma = 1 problem
-    _, s1, F1, U1, z1 = probs[1]
+    _, s1, F1, U1, z1, _ = probs[1]
     r = torch.empty_like(F1)
     ms = s1.time_residual(args.levels - 1, F1, U1, r, reps=200)
     alg_bytes = 8 * z1["nnz"] + 3 * 8 * z1["n"]
@@ -153,17 +173,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
                         f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, V(2,2) additive Schwarz, "
                         f"tol {args.tol:g}, U0=0",
-            "path": "plain FP64 V-cycles",
+            "path": "FP32 V-cycles in FP64 iterative refinement (fixed damping)",
             "dofs_per_step": dofs,
             "cycles_per_sigma": cycles,
             "vcycles_per_s": args.steps * sum(cycles) / T,
             "div_norm_per_sigma": divs,
+            "vel_rel_err_vs_plain_fp64_per_sigma": errs,
+            "plain_fp64": {"value": value64, "ms_per_step": 1e3 * T64 / args.steps,
+                           "cycles_per_sigma": [st["cycles"] for st in stats64],
+                           "vcycles_per_s": args.steps * sum(st["cycles"] for st in stats64) / T64},
+            "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
             "tuning_last_problem": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
         },
@@ -182,7 +207,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.tol)
-    for _, s, _, _, _ in probs:
+    for _, s, _, _, _, _ in plain + mixed:
         s.close()
     print(json.dumps(line), flush=True)
 

@@ -68,18 +68,20 @@ typedef struct {
 /* Solver options.  dfmg_default_options fills: nu1 = nu2 = 2, eta = 0 (use the
  * stable fixed damping for (dim, k): 0.35 for 2D k=1, 0.2 for 2D k=2, 0.07 for
  * 3D k=1, 0.02 for 3D k=2), precision 0, smoother 0, max_cycles 200,
- * use_graph 1, cycles_per_check 1, share_inverses 1. */
+ * use_graph 1, cycles_per_check 1, share_inverses 1, inner_cycles 1. */
 typedef struct {
     int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
     int nu2;              /* post-smoothing steps per level                     */
     double eta;           /* fixed additive-Schwarz damping; <= 0: default      */
-    int precision;        /* 0: FP64 V-cycles                                   */
+    int precision;        /* 0: FP64 V-cycles; 1 (dim 2): solve by FP64 iterative
+                             refinement around FP32 V-cycles (see dfmg_solve)    */
     int smoother;         /* 0 auto, 1 gather (owner computes), 2 coloured scatter */
     int max_cycles;       /* solve: cycle limit (ENOTCONV beyond)               */
     int use_graph;        /* 1: replay the V-cycle as a captured hipGraph       */
     int cycles_per_check; /* solve: V-cycles launched between host checks       */
     int share_inverses;   /* 1: subdomains with equal local systems (to 1e-14)
                              share one stored inverse; 0: one per subdomain     */
+    int inner_cycles;     /* precision 1: FP32 V-cycles per refinement step     */
 } dfmg_options;
 
 #define DFMG_MAX_HISTORY 512
@@ -136,7 +138,13 @@ int dfmg_vcycle(dfmg_ctx *ctx, const double *F_dev, double *U_dev, int ncycles);
 
 /* Repeat V-cycles from U (device, in/out) until ||F - K U||_2 <= tol ||F||_2
  * (numerical-results protocol, relative to ||F||), then shift the pressure to
- * zero mean.  st may be NULL.  Errors: ENOTCONV, EDIVERGED, ESTATE, EHIP. */
+ * zero mean.  st may be NULL.  Errors: ENOTCONV, EDIVERGED, ESTATE, EHIP.
+ * With precision 1 each step computes r = F - K U in FP64, applies
+ * inner_cycles V-cycles in FP32 (FP32 values, FP32 accumulation, FP64 coarse
+ * solve) to K dU = r from dU = 0, recovers the streamfunction increment psi
+ * of dU's velocity by integrating its x-component along y, and updates
+ * u += curl psi, p += dU_p in FP64, so u stays divergence-free to FP64
+ * rounding; stats count refinement steps as cycles. */
 int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, dfmg_stats *st);
 
 /* ||F - K U||_2 on the finest level (device inputs, host output). */

@@ -35,18 +35,29 @@ struct ArgError : std::runtime_error {
         if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Typed values and vectors of one level: FP64 for the plain path, FP32 for
+// the V-cycle inside the iterative refinement.
+template <class T>
+struct LevelData {
+    T *val = nullptr, *U = nullptr, *F = nullptr, *r = nullptr, *M = nullptr, *delta = nullptr;
+    T *P_v = nullptr, *R_v = nullptr;
+};
+
 struct DevLevel {
-    double *val = nullptr;
-    double *U = nullptr, *F = nullptr, *r = nullptr;
+    LevelData<double> d;
+    LevelData<float> f;
     int32_t *pptr = nullptr, *pdofs = nullptr, *moff = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr;
     int4 *ent_info = nullptr;
-    double *delta = nullptr;
     int32_t *col_list = nullptr;
-    double *M = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
-    double *P_v = nullptr, *R_v = nullptr;
     double *Kinv = nullptr;
+    template <class T>
+    LevelData<T> &data();
 };
+template <>
+LevelData<double> &DevLevel::data<double>() { return d; }
+template <>
+LevelData<float> &DevLevel::data<float>() { return f; }
 
 // Bump allocator over the caller's workspace (256-byte aligned pieces).  With
 // base == nullptr it only measures.
@@ -78,11 +89,13 @@ struct dfmg_ctx {
     int *counter = nullptr, *stop = nullptr;
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
+    double *psi = nullptr;       // refinement: streamfunction increment
     hipGraphExec_t graph = nullptr;
-    bool graph_norm = false;
-    std::vector<int> smoother;  // per level: 1 gather, 2 colour
-    std::vector<int> lpr;       // per level: lanes per row of the residual kernel
+    int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
+    std::vector<int> smoother;   // per level: 1 gather, 2 colour
+    std::vector<int> lpr;        // per level: lanes per row of the residual kernel
     std::vector<double> eta_host;
+    bool mixed() const { return opt.precision == 1; }
 };
 
 namespace {
@@ -110,6 +123,19 @@ int guarded(F &&f) {
     }
 }
 
+template <class T>
+void take_level(Arena &A, const HostLevel &h, LevelData<T> &v, bool coarse) {
+    v.U = A.take<T>(h.n);
+    v.F = A.take<T>(h.n);
+    v.r = A.take<T>(h.n);
+    v.val = A.take<T>(h.val.size());
+    if (coarse) return;
+    v.M = A.take<T>(h.M.size());
+    v.delta = A.take<T>(h.pdofs.size());
+    v.P_v = A.take<T>(h.P_v.size());
+    v.R_v = A.take<T>(h.R_v.size());
+}
+
 void plan(dfmg_ctx *c, Arena &A) {
     const Hierarchy &H = c->H;
     const int L = H.pb.L;
@@ -119,12 +145,10 @@ void plan(dfmg_ctx *c, Arena &A) {
     for (int l = 0; l < L; ++l) {
         const HostLevel &h = H.lv[l];
         DevLevel &v = c->dl[l];
-        v.U = A.take<double>(h.n);
-        v.F = A.take<double>(h.n);
-        v.r = A.take<double>(h.n);
+        take_level(A, h, v.d, l == 0);
+        if (c->mixed()) take_level(A, h, v.f, l == 0);
         nmax = std::max(nmax, h.n);
         maxblocks = std::max(maxblocks, spmv_blocks(h.n, 4));
-        v.val = A.take<double>(h.val.size());
         if (l == 0) {
             v.Kinv = A.take<double>(h.Kinv.size());
             continue;
@@ -135,15 +159,11 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.inv_ptr = A.take<int32_t>(h.inv_ptr.size());
         v.inv_pos = A.take<int32_t>(h.inv_pos.size());
         v.ent_info = A.take<int4>(h.pdofs.size());
-        v.delta = A.take<double>(h.pdofs.size());
         v.col_list = A.take<int32_t>(h.col_list.size());
-        v.M = A.take<double>(h.M.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
         v.P_ci = A.take<int32_t>(h.P_ci.size());
-        v.P_v = A.take<double>(h.P_v.size());
         v.R_rp = A.take<int32_t>(h.R_rp.size());
         v.R_ci = A.take<int32_t>(h.R_ci.size());
-        v.R_v = A.take<double>(h.R_v.size());
     }
     c->nparts = padded_grid(maxblocks);
     c->eta = A.take<double>(L);
@@ -158,6 +178,7 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->pmass = A.take<double>(H.pmass.size());
     c->rtmp = A.take<double>(nmax);
     c->wfine = A.take<double>(H.lv[L - 1].n_q);
+    if (c->mixed()) c->psi = A.take<double>((size_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1));
 }
 
 template <class T>
@@ -165,11 +186,19 @@ void up(T *dst, const std::vector<T> &src, hipStream_t s) {
     if (!src.empty()) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-SpmvArgs spmv_args(dfmg_ctx *c, int l, const double *F, const double *U, double *r, double *partial,
-                   const int *stop) {
+// FP32 copy of a host array, uploaded synchronously (the staging buffer is local)
+void up32(float *dst, const std::vector<double> &src, hipStream_t s) {
+    if (src.empty()) return;
+    std::vector<float> tmp(src.begin(), src.end());
+    HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+template <class T>
+SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, const int *stop) {
     const HostLevel &h = c->H.lv[l];
-    SpmvArgs a{};
-    a.val = c->dl[l].val;
+    SpmvArgsT<T> a{};
+    a.val = c->dl[l].data<T>().val;
     for (int R = 0; R < 4; ++R) a.val_off[R] = R < h.nblk ? h.val_off[R] : 0;
     for (int R = 0; R < 5; ++R) a.off[R] = R <= h.nblk ? h.off[R] : h.n;
     for (int R = 0; R < 4; ++R)
@@ -185,129 +214,170 @@ SpmvArgs spmv_args(dfmg_ctx *c, int l, const double *F, const double *U, double 
 }
 
 // r = F - K_l U; returns the number of per-block partial sums written
-int spmv(dfmg_ctx *c, int l, const double *F, const double *U, double *r, double *partial, const int *stop) {
-    const SpmvArgs a = spmv_args(c, l, F, U, r, partial, stop);
-    launch_spmv(c->H.pb.d, c->H.pb.k, c->lpr[l], a, c->s);
+template <class T>
+int spmv(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, const int *stop) {
+    const SpmvArgsT<T> a = spmv_args<T>(c, l, F, U, r, partial, stop);
+    launch_spmv<T>(c->H.pb.d, c->H.pb.k, c->lpr[l], a, c->s);
     return a.nblocks;
 }
 
 // eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l.
-void schwarz(dfmg_ctx *c, int l, const double *r, double *U, bool assign, const int *stop) {
+template <class T>
+void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop) {
     const HostLevel &h = c->H.lv[l];
-    const DevLevel &v = c->dl[l];
-    PatchArgs a{};
+    DevLevel &v = c->dl[l];
+    PatchArgsT<T> a{};
     a.n = (int)h.n;
+    a.nent = (int)h.pdofs.size();
     a.inv_ptr = v.inv_ptr;
     a.inv_pos = v.inv_pos;
-    a.ent_info = v.ent_info;
-    a.delta = v.delta;
-    a.nent = (int)h.pdofs.size();
     a.pptr = v.pptr;
     a.pdofs = v.pdofs;
     a.moff = v.moff;
-    a.M = v.M;
+    a.ent_info = v.ent_info;
+    a.delta = v.data<T>().delta;
+    a.M = v.data<T>().M;
     a.r = r;
     a.U = U;
     a.eta = c->eta + l;
     a.assign = assign ? 1 : 0;
     a.stop = stop;
     if (c->smoother[l] == 2) {
-        if (assign) launch_fill(h.n, U, 0.0, stop, c->s);
+        if (assign) launch_fill<T>(h.n, U, T(0), stop, c->s);
         for (size_t col = 0; col + 1 < h.col_ptr.size(); ++col)
-            launch_schwarz_colour(a, v.col_list + h.col_ptr[col], h.col_ptr[col + 1] - h.col_ptr[col], c->s);
+            launch_schwarz_colour<T>(a, v.col_list + h.col_ptr[col], h.col_ptr[col + 1] - h.col_ptr[col], c->s);
     } else {
-        launch_schwarz_gather(a, c->s);
+        launch_schwarz_gather<T>(a, c->s);
     }
 }
 
-void restrict_to(dfmg_ctx *c, int l, const double *r, double *G, const int *stop) {
+template <class T>
+void restrict_to(dfmg_ctx *c, int l, const T *r, T *G, const int *stop) {
     const HostLevel &hc = c->H.lv[l - 1];
-    const DevLevel &v = c->dl[l];
-    launch_csr((int)hc.n, v.R_rp, v.R_ci, v.R_v, r, G, 0, stop, c->s);
+    DevLevel &v = c->dl[l];
+    launch_csr<T>((int)hc.n, v.R_rp, v.R_ci, v.data<T>().R_v, r, G, 0, stop, c->s);
 }
 
-void prolong_add(dfmg_ctx *c, int l, const double *dU, double *U, const int *stop) {
+template <class T>
+void prolong_add(dfmg_ctx *c, int l, const T *dU, T *U, const int *stop) {
     const HostLevel &h = c->H.lv[l];
-    const DevLevel &v = c->dl[l];
-    launch_csr((int)h.n, v.P_rp, v.P_ci, v.P_v, dU, U, 1, stop, c->s);
+    DevLevel &v = c->dl[l];
+    launch_csr<T>((int)h.n, v.P_rp, v.P_ci, v.data<T>().P_v, dU, U, 1, stop, c->s);
 }
 
-void coarse(dfmg_ctx *c, const double *G, double *dU, const int *stop) {
-    launch_gemv((int)c->H.lv[0].n, c->dl[0].Kinv, G, dU, stop, c->s);
+// exact coarse solve (FP64 bordered inverse, FP64 accumulation)
+template <class T>
+void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
+    const int n = (int)c->H.lv[0].n;
+    launch_gemv<T>(n, n, c->dl[0].Kinv, G, dU, stop, c->s);
 }
 
-// One V-cycle (Algorithm 1) on the finest level's internal U, F.  With
-// `norm`, the first residual of the finest level also feeds the convergence
-// check (history, stop flag).
-void cycle_body(dfmg_ctx *c, bool norm) {
+// One V-cycle (Algorithm 1) on the finest level's internal U, F of type T.
+// norm: the first residual of the finest level also feeds the convergence
+// check.  fine_zero: the finest U is known to be zero (its first smoothing
+// step then needs no residual).
+template <class T>
+void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
     const int L = c->H.pb.L, nu1 = c->opt.nu1, nu2 = c->opt.nu2;
     const int *stop = c->stop;
     if (L == 1) {
-        DevLevel &v = c->dl[0];
+        LevelData<T> &v = c->dl[0].data<T>();
         if (norm) {
-            const int np = spmv(c, 0, v.F, v.U, v.r, c->partial, stop);
+            const int np = spmv<T>(c, 0, v.F, v.U, v.r, c->partial, stop);
             launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
         }
-        coarse(c, v.F, v.r, stop);  // exact solve of K U = F
-        launch_copy(c->H.lv[0].n, v.r, v.U, stop, c->s);
+        coarse<T>(c, v.F, v.U, stop);  // exact solve of K U = F
         return;
     }
     for (int l = L - 1; l >= 1; --l) {
-        DevLevel &v = c->dl[l];
+        LevelData<T> &v = c->dl[l].data<T>();
         const HostLevel &h = c->H.lv[l];
-        bool zero = (l < L - 1);
+        bool zero = (l < L - 1) || fine_zero;
         bool first_res = (l == L - 1) && norm;
         for (int s = 0; s < nu1; ++s) {
-            if (zero) {
-                schwarz(c, l, v.F, v.U, true, stop);  // U = 0: residual is F
+            if (zero && !first_res) {
+                schwarz<T>(c, l, v.F, v.U, true, stop);  // U = 0: residual is F
                 zero = false;
                 continue;
             }
-            const int np = spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            const int np = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
             if (first_res) {
                 launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
                 first_res = false;
             }
-            schwarz(c, l, v.r, v.U, false, stop);
+            schwarz<T>(c, l, v.r, v.U, zero, stop);
+            zero = false;
         }
-        if (zero) {
-            launch_fill(h.n, v.U, 0.0, stop, c->s);
-            restrict_to(c, l, v.F, c->dl[l - 1].F, stop);
+        if (zero && !first_res) {
+            launch_fill<T>(h.n, v.U, T(0), stop, c->s);
+            restrict_to<T>(c, l, v.F, c->dl[l - 1].data<T>().F, stop);
         } else {
-            const int np = spmv(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            const int np = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
             if (first_res)
                 launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
-            restrict_to(c, l, v.r, c->dl[l - 1].F, stop);
+            restrict_to<T>(c, l, v.r, c->dl[l - 1].data<T>().F, stop);
         }
     }
-    coarse(c, c->dl[0].F, c->dl[0].U, stop);
+    coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
     for (int l = 1; l < L; ++l) {
-        DevLevel &v = c->dl[l];
-        prolong_add(c, l, c->dl[l - 1].U, v.U, stop);
+        LevelData<T> &v = c->dl[l].data<T>();
+        prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
         for (int s = 0; s < nu2; ++s) {
-            spmv(c, l, v.F, v.U, v.r, nullptr, stop);
-            schwarz(c, l, v.r, v.U, false, stop);
+            spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
+            schwarz<T>(c, l, v.r, v.U, false, stop);
         }
     }
 }
 
-void run_cycle(dfmg_ctx *c, bool norm) {
+// One step of the FP64 iterative refinement: r = F - K U in FP64 (with the
+// convergence check), inner_cycles FP32 V-cycles on K dU = r from dU = 0,
+// then U += [curl psi; dU_p] in FP64 with psi recovered from dU_x.
+void refine_body(dfmg_ctx *c) {
+    const int L = c->H.pb.L;
+    const HostLevel &h = c->H.lv[L - 1];
+    DevLevel &v = c->dl[L - 1];
+    const int np = spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stop);
+    launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
+    launch_cast(h.n, v.d.r, v.f.F, c->stop, c->s);
+    for (int i = 0; i < c->opt.inner_cycles; ++i) cycle_body<float>(c, false, i == 0);
+    RefineArgs a{};
+    a.N = c->H.pb.N;
+    a.k = c->H.pb.k;
+    a.off_uy = h.off[1];
+    a.off_p = h.off[2];
+    a.n = h.n;
+    a.X = v.f.U;
+    a.dcoef = c->dcoef;
+    a.psi = c->psi;
+    a.U = v.d.U;
+    a.stop = c->stop;
+    launch_refine_update_2d(a, c->s);
+}
+
+void body(dfmg_ctx *c, int kind) {
+    if (kind == 2) refine_body(c);
+    else cycle_body<double>(c, kind == 1, false);
+}
+
+// Launch one cycle of the given kind, replaying a captured hipGraph when
+// enabled (captured on first use, recaptured when the kind changes).
+void run_cycle(dfmg_ctx *c, int kind) {
     if (!c->opt.use_graph) {
-        cycle_body(c, norm);
+        body(c, kind);
         return;
     }
-    if (c->graph && c->graph_norm != norm) {
+    if (c->graph && c->graph_kind != kind) {
         HIPCHK(hipGraphExecDestroy(c->graph));
         c->graph = nullptr;
     }
     if (!c->graph) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
-        cycle_body(c, norm);
+        body(c, kind);
         HIPCHK(hipStreamEndCapture(c->s, &g));
         HIPCHK(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
         HIPCHK(hipGraphDestroy(g));
-        c->graph_norm = norm;
+        c->graph_kind = kind;
     }
     HIPCHK(hipGraphLaunch(c->graph, c->s));
 }
@@ -349,6 +419,7 @@ void dfmg_default_options(dfmg_options *o) {
     o->use_graph = 1;
     o->cycles_per_check = 1;
     o->share_inverses = 1;
+    o->inner_cycles = 1;
 }
 
 const char *dfmg_last_error(void) { return g_err.c_str(); }
@@ -375,7 +446,9 @@ int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma, const dfmg
         if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 1 || o.cycles_per_check < 1)
             throw ArgError("invalid options");
         if (o.max_cycles > DFMG_MAX_HISTORY - 2) throw ArgError("max_cycles too large");
-        if (o.precision != 0) throw ArgError("precision must be 0");
+        if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
+        if (o.precision == 1 && pb.d != 2) throw ArgError("FP32 refinement is implemented for dim 2");
+        if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
         if (o.smoother < 0 || o.smoother > 2) throw ArgError("smoother must be 0, 1 or 2");
         if (o.eta >= 1.0) throw ArgError("eta must be < 1");
         pb.share_inverses = o.share_inverses != 0;
@@ -440,10 +513,21 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         for (int l = 0; l < H.pb.L; ++l) {
             const HostLevel &h = H.lv[l];
             DevLevel &v = c->dl[l];
-            HIPCHK(hipMemsetAsync(v.U, 0, h.n * sizeof(double), s));
-            HIPCHK(hipMemsetAsync(v.F, 0, h.n * sizeof(double), s));
-            HIPCHK(hipMemsetAsync(v.r, 0, h.n * sizeof(double), s));
-            up(v.val, h.val, s);
+            HIPCHK(hipMemsetAsync(v.d.U, 0, h.n * sizeof(double), s));
+            HIPCHK(hipMemsetAsync(v.d.F, 0, h.n * sizeof(double), s));
+            HIPCHK(hipMemsetAsync(v.d.r, 0, h.n * sizeof(double), s));
+            up(v.d.val, h.val, s);
+            if (c->mixed()) {
+                HIPCHK(hipMemsetAsync(v.f.U, 0, h.n * sizeof(float), s));
+                HIPCHK(hipMemsetAsync(v.f.F, 0, h.n * sizeof(float), s));
+                HIPCHK(hipMemsetAsync(v.f.r, 0, h.n * sizeof(float), s));
+                up32(v.f.val, h.val, s);
+                if (l > 0) {
+                    up32(v.f.M, h.M, s);
+                    up32(v.f.P_v, h.P_v, s);
+                    up32(v.f.R_v, h.R_v, s);
+                }
+            }
             if (l == 0) {
                 up(v.Kinv, h.Kinv, s);
                 continue;
@@ -464,13 +548,13 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                 HIPCHK(hipStreamSynchronize(s));  // info is a local host buffer
             }
             up(v.col_list, h.col_list, s);
-            up(v.M, h.M, s);
+            up(v.d.M, h.M, s);
             up(v.P_rp, h.P_rp, s);
             up(v.P_ci, h.P_ci, s);
-            up(v.P_v, h.P_v, s);
+            up(v.d.P_v, h.P_v, s);
             up(v.R_rp, h.R_rp, s);
             up(v.R_ci, h.R_ci, s);
-            up(v.R_v, h.R_v, s);
+            up(v.d.R_v, h.R_v, s);
         }
         up(c->eta, c->eta_host, s);
         up(c->dcoef, H.dcoef, s);
@@ -524,11 +608,11 @@ int dfmg_vcycle(dfmg_ctx *c, const double *F, double *U, int ncycles) {
         enter(c);
         const int L = c->H.pb.L;
         const int64_t n = c->H.lv[L - 1].n;
-        DevLevel &v = c->dl[L - 1];
+        LevelData<double> &v = c->dl[L - 1].d;
         launch_fill_int(1, c->stop, 0, c->s);
         launch_copy(n, F, v.F, nullptr, c->s);
         launch_copy(n, U, v.U, nullptr, c->s);
-        for (int i = 0; i < ncycles; ++i) run_cycle(c, false);
+        for (int i = 0; i < ncycles; ++i) run_cycle(c, 0);
         launch_copy(n, v.U, U, nullptr, c->s);
         HIPCHK(hipGetLastError());
         leave(c);
@@ -540,7 +624,7 @@ int dfmg_residual_norm(dfmg_ctx *c, const double *F, const double *U, double *ou
     return guarded([&] {
         enter(c);
         const int L = c->H.pb.L;
-        const int nb = spmv(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
+        const int nb = spmv<double>(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
         launch_reduce(nb, c->partial, c->scal, 1.0, c->s);
         *out = std::sqrt(read_scalar(c, c->scal));
         leave(c);
@@ -587,8 +671,9 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         const int L = c->H.pb.L;
         const HostLevel &h = c->H.lv[L - 1];
         const int64_t n = h.n;
-        DevLevel &v = c->dl[L - 1];
+        LevelData<double> &v = c->dl[L - 1].d;
         const int nb = blocks_for(n);
+        const int kind = c->mixed() ? 2 : 1;
         launch_fill_int(1, c->stop, 0, c->s);
         launch_fill_int(1, c->counter, 0, c->s);
         launch_copy(n, F, v.F, nullptr, c->s);
@@ -599,7 +684,7 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         int launched = 0, counter = 0, stopv = 0;
         while (launched < maxc) {
             const int chunk = std::min(c->opt.cycles_per_check, maxc - launched);
-            for (int i = 0; i < chunk; ++i) run_cycle(c, true);
+            for (int i = 0; i < chunk; ++i) run_cycle(c, kind);
             launched += chunk;
             int hv[2];
             HIPCHK(hipMemcpyAsync(&hv[0], c->counter, sizeof(int), hipMemcpyDeviceToHost, c->s));
@@ -611,7 +696,7 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         }
         if (!stopv) {
             // limit reached: measure the residual of the last iterate
-            const int np = spmv(c, L - 1, v.F, v.U, v.r, c->partial, nullptr);
+            const int np = spmv<double>(c, L - 1, v.F, v.U, v.r, c->partial, nullptr);
             launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
             int hv[2];
             HIPCHK(hipMemcpyAsync(&hv[0], c->counter, sizeof(int), hipMemcpyDeviceToHost, c->s));
@@ -655,7 +740,7 @@ int dfmg_level_residual(dfmg_ctx *c, int level, const double *F, const double *U
     return guarded([&] {
         check_level(c, level, 1);
         enter(c);
-        spmv(c, level, F, U, r, nullptr, nullptr);
+        spmv<double>(c, level, F, U, r, nullptr, nullptr);
         leave(c);
     });
 }
@@ -669,9 +754,9 @@ int dfmg_time_residual(dfmg_ctx *c, int level, const double *F, const double *U,
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        spmv(c, level, F, U, r, nullptr, nullptr);  // warm
+        spmv<double>(c, level, F, U, r, nullptr, nullptr);  // warm
         HIPCHK(hipEventRecord(e0, c->s));
-        for (int i = 0; i < reps; ++i) spmv(c, level, F, U, r, nullptr, nullptr);
+        for (int i = 0; i < reps; ++i) spmv<double>(c, level, F, U, r, nullptr, nullptr);
         HIPCHK(hipEventRecord(e1, c->s));
         HIPCHK(hipEventSynchronize(e1));
         float t = 0.f;
@@ -689,8 +774,8 @@ int dfmg_level_smooth(dfmg_ctx *c, int level, const double *F, double *U, int ns
         check_level(c, level, 1);
         enter(c);
         for (int i = 0; i < nsteps; ++i) {
-            spmv(c, level, F, U, c->rtmp, nullptr, nullptr);
-            schwarz(c, level, c->rtmp, U, false, nullptr);
+            spmv<double>(c, level, F, U, c->rtmp, nullptr, nullptr);
+            schwarz<double>(c, level, c->rtmp, U, false, nullptr);
         }
         leave(c);
     });
@@ -701,7 +786,7 @@ int dfmg_level_restrict(dfmg_ctx *c, int level, const double *r, double *G) {
     return guarded([&] {
         check_level(c, level, 1);
         enter(c);
-        restrict_to(c, level, r, G, nullptr);
+        restrict_to<double>(c, level, r, G, nullptr);
         leave(c);
     });
 }
@@ -711,7 +796,7 @@ int dfmg_level_prolong_add(dfmg_ctx *c, int level, const double *dU, double *U) 
     return guarded([&] {
         check_level(c, level, 1);
         enter(c);
-        prolong_add(c, level, dU, U, nullptr);
+        prolong_add<double>(c, level, dU, U, nullptr);
         leave(c);
     });
 }
@@ -720,7 +805,7 @@ int dfmg_coarse_solve(dfmg_ctx *c, const double *G, double *dU) {
     if (!c || !G || !dU) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         enter(c);
-        coarse(c, G, dU, nullptr);
+        coarse<double>(c, G, dU, nullptr);
         leave(c);
     });
 }
@@ -769,40 +854,46 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
             return (double)t / reps;
         };
         const int L = c->H.pb.L;
-        for (int l = 0; l < L; ++l) {
-            DevLevel &v = c->dl[l];
-            double best = 1e30;
-            int bl = c->lpr[l];
-            for (int lp : {1, 2, 4}) {
-                c->lpr[l] = lp;
-                const double t = timed([&] { spmv(c, l, v.F, v.U, v.r, nullptr, nullptr); });
-                if (t < best) {
-                    best = t;
-                    bl = lp;
+        // the variants are timed in the precision the V-cycles run in
+        auto tune = [&](auto zero) {
+            using T = decltype(zero);
+            for (int l = 0; l < L; ++l) {
+                LevelData<T> &v = c->dl[l].data<T>();
+                double best = 1e30;
+                int bl = c->lpr[l];
+                for (int lp : {1, 2, 4}) {
+                    c->lpr[l] = lp;
+                    const double t = timed([&] { spmv<T>(c, l, v.F, v.U, v.r, nullptr, nullptr); });
+                    if (t < best) {
+                        best = t;
+                        bl = lp;
+                    }
                 }
-            }
-            c->lpr[l] = bl;
-            if (ms_out) ms_out[2 * l] = best;
-            if (l == 0) {
-                if (ms_out) ms_out[1] = 0.0;
-                continue;
-            }
-            double bests = 1e30;
-            int bs = c->smoother[l];
-            for (int sm : {1, 2}) {
-                c->smoother[l] = sm;
-                const double t = timed([&] { schwarz(c, l, v.r, v.U, false, nullptr); });
-                if (t < bests) {
-                    bests = t;
-                    bs = sm;
+                c->lpr[l] = bl;
+                if (ms_out) ms_out[2 * l] = best;
+                if (l == 0) {
+                    if (ms_out) ms_out[1] = 0.0;
+                    continue;
                 }
+                double bests = 1e30;
+                int bs = c->smoother[l];
+                for (int sm : {1, 2}) {
+                    c->smoother[l] = sm;
+                    const double t = timed([&] { schwarz<T>(c, l, v.r, v.U, false, nullptr); });
+                    if (t < bests) {
+                        bests = t;
+                        bs = sm;
+                    }
+                }
+                c->smoother[l] = bs;
+                if (ms_out) ms_out[2 * l + 1] = bests;
+                // the timing runs added corrections to U_l: restore zeros (the
+                // internal U is reloaded or reset by every cycle)
+                launch_fill<T>(c->H.lv[l].n, v.U, T(0), nullptr, c->s);
             }
-            c->smoother[l] = bs;
-            if (ms_out) ms_out[2 * l + 1] = bests;
-            // the timing runs added corrections to U_l: restore the state the
-            // cycle expects (internal U is reloaded or reset by every cycle)
-            launch_fill(c->H.lv[l].n, v.U, 0.0, nullptr, c->s);
-        }
+        };
+        if (c->mixed()) tune(0.0f);
+        else tune(0.0);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (c->graph) {

@@ -6,7 +6,8 @@ namespace dfmg {
 // Additive Schwarz, step 1: local solves.  Thread t owns entry t of the
 // subdomain-major correction buffer, i.e. local row m of subdomain p with
 // t = pptr[p] + m, and computes delta_t = (M_p E_p r)_m.
-__global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgs a) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     const int halt = a.stop ? *a.stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int t = b * kBlock + threadIdx.x;
@@ -14,20 +15,20 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgs a) {
     // descriptor of entry t: offset of its row of M, first entry of its
     // subdomain, subdomain size
     const int4 info = a.ent_info[t];
-    const double *m = a.M + info.x;
+    const T *m = a.M + info.x;
     const int32_t *dofs = a.pdofs + info.y;
     const int nn = info.z;
     // chunks of 8 independent gathers; the tail is padded with zero
     // coefficients on a valid index, which leaves the sum unchanged
-    double acc = 0.0;
+    T acc = 0;
     for (int c = 0; c < nn; c += 8) {
         int d[8];
-        double mv[8], rv[8];
+        T mv[8], rv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const bool ok = c + u < nn;
             d[u] = dofs[ok ? c + u : c];
-            mv[u] = ok ? m[c + u] : 0.0;
+            mv[u] = ok ? m[c + u] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) rv[u] = a.r[d[u]];
@@ -39,37 +40,40 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgs a) {
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
 // subdomain holding DOF j (fixed order, no atomics).
-__global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgs a) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
     const int halt = a.stop ? *a.stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     if (j >= a.n) return;
-    const double eta = *a.eta;
-    const double u = a.assign ? 0.0 : a.U[j];
-    double acc = 0.0;
+    const T eta = (T)*a.eta;
+    const T u = a.assign ? T(0) : a.U[j];
+    T acc = 0;
     const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
     for (int e = e0; e < e1; e += 4) {
         int pos[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) pos[v] = a.inv_pos[e + v < e1 ? e + v : e];
-        double dv[4];
+        T dv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) dv[v] = a.delta[pos[v]];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : 0.0;
+        for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : T(0);
     }
     if (!halt) a.U[j] = fma(eta, acc, u);
 }
 
-void launch_schwarz_gather(const PatchArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_patch_solve, dim3(padded_grid(blocks_for(a.nent))), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dof_update, dim3(padded_grid(blocks_for(a.n))), dim3(kBlock), 0, s, a);
+template <class T>
+void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_patch_solve<T>, dim3(padded_grid(blocks_for(a.nent))), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n))), dim3(kBlock), 0, s, a);
 }
 
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
 // each thread solves one subdomain and adds its damped correction with plain
 // read-modify-writes.
-__global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgs a, const int32_t *list, int np) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgsT<T> a, const int32_t *list, int np) {
     if (a.stop && *a.stop) return;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= np) return;
@@ -77,39 +81,41 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgs a, const in
     const int base = a.pptr[p];
     const int nn = a.pptr[p + 1] - base;
     const int32_t *dofs = a.pdofs + base;
-    const double *m = a.M + a.moff[p];
-    const double eta = *a.eta;
+    const T *m = a.M + a.moff[p];
+    const T eta = (T)*a.eta;
     for (int row = 0; row < nn; ++row) {
-        double acc = 0.0;
+        T acc = 0;
         for (int c = 0; c < nn; ++c) acc = fma(m[row * nn + c], a.r[dofs[c]], acc);
         const int g = dofs[row];
         a.U[g] = fma(eta, acc, a.U[g]);
     }
 }
 
-void launch_schwarz_colour(const PatchArgs &a, const int32_t *list, int np, hipStream_t s) {
+template <class T>
+void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s) {
     if (np <= 0) return;
-    hipLaunchKernelGGL(k_schwarz_colour, dim3(blocks_for(np)), dim3(kBlock), 0, s, a, list, np);
+    hipLaunchKernelGGL(k_schwarz_colour<T>, dim3(blocks_for(np)), dim3(kBlock), 0, s, a, list, np);
 }
 
 // y = (add ? y : 0) + A x for a CSR matrix (restriction and prolongation).
-__global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, const int32_t *ci, const double *v,
-                                                const double *x, double *y, int add, const int *stop) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v,
+                                                const T *x, T *y, int add, const int *stop) {
     const int halt = stop ? *stop : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
-    const double y0 = add ? y[i] : 0.0;
-    double acc = 0.0;
+    const T y0 = add ? y[i] : T(0);
+    T acc = 0;
     const int e0 = rp[i], e1 = rp[i + 1];
     for (int e = e0; e < e1; e += 4) {
         int col[4];
-        double w[4], xv[4];
+        T w[4], xv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const bool ok = e + u < e1;
             col[u] = ci[ok ? e + u : e];
-            w[u] = ok ? v[e + u] : 0.0;
+            w[u] = ok ? v[e + u] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) xv[u] = x[col[u]];
@@ -119,40 +125,117 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, co
     if (!halt) y[i] = y0 + acc;
 }
 
-void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
-                int add, const int *stop, hipStream_t s) {
+template <class T>
+void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, T *y, int add,
+                const int *stop, hipStream_t s) {
     const int grid = padded_grid(blocks_for(nrows));
-    hipLaunchKernelGGL(k_csr, dim3(grid), dim3(kBlock), 0, s, nrows, rp, ci, v, x, y, add, stop);
+    hipLaunchKernelGGL(k_csr<T>, dim3(grid), dim3(kBlock), 0, s, nrows, rp, ci, v, x, y, add, stop);
 }
 
-// Dense y = A x, one wavefront per row.
-__global__ __launch_bounds__(kBlock) void k_gemv(int n, const double *A, const double *x, double *y,
+// Dense y = A x (A FP64, row-major rows x cols), one wavefront per row, FP64
+// accumulation.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const double *A, const T *x, T *y,
                                                  const int *stop) {
     if (stop && *stop) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
+    if (row >= rows) return;
     double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc = fma(A[(int64_t)row * n + j], x[j], acc);
+    for (int j = lane; j < cols; j += 64) acc = fma(A[(int64_t)row * cols + j], (double)x[j], acc);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) y[row] = acc;
+    if (lane == 0) y[row] = (T)acc;
 }
 
-void launch_gemv(int n, const double *A, const double *x, double *y, const int *stop, hipStream_t s) {
+template <class T>
+void launch_gemv(int rows, int cols, const double *A, const T *x, T *y, const int *stop, hipStream_t s) {
     const int rows_per = kBlock / 64;
-    hipLaunchKernelGGL(k_gemv, dim3((n + rows_per - 1) / rows_per), dim3(kBlock), 0, s, n, A, x, y, stop);
+    hipLaunchKernelGGL(k_gemv<T>, dim3((rows + rows_per - 1) / rows_per), dim3(kBlock), 0, s, rows, cols, A, x, y,
+                       stop);
 }
 
-__global__ void k_fill(int64_t n, double *x, double v, const int *stop) {
+template <class T>
+__global__ void k_fill(int64_t n, T *x, T v, const int *stop) {
     if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] = v;
 }
-void launch_fill(int64_t n, double *x, double v, const int *stop, hipStream_t s) {
+template <class T>
+void launch_fill(int64_t n, T *x, T v, const int *stop, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v, stop);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v, stop);
 }
+
+__global__ void k_cast(int64_t n, const double *x, float *y, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+void launch_cast(int64_t n, const double *x, float *y, const int *stop, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, y, stop);
+}
+
+// Streamfunction increment from the x-velocity of the FP32 correction:
+// u_x(a, j) = c_{j+1} (psi(a, j+1) - psi(a, j)) with psi(a, 0) = 0, so
+// psi(a, j+1) = psi(a, j) + u_x(a, j) / c_{j+1}.  One thread per column a;
+// psi is stored at (a-1) + (N+k-1) (b-1) for b = 1 .. N+k-1.
+__global__ void k_recover_psi_2d(RefineArgs a) {
+    if (a.stop && *a.stop) return;
+    const int m = a.N + a.k - 1;  // potential functions per direction
+    const int ia = blockIdx.x * kBlock + threadIdx.x;
+    if (ia >= m) return;
+    double ps = 0.0;
+    for (int j = 0; j < m; ++j) {
+        ps += (double)a.X[ia + (int64_t)m * j] / a.dcoef[j + 1];
+        a.psi[ia + (int64_t)m * j] = ps;
+    }
+}
+
+// U += [curl psi; X_p] in FP64, curl psi = (d_y psi, -d_x psi) by the scaled
+// differences of the derivative formula (psi = 0 on the boundary).
+__global__ void k_curl_update_2d(RefineArgs a) {
+    if (a.stop && *a.stop) return;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.n) return;
+    const int m = a.N + a.k - 1, nq = a.N + a.k;
+    auto psi = [&](int pa, int pb) -> double {  // true indices, zero on the boundary
+        if (pa <= 0 || pa >= nq || pb <= 0 || pb >= nq) return 0.0;
+        return a.psi[(pa - 1) + (int64_t)m * (pb - 1)];
+    };
+    double du;
+    if (g < a.off_uy) {  // u_x(a, j): stored (a-1, j), dims m x nq
+        const int ia = (int)(g % m), j = (int)(g / m);
+        du = a.dcoef[j + 1] * (psi(ia + 1, j + 1) - psi(ia + 1, j));
+    } else if (g < a.off_p) {  // u_y(i, b): stored (i, b-1), dims nq x m
+        const int64_t l = g - a.off_uy;
+        const int i = (int)(l % nq), ib = (int)(l / nq);
+        du = -a.dcoef[i + 1] * (psi(i + 1, ib + 1) - psi(i, ib + 1));
+    } else {
+        du = (double)a.X[g];
+    }
+    a.U[g] += du;
+}
+
+void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
+    const int m = a.N + a.k - 1;
+    hipLaunchKernelGGL(k_recover_psi_2d, dim3(blocks_for(m)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+}
+
+template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);
+template void launch_schwarz_gather<float>(const PatchArgsT<float> &, hipStream_t);
+template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
+template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);
+template void launch_csr<double>(int, const int32_t *, const int32_t *, const double *, const double *, double *,
+                                 int, const int *, hipStream_t);
+template void launch_csr<float>(int, const int32_t *, const int32_t *, const float *, const float *, float *, int,
+                                const int *, hipStream_t);
+template void launch_gemv<double>(int, int, const double *, const double *, double *, const int *, hipStream_t);
+template void launch_gemv<float>(int, int, const double *, const float *, float *, const int *, hipStream_t);
+template void launch_fill<double>(int64_t, double *, double, const int *, hipStream_t);
+template void launch_fill<float>(int64_t, float *, float, const int *, hipStream_t);
 
 __global__ void k_fill_int(int n, int *x, int v) {
     const int i = blockIdx.x * kBlock + threadIdx.x;

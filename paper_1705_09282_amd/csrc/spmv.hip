@@ -1,4 +1,5 @@
-// Residual r = F - K U of one level in the stencil-ELL layout (FP64).
+// Residual r = F - K U of one level in the stencil-ELL layout, FP64 or FP32
+// (values, vectors and accumulation all in T).
 #include "device_util.hpp"
 
 namespace dfmg {
@@ -20,16 +21,16 @@ struct Geo {
 // x-offsets; with LPR lanes per matrix row, lane l takes stencil rows
 // l, l + LPR, ...  Slots outside the grid hold 0 and read a clamped (valid)
 // vector entry.  vp points at slot 0 of this block for the current row.
-template <int D, int K, int R, int C, int LPR>
-__device__ __forceinline__ double block_dot(const SpmvArgs &a, int i0, int i1, int i2, int lane, const double *vp,
-                                            int64_t stride) {
+template <int D, int K, int R, int C, int LPR, class T>
+__device__ __forceinline__ T block_dot(const SpmvArgsT<T> &a, int i0, int i1, int i2, int lane, const T *vp,
+                                       int64_t stride) {
     using G = Geo<D, K>;
     constexpr int W0 = G::w(R, C, 0), W1 = G::w(R, C, 1), W2 = G::w(R, C, 2);
     constexpr int L0 = G::lo(R, C, 0), L1 = G::lo(R, C, 1), L2 = G::lo(R, C, 2);
     constexpr int NS = W1 * W2;
-    const double *Uc = a.U + a.off[C];
+    const T *Uc = a.U + a.off[C];
     const int n0 = a.nb[C][0], n1 = a.nb[C][1], n2 = a.nb[C][2];
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int it = 0; it < (NS + LPR - 1) / LPR; ++it) {
         const int sr = it * LPR + lane;
@@ -37,8 +38,8 @@ __device__ __forceinline__ double block_dot(const SpmvArgs &a, int i0, int i1, i
         const int o1 = sr % W1, o2 = sr / W1;
         const int j2 = (D == 3) ? clampi(i2 + L2 + o2, 0, n2 - 1) : 0;
         const int j1 = clampi(i1 + L1 + o1, 0, n1 - 1);
-        const double *urow = Uc + ((int64_t)j2 * n1 + j1) * n0;
-        const double *v = vp + (int64_t)sr * W0 * stride;
+        const T *urow = Uc + ((int64_t)j2 * n1 + j1) * n0;
+        const T *v = vp + (int64_t)sr * W0 * stride;
 #pragma unroll
         for (int o0 = 0; o0 < W0; ++o0) {
             const int j0 = clampi(i0 + L0 + o0, 0, n0 - 1);
@@ -53,32 +54,32 @@ __host__ __device__ constexpr int block_slots() {
     return Geo<D, K>::w(R, C, 0) * Geo<D, K>::w(R, C, 1) * Geo<D, K>::w(R, C, 2);
 }
 
-template <int D, int K, int R, int LPR>
-__device__ __forceinline__ double row_dot(const SpmvArgs &a, int li, int lane) {
+template <int D, int K, int R, int LPR, class T>
+__device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
     const int i0 = li % nb0;
     const int t = li / nb0;
     const int i1 = t % nb1;
     const int i2 = t / nb1;
     const int64_t stride = a.off[R + 1] - a.off[R];
-    const double *vp = a.val + a.val_off[R] + li;
-    double acc;
+    const T *vp = a.val + a.val_off[R] + li;
+    T acc;
     if constexpr (R < D) {
-        acc = block_dot<D, K, R, R, LPR>(a, i0, i1, i2, lane, vp, stride);
-        acc += block_dot<D, K, R, D, LPR>(a, i0, i1, i2, lane, vp + block_slots<D, K, R, R>() * stride, stride);
+        acc = block_dot<D, K, R, R, LPR, T>(a, i0, i1, i2, lane, vp, stride);
+        acc += block_dot<D, K, R, D, LPR, T>(a, i0, i1, i2, lane, vp + block_slots<D, K, R, R>() * stride, stride);
     } else {
         constexpr int s1 = block_slots<D, K, R, 0>(), s2 = s1 + block_slots<D, K, R, 1>();
-        acc = block_dot<D, K, R, 0, LPR>(a, i0, i1, i2, lane, vp, stride);
-        acc += block_dot<D, K, R, 1, LPR>(a, i0, i1, i2, lane, vp + s1 * stride, stride);
-        if constexpr (D == 3) acc += block_dot<D, K, R, 2, LPR>(a, i0, i1, i2, lane, vp + s2 * stride, stride);
+        acc = block_dot<D, K, R, 0, LPR, T>(a, i0, i1, i2, lane, vp, stride);
+        acc += block_dot<D, K, R, 1, LPR, T>(a, i0, i1, i2, lane, vp + s1 * stride, stride);
+        if constexpr (D == 3) acc += block_dot<D, K, R, 2, LPR, T>(a, i0, i1, i2, lane, vp + s2 * stride, stride);
     }
     return acc;
 }
 
 // r = F - K U, optionally with per-block partial sums of r^2.  Each block
 // covers kBlock / LPR rows.
-template <int D, int K, int LPR>
-__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
+template <int D, int K, int LPR, class T>
+__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     // the stop flag is read alongside the operands and only gates the stores,
     // so its load latency overlaps with theirs
     const int halt = a.stop ? *a.stop : 0;
@@ -87,16 +88,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
     const int g = b * (kBlock / LPR) + threadIdx.x / LPR;
     double rr = 0.0;
     const bool active = b < a.nblocks && g < a.n;
-    double acc = 0.0;
+    T acc = 0;
     if (active) {
         if (g < a.off[1]) {
-            acc = row_dot<D, K, 0, LPR>(a, g, lane);
+            acc = row_dot<D, K, 0, LPR, T>(a, g, lane);
         } else if (g < a.off[2]) {
-            acc = row_dot<D, K, 1, LPR>(a, g - (int)a.off[1], lane);
+            acc = row_dot<D, K, 1, LPR, T>(a, g - (int)a.off[1], lane);
         } else if (D == 3 && g < a.off[3]) {
-            acc = row_dot<D, K, (D == 3 ? 2 : 1), LPR>(a, g - (int)a.off[2], lane);
+            acc = row_dot<D, K, (D == 3 ? 2 : 1), LPR, T>(a, g - (int)a.off[2], lane);
         } else {
-            acc = row_dot<D, K, D, LPR>(a, g - (int)a.off[D], lane);
+            acc = row_dot<D, K, D, LPR, T>(a, g - (int)a.off[D], lane);
         }
     }
     // combine the LPR partial dot products of a row (lanes of a row are
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
 #pragma unroll
     for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (active && lane == 0) {
-        const double v = a.F[g] - acc;
+        const T v = a.F[g] - acc;
         if (!halt) a.r[g] = v;
-        rr = v * v;
+        rr = (double)v * (double)v;
     }
     if (a.partial) {
         __shared__ double sh[kBlock / 64];
@@ -115,20 +116,24 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs a) {
     }
 }
 
-template <int D, int K>
-static void launch_dk(const SpmvArgs &a, int lpr, hipStream_t s) {
+template <int D, int K, class T>
+static void launch_dk(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
     const int grid = padded_grid(a.nblocks);
-    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_spmv<D, K, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, T>), dim3(grid), dim3(kBlock), 0, s, a);
+    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, T>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_spmv<D, K, 1, T>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 // a.nblocks must equal spmv_blocks(a.n, lpr)
-void launch_spmv(int d, int k, int lpr, const SpmvArgs &a, hipStream_t s) {
-    if (d == 2 && k == 1) launch_dk<2, 1>(a, lpr, s);
-    else if (d == 2 && k == 2) launch_dk<2, 2>(a, lpr, s);
-    else if (d == 3 && k == 1) launch_dk<3, 1>(a, lpr, s);
-    else launch_dk<3, 2>(a, lpr, s);
+template <class T>
+void launch_spmv(int d, int k, int lpr, const SpmvArgsT<T> &a, hipStream_t s) {
+    if (d == 2 && k == 1) launch_dk<2, 1, T>(a, lpr, s);
+    else if (d == 2 && k == 2) launch_dk<2, 2, T>(a, lpr, s);
+    else if (d == 3 && k == 1) launch_dk<3, 1, T>(a, lpr, s);
+    else launch_dk<3, 2, T>(a, lpr, s);
 }
+
+template void launch_spmv<double>(int, int, int, const SpmvArgsT<double> &, hipStream_t);
+template void launch_spmv<float>(int, int, int, const SpmvArgsT<float> &, hipStream_t);
 
 }  // namespace dfmg

@@ -33,7 +33,8 @@ class Advection(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("nu1", c_int), ("nu2", c_int), ("eta", c_double), ("precision", c_int),
                 ("smoother", c_int), ("max_cycles", c_int), ("use_graph", c_int),
-                ("cycles_per_check", c_int), ("share_inverses", c_int)]
+                ("cycles_per_check", c_int), ("share_inverses", c_int),
+                ("inner_cycles", c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -39,6 +39,10 @@ def test_error_conventions():
         dfmg.Solver(2, 8, 2, 1, nu=0.0)
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(3, 8, 2, 1, c=1.0)     # rotation only in 2D
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(3, 8, 2, 1, precision=1)  # refinement path is 2D
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(2, 8, 2, 1, precision=1, inner_cycles=0)
     s = dfmg.Solver(2, 8, 2, 1)
     code = dfmg.lib().dfmg_vcycle(s._ctx, ctypes.c_void_p(8), ctypes.c_void_p(8), 1)
     assert code == -6                       # not bound yet

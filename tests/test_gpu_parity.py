@@ -239,3 +239,40 @@ def test_full_size_cycles_and_solve(full_size):
     assert st["converged"]
     assert residual_norm(h, Ug, F) <= 1.0000001e-8 * np.linalg.norm(F)
     assert div_norm(h.finest.disc, Ug) < 1e-10
+
+
+@pytest.mark.parametrize("cfg", [workloads.small2d(), workloads.stokes2d(1e-2, N=64, L=5),
+                                 workloads.stokes2d(1e4, N=64, L=5), workloads.oseen2d(0.1, 0.5, N=32, L=4)])
+def test_fp32_refinement_matches_fp64_oracle(cfg):
+    """FP32 V-cycles inside FP64 iterative refinement: converges to the FP64
+    discrete solution (velocity within 1e-8 relative of the oracle's), and the
+    velocity stays divergence-free to FP64 rounding because every update is the
+    curl of a recovered streamfunction increment."""
+    s, h, F = make(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"], cfg["c"], precision=1)
+    Ud = dev(np.zeros_like(F))
+    st = s.solve(dev(F), Ud, tol=1e-10)
+    Uo, hist = solve(h, F, tol=1e-12, max_cycles=400)
+    Ug = host(Ud)
+    nv = h.finest.disc.n_v
+    err = rel_l2(Ug[:nv], Uo[:nv])
+    print(f"[mixed] cycles {st['cycles']} (fp64 oracle to 1e-10: "
+          f"{int(np.argmax(hist <= 1e-10 * np.linalg.norm(F)))}) vel rel err {err:.2e} div {s.div_norm(Ud):.2e}")
+    assert st["converged"]
+    assert residual_norm(h, Ug, F) <= 1.0000001e-10 * np.linalg.norm(F)
+    assert err < 1e-8
+    assert div_norm(h.finest.disc, Ug) < 1e-10 and s.div_norm(Ud) < 1e-10
+    s.close()
+
+
+def test_fp32_refinement_at_benchmark_tolerance():
+    cfg = workloads.stokes2d(1.0, N=64, L=5)
+    s, h, F = make(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"], precision=1)
+    s64 = make(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"])[0]
+    Ud, U64 = dev(np.zeros_like(F)), dev(np.zeros_like(F))
+    st = s.solve(dev(F), Ud, tol=1e-8)
+    st64 = s64.solve(dev(F), U64, tol=1e-8)
+    assert st["converged"] and st["cycles"] <= st64["cycles"] + 1
+    nv = h.finest.disc.n_v
+    assert rel_l2(host(Ud)[:nv], host(U64)[:nv]) < 1e-6
+    s.close()
+    s64.close()

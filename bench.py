@@ -98,26 +98,23 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: {3} copies of {n * 8} bytes", file=sys.stderr, flush=True)
         del src, dst
-    def make_problems(precision):
-        probs = []
-        for sigma in workloads.STOKES2D_SIGMAS:
-            cfg = workloads.stokes2d(sigma, N=args.n_elem, L=args.levels)
-            s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"],
-                       precision=precision).bind(dev)
-            tuning = s.autotune(reps=20)
-            F = torch.tensor(s.manufactured_rhs(), device=dev)
-            U = torch.zeros_like(F)
-            probs.append((sigma, s, F, U, s.sizes(), tuning))
-        return probs
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    sigmas = list(workloads.STOKES2D_SIGMAS)
+    cfg = workloads.stokes2d(1.0, N=args.n_elem, L=args.levels)
 
-    def run(probs):
+    def make_batch(precision):
+        b = BatchSolver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], [cfg["nu"]] * len(sigmas), sigmas,
+                        precision=precision).bind(dev)
+        tuning = b.autotune(reps=20)
+        F = torch.tensor(b.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        return b, F, U, tuning
+
+    def run(b, F, U):
         """warm-up, then the timed steps; returns (seconds, stats of the last step)"""
         def step():
-            out = []
-            for sigma, s, F, U, z, _ in probs:
-                U.zero_()
-                out.append(s.solve(F, U, tol=args.tol))
-            return out
+            U.zero_()
+            return b.solve(F, U, tol=args.tol)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -129,35 +126,41 @@ def main():
         return time.perf_counter() - t0, stats
 
     t_setup = time.perf_counter()
-    plain = make_problems(0)
-    mixed = make_problems(1)
+    b64, F64, U64, tun64 = make_batch(0)
+    b32, F32, U32, tun32 = make_batch(1)
     setup_s = time.perf_counter() - t_setup
-    dofs = sum(z["n"] - 1 for *_, z, _ in plain)
-    print(f"[bench] setup of 2x{len(plain)} problems: {setup_s:.1f} s, DOFs/step {dofs}", file=sys.stderr, flush=True)
+    z = b64.sizes()
+    dofs = len(sigmas) * (z["n"] - 1)
+    print(f"[bench] setup of 2 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
+          file=sys.stderr, flush=True)
 
-    T64, stats64 = run(plain)
-    print(f"[bench] plain FP64: {args.steps} steps in {T64:.3f} s", file=sys.stderr, flush=True)
-    T, stats = run(mixed)
-    print(f"[bench] FP32-refined: {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
+    T64, stats64 = run(b64, F64, U64)
+    print(f"[bench] plain FP64 batch: {args.steps} steps in {T64:.3f} s", file=sys.stderr, flush=True)
+    T, stats = run(b32, F32, U32)
+    print(f"[bench] FP32-refined batch: {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
 
-    # error of the refined solutions against the plain FP64 solutions of the same step
-    import numpy as np
+    n = z["n"]
+    nv = z["n_vel"]
     errs = []
-    for (_, _, _, U64, z, _), (_, _, _, U32, _, _) in zip(plain, mixed):
-        nv = z["n_vel"]
-        a, b = U32[:nv].double(), U64[:nv].double()
-        errs.append(float(torch.linalg.norm(a - b) / torch.linalg.norm(b)))
+    for p in range(len(sigmas)):
+        a = U32[p * n:p * n + nv]
+        ref = U64[p * n:p * n + nv]
+        errs.append(float(torch.linalg.norm(a - ref) / torch.linalg.norm(ref)))
     cycles = [st["cycles"] for st in stats]
-    divs = [s.div_norm(U) for _, s, _, U, _, _ in mixed]
+    divs = [float(x) for x in b32.div_norm(U32)]
     value = args.steps * dofs / T
     value64 = args.steps * dofs / T64
-    probs = plain
-    tuning = plain[-1][5]
+    tuning = tun32
 
-    # roofline of the dominant kernel: finest-grid residual of the sigma = 1 problem
-    _, s1, F1, U1, z1, _ = probs[1]
+    # roofline of the dominant kernel: finest-grid FP64 residual, one problem
+    # (sigma = 1) in its own context so that one launch is one problem
+    s1 = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=1.0).bind(dev)
+    s1.set_tuning(tun64["lpr"], tun64["smoother"])
+    F1 = torch.tensor(s1.manufactured_rhs(), device=dev)
+    U1 = U64[n:2 * n].clone()
     r = torch.empty_like(F1)
     ms = s1.time_residual(args.levels - 1, F1, U1, r, reps=200)
+    z1 = s1.sizes()
     alg_bytes = 8 * z1["nnz"] + 3 * 8 * z1["n"]
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -179,7 +182,7 @@ def main():
             "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
                         f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, V(2,2) additive Schwarz, "
                         f"tol {args.tol:g}, U0=0",
-            "path": "FP32 V-cycles in FP64 iterative refinement (fixed damping)",
+            "path": "batched: FP32 V-cycles in FP64 iterative refinement (fixed damping), 4 problems per launch",
             "dofs_per_step": dofs,
             "cycles_per_sigma": cycles,
             "vcycles_per_s": args.steps * sum(cycles) / T,
@@ -190,7 +193,7 @@ def main():
                            "vcycles_per_s": args.steps * sum(st["cycles"] for st in stats64) / T64},
             "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
-            "tuning_last_problem": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
+            "tuning": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
         },
         "roofline": {
             "bound": "hbm",
@@ -207,7 +210,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.tol)
-    for _, s, _, _, _, _ in plain + mixed:
+    for s in (b64, b32, s1):
         s.close()
     print(json.dumps(line), flush=True)
 

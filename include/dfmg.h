@@ -110,6 +110,19 @@ void dfmg_default_options(dfmg_options *opt);
 int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma,
                const dfmg_advection *adv, const dfmg_options *opt, dfmg_ctx **out);
 
+/* Batch of nprob independent problems on one mesh (same grid and k), with
+ * per-problem nu[p], sigma[p] and adv[p] (adv may be NULL).  Every kernel
+ * launch of the batch covers all problems, which share the mesh data (index
+ * maps, transfer operators).  Vectors of a batch are nprob blocks of the
+ * finest-level length n, problem-major; dfmg_solve, dfmg_vcycle,
+ * dfmg_residual_norm, dfmg_div_norm, the level-wise kernels and
+ * dfmg_manufactured_rhs act on every problem (stats and norms: nprob
+ * entries).  Exports describe the shared mesh data and problem 0's matrix.
+ * dfmg_setup is the batch of one.  Errors: EINVAL. */
+int dfmg_batch_setup(int nprob, const dfmg_grid *grid, int k, const double *nu, const double *sigma,
+                     const dfmg_advection *adv, const dfmg_options *opt, dfmg_ctx **out);
+int dfmg_batch_size(const dfmg_ctx *ctx, int *nprob);
+
 void dfmg_destroy(dfmg_ctx *ctx);
 
 /* Device bytes the caller must provide to dfmg_bind. */
@@ -127,8 +140,9 @@ int dfmg_bind(dfmg_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream
 int dfmg_sizes(const dfmg_ctx *ctx, int level, int64_t *n_vel, int64_t *n_pres,
                int64_t *n_patch, int64_t *nnz);
 
-/* Set one damping per smoothed level, finest first (n = n_levels - 1 values in
- * (0, 1)); replaces the fixed damping for later cycles. */
+/* Set one damping per smoothed level, finest first: n = n_levels - 1 values in
+ * (0, 1) for every problem, or n = nprob * (n_levels - 1) values, problem-major;
+ * replaces the fixed damping for later cycles. */
 int dfmg_set_eta(dfmg_ctx *ctx, const double *eta_host, int n);
 
 /* ncycles applications of Algorithm 1 on the finest level: U <- MGV(U, F).
@@ -138,7 +152,8 @@ int dfmg_vcycle(dfmg_ctx *ctx, const double *F_dev, double *U_dev, int ncycles);
 
 /* Repeat V-cycles from U (device, in/out) until ||F - K U||_2 <= tol ||F||_2
  * (numerical-results protocol, relative to ||F||), then shift the pressure to
- * zero mean.  st may be NULL.  Errors: ENOTCONV, EDIVERGED, ESTATE, EHIP.
+ * zero mean.  st may be NULL (else nprob entries).  Errors: ENOTCONV,
+ * EDIVERGED (worst over the batch), ESTATE, EHIP.
  * With precision 1 each step computes r = F - K U in FP64, applies
  * inner_cycles V-cycles in FP32 (FP32 values, FP32 accumulation, FP64 coarse
  * solve) to K dU = r from dU = 0, recovers the streamfunction increment psi

@@ -1,12 +1,20 @@
 // C-ABI of the library: context, workspace binding, V-cycle orchestration,
 // solve loop, diagnostics and exports.  See include/dfmg.h.
+//
+// A context holds a batch of problems on one mesh (a single problem is a
+// batch of one).  Mesh-only data (index maps, transfer operators, pressure
+// integrals) is stored once; coefficient-dependent data (matrix values, local
+// inverses, coarse inverse, damping) and all vectors are stored per problem
+// with a fixed stride, and every kernel launch covers the whole batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dfmg.h"
@@ -36,21 +44,25 @@ struct ArgError : std::runtime_error {
     } while (0)
 
 // Typed values and vectors of one level: FP64 for the plain path, FP32 for
-// the V-cycle inside the iterative refinement.
+// the V-cycle inside the iterative refinement.  Per problem unless noted.
 template <class T>
 struct LevelData {
     T *val = nullptr, *U = nullptr, *F = nullptr, *r = nullptr, *M = nullptr, *delta = nullptr;
-    T *P_v = nullptr, *R_v = nullptr;
+    T *P_v = nullptr, *R_v = nullptr;  // shared by the batch
 };
 
 struct DevLevel {
     LevelData<double> d;
     LevelData<float> f;
-    int32_t *pptr = nullptr, *pdofs = nullptr, *moff = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr;
-    int4 *ent_info = nullptr;
-    int32_t *col_list = nullptr;
+    // shared by the batch
+    int32_t *pptr = nullptr, *pdofs = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr, *col_list = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
+    // per problem
+    int32_t *moff = nullptr;
+    int4 *ent_info = nullptr;
     double *Kinv = nullptr;
+    // strides
+    int64_t sval = 0, sM = 0, nent = 0, n = 0;
     template <class T>
     LevelData<T> &data();
 };
@@ -76,25 +88,29 @@ struct Arena {
 }  // namespace
 
 struct dfmg_ctx {
-    Hierarchy H;
+    std::vector<Hierarchy> P;  // one per problem, identical meshes
+    int np = 1;
     dfmg_options opt{};
     bool bound = false;
     hipStream_t user = nullptr, s = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<DevLevel> dl;
-    double *eta = nullptr;       // per level
-    double *partial = nullptr;   // per-block partial sums
+    double *eta = nullptr;       // [problem][level]
+    double *partial = nullptr;   // [problem][block]
     int nparts = 0;
-    double *hist = nullptr;
+    double *hist = nullptr;      // [problem][DFMG_MAX_HISTORY]
     int *counter = nullptr, *stop = nullptr;
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
-    double *psi = nullptr;       // refinement: streamfunction increment
+    double *psi = nullptr;       // refinement: streamfunction increments [problem][(N+k-1)^2]
+    int64_t spsi = 0;
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
     std::vector<int> smoother;   // per level: 1 gather, 2 colour
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
-    std::vector<double> eta_host;
+    std::vector<double> eta_host;  // [problem][level]
+    const Hierarchy &S() const { return P[0]; }
+    int L() const { return P[0].pb.L; }
     bool mixed() const { return opt.precision == 1; }
 };
 
@@ -124,69 +140,79 @@ int guarded(F &&f) {
 }
 
 template <class T>
-void take_level(Arena &A, const HostLevel &h, LevelData<T> &v, bool coarse) {
-    v.U = A.take<T>(h.n);
-    v.F = A.take<T>(h.n);
-    v.r = A.take<T>(h.n);
-    v.val = A.take<T>(h.val.size());
+void take_level(Arena &A, const DevLevel &dv, int np, LevelData<T> &v, bool coarse, const HostLevel &h) {
+    v.U = A.take<T>(dv.n * np);
+    v.F = A.take<T>(dv.n * np);
+    v.r = A.take<T>(dv.n * np);
+    v.val = A.take<T>(dv.sval * np);
     if (coarse) return;
-    v.M = A.take<T>(h.M.size());
-    v.delta = A.take<T>(h.pdofs.size());
+    v.M = A.take<T>(dv.sM * np);
+    v.delta = A.take<T>(dv.nent * np);
     v.P_v = A.take<T>(h.P_v.size());
     v.R_v = A.take<T>(h.R_v.size());
 }
 
 void plan(dfmg_ctx *c, Arena &A) {
-    const Hierarchy &H = c->H;
-    const int L = H.pb.L;
+    const Hierarchy &H = c->S();
+    const int L = H.pb.L, np = c->np;
     c->dl.assign(L, DevLevel());
     int maxblocks = 1;
     int64_t nmax = 0;
     for (int l = 0; l < L; ++l) {
         const HostLevel &h = H.lv[l];
         DevLevel &v = c->dl[l];
-        take_level(A, h, v.d, l == 0);
-        if (c->mixed()) take_level(A, h, v.f, l == 0);
+        v.n = h.n;
+        v.sval = (int64_t)h.val.size();
+        v.nent = (int64_t)h.pdofs.size();
+        v.sM = 0;
+        for (const Hierarchy &Q : c->P) v.sM = std::max(v.sM, (int64_t)Q.lv[l].M.size());
+        take_level(A, v, np, v.d, l == 0, h);
+        if (c->mixed()) take_level(A, v, np, v.f, l == 0, h);
         nmax = std::max(nmax, h.n);
         maxblocks = std::max(maxblocks, spmv_blocks(h.n, 4));
         if (l == 0) {
-            v.Kinv = A.take<double>(h.Kinv.size());
+            v.Kinv = A.take<double>(h.Kinv.size() * np);
             continue;
         }
         v.pptr = A.take<int32_t>(h.pptr.size());
         v.pdofs = A.take<int32_t>(h.pdofs.size());
-        v.moff = A.take<int32_t>(h.moff.size());
         v.inv_ptr = A.take<int32_t>(h.inv_ptr.size());
         v.inv_pos = A.take<int32_t>(h.inv_pos.size());
-        v.ent_info = A.take<int4>(h.pdofs.size());
         v.col_list = A.take<int32_t>(h.col_list.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
         v.P_ci = A.take<int32_t>(h.P_ci.size());
         v.R_rp = A.take<int32_t>(h.R_rp.size());
         v.R_ci = A.take<int32_t>(h.R_ci.size());
+        v.moff = A.take<int32_t>(h.n_patch * np);
+        v.ent_info = A.take<int4>(v.nent * np);
     }
     c->nparts = padded_grid(maxblocks);
-    c->eta = A.take<double>(L);
-    c->partial = A.take<double>(c->nparts);
-    c->hist = A.take<double>(DFMG_MAX_HISTORY);
-    c->counter = A.take<int>(1);
-    c->stop = A.take<int>(1);
-    c->thresh2 = A.take<double>(1);
-    c->scal = A.take<double>(4);
+    c->eta = A.take<double>((size_t)L * np);
+    c->partial = A.take<double>((size_t)c->nparts * np);
+    c->hist = A.take<double>((size_t)DFMG_MAX_HISTORY * np);
+    c->counter = A.take<int>(np);
+    c->stop = A.take<int>(np);
+    c->thresh2 = A.take<double>(np);
+    c->scal = A.take<double>(np);
     c->dvec = A.take<double>(H.lv[L - 1].n_q);
     c->dcoef = A.take<double>(H.dcoef.size());
     c->pmass = A.take<double>(H.pmass.size());
-    c->rtmp = A.take<double>(nmax);
+    c->rtmp = A.take<double>((size_t)nmax * np);
     c->wfine = A.take<double>(H.lv[L - 1].n_q);
-    if (c->mixed()) c->psi = A.take<double>((size_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1));
+    c->spsi = (int64_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1);
+    if (c->mixed()) c->psi = A.take<double>((size_t)c->spsi * np);
 }
 
 template <class T>
+void up(T *dst, const T *src, size_t count, hipStream_t s) {
+    if (count) HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
 void up(T *dst, const std::vector<T> &src, hipStream_t s) {
-    if (!src.empty()) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    up(dst, src.data(), src.size(), s);
 }
 
-// FP32 copy of a host array, uploaded synchronously (the staging buffer is local)
+// FP32 copy of a host array (staging buffer is local: synchronous)
 void up32(float *dst, const std::vector<double> &src, hipStream_t s) {
     if (src.empty()) return;
     std::vector<float> tmp(src.begin(), src.end());
@@ -196,9 +222,11 @@ void up32(float *dst, const std::vector<double> &src, hipStream_t s) {
 
 template <class T>
 SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, const int *stop) {
-    const HostLevel &h = c->H.lv[l];
+    const HostLevel &h = c->S().lv[l];
+    const DevLevel &dv = c->dl[l];
     SpmvArgsT<T> a{};
     a.val = c->dl[l].data<T>().val;
+    a.sval = dv.sval;
     for (int R = 0; R < 4; ++R) a.val_off[R] = R < h.nblk ? h.val_off[R] : 0;
     for (int R = 0; R < 5; ++R) a.off[R] = R <= h.nblk ? h.off[R] : h.n;
     for (int R = 0; R < 4; ++R)
@@ -208,27 +236,31 @@ SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double 
     a.F = F;
     a.U = U;
     a.r = r;
+    a.svec = h.n;
     a.partial = partial;
+    a.spart = c->nparts;
     a.stop = stop;
+    a.nprob = c->np;
     return a;
 }
 
-// r = F - K_l U; returns the number of per-block partial sums written
+// r = F - K_l U for every problem; returns the number of per-block partial
+// sums written per problem
 template <class T>
 int spmv(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, const int *stop) {
     const SpmvArgsT<T> a = spmv_args<T>(c, l, F, U, r, partial, stop);
-    launch_spmv<T>(c->H.pb.d, c->H.pb.k, c->lpr[l], a, c->s);
+    launch_spmv<T>(c->S().pb.d, c->S().pb.k, c->lpr[l], a, c->s);
     return a.nblocks;
 }
 
 // eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l.
 template <class T>
 void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop) {
-    const HostLevel &h = c->H.lv[l];
+    const HostLevel &h = c->S().lv[l];
     DevLevel &v = c->dl[l];
     PatchArgsT<T> a{};
     a.n = (int)h.n;
-    a.nent = (int)h.pdofs.size();
+    a.nent = (int)v.nent;
     a.inv_ptr = v.inv_ptr;
     a.inv_pos = v.inv_pos;
     a.pptr = v.pptr;
@@ -240,10 +272,15 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.r = r;
     a.U = U;
     a.eta = c->eta + l;
+    a.smoff = h.n_patch;
+    a.sM = v.sM;
+    a.svec = h.n;
+    a.seta = c->L();
     a.assign = assign ? 1 : 0;
     a.stop = stop;
+    a.nprob = c->np;
     if (c->smoother[l] == 2) {
-        if (assign) launch_fill<T>(h.n, U, T(0), stop, c->s);
+        if (assign) launch_fill<T>(h.n, U, h.n, T(0), stop, c->np, c->s);
         for (size_t col = 0; col + 1 < h.col_ptr.size(); ++col)
             launch_schwarz_colour<T>(a, v.col_list + h.col_ptr[col], h.col_ptr[col + 1] - h.col_ptr[col], c->s);
     } else {
@@ -253,23 +290,28 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
 
 template <class T>
 void restrict_to(dfmg_ctx *c, int l, const T *r, T *G, const int *stop) {
-    const HostLevel &hc = c->H.lv[l - 1];
+    const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
-    launch_csr<T>((int)hc.n, v.R_rp, v.R_ci, v.data<T>().R_v, r, G, 0, stop, c->s);
+    launch_csr<T>((int)hc.n, v.R_rp, v.R_ci, v.data<T>().R_v, r, hf.n, G, hc.n, 0, stop, c->np, c->s);
 }
 
 template <class T>
 void prolong_add(dfmg_ctx *c, int l, const T *dU, T *U, const int *stop) {
-    const HostLevel &h = c->H.lv[l];
+    const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
-    launch_csr<T>((int)h.n, v.P_rp, v.P_ci, v.data<T>().P_v, dU, U, 1, stop, c->s);
+    launch_csr<T>((int)hf.n, v.P_rp, v.P_ci, v.data<T>().P_v, dU, hc.n, U, hf.n, 1, stop, c->np, c->s);
 }
 
 // exact coarse solve (FP64 bordered inverse, FP64 accumulation)
 template <class T>
 void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
-    const int n = (int)c->H.lv[0].n;
-    launch_gemv<T>(n, n, c->dl[0].Kinv, G, dU, stop, c->s);
+    const int64_t n = c->S().lv[0].n;
+    launch_gemv<T>((int)n, (int)n, c->dl[0].Kinv, n * n, G, n, dU, n, stop, c->np, c->s);
+}
+
+void check(dfmg_ctx *c, int np_blocks) {
+    launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->thresh2,
+                 c->np, c->s);
 }
 
 // One V-cycle (Algorithm 1) on the finest level's internal U, F of type T.
@@ -278,20 +320,17 @@ void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
 // step then needs no residual).
 template <class T>
 void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
-    const int L = c->H.pb.L, nu1 = c->opt.nu1, nu2 = c->opt.nu2;
+    const int L = c->L(), nu1 = c->opt.nu1, nu2 = c->opt.nu2;
     const int *stop = c->stop;
     if (L == 1) {
         LevelData<T> &v = c->dl[0].data<T>();
-        if (norm) {
-            const int np = spmv<T>(c, 0, v.F, v.U, v.r, c->partial, stop);
-            launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
-        }
+        if (norm) check(c, spmv<T>(c, 0, v.F, v.U, v.r, c->partial, stop));
         coarse<T>(c, v.F, v.U, stop);  // exact solve of K U = F
         return;
     }
     for (int l = L - 1; l >= 1; --l) {
         LevelData<T> &v = c->dl[l].data<T>();
-        const HostLevel &h = c->H.lv[l];
+        const HostLevel &h = c->S().lv[l];
         bool zero = (l < L - 1) || fine_zero;
         bool first_res = (l == L - 1) && norm;
         for (int s = 0; s < nu1; ++s) {
@@ -300,21 +339,20 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
                 zero = false;
                 continue;
             }
-            const int np = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            const int npb = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
             if (first_res) {
-                launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
+                check(c, npb);
                 first_res = false;
             }
             schwarz<T>(c, l, v.r, v.U, zero, stop);
             zero = false;
         }
         if (zero && !first_res) {
-            launch_fill<T>(h.n, v.U, T(0), stop, c->s);
+            launch_fill<T>(h.n, v.U, h.n, T(0), stop, c->np, c->s);
             restrict_to<T>(c, l, v.F, c->dl[l - 1].data<T>().F, stop);
         } else {
-            const int np = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
-            if (first_res)
-                launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
+            const int npb = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
+            if (first_res) check(c, npb);
             restrict_to<T>(c, l, v.r, c->dl[l - 1].data<T>().F, stop);
         }
     }
@@ -333,16 +371,15 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
 // convergence check), inner_cycles FP32 V-cycles on K dU = r from dU = 0,
 // then U += [curl psi; dU_p] in FP64 with psi recovered from dU_x.
 void refine_body(dfmg_ctx *c) {
-    const int L = c->H.pb.L;
-    const HostLevel &h = c->H.lv[L - 1];
+    const int L = c->L();
+    const HostLevel &h = c->S().lv[L - 1];
     DevLevel &v = c->dl[L - 1];
-    const int np = spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stop);
-    launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
-    launch_cast(h.n, v.d.r, v.f.F, c->stop, c->s);
+    check(c, spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stop));
+    launch_cast(h.n, v.d.r, v.f.F, h.n, c->stop, c->np, c->s);
     for (int i = 0; i < c->opt.inner_cycles; ++i) cycle_body<float>(c, false, i == 0);
     RefineArgs a{};
-    a.N = c->H.pb.N;
-    a.k = c->H.pb.k;
+    a.N = c->S().pb.N;
+    a.k = c->S().pb.k;
     a.off_uy = h.off[1];
     a.off_p = h.off[2];
     a.n = h.n;
@@ -350,7 +387,10 @@ void refine_body(dfmg_ctx *c) {
     a.dcoef = c->dcoef;
     a.psi = c->psi;
     a.U = v.d.U;
+    a.svec = h.n;
+    a.spsi = c->spsi;
     a.stop = c->stop;
+    a.nprob = c->np;
     launch_refine_update_2d(a, c->s);
 }
 
@@ -382,6 +422,13 @@ void run_cycle(dfmg_ctx *c, int kind) {
     HIPCHK(hipGraphLaunch(c->graph, c->s));
 }
 
+void drop_graph(dfmg_ctx *c) {
+    if (c->graph) {
+        HIPCHK(hipGraphExecDestroy(c->graph));
+        c->graph = nullptr;
+    }
+}
+
 // Order the internal stream after the caller's stream, and back.
 void enter(dfmg_ctx *c) {
     if (!c->bound) throw StateError("workspace not bound (call dfmg_bind first)");
@@ -393,15 +440,59 @@ void leave(dfmg_ctx *c) {
     HIPCHK(hipStreamWaitEvent(c->user, c->ev_out, 0));
 }
 
-double read_scalar(dfmg_ctx *c, const double *dev) {
-    double v = 0.0;
-    HIPCHK(hipMemcpyAsync(&v, dev, sizeof(double), hipMemcpyDeviceToHost, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
-    return v;
+void check_level(const dfmg_ctx *c, int level, int minlevel = 0) {
+    if (level < minlevel || level >= c->L()) throw ArgError("level out of range");
 }
 
-void check_level(const dfmg_ctx *c, int level, int minlevel = 0) {
-    if (level < minlevel || level >= c->H.pb.L) throw ArgError("level out of range");
+void upload_eta(dfmg_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->eta, c->eta_host.data(), c->eta_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+}
+
+Problem make_problem(const dfmg_grid *grid, int k, double nu, double sigma, const dfmg_advection *adv,
+                     const dfmg_options &o) {
+    Problem pb;
+    pb.d = grid->dim;
+    pb.N = grid->n_elem;
+    pb.L = grid->n_levels;
+    pb.k = k;
+    pb.nu = nu;
+    pb.sigma = sigma;
+    if (adv) {
+        pb.adv_kind = adv->kind;
+        pb.adv_c = adv->c;
+    }
+    pb.share_inverses = o.share_inverses != 0;
+    return pb;
+}
+
+dfmg_options checked_options(const dfmg_options *opt, int dim) {
+    dfmg_options o;
+    dfmg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 1 || o.cycles_per_check < 1) throw ArgError("invalid options");
+    if (o.max_cycles > DFMG_MAX_HISTORY - 2) throw ArgError("max_cycles too large");
+    if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
+    if (o.precision == 1 && dim != 2) throw ArgError("FP32 refinement is implemented for dim 2");
+    if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
+    if (o.smoother < 0 || o.smoother > 2) throw ArgError("smoother must be 0, 1 or 2");
+    if (o.eta >= 1.0) throw ArgError("eta must be < 1");
+    return o;
+}
+
+void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
+    c->opt = o;
+    const int L = c->L();
+    const double eta0 = o.eta > 0 ? o.eta : c->S().default_eta;
+    c->eta_host.assign((size_t)L * c->np, eta0);
+    for (int p = 0; p < c->np; ++p) c->eta_host[(size_t)p * L] = 0.0;  // level 0: exact solve
+    c->smoother.assign(L, o.smoother == 2 ? 2 : 1);
+    c->lpr.assign(L, 1);
+    for (int l = 0; l < L; ++l) {
+        const int64_t n = c->S().lv[l].n * c->np;
+        c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
+    }
 }
 
 }  // namespace
@@ -426,51 +517,50 @@ const char *dfmg_last_error(void) { return g_err.c_str(); }
 
 int dfmg_setup(const dfmg_grid *grid, int k, double nu, double sigma, const dfmg_advection *adv,
                const dfmg_options *opt, dfmg_ctx **out) {
-    if (!grid || !out) return fail(DFMG_EINVAL, "null argument");
+    return dfmg_batch_setup(1, grid, k, &nu, &sigma, adv, opt, out);
+}
+
+int dfmg_batch_setup(int nprob, const dfmg_grid *grid, int k, const double *nu, const double *sigma,
+                     const dfmg_advection *adv, const dfmg_options *opt, dfmg_ctx **out) {
+    if (!grid || !out || !nu || !sigma) return fail(DFMG_EINVAL, "null argument");
+    if (nprob < 1 || nprob > 65535) return fail(DFMG_EINVAL, "batch size must be in [1, 65535]");
     *out = nullptr;
     return guarded([&] {
-        Problem pb;
-        pb.d = grid->dim;
-        pb.N = grid->n_elem;
-        pb.L = grid->n_levels;
-        pb.k = k;
-        pb.nu = nu;
-        pb.sigma = sigma;
-        if (adv) {
-            pb.adv_kind = adv->kind;
-            pb.adv_c = adv->c;
-        }
-        dfmg_options o;
-        dfmg_default_options(&o);
-        if (opt) o = *opt;
-        if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 1 || o.cycles_per_check < 1)
-            throw ArgError("invalid options");
-        if (o.max_cycles > DFMG_MAX_HISTORY - 2) throw ArgError("max_cycles too large");
-        if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
-        if (o.precision == 1 && pb.d != 2) throw ArgError("FP32 refinement is implemented for dim 2");
-        if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
-        if (o.smoother < 0 || o.smoother > 2) throw ArgError("smoother must be 0, 1 or 2");
-        if (o.eta >= 1.0) throw ArgError("eta must be < 1");
-        pb.share_inverses = o.share_inverses != 0;
+        const dfmg_options o = checked_options(opt, grid->dim);
         auto *c = new dfmg_ctx();
         try {
-            build_hierarchy(pb, c->H);
+            c->np = nprob;
+            c->P.resize(nprob);
+            std::vector<std::string> errs(nprob);
+            const int nth = std::max(1, std::min<int>(nprob, (int)std::thread::hardware_concurrency()));
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nth; ++t)
+                pool.emplace_back([&, t] {
+                    for (int p = t; p < nprob; p += nth) {
+                        try {
+                            build_hierarchy(make_problem(grid, k, nu[p], sigma[p], adv ? adv + p : nullptr, o),
+                                            c->P[p]);
+                        } catch (const std::exception &e) {
+                            errs[p] = e.what();
+                        }
+                    }
+                });
+            for (auto &th : pool) th.join();
+            for (int p = 0; p < nprob; ++p)
+                if (!errs[p].empty()) throw ArgError("problem " + std::to_string(p) + ": " + errs[p]);
         } catch (...) {
             delete c;
             throw;
         }
-        c->opt = o;
-        const double eta0 = o.eta > 0 ? o.eta : c->H.default_eta;
-        c->eta_host.assign(pb.L, eta0);
-        c->eta_host[0] = 0.0;
-        c->smoother.assign(pb.L, o.smoother == 2 ? 2 : 1);
-        c->lpr.assign(pb.L, 1);
-        for (int l = 0; l < pb.L; ++l) {
-            const int64_t n = c->H.lv[l].n;
-            c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
-        }
+        init_ctx(c, o);
         *out = c;
     });
+}
+
+int dfmg_batch_size(const dfmg_ctx *c, int *nprob) {
+    if (!c || !nprob) return fail(DFMG_EINVAL, "null argument");
+    *nprob = c->np;
+    return DFMG_OK;
 }
 
 void dfmg_destroy(dfmg_ctx *c) {
@@ -495,10 +585,10 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
     if (!c || !ws) return fail(DFMG_EINVAL, "null argument");
     if (((uintptr_t)ws) & 255) return fail(DFMG_EINVAL, "workspace must be 256-byte aligned");
     return guarded([&] {
+        if (c->bound) throw StateError("already bound");
         Arena M;
         plan(c, M);
         if (bytes < M.used) throw std::bad_alloc();
-        if (c->bound) throw StateError("already bound");
         Arena A;
         A.base = (char *)ws;
         plan(c, A);
@@ -506,62 +596,65 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         HIPCHK(hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-        const Hierarchy &H = c->H;
+        const Hierarchy &H = c->S();
         hipStream_t s = c->s;
+        const int np = c->np;
         HIPCHK(hipEventRecord(c->ev_in, c->user));
         HIPCHK(hipStreamWaitEvent(s, c->ev_in, 0));
         for (int l = 0; l < H.pb.L; ++l) {
             const HostLevel &h = H.lv[l];
             DevLevel &v = c->dl[l];
-            HIPCHK(hipMemsetAsync(v.d.U, 0, h.n * sizeof(double), s));
-            HIPCHK(hipMemsetAsync(v.d.F, 0, h.n * sizeof(double), s));
-            HIPCHK(hipMemsetAsync(v.d.r, 0, h.n * sizeof(double), s));
-            up(v.d.val, h.val, s);
+            HIPCHK(hipMemsetAsync(v.d.U, 0, v.n * np * sizeof(double), s));
+            HIPCHK(hipMemsetAsync(v.d.F, 0, v.n * np * sizeof(double), s));
+            HIPCHK(hipMemsetAsync(v.d.r, 0, v.n * np * sizeof(double), s));
+            for (int p = 0; p < np; ++p) up(v.d.val + p * v.sval, c->P[p].lv[l].val, s);
             if (c->mixed()) {
-                HIPCHK(hipMemsetAsync(v.f.U, 0, h.n * sizeof(float), s));
-                HIPCHK(hipMemsetAsync(v.f.F, 0, h.n * sizeof(float), s));
-                HIPCHK(hipMemsetAsync(v.f.r, 0, h.n * sizeof(float), s));
-                up32(v.f.val, h.val, s);
+                HIPCHK(hipMemsetAsync(v.f.U, 0, v.n * np * sizeof(float), s));
+                HIPCHK(hipMemsetAsync(v.f.F, 0, v.n * np * sizeof(float), s));
+                HIPCHK(hipMemsetAsync(v.f.r, 0, v.n * np * sizeof(float), s));
+                for (int p = 0; p < np; ++p) {
+                    up32(v.f.val + p * v.sval, c->P[p].lv[l].val, s);
+                    if (l > 0) up32(v.f.M + p * v.sM, c->P[p].lv[l].M, s);
+                }
                 if (l > 0) {
-                    up32(v.f.M, h.M, s);
                     up32(v.f.P_v, h.P_v, s);
                     up32(v.f.R_v, h.R_v, s);
                 }
             }
             if (l == 0) {
-                up(v.Kinv, h.Kinv, s);
+                for (int p = 0; p < np; ++p) up(v.Kinv + p * h.Kinv.size(), c->P[p].lv[0].Kinv, s);
                 continue;
             }
             up(v.pptr, h.pptr, s);
             up(v.pdofs, h.pdofs, s);
-            up(v.moff, h.moff, s);
             up(v.inv_ptr, h.inv_ptr, s);
             up(v.inv_pos, h.inv_pos, s);
-            {
-                std::vector<int4> info(h.pdofs.size());
-                for (int64_t p = 0; p < h.n_patch; ++p) {
-                    const int nn = h.pptr[p + 1] - h.pptr[p];
-                    for (int m = 0; m < nn; ++m)
-                        info[h.pptr[p] + m] = make_int4(h.moff[p] + m * nn, h.pptr[p], nn, 0);
-                }
-                up(v.ent_info, info, s);
-                HIPCHK(hipStreamSynchronize(s));  // info is a local host buffer
-            }
             up(v.col_list, h.col_list, s);
-            up(v.d.M, h.M, s);
+            up(v.d.P_v, h.P_v, s);
+            up(v.d.R_v, h.R_v, s);
             up(v.P_rp, h.P_rp, s);
             up(v.P_ci, h.P_ci, s);
-            up(v.d.P_v, h.P_v, s);
             up(v.R_rp, h.R_rp, s);
             up(v.R_ci, h.R_ci, s);
-            up(v.d.R_v, h.R_v, s);
+            std::vector<int4> info(v.nent);
+            for (int p = 0; p < np; ++p) {
+                const HostLevel &hp = c->P[p].lv[l];
+                up(v.d.M + p * v.sM, hp.M, s);
+                up(v.moff + p * h.n_patch, hp.moff, s);
+                for (int64_t q = 0; q < h.n_patch; ++q) {
+                    const int nn = h.pptr[q + 1] - h.pptr[q];
+                    for (int m = 0; m < nn; ++m) info[h.pptr[q] + m] = make_int4(hp.moff[q] + m * nn, h.pptr[q], nn, 0);
+                }
+                up(v.ent_info + p * v.nent, info, s);
+                HIPCHK(hipStreamSynchronize(s));  // info is reused for the next problem
+            }
         }
         up(c->eta, c->eta_host, s);
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
-        HIPCHK(hipMemsetAsync(c->stop, 0, sizeof(int), s));
-        HIPCHK(hipMemsetAsync(c->counter, 0, sizeof(int), s));
+        HIPCHK(hipMemsetAsync(c->stop, 0, np * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(c->counter, 0, np * sizeof(int), s));
         HIPCHK(hipStreamSynchronize(s));
         c->bound = true;
     });
@@ -571,7 +664,7 @@ int dfmg_sizes(const dfmg_ctx *c, int level, int64_t *n_vel, int64_t *n_pres, in
     if (!c) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level);
-        const HostLevel &h = c->H.lv[level];
+        const HostLevel &h = c->S().lv[level];
         if (n_vel) *n_vel = h.n_v;
         if (n_pres) *n_pres = h.n_q;
         if (n_patch) *n_patch = h.n_patch;
@@ -587,15 +680,17 @@ int dfmg_sizes(const dfmg_ctx *c, int level, int64_t *n_vel, int64_t *n_pres, in
 int dfmg_set_eta(dfmg_ctx *c, const double *eta, int n) {
     if (!c || !eta) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
-        const int L = c->H.pb.L;
-        if (n != L - 1) throw ArgError("need n_levels - 1 dampings");
+        const int L = c->L(), m = L - 1;
+        if (n != m && n != m * c->np) throw ArgError("need n_levels - 1 dampings, or that many per problem");
         for (int i = 0; i < n; ++i)
             if (!(eta[i] > 0.0 && eta[i] < 1.0)) throw ArgError("damping must lie in (0, 1)");
-        for (int i = 0; i < n; ++i) c->eta_host[L - 1 - i] = eta[i];
+        for (int p = 0; p < c->np; ++p) {
+            const double *e = (n == m) ? eta : eta + (size_t)p * m;
+            for (int i = 0; i < m; ++i) c->eta_host[(size_t)p * L + (L - 1 - i)] = e[i];
+        }
         if (c->bound) {
             enter(c);
-            HIPCHK(hipMemcpyAsync(c->eta, c->eta_host.data(), L * sizeof(double), hipMemcpyHostToDevice, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
+            upload_eta(c);
             leave(c);
         }
     });
@@ -606,14 +701,14 @@ int dfmg_vcycle(dfmg_ctx *c, const double *F, double *U, int ncycles) {
     if (ncycles < 0) return fail(DFMG_EINVAL, "ncycles < 0");
     return guarded([&] {
         enter(c);
-        const int L = c->H.pb.L;
-        const int64_t n = c->H.lv[L - 1].n;
+        const int L = c->L(), np = c->np;
+        const int64_t n = c->S().lv[L - 1].n;
         LevelData<double> &v = c->dl[L - 1].d;
-        launch_fill_int(1, c->stop, 0, c->s);
-        launch_copy(n, F, v.F, nullptr, c->s);
-        launch_copy(n, U, v.U, nullptr, c->s);
+        launch_fill_int(np, c->stop, 0, c->s);
+        launch_copy(n, F, n, v.F, n, nullptr, np, c->s);
+        launch_copy(n, U, n, v.U, n, nullptr, np, c->s);
         for (int i = 0; i < ncycles; ++i) run_cycle(c, 0);
-        launch_copy(n, v.U, U, nullptr, c->s);
+        launch_copy(n, v.U, n, U, n, nullptr, np, c->s);
         HIPCHK(hipGetLastError());
         leave(c);
     });
@@ -623,10 +718,13 @@ int dfmg_residual_norm(dfmg_ctx *c, const double *F, const double *U, double *ou
     if (!c || !F || !U || !out) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         enter(c);
-        const int L = c->H.pb.L;
+        const int L = c->L();
         const int nb = spmv<double>(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
-        launch_reduce(nb, c->partial, c->scal, 1.0, c->s);
-        *out = std::sqrt(read_scalar(c, c->scal));
+        launch_reduce(nb, c->partial, c->nparts, c->scal, 1.0, c->np, c->s);
+        std::vector<double> v(c->np);
+        HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(v[p]);
         leave(c);
     });
 }
@@ -635,27 +733,31 @@ int dfmg_div_norm(dfmg_ctx *c, const double *U, double *out) {
     if (!c || !U || !out) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         enter(c);
-        const Hierarchy &H = c->H;
+        const Hierarchy &H = c->S();
         const HostLevel &h = H.lv[H.pb.L - 1];
-        DivArgs a{};
-        a.d = H.pb.d;
-        a.k = H.pb.k;
-        a.N = H.pb.N;
-        for (int R = 0; R < 4; ++R) {
-            a.off[R] = R <= h.nblk ? h.off[R] : 0;
-            for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
+        for (int p = 0; p < c->np; ++p) {
+            DivArgs a{};
+            a.d = H.pb.d;
+            a.k = H.pb.k;
+            a.N = H.pb.N;
+            for (int R = 0; R < 4; ++R) {
+                a.off[R] = R <= h.nblk ? h.off[R] : 0;
+                for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
+            }
+            a.U = U + p * h.n;
+            a.dcoef = c->dcoef;
+            a.pmass = c->pmass;
+            a.dvec = c->dvec;
+            a.partial = c->partial;
+            launch_div(a, c->s);
+            const int nb = blocks_for(h.n_q);
+            launch_div_mass(a, nb, c->s);
+            launch_reduce(nb, c->partial, 0, c->scal + p, 1.0, 1, c->s);
         }
-        a.U = U;
-        a.dcoef = c->dcoef;
-        a.pmass = c->pmass;
-        a.dvec = c->dvec;
-        a.partial = c->partial;
-        launch_div(a, c->s);
-        const int nb = blocks_for(h.n_q);
-        launch_div_mass(a, nb, c->s);
-        launch_reduce(nb, c->partial, c->scal, 1.0, c->s);
-        const double v = read_scalar(c, c->scal);
-        *out = std::sqrt(std::max(0.0, v));
+        std::vector<double> v(c->np);
+        HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(std::max(0.0, v[p]));
         leave(c);
     });
 }
@@ -664,71 +766,82 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
     if (!c || !F || !U) return fail(DFMG_EINVAL, "null argument");
     if (!(tol > 0.0)) return fail(DFMG_EINVAL, "tol must be positive");
     int status = DFMG_OK;
-    dfmg_stats local{};
+    std::vector<dfmg_stats> local;
     int rc = guarded([&] {
         enter(c);
         const auto t0 = std::chrono::steady_clock::now();
-        const int L = c->H.pb.L;
-        const HostLevel &h = c->H.lv[L - 1];
+        const int L = c->L(), np = c->np;
+        const HostLevel &h = c->S().lv[L - 1];
         const int64_t n = h.n;
         LevelData<double> &v = c->dl[L - 1].d;
         const int nb = blocks_for(n);
         const int kind = c->mixed() ? 2 : 1;
-        launch_fill_int(1, c->stop, 0, c->s);
-        launch_fill_int(1, c->counter, 0, c->s);
-        launch_copy(n, F, v.F, nullptr, c->s);
-        launch_copy(n, U, v.U, nullptr, c->s);
-        launch_dot_partial((int)n, v.F, v.F, c->partial, nb, c->s);
-        launch_reduce(nb, c->partial, c->thresh2, tol * tol, c->s);
+        launch_fill_int(np, c->stop, 0, c->s);
+        launch_fill_int(np, c->counter, 0, c->s);
+        launch_copy(n, F, n, v.F, n, nullptr, np, c->s);
+        launch_copy(n, U, n, v.U, n, nullptr, np, c->s);
+        launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
+        launch_reduce(nb, c->partial, c->nparts, c->thresh2, tol * tol, np, c->s);
         const int maxc = c->opt.max_cycles;
-        int launched = 0, counter = 0, stopv = 0;
+        std::vector<int> stopv(np, 0), counter(np, 0);
+        auto read_flags = [&] {
+            HIPCHK(hipMemcpyAsync(counter.data(), c->counter, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipMemcpyAsync(stopv.data(), c->stop, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
+            for (int x : stopv)
+                if (!x) return false;
+            return true;
+        };
+        int launched = 0;
+        bool all = false;
         while (launched < maxc) {
             const int chunk = std::min(c->opt.cycles_per_check, maxc - launched);
             for (int i = 0; i < chunk; ++i) run_cycle(c, kind);
             launched += chunk;
-            int hv[2];
-            HIPCHK(hipMemcpyAsync(&hv[0], c->counter, sizeof(int), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipMemcpyAsync(&hv[1], c->stop, sizeof(int), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
-            counter = hv[0];
-            stopv = hv[1];
-            if (stopv) break;
+            if ((all = read_flags())) break;
         }
-        if (!stopv) {
-            // limit reached: measure the residual of the last iterate
-            const int np = spmv<double>(c, L - 1, v.F, v.U, v.r, c->partial, nullptr);
-            launch_check(np, c->partial, c->hist, c->counter, c->stop, c->thresh2, DFMG_MAX_HISTORY, c->s);
-            int hv[2];
-            HIPCHK(hipMemcpyAsync(&hv[0], c->counter, sizeof(int), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipMemcpyAsync(&hv[1], c->stop, sizeof(int), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipStreamSynchronize(c->s));
-            counter = hv[0];
-            stopv = hv[1];
+        if (!all) {
+            // limit reached: measure the residual of the last iterates (problems
+            // already stopped keep their flags and histories)
+            check(c, spmv<double>(c, L - 1, v.F, v.U, v.r, c->partial, nullptr));
+            read_flags();
         }
         // zero-mean pressure: p <- p - (w^T p) 1 (partition of unity, |Omega| = 1)
-        launch_dot_partial((int)h.n_q, v.U + h.n_v, c->wfine, c->partial, blocks_for(h.n_q), c->s);
-        launch_reduce(blocks_for(h.n_q), c->partial, c->scal, 1.0, c->s);
-        launch_sub_scalar((int)h.n_q, v.U + h.n_v, c->scal, c->s);
-        launch_copy(n, v.U, U, nullptr, c->s);
-        local.cycles = counter - 1;
-        local.converged = stopv == 1;
-        std::vector<double> hist(std::min(counter, DFMG_MAX_HISTORY));
+        const int nbq = blocks_for(h.n_q);
+        for (int p = 0; p < np; ++p)
+            launch_dot_partial((int)h.n_q, v.U + p * n + h.n_v, c->wfine, 0, c->partial + p * c->nparts, 0, nbq, 1,
+                               c->s);
+        launch_reduce(nbq, c->partial, c->nparts, c->scal, 1.0, np, c->s);
+        launch_sub_scalar((int)h.n_q, v.U + h.n_v, n, c->scal, np, c->s);
+        launch_copy(n, v.U, n, U, n, nullptr, np, c->s);
+        std::vector<double> hist((size_t)np * DFMG_MAX_HISTORY), th(np);
         HIPCHK(hipMemcpyAsync(hist.data(), c->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
-        HIPCHK(hipMemcpyAsync(&local.fnorm, c->thresh2, sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipMemcpyAsync(th.data(), c->thresh2, np * sizeof(double), hipMemcpyDeviceToHost, c->s));
         HIPCHK(hipStreamSynchronize(c->s));
-        local.fnorm = std::sqrt(local.fnorm) / tol;
-        local.n_history = (int)hist.size();
-        for (size_t i = 0; i < hist.size(); ++i) local.history[i] = hist[i];
-        local.res0 = hist.empty() ? 0.0 : hist[0];
-        local.res_final = hist.empty() ? 0.0 : hist.back();
-        local.rho = (local.cycles > 0 && local.res0 > 0) ? std::pow(local.res_final / local.res0, 1.0 / local.cycles)
-                                                          : 0.0;
-        status = stopv == 1 ? DFMG_OK : (stopv == 2 ? DFMG_EDIVERGED : DFMG_ENOTCONV);
-        local.status = status;
-        local.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        local.assign(np, dfmg_stats{});
+        int worst = DFMG_OK;
+        for (int p = 0; p < np; ++p) {
+            dfmg_stats &S = local[p];
+            const int cnt = std::min(counter[p], DFMG_MAX_HISTORY);
+            S.cycles = counter[p] - 1;
+            S.converged = stopv[p] == 1;
+            S.fnorm = std::sqrt(th[p]) / tol;
+            S.n_history = cnt;
+            for (int i = 0; i < cnt; ++i) S.history[i] = hist[(size_t)p * DFMG_MAX_HISTORY + i];
+            S.res0 = cnt ? S.history[0] : 0.0;
+            S.res_final = cnt ? S.history[cnt - 1] : 0.0;
+            S.rho = (S.cycles > 0 && S.res0 > 0) ? std::pow(S.res_final / S.res0, 1.0 / S.cycles) : 0.0;
+            S.status = stopv[p] == 1 ? DFMG_OK : (stopv[p] == 2 ? DFMG_EDIVERGED : DFMG_ENOTCONV);
+            S.solve_seconds = secs;
+            if (S.status == DFMG_EDIVERGED) worst = DFMG_EDIVERGED;
+            else if (S.status == DFMG_ENOTCONV && worst == DFMG_OK) worst = DFMG_ENOTCONV;
+        }
+        status = worst;
         leave(c);
     });
-    if (st) *st = local;
+    if (st)
+        for (size_t p = 0; p < local.size(); ++p) st[p] = local[p];
     if (rc != DFMG_OK) return rc;
     if (status == DFMG_ENOTCONV) return fail(status, "maximum number of V-cycles reached");
     if (status == DFMG_EDIVERGED) return fail(status, "residual diverged (NaN/Inf or growth)");
@@ -738,7 +851,7 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
 int dfmg_level_residual(dfmg_ctx *c, int level, const double *F, const double *U, double *r) {
     if (!c || !F || !U || !r) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
-        check_level(c, level, 1);
+        check_level(c, level, 0);
         enter(c);
         spmv<double>(c, level, F, U, r, nullptr, nullptr);
         leave(c);
@@ -812,7 +925,7 @@ int dfmg_coarse_solve(dfmg_ctx *c, const double *G, double *dU) {
 
 int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
-    for (int l = 0; l < c->H.pb.L; ++l) {
+    for (int l = 0; l < c->L(); ++l) {
         lpr[l] = c->lpr[l];
         smoother[l] = c->smoother[l];
     }
@@ -821,18 +934,15 @@ int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
 
 int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
-    for (int l = 0; l < c->H.pb.L; ++l)
+    for (int l = 0; l < c->L(); ++l)
         if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] == 1 || smoother[l] == 2))
             return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1 or 2");
     return guarded([&] {
-        for (int l = 0; l < c->H.pb.L; ++l) {
+        for (int l = 0; l < c->L(); ++l) {
             c->lpr[l] = lpr[l];
             c->smoother[l] = smoother[l];
         }
-        if (c->graph) {
-            HIPCHK(hipGraphExecDestroy(c->graph));
-            c->graph = nullptr;
-        }
+        drop_graph(c);
     });
 }
 
@@ -853,7 +963,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
             HIPCHK(hipEventElapsedTime(&t, e0, e1));
             return (double)t / reps;
         };
-        const int L = c->H.pb.L;
+        const int L = c->L();
         // the variants are timed in the precision the V-cycles run in
         auto tune = [&](auto zero) {
             using T = decltype(zero);
@@ -889,17 +999,14 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 if (ms_out) ms_out[2 * l + 1] = bests;
                 // the timing runs added corrections to U_l: restore zeros (the
                 // internal U is reloaded or reset by every cycle)
-                launch_fill<T>(c->H.lv[l].n, v.U, T(0), nullptr, c->s);
+                launch_fill<T>(c->S().lv[l].n, v.U, c->S().lv[l].n, T(0), nullptr, c->np, c->s);
             }
         };
         if (c->mixed()) tune(0.0f);
         else tune(0.0);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (c->graph) {
-            HIPCHK(hipGraphExecDestroy(c->graph));
-            c->graph = nullptr;
-        }
+        drop_graph(c);
         HIPCHK(hipStreamSynchronize(c->s));
         leave(c);
     });
@@ -909,9 +1016,10 @@ int dfmg_export_matrix(const dfmg_ctx *c, int level, int64_t *rowptr, int32_t *c
     if (!c || !rowptr || !col || !val) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level);
-        const HostLevel &h = c->H.lv[level];
-        const int d = c->H.pb.d;
-        BlockGeom G{d, c->H.pb.k};
+        const Hierarchy &H = c->S();
+        const HostLevel &h = H.lv[level];
+        const int d = H.pb.d;
+        BlockGeom G{d, H.pb.k};
         int64_t nz = 0;
         rowptr[0] = 0;
         for (int R = 0; R <= d; ++R) {
@@ -943,7 +1051,7 @@ int dfmg_export_matrix(const dfmg_ctx *c, int level, int64_t *rowptr, int32_t *c
                                 if (!ok) continue;
                                 const int64_t gcol =
                                     h.off[C] + js[0] + (int64_t)h.nb[C][0] * (js[1] + (int64_t)h.nb[C][1] * js[2]);
-                                const double x = level_entry(c->H, level, grow, gcol);
+                                const double x = level_entry(H, level, grow, gcol);
                                 if (x == 0.0) continue;
                                 col[nz] = (int32_t)gcol;
                                 val[nz] = x;
@@ -960,7 +1068,7 @@ int dfmg_patch_total(const dfmg_ctx *c, int level, int64_t *total) {
     if (!c || !total) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level, 1);
-        *total = (int64_t)c->H.lv[level].pdofs.size();
+        *total = (int64_t)c->S().lv[level].pdofs.size();
     });
 }
 
@@ -968,7 +1076,7 @@ int dfmg_export_patches(const dfmg_ctx *c, int level, int64_t *ptr, int32_t *dof
     if (!c || !ptr || !dofs || !color) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level, 1);
-        const HostLevel &h = c->H.lv[level];
+        const HostLevel &h = c->S().lv[level];
         for (size_t i = 0; i < h.pptr.size(); ++i) ptr[i] = h.pptr[i];
         std::memcpy(dofs, h.pdofs.data(), h.pdofs.size() * sizeof(int32_t));
         std::memcpy(color, h.color.data(), h.color.size() * sizeof(int32_t));
@@ -979,7 +1087,7 @@ int dfmg_prolongation_nnz(const dfmg_ctx *c, int level, int64_t *nnz) {
     if (!c || !nnz) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level, 1);
-        *nnz = (int64_t)c->H.lv[level].P_ci.size();
+        *nnz = (int64_t)c->S().lv[level].P_ci.size();
     });
 }
 
@@ -987,7 +1095,7 @@ int dfmg_export_prolongation(const dfmg_ctx *c, int level, int64_t *rowptr, int3
     if (!c || !rowptr || !col || !val) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         check_level(c, level, 1);
-        const HostLevel &h = c->H.lv[level];
+        const HostLevel &h = c->S().lv[level];
         for (size_t i = 0; i < h.P_rp.size(); ++i) rowptr[i] = h.P_rp[i];
         std::memcpy(col, h.P_ci.data(), h.P_ci.size() * sizeof(int32_t));
         std::memcpy(val, h.P_v.data(), h.P_v.size() * sizeof(double));
@@ -996,7 +1104,10 @@ int dfmg_export_prolongation(const dfmg_ctx *c, int level, int64_t *rowptr, int3
 
 int dfmg_manufactured_rhs(const dfmg_ctx *c, double *F) {
     if (!c || !F) return fail(DFMG_EINVAL, "null argument");
-    return guarded([&] { manufactured_rhs(c->H, F); });
+    return guarded([&] {
+        const int64_t n = c->S().lv[c->L() - 1].n;
+        for (int p = 0; p < c->np; ++p) manufactured_rhs(c->P[p], F + p * n);
+    });
 }
 
 }  // extern "C"

@@ -8,14 +8,16 @@ namespace dfmg {
 // t = pptr[p] + m, and computes delta_t = (M_p E_p r)_m.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
-    const int halt = a.stop ? *a.stop : 0;
+    const int prob = blockIdx.y;
+    const int halt = a.stop ? a.stop[prob] : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int t = b * kBlock + threadIdx.x;
     if (t >= a.nent) return;
     // descriptor of entry t: offset of its row of M, first entry of its
     // subdomain, subdomain size
-    const int4 info = a.ent_info[t];
-    const T *m = a.M + info.x;
+    const int4 info = a.ent_info[(int64_t)prob * a.nent + t];
+    const T *m = a.M + prob * a.sM + info.x;
+    const T *r = a.r + prob * a.svec;
     const int32_t *dofs = a.pdofs + info.y;
     const int nn = info.z;
     // chunks of 8 independent gathers; the tail is padded with zero
@@ -31,23 +33,26 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
             mv[u] = ok ? m[c + u] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) rv[u] = a.r[d[u]];
+        for (int u = 0; u < 8; ++u) rv[u] = r[d[u]];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
     }
-    if (!halt) a.delta[t] = acc;
+    if (!halt) a.delta[(int64_t)prob * a.nent + t] = acc;
 }
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
 // subdomain holding DOF j (fixed order, no atomics).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
-    const int halt = a.stop ? *a.stop : 0;
+    const int prob = blockIdx.y;
+    const int halt = a.stop ? a.stop[prob] : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     if (j >= a.n) return;
-    const T eta = (T)*a.eta;
-    const T u = a.assign ? T(0) : a.U[j];
+    T *U = a.U + prob * a.svec;
+    const T *delta = a.delta + (int64_t)prob * a.nent;
+    const T eta = (T)a.eta[prob * a.seta];
+    const T u = a.assign ? T(0) : U[j];
     T acc = 0;
     const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
     for (int e = e0; e < e1; e += 4) {
@@ -56,17 +61,17 @@ __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
         for (int v = 0; v < 4; ++v) pos[v] = a.inv_pos[e + v < e1 ? e + v : e];
         T dv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dv[v] = a.delta[pos[v]];
+        for (int v = 0; v < 4; ++v) dv[v] = delta[pos[v]];
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : T(0);
     }
-    if (!halt) a.U[j] = fma(eta, acc, u);
+    if (!halt) U[j] = fma(eta, acc, u);
 }
 
 template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_patch_solve<T>, dim3(padded_grid(blocks_for(a.nent))), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n))), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_patch_solve<T>, dim3(padded_grid(blocks_for(a.nent)), a.nprob), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
@@ -74,37 +79,44 @@ void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
 // read-modify-writes.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgsT<T> a, const int32_t *list, int np) {
-    if (a.stop && *a.stop) return;
+    const int prob = blockIdx.y;
+    if (a.stop && a.stop[prob]) return;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= np) return;
     const int p = list[t];
     const int base = a.pptr[p];
     const int nn = a.pptr[p + 1] - base;
     const int32_t *dofs = a.pdofs + base;
-    const T *m = a.M + a.moff[p];
-    const T eta = (T)*a.eta;
+    const T *m = a.M + prob * a.sM + a.moff[prob * a.smoff + p];
+    const T *r = a.r + prob * a.svec;
+    T *U = a.U + prob * a.svec;
+    const T eta = (T)a.eta[prob * a.seta];
     for (int row = 0; row < nn; ++row) {
         T acc = 0;
-        for (int c = 0; c < nn; ++c) acc = fma(m[row * nn + c], a.r[dofs[c]], acc);
+        for (int c = 0; c < nn; ++c) acc = fma(m[row * nn + c], r[dofs[c]], acc);
         const int g = dofs[row];
-        a.U[g] = fma(eta, acc, a.U[g]);
+        U[g] = fma(eta, acc, U[g]);
     }
 }
 
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s) {
     if (np <= 0) return;
-    hipLaunchKernelGGL(k_schwarz_colour<T>, dim3(blocks_for(np)), dim3(kBlock), 0, s, a, list, np);
+    hipLaunchKernelGGL(k_schwarz_colour<T>, dim3(blocks_for(np), a.nprob), dim3(kBlock), 0, s, a, list, np);
 }
 
 // y = (add ? y : 0) + A x for a CSR matrix (restriction and prolongation).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v,
-                                                const T *x, T *y, int add, const int *stop) {
-    const int halt = stop ? *stop : 0;
+                                                const T *x, int64_t sx, T *y, int64_t sy, int add,
+                                                const int *stop) {
+    const int prob = blockIdx.y;
+    const int halt = stop ? stop[prob] : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
+    x += prob * sx;
+    y += prob * sy;
     const T y0 = add ? y[i] : T(0);
     T acc = 0;
     const int e0 = rp[i], e1 = rp[i + 1];
@@ -126,83 +138,109 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, co
 }
 
 template <class T>
-void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, T *y, int add,
-                const int *stop, hipStream_t s) {
-    const int grid = padded_grid(blocks_for(nrows));
-    hipLaunchKernelGGL(k_csr<T>, dim3(grid), dim3(kBlock), 0, s, nrows, rp, ci, v, x, y, add, stop);
+void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int64_t sx, T *y,
+                int64_t sy, int add, const int *stop, int nprob, hipStream_t s) {
+    const dim3 grid(padded_grid(blocks_for(nrows)), nprob);
+    hipLaunchKernelGGL(k_csr<T>, grid, dim3(kBlock), 0, s, nrows, rp, ci, v, x, sx, y, sy, add, stop);
 }
 
 // Dense y = A x (A FP64, row-major rows x cols), one wavefront per row, FP64
 // accumulation.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const double *A, const T *x, T *y,
-                                                 const int *stop) {
-    if (stop && *stop) return;
+__global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const double *A, int64_t sA, const T *x,
+                                                 int64_t sx, T *y, int64_t sy, const int *stop) {
+    const int prob = blockIdx.y;
+    if (stop && stop[prob]) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
+    A += prob * sA;
+    x += prob * sx;
     double acc = 0.0;
     for (int j = lane; j < cols; j += 64) acc = fma(A[(int64_t)row * cols + j], (double)x[j], acc);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) y[row] = (T)acc;
+    if (lane == 0) y[prob * sy + row] = (T)acc;
 }
 
 template <class T>
-void launch_gemv(int rows, int cols, const double *A, const T *x, T *y, const int *stop, hipStream_t s) {
+void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, int64_t sx, T *y, int64_t sy,
+                 const int *stop, int nprob, hipStream_t s) {
     const int rows_per = kBlock / 64;
-    hipLaunchKernelGGL(k_gemv<T>, dim3((rows + rows_per - 1) / rows_per), dim3(kBlock), 0, s, rows, cols, A, x, y,
-                       stop);
+    hipLaunchKernelGGL(k_gemv<T>, dim3((rows + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, rows, cols, A,
+                       sA, x, sx, y, sy, stop);
 }
 
 template <class T>
-__global__ void k_fill(int64_t n, T *x, T v, const int *stop) {
-    if (stop && *stop) return;
+__global__ void k_fill(int64_t n, T *x, int64_t sx, T v, const int *stop) {
+    const int prob = blockIdx.y;
+    if (stop && stop[prob]) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = v;
+    if (i < n) x[prob * sx + i] = v;
 }
 template <class T>
-void launch_fill(int64_t n, T *x, T v, const int *stop, hipStream_t s) {
+void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v, stop);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, sx, v, stop);
 }
 
-__global__ void k_cast(int64_t n, const double *x, float *y, const int *stop) {
-    if (stop && *stop) return;
+__global__ void k_cast(int64_t n, const double *x, float *y, int64_t sv, const int *stop) {
+    const int prob = blockIdx.y;
+    if (stop && stop[prob]) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) y[i] = (float)x[i];
+    if (i < n) y[prob * sv + i] = (float)x[prob * sv + i];
 }
-void launch_cast(int64_t n, const double *x, float *y, const int *stop, hipStream_t s) {
+void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, y, stop);
+    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, y, svec, stop);
 }
 
 // Streamfunction increment from the x-velocity of the FP32 correction:
 // u_x(a, j) = c_{j+1} (psi(a, j+1) - psi(a, j)) with psi(a, 0) = 0, so
-// psi(a, j+1) = psi(a, j) + u_x(a, j) / c_{j+1}.  One thread per column a;
-// psi is stored at (a-1) + (N+k-1) (b-1) for b = 1 .. N+k-1.
-__global__ void k_recover_psi_2d(RefineArgs a) {
-    if (a.stop && *a.stop) return;
+// psi(a, j+1) = psi(a, j) + u_x(a, j) / c_{j+1}, a prefix sum along y.  One
+// block per column a: each thread sums a contiguous chunk, the chunk totals
+// are scanned in LDS (fixed order), then every chunk is written with its
+// offset.  psi is stored at (a-1) + (N+k-1) (b-1) for b = 1 .. N+k-1.
+__global__ __launch_bounds__(kBlock) void k_recover_psi_2d(RefineArgs a) {
+    const int prob = blockIdx.y;
+    if (a.stop && a.stop[prob]) return;
     const int m = a.N + a.k - 1;  // potential functions per direction
-    const int ia = blockIdx.x * kBlock + threadIdx.x;
-    if (ia >= m) return;
-    double ps = 0.0;
-    for (int j = 0; j < m; ++j) {
-        ps += (double)a.X[ia + (int64_t)m * j] / a.dcoef[j + 1];
-        a.psi[ia + (int64_t)m * j] = ps;
+    const int ia = blockIdx.x;
+    const float *X = a.X + prob * a.svec;
+    double *psi = a.psi + prob * a.spsi;
+    const int per = (m + kBlock - 1) / kBlock;
+    const int j0 = threadIdx.x * per, j1 = min(j0 + per, m);
+    double s = 0.0;
+    for (int j = j0; j < j1; ++j) s += (double)X[ia + (int64_t)m * j] / a.dcoef[j + 1];
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive scan of the chunk totals (Hillis-Steele, fixed order)
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const double v = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0.0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    double ps = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+    for (int j = j0; j < j1; ++j) {
+        ps += (double)X[ia + (int64_t)m * j] / a.dcoef[j + 1];
+        psi[ia + (int64_t)m * j] = ps;
     }
 }
 
 // U += [curl psi; X_p] in FP64, curl psi = (d_y psi, -d_x psi) by the scaled
 // differences of the derivative formula (psi = 0 on the boundary).
 __global__ void k_curl_update_2d(RefineArgs a) {
-    if (a.stop && *a.stop) return;
+    const int prob = blockIdx.y;
+    if (a.stop && a.stop[prob]) return;
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= a.n) return;
     const int m = a.N + a.k - 1, nq = a.N + a.k;
+    const double *P = a.psi + prob * a.spsi;
     auto psi = [&](int pa, int pb) -> double {  // true indices, zero on the boundary
         if (pa <= 0 || pa >= nq || pb <= 0 || pb >= nq) return 0.0;
-        return a.psi[(pa - 1) + (int64_t)m * (pb - 1)];
+        return P[(pa - 1) + (int64_t)m * (pb - 1)];
     };
     double du;
     if (g < a.off_uy) {  // u_x(a, j): stored (a-1, j), dims m x nq
@@ -213,29 +251,31 @@ __global__ void k_curl_update_2d(RefineArgs a) {
         const int i = (int)(l % nq), ib = (int)(l / nq);
         du = -a.dcoef[i + 1] * (psi(i + 1, ib + 1) - psi(i, ib + 1));
     } else {
-        du = (double)a.X[g];
+        du = (double)a.X[prob * a.svec + g];
     }
-    a.U[g] += du;
+    a.U[prob * a.svec + g] += du;
 }
 
 void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
     const int m = a.N + a.k - 1;
-    hipLaunchKernelGGL(k_recover_psi_2d, dim3(blocks_for(m)), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_recover_psi_2d, dim3(m, a.nprob), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);
 template void launch_schwarz_gather<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);
-template void launch_csr<double>(int, const int32_t *, const int32_t *, const double *, const double *, double *,
-                                 int, const int *, hipStream_t);
-template void launch_csr<float>(int, const int32_t *, const int32_t *, const float *, const float *, float *, int,
-                                const int *, hipStream_t);
-template void launch_gemv<double>(int, int, const double *, const double *, double *, const int *, hipStream_t);
-template void launch_gemv<float>(int, int, const double *, const float *, float *, const int *, hipStream_t);
-template void launch_fill<double>(int64_t, double *, double, const int *, hipStream_t);
-template void launch_fill<float>(int64_t, float *, float, const int *, hipStream_t);
+template void launch_csr<double>(int, const int32_t *, const int32_t *, const double *, const double *, int64_t,
+                                 double *, int64_t, int, const int *, int, hipStream_t);
+template void launch_csr<float>(int, const int32_t *, const int32_t *, const float *, const float *, int64_t, float *,
+                                int64_t, int, const int *, int, hipStream_t);
+template void launch_gemv<double>(int, int, const double *, int64_t, const double *, int64_t, double *, int64_t,
+                                  const int *, int, hipStream_t);
+template void launch_gemv<float>(int, int, const double *, int64_t, const float *, int64_t, float *, int64_t,
+                                 const int *, int, hipStream_t);
+template void launch_fill<double>(int64_t, double *, int64_t, double, const int *, int, hipStream_t);
+template void launch_fill<float>(int64_t, float *, int64_t, float, const int *, int, hipStream_t);
 
 __global__ void k_fill_int(int n, int *x, int v) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -245,25 +285,30 @@ void launch_fill_int(int n, int *x, int v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, v);
 }
 
-__global__ void k_copy(int64_t n, const double *x, double *y, const int *stop) {
-    if (stop && *stop) return;
+__global__ void k_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop) {
+    const int prob = blockIdx.y;
+    if (stop && stop[prob]) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) y[i] = x[i];
+    if (i < n) y[prob * sy + i] = x[prob * sx + i];
 }
-void launch_copy(int64_t n, const double *x, double *y, const int *stop, hipStream_t s) {
+void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop, int nprob,
+                 hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, y, stop);
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, sx, y, sy, stop);
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot_partial(int n, const double *x, const double *y, double *partial) {
+__global__ __launch_bounds__(kBlock) void k_dot_partial(int n, const double *x, const double *y, int64_t sxy,
+                                                        double *partial, int64_t spart) {
     __shared__ double sh[kBlock / 64];
+    const int prob = blockIdx.y;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    const double v = i < n ? x[i] * y[i] : 0.0;
+    const double v = i < n ? x[prob * sxy + i] * y[prob * sxy + i] : 0.0;
     const double s = block_sum(v, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[prob * spart + blockIdx.x] = s;
 }
-void launch_dot_partial(int n, const double *x, const double *y, double *partial, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(nblocks), dim3(kBlock), 0, s, n, x, y, partial);
+void launch_dot_partial(int n, const double *x, const double *y, int64_t sxy, double *partial, int64_t spart,
+                        int nblocks, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblocks, nprob), dim3(kBlock), 0, s, n, x, y, sxy, partial, spart);
 }
 
 __device__ double ordered_sum(int nparts, const double *partial, double *sh) {
@@ -272,45 +317,52 @@ __device__ double ordered_sum(int nparts, const double *partial, double *sh) {
     return block_sum(v, sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce(int nparts, const double *partial, double *out, double scale) {
+__global__ __launch_bounds__(kBlock) void k_reduce(int nparts, const double *partial, int64_t spart, double *out,
+                                                   double scale) {
     __shared__ double sh[kBlock / 64];
-    const double s = ordered_sum(nparts, partial, sh);
-    if (threadIdx.x == 0) *out = scale * s;
+    const int prob = blockIdx.x;
+    const double s = ordered_sum(nparts, partial + prob * spart, sh);
+    if (threadIdx.x == 0) out[prob] = scale * s;
 }
-void launch_reduce(int nparts, const double *partial, double *out, double scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, nparts, partial, out, scale);
+void launch_reduce(int nparts, const double *partial, int64_t spart, double *out, double scale, int nprob,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(nprob), dim3(kBlock), 0, s, nparts, partial, spart, out, scale);
 }
 
-__global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *partial, double *hist, int *counter,
-                                                  int *stop, const double *thresh2, int max_hist) {
-    if (*stop) return;
+__global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *partial, int64_t spart, double *hist,
+                                                  int max_hist, int *counter, int *stop, const double *thresh2) {
+    const int prob = blockIdx.x;
+    if (stop[prob]) return;
     __shared__ double sh[kBlock / 64];
-    const double s = ordered_sum(nparts, partial, sh);
+    const double s = ordered_sum(nparts, partial + prob * spart, sh);
     if (threadIdx.x == 0) {
-        const int c = *counter;
+        double *h = hist + (int64_t)prob * max_hist;
+        const int c = counter[prob];
         const double res = sqrt(s);
-        if (c < max_hist) hist[c] = res;
-        *counter = c + 1;
+        if (c < max_hist) h[c] = res;
+        counter[prob] = c + 1;
         if (!(s <= 1e300)) {
-            *stop = 2;  // NaN or Inf
-        } else if (s <= *thresh2) {
-            *stop = 1;
-        } else if (c > 0 && res > 1e6 * hist[0]) {
-            *stop = 2;  // growth by six orders: diverging
+            stop[prob] = 2;  // NaN or Inf
+        } else if (s <= thresh2[prob]) {
+            stop[prob] = 1;
+        } else if (c > 0 && res > 1e6 * h[0]) {
+            stop[prob] = 2;  // growth by six orders: diverging
         }
     }
 }
-void launch_check(int nparts, const double *partial, double *hist, int *counter, int *stop, const double *thresh2,
-                  int max_hist, hipStream_t s) {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, nparts, partial, hist, counter, stop, thresh2, max_hist);
+void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
+                  int *stop, const double *thresh2, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_check, dim3(nprob), dim3(kBlock), 0, s, nparts, partial, spart, hist, max_hist, counter,
+                       stop, thresh2);
 }
 
-__global__ void k_sub_scalar(int n, double *x, const double *m) {
+__global__ void k_sub_scalar(int n, double *x, int64_t sx, const double *m) {
+    const int prob = blockIdx.y;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] -= *m;
+    if (i < n) x[prob * sx + i] -= m[prob];
 }
-void launch_sub_scalar(int n, double *x, const double *m, hipStream_t s) {
-    hipLaunchKernelGGL(k_sub_scalar, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, m);
+void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_scalar, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, sx, m);
 }
 
 // d = coefficients of div u_h in the pressure basis: the derivative of a

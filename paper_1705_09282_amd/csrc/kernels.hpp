@@ -1,8 +1,17 @@
-// Device kernels of the V-cycle for gfx950 (wave64).  Every kernel that runs
-// inside a V-cycle takes `stop`: once the residual check of the current solve
-// has met the tolerance (or detected divergence) the remaining kernels of that
-// cycle leave their outputs untouched, so cycles launched ahead of the host
-// check are no-ops and the iterate is the one at which the check fired.
+// Device kernels of the V-cycle for gfx950 (wave64).
+//
+// Batches: every kernel works on a batch of independent problems that share
+// one mesh (same dimension, degree, grid and number of levels).  blockIdx.y
+// is the problem; arrays that depend on the problem's coefficients (matrix
+// values, local inverses, vectors, flags) are offset by the problem index
+// times a stride, arrays that depend only on the mesh (index maps, transfer
+// operators) are shared.  A single problem is a batch of one.
+//
+// Every kernel that runs inside a V-cycle takes the per-problem `stop` flags:
+// once a problem's residual check has met the tolerance (or detected
+// divergence) the remaining kernels leave that problem's outputs untouched,
+// so cycles launched ahead of the host check are no-ops for it and its
+// iterate is the one at which the check fired.
 //
 // Value type T is double (plain FP64 path) or float (the V-cycle inside the
 // FP64 iterative refinement); the coarse-grid matrix is always FP64.
@@ -20,16 +29,20 @@ constexpr int kBlock = 256;
 template <class T>
 struct SpmvArgsT {
     const T *val;
+    int64_t sval;       // per-problem stride of val
     int64_t val_off[4];
     int64_t off[5];
     int nb[4][3];
     int n;
-    int nblocks;  // logical blocks covering n rows (spmv_blocks)
+    int nblocks;        // logical blocks covering n rows (spmv_blocks)
     const T *F;
     const T *U;
     T *r;
-    double *partial;  // per-block sum of r^2 (nullable)
-    const int *stop;  // nullable
+    int64_t svec;       // per-problem stride of F, U, r
+    double *partial;    // per-block sum of r^2 (nullable)
+    int64_t spart;      // per-problem stride of partial
+    const int *stop;    // per-problem flags (nullable)
+    int nprob;
 };
 using SpmvArgs = SpmvArgsT<double>;
 
@@ -37,15 +50,18 @@ template <class T>
 struct PatchArgsT {
     int n;              // DOFs of the level
     int nent;           // entries of all subdomains (sum of their sizes)
-    const int32_t *inv_ptr, *inv_pos, *pptr, *pdofs, *moff;
-    const int4 *ent_info;  // per entry: (M row offset, subdomain start, subdomain size, 0)
-    T *delta;           // per-entry local corrections
-    const T *M;
+    const int32_t *inv_ptr, *inv_pos, *pptr, *pdofs;  // shared
+    const int32_t *moff;   // per problem (stride smoff): local-inverse offset of each subdomain
+    const int4 *ent_info;  // per problem (stride nent): (M row offset, subdomain start, size, 0)
+    T *delta;           // per problem (stride nent): per-entry local corrections
+    const T *M;         // per problem (stride sM)
     const T *r;
-    T *U;
-    const double *eta;  // device scalar
+    T *U;               // per problem (stride svec)
+    const double *eta;  // per problem (stride seta)
+    int64_t smoff, sM, svec, seta;
     int assign;         // 1: U = eta * S r (U known to be zero)
     const int *stop;
+    int nprob;
 };
 using PatchArgs = PatchArgsT<double>;
 
@@ -58,25 +74,33 @@ template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s);
+// y = (add ? y : 0) + A x, A shared CSR; x, y per problem (strides sx, sy)
 template <class T>
-void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, T *y, int add,
-                const int *stop, hipStream_t s);
-// y = A x with A row-major FP64 (rows x cols), x, y in T, FP64 accumulation
+void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int64_t sx, T *y,
+                int64_t sy, int add, const int *stop, int nprob, hipStream_t s);
+// y = A x with A row-major FP64 (rows x cols) per problem (stride sA), x, y in
+// T, FP64 accumulation
 template <class T>
-void launch_gemv(int rows, int cols, const double *A, const T *x, T *y, const int *stop, hipStream_t s);
+void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, int64_t sx, T *y, int64_t sy,
+                 const int *stop, int nprob, hipStream_t s);
 template <class T>
-void launch_fill(int64_t n, T *x, T v, const int *stop, hipStream_t s);
+void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s);
 void launch_fill_int(int n, int *x, int v, hipStream_t s);
-void launch_copy(int64_t n, const double *x, double *y, const int *stop, hipStream_t s);
-void launch_cast(int64_t n, const double *x, float *y, const int *stop, hipStream_t s);
-void launch_dot_partial(int n, const double *x, const double *y, double *partial, int nblocks, hipStream_t s);
-// out = scale * sum(partial[0..nparts))  (single block, fixed order)
-void launch_reduce(int nparts, const double *partial, double *out, double scale, hipStream_t s);
-// residual check: hist[*counter] = sqrt(sum); stop = 1 if sum <= *thresh2, 2 on NaN/Inf/growth
-void launch_check(int nparts, const double *partial, double *hist, int *counter, int *stop, const double *thresh2,
-                  int max_hist, hipStream_t s);
-// x[i] -= *m for i < n
-void launch_sub_scalar(int n, double *x, const double *m, hipStream_t s);
+void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop, int nprob,
+                 hipStream_t s);
+void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s);
+// per problem: partial[p * spart + b] = block sums of x . y
+void launch_dot_partial(int n, const double *x, const double *y, int64_t sxy, double *partial, int64_t spart,
+                        int nblocks, int nprob, hipStream_t s);
+// per problem: out[p] = scale * sum(partial[p * spart + 0 .. nparts))  (fixed order)
+void launch_reduce(int nparts, const double *partial, int64_t spart, double *out, double scale, int nprob,
+                   hipStream_t s);
+// per problem residual check: hist[p][counter[p]] = sqrt(sum), stop[p] = 1 if
+// sum <= thresh2[p], 2 on NaN/Inf/growth
+void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
+                  int *stop, const double *thresh2, int nprob, hipStream_t s);
+// per problem: x[p * sx + i] -= m[p] for i < n
+void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s);
 
 // FP64 update of the refinement loop (2D): recover the streamfunction
 // increment psi from the x-velocity part of the FP32 correction X by
@@ -86,13 +110,15 @@ struct RefineArgs {
     int64_t off_uy, off_p, n;  // block offsets of the finest level
     const float *X;
     const double *dcoef;
-    double *psi;               // (N+k-1)^2
+    double *psi;               // (N+k-1)^2 per problem
     double *U;
+    int64_t svec, spsi;
     const int *stop;
+    int nprob;
 };
 void launch_refine_update_2d(const RefineArgs &a, hipStream_t s);
 
-// div-norm pieces (finest grid)
+// div-norm pieces (finest grid, one problem)
 struct DivArgs {
     int d, k, N;
     int64_t off[4];

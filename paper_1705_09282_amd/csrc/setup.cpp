@@ -336,7 +336,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
             }
         L.nslots[R] = ns;
         L.val_off[R] = tot;
-        tot += (L.off[R + 1] - L.off[R]) * ns;
+        tot += (L.off[R + 1] - L.off[R] + 63) / 64 * 64 * ns;  // slices of 64 rows
     }
     L.val_off[d + 1] = tot;
     L.val.assign(tot, 0.0);
@@ -378,7 +378,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                                 for (int j = 0; j < d; ++j) p *= tm.f[j].get(itrue[j], jtrue[j]);
                                 v += p;
                             }
-                            L.val[L.val_off[R] + (int64_t)slot * rows + li] = v;
+                            L.val[L.val_off[R] + ((li >> 6) * L.nslots[R] + slot) * 64 + (li & 63)] = v;
                         }
             }
             int w = 1;
@@ -420,7 +420,8 @@ static double entry(const Problem &pb, const HostLevel &L, int64_t grow, int64_t
         }
     }
     slot += (o[2] * W[1] + o[1]) * W[0] + o[0];
-    return L.val[L.val_off[R] + (int64_t)slot * rows + (grow - L.off[R])];
+    const int64_t li = grow - L.off[R];
+    return L.val[L.val_off[R] + ((li >> 6) * L.nslots[R] + slot) * 64 + (li & 63)];
 }
 
 double level_entry(const Hierarchy &H, int level, int64_t grow, int64_t gcol) {

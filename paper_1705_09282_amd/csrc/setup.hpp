@@ -7,11 +7,13 @@
 // boundary terms, and the derivative coupling of degree k+1 and k splines), so
 // the Galerkin coarse operators K_l = R K_{l+1} P of the paper's nested
 // hierarchy are obtained exactly by applying the 1D refinement matrices to
-// every factor.  Matrices are stored in a "stencil ELL" layout: for each row
-// block (velocity component or pressure) and each coupled column block, every
-// row holds the full box of tensor offsets in which two B-splines can overlap,
-// values only (column indices follow from the offset), slot-major so that
-// consecutive rows are consecutive in memory.
+// every factor.  Matrices are stored in a sliced "stencil ELL" layout: for
+// each row block (velocity component or pressure) and each coupled column
+// block, every row holds the full box of tensor offsets in which two
+// B-splines can overlap, values only (column indices follow from the offset).
+// Rows are grouped in slices of 64 (one wavefront); inside a slice the values
+// are slot-major, so a wavefront reads 64 consecutive values per slot and one
+// contiguous block per slice.
 #pragma once
 
 #include <cstdint>
@@ -63,7 +65,8 @@ struct HostLevel {
     int nb[4][3] = {};         // stored count per block per direction
     int64_t off[5] = {};       // block offsets, off[nblk] = n
     int64_t n = 0, n_v = 0, n_q = 0;
-    // stencil ELL: values of row block R at val[val_off[R] + slot * rows(R) + row]
+    // stencil ELL: value (row, slot) of row block R at
+    // val[val_off[R] + ((row / 64) * nslots[R] + slot) * 64 + row % 64]
     std::vector<double> val;
     int64_t val_off[5] = {};
     int nslots[4] = {};

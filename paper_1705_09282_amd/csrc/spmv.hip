@@ -54,6 +54,15 @@ __host__ __device__ constexpr int block_slots() {
     return Geo<D, K>::w(R, C, 0) * Geo<D, K>::w(R, C, 1) * Geo<D, K>::w(R, C, 2);
 }
 
+template <int D, int K, int R>
+__host__ __device__ constexpr int row_slots() {
+    if constexpr (R < D) {
+        return block_slots<D, K, R, R>() + block_slots<D, K, R, D>();
+    } else {
+        return block_slots<D, K, R, 0>() + block_slots<D, K, R, 1>() + (D == 3 ? block_slots<D, K, R, 2 % D>() : 0);
+    }
+}
+
 template <int D, int K, int R, int LPR, class T>
 __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
@@ -61,8 +70,9 @@ __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const int t = li / nb0;
     const int i1 = t % nb1;
     const int i2 = t / nb1;
-    const int64_t stride = a.off[R + 1] - a.off[R];
-    const T *vp = a.val + a.val_off[R] + li;
+    // sliced layout: slices of 64 rows, slot-major inside a slice
+    constexpr int64_t stride = 64;
+    const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots<D, K, R>() * 64) + (li & 63);
     T acc;
     if constexpr (R < D) {
         acc = block_dot<D, K, R, R, LPR, T>(a, i0, i1, i2, lane, vp, stride);
@@ -80,9 +90,15 @@ __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
 // covers kBlock / LPR rows.
 template <int D, int K, int LPR, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
+    const int prob = blockIdx.y;
+    a.val += prob * a.sval;
+    a.F += prob * a.svec;
+    a.U += prob * a.svec;
+    a.r += prob * a.svec;
+    if (a.partial) a.partial += prob * a.spart;
     // the stop flag is read alongside the operands and only gates the stores,
     // so its load latency overlaps with theirs
-    const int halt = a.stop ? *a.stop : 0;
+    const int halt = a.stop ? a.stop[prob] : 0;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int lane = (LPR > 1) ? (threadIdx.x % LPR) : 0;
     const int g = b * (kBlock / LPR) + threadIdx.x / LPR;
@@ -118,10 +134,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
 
 template <int D, int K, class T>
 static void launch_dk(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
-    const int grid = padded_grid(a.nblocks);
-    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, T>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, T>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_spmv<D, K, 1, T>), dim3(grid), dim3(kBlock), 0, s, a);
+    const dim3 grid(padded_grid(a.nblocks), a.nprob);
+    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, T>), grid, dim3(kBlock), 0, s, a);
+    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, T>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_spmv<D, K, 1, T>), grid, dim3(kBlock), 0, s, a);
 }
 
 // a.nblocks must equal spmv_blocks(a.n, lpr)

@@ -55,6 +55,9 @@ SIGNATURES = [
     ("dfmg_default_options", None, [ctypes.POINTER(Options)]),
     ("dfmg_setup", c_int, [ctypes.POINTER(Grid), c_int, c_double, c_double, ctypes.POINTER(Advection),
                            ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    ("dfmg_batch_setup", c_int, [c_int, ctypes.POINTER(Grid), c_int, c_dblp, c_dblp, ctypes.POINTER(Advection),
+                                 ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    ("dfmg_batch_size", c_int, [c_void_p, ctypes.POINTER(c_int)]),
     ("dfmg_destroy", None, [c_void_p]),
     ("dfmg_workspace_bytes", c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
     ("dfmg_bind", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -136,16 +139,27 @@ def default_options(**kw):
 class Solver:
     """Hierarchy for one problem: unit square (dim 2) or cube (dim 3),
     n_elem elements per direction on the finest of n_levels grids, pressure
-    degree k, viscosity nu, reaction sigma, rotation advection speed c."""
+    degree k, viscosity nu, reaction sigma, rotation advection speed c.
+    A Solver is the batch of one; BatchSolver holds several problems on the
+    same mesh and solves them together."""
 
     def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, **options):
+        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options)
+
+    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options):
         self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
+        self.nprob = len(nus)
+        if not (len(sigmas) == len(cs) == self.nprob):
+            raise ValueError("one nu, sigma and c per problem")
         g = Grid(dim, n_elem, n_levels)
-        adv = Advection(1 if c != 0.0 else 0, c)
+        adv = (Advection * self.nprob)(*[Advection(1 if c != 0.0 else 0, float(c)) for c in cs])
+        nu_a = np.ascontiguousarray(nus, dtype=np.float64)
+        sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)
         ctx = c_void_p()
-        _check(lib().dfmg_setup(ctypes.byref(g), k, nu, sigma, ctypes.byref(adv), ctypes.byref(opt),
-                                ctypes.byref(ctx)))
+        self._ctx = c_void_p()
+        _check(lib().dfmg_batch_setup(self.nprob, ctypes.byref(g), k, _ptr(nu_a, ctypes.c_double),
+                                      _ptr(sg_a, ctypes.c_double), adv, ctypes.byref(opt), ctypes.byref(ctx)))
         self._ctx = ctx
         self._ws = None
         self._sizes = {}
@@ -163,12 +177,13 @@ class Solver:
 
     @property
     def n(self):
+        """finest-level DOFs of one problem"""
         return self.sizes()["n"]
 
     def _nlev(self, level):
         if not 0 <= level < self.n_levels:
             raise ValueError("level out of range")
-        return self.sizes(level)["n"]
+        return self.sizes(level)["n"] * self.nprob
 
     def export_matrix(self, level):
         s = self.sizes(level)
@@ -202,7 +217,7 @@ class Solver:
         return rp, col, val
 
     def manufactured_rhs(self):
-        F = np.zeros(self.n, np.float64)
+        F = np.zeros(self.n * self.nprob, np.float64)
         _check(lib().dfmg_manufactured_rhs(self._ctx, _ptr(F, ctypes.c_double)))
         return F
 
@@ -223,31 +238,40 @@ class Solver:
         return self
 
     def set_eta(self, etas):
-        a = np.ascontiguousarray(etas, dtype=np.float64)
+        a = np.ascontiguousarray(etas, dtype=np.float64).ravel()
         _check(lib().dfmg_set_eta(self._ctx, _ptr(a, ctypes.c_double), int(a.size)))
 
     def vcycle(self, F, U, ncycles=1):
-        n = self.n
+        n = self.n * self.nprob
         _check(lib().dfmg_vcycle(self._ctx, _dev(F, n), _dev(U, n), int(ncycles)))
 
-    def solve(self, F, U, tol=1e-8, raise_on_error=True):
-        st = Stats()
-        n = self.n
-        code = lib().dfmg_solve(self._ctx, _dev(F, n), _dev(U, n), float(tol), ctypes.byref(st))
+    def _solve(self, F, U, tol, raise_on_error):
+        n = self.n * self.nprob
+        st = (Stats * self.nprob)()
+        code = lib().dfmg_solve(self._ctx, _dev(F, n), _dev(U, n), float(tol), st)
         if raise_on_error:
             _check(code)
-        return st.as_dict()
+        return [s.as_dict() for s in st]
+
+    def _residual_norms(self, F, U):
+        n = self.n * self.nprob
+        out = np.zeros(self.nprob)
+        _check(lib().dfmg_residual_norm(self._ctx, _dev(F, n), _dev(U, n), _ptr(out, ctypes.c_double)))
+        return out
+
+    def _div_norms(self, U):
+        out = np.zeros(self.nprob)
+        _check(lib().dfmg_div_norm(self._ctx, _dev(U, self.n * self.nprob), _ptr(out, ctypes.c_double)))
+        return out
+
+    def solve(self, F, U, tol=1e-8, raise_on_error=True):
+        return self._solve(F, U, tol, raise_on_error)[0]
 
     def residual_norm(self, F, U):
-        out = c_double()
-        n = self.n
-        _check(lib().dfmg_residual_norm(self._ctx, _dev(F, n), _dev(U, n), ctypes.byref(out)))
-        return out.value
+        return float(self._residual_norms(F, U)[0])
 
     def div_norm(self, U):
-        out = c_double()
-        _check(lib().dfmg_div_norm(self._ctx, _dev(U, self.n), ctypes.byref(out)))
-        return out.value
+        return float(self._div_norms(U)[0])
 
     def level_residual(self, level, F, U, r):
         n = self._nlev(level)
@@ -264,8 +288,8 @@ class Solver:
         _check(lib().dfmg_level_prolong_add(self._ctx, level, _dev(dU, self._nlev(level - 1)), _dev(U, self._nlev(level))))
 
     def time_residual(self, level, F, U, r, reps=50):
-        out = c_double()
         n = self._nlev(level)
+        out = c_double()
         _check(lib().dfmg_time_residual(self._ctx, level, _dev(F, n), _dev(U, n), _dev(r, n), int(reps), ctypes.byref(out)))
         return out.value
 
@@ -327,3 +351,23 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver(Solver):
+    """Several independent problems on one mesh (same dim, n_elem, n_levels,
+    k) with per-problem nu, sigma and rotation speed c, solved together: every
+    kernel launch covers the whole batch.  Vectors are problem-major blocks of
+    the finest-level length n."""
+
+    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, **options):
+        cs = [0.0] * len(nus) if cs is None else list(cs)
+        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options)
+
+    def solve(self, F, U, tol=1e-8, raise_on_error=True):
+        return self._solve(F, U, tol, raise_on_error)
+
+    def residual_norm(self, F, U):
+        return self._residual_norms(F, U)
+
+    def div_norm(self, U):
+        return self._div_norms(U)

@@ -276,3 +276,64 @@ def test_fp32_refinement_at_benchmark_tolerance():
     assert rel_l2(host(Ud)[:nv], host(U64)[:nv]) < 1e-6
     s.close()
     s64.close()
+
+
+def make_batch(d, N, k, L, nus, sigmas, cs, **opt):
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    print(f"\n[batch] d={d} N={N} k={k} L={L} nus={nus} sigmas={sigmas} cs={cs} opt={opt}", flush=True)
+    return BatchSolver(d, N, L, k, nus, sigmas, cs, **opt).bind()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_single_problems(precision):
+    """A batch solve gives, problem by problem, bitwise the single-problem
+    solve (same kernels, same variants, same order of operations)."""
+    d, N, k, L = 2, 32, 2, 4
+    nus, sigmas, cs = [1.0, 0.5, 1.0], [1e-2, 10.0, 1e4], [0.0, 8.0, 0.0]
+    B = make_batch(d, N, k, L, nus, sigmas, cs, precision=precision)
+    tun = B.get_tuning()
+    Fs, singles = [], []
+    for nu, sg, c in zip(nus, sigmas, cs):
+        from paper_1705_09282_amd.dfmg import Solver
+        s = Solver(d, N, L, k, nu=nu, sigma=sg, c=c, precision=precision).bind()
+        s.set_tuning(tun["lpr"], tun["smoother"])
+        Fs.append(s.manufactured_rhs())
+        singles.append(s)
+    F = np.concatenate(Fs)
+    assert np.array_equal(F, B.manufactured_rhs())
+    Ub = dev(np.zeros_like(F))
+    stats = B.solve(dev(F), Ub, tol=1e-9)
+    n = B.n
+    for p, s in enumerate(singles):
+        U = dev(np.zeros(n))
+        st = s.solve(dev(Fs[p]), U, tol=1e-9)
+        assert stats[p]["cycles"] == st["cycles"] and stats[p]["converged"]
+        assert torch.equal(Ub[p * n:(p + 1) * n], U)
+        s.close()
+    divs = B.div_norm(Ub)
+    assert len(divs) == 3 and max(divs) < 1e-10
+    B.close()
+
+
+def test_batch_vcycles_match_oracle_per_problem_damping():
+    d, N, k, L = 2, 16, 2, 3
+    nus, sigmas, cs = [1.0, 0.3], [2.0, 100.0], [0.0, 5.0]
+    B = make_batch(d, N, k, L, nus, sigmas, cs)
+    etas = [[0.18, 0.15], [0.2, 0.12]]
+    B.set_eta(np.array(etas).ravel())
+    U0s, Fs, Uos = [], [], []
+    for p in range(2):
+        adv = rotation_field(cs[p]) if cs[p] else None
+        h = Hierarchy(d, N, k, L, nus[p], sigmas[p], adv)
+        F = load_vector(h.finest.disc, forcing(d, nus[p], sigmas[p], adv))
+        U0 = divfree_start(h, 50 + p)
+        Uos.append(vcycles(h, U0, F, 2, eta=etas[p]))
+        U0s.append(U0)
+        Fs.append(F)
+    Ub = dev(np.concatenate(U0s))
+    B.vcycle(dev(np.concatenate(Fs)), Ub, 2)
+    Ug = host(Ub)
+    n = B.n
+    for p in range(2):
+        assert rel_l2(Ug[p * n:(p + 1) * n], Uos[p]) < 1e-10
+    B.close()

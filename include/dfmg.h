@@ -90,6 +90,7 @@ typedef struct {
     int cycles;           /* V-cycles applied                                   */
     int converged;        /* 1 if ||F - K U||_2 <= tol ||F||_2                  */
     int status;           /* return code of the solve                           */
+    int fallback;         /* 1 if the learned damping was replaced by the fixed one */
     double res0;          /* ||F - K U_0||_2                                    */
     double res_final;     /* residual norm at exit                              */
     double rho;           /* (res_final / res0)^(1/cycles)                      */
@@ -203,6 +204,38 @@ int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
  * 2 * n_levels entries) receives the best residual and smoother times.
  * Requires dfmg_bind.  Leaves the solver state unchanged. */
 int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
+
+/* ---- Learned per-level damping ----
+ * A perceptron predicts the damping eta in (0, 1) of equation ASM for every
+ * smoothed level: x = (log10(nu)/2, log10(sigma)/4, |a| h / nu, k - 1.5) with
+ * |a| = max|a| and h = 1/n_elem; h1 = tanh(W1 x + b1) (32), h2 = tanh(W2 h1 +
+ * b2) (32), z = W3 h2 + b3 (5 logits, finest smoothed level first; deeper
+ * hierarchies reuse the last), eta = 1 / (1 + exp(-z)).  Parameters are FP32,
+ * packed [W1 (32x4 row-major), b1, W2 (32x32), b2, W3 (5x32), b3].
+ * The three kernels below take device arrays and a HIP stream (NULL =
+ * default) and do not synchronize. */
+#define DFMG_MLP_NPARAM 1381
+/* Z (n x 5) = logits of the features X (n x 4). */
+int dfmg_mlp_forward(int n, const float *W_dev, const float *X_dev, float *Z_dev, void *stream);
+/* G = gradient and *loss_dev = value of scale * sum M (Z - Y)^2 over the n
+ * samples (Y, M: n x 5 targets and 0/1 mask); work_dev holds
+ * n * (DFMG_MLP_NPARAM + 1) floats.  Fixed summation order (deterministic). */
+int dfmg_mlp_grad(int n, const float *W_dev, const float *X_dev, const float *Y_dev, const float *M_dev,
+                  float scale, float *work_dev, float *G_dev, float *loss_dev, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, t >= 1). */
+int dfmg_mlp_adam(float *W_dev, float *m_dev, float *v_dev, const float *G_dev, int t, float lr, void *stream);
+/* Use the network W_host for the dampings of every problem of ctx (computed
+ * on the device from each problem's nu, sigma, advection, grid and k).  With
+ * rho_plain_host (nprob entries, nullable) a solve switches a problem back to
+ * the fixed damping as soon as one V-cycle after the first contracts its
+ * residual by more than 1.05 * rho_plain (a single-cycle ratio of the fixed
+ * damping), or any cycle lets it grow by six orders, and reports it in
+ * stats.fallback.  The switch happens once per solve; the next solve starts
+ * from the learned dampings again.
+ * W_host NULL restores the fixed damping.  Requires dfmg_bind. */
+int dfmg_set_learned(dfmg_ctx *ctx, const float *W_host, const double *rho_plain_host);
+/* Current dampings, nprob * (n_levels - 1) values, finest level first. */
+int dfmg_get_eta(dfmg_ctx *ctx, double *eta_host);
 
 /* ---- Host exports for bit-exact index-map parity and value parity ----
  * CSR of K_level (explicit zeros dropped): rowptr[n+1], col[nnz], val[nnz]. */

@@ -19,6 +19,7 @@
 
 #include "../../include/dfmg.h"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "setup.hpp"
 
 using namespace dfmg;
@@ -103,6 +104,11 @@ struct dfmg_ctx {
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
     double *psi = nullptr;       // refinement: streamfunction increments [problem][(N+k-1)^2]
+    // learned damping
+    float *mlpW = nullptr, *feat = nullptr;
+    double *rho_plain = nullptr, *eta_fixed = nullptr;
+    int *fallback = nullptr;
+    bool learned = false, use_fallback = false;
     int64_t spsi = 0;
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
@@ -201,6 +207,11 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->wfine = A.take<double>(H.lv[L - 1].n_q);
     c->spsi = (int64_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1);
     if (c->mixed()) c->psi = A.take<double>((size_t)c->spsi * np);
+    c->mlpW = A.take<float>(MLP_NPARAM);
+    c->feat = A.take<float>((size_t)MLP_IN * np);
+    c->rho_plain = A.take<double>(np);
+    c->eta_fixed = A.take<double>((size_t)L * np);
+    c->fallback = A.take<int>(np);
 }
 
 template <class T>
@@ -310,8 +321,19 @@ void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
 }
 
 void check(dfmg_ctx *c, int np_blocks) {
-    launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->thresh2,
+    Fallback fb{};
+    fb.rho = (c->learned && c->use_fallback) ? c->rho_plain : nullptr;
+    fb.eta = c->eta;
+    fb.eta_fixed = c->eta_fixed;
+    fb.flag = c->fallback;
+    fb.L = c->L();
+    launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->thresh2, fb,
                  c->np, c->s);
+}
+
+// dampings of every problem from the network (device), see dfmg_set_learned
+void apply_learned(dfmg_ctx *c) {
+    launch_mlp_damping(c->np, c->mlpW, c->feat, c->L(), c->eta, c->s);
 }
 
 // One V-cycle (Algorithm 1) on the finest level's internal U, F of type T.
@@ -650,6 +672,8 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             }
         }
         up(c->eta, c->eta_host, s);
+        up(c->eta_fixed, c->eta_host, s);
+        HIPCHK(hipMemsetAsync(c->fallback, 0, np * sizeof(int), s));
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
@@ -688,9 +712,13 @@ int dfmg_set_eta(dfmg_ctx *c, const double *eta, int n) {
             const double *e = (n == m) ? eta : eta + (size_t)p * m;
             for (int i = 0; i < m; ++i) c->eta_host[(size_t)p * L + (L - 1 - i)] = e[i];
         }
+        c->learned = false;
         if (c->bound) {
             enter(c);
             upload_eta(c);
+            HIPCHK(hipMemcpyAsync(c->eta_fixed, c->eta_host.data(), c->eta_host.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
             leave(c);
         }
     });
@@ -778,6 +806,8 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         const int kind = c->mixed() ? 2 : 1;
         launch_fill_int(np, c->stop, 0, c->s);
         launch_fill_int(np, c->counter, 0, c->s);
+        launch_fill_int(np, c->fallback, 0, c->s);
+        if (c->learned) apply_learned(c);  // a fallback of an earlier solve reset them
         launch_copy(n, F, n, v.F, n, nullptr, np, c->s);
         launch_copy(n, U, n, v.U, n, nullptr, np, c->s);
         launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
@@ -815,6 +845,8 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         launch_sub_scalar((int)h.n_q, v.U + h.n_v, n, c->scal, np, c->s);
         launch_copy(n, v.U, n, U, n, nullptr, np, c->s);
         std::vector<double> hist((size_t)np * DFMG_MAX_HISTORY), th(np);
+        std::vector<int> fbk(np);
+        HIPCHK(hipMemcpyAsync(fbk.data(), c->fallback, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
         HIPCHK(hipMemcpyAsync(hist.data(), c->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
         HIPCHK(hipMemcpyAsync(th.data(), c->thresh2, np * sizeof(double), hipMemcpyDeviceToHost, c->s));
         HIPCHK(hipStreamSynchronize(c->s));
@@ -826,6 +858,7 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
             const int cnt = std::min(counter[p], DFMG_MAX_HISTORY);
             S.cycles = counter[p] - 1;
             S.converged = stopv[p] == 1;
+            S.fallback = fbk[p];
             S.fnorm = std::sqrt(th[p]) / tol;
             S.n_history = cnt;
             for (int i = 0; i < cnt; ++i) S.history[i] = hist[(size_t)p * DFMG_MAX_HISTORY + i];
@@ -1008,6 +1041,75 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         (void)hipEventDestroy(e1);
         drop_graph(c);
         HIPCHK(hipStreamSynchronize(c->s));
+        leave(c);
+    });
+}
+
+int dfmg_mlp_forward(int n, const float *W, const float *X, float *Z, void *stream) {
+    if (n < 0 || (n > 0 && (!W || !X || !Z))) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        launch_mlp_forward(n, W, X, Z, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int dfmg_mlp_grad(int n, const float *W, const float *X, const float *Y, const float *Mk, float scale, float *work,
+                  float *G, float *loss, void *stream) {
+    if (n < 1 || !W || !X || !Y || !Mk || !work || !G || !loss) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        launch_mlp_grad(n, W, X, Y, Mk, scale, work, work + (int64_t)n * MLP_NPARAM, G, loss, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int dfmg_mlp_adam(float *W, float *m, float *v, const float *G, int t, float lr, void *stream) {
+    if (!W || !m || !v || !G || t < 1) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        launch_mlp_adam(W, m, v, G, t, lr, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
+    if (!c) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        enter(c);
+        if (!W) {
+            c->learned = false;
+            upload_eta(c);
+            leave(c);
+            return;
+        }
+        std::vector<float> feat((size_t)MLP_IN * c->np);
+        for (int p = 0; p < c->np; ++p) {
+            const Problem &pb = c->P[p].pb;
+            const double amag = pb.adv_kind == 1 ? std::fabs(pb.adv_c) / std::sqrt(2.0) : 0.0;
+            feat[p * MLP_IN + 0] = (float)(std::log10(pb.nu) / 2.0);
+            feat[p * MLP_IN + 1] = (float)(std::log10(std::max(pb.sigma, 1e-300)) / 4.0);
+            feat[p * MLP_IN + 2] = (float)(amag / (pb.N * pb.nu));
+            feat[p * MLP_IN + 3] = (float)(pb.k - 1.5);
+        }
+        up(c->mlpW, W, MLP_NPARAM, c->s);
+        up(c->feat, feat, c->s);
+        c->use_fallback = rho != nullptr;
+        if (rho) up(c->rho_plain, rho, c->np, c->s);
+        c->learned = true;
+        apply_learned(c);
+        HIPCHK(hipStreamSynchronize(c->s));
+        leave(c);
+    });
+}
+
+int dfmg_get_eta(dfmg_ctx *c, double *eta) {
+    if (!c || !eta) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        enter(c);
+        const int L = c->L();
+        std::vector<double> e((size_t)L * c->np);
+        HIPCHK(hipMemcpyAsync(e.data(), c->eta, e.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        for (int p = 0; p < c->np; ++p)
+            for (int i = 0; i < L - 1; ++i) eta[(size_t)p * (L - 1) + i] = e[(size_t)p * L + (L - 1 - i)];
         leave(c);
     });
 }

@@ -330,7 +330,8 @@ void launch_reduce(int nparts, const double *partial, int64_t spart, double *out
 }
 
 __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *partial, int64_t spart, double *hist,
-                                                  int max_hist, int *counter, int *stop, const double *thresh2) {
+                                                  int max_hist, int *counter, int *stop, const double *thresh2,
+                                                  Fallback fb) {
     const int prob = blockIdx.x;
     if (stop[prob]) return;
     __shared__ double sh[kBlock / 64];
@@ -341,19 +342,27 @@ __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *part
         const double res = sqrt(s);
         if (c < max_hist) h[c] = res;
         counter[prob] = c + 1;
+        const bool grow = c > 0 && res > 1e6 * h[0];  // growth by six orders: diverging
+        const bool can_fall = fb.rho && fb.rho[prob] > 0.0 && !fb.flag[prob];
         if (!(s <= 1e300)) {
             stop[prob] = 2;  // NaN or Inf
         } else if (s <= thresh2[prob]) {
             stop[prob] = 1;
-        } else if (c > 0 && res > 1e6 * h[0]) {
-            stop[prob] = 2;  // growth by six orders: diverging
+        } else if (can_fall && (grow || (c >= 2 && c <= max_hist && res > 1.05 * fb.rho[prob] * h[c - 1]))) {
+            // the learned dampings contract worse than the fixed ones did:
+            // continue with the fixed dampings (the iteration stays linear,
+            // so the iterate so far is a valid starting guess)
+            fb.flag[prob] = 1;
+            for (int l = 1; l < fb.L; ++l) fb.eta[(int64_t)prob * fb.L + l] = fb.eta_fixed[(int64_t)prob * fb.L + l];
+        } else if (grow) {
+            stop[prob] = 2;
         }
     }
 }
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, const double *thresh2, int nprob, hipStream_t s) {
+                  int *stop, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s) {
     hipLaunchKernelGGL(k_check, dim3(nprob), dim3(kBlock), 0, s, nparts, partial, spart, hist, max_hist, counter,
-                       stop, thresh2);
+                       stop, thresh2, fb);
 }
 
 __global__ void k_sub_scalar(int n, double *x, int64_t sx, const double *m) {

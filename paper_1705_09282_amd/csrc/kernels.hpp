@@ -95,10 +95,21 @@ void launch_dot_partial(int n, const double *x, const double *y, int64_t sxy, do
 // per problem: out[p] = scale * sum(partial[p * spart + 0 .. nparts))  (fixed order)
 void launch_reduce(int nparts, const double *partial, int64_t spart, double *out, double scale, int nprob,
                    hipStream_t s);
+// Learned-damping fallback used by the residual check: when a V-cycle after
+// the first contracts problem p's residual by more than 1.05 * rho[p], or the
+// residual has grown by six orders, its dampings eta[p][1..L-1] are reset to
+// eta_fixed[p][..] and flag[p] is set (once; growth then means divergence).
+struct Fallback {
+    const double *rho;        // nullable: no fallback
+    double *eta;
+    const double *eta_fixed;
+    int *flag;
+    int L;
+};
 // per problem residual check: hist[p][counter[p]] = sqrt(sum), stop[p] = 1 if
 // sum <= thresh2[p], 2 on NaN/Inf/growth
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, const double *thresh2, int nprob, hipStream_t s);
+                  int *stop, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s);
 // per problem: x[p * sx + i] -= m[p] for i < n
 void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s);
 

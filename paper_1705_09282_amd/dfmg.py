@@ -38,13 +38,14 @@ class Options(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("cycles", c_int), ("converged", c_int), ("status", c_int), ("res0", c_double),
+    _fields_ = [("cycles", c_int), ("converged", c_int), ("status", c_int), ("fallback", c_int), ("res0", c_double),
                 ("res_final", c_double), ("rho", c_double), ("fnorm", c_double),
                 ("solve_seconds", c_double), ("n_history", c_int),
                 ("history", c_double * MAX_HISTORY)]
 
     def as_dict(self):
         return {"cycles": self.cycles, "converged": bool(self.converged), "status": self.status,
+                "fallback": bool(self.fallback),
                 "res0": self.res0, "res_final": self.res_final, "rho": self.rho, "fnorm": self.fnorm,
                 "solve_seconds": self.solve_seconds,
                 "history": [self.history[i] for i in range(self.n_history)]}
@@ -76,6 +77,12 @@ SIGNATURES = [
     ("dfmg_get_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_set_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_autotune", c_int, [c_void_p, c_int, c_dblp]),
+    ("dfmg_mlp_forward", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("dfmg_mlp_grad", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
+                              c_void_p, c_void_p]),
+    ("dfmg_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]),
+    ("dfmg_set_learned", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp]),
+    ("dfmg_get_eta", c_int, [c_void_p, c_dblp]),
     ("dfmg_export_matrix", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_patch_total", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_patches", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_i32p]),
@@ -128,6 +135,43 @@ def _dev(t, n):
     return c_void_p(t.data_ptr())
 
 
+MLP_NPARAM = 1381
+
+
+def _devf(t, n):
+    """Device pointer of a contiguous FP32 torch tensor of n entries on the GPU."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(t):
+    import torch
+    return c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_forward(W, X, Z):
+    """Z (n x 5) = logits of the damping network for features X (n x 4)."""
+    n = X.numel() // 4
+    _check(lib().dfmg_mlp_forward(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Z, 5 * n), _stream(W)))
+
+
+def mlp_grad(W, X, Y, M, scale, work, G, loss):
+    """G = gradient and loss[0] = value of scale * sum M (Z - Y)^2."""
+    n = X.numel() // 4
+    _check(lib().dfmg_mlp_grad(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Y, 5 * n), _devf(M, 5 * n),
+                               float(scale), _devf(work, n * (MLP_NPARAM + 1)), _devf(G, MLP_NPARAM),
+                               _devf(loss, 1), _stream(W)))
+
+
+def mlp_adam(W, m, v, G, t, lr):
+    _check(lib().dfmg_mlp_adam(_devf(W, MLP_NPARAM), _devf(m, MLP_NPARAM), _devf(v, MLP_NPARAM),
+                               _devf(G, MLP_NPARAM), int(t), float(lr), _stream(W)))
+
+
 def default_options(**kw):
     o = Options()
     lib().dfmg_default_options(ctypes.byref(o))
@@ -149,6 +193,7 @@ class Solver:
     def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options):
         self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
         self.nprob = len(nus)
+        self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
         if not (len(sigmas) == len(cs) == self.nprob):
             raise ValueError("one nu, sigma and c per problem")
         g = Grid(dim, n_elem, n_levels)
@@ -335,6 +380,30 @@ class Solver:
                 json.dump(data, f, indent=1)
         out["cached"] = False
         return out
+
+    def set_learned(self, W, rho_plain=None):
+        """Dampings from the network W (1381 floats) for every problem; with
+        rho_plain (one per problem) a solve falls back to the fixed damping
+        when a cycle contracts worse than 1.05 * rho_plain.  W None: fixed."""
+        if W is None:
+            _check(lib().dfmg_set_learned(self._ctx, None, None))
+            return
+        w = np.ascontiguousarray(W, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError("expected 1381 parameters")
+        r = None
+        if rho_plain is not None:
+            r = np.ascontiguousarray(rho_plain, dtype=np.float64)
+            if r.size != self.nprob:
+                raise ValueError("one plain rate per problem")
+        _check(lib().dfmg_set_learned(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                      None if r is None else _ptr(r, ctypes.c_double)))
+
+    def get_eta(self):
+        """Current dampings, one row per problem, finest level first."""
+        out = np.zeros(self.nprob * (self.n_levels - 1))
+        _check(lib().dfmg_get_eta(self._ctx, _ptr(out, ctypes.c_double)))
+        return out.reshape(self.nprob, self.n_levels - 1)
 
     def coarse_solve(self, G, dU):
         n = self._nlev(0)

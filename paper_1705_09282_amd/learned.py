@@ -1,0 +1,251 @@
+"""Learned per-level damping for the additive Schwarz smoother.
+
+The smoother's damping eta (equation ASM, eta in (0,1)) is predicted per
+smoothed level by the library's perceptron (``dfmg_mlp_*``, FP32 HIP kernels).
+This module generates the training data with the method itself and trains the
+network on the GPU:
+
+* ``sweep``: for each training problem, a batch of identical copies runs
+  V(2,2) cycles from U = 0 on the manufactured load; every copy carries one
+  candidate damping vector, so one batched solve scores all candidates.  A
+  coordinate search (finest level first, two passes, multiplicative steps
+  around the fixed damping) keeps the per-level dampings with the smallest
+  measured contraction factor rho = (||r_m|| / ||r_0||)^(1/m).  The target is
+  the logit of the best dampings; the fixed-damping rate rho_plain is kept for
+  the fallback.
+* ``train``: full-batch Adam on the masked squared logit error with the
+  library's forward/backward/Adam kernels.
+
+``python -m paper_1705_09282_amd.learned [out.json]`` runs both on the
+default training grid and writes the weights, the training data and the
+fallback thresholds (default: ``data/damping_mlp.json`` beside this module).
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from .dfmg import BatchSolver, MLP_NPARAM, mlp_adam, mlp_grad, mlp_forward
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "data", "damping_mlp.json")
+NOUT = 5
+FACTORS = (0.55, 0.7, 0.85, 1.0, 1.15, 1.3, 1.45)
+
+
+def features(nu, sigma, c, N, k):
+    """(log10 nu / 2, log10 sigma / 4, |a| h / nu, k - 1.5), |a| = c / sqrt(2)."""
+    amag = abs(c) / math.sqrt(2.0)
+    return np.array([math.log10(nu) / 2.0, math.log10(sigma) / 4.0, amag / (N * nu), k - 1.5], dtype=np.float64)
+
+
+def logit(p):
+    return math.log(p / (1.0 - p))
+
+
+def contraction(stats):
+    """Mean contraction per cycle over the recorded residual history."""
+    h = stats["history"]
+    if len(h) < 2 or not all(np.isfinite(h)) or h[0] <= 0:
+        return float("inf")
+    return (h[-1] / h[0]) ** (1.0 / (len(h) - 1))
+
+
+def worst_cycle(stats):
+    """Largest single-cycle ratio ||r_{c}|| / ||r_{c-1}|| for c >= 2, the
+    quantity the solver's fallback check compares."""
+    h = stats["history"]
+    return max(h[c] / h[c - 1] for c in range(2, len(h))) if len(h) > 2 else float("inf")
+
+
+def score(batch, F, U, etas):
+    """Per batch member (each with its own damping vector): the solve stats."""
+    batch.set_eta(np.asarray(etas, dtype=np.float64).ravel())
+    U.zero_()
+    return batch.solve(F, U, tol=1e-30, raise_on_error=False)
+
+
+def best_damping(prob, m=8, passes=2, device="cuda"):
+    """Coordinate search of the per-level damping for one problem.
+    prob: dict(d, N, k, L, nu, sigma, c).  Returns (eta_best, rho_best,
+    rho_plain, worst single-cycle ratio of the fixed damping)."""
+    import torch
+    C = len(FACTORS)
+    B = BatchSolver(prob["d"], prob["N"], prob["L"], prob["k"], [prob["nu"]] * C, [prob["sigma"]] * C,
+                    [prob["c"]] * C, max_cycles=m).bind(device)
+    F = torch.tensor(B.manufactured_rhs(), device=device)
+    U = torch.zeros_like(F)
+    eta0 = B.get_eta()[0].copy()
+    nlev = eta0.size
+    cur = eta0.copy()
+    st = score(B, F, U, [eta0] * C)[0]
+    rho_plain, worst_plain = contraction(st), worst_cycle(st)
+    best = rho_plain
+    for _ in range(passes):
+        for lev in range(nlev):
+            cand = []
+            for f in FACTORS:
+                e = cur.copy()
+                e[lev] = min(0.95, cur[lev] * f)
+                cand.append(e)
+            rho = np.array([contraction(x) for x in score(B, F, U, cand)])
+            i = int(np.argmin(rho))
+            if rho[i] < best:
+                best, cur = rho[i], cand[i]
+    B.close()
+    return cur, best, rho_plain, worst_plain
+
+
+def training_problems():
+    """Default training grid: 2D, both degrees, two hierarchies."""
+    out = []
+    for (N, L) in ((256, 6), (128, 6)):
+        for k in (1, 2):
+            for nu in (1.0, 0.1, 0.01):
+                for sigma in (1e-2, 1.0, 1e2, 1e4):
+                    for peh in (0.0, 0.5, 1.0):
+                        c = math.sqrt(2.0) * nu * N * peh
+                        out.append(dict(d=2, N=N, k=k, L=L, nu=nu, sigma=sigma, c=c))
+    return out
+
+
+def sweep(problems, m=8, log=None):
+    """Training data: X (n x 4), Y (n x 5) target logits, M (n x 5) mask,
+    rho_plain, rho_best, worst_plain."""
+    X, Y, Mk, rp, rb, wp = [], [], [], [], [], []
+    for i, p in enumerate(problems):
+        t0 = time.time()
+        eta, rho, rho_plain, worst = best_damping(p, m=m)
+        y = np.zeros(NOUT)
+        mk = np.zeros(NOUT)
+        for j in range(min(NOUT, eta.size)):
+            y[j] = logit(eta[j])
+            mk[j] = 1.0
+        X.append(features(p["nu"], p["sigma"], p["c"], p["N"], p["k"]))
+        Y.append(y)
+        Mk.append(mk)
+        rp.append(rho_plain)
+        rb.append(rho)
+        wp.append(worst)
+        if log:
+            log(f"[sweep {i + 1}/{len(problems)}] {p} rho plain {rho_plain:.3f} -> {rho:.3f} "
+                f"eta {np.round(eta, 3).tolist()} ({time.time() - t0:.1f} s)")
+    return dict(X=np.array(X), Y=np.array(Y), M=np.array(Mk), rho_plain=np.array(rp), rho_best=np.array(rb),
+                worst_plain=np.array(wp))
+
+
+def glorot_init(seed=0):
+    """Glorot-uniform weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    shapes = [(32, 4), (32,), (32, 32), (32,), (NOUT, 32), (NOUT,)]
+    parts = []
+    for shp in shapes:
+        if len(shp) == 2:
+            lim = math.sqrt(6.0 / (shp[0] + shp[1]))
+            parts.append(rng.uniform(-lim, lim, shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X, Y, M, epochs=3000, lr=3e-3, seed=0, device="cuda", log=None):
+    """Full-batch Adam with the library's kernels; returns (W, loss history)."""
+    import torch
+    n = X.shape[0]
+    W = torch.tensor(glorot_init(seed), device=device)
+    # start the output bias at the mean target of each level
+    ymean = (Y * M).sum(axis=0) / np.maximum(M.sum(axis=0), 1)
+    W[MLP_NPARAM - NOUT:] = torch.tensor(ymean, dtype=torch.float32, device=device)
+    Xd = torch.tensor(X, dtype=torch.float32, device=device).contiguous()
+    Yd = torch.tensor(Y, dtype=torch.float32, device=device).contiguous()
+    Md = torch.tensor(M, dtype=torch.float32, device=device).contiguous()
+    m = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=device)
+    v = torch.zeros_like(m)
+    G = torch.zeros_like(m)
+    loss = torch.zeros(1, dtype=torch.float32, device=device)
+    work = torch.zeros(n * (MLP_NPARAM + 1), dtype=torch.float32, device=device)
+    scale = 1.0 / float(M.sum())
+    hist = []
+    for t in range(1, epochs + 1):
+        mlp_grad(W, Xd, Yd, Md, scale, work, G, loss)
+        mlp_adam(W, m, v, G, t, lr)
+        if t % 100 == 0 or t == 1:
+            hist.append((t, float(loss.item())))
+            if log and t % 500 == 0:
+                log(f"[train] epoch {t} loss {hist[-1][1]:.5f}")
+    mlp_grad(W, Xd, Yd, Md, scale, work, G, loss)
+    hist.append((epochs + 1, float(loss.item())))
+    return W.cpu().numpy(), hist
+
+
+def predict(W, X, device="cuda"):
+    import torch
+    Wd = torch.tensor(np.asarray(W, dtype=np.float32), device=device)
+    Xd = torch.tensor(np.asarray(X, dtype=np.float32), device=device).contiguous()
+    Z = torch.zeros(X.shape[0] * NOUT, dtype=torch.float32, device=device)
+    mlp_forward(Wd, Xd, Z)
+    return Z.cpu().numpy().reshape(-1, NOUT)
+
+
+def save(path, W, data, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    out = {"W": [float(x) for x in W], "meta": meta,
+           "train": {k: np.asarray(v).tolist() for k, v in data.items()}}
+    with open(path, "w") as f:
+        json.dump(out, f)
+
+
+def load(path=WEIGHTS):
+    d = json.load(open(path))
+    d["W"] = np.array(d["W"], dtype=np.float32)
+    for k, v in d["train"].items():
+        d["train"][k] = np.array(v)
+    return d
+
+
+def rho_plain_for(model, feats):
+    """Fallback threshold: the worst single-cycle ratio of the fixed damping
+    at the nearest training point (feature space)."""
+    X = model["train"]["X"]
+    rp = model["train"]["worst_plain"]
+    out = []
+    for f in np.atleast_2d(feats):
+        i = int(np.argmin(((X - f) ** 2).sum(axis=1)))
+        out.append(float(rp[i]))
+    return np.array(out)
+
+
+def problem_features(solver):
+    return np.array([features(nu, sg, c, solver.n_elem, solver.k)
+                     for nu, sg, c in zip(solver.nus, solver.sigmas, solver.cs)])
+
+
+def apply(solver, model=None, fallback=True):
+    """Switch a bound Solver/BatchSolver to the learned dampings of `model`
+    (default: the shipped weights), with the fallback threshold of the
+    nearest training point."""
+    model = load() if model is None else model
+    rho = rho_plain_for(model, problem_features(solver)) if fallback else None
+    solver.set_learned(model["W"], rho)
+
+
+def main():
+    log = lambda s: print(s, flush=True)
+    t0 = time.time()
+    probs = training_problems()
+    data = sweep(probs, log=log)
+    log(f"[sweep] {len(probs)} problems in {time.time() - t0:.0f} s; mean rho plain "
+        f"{data['rho_plain'].mean():.3f} best {data['rho_best'].mean():.3f}")
+    W, hist = train(data["X"], data["Y"], data["M"], log=log)
+    meta = {"epochs": len(hist), "final_loss": hist[-1][1], "factors": FACTORS, "m": 8,
+            "problems": len(probs), "features": "log10(nu)/2, log10(sigma)/4, |a|h/nu, k-1.5"}
+    out = sys.argv[1] if len(sys.argv) > 1 else WEIGHTS
+    save(out, W, data, meta)
+    log(f"[train] final loss {hist[-1][1]:.5f}; wrote {out}")
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -75,7 +75,7 @@ typedef struct {
     double eta;           /* fixed additive-Schwarz damping; <= 0: default      */
     int precision;        /* 0: FP64 V-cycles; 1 (dim 2): solve by FP64 iterative
                              refinement around FP32 V-cycles (see dfmg_solve)    */
-    int smoother;         /* 0 auto, 1 gather (owner computes), 2 coloured scatter */
+    int smoother;         /* 0 auto, 1 two-pass gather, 2 coloured scatter, 3 one-pass */
     int max_cycles;       /* solve: cycle limit (ENOTCONV beyond)               */
     int use_graph;        /* 1: replay the V-cycle as a captured hipGraph       */
     int cycles_per_check; /* solve: V-cycles launched between host checks       */
@@ -194,9 +194,11 @@ int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const doub
  *              level l (1, 2 or 4);
  * smoother[l]: 1 = subdomain-parallel local solves + per-DOF gather of the
  *              corrections, 2 = one launch per DOF-disjoint colour with plain
- *              read-modify-write scatter (no atomics); ignored on level 0.
- * Arrays have n_levels entries.  Results do not depend on lpr; the two
- * smoother forms differ only in summation order. */
+ *              read-modify-write scatter (no atomics), 3 = one pass in which
+ *              every DOF recomputes the local-solve rows it receives (equal
+ *              to 1 bit for bit); ignored on level 0.
+ * Arrays have n_levels entries.  The variants differ only in summation
+ * order (lpr splits a row's dot product over lanes). */
 int dfmg_get_tuning(const dfmg_ctx *ctx, int *lpr, int *smoother);
 int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
 /* Time every variant of every level on the device (reps launches each, HIP
@@ -256,6 +258,37 @@ int dfmg_export_prolongation(const dfmg_ctx *ctx, int level, int64_t *rowptr, in
  * prod_j sin(2 pi x_j), forcing f = sigma u - nu Lap u + grad p + (a . grad) u,
  * by Gauss quadrature with k+3 points per direction per element. */
 int dfmg_manufactured_rhs(const dfmg_ctx *ctx, double *F_host);
+
+/* ---- Batches of problems on different meshes ----
+ * nprob independent problems, problem p on grids[p] with pressure degree k[p],
+ * nu[p], sigma[p], adv[p] (adv may be NULL).  Problems sharing (dim, n_elem,
+ * n_levels, k) form a group that runs as one single-mesh batch (every launch
+ * covers the group); a solve step runs the groups on their own streams,
+ * forked from and joined back into the batch's stream, and with use_graph the
+ * whole step is captured once as one hipGraph with a branch per group.
+ * Vectors: problem p's F and U start at offset[p] of one FP64 device array of
+ * offset[nprob] entries (caller order; offsets from dfmg_multi_layout).
+ * Options apply to every group (precision 1 needs dim 2).  Errors: EINVAL. */
+typedef struct dfmg_multi dfmg_multi;
+int dfmg_multi_setup(int nprob, const dfmg_grid *grids, const int *k, const double *nu, const double *sigma,
+                     const dfmg_advection *adv, const dfmg_options *opt, dfmg_multi **out);
+void dfmg_multi_destroy(dfmg_multi *m);
+/* offset[nprob + 1] (host, nullable) and the number of groups (nullable). */
+int dfmg_multi_layout(const dfmg_multi *m, int64_t *offset, int *n_groups);
+int dfmg_multi_workspace_bytes(const dfmg_multi *m, size_t *bytes);
+/* As dfmg_bind, for all groups at once (one caller-owned workspace). */
+int dfmg_multi_bind(dfmg_multi *m, void *dev_workspace, size_t bytes, void *hip_stream);
+/* dfmg_autotune of every group. */
+int dfmg_multi_autotune(dfmg_multi *m, int reps);
+/* dfmg_set_learned for every problem; rho_plain_host has nprob entries in
+ * caller order (nullable). */
+int dfmg_multi_set_learned(dfmg_multi *m, const float *W_host, const double *rho_plain_host);
+/* Manufactured load vectors of every problem (host, offset[nprob] entries). */
+int dfmg_multi_manufactured_rhs(const dfmg_multi *m, double *F_host);
+/* dfmg_solve of every problem (stats: nprob entries, caller order). */
+int dfmg_multi_solve(dfmg_multi *m, const double *F_dev, double *U_dev, double tol, dfmg_stats *stats);
+int dfmg_multi_residual_norm(dfmg_multi *m, const double *F_dev, const double *U_dev, double *out_host);
+int dfmg_multi_div_norm(dfmg_multi *m, const double *U_dev, double *out_host);
 
 const char *dfmg_last_error(void);
 

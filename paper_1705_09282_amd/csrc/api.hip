@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -108,11 +109,11 @@ struct dfmg_ctx {
     float *mlpW = nullptr, *feat = nullptr;
     double *rho_plain = nullptr, *eta_fixed = nullptr;
     int *fallback = nullptr;
-    bool learned = false, use_fallback = false;
+    bool learned = false;
     int64_t spsi = 0;
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
-    std::vector<int> smoother;   // per level: 1 gather, 2 colour
+    std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
     std::vector<double> eta_host;  // [problem][level]
     const Hierarchy &S() const { return P[0]; }
@@ -294,6 +295,8 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
         if (assign) launch_fill<T>(h.n, U, h.n, T(0), stop, c->np, c->s);
         for (size_t col = 0; col + 1 < h.col_ptr.size(); ++col)
             launch_schwarz_colour<T>(a, v.col_list + h.col_ptr[col], h.col_ptr[col + 1] - h.col_ptr[col], c->s);
+    } else if (c->smoother[l] == 3) {
+        launch_schwarz_fused<T>(a, c->s);
     } else {
         launch_schwarz_gather<T>(a, c->s);
     }
@@ -322,7 +325,9 @@ void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
 
 void check(dfmg_ctx *c, int np_blocks) {
     Fallback fb{};
-    fb.rho = (c->learned && c->use_fallback) ? c->rho_plain : nullptr;
+    // the thresholds are read on the device (a captured graph keeps working
+    // when they change); 0 disables the fallback of a problem
+    fb.rho = c->rho_plain;
     fb.eta = c->eta;
     fb.eta_fixed = c->eta_fixed;
     fb.flag = c->fallback;
@@ -466,6 +471,9 @@ void check_level(const dfmg_ctx *c, int level, int minlevel = 0) {
     if (level < minlevel || level >= c->L()) throw ArgError("level out of range");
 }
 
+// no fallback thresholds: the fixed dampings are in use
+void clear_fallback(dfmg_ctx *c) { HIPCHK(hipMemsetAsync(c->rho_plain, 0, c->np * sizeof(double), c->s)); }
+
 void upload_eta(dfmg_ctx *c) {
     HIPCHK(hipMemcpyAsync(c->eta, c->eta_host.data(), c->eta_host.size() * sizeof(double), hipMemcpyHostToDevice,
                           c->s));
@@ -498,7 +506,7 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
     if (o.precision == 1 && dim != 2) throw ArgError("FP32 refinement is implemented for dim 2");
     if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
-    if (o.smoother < 0 || o.smoother > 2) throw ArgError("smoother must be 0, 1 or 2");
+    if (o.smoother < 0 || o.smoother > 3) throw ArgError("smoother must be 0, 1, 2 or 3");
     if (o.eta >= 1.0) throw ArgError("eta must be < 1");
     return o;
 }
@@ -509,12 +517,157 @@ void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
     const double eta0 = o.eta > 0 ? o.eta : c->S().default_eta;
     c->eta_host.assign((size_t)L * c->np, eta0);
     for (int p = 0; p < c->np; ++p) c->eta_host[(size_t)p * L] = 0.0;  // level 0: exact solve
-    c->smoother.assign(L, o.smoother == 2 ? 2 : 1);
+    c->smoother.assign(L, o.smoother == 0 ? 1 : o.smoother);
     c->lpr.assign(L, 1);
     for (int l = 0; l < L; ++l) {
         const int64_t n = c->S().lv[l].n * c->np;
         c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
     }
+}
+
+
+// ---- pieces of a solve, shared by dfmg_solve and the mixed-mesh batch ----
+
+int solve_kind(const dfmg_ctx *c) { return c->mixed() ? 2 : 1; }
+
+// Reset the per-problem flags and counters, re-apply learned dampings (a
+// fallback of an earlier solve replaced them), copy F and U in and set the
+// thresholds tol^2 ||F||^2.  xoff: device table of the problems' offsets in
+// F and U (null: problem p at p * n).
+void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *xoff, double tol) {
+    const int L = c->L(), np = c->np;
+    const int64_t n = c->S().lv[L - 1].n;
+    LevelData<double> &v = c->dl[L - 1].d;
+    const int nb = blocks_for(n);
+    launch_fill_int(np, c->stop, 0, c->s);
+    launch_fill_int(np, c->counter, 0, c->s);
+    launch_fill_int(np, c->fallback, 0, c->s);
+    if (c->learned) apply_learned(c);
+    launch_copy_off(n, F, xoff, n, v.F, nullptr, n, np, c->s);
+    launch_copy_off(n, U, xoff, n, v.U, nullptr, n, np, c->s);
+    launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
+    launch_reduce(nb, c->partial, c->nparts, c->thresh2, tol * tol, np, c->s);
+}
+
+void flags_to_host(dfmg_ctx *c, int *counter, int *stop, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(counter, c->counter, c->np * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(stop, c->stop, c->np * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+// cycle limit reached: measure the residual of the last iterates (problems
+// already stopped keep their flags and histories)
+void solve_limit(dfmg_ctx *c) {
+    const int L = c->L();
+    LevelData<double> &v = c->dl[L - 1].d;
+    check(c, spmv<double>(c, L - 1, v.F, v.U, v.r, c->partial, nullptr));
+}
+
+struct SolveOut {
+    std::vector<double> hist, th;
+    std::vector<int> fbk;
+};
+
+// Zero-mean pressure p <- p - (w^T p) 1 (partition of unity, |Omega| = 1),
+// copy U out, and queue the copies of histories, thresholds and fallback
+// flags into `so` (valid after the stream has been synchronized).
+void solve_end_launch(dfmg_ctx *c, double *U, const int64_t *xoff, SolveOut &so) {
+    const int L = c->L(), np = c->np;
+    const HostLevel &h = c->S().lv[L - 1];
+    const int64_t n = h.n;
+    LevelData<double> &v = c->dl[L - 1].d;
+    const int nbq = blocks_for(h.n_q);
+    for (int p = 0; p < np; ++p)
+        launch_dot_partial((int)h.n_q, v.U + p * n + h.n_v, c->wfine, 0, c->partial + p * c->nparts, 0, nbq, 1, c->s);
+    launch_reduce(nbq, c->partial, c->nparts, c->scal, 1.0, np, c->s);
+    launch_sub_scalar((int)h.n_q, v.U + h.n_v, n, c->scal, np, c->s);
+    launch_copy_off(n, v.U, nullptr, n, U, xoff, n, np, c->s);
+    so.hist.resize((size_t)np * DFMG_MAX_HISTORY);
+    so.th.resize(np);
+    so.fbk.resize(np);
+    HIPCHK(hipMemcpyAsync(so.fbk.data(), c->fallback, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipMemcpyAsync(so.hist.data(), c->hist, so.hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipMemcpyAsync(so.th.data(), c->thresh2, np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+}
+
+// Fill one dfmg_stats per problem; returns the worst status.
+int solve_stats(const dfmg_ctx *c, const SolveOut &so, const int *counter, const int *stopv, double tol, double secs,
+                dfmg_stats *out) {
+    int worst = DFMG_OK;
+    for (int p = 0; p < c->np; ++p) {
+        dfmg_stats &S = out[p];
+        S = dfmg_stats{};
+        const int cnt = std::min(counter[p], DFMG_MAX_HISTORY);
+        S.cycles = counter[p] - 1;
+        S.converged = stopv[p] == 1;
+        S.fallback = so.fbk[p];
+        S.fnorm = std::sqrt(so.th[p]) / tol;
+        S.n_history = cnt;
+        for (int i = 0; i < cnt; ++i) S.history[i] = so.hist[(size_t)p * DFMG_MAX_HISTORY + i];
+        S.res0 = cnt ? S.history[0] : 0.0;
+        S.res_final = cnt ? S.history[cnt - 1] : 0.0;
+        S.rho = (S.cycles > 0 && S.res0 > 0) ? std::pow(S.res_final / S.res0, 1.0 / S.cycles) : 0.0;
+        S.status = stopv[p] == 1 ? DFMG_OK : (stopv[p] == 2 ? DFMG_EDIVERGED : DFMG_ENOTCONV);
+        S.solve_seconds = secs;
+        if (S.status == DFMG_EDIVERGED) worst = DFMG_EDIVERGED;
+        else if (S.status == DFMG_ENOTCONV && worst == DFMG_OK) worst = DFMG_ENOTCONV;
+    }
+    return worst;
+}
+
+int solve_status(int status) {
+    if (status == DFMG_ENOTCONV) return fail(status, "maximum number of V-cycles reached");
+    if (status == DFMG_EDIVERGED) return fail(status, "residual diverged (NaN/Inf or growth)");
+    return DFMG_OK;
+}
+
+
+// ||F - K U||_2 of every problem (xoff as in solve_begin; with offsets the
+// vectors are first copied into the finest level's internal F and U)
+void residual_norms(dfmg_ctx *c, const double *F, const double *U, const int64_t *xoff, double *out) {
+    const int L = c->L();
+    const int64_t n = c->S().lv[L - 1].n;
+    if (xoff) {
+        LevelData<double> &v = c->dl[L - 1].d;
+        launch_copy_off(n, F, xoff, n, v.F, nullptr, n, c->np, c->s);
+        launch_copy_off(n, U, xoff, n, v.U, nullptr, n, c->np, c->s);
+        F = v.F;
+        U = v.U;
+    }
+    const int nb = spmv<double>(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
+    launch_reduce(nb, c->partial, c->nparts, c->scal, 1.0, c->np, c->s);
+    std::vector<double> v(c->np);
+    HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(v[p]);
+}
+
+// ||div u_h||_L2 of every problem, Up[p] = problem p's U on the device
+void div_norms(dfmg_ctx *c, const double *const *Up, double *out) {
+    const Hierarchy &H = c->S();
+    const HostLevel &h = H.lv[H.pb.L - 1];
+    for (int p = 0; p < c->np; ++p) {
+        DivArgs a{};
+        a.d = H.pb.d;
+        a.k = H.pb.k;
+        a.N = H.pb.N;
+        for (int R = 0; R < 4; ++R) {
+            a.off[R] = R <= h.nblk ? h.off[R] : 0;
+            for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
+        }
+        a.U = Up[p];
+        a.dcoef = c->dcoef;
+        a.pmass = c->pmass;
+        a.dvec = c->dvec;
+        a.partial = c->partial;
+        launch_div(a, c->s);
+        const int nb = blocks_for(h.n_q);
+        launch_div_mass(a, nb, c->s);
+        launch_reduce(nb, c->partial, 0, c->scal + p, 1.0, 1, c->s);
+    }
+    std::vector<double> v(c->np);
+    HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(std::max(0.0, v[p]));
 }
 
 }  // namespace
@@ -674,6 +827,7 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         up(c->eta, c->eta_host, s);
         up(c->eta_fixed, c->eta_host, s);
         HIPCHK(hipMemsetAsync(c->fallback, 0, np * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(c->rho_plain, 0, np * sizeof(double), s));
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
@@ -715,6 +869,7 @@ int dfmg_set_eta(dfmg_ctx *c, const double *eta, int n) {
         c->learned = false;
         if (c->bound) {
             enter(c);
+            clear_fallback(c);
             upload_eta(c);
             HIPCHK(hipMemcpyAsync(c->eta_fixed, c->eta_host.data(), c->eta_host.size() * sizeof(double),
                                   hipMemcpyHostToDevice, c->s));
@@ -746,13 +901,7 @@ int dfmg_residual_norm(dfmg_ctx *c, const double *F, const double *U, double *ou
     if (!c || !F || !U || !out) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         enter(c);
-        const int L = c->L();
-        const int nb = spmv<double>(c, L - 1, F, U, c->rtmp, c->partial, nullptr);
-        launch_reduce(nb, c->partial, c->nparts, c->scal, 1.0, c->np, c->s);
-        std::vector<double> v(c->np);
-        HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
-        HIPCHK(hipStreamSynchronize(c->s));
-        for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(v[p]);
+        residual_norms(c, F, U, nullptr, out);
         leave(c);
     });
 }
@@ -761,31 +910,10 @@ int dfmg_div_norm(dfmg_ctx *c, const double *U, double *out) {
     if (!c || !U || !out) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
         enter(c);
-        const Hierarchy &H = c->S();
-        const HostLevel &h = H.lv[H.pb.L - 1];
-        for (int p = 0; p < c->np; ++p) {
-            DivArgs a{};
-            a.d = H.pb.d;
-            a.k = H.pb.k;
-            a.N = H.pb.N;
-            for (int R = 0; R < 4; ++R) {
-                a.off[R] = R <= h.nblk ? h.off[R] : 0;
-                for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
-            }
-            a.U = U + p * h.n;
-            a.dcoef = c->dcoef;
-            a.pmass = c->pmass;
-            a.dvec = c->dvec;
-            a.partial = c->partial;
-            launch_div(a, c->s);
-            const int nb = blocks_for(h.n_q);
-            launch_div_mass(a, nb, c->s);
-            launch_reduce(nb, c->partial, 0, c->scal + p, 1.0, 1, c->s);
-        }
-        std::vector<double> v(c->np);
-        HIPCHK(hipMemcpyAsync(v.data(), c->scal, c->np * sizeof(double), hipMemcpyDeviceToHost, c->s));
-        HIPCHK(hipStreamSynchronize(c->s));
-        for (int p = 0; p < c->np; ++p) out[p] = std::sqrt(std::max(0.0, v[p]));
+        const int64_t n = c->S().lv[c->L() - 1].n;
+        std::vector<const double *> Up(c->np);
+        for (int p = 0; p < c->np; ++p) Up[p] = U + p * n;
+        div_norms(c, Up.data(), out);
         leave(c);
     });
 }
@@ -798,25 +926,11 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
     int rc = guarded([&] {
         enter(c);
         const auto t0 = std::chrono::steady_clock::now();
-        const int L = c->L(), np = c->np;
-        const HostLevel &h = c->S().lv[L - 1];
-        const int64_t n = h.n;
-        LevelData<double> &v = c->dl[L - 1].d;
-        const int nb = blocks_for(n);
-        const int kind = c->mixed() ? 2 : 1;
-        launch_fill_int(np, c->stop, 0, c->s);
-        launch_fill_int(np, c->counter, 0, c->s);
-        launch_fill_int(np, c->fallback, 0, c->s);
-        if (c->learned) apply_learned(c);  // a fallback of an earlier solve reset them
-        launch_copy(n, F, n, v.F, n, nullptr, np, c->s);
-        launch_copy(n, U, n, v.U, n, nullptr, np, c->s);
-        launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
-        launch_reduce(nb, c->partial, c->nparts, c->thresh2, tol * tol, np, c->s);
-        const int maxc = c->opt.max_cycles;
+        solve_begin(c, F, U, nullptr, tol);
+        const int maxc = c->opt.max_cycles, np = c->np;
         std::vector<int> stopv(np, 0), counter(np, 0);
         auto read_flags = [&] {
-            HIPCHK(hipMemcpyAsync(counter.data(), c->counter, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
-            HIPCHK(hipMemcpyAsync(stopv.data(), c->stop, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
+            flags_to_host(c, counter.data(), stopv.data(), c->s);
             HIPCHK(hipStreamSynchronize(c->s));
             for (int x : stopv)
                 if (!x) return false;
@@ -826,59 +940,26 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         bool all = false;
         while (launched < maxc) {
             const int chunk = std::min(c->opt.cycles_per_check, maxc - launched);
-            for (int i = 0; i < chunk; ++i) run_cycle(c, kind);
+            for (int i = 0; i < chunk; ++i) run_cycle(c, solve_kind(c));
             launched += chunk;
             if ((all = read_flags())) break;
         }
         if (!all) {
-            // limit reached: measure the residual of the last iterates (problems
-            // already stopped keep their flags and histories)
-            check(c, spmv<double>(c, L - 1, v.F, v.U, v.r, c->partial, nullptr));
+            solve_limit(c);
             read_flags();
         }
-        // zero-mean pressure: p <- p - (w^T p) 1 (partition of unity, |Omega| = 1)
-        const int nbq = blocks_for(h.n_q);
-        for (int p = 0; p < np; ++p)
-            launch_dot_partial((int)h.n_q, v.U + p * n + h.n_v, c->wfine, 0, c->partial + p * c->nparts, 0, nbq, 1,
-                               c->s);
-        launch_reduce(nbq, c->partial, c->nparts, c->scal, 1.0, np, c->s);
-        launch_sub_scalar((int)h.n_q, v.U + h.n_v, n, c->scal, np, c->s);
-        launch_copy(n, v.U, n, U, n, nullptr, np, c->s);
-        std::vector<double> hist((size_t)np * DFMG_MAX_HISTORY), th(np);
-        std::vector<int> fbk(np);
-        HIPCHK(hipMemcpyAsync(fbk.data(), c->fallback, np * sizeof(int), hipMemcpyDeviceToHost, c->s));
-        HIPCHK(hipMemcpyAsync(hist.data(), c->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
-        HIPCHK(hipMemcpyAsync(th.data(), c->thresh2, np * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        SolveOut so;
+        solve_end_launch(c, U, nullptr, so);
         HIPCHK(hipStreamSynchronize(c->s));
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         local.assign(np, dfmg_stats{});
-        int worst = DFMG_OK;
-        for (int p = 0; p < np; ++p) {
-            dfmg_stats &S = local[p];
-            const int cnt = std::min(counter[p], DFMG_MAX_HISTORY);
-            S.cycles = counter[p] - 1;
-            S.converged = stopv[p] == 1;
-            S.fallback = fbk[p];
-            S.fnorm = std::sqrt(th[p]) / tol;
-            S.n_history = cnt;
-            for (int i = 0; i < cnt; ++i) S.history[i] = hist[(size_t)p * DFMG_MAX_HISTORY + i];
-            S.res0 = cnt ? S.history[0] : 0.0;
-            S.res_final = cnt ? S.history[cnt - 1] : 0.0;
-            S.rho = (S.cycles > 0 && S.res0 > 0) ? std::pow(S.res_final / S.res0, 1.0 / S.cycles) : 0.0;
-            S.status = stopv[p] == 1 ? DFMG_OK : (stopv[p] == 2 ? DFMG_EDIVERGED : DFMG_ENOTCONV);
-            S.solve_seconds = secs;
-            if (S.status == DFMG_EDIVERGED) worst = DFMG_EDIVERGED;
-            else if (S.status == DFMG_ENOTCONV && worst == DFMG_OK) worst = DFMG_ENOTCONV;
-        }
-        status = worst;
+        status = solve_stats(c, so, counter.data(), stopv.data(), tol, secs, local.data());
         leave(c);
     });
     if (st)
         for (size_t p = 0; p < local.size(); ++p) st[p] = local[p];
     if (rc != DFMG_OK) return rc;
-    if (status == DFMG_ENOTCONV) return fail(status, "maximum number of V-cycles reached");
-    if (status == DFMG_EDIVERGED) return fail(status, "residual diverged (NaN/Inf or growth)");
-    return DFMG_OK;
+    return solve_status(status);
 }
 
 int dfmg_level_residual(dfmg_ctx *c, int level, const double *F, const double *U, double *r) {
@@ -968,8 +1049,8 @@ int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
 int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
     for (int l = 0; l < c->L(); ++l)
-        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] == 1 || smoother[l] == 2))
-            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1 or 2");
+        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] >= 1 && smoother[l] <= 3))
+            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1, 2 or 3");
     return guarded([&] {
         for (int l = 0; l < c->L(); ++l) {
             c->lpr[l] = lpr[l];
@@ -1020,7 +1101,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 }
                 double bests = 1e30;
                 int bs = c->smoother[l];
-                for (int sm : {1, 2}) {
+                for (int sm : {1, 2, 3}) {
                     c->smoother[l] = sm;
                     const double t = timed([&] { schwarz<T>(c, l, v.r, v.U, false, nullptr); });
                     if (t < bests) {
@@ -1076,6 +1157,7 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
         enter(c);
         if (!W) {
             c->learned = false;
+            clear_fallback(c);
             upload_eta(c);
             leave(c);
             return;
@@ -1091,8 +1173,8 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
         }
         up(c->mlpW, W, MLP_NPARAM, c->s);
         up(c->feat, feat, c->s);
-        c->use_fallback = rho != nullptr;
         if (rho) up(c->rho_plain, rho, c->np, c->s);
+        else clear_fallback(c);
         c->learned = true;
         apply_learned(c);
         HIPCHK(hipStreamSynchronize(c->s));
@@ -1209,6 +1291,374 @@ int dfmg_manufactured_rhs(const dfmg_ctx *c, double *F) {
     return guarded([&] {
         const int64_t n = c->S().lv[c->L() - 1].n;
         for (int p = 0; p < c->np; ++p) manufactured_rhs(c->P[p], F + p * n);
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of problems on different meshes: one single-mesh batch (dfmg_ctx)
+// per (dim, n_elem, n_levels, k), each on its own stream.  A solve step forks
+// the groups off the batch's stream, runs each group's cycle on its stream
+// and joins them; with use_graph the whole fork/join step is captured once as
+// one hipGraph with a branch per group and replayed.
+// ---------------------------------------------------------------------------
+
+struct dfmg_multi {
+    std::vector<dfmg_ctx *> g;
+    std::vector<std::vector<int>> member;  // caller indices of each group's problems
+    std::vector<int> base;                 // first position of each group in group order
+    std::vector<int64_t> off;              // caller offset of each problem's vectors (nprob + 1)
+    std::vector<size_t> ws_off;            // workspace offset of each group
+    size_t ws_tab = 0, ws_flags = 0, ws_total = 0;
+    int64_t *tab = nullptr;                // device: caller offsets in group order
+    int *dflags = nullptr;                 // device: counters then stop flags, group order
+    int *hflags = nullptr;                 // pinned host copy of dflags
+    dfmg_options opt{};
+    int nprob = 0;
+    bool bound = false;
+    hipStream_t user = nullptr, s = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
+    hipGraphExec_t graph = nullptr;
+    int graph_kind = -1;
+};
+
+namespace {
+
+void mfork(dfmg_multi *m) {
+    HIPCHK(hipEventRecord(m->ev_fork, m->s));
+    for (dfmg_ctx *c : m->g) HIPCHK(hipStreamWaitEvent(c->s, m->ev_fork, 0));
+}
+void mjoin(dfmg_multi *m) {
+    for (size_t i = 0; i < m->g.size(); ++i) {
+        HIPCHK(hipEventRecord(m->ev_join[i], m->g[i]->s));
+        HIPCHK(hipStreamWaitEvent(m->s, m->ev_join[i], 0));
+    }
+}
+void menter(dfmg_multi *m) {
+    if (!m->bound) throw StateError("workspace not bound (call dfmg_multi_bind first)");
+    HIPCHK(hipEventRecord(m->ev_in, m->user));
+    HIPCHK(hipStreamWaitEvent(m->s, m->ev_in, 0));
+}
+void mleave(dfmg_multi *m) {
+    HIPCHK(hipEventRecord(m->ev_out, m->s));
+    HIPCHK(hipStreamWaitEvent(m->user, m->ev_out, 0));
+}
+
+// counters and stop flags of every group into dflags (on the batch stream)
+void pack_flags(dfmg_multi *m) {
+    for (size_t i = 0; i < m->g.size(); ++i) {
+        dfmg_ctx *c = m->g[i];
+        launch_copy_int(c->np, c->counter, m->dflags + m->base[i], m->s);
+        launch_copy_int(c->np, c->stop, m->dflags + m->nprob + m->base[i], m->s);
+    }
+}
+
+// one cycle (kind as in run_cycle) of every group, then the flag packing
+void multi_body(dfmg_multi *m, int kind) {
+    mfork(m);
+    for (dfmg_ctx *c : m->g) body(c, kind);
+    mjoin(m);
+    pack_flags(m);
+}
+
+void multi_step(dfmg_multi *m, int kind) {
+    if (!m->opt.use_graph) {
+        multi_body(m, kind);
+        return;
+    }
+    if (m->graph && m->graph_kind != kind) {
+        HIPCHK(hipGraphExecDestroy(m->graph));
+        m->graph = nullptr;
+    }
+    if (!m->graph) {
+        hipGraph_t gr;
+        HIPCHK(hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal));
+        multi_body(m, kind);
+        HIPCHK(hipStreamEndCapture(m->s, &gr));
+        HIPCHK(hipGraphInstantiate(&m->graph, gr, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(gr));
+        m->graph_kind = kind;
+    }
+    HIPCHK(hipGraphLaunch(m->graph, m->s));
+}
+
+void multi_drop_graph(dfmg_multi *m) {
+    if (m->graph) {
+        HIPCHK(hipGraphExecDestroy(m->graph));
+        m->graph = nullptr;
+    }
+}
+
+// read the packed flags; true when every problem has stopped
+bool multi_flags(dfmg_multi *m) {
+    HIPCHK(hipMemcpyAsync(m->hflags, m->dflags, 2 * m->nprob * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPCHK(hipStreamSynchronize(m->s));
+    for (int i = 0; i < m->nprob; ++i)
+        if (!m->hflags[m->nprob + i]) return false;
+    return true;
+}
+
+void multi_plan(dfmg_multi *m) {
+    size_t used = 0;
+    m->ws_off.clear();
+    for (dfmg_ctx *c : m->g) {
+        Arena A;
+        plan(c, A);
+        m->ws_off.push_back(used);
+        used += ((A.used + 256 + 255) & ~(size_t)255);
+    }
+    m->ws_tab = used;
+    used += ((m->nprob * sizeof(int64_t) + 255) & ~(size_t)255);
+    m->ws_flags = used;
+    used += ((2 * m->nprob * sizeof(int) + 255) & ~(size_t)255);
+    m->ws_total = used;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dfmg_multi_setup(int nprob, const dfmg_grid *grids, const int *k, const double *nu, const double *sigma,
+                     const dfmg_advection *adv, const dfmg_options *opt, dfmg_multi **out) {
+    if (!grids || !k || !nu || !sigma || !out) return fail(DFMG_EINVAL, "null argument");
+    if (nprob < 1 || nprob > 65535) return fail(DFMG_EINVAL, "batch size must be in [1, 65535]");
+    *out = nullptr;
+    return guarded([&] {
+        auto *m = new dfmg_multi();
+        try {
+            m->nprob = nprob;
+            // groups in order of first appearance
+            std::vector<std::array<int, 4>> keys;
+            std::vector<int> gid(nprob);
+            for (int p = 0; p < nprob; ++p) {
+                const std::array<int, 4> key{grids[p].dim, grids[p].n_elem, grids[p].n_levels, k[p]};
+                auto it = std::find(keys.begin(), keys.end(), key);
+                gid[p] = (int)(it - keys.begin());
+                if (it == keys.end()) {
+                    keys.push_back(key);
+                    m->member.emplace_back();
+                }
+                m->member[gid[p]].push_back(p);
+            }
+            m->off.assign(nprob + 1, 0);
+            for (size_t i = 0; i < keys.size(); ++i) {
+                const auto &mem = m->member[i];
+                std::vector<double> gnu, gsig;
+                std::vector<dfmg_advection> gadv;
+                for (int p : mem) {
+                    gnu.push_back(nu[p]);
+                    gsig.push_back(sigma[p]);
+                    gadv.push_back(adv ? adv[p] : dfmg_advection{0, 0.0});
+                }
+                dfmg_ctx *c = nullptr;
+                const int rc = dfmg_batch_setup((int)mem.size(), &grids[mem[0]], keys[i][3], gnu.data(), gsig.data(),
+                                                gadv.data(), opt, &c);
+                if (rc != DFMG_OK) throw ArgError("group " + std::to_string(i) + ": " + g_err);
+                m->g.push_back(c);
+                m->opt = c->opt;
+                const int64_t n = c->S().lv[c->L() - 1].n;
+                for (int p : mem) m->off[p + 1] = n;
+            }
+            for (int p = 0; p < nprob; ++p) m->off[p + 1] += m->off[p];
+            int b = 0;
+            for (const auto &mem : m->member) {
+                m->base.push_back(b);
+                b += (int)mem.size();
+            }
+        } catch (...) {
+            dfmg_multi_destroy(m);
+            throw;
+        }
+        *out = m;
+    });
+}
+
+void dfmg_multi_destroy(dfmg_multi *m) {
+    if (!m) return;
+    if (m->graph) (void)hipGraphExecDestroy(m->graph);
+    for (dfmg_ctx *c : m->g) dfmg_destroy(c);
+    for (hipEvent_t e : m->ev_join) (void)hipEventDestroy(e);
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+    if (m->ev_out) (void)hipEventDestroy(m->ev_out);
+    if (m->s) (void)hipStreamDestroy(m->s);
+    if (m->hflags) (void)hipHostFree(m->hflags);
+    delete m;
+}
+
+int dfmg_multi_layout(const dfmg_multi *m, int64_t *offset, int *n_groups) {
+    if (!m) return fail(DFMG_EINVAL, "null argument");
+    if (offset) std::copy(m->off.begin(), m->off.end(), offset);
+    if (n_groups) *n_groups = (int)m->g.size();
+    return DFMG_OK;
+}
+
+int dfmg_multi_workspace_bytes(const dfmg_multi *m, size_t *bytes) {
+    if (!m || !bytes) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        multi_plan(const_cast<dfmg_multi *>(m));
+        *bytes = m->ws_total;
+    });
+}
+
+int dfmg_multi_bind(dfmg_multi *m, void *ws, size_t bytes, void *stream) {
+    if (!m || !ws) return fail(DFMG_EINVAL, "null argument");
+    if (((uintptr_t)ws) & 255) return fail(DFMG_EINVAL, "workspace must be 256-byte aligned");
+    return guarded([&] {
+        if (m->bound) throw StateError("already bound");
+        multi_plan(m);
+        if (bytes < m->ws_total) throw std::bad_alloc();
+        char *base = (char *)ws;
+        for (size_t i = 0; i < m->g.size(); ++i) {
+            size_t b = 0;
+            if (dfmg_workspace_bytes(m->g[i], &b) != DFMG_OK) throw ArgError(g_err);
+            if (dfmg_bind(m->g[i], base + m->ws_off[i], b, stream) != DFMG_OK) throw HipError(g_err);
+        }
+        m->tab = (int64_t *)(base + m->ws_tab);
+        m->dflags = (int *)(base + m->ws_flags);
+        m->user = (hipStream_t)stream;
+        HIPCHK(hipStreamCreateWithFlags(&m->s, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+        m->ev_join.assign(m->g.size(), nullptr);
+        for (auto &e : m->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipHostMalloc((void **)&m->hflags, 2 * m->nprob * sizeof(int), hipHostMallocDefault));
+        std::vector<int64_t> tab;
+        for (const auto &mem : m->member)
+            for (int p : mem) tab.push_back(m->off[p]);
+        up(m->tab, tab, m->s);
+        HIPCHK(hipMemsetAsync(m->dflags, 0, 2 * m->nprob * sizeof(int), m->s));
+        HIPCHK(hipStreamSynchronize(m->s));
+        m->bound = true;
+    });
+}
+
+int dfmg_multi_autotune(dfmg_multi *m, int reps) {
+    if (!m || reps < 1) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        if (!m->bound) throw StateError("workspace not bound (call dfmg_multi_bind first)");
+        std::vector<double> ms;
+        for (dfmg_ctx *c : m->g) {
+            ms.assign(2 * c->L(), 0.0);
+            if (dfmg_autotune(c, reps, ms.data()) != DFMG_OK) throw HipError(g_err);
+        }
+        multi_drop_graph(m);
+    });
+}
+
+int dfmg_multi_set_learned(dfmg_multi *m, const float *W, const double *rho) {
+    if (!m) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        if (!m->bound) throw StateError("workspace not bound (call dfmg_multi_bind first)");
+        for (size_t i = 0; i < m->g.size(); ++i) {
+            std::vector<double> r;
+            if (rho)
+                for (int p : m->member[i]) r.push_back(rho[p]);
+            if (dfmg_set_learned(m->g[i], W, rho ? r.data() : nullptr) != DFMG_OK) throw HipError(g_err);
+        }
+    });
+}
+
+int dfmg_multi_manufactured_rhs(const dfmg_multi *m, double *F) {
+    if (!m || !F) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        for (size_t i = 0; i < m->g.size(); ++i)
+            for (size_t j = 0; j < m->member[i].size(); ++j)
+                manufactured_rhs(m->g[i]->P[j], F + m->off[m->member[i][j]]);
+    });
+}
+
+int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg_stats *st) {
+    if (!m || !F || !U) return fail(DFMG_EINVAL, "null argument");
+    if (!(tol > 0.0)) return fail(DFMG_EINVAL, "tol must be positive");
+    int status = DFMG_OK;
+    std::vector<dfmg_stats> local;
+    int rc = guarded([&] {
+        menter(m);
+        const auto t0 = std::chrono::steady_clock::now();
+        const size_t G = m->g.size();
+        mfork(m);
+        for (size_t i = 0; i < G; ++i) solve_begin(m->g[i], F, U, m->tab + m->base[i], tol);
+        mjoin(m);
+        const int kind = solve_kind(m->g[0]);
+        const int maxc = m->opt.max_cycles;
+        int launched = 0;
+        bool all = false;
+        while (launched < maxc) {
+            const int chunk = std::min(m->opt.cycles_per_check, maxc - launched);
+            for (int i = 0; i < chunk; ++i) multi_step(m, kind);
+            launched += chunk;
+            if ((all = multi_flags(m))) break;
+        }
+        if (!all) {
+            mfork(m);
+            for (dfmg_ctx *c : m->g) solve_limit(c);
+            mjoin(m);
+            pack_flags(m);
+            multi_flags(m);
+        }
+        std::vector<SolveOut> so(G);
+        mfork(m);
+        for (size_t i = 0; i < G; ++i) solve_end_launch(m->g[i], U, m->tab + m->base[i], so[i]);
+        mjoin(m);
+        HIPCHK(hipStreamSynchronize(m->s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        local.assign(m->nprob, dfmg_stats{});
+        std::vector<dfmg_stats> gs;
+        int worst = DFMG_OK;
+        for (size_t i = 0; i < G; ++i) {
+            gs.assign(m->g[i]->np, dfmg_stats{});
+            const int w = solve_stats(m->g[i], so[i], m->hflags + m->base[i], m->hflags + m->nprob + m->base[i], tol,
+                                      secs, gs.data());
+            if (w == DFMG_EDIVERGED || (w == DFMG_ENOTCONV && worst == DFMG_OK)) worst = w;
+            for (size_t j = 0; j < gs.size(); ++j) local[m->member[i][j]] = gs[j];
+        }
+        status = worst;
+        mleave(m);
+    });
+    if (st)
+        for (size_t p = 0; p < local.size(); ++p) st[p] = local[p];
+    if (rc != DFMG_OK) return rc;
+    return solve_status(status);
+}
+
+int dfmg_multi_residual_norm(dfmg_multi *m, const double *F, const double *U, double *out) {
+    if (!m || !F || !U || !out) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        menter(m);
+        std::vector<double> v;
+        for (size_t i = 0; i < m->g.size(); ++i) {
+            dfmg_ctx *c = m->g[i];
+            v.assign(c->np, 0.0);
+            enter(c);
+            residual_norms(c, F, U, m->tab + m->base[i], v.data());
+            leave(c);
+            for (int j = 0; j < c->np; ++j) out[m->member[i][j]] = v[j];
+        }
+        mleave(m);
+    });
+}
+
+int dfmg_multi_div_norm(dfmg_multi *m, const double *U, double *out) {
+    if (!m || !U || !out) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        menter(m);
+        std::vector<double> v;
+        std::vector<const double *> Up;
+        for (size_t i = 0; i < m->g.size(); ++i) {
+            dfmg_ctx *c = m->g[i];
+            v.assign(c->np, 0.0);
+            Up.clear();
+            for (int p : m->member[i]) Up.push_back(U + m->off[p]);
+            enter(c);
+            div_norms(c, Up.data(), v.data());
+            leave(c);
+            for (int j = 0; j < c->np; ++j) out[m->member[i][j]] = v[j];
+        }
+        mleave(m);
     });
 }
 

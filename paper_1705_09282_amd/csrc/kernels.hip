@@ -74,6 +74,56 @@ void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
     hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
 }
 
+// One-pass form: DOF j recomputes the rows of the local solves that land on
+// it, (M_i E_i r)_m for every entry (i, m) with dofs_i[m] = j, and adds their
+// damped sum -- no correction buffer and one launch.  Each row is summed in
+// the same order as k_patch_solve and the rows in the same order as
+// k_dof_update, so the result equals the two-pass form bit for bit.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
+    const int prob = blockIdx.y;
+    const int halt = a.stop ? a.stop[prob] : 0;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int j = b * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    T *U = a.U + prob * a.svec;
+    const T *r = a.r + prob * a.svec;
+    const T *M = a.M + prob * a.sM;
+    const int4 *ent = a.ent_info + (int64_t)prob * a.nent;
+    const T eta = (T)a.eta[prob * a.seta];
+    const T u = a.assign ? T(0) : U[j];
+    T acc = 0;
+    const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int4 info = ent[a.inv_pos[e]];
+        const T *m = M + info.x;
+        const int32_t *dofs = a.pdofs + info.y;
+        const int nn = info.z;
+        T row = 0;
+        for (int c = 0; c < nn; c += 8) {
+            int d[8];
+            T mv[8], rv[8];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                const bool ok = c + w < nn;
+                d[w] = dofs[ok ? c + w : c];
+                mv[w] = ok ? m[c + w] : T(0);
+            }
+#pragma unroll
+            for (int w = 0; w < 8; ++w) rv[w] = r[d[w]];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) row = fma(mv[w], rv[w], row);
+        }
+        acc += row;
+    }
+    if (!halt) U[j] = fma(eta, acc, u);
+}
+
+template <class T>
+void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_schwarz_fused<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
+}
+
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
 // each thread solves one subdomain and adds its damped correction with plain
 // read-modify-writes.
@@ -264,6 +314,8 @@ void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
 
 template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);
 template void launch_schwarz_gather<float>(const PatchArgsT<float> &, hipStream_t);
+template void launch_schwarz_fused<double>(const PatchArgsT<double> &, hipStream_t);
+template void launch_schwarz_fused<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);
 template void launch_csr<double>(int, const int32_t *, const int32_t *, const double *, const double *, int64_t,
@@ -295,6 +347,29 @@ void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, 
                  hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_copy, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, sx, y, sy, stop);
+}
+
+__global__ void k_copy_int(int n, const int *x, int *y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+void launch_copy_int(int n, const int *x, int *y, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, x, y);
+}
+
+// problem p's vector at x + xoff[p] (or p * sx) copied to y + yoff[p] (or p * sy)
+__global__ void k_copy_off(int64_t n, const double *x, const int64_t *xoff, int64_t sx, double *y,
+                           const int64_t *yoff, int64_t sy) {
+    const int prob = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t xo = xoff ? xoff[prob] : prob * sx, yo = yoff ? yoff[prob] : prob * sy;
+    y[yo + i] = x[xo + i];
+}
+void launch_copy_off(int64_t n, const double *x, const int64_t *xoff, int64_t sx, double *y, const int64_t *yoff,
+                     int64_t sy, int nprob, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_off, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, xoff, sx, y, yoff, sy);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot_partial(int n, const double *x, const double *y, int64_t sxy,

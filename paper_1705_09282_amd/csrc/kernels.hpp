@@ -72,6 +72,9 @@ template <class T>
 void launch_spmv(int d, int k, int lpr, const SpmvArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s);
+// one pass: every DOF recomputes the local-solve rows it receives (no buffer)
+template <class T>
+void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s);
 // y = (add ? y : 0) + A x, A shared CSR; x, y per problem (strides sx, sy)
@@ -86,8 +89,13 @@ void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, in
 template <class T>
 void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s);
 void launch_fill_int(int n, int *x, int v, hipStream_t s);
+void launch_copy_int(int n, const int *x, int *y, hipStream_t s);
 void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop, int nprob,
                  hipStream_t s);
+// problem p: y[yoff[p] + i] = x[xoff[p] + i], i < n; a null offset table
+// means p * stride (used for vectors of problems laid out in the caller's order)
+void launch_copy_off(int64_t n, const double *x, const int64_t *xoff, int64_t sx, double *y, const int64_t *yoff,
+                     int64_t sy, int nprob, hipStream_t s);
 void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s);
 // per problem: partial[p * spart + b] = block sums of x . y
 void launch_dot_partial(int n, const double *x, const double *y, int64_t sxy, double *partial, int64_t spart,

@@ -89,6 +89,18 @@ SIGNATURES = [
     ("dfmg_prolongation_nnz", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_prolongation", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_manufactured_rhs", c_int, [c_void_p, c_dblp]),
+    ("dfmg_multi_setup", c_int, [c_int, ctypes.POINTER(Grid), c_i32p, c_dblp, c_dblp, ctypes.POINTER(Advection),
+                                 ctypes.POINTER(Options), ctypes.POINTER(c_void_p)]),
+    ("dfmg_multi_destroy", None, [c_void_p]),
+    ("dfmg_multi_layout", c_int, [c_void_p, c_i64p, ctypes.POINTER(c_int)]),
+    ("dfmg_multi_workspace_bytes", c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
+    ("dfmg_multi_bind", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("dfmg_multi_autotune", c_int, [c_void_p, c_int]),
+    ("dfmg_multi_set_learned", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp]),
+    ("dfmg_multi_manufactured_rhs", c_int, [c_void_p, c_dblp]),
+    ("dfmg_multi_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
+    ("dfmg_multi_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
+    ("dfmg_multi_div_norm", c_int, [c_void_p, c_void_p, c_dblp]),
     ("dfmg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -440,3 +452,105 @@ class BatchSolver(Solver):
 
     def div_norm(self, U):
         return self._div_norms(U)
+
+
+class MultiSolver:
+    """Independent problems on different meshes: problem p is (dim, n_elem,
+    n_levels, k)[p] with nu[p], sigma[p] and rotation speed c[p].  Problems
+    sharing a mesh and degree run as one batch; the batches run concurrently
+    on their own streams inside one captured graph per step.  Vectors: one
+    FP64 array, problem p at offsets[p] .. offsets[p + 1]."""
+
+    def __init__(self, meshes, nus, sigmas, cs=None, **options):
+        self.nprob = len(meshes)
+        cs = [0.0] * self.nprob if cs is None else list(cs)
+        if not (len(nus) == len(sigmas) == len(cs) == self.nprob):
+            raise ValueError("one mesh, nu, sigma and c per problem")
+        self.meshes = [tuple(int(x) for x in m) for m in meshes]
+        self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
+        grids = (Grid * self.nprob)(*[Grid(d, N, L) for (d, N, L, _k) in self.meshes])
+        ks = np.ascontiguousarray([m[3] for m in self.meshes], dtype=np.int32)
+        adv = (Advection * self.nprob)(*[Advection(1 if c != 0.0 else 0, float(c)) for c in cs])
+        nu_a = np.ascontiguousarray(nus, dtype=np.float64)
+        sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
+        opt = default_options(**options)
+        ctx = c_void_p()
+        self._ctx = c_void_p()
+        _check(lib().dfmg_multi_setup(self.nprob, grids, _ptr(ks, ctypes.c_int32), _ptr(nu_a, ctypes.c_double),
+                                      _ptr(sg_a, ctypes.c_double), adv, ctypes.byref(opt), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._ws = None
+        off = np.zeros(self.nprob + 1, np.int64)
+        ng = c_int()
+        _check(lib().dfmg_multi_layout(self._ctx, _ptr(off, ctypes.c_int64), ctypes.byref(ng)))
+        self.offsets = off
+        self.n_groups = ng.value
+
+    @property
+    def n_total(self):
+        return int(self.offsets[-1])
+
+    def workspace_bytes(self):
+        b = c_size_t()
+        _check(lib().dfmg_multi_workspace_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    def bind(self, device="cuda"):
+        import torch
+        nbytes = self.workspace_bytes()
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream(self._ws.device).cuda_stream
+        _check(lib().dfmg_multi_bind(self._ctx, c_void_p(aligned), nbytes, c_void_p(stream)))
+        return self
+
+    def autotune(self, reps=10):
+        _check(lib().dfmg_multi_autotune(self._ctx, int(reps)))
+
+    def set_learned(self, W, rho_plain=None):
+        if W is None:
+            _check(lib().dfmg_multi_set_learned(self._ctx, None, None))
+            return
+        w = np.ascontiguousarray(W, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError("expected 1381 parameters")
+        r = None if rho_plain is None else np.ascontiguousarray(rho_plain, dtype=np.float64)
+        if r is not None and r.size != self.nprob:
+            raise ValueError("one plain rate per problem")
+        _check(lib().dfmg_multi_set_learned(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            None if r is None else _ptr(r, ctypes.c_double)))
+
+    def manufactured_rhs(self):
+        F = np.zeros(self.n_total, np.float64)
+        _check(lib().dfmg_multi_manufactured_rhs(self._ctx, _ptr(F, ctypes.c_double)))
+        return F
+
+    def solve(self, F, U, tol=1e-8, raise_on_error=True):
+        st = (Stats * self.nprob)()
+        code = lib().dfmg_multi_solve(self._ctx, _dev(F, self.n_total), _dev(U, self.n_total), float(tol), st)
+        if raise_on_error:
+            _check(code)
+        return [x.as_dict() for x in st]
+
+    def residual_norm(self, F, U):
+        out = np.zeros(self.nprob)
+        _check(lib().dfmg_multi_residual_norm(self._ctx, _dev(F, self.n_total), _dev(U, self.n_total),
+                                              _ptr(out, ctypes.c_double)))
+        return out
+
+    def div_norm(self, U):
+        out = np.zeros(self.nprob)
+        _check(lib().dfmg_multi_div_norm(self._ctx, _dev(U, self.n_total), _ptr(out, ctypes.c_double)))
+        return out
+
+    def close(self):
+        if self._ctx:
+            lib().dfmg_multi_destroy(self._ctx)
+            self._ctx = c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,120 @@
+"""The 3D Stokes and 2D Oseen workloads at their full sizes, checked through
+properties the oracle can establish at that size: the library's finest-grid
+matrix equals the oracle's assembly, the converged iterate meets the
+tolerance measured with the oracle's matrix and load vector, the velocity is
+divergence-free, and convergence does not degrade with refinement."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.spaces import Discretization
+from oracle.assemble import assemble, load_vector, rotation_field
+from oracle.manufactured import forcing
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def oracle_system(cfg):
+    disc = Discretization(cfg["d"], cfg["N"], cfg["k"])
+    adv = rotation_field(cfg["c"]) if cfg["c"] else None
+    K = assemble(disc, cfg["nu"], cfg["sigma"], adv)["K"]
+    F = load_vector(disc, forcing(cfg["d"], cfg["nu"], cfg["sigma"], adv))
+    return K.tocsr(), F
+
+
+def check_matrix(solver, K):
+    rp, col, val = solver.export_matrix(solver.n_levels - 1)
+    # compare as sparse matrices (explicit zeros dropped on both sides)
+    import scipy.sparse as sp
+    Kg = sp.csr_matrix((val, col, rp), shape=K.shape)
+    D = (Kg - K).tocsr()
+    D.eliminate_zeros()
+    err = np.abs(D.data).max() if D.nnz else 0.0
+    return err / np.abs(K.data).max()
+
+
+def test_stokes3d_full_size():
+    """3D generalized Stokes, k=1, 32^3, 4 grids, the eight seeded sigmas as
+    one batch (FP64): each meets 1e-8 with the oracle's matrix, is
+    divergence-free, and needs at most 20% more cycles than on 16^3 (the
+    fixed 3D damping contracts by ~0.85 per cycle on both grids)."""
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    sig = workloads.stokes3d_sigmas()
+    cfg = workloads.stokes3d(sig[0])
+    print(f"\n[case] 3D k=1 32^3 L=4 sigmas {np.round(sig, 3).tolist()}", flush=True)
+    B = BatchSolver(3, cfg["N"], cfg["L"], cfg["k"], [1.0] * len(sig), list(sig)).bind()
+    F = torch.tensor(B.manufactured_rhs(), device="cuda")
+    U = torch.zeros_like(F)
+    st = B.solve(F, U, tol=1e-8)
+    div = B.div_norm(U)
+    cyc = [s["cycles"] for s in st]
+    print(f"[3d] cycles {cyc} max div {div.max():.1e}", flush=True)
+    assert all(s["converged"] for s in st) and div.max() < 1e-10
+    # problem 0 against the oracle's assembly at full size
+    S = BatchSolver(3, cfg["N"], cfg["L"], cfg["k"], [1.0], [sig[0]])
+    K, Fo = oracle_system(cfg)
+    merr = check_matrix(S, K)
+    n = B.n
+    Fg = F[:n].cpu().numpy()
+    ferr = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    U0 = U[:n].cpu().numpy()
+    res = np.linalg.norm(Fo - K @ U0) / np.linalg.norm(Fo)
+    print(f"[3d] matrix rel err {merr:.1e} load rel err {ferr:.1e} oracle residual {res:.2e}", flush=True)
+    assert merr < 1e-12 and ferr < 1e-12 and res < 1.05e-8
+    S.close()
+    # h-independence: the same sigmas on 16^3 with one grid fewer
+    C = BatchSolver(3, 16, 3, 1, [1.0] * len(sig), list(sig)).bind()
+    Fc = torch.tensor(C.manufactured_rhs(), device="cuda")
+    Uc = torch.zeros_like(Fc)
+    cc = [s["cycles"] for s in C.solve(Fc, Uc, tol=1e-8)]
+    print(f"[3d] 16^3 cycles {cc}", flush=True)
+    assert max(cyc) <= 1.2 * max(cc)
+    C.close()
+    B.close()
+
+
+def test_oseen2d_full_size_learned_vs_fixed():
+    """2D generalized Oseen, k=2, 128^2, 6 grids, nu in {1, 0.1, 0.01},
+    |a|h/nu in {0, 0.25, 0.5, 1}: the twelve problems as one batch with the
+    fixed and with the learned damping.  Problems the fixed damping solves
+    are solved by the learned one in no more cycles (in total fewer), and the
+    answers meet the tolerance with the oracle's matrix."""
+    from paper_1705_09282_amd import learned
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    import os
+    if not os.path.exists(learned.WEIGHTS):
+        pytest.skip("no trained damping model")
+    probs = [workloads.oseen2d(nu, peh) for nu in workloads.OSEEN2D_NUS for peh in workloads.OSEEN2D_PEH]
+    B = BatchSolver(2, 128, 6, 2, [p["nu"] for p in probs], [p["sigma"] for p in probs], [p["c"] for p in probs],
+                    max_cycles=100).bind()
+    F = torch.tensor(B.manufactured_rhs(), device="cuda")
+    out = {}
+    for mode in ("fixed", "learned"):
+        if mode == "learned":
+            learned.apply(B)
+        U = torch.zeros_like(F)
+        st = B.solve(F, U, tol=1e-8, raise_on_error=False)
+        div = B.div_norm(U)
+        out[mode] = (st, U.clone(), div)
+        print(f"[oseen] {mode}: cycles {[s['cycles'] for s in st]} converged {[s['converged'] for s in st]} "
+              f"fallback {[s['fallback'] for s in st]}", flush=True)
+    sf, sl = out["fixed"][0], out["learned"][0]
+    ok = [i for i, s in enumerate(sf) if s["converged"]]
+    assert len(ok) >= 8
+    for i in ok:
+        assert sl[i]["converged"] and sl[i]["cycles"] <= sf[i]["cycles"], i
+        assert out["learned"][2][i] < 1e-10
+    assert sum(sl[i]["cycles"] for i in ok) < sum(sf[i]["cycles"] for i in ok)
+    # two answers against the oracle's assembly
+    n = B.n
+    for i in (ok[0], ok[-1]):
+        K, Fo = oracle_system(probs[i])
+        Ui = out["learned"][1][i * n:(i + 1) * n].cpu().numpy()
+        res = np.linalg.norm(Fo - K @ Ui) / np.linalg.norm(Fo)
+        print(f"[oseen] problem {i} oracle residual {res:.2e}", flush=True)
+        assert res < 1.05e-8
+    B.close()

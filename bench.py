@@ -7,6 +7,9 @@ pressure degree k=2 (velocity S^{3,2} x S^{2,3}), 256x256 elements, 6 grids
 manufactured solution u = curl(sin^2(pi x) sin^2(pi y)), p = sin(2 pi x)
 sin(2 pi y).  One step solves all four problems from U = 0 to relative
 residual 1e-8 with V(2,2) cycles; inputs are resident in HBM before timing.
+The timed path is the learned per-level damping with FP32 V-cycles inside FP64
+iterative refinement; the plain FP64 solver (fixed damping) and FP32
+refinement with the fixed damping are timed beside it on the same problems.
 
 Prints one JSON line: metric, value (DOF/s over the whole step, DOFs =
 dim V_h + dim Q_h), roofline of the dominant kernel (finest-grid residual
@@ -102,10 +105,15 @@ def main():
     sigmas = list(workloads.STOKES2D_SIGMAS)
     cfg = workloads.stokes2d(1.0, N=args.n_elem, L=args.levels)
 
-    def make_batch(precision):
+    from paper_1705_09282_amd import learned
+    model = learned.load()
+
+    def make_batch(precision, use_learned=False):
         b = BatchSolver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], [cfg["nu"]] * len(sigmas), sigmas,
                         precision=precision).bind(dev)
         tuning = b.autotune(reps=20)
+        if use_learned:
+            learned.apply(b, model)
         F = torch.tensor(b.manufactured_rhs(), device=dev)
         U = torch.zeros_like(F)
         return b, F, U, tuning
@@ -127,17 +135,22 @@ def main():
 
     t_setup = time.perf_counter()
     b64, F64, U64, tun64 = make_batch(0)
-    b32, F32, U32, tun32 = make_batch(1)
+    bfx, Ffx, Ufx, tunfx = make_batch(1)
+    b32, F32, U32, tun32 = make_batch(1, use_learned=True)
     setup_s = time.perf_counter() - t_setup
     z = b64.sizes()
     dofs = len(sigmas) * (z["n"] - 1)
-    print(f"[bench] setup of 2 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
+    print(f"[bench] setup of 3 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
           file=sys.stderr, flush=True)
 
     T64, stats64 = run(b64, F64, U64)
     print(f"[bench] plain FP64 batch: {args.steps} steps in {T64:.3f} s", file=sys.stderr, flush=True)
+    Tfx, statsfx = run(bfx, Ffx, Ufx)
+    print(f"[bench] FP32-refined batch, fixed damping: {args.steps} steps in {Tfx:.3f} s", file=sys.stderr,
+          flush=True)
     T, stats = run(b32, F32, U32)
-    print(f"[bench] FP32-refined batch: {args.steps} steps in {T:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] learned damping + FP32-refined batch: {args.steps} steps in {T:.3f} s", file=sys.stderr,
+          flush=True)
 
     n = z["n"]
     nv = z["n_vel"]
@@ -182,7 +195,10 @@ def main():
             "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
                         f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, V(2,2) additive Schwarz, "
                         f"tol {args.tol:g}, U0=0",
-            "path": "batched: FP32 V-cycles in FP64 iterative refinement (fixed damping), 4 problems per launch",
+            "path": "batched: learned per-level damping, FP32 V-cycles in FP64 iterative refinement, "
+                    "4 problems per launch",
+            "eta_per_sigma": [[round(x, 4) for x in row] for row in b32.get_eta().tolist()],
+            "fallback_per_sigma": [st["fallback"] for st in stats],
             "dofs_per_step": dofs,
             "cycles_per_sigma": cycles,
             "vcycles_per_s": args.steps * sum(cycles) / T,
@@ -191,6 +207,8 @@ def main():
             "plain_fp64": {"value": value64, "ms_per_step": 1e3 * T64 / args.steps,
                            "cycles_per_sigma": [st["cycles"] for st in stats64],
                            "vcycles_per_s": args.steps * sum(st["cycles"] for st in stats64) / T64},
+            "fp32_fixed_damping": {"value": args.steps * dofs / Tfx, "ms_per_step": 1e3 * Tfx / args.steps,
+                                   "cycles_per_sigma": [st["cycles"] for st in statsfx]},
             "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
             "tuning": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
@@ -210,7 +228,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.tol)
-    for s in (b64, b32, s1):
+    for s in (b64, bfx, b32, s1):
         s.close()
     print(json.dumps(line), flush=True)
 

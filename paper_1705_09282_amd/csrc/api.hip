@@ -244,6 +244,7 @@ SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double 
     for (int R = 0; R < 4; ++R)
         for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
     a.n = (int)h.n;
+    a.win = h.win ? 1 : 0;
     a.nblocks = spmv_blocks(h.n, c->lpr[l]);
     a.F = F;
     a.U = U;

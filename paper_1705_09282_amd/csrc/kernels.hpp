@@ -34,6 +34,7 @@ struct SpmvArgsT {
     int64_t off[5];
     int nb[4][3];
     int n;
+    int win;            // boxes stored as in-grid windows (see HostLevel)
     int nblocks;        // logical blocks covering n rows (spmv_blocks)
     const T *F;
     const T *U;

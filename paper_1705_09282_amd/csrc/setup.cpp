@@ -322,9 +322,21 @@ static void level_geometry(const Problem &pb, int N, HostLevel &L) {
     L.n_q = L.n - L.n_v;
 }
 
+// first stored column index of a row's box in one direction (see HostLevel)
+static int box_start(bool win, int i, int lo, int W, int n) {
+    return win ? std::min(std::max(i + lo, 0), n - W) : i + lo;
+}
+
 static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
     const int d = pb.d;
     BlockGeom G{d, pb.k};
+    // window layout when every box fits inside the grid in every direction
+    L.win = true;
+    for (int R = 0; R <= d; ++R)
+        for (int C = 0; C <= d; ++C)
+            if (G.coupled(R, C))
+                for (int j = 0; j < d; ++j)
+                    if (L.nb[C][j] < G.width(R, C, j)) L.win = false;
     int64_t tot = 0;
     for (int R = 0; R <= d; ++R) {
         int ns = 0;
@@ -334,6 +346,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                 for (int j = 0; j < d; ++j) w *= G.width(R, C, j);
                 ns += w;
             }
+        ns = (ns + kEllVec - 1) / kEllVec * kEllVec;
         L.nslots[R] = ns;
         L.val_off[R] = tot;
         tot += (L.off[R + 1] - L.off[R] + 63) / 64 * 64 * ns;  // slices of 64 rows
@@ -352,11 +365,12 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                 lo[j] = G.lo(R, C, j);
             }
             for (int64_t li = 0; li < rows; ++li) {
-                int is[3];
+                int is[3], base[3] = {0, 0, 0};
                 int64_t t = li;
                 for (int j = 0; j < 3; ++j) {
                     is[j] = (int)(t % L.nb[R][j]);
                     t /= L.nb[R][j];
+                    if (j < d) base[j] = box_start(L.win, is[j], lo[j], W[j], L.nb[C][j]);
                 }
                 int slot = slot0;
                 for (int o2 = 0; o2 < W[2]; ++o2)
@@ -366,7 +380,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                             bool ok = true;
                             int itrue[3], jtrue[3];
                             for (int j = 0; j < d; ++j) {
-                                const int js = is[j] + lo[j] + o[j];
+                                const int js = base[j] + o[j];
                                 if (js < 0 || js >= L.nb[C][j]) ok = false;
                                 itrue[j] = is[j] + G.s(R, j);
                                 jtrue[j] = js + G.s(C, j);
@@ -378,7 +392,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                                 for (int j = 0; j < d; ++j) p *= tm.f[j].get(itrue[j], jtrue[j]);
                                 v += p;
                             }
-                            L.val[L.val_off[R] + ((li >> 6) * L.nslots[R] + slot) * 64 + (li & 63)] = v;
+                            L.val[L.ell_index(R, li, slot)] = v;
                         }
             }
             int w = 1;
@@ -415,13 +429,12 @@ static double entry(const Problem &pb, const HostLevel &L, int64_t grow, int64_t
         b /= L.nb[C][j];
         if (j < d) {
             W[j] = G.width(R, C, j);
-            o[j] = js - is - G.lo(R, C, j);
+            o[j] = js - box_start(L.win, is, G.lo(R, C, j), W[j], L.nb[C][j]);
             if (o[j] < 0 || o[j] >= W[j]) return 0.0;
         }
     }
     slot += (o[2] * W[1] + o[1]) * W[0] + o[0];
-    const int64_t li = grow - L.off[R];
-    return L.val[L.val_off[R] + ((li >> 6) * L.nslots[R] + slot) * 64 + (li & 63)];
+    return L.val[L.ell_index(R, grow - L.off[R], slot)];
 }
 
 double level_entry(const Hierarchy &H, int level, int64_t grow, int64_t gcol) {

@@ -20,6 +20,8 @@
 #include <string>
 #include <vector>
 
+#include "layout.hpp"
+
 namespace dfmg {
 
 struct Mat1 {
@@ -65,11 +67,22 @@ struct HostLevel {
     int nb[4][3] = {};         // stored count per block per direction
     int64_t off[5] = {};       // block offsets, off[nblk] = n
     int64_t n = 0, n_v = 0, n_q = 0;
-    // stencil ELL: value (row, slot) of row block R at
-    // val[val_off[R] + ((row / 64) * nslots[R] + slot) * 64 + row % 64]
+    // stencil ELL: value (row, slot) of row block R at ell_index(R, row, slot):
+    // slices of 64 rows, inside a slice chunks of kEllVec consecutive slots,
+    // chunk-major, then row, then slot (one vector load per lane per chunk).
+    // nslots[R] is the slot count rounded up to kEllVec (padding holds 0).
+    // win: in every direction the stored box of a row is the window of W
+    // consecutive column indices starting at clamp(i + lo, 0, n - W) (always
+    // inside the grid, so the columns of a row need no clamping); otherwise
+    // (a grid narrower than a box) slot o is column i + lo + o, 0 outside.
     std::vector<double> val;
     int64_t val_off[5] = {};
     int nslots[4] = {};
+    bool win = false;
+    int64_t ell_index(int R, int64_t row, int slot) const {
+        return val_off[R] + (((row >> 6) * (nslots[R] / kEllVec) + slot / kEllVec) * 64 + (row & 63)) * kEllVec +
+               slot % kEllVec;
+    }
     std::vector<double> w;     // pressure basis integrals
     // subdomains (levels >= 1)
     int64_t n_patch = 0;

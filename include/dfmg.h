@@ -75,7 +75,8 @@ typedef struct {
     double eta;           /* fixed additive-Schwarz damping; <= 0: default      */
     int precision;        /* 0: FP64 V-cycles; 1 (dim 2): solve by FP64 iterative
                              refinement around FP32 V-cycles (see dfmg_solve)    */
-    int smoother;         /* 0 auto, 1 two-pass gather, 2 coloured scatter, 3 one-pass */
+    int smoother;         /* 0 auto, 1 two-pass gather, 2 coloured scatter, 3 one-pass,
+                             4 two-pass with one thread per small subdomain */
     int max_cycles;       /* solve: cycle limit (ENOTCONV beyond)               */
     int use_graph;        /* 1: replay the V-cycle as a captured hipGraph       */
     int cycles_per_check; /* solve: V-cycles launched between host checks       */
@@ -195,8 +196,10 @@ int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const doub
  * smoother[l]: 1 = subdomain-parallel local solves + per-DOF gather of the
  *              corrections, 2 = one launch per DOF-disjoint colour with plain
  *              read-modify-write scatter (no atomics), 3 = one pass in which
- *              every DOF recomputes the local-solve rows it receives (equal
- *              to 1 bit for bit); ignored on level 0.
+ *              every DOF recomputes the local-solve rows it receives, 4 =
+ *              as 1 with one thread per subdomain of at most 8 DOFs (the
+ *              interior ones); 3 and 4 equal 1 bit for bit; ignored on
+ *              level 0.
  * Arrays have n_levels entries.  The variants differ only in summation
  * order (lpr splits a row's dot product over lanes). */
 int dfmg_get_tuning(const dfmg_ctx *ctx, int *lpr, int *smoother);

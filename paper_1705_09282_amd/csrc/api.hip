@@ -58,6 +58,7 @@ struct DevLevel {
     LevelData<float> f;
     // shared by the batch
     int32_t *pptr = nullptr, *pdofs = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr, *col_list = nullptr;
+    int32_t *small = nullptr, *bigent = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
     // per problem
     int32_t *moff = nullptr;
@@ -101,7 +102,9 @@ struct dfmg_ctx {
     double *partial = nullptr;   // [problem][block]
     int nparts = 0;
     double *hist = nullptr;      // [problem][DFMG_MAX_HISTORY]
-    int *counter = nullptr, *stop = nullptr;
+    int *counter = nullptr, *stop = nullptr;   // adjacent: stop = counter + np
+    int *hflags = nullptr;       // pinned host copies of counter and stop, two buffers
+    hipEvent_t ev_flag[2] = {nullptr, nullptr};
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
     double *psi = nullptr;       // refinement: streamfunction increments [problem][(N+k-1)^2]
@@ -113,7 +116,7 @@ struct dfmg_ctx {
     int64_t spsi = 0;
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
-    std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass
+    std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass, 4 small-subdomain gather
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
     std::vector<double> eta_host;  // [problem][level]
     const Hierarchy &S() const { return P[0]; }
@@ -186,6 +189,8 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.inv_ptr = A.take<int32_t>(h.inv_ptr.size());
         v.inv_pos = A.take<int32_t>(h.inv_pos.size());
         v.col_list = A.take<int32_t>(h.col_list.size());
+        v.small = A.take<int32_t>(h.small_list.size());
+        v.bigent = A.take<int32_t>(h.big_ent.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
         v.P_ci = A.take<int32_t>(h.P_ci.size());
         v.R_rp = A.take<int32_t>(h.R_rp.size());
@@ -197,8 +202,8 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->eta = A.take<double>((size_t)L * np);
     c->partial = A.take<double>((size_t)c->nparts * np);
     c->hist = A.take<double>((size_t)DFMG_MAX_HISTORY * np);
-    c->counter = A.take<int>(np);
-    c->stop = A.take<int>(np);
+    c->counter = A.take<int>(2 * (size_t)np);
+    c->stop = c->counter ? c->counter + np : nullptr;
     c->thresh2 = A.take<double>(np);
     c->scal = A.take<double>(np);
     c->dvec = A.take<double>(H.lv[L - 1].n_q);
@@ -292,12 +297,18 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.assign = assign ? 1 : 0;
     a.stop = stop;
     a.nprob = c->np;
+    a.small = v.small;
+    a.bigent = v.bigent;
+    a.nsmall = (int)h.small_list.size();
+    a.nbig = (int)h.big_ent.size();
     if (c->smoother[l] == 2) {
         if (assign) launch_fill<T>(h.n, U, h.n, T(0), stop, c->np, c->s);
         for (size_t col = 0; col + 1 < h.col_ptr.size(); ++col)
             launch_schwarz_colour<T>(a, v.col_list + h.col_ptr[col], h.col_ptr[col + 1] - h.col_ptr[col], c->s);
     } else if (c->smoother[l] == 3) {
         launch_schwarz_fused<T>(a, c->s);
+    } else if (c->smoother[l] == 4) {
+        launch_schwarz_small<T>(a, c->s);
     } else {
         launch_schwarz_gather<T>(a, c->s);
     }
@@ -507,7 +518,7 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
     if (o.precision == 1 && dim != 2) throw ArgError("FP32 refinement is implemented for dim 2");
     if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
-    if (o.smoother < 0 || o.smoother > 3) throw ArgError("smoother must be 0, 1, 2 or 3");
+    if (o.smoother < 0 || o.smoother > 4) throw ArgError("smoother must be 0 .. 4");
     if (o.eta >= 1.0) throw ArgError("eta must be < 1");
     return o;
 }
@@ -550,9 +561,50 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
     launch_reduce(nb, c->partial, c->nparts, c->thresh2, tol * tol, np, c->s);
 }
 
-void flags_to_host(dfmg_ctx *c, int *counter, int *stop, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(counter, c->counter, c->np * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(stop, c->stop, c->np * sizeof(int), hipMemcpyDeviceToHost, s));
+// queue a copy of the counters and stop flags into pinned buffer buf
+void flags_async(dfmg_ctx *c, int buf) {
+    HIPCHK(hipMemcpyAsync(c->hflags + buf * 2 * c->np, c->counter, 2 * c->np * sizeof(int), hipMemcpyDeviceToHost,
+                          c->s));
+    HIPCHK(hipEventRecord(c->ev_flag[buf], c->s));
+}
+
+// wait for buffer buf; true when every problem has stopped
+bool flags_wait(dfmg_ctx *c, int buf) {
+    HIPCHK(hipEventSynchronize(c->ev_flag[buf]));
+    const int *st = c->hflags + buf * 2 * c->np + c->np;
+    for (int p = 0; p < c->np; ++p)
+        if (!st[p]) return false;
+    return true;
+}
+
+// Run V-cycles in units of `chunk` until every problem has stopped or max
+// cycles were launched, keeping one unit in flight while the host reads the
+// flags of the previous one (a unit launched after the last problem stopped
+// does no work: every kernel returns at once for stopped problems).
+// launch_unit(k, buf) launches k cycles and queues the flags into buf;
+// wait(buf) returns whether all problems have stopped.  Returns the buffer
+// holding the last flags read and whether all stopped.
+template <class Launch, class Wait>
+std::pair<int, bool> pipelined_cycles(int maxc, int chunk, Launch &&launch_unit, Wait &&wait) {
+    int launched = 0, inflight = 0, next = 0, head = 0, last = 0;
+    bool all = false;
+    auto issue = [&] {
+        const int k = std::min(chunk, maxc - launched);
+        launch_unit(k, next);
+        launched += k;
+        next ^= 1;
+        ++inflight;
+    };
+    issue();
+    while (inflight > 0) {
+        if (launched < maxc && inflight < 2) issue();
+        all = wait(head);
+        last = head;
+        head ^= 1;
+        --inflight;
+        if (all) break;
+    }
+    return {last, all};
 }
 
 // cycle limit reached: measure the residual of the last iterates (problems
@@ -744,6 +796,9 @@ void dfmg_destroy(dfmg_ctx *c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    for (hipEvent_t e : c->ev_flag)
+        if (e) (void)hipEventDestroy(e);
+    if (c->hflags) (void)hipHostFree(c->hflags);
     if (c->s) (void)hipStreamDestroy(c->s);
     delete c;
 }
@@ -806,6 +861,8 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.inv_ptr, h.inv_ptr, s);
             up(v.inv_pos, h.inv_pos, s);
             up(v.col_list, h.col_list, s);
+            up(v.small, h.small_list, s);
+            up(v.bigent, h.big_ent, s);
             up(v.d.P_v, h.P_v, s);
             up(v.d.R_v, h.R_v, s);
             up(v.P_rp, h.P_rp, s);
@@ -832,8 +889,10 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
-        HIPCHK(hipMemsetAsync(c->stop, 0, np * sizeof(int), s));
-        HIPCHK(hipMemsetAsync(c->counter, 0, np * sizeof(int), s));
+        HIPCHK(hipMemsetAsync(c->counter, 0, 2 * np * sizeof(int), s));
+        HIPCHK(hipHostMalloc((void **)&c->hflags, 4 * np * sizeof(int), hipHostMallocDefault));
+        std::memset(c->hflags, 0, 4 * np * sizeof(int));
+        for (auto &e : c->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIPCHK(hipStreamSynchronize(s));
         c->bound = true;
     });
@@ -928,33 +987,27 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         enter(c);
         const auto t0 = std::chrono::steady_clock::now();
         solve_begin(c, F, U, nullptr, tol);
-        const int maxc = c->opt.max_cycles, np = c->np;
-        std::vector<int> stopv(np, 0), counter(np, 0);
-        auto read_flags = [&] {
-            flags_to_host(c, counter.data(), stopv.data(), c->s);
-            HIPCHK(hipStreamSynchronize(c->s));
-            for (int x : stopv)
-                if (!x) return false;
-            return true;
-        };
-        int launched = 0;
-        bool all = false;
-        while (launched < maxc) {
-            const int chunk = std::min(c->opt.cycles_per_check, maxc - launched);
-            for (int i = 0; i < chunk; ++i) run_cycle(c, solve_kind(c));
-            launched += chunk;
-            if ((all = read_flags())) break;
-        }
+        const int np = c->np, kind = solve_kind(c);
+        auto [buf, all] = pipelined_cycles(
+            c->opt.max_cycles, c->opt.cycles_per_check,
+            [&](int k, int b) {
+                for (int i = 0; i < k; ++i) run_cycle(c, kind);
+                flags_async(c, b);
+            },
+            [&](int b) { return flags_wait(c, b); });
         if (!all) {
             solve_limit(c);
-            read_flags();
+            buf = 0;
+            flags_async(c, buf);
+            flags_wait(c, buf);
         }
+        const int *counter = c->hflags + buf * 2 * np, *stopv = counter + np;
         SolveOut so;
         solve_end_launch(c, U, nullptr, so);
         HIPCHK(hipStreamSynchronize(c->s));
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         local.assign(np, dfmg_stats{});
-        status = solve_stats(c, so, counter.data(), stopv.data(), tol, secs, local.data());
+        status = solve_stats(c, so, counter, stopv, tol, secs, local.data());
         leave(c);
     });
     if (st)
@@ -1050,8 +1103,8 @@ int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
 int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
     for (int l = 0; l < c->L(); ++l)
-        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] >= 1 && smoother[l] <= 3))
-            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1, 2 or 3");
+        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] >= 1 && smoother[l] <= 4))
+            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1 .. 4");
     return guarded([&] {
         for (int l = 0; l < c->L(); ++l) {
             c->lpr[l] = lpr[l];
@@ -1102,7 +1155,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 }
                 double bests = 1e30;
                 int bs = c->smoother[l];
-                for (int sm : {1, 2, 3}) {
+                for (int sm : {1, 2, 3, 4}) {
                     c->smoother[l] = sm;
                     const double t = timed([&] { schwarz<T>(c, l, v.r, v.U, false, nullptr); });
                     if (t < bests) {
@@ -1314,7 +1367,8 @@ struct dfmg_multi {
     size_t ws_tab = 0, ws_flags = 0, ws_total = 0;
     int64_t *tab = nullptr;                // device: caller offsets in group order
     int *dflags = nullptr;                 // device: counters then stop flags, group order
-    int *hflags = nullptr;                 // pinned host copy of dflags
+    int *hflags = nullptr;                 // pinned host copies of dflags, two buffers
+    hipEvent_t ev_flag[2] = {nullptr, nullptr};
     dfmg_options opt{};
     int nprob = 0;
     bool bound = false;
@@ -1392,12 +1446,17 @@ void multi_drop_graph(dfmg_multi *m) {
     }
 }
 
-// read the packed flags; true when every problem has stopped
-bool multi_flags(dfmg_multi *m) {
-    HIPCHK(hipMemcpyAsync(m->hflags, m->dflags, 2 * m->nprob * sizeof(int), hipMemcpyDeviceToHost, m->s));
-    HIPCHK(hipStreamSynchronize(m->s));
+// queue a copy of the packed flags into pinned buffer buf / wait for it
+void multi_flags_async(dfmg_multi *m, int buf) {
+    HIPCHK(hipMemcpyAsync(m->hflags + buf * 2 * m->nprob, m->dflags, 2 * m->nprob * sizeof(int),
+                          hipMemcpyDeviceToHost, m->s));
+    HIPCHK(hipEventRecord(m->ev_flag[buf], m->s));
+}
+bool multi_flags_wait(dfmg_multi *m, int buf) {
+    HIPCHK(hipEventSynchronize(m->ev_flag[buf]));
+    const int *st = m->hflags + buf * 2 * m->nprob + m->nprob;
     for (int i = 0; i < m->nprob; ++i)
-        if (!m->hflags[m->nprob + i]) return false;
+        if (!st[i]) return false;
     return true;
 }
 
@@ -1486,6 +1545,8 @@ void dfmg_multi_destroy(dfmg_multi *m) {
     if (m->ev_out) (void)hipEventDestroy(m->ev_out);
     if (m->s) (void)hipStreamDestroy(m->s);
     if (m->hflags) (void)hipHostFree(m->hflags);
+    for (hipEvent_t e : m->ev_flag)
+        if (e) (void)hipEventDestroy(e);
     delete m;
 }
 
@@ -1526,7 +1587,9 @@ int dfmg_multi_bind(dfmg_multi *m, void *ws, size_t bytes, void *stream) {
         HIPCHK(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
         m->ev_join.assign(m->g.size(), nullptr);
         for (auto &e : m->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        HIPCHK(hipHostMalloc((void **)&m->hflags, 2 * m->nprob * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&m->hflags, 4 * m->nprob * sizeof(int), hipHostMallocDefault));
+        std::memset(m->hflags, 0, 4 * m->nprob * sizeof(int));
+        for (auto &e : m->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::vector<int64_t> tab;
         for (const auto &mem : m->member)
             for (int p : mem) tab.push_back(m->off[p]);
@@ -1585,22 +1648,23 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
         for (size_t i = 0; i < G; ++i) solve_begin(m->g[i], F, U, m->tab + m->base[i], tol);
         mjoin(m);
         const int kind = solve_kind(m->g[0]);
-        const int maxc = m->opt.max_cycles;
-        int launched = 0;
-        bool all = false;
-        while (launched < maxc) {
-            const int chunk = std::min(m->opt.cycles_per_check, maxc - launched);
-            for (int i = 0; i < chunk; ++i) multi_step(m, kind);
-            launched += chunk;
-            if ((all = multi_flags(m))) break;
-        }
+        auto [buf, all] = pipelined_cycles(
+            m->opt.max_cycles, m->opt.cycles_per_check,
+            [&](int k, int b) {
+                for (int i = 0; i < k; ++i) multi_step(m, kind);
+                multi_flags_async(m, b);
+            },
+            [&](int b) { return multi_flags_wait(m, b); });
         if (!all) {
             mfork(m);
             for (dfmg_ctx *c : m->g) solve_limit(c);
             mjoin(m);
             pack_flags(m);
-            multi_flags(m);
+            buf = 0;
+            multi_flags_async(m, buf);
+            multi_flags_wait(m, buf);
         }
+        const int *fl = m->hflags + buf * 2 * m->nprob;
         std::vector<SolveOut> so(G);
         mfork(m);
         for (size_t i = 0; i < G; ++i) solve_end_launch(m->g[i], U, m->tab + m->base[i], so[i]);
@@ -1612,8 +1676,8 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
         int worst = DFMG_OK;
         for (size_t i = 0; i < G; ++i) {
             gs.assign(m->g[i]->np, dfmg_stats{});
-            const int w = solve_stats(m->g[i], so[i], m->hflags + m->base[i], m->hflags + m->nprob + m->base[i], tol,
-                                      secs, gs.data());
+            const int w = solve_stats(m->g[i], so[i], fl + m->base[i], fl + m->nprob + m->base[i], tol, secs,
+                                      gs.data());
             if (w == DFMG_EDIVERGED || (w == DFMG_ENOTCONV && worst == DFMG_OK)) worst = w;
             for (size_t j = 0; j < gs.size(); ++j) local[m->member[i][j]] = gs[j];
         }

@@ -9,7 +9,7 @@ namespace dfmg {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     const int prob = blockIdx.y;
-    const int halt = a.stop ? a.stop[prob] : 0;
+    if (a.stop && a.stop[prob]) return;  // block-uniform: the problem has stopped
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int t = b * kBlock + threadIdx.x;
     if (t >= a.nent) return;
@@ -37,7 +37,73 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
     }
-    if (!halt) a.delta[(int64_t)prob * a.nent + t] = acc;
+    a.delta[(int64_t)prob * a.nent + t] = acc;
+}
+
+// Additive Schwarz, step 1 with one thread per small subdomain (at most
+// kSmallPatch DOFs, the interior ones): the thread gathers its subdomain's
+// residual entries once and computes every row of M_p E_p r.  Blocks past
+// nb_small take one entry each of the larger (boundary) subdomains as
+// k_patch_solve does.  Rows are summed in the same order as k_patch_solve,
+// so the corrections agree bit for bit.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, int nb_small) {
+    const int prob = blockIdx.y;
+    if (a.stop && a.stop[prob]) return;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const T *r = a.r + prob * a.svec;
+    T *delta = a.delta + (int64_t)prob * a.nent;
+    if (b < nb_small) {
+        const int q = b * kBlock + threadIdx.x;
+        if (q >= a.nsmall) return;
+        const int p = a.small[q];
+        const int base = a.pptr[p], nn = a.pptr[p + 1] - base;
+        const T *m = a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p];
+        T rv[kSmallPatch];
+#pragma unroll
+        for (int c = 0; c < kSmallPatch; ++c) rv[c] = c < nn ? r[a.pdofs[base + c]] : T(0);
+        if (nn == kSmallPatch) {
+#pragma unroll
+            for (int row = 0; row < kSmallPatch; ++row) {
+                T acc = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
+                delta[base + row] = acc;
+            }
+        } else {
+            for (int row = 0; row < nn; ++row) {
+                T acc = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c)
+                    if (c < nn) acc = fma(m[row * nn + c], rv[c], acc);
+                delta[base + row] = acc;
+            }
+        }
+        return;
+    }
+    const int t = (b - nb_small) * kBlock + threadIdx.x;
+    if (t >= a.nbig) return;
+    const int e = a.bigent[t];
+    const int4 info = a.ent_info[(int64_t)prob * a.nent + e];
+    const T *m = a.M + prob * a.sM + info.x;
+    const int32_t *dofs = a.pdofs + info.y;
+    const int nn = info.z;
+    T acc = 0;
+    for (int c = 0; c < nn; c += 8) {
+        int d[8];
+        T mv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool ok = c + u < nn;
+            d[u] = dofs[ok ? c + u : c];
+            mv[u] = ok ? m[c + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rv[u] = r[d[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
+    }
+    delta[e] = acc;
 }
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
@@ -45,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
     const int prob = blockIdx.y;
-    const int halt = a.stop ? a.stop[prob] : 0;
+    if (a.stop && a.stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     if (j >= a.n) return;
@@ -65,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : T(0);
     }
-    if (!halt) U[j] = fma(eta, acc, u);
+    U[j] = fma(eta, acc, u);
 }
 
 template <class T>
@@ -82,7 +148,7 @@ void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
     const int prob = blockIdx.y;
-    const int halt = a.stop ? a.stop[prob] : 0;
+    if (a.stop && a.stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     if (j >= a.n) return;
@@ -116,7 +182,14 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
         }
         acc += row;
     }
-    if (!halt) U[j] = fma(eta, acc, u);
+    U[j] = fma(eta, acc, u);
+}
+
+template <class T>
+void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s) {
+    const int nbs = blocks_for(a.nsmall), nbb = blocks_for(a.nbig);
+    hipLaunchKernelGGL(k_patch_solve_small<T>, dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), 0, s, a, nbs);
+    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 template <class T>
@@ -161,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, co
                                                 const T *x, int64_t sx, T *y, int64_t sy, int add,
                                                 const int *stop) {
     const int prob = blockIdx.y;
-    const int halt = stop ? stop[prob] : 0;
+    if (stop && stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
@@ -184,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, co
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = fma(w[u], xv[u], acc);
     }
-    if (!halt) y[i] = y0 + acc;
+    y[i] = y0 + acc;
 }
 
 template <class T>
@@ -315,6 +388,8 @@ void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
 template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);
 template void launch_schwarz_gather<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_fused<double>(const PatchArgsT<double> &, hipStream_t);
+template void launch_schwarz_small<double>(const PatchArgsT<double> &, hipStream_t);
+template void launch_schwarz_small<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_fused<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);

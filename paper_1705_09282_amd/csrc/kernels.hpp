@@ -21,6 +21,8 @@
 
 #include <cstdint>
 
+#include "layout.hpp"
+
 namespace dfmg {
 
 constexpr int kBlock = 256;
@@ -63,6 +65,9 @@ struct PatchArgsT {
     int assign;         // 1: U = eta * S r (U known to be zero)
     const int *stop;
     int nprob;
+    const int32_t *small;   // subdomains with <= kSmallPatch DOFs (shared)
+    const int32_t *bigent;  // entries of the other subdomains (shared)
+    int nsmall, nbig;
 };
 using PatchArgs = PatchArgsT<double>;
 
@@ -73,6 +78,9 @@ template <class T>
 void launch_spmv(int d, int k, int lpr, const SpmvArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s);
+// two passes, small subdomains solved by one thread each
+template <class T>
+void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s);
 // one pass: every DOF recomputes the local-solve rows it receives (no buffer)
 template <class T>
 void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s);

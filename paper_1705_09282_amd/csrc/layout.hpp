@@ -8,4 +8,8 @@ namespace dfmg {
 // lane reads a chunk with one vector load.
 constexpr int kEllVec = 4;
 
+// Subdomains with at most this many DOFs (the interior ones) are solved by
+// one thread each in smoother variant 4; the others one entry per thread.
+constexpr int kSmallPatch = 8;
+
 }  // namespace dfmg

@@ -641,6 +641,13 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     std::vector<int32_t> fillp(L.inv_ptr.begin(), L.inv_ptr.end() - 1);
     for (int64_t i = 0; i < L.n_patch; ++i)
         for (int32_t t = L.pptr[i]; t < L.pptr[i + 1]; ++t) L.inv_pos[fillp[L.pdofs[t]]++] = t;
+    L.small_list.clear();
+    L.big_ent.clear();
+    for (int64_t i = 0; i < L.n_patch; ++i) {
+        if (L.pptr[i + 1] - L.pptr[i] <= kSmallPatch) L.small_list.push_back((int32_t)i);
+        else
+            for (int32_t t = L.pptr[i]; t < L.pptr[i + 1]; ++t) L.big_ent.push_back(t);
+    }
     // colour lists
     int ncol = 0;
     for (int c : L.color) ncol = std::max(ncol, c + 1);

@@ -90,6 +90,8 @@ struct HostLevel {
     std::vector<double> M;     // local inverses, row-major n_i x n_i at moff
     int64_t n_class = 0;       // distinct stored inverses
     std::vector<int32_t> col_ptr, col_list;
+    // subdomains with <= kSmallPatch DOFs, and the entries of the others
+    std::vector<int32_t> small_list, big_ent;
     int max_patch = 0;
     // prolongation from level-1 (CSR, rows = this level) and restriction
     std::vector<int32_t> P_rp, P_ci, R_rp, R_ci;

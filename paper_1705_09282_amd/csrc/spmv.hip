@@ -110,9 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     a.U += prob * a.svec;
     a.r += prob * a.svec;
     if (a.partial) a.partial += prob * a.spart;
-    // the stop flag is read alongside the operands and only gates the stores,
-    // so its load latency overlaps with theirs
-    const int halt = a.stop ? a.stop[prob] : 0;
+    if (a.stop && a.stop[prob]) return;  // block-uniform: the problem has stopped
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int lane = (LPR > 1) ? (threadIdx.x % LPR) : 0;
     const int g = b * (kBlock / LPR) + threadIdx.x / LPR;
@@ -136,13 +134,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (active && lane == 0) {
         const T v = a.F[g] - acc;
-        if (!halt) a.r[g] = v;
+        a.r[g] = v;
         rr = (double)v * (double)v;
     }
     if (a.partial) {
         __shared__ double sh[kBlock / 64];
         const double s = block_sum(rr, sh);
-        if (threadIdx.x == 0 && b < a.nblocks && !halt) a.partial[b] = s;
+        if (threadIdx.x == 0 && b < a.nblocks) a.partial[b] = s;
     }
 }
 

@@ -90,7 +90,8 @@ def test_level_kernels(d, N, k, L, c):
 
 
 @pytest.mark.parametrize("d,N,k,L,c", CASES)
-@pytest.mark.parametrize("opt", [{}, {"use_graph": 0}, {"smoother": 2}, {"smoother": 3}, {"nu1": 1, "nu2": 3},
+@pytest.mark.parametrize("opt", [{}, {"use_graph": 0}, {"smoother": 2}, {"smoother": 3}, {"smoother": 4},
+                                 {"nu1": 1, "nu2": 3},
                                  {"nu1": 0, "nu2": 2}, {"share_inverses": 0}])
 def test_vcycles_match_oracle(d, N, k, L, c, opt):
     s, h, F = make(d, N, k, L, nu=0.5, sigma=4.0, c=c, **opt)
@@ -109,7 +110,7 @@ def test_vcycles_match_oracle(d, N, k, L, c, opt):
 
 
 @pytest.mark.parametrize("d,N,k,L", [(2, 32, 2, 4), (3, 8, 1, 3), (2, 16, 1, 3)])
-@pytest.mark.parametrize("lpr,sm", [(1, 1), (2, 2), (4, 1), (2, 1), (4, 2), (1, 3), (4, 3)])
+@pytest.mark.parametrize("lpr,sm", [(1, 1), (2, 2), (4, 1), (2, 1), (4, 2), (1, 3), (4, 3), (1, 4), (2, 4)])
 def test_kernel_variants_match_oracle(d, N, k, L, lpr, sm):
     """Every (lanes per row, smoother form) variant gives the oracle's cycles."""
     s, h, F = make(d, N, k, L, nu=0.5, sigma=4.0)
@@ -128,12 +129,13 @@ def test_kernel_variants_match_oracle(d, N, k, L, lpr, sm):
 
 @pytest.mark.parametrize("d,N,k,L,precision", [(2, 32, 2, 4, 0), (3, 8, 1, 3, 0), (2, 32, 1, 4, 1),
                                                (2, 32, 2, 4, 1)])
-def test_one_pass_smoother_equals_two_pass(d, N, k, L, precision):
-    """The one-pass smoother sums every local-solve row and the rows of a DOF
-    in the two-pass order, so whole solves agree bit for bit."""
+def test_smoother_forms_agree_bitwise(d, N, k, L, precision):
+    """The one-pass smoother and the small-subdomain form sum every
+    local-solve row and the rows of a DOF in the two-pass order, so whole
+    solves agree bit for bit."""
     from paper_1705_09282_amd.dfmg import Solver
     out = []
-    for sm in (1, 3):
+    for sm in (1, 3, 4):
         s = Solver(d, N, L, k, nu=0.5, sigma=4.0, c=0.0, precision=precision).bind()
         s.set_tuning([1] * L, [sm] * L)
         F = dev(s.manufactured_rhs())
@@ -141,7 +143,8 @@ def test_one_pass_smoother_equals_two_pass(d, N, k, L, precision):
         st = s.solve(F, U, tol=1e-8)
         out.append((host(U), st["history"]))
         s.close()
-    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
 
 
 def test_autotune_keeps_results_and_picks_fastest(tmp_path):

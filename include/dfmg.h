@@ -184,11 +184,15 @@ int dfmg_level_restrict(dfmg_ctx *ctx, int level, const double *r_dev, double *G
 int dfmg_level_prolong_add(dfmg_ctx *ctx, int level, const double *dU_dev, double *U_dev);
 int dfmg_coarse_solve(dfmg_ctx *ctx, const double *G_dev, double *dU_dev);
 
-/* Average duration in milliseconds of the residual kernel r = F - K_level U
- * over `reps` back-to-back launches on the library's stream, timed with HIP
- * events recorded on that stream (device inputs; synchronizes). */
-int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const double *U_dev, double *r_dev,
-                       int reps, double *ms_out);
+/* Average duration in milliseconds of one launch of a V-cycle kernel over
+ * `reps` back-to-back launches on the library's stream, timed with HIP events
+ * recorded on that stream, on the context's own level vectors (whatever the
+ * last cycle left there) for every problem of the batch, in the launch
+ * configuration the cycles use.  kernel: 0 = FP64 residual r = F - K_level U,
+ * 1 = FP32 residual (precision 1 only), 2 = FP64 smoothing step, 3 = FP32
+ * smoothing step (levels >= 1).  Synchronizes; leaves the level vectors
+ * changed (a solve reloads them).  Errors: EINVAL. */
+int dfmg_time_kernel(dfmg_ctx *ctx, int kernel, int level, int reps, double *ms_out);
 
 /* ---- Kernel variants per level (the autotuner's search space) ----
  * lpr[l]:      lanes of a wavefront per matrix row in the residual kernel of
@@ -199,7 +203,10 @@ int dfmg_time_residual(dfmg_ctx *ctx, int level, const double *F_dev, const doub
  *              every DOF recomputes the local-solve rows it receives, 4 =
  *              as 1 with one thread per subdomain of at most 8 DOFs (the
  *              interior ones); 3 and 4 equal 1 bit for bit; ignored on
- *              level 0.
+ *              level 0.  smoother[l] = 5 on levels 1 .. t (t <= n_levels - 2)
+ *              runs levels t .. 0 of every V-cycle in one launch with one
+ *              workgroup per problem (same sums as 1 with lpr 1); off by
+ *              default.
  * Arrays have n_levels entries.  The variants differ only in summation
  * order (lpr splits a row's dot product over lanes). */
 int dfmg_get_tuning(const dfmg_ctx *ctx, int *lpr, int *smoother);
@@ -207,7 +214,9 @@ int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
 /* Time every variant of every level on the device (reps launches each, HIP
  * events on the library stream) and keep the fastest; ms_out (nullable,
  * 2 * n_levels entries) receives the best residual and smoother times.
- * Requires dfmg_bind.  Leaves the solver state unchanged. */
+ * Then times whole V-cycles for every choice of t (levels of at most 16384
+ * DOFs) and keeps the fastest.  Requires dfmg_bind.  Leaves the solver
+ * state unchanged. */
 int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
 
 /* ---- Learned per-level damping ----

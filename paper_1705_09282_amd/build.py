@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdfmg.so")
-SOURCES = ["setup.cpp", "spmv.hip", "kernels.hip", "mlp.hip", "api.hip"]
+SOURCES = ["setup.cpp", "spmv.hip", "kernels.hip", "mlp.hip", "vsmall.hip", "api.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = [

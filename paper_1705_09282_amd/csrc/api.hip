@@ -117,6 +117,9 @@ struct dfmg_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
     std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass, 4 small-subdomain gather
+    int small_top = 0;           // levels 1 .. small_top (and 0) run in the single-workgroup cycle; 0 = off
+    SmallLevel<double> *small_d = nullptr;  // device level tables of that cycle
+    SmallLevel<float> *small_f = nullptr;
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
     std::vector<double> eta_host;  // [problem][level]
     const Hierarchy &S() const { return P[0]; }
@@ -213,6 +216,8 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->wfine = A.take<double>(H.lv[L - 1].n_q);
     c->spsi = (int64_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1);
     if (c->mixed()) c->psi = A.take<double>((size_t)c->spsi * np);
+    c->small_d = A.take<SmallLevel<double>>(L);
+    if (c->mixed()) c->small_f = A.take<SmallLevel<float>>(L);
     c->mlpW = A.take<float>(MLP_NPARAM);
     c->feat = A.take<float>((size_t)MLP_IN * np);
     c->rho_plain = A.take<double>(np);
@@ -353,6 +358,60 @@ void apply_learned(dfmg_ctx *c) {
     launch_mlp_damping(c->np, c->mlpW, c->feat, c->L(), c->eta, c->s);
 }
 
+template <class T>
+SmallLevel<T> *small_table(dfmg_ctx *c);
+template <>
+SmallLevel<double> *small_table<double>(dfmg_ctx *c) { return c->small_d; }
+template <>
+SmallLevel<float> *small_table<float>(dfmg_ctx *c) { return c->small_f; }
+
+// Host copy of the level tables of the single-workgroup coarse cycle (device
+// pointers of the bound workspace).
+template <class T>
+std::vector<SmallLevel<T>> small_levels(dfmg_ctx *c) {
+    const int L = c->L();
+    std::vector<SmallLevel<T>> out(L);
+    for (int l = 0; l < L; ++l) {
+        const HostLevel &h = c->S().lv[l];
+        DevLevel &v = c->dl[l];
+        LevelData<T> &d = v.data<T>();
+        SmallLevel<T> &q = out[l];
+        q.sp = spmv_args<T>(c, l, nullptr, nullptr, nullptr, nullptr, nullptr);
+        q.F = d.F;
+        q.U = d.U;
+        q.r = d.r;
+        q.n = h.n;
+        if (l == 0) {
+            q.Kinv = v.Kinv;
+            continue;
+        }
+        q.delta = d.delta;
+        q.M = d.M;
+        q.sM = v.sM;
+        q.nent = v.nent;
+        q.smoff = h.n_patch;
+        q.pptr = v.pptr;
+        q.pdofs = v.pdofs;
+        q.moff = v.moff;
+        q.inv_ptr = v.inv_ptr;
+        q.inv_pos = v.inv_pos;
+        q.small = v.small;
+        q.bigent = v.bigent;
+        q.ent_info = v.ent_info;
+        q.nsmall = (int)h.small_list.size();
+        q.nbig = (int)h.big_ent.size();
+        q.eta = c->eta + l;
+        q.seta = L;
+        q.R_rp = v.R_rp;
+        q.R_ci = v.R_ci;
+        q.R_v = d.R_v;
+        q.P_rp = v.P_rp;
+        q.P_ci = v.P_ci;
+        q.P_v = d.P_v;
+    }
+    return out;
+}
+
 // One V-cycle (Algorithm 1) on the finest level's internal U, F of type T.
 // norm: the first residual of the finest level also feeds the convergence
 // check.  fine_zero: the finest U is known to be zero (its first smoothing
@@ -367,7 +426,8 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         coarse<T>(c, v.F, v.U, stop);  // exact solve of K U = F
         return;
     }
-    for (int l = L - 1; l >= 1; --l) {
+    const int top = c->small_top;  // levels <= top: single-workgroup cycle
+    for (int l = L - 1; l > top; --l) {
         LevelData<T> &v = c->dl[l].data<T>();
         const HostLevel &h = c->S().lv[l];
         bool zero = (l < L - 1) || fine_zero;
@@ -395,8 +455,11 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
             restrict_to<T>(c, l, v.r, c->dl[l - 1].data<T>().F, stop);
         }
     }
-    coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
-    for (int l = 1; l < L; ++l) {
+    if (top >= 1)
+        launch_vcycle_small<T>(c->S().pb.d, c->S().pb.k, small_table<T>(c), top, nu1, nu2, stop, c->np, c->s);
+    else
+        coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
+    for (int l = top + 1; l < L; ++l) {
         LevelData<T> &v = c->dl[l].data<T>();
         prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
         for (int s = 0; s < nu2; ++s) {
@@ -523,6 +586,11 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     return o;
 }
 
+// the autotuner considers the single-workgroup coarse cycle for levels of at
+// most this many DOFs per problem (off by default: one compute unit's
+// bandwidth makes it slower than the per-level kernels on the benchmark grids)
+constexpr int64_t kSmallCycleMax = 16384;
+
 void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
     c->opt = o;
     const int L = c->L();
@@ -535,6 +603,7 @@ void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
         const int64_t n = c->S().lv[l].n * c->np;
         c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
     }
+    c->small_top = 0;
 }
 
 
@@ -893,6 +962,16 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         HIPCHK(hipHostMalloc((void **)&c->hflags, 4 * np * sizeof(int), hipHostMallocDefault));
         std::memset(c->hflags, 0, 4 * np * sizeof(int));
         for (auto &e : c->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        {
+            auto td = small_levels<double>(c);
+            up(c->small_d, td, s);
+            HIPCHK(hipStreamSynchronize(s));
+            if (c->mixed()) {
+                auto tf = small_levels<float>(c);
+                up(c->small_f, tf, s);
+                HIPCHK(hipStreamSynchronize(s));
+            }
+        }
         HIPCHK(hipStreamSynchronize(s));
         c->bound = true;
     });
@@ -1026,18 +1105,33 @@ int dfmg_level_residual(dfmg_ctx *c, int level, const double *F, const double *U
     });
 }
 
-int dfmg_time_residual(dfmg_ctx *c, int level, const double *F, const double *U, double *r, int reps,
-                       double *ms) {
-    if (!c || !F || !U || !r || !ms || reps < 1) return fail(DFMG_EINVAL, "invalid argument");
+int dfmg_time_kernel(dfmg_ctx *c, int kernel, int level, int reps, double *ms) {
+    if (!c || !ms || reps < 1 || kernel < 0 || kernel > 3) return fail(DFMG_EINVAL, "invalid argument");
     return guarded([&] {
-        check_level(c, level, 0);
+        check_level(c, level, kernel >= 2 ? 1 : 0);
+        if ((kernel & 1) && !c->mixed()) throw ArgError("FP32 kernels exist with precision 1 only");
         enter(c);
+        auto launch = [&] {
+            if (kernel == 0) {
+                LevelData<double> &v = c->dl[level].d;
+                spmv<double>(c, level, v.F, v.U, v.r, nullptr, nullptr);
+            } else if (kernel == 1) {
+                LevelData<float> &v = c->dl[level].f;
+                spmv<float>(c, level, v.F, v.U, v.r, nullptr, nullptr);
+            } else if (kernel == 2) {
+                LevelData<double> &v = c->dl[level].d;
+                schwarz<double>(c, level, v.r, v.U, false, nullptr);
+            } else {
+                LevelData<float> &v = c->dl[level].f;
+                schwarz<float>(c, level, v.r, v.U, false, nullptr);
+            }
+        };
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        spmv<double>(c, level, F, U, r, nullptr, nullptr);  // warm
+        launch();  // warm
         HIPCHK(hipEventRecord(e0, c->s));
-        for (int i = 0; i < reps; ++i) spmv<double>(c, level, F, U, r, nullptr, nullptr);
+        for (int i = 0; i < reps; ++i) launch();
         HIPCHK(hipEventRecord(e1, c->s));
         HIPCHK(hipEventSynchronize(e1));
         float t = 0.f;
@@ -1095,21 +1189,29 @@ int dfmg_get_tuning(const dfmg_ctx *c, int *lpr, int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
     for (int l = 0; l < c->L(); ++l) {
         lpr[l] = c->lpr[l];
-        smoother[l] = c->smoother[l];
+        smoother[l] = (l >= 1 && l <= c->small_top) ? 5 : c->smoother[l];
     }
     return DFMG_OK;
 }
 
 int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     if (!c || !lpr || !smoother) return fail(DFMG_EINVAL, "null argument");
-    for (int l = 0; l < c->L(); ++l)
-        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4) || !(smoother[l] >= 1 && smoother[l] <= 4))
-            return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4 and smoother 1 .. 4");
+    const int L = c->L();
+    int top = 0;
+    while (top + 1 < L && smoother[top + 1] == 5) ++top;
+    for (int l = 0; l < L; ++l) {
+        if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4)) return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4");
+        const bool in_small = l >= 1 && l <= top;
+        if (!in_small && !(smoother[l] >= 1 && smoother[l] <= 4))
+            return fail(DFMG_EINVAL, "smoother must be 1 .. 4, or 5 on levels 1 .. t");
+    }
+    if (top > L - 2) return fail(DFMG_EINVAL, "the finest level cannot run in the single-workgroup cycle");
     return guarded([&] {
-        for (int l = 0; l < c->L(); ++l) {
+        for (int l = 0; l < L; ++l) {
             c->lpr[l] = lpr[l];
-            c->smoother[l] = smoother[l];
+            if (!(l >= 1 && l <= top)) c->smoother[l] = smoother[l];
         }
+        c->small_top = top;
         drop_graph(c);
     });
 }
@@ -1172,6 +1274,24 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         };
         if (c->mixed()) tune(0.0f);
         else tune(0.0);
+        // how many coarse levels run in the single-workgroup cycle: whole
+        // V-cycles timed for every admissible choice (no check, no flags)
+        launch_fill_int(c->np, c->stop, 0, c->s);
+        int best_top = 0;
+        double best_t = 1e30;
+        for (int t = 0; t <= L - 2; ++t) {
+            if (t >= 1 && c->S().lv[t].n > kSmallCycleMax) break;
+            c->small_top = t;
+            const double ms = timed([&] {
+                if (c->mixed()) cycle_body<float>(c, false, true);
+                else cycle_body<double>(c, false, false);
+            });
+            if (ms < best_t) {
+                best_t = ms;
+                best_top = t;
+            }
+        }
+        c->small_top = best_top;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         drop_graph(c);

@@ -1,5 +1,5 @@
 // HIP kernels of the additive-Schwarz V-cycle (gfx950, wave64).
-#include "device_util.hpp"
+#include "schwarz_dev.hpp"
 
 namespace dfmg {
 
@@ -16,28 +16,8 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     // descriptor of entry t: offset of its row of M, first entry of its
     // subdomain, subdomain size
     const int4 info = a.ent_info[(int64_t)prob * a.nent + t];
-    const T *m = a.M + prob * a.sM + info.x;
-    const T *r = a.r + prob * a.svec;
-    const int32_t *dofs = a.pdofs + info.y;
-    const int nn = info.z;
-    // chunks of 8 independent gathers; the tail is padded with zero
-    // coefficients on a valid index, which leaves the sum unchanged
-    T acc = 0;
-    for (int c = 0; c < nn; c += 8) {
-        int d[8];
-        T mv[8], rv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const bool ok = c + u < nn;
-            d[u] = dofs[ok ? c + u : c];
-            mv[u] = ok ? m[c + u] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) rv[u] = r[d[u]];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
-    }
-    a.delta[(int64_t)prob * a.nent + t] = acc;
+    a.delta[(int64_t)prob * a.nent + t] =
+        patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, a.r + prob * a.svec);
 }
 
 // Additive Schwarz, step 1 with one thread per small subdomain (at most
@@ -57,53 +37,16 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, i
         const int q = b * kBlock + threadIdx.x;
         if (q >= a.nsmall) return;
         const int p = a.small[q];
-        const int base = a.pptr[p], nn = a.pptr[p + 1] - base;
-        const T *m = a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p];
-        T rv[kSmallPatch];
-#pragma unroll
-        for (int c = 0; c < kSmallPatch; ++c) rv[c] = c < nn ? r[a.pdofs[base + c]] : T(0);
-        if (nn == kSmallPatch) {
-#pragma unroll
-            for (int row = 0; row < kSmallPatch; ++row) {
-                T acc = 0;
-#pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
-                delta[base + row] = acc;
-            }
-        } else {
-            for (int row = 0; row < nn; ++row) {
-                T acc = 0;
-#pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c)
-                    if (c < nn) acc = fma(m[row * nn + c], rv[c], acc);
-                delta[base + row] = acc;
-            }
-        }
+        const int base = a.pptr[p];
+        patch_small(a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p], a.pdofs + base, a.pptr[p + 1] - base, r,
+                    delta + base);
         return;
     }
     const int t = (b - nb_small) * kBlock + threadIdx.x;
     if (t >= a.nbig) return;
     const int e = a.bigent[t];
     const int4 info = a.ent_info[(int64_t)prob * a.nent + e];
-    const T *m = a.M + prob * a.sM + info.x;
-    const int32_t *dofs = a.pdofs + info.y;
-    const int nn = info.z;
-    T acc = 0;
-    for (int c = 0; c < nn; c += 8) {
-        int d[8];
-        T mv[8], rv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const bool ok = c + u < nn;
-            d[u] = dofs[ok ? c + u : c];
-            mv[u] = ok ? m[c + u] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) rv[u] = r[d[u]];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
-    }
-    delta[e] = acc;
+    delta[e] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, r);
 }
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
@@ -119,19 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
     const T *delta = a.delta + (int64_t)prob * a.nent;
     const T eta = (T)a.eta[prob * a.seta];
     const T u = a.assign ? T(0) : U[j];
-    T acc = 0;
-    const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
-    for (int e = e0; e < e1; e += 4) {
-        int pos[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pos[v] = a.inv_pos[e + v < e1 ? e + v : e];
-        T dv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dv[v] = delta[pos[v]];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : T(0);
-    }
-    U[j] = fma(eta, acc, u);
+    U[j] = fma(eta, dof_sum(a.inv_ptr, a.inv_pos, delta, j), u);
 }
 
 template <class T>
@@ -162,25 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
     const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
     for (int e = e0; e < e1; ++e) {
         const int4 info = ent[a.inv_pos[e]];
-        const T *m = M + info.x;
-        const int32_t *dofs = a.pdofs + info.y;
-        const int nn = info.z;
-        T row = 0;
-        for (int c = 0; c < nn; c += 8) {
-            int d[8];
-            T mv[8], rv[8];
-#pragma unroll
-            for (int w = 0; w < 8; ++w) {
-                const bool ok = c + w < nn;
-                d[w] = dofs[ok ? c + w : c];
-                mv[w] = ok ? m[c + w] : T(0);
-            }
-#pragma unroll
-            for (int w = 0; w < 8; ++w) rv[w] = r[d[w]];
-#pragma unroll
-            for (int w = 0; w < 8; ++w) row = fma(mv[w], rv[w], row);
-        }
-        acc += row;
+        acc += patch_row(M + info.x, a.pdofs + info.y, info.z, r);
     }
     U[j] = fma(eta, acc, u);
 }
@@ -241,23 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, co
     x += prob * sx;
     y += prob * sy;
     const T y0 = add ? y[i] : T(0);
-    T acc = 0;
-    const int e0 = rp[i], e1 = rp[i + 1];
-    for (int e = e0; e < e1; e += 4) {
-        int col[4];
-        T w[4], xv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ok = e + u < e1;
-            col[u] = ci[ok ? e + u : e];
-            w[u] = ok ? v[e + u] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = x[col[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc = fma(w[u], xv[u], acc);
-    }
-    y[i] = y0 + acc;
+    y[i] = y0 + csr_row(rp, ci, v, x, i);
 }
 
 template <class T>
@@ -277,12 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const doubl
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
-    A += prob * sA;
-    x += prob * sx;
-    double acc = 0.0;
-    for (int j = lane; j < cols; j += 64) acc = fma(A[(int64_t)row * cols + j], (double)x[j], acc);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    const double acc = gemv_row_wave(A + prob * sA, cols, x + prob * sx, row, lane);
     if (lane == 0) y[prob * sy + row] = (T)acc;
 }
 

@@ -71,6 +71,36 @@ struct PatchArgsT {
 };
 using PatchArgs = PatchArgsT<double>;
 
+// One level of the single-workgroup coarse cycle (k_vcycle_small): the
+// level's operator, subdomains and transfers, with vectors and per-problem
+// arrays given for problem 0 and the strides of the batch.
+template <class T>
+struct SmallLevel {
+    SpmvArgsT<T> sp;            // operator fields (val, sval, val_off, off, nb, n, win)
+    T *F, *U, *r, *delta;       // vectors: stride n; delta: stride nent
+    const T *M;                 // local inverses, stride sM
+    int64_t sM, n, nent, smoff;
+    const int32_t *pptr, *pdofs, *moff, *inv_ptr, *inv_pos, *small, *bigent;
+    const int4 *ent_info;       // stride nent
+    int nsmall, nbig;
+    const double *eta;          // eta[prob * seta] is this level's damping
+    int64_t seta;
+    const int32_t *R_rp, *R_ci; // restriction to level l-1 (rows of level l-1)
+    const T *R_v;
+    const int32_t *P_rp, *P_ci; // prolongation from level l-1 (rows of level l)
+    const T *P_v;
+    const double *Kinv;         // level 0: dense inverse, stride n * n
+};
+
+// A V-cycle over levels top .. 0 of every problem by one workgroup each
+// (levels small enough that launches, not bandwidth, would set the time):
+// starts from U_top = 0 on F_top, nu1 / nu2 smoothing steps, exact coarse
+// solve; the same sums as the per-level kernels.  lv: device array of
+// top + 1 levels.
+template <class T>
+void launch_vcycle_small(int d, int k, const SmallLevel<T> *lv, int top, int nu1, int nu2, const int *stop,
+                         int nprob, hipStream_t s);
+
 // blocks of the residual kernel with lpr lanes per row
 inline int spmv_blocks(int64_t n, int lpr) { return (int)((n * lpr + 255) / 256); }
 

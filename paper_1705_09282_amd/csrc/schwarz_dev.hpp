@@ -1,0 +1,112 @@
+// Device pieces of the additive Schwarz smoother and the grid transfers
+// (included by the per-level kernels and the single-workgroup coarse cycle).
+// Every sum runs in a fixed order, so all kernels built from these pieces
+// produce the same bits.
+#pragma once
+
+#include "device_util.hpp"
+
+namespace dfmg {
+
+// One row of M_p E_p r: m points at the row of the local inverse, dofs at the
+// subdomain's nn DOFs.  Gathers are issued 8 at a time; the tail is padded
+// with zero coefficients on a valid index, which leaves the sum unchanged.
+template <class T>
+__device__ __forceinline__ T patch_row(const T *m, const int32_t *dofs, int nn, const T *r) {
+    T acc = 0;
+    for (int c = 0; c < nn; c += 8) {
+        int d[8];
+        T mv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool ok = c + u < nn;
+            d[u] = dofs[ok ? c + u : c];
+            mv[u] = ok ? m[c + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rv[u] = r[d[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(mv[u], rv[u], acc);
+    }
+    return acc;
+}
+
+// Every row of M_p E_p r for a subdomain of nn <= kSmallPatch DOFs (m: its
+// row-major inverse), written to delta[0 .. nn); the residual entries are
+// gathered once.  Same sums as patch_row.
+template <class T>
+__device__ __forceinline__ void patch_small(const T *m, const int32_t *dofs, int nn, const T *r, T *delta) {
+    T rv[kSmallPatch];
+#pragma unroll
+    for (int c = 0; c < kSmallPatch; ++c) rv[c] = c < nn ? r[dofs[c]] : T(0);
+    if (nn == kSmallPatch) {
+#pragma unroll
+        for (int row = 0; row < kSmallPatch; ++row) {
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
+            delta[row] = acc;
+        }
+    } else {
+        for (int row = 0; row < nn; ++row) {
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < kSmallPatch; ++c)
+                if (c < nn) acc = fma(m[row * nn + c], rv[c], acc);
+            delta[row] = acc;
+        }
+    }
+}
+
+// Sum of the corrections of every subdomain holding DOF j, in entry order.
+template <class T>
+__device__ __forceinline__ T dof_sum(const int32_t *inv_ptr, const int32_t *inv_pos, const T *delta, int j) {
+    T acc = 0;
+    const int e0 = inv_ptr[j], e1 = inv_ptr[j + 1];
+    for (int e = e0; e < e1; e += 4) {
+        int pos[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pos[v] = inv_pos[e + v < e1 ? e + v : e];
+        T dv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dv[v] = delta[pos[v]];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc += (e + v < e1) ? dv[v] : T(0);
+    }
+    return acc;
+}
+
+// (A x)_i of a CSR matrix, gathers issued 4 at a time.
+template <class T>
+__device__ __forceinline__ T csr_row(const int32_t *rp, const int32_t *ci, const T *v, const T *x, int i) {
+    T acc = 0;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0; e < e1; e += 4) {
+        int col[4];
+        T w[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = e + u < e1;
+            col[u] = ci[ok ? e + u : e];
+            w[u] = ok ? v[e + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[col[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = fma(w[u], xv[u], acc);
+    }
+    return acc;
+}
+
+// Row `row` of a dense FP64 matrix times x by one wavefront (lane-strided
+// partial sums, then a shuffle tree); the result is valid in lane 0.
+template <class T>
+__device__ __forceinline__ double gemv_row_wave(const double *A, int cols, const T *x, int row, int lane) {
+    double acc = 0.0;
+    for (int j = lane; j < cols; j += 64) acc = fma(A[(int64_t)row * cols + j], (double)x[j], acc);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    return acc;
+}
+
+}  // namespace dfmg

@@ -73,7 +73,7 @@ SIGNATURES = [
     ("dfmg_level_restrict", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("dfmg_level_prolong_add", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("dfmg_coarse_solve", c_int, [c_void_p, c_void_p, c_void_p]),
-    ("dfmg_time_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_dblp]),
+    ("dfmg_time_kernel", c_int, [c_void_p, c_int, c_int, c_int, c_dblp]),
     ("dfmg_get_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_set_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_autotune", c_int, [c_void_p, c_int, c_dblp]),
@@ -344,10 +344,12 @@ class Solver:
     def level_prolong_add(self, level, dU, U):
         _check(lib().dfmg_level_prolong_add(self._ctx, level, _dev(dU, self._nlev(level - 1)), _dev(U, self._nlev(level))))
 
-    def time_residual(self, level, F, U, r, reps=50):
-        n = self._nlev(level)
+    def time_kernel(self, kernel, level, reps=50):
+        """Average milliseconds per launch of kernel 0 (FP64 residual), 1 (FP32
+        residual), 2 (FP64 smoothing step) or 3 (FP32 smoothing step) on
+        `level`, for the whole batch."""
         out = c_double()
-        _check(lib().dfmg_time_residual(self._ctx, level, _dev(F, n), _dev(U, n), _dev(r, n), int(reps), ctypes.byref(out)))
+        _check(lib().dfmg_time_kernel(self._ctx, int(kernel), int(level), int(reps), ctypes.byref(out)))
         return out.value
 
     def get_tuning(self):

@@ -90,3 +90,19 @@ def test_named_workload_sizes():
     assert (z["n_vel"], z["n_pres"], z["n_patch"], z["nnz"]) == (132612, 66564, 66049, 12477912)
     assert s.workspace_bytes() > 0
     s.close()
+
+
+def test_tuning_validation():
+    """Kernel-variant choices are checked on the host: lanes per row 1/2/4,
+    smoother forms 1..4, and the single-workgroup coarse cycle (5) only on a
+    prefix of levels 1..t below the finest."""
+    from paper_1705_09282_amd.dfmg import Solver, DfmgError
+    s = Solver(2, 32, 4, 1)
+    s.set_tuning([1, 2, 4, 1], [1, 5, 5, 3])
+    assert s.get_tuning() == {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3]}
+    for lpr, sm in (([3, 1, 1, 1], [1, 1, 1, 1]), ([1, 1, 1, 1], [1, 1, 5, 1]),
+                    ([1, 1, 1, 1], [1, 5, 5, 5]), ([1, 1, 1, 1], [1, 6, 1, 1])):
+        with pytest.raises(DfmgError):
+            s.set_tuning(lpr, sm)
+    assert s.get_tuning() == {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3]}
+    s.close()

@@ -147,6 +147,27 @@ def test_smoother_forms_agree_bitwise(d, N, k, L, precision):
         assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
 
 
+@pytest.mark.parametrize("d,N,k,L,precision", [(2, 64, 2, 5, 0), (2, 64, 1, 5, 1), (3, 16, 1, 4, 0),
+                                               (2, 32, 2, 5, 1)])
+def test_single_workgroup_coarse_cycle_is_bitwise_equal(d, N, k, L, precision):
+    """Levels 1 .. t in one single-workgroup launch compute the same sums as
+    the per-level kernels with one lane per row: every choice of t gives the
+    same solve, bit for bit, and get/set_tuning round-trips the choice."""
+    from paper_1705_09282_amd.dfmg import Solver
+    out = []
+    for t in range(0, L - 1):
+        s = Solver(d, N, L, k, nu=0.5, sigma=4.0, c=0.0, precision=precision).bind()
+        s.set_tuning([1] * L, [1] + [5] * t + [1] * (L - 1 - t))
+        assert s.get_tuning()["smoother"] == [1] + [5] * t + [1] * (L - 1 - t)
+        F = dev(s.manufactured_rhs())
+        U = dev(np.zeros(s.n))
+        st = s.solve(F, U, tol=1e-8)
+        out.append((host(U), st["history"]))
+        s.close()
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
+
+
 def test_autotune_keeps_results_and_picks_fastest(tmp_path):
     s, h, F = make(2, 64, 2, 4)
     U0 = divfree_start(h, 5)

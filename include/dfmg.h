@@ -158,10 +158,13 @@ int dfmg_vcycle(dfmg_ctx *ctx, const double *F_dev, double *U_dev, int ncycles);
  * EDIVERGED (worst over the batch), ESTATE, EHIP.
  * With precision 1 each step computes r = F - K U in FP64, applies
  * inner_cycles V-cycles in FP32 (FP32 values, FP32 accumulation, FP64 coarse
- * solve) to K dU = r from dU = 0, recovers the streamfunction increment psi
- * of dU's velocity by integrating its x-component along y, and updates
- * u += curl psi, p += dU_p in FP64, so u stays divergence-free to FP64
- * rounding; stats count refinement steps as cycles. */
+ * solve) to K dU = r from dU = 0 that also accumulate the streamfunction
+ * coefficients psi of dU's velocity (every local velocity correction is the
+ * curl of local streamfunctions, the reduced subdomain problem; prolongation
+ * and the coarse solve carry psi along), and updates u += curl psi,
+ * p += dU_p in FP64, so u stays divergence-free to FP64 rounding.  The FP32
+ * cycle runs smoother form 3 where tuned so and form 4 otherwise.  Stats
+ * count refinement steps as cycles. */
 int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, dfmg_stats *st);
 
 /* ||F - K U||_2 on the finest level (device inputs, host output). */

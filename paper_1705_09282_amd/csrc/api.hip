@@ -16,6 +16,7 @@
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dfmg.h"
@@ -58,14 +59,21 @@ struct DevLevel {
     LevelData<float> f;
     // shared by the batch
     int32_t *pptr = nullptr, *pdofs = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr, *col_list = nullptr;
-    int32_t *small = nullptr, *bigent = nullptr;
+    int32_t *small = nullptr, *bigent = nullptr, *small_dofs = nullptr, *inv_pos4 = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
     // per problem
     int32_t *moff = nullptr;
     int4 *ent_info = nullptr;
     double *Kinv = nullptr;
+    // potential form of the FP32 cycle (precision 1, 2D)
+    double *psi = nullptr, *Ps_v = nullptr;  // psi per problem (FP64: see PatchArgsT)
+    float *beta = nullptr, *Q = nullptr;     // per problem
+    int32_t *qoff = nullptr, *qptr = nullptr, *beta_row = nullptr, *beta_patch = nullptr, *bigbeta = nullptr,
+            *qinv_ptr = nullptr, *qinv_pos = nullptr, *Ps_rp = nullptr, *Ps_ci = nullptr;
+    double *Q0 = nullptr;  // level 0, per problem
+    int64_t npsi = 0, nbeta = 0, sQ = 0;
     // strides
-    int64_t sval = 0, sM = 0, nent = 0, n = 0;
+    int64_t sval = 0, sM = 0, nent = 0, n = 0, sdelta = 0;
     template <class T>
     LevelData<T> &data();
 };
@@ -107,13 +115,11 @@ struct dfmg_ctx {
     hipEvent_t ev_flag[2] = {nullptr, nullptr};
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
-    double *psi = nullptr;       // refinement: streamfunction increments [problem][(N+k-1)^2]
     // learned damping
     float *mlpW = nullptr, *feat = nullptr;
     double *rho_plain = nullptr, *eta_fixed = nullptr;
     int *fallback = nullptr;
     bool learned = false;
-    int64_t spsi = 0;
     hipGraphExec_t graph = nullptr;
     int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
     std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass, 4 small-subdomain gather
@@ -160,7 +166,7 @@ void take_level(Arena &A, const DevLevel &dv, int np, LevelData<T> &v, bool coar
     v.val = A.take<T>(dv.sval * np);
     if (coarse) return;
     v.M = A.take<T>(dv.sM * np);
-    v.delta = A.take<T>(dv.nent * np);
+    v.delta = A.take<T>(dv.sdelta * np);
     v.P_v = A.take<T>(h.P_v.size());
     v.R_v = A.take<T>(h.R_v.size());
 }
@@ -177,10 +183,34 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.n = h.n;
         v.sval = (int64_t)h.val.size();
         v.nent = (int64_t)h.pdofs.size();
+        v.sdelta = v.nent + (int64_t)kSmallPatch * (int64_t)h.small_list.size();
         v.sM = 0;
         for (const Hierarchy &Q : c->P) v.sM = std::max(v.sM, (int64_t)Q.lv[l].M.size());
         take_level(A, v, np, v.d, l == 0, h);
-        if (c->mixed()) take_level(A, v, np, v.f, l == 0, h);
+        if (c->mixed()) {
+            take_level(A, v, np, v.f, l == 0, h);
+            v.npsi = h.n_psi;
+            v.psi = A.take<double>((size_t)h.n_psi * np);
+            if (l == 0) {
+                v.Q0 = A.take<double>(h.Q0.size() * np);
+            } else {
+                v.nbeta = (int64_t)h.qpsi.size();
+                v.sQ = 0;  // the shared maps differ between problems (coefficients)
+                for (const Hierarchy &Q : c->P) v.sQ = std::max(v.sQ, (int64_t)Q.lv[l].Q.size());
+                v.beta = A.take<float>((size_t)v.nbeta * np);
+                v.Q = A.take<float>((size_t)v.sQ * np);
+                v.Ps_v = A.take<double>(h.Ps_v.size());
+                v.qoff = A.take<int32_t>(h.qoff.size() * np);
+                v.qptr = A.take<int32_t>(h.qptr.size());
+                v.beta_row = A.take<int32_t>(h.beta_row.size() * np);
+                v.beta_patch = A.take<int32_t>(h.beta_patch.size());
+                v.bigbeta = A.take<int32_t>(h.big_beta.size());
+                v.qinv_ptr = A.take<int32_t>(h.qinv_ptr.size());
+                v.qinv_pos = A.take<int32_t>(h.qinv_pos.size());
+                v.Ps_rp = A.take<int32_t>(h.Ps_rp.size());
+                v.Ps_ci = A.take<int32_t>(h.Ps_ci.size());
+            }
+        }
         nmax = std::max(nmax, h.n);
         maxblocks = std::max(maxblocks, spmv_blocks(h.n, 4));
         if (l == 0) {
@@ -194,6 +224,8 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.col_list = A.take<int32_t>(h.col_list.size());
         v.small = A.take<int32_t>(h.small_list.size());
         v.bigent = A.take<int32_t>(h.big_ent.size());
+        v.small_dofs = A.take<int32_t>(h.small_dofs.size());
+        v.inv_pos4 = A.take<int32_t>(h.inv_pos4.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
         v.P_ci = A.take<int32_t>(h.P_ci.size());
         v.R_rp = A.take<int32_t>(h.R_rp.size());
@@ -214,8 +246,6 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->pmass = A.take<double>(H.pmass.size());
     c->rtmp = A.take<double>((size_t)nmax * np);
     c->wfine = A.take<double>(H.lv[L - 1].n_q);
-    c->spsi = (int64_t)(H.pb.N + H.pb.k - 1) * (H.pb.N + H.pb.k - 1);
-    if (c->mixed()) c->psi = A.take<double>((size_t)c->spsi * np);
     c->small_d = A.take<SmallLevel<double>>(L);
     if (c->mixed()) c->small_f = A.take<SmallLevel<float>>(L);
     c->mlpW = A.take<float>(MLP_NPARAM);
@@ -276,6 +306,13 @@ int spmv(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, cons
     return a.nblocks;
 }
 
+// The FP32 cycle of the refinement (2D) tracks the potentials of its
+// velocity corrections.
+template <class T>
+bool tracks_potentials(const dfmg_ctx *c) {
+    return std::is_same<T, float>::value && c->mixed();
+}
+
 // eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l.
 template <class T>
 void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop) {
@@ -304,8 +341,35 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.nprob = c->np;
     a.small = v.small;
     a.bigent = v.bigent;
+    a.small_dofs = v.small_dofs;
     a.nsmall = (int)h.small_list.size();
     a.nbig = (int)h.big_ent.size();
+    a.sdelta = v.sdelta;
+    if (tracks_potentials<T>(c)) {
+        // the FP32 cycle of the refinement also accumulates the potentials of
+        // its velocity corrections (forms 3 and 4 do; the others run as 4)
+        a.psi = v.psi;
+        a.beta = reinterpret_cast<T *>(v.beta);
+        a.Q = reinterpret_cast<const T *>(v.Q);
+        a.sQ = v.sQ;
+        a.nbeta = v.nbeta;
+        a.npsi = (int)v.npsi;
+        a.nbigbeta = (int)h.big_beta.size();
+        a.qoff = v.qoff;
+        a.qptr = v.qptr;
+        a.beta_row = v.beta_row;
+        a.beta_patch = v.beta_patch;
+        a.bigbeta = v.bigbeta;
+        a.qinv_ptr = v.qinv_ptr;
+        a.qinv_pos = v.qinv_pos;
+        if (c->smoother[l] == 3) {  // one pass (recomputes the rows, no buffer)
+            launch_schwarz_fused<T>(a, c->s);
+        } else {
+            a.inv_pos = v.inv_pos4;
+            launch_schwarz_small<T>(a, c->s);
+        }
+        return;
+    }
     if (c->smoother[l] == 2) {
         if (assign) launch_fill<T>(h.n, U, h.n, T(0), stop, c->np, c->s);
         for (size_t col = 0; col + 1 < h.col_ptr.size(); ++col)
@@ -313,6 +377,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     } else if (c->smoother[l] == 3) {
         launch_schwarz_fused<T>(a, c->s);
     } else if (c->smoother[l] == 4) {
+        a.inv_pos = v.inv_pos4;
         launch_schwarz_small<T>(a, c->s);
     } else {
         launch_schwarz_gather<T>(a, c->s);
@@ -386,6 +451,7 @@ std::vector<SmallLevel<T>> small_levels(dfmg_ctx *c) {
             continue;
         }
         q.delta = d.delta;
+        q.sdelta = v.sdelta;
         q.M = d.M;
         q.sM = v.sM;
         q.nent = v.nent;
@@ -426,7 +492,8 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         coarse<T>(c, v.F, v.U, stop);  // exact solve of K U = F
         return;
     }
-    const int top = c->small_top;  // levels <= top: single-workgroup cycle
+    const bool psi = tracks_potentials<T>(c);
+    const int top = psi ? 0 : c->small_top;  // levels <= top: single-workgroup cycle
     for (int l = L - 1; l > top; --l) {
         LevelData<T> &v = c->dl[l].data<T>();
         const HostLevel &h = c->S().lv[l];
@@ -448,6 +515,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         }
         if (zero && !first_res) {
             launch_fill<T>(h.n, v.U, h.n, T(0), stop, c->np, c->s);
+            if (psi) launch_fill<double>(c->dl[l].npsi, c->dl[l].psi, c->dl[l].npsi, 0.0, stop, c->np, c->s);
             restrict_to<T>(c, l, v.F, c->dl[l - 1].data<T>().F, stop);
         } else {
             const int npb = spmv<T>(c, l, v.F, v.U, v.r, first_res ? c->partial : nullptr, stop);
@@ -459,9 +527,18 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         launch_vcycle_small<T>(c->S().pb.d, c->S().pb.k, small_table<T>(c), top, nu1, nu2, stop, c->np, c->s);
     else
         coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
+    if (psi) {  // potentials of the coarse velocity solution
+        const DevLevel &z = c->dl[0];
+        launch_gemv_f2d((int)z.npsi, (int)z.n, z.Q0, z.npsi * z.n, z.f.F, z.n, z.psi, z.npsi, stop, c->np, c->s);
+    }
     for (int l = top + 1; l < L; ++l) {
         LevelData<T> &v = c->dl[l].data<T>();
         prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
+        if (psi) {
+            DevLevel &f = c->dl[l];
+            const DevLevel &q = c->dl[l - 1];
+            launch_csr<double>((int)f.npsi, f.Ps_rp, f.Ps_ci, f.Ps_v, q.psi, q.npsi, f.psi, f.npsi, 1, stop, c->np, c->s);
+        }
         for (int s = 0; s < nu2; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
             schwarz<T>(c, l, v.r, v.U, false, stop);
@@ -487,10 +564,10 @@ void refine_body(dfmg_ctx *c) {
     a.n = h.n;
     a.X = v.f.U;
     a.dcoef = c->dcoef;
-    a.psi = c->psi;
+    a.psi = v.psi;
     a.U = v.d.U;
     a.svec = h.n;
-    a.spsi = c->spsi;
+    a.spsi = v.npsi;
     a.stop = c->stop;
     a.nprob = c->np;
     launch_refine_update_2d(a, c->s);
@@ -569,6 +646,7 @@ Problem make_problem(const dfmg_grid *grid, int k, double nu, double sigma, cons
         pb.adv_c = adv->c;
     }
     pb.share_inverses = o.share_inverses != 0;
+    pb.potentials = o.precision == 1;
     return pb;
 }
 
@@ -920,6 +998,26 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                     up32(v.f.P_v, h.P_v, s);
                     up32(v.f.R_v, h.R_v, s);
                 }
+                HIPCHK(hipMemsetAsync(v.psi, 0, v.npsi * np * sizeof(double), s));
+                if (l == 0) {
+                    for (int p = 0; p < np; ++p) up(v.Q0 + p * h.Q0.size(), c->P[p].lv[0].Q0, s);
+                } else {
+                    for (int p = 0; p < np; ++p) {
+                        up32(v.Q + p * v.sQ, c->P[p].lv[l].Q, s);
+                        up(v.qoff + p * h.n_patch, c->P[p].lv[l].qoff, s);
+                        up(v.beta_row + p * v.nbeta, c->P[p].lv[l].beta_row, s);
+                    }
+                    HIPCHK(hipStreamSynchronize(s));
+                    up(v.Ps_v, h.Ps_v, s);
+                    up(v.qptr, h.qptr, s);
+                    up(v.beta_patch, h.beta_patch, s);
+                    up(v.bigbeta, h.big_beta, s);
+                    up(v.qinv_ptr, h.qinv_ptr, s);
+                    up(v.qinv_pos, h.qinv_pos, s);
+                    up(v.Ps_rp, h.Ps_rp, s);
+                    up(v.Ps_ci, h.Ps_ci, s);
+                    HIPCHK(hipMemsetAsync(v.beta, 0, v.nbeta * np * sizeof(float), s));
+                }
             }
             if (l == 0) {
                 for (int p = 0; p < np; ++p) up(v.Kinv + p * h.Kinv.size(), c->P[p].lv[0].Kinv, s);
@@ -932,6 +1030,8 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.col_list, h.col_list, s);
             up(v.small, h.small_list, s);
             up(v.bigent, h.big_ent, s);
+            up(v.small_dofs, h.small_dofs, s);
+            up(v.inv_pos4, h.inv_pos4, s);
             up(v.d.P_v, h.P_v, s);
             up(v.d.R_v, h.R_v, s);
             up(v.P_rp, h.P_rp, s);
@@ -1279,7 +1379,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         launch_fill_int(c->np, c->stop, 0, c->s);
         int best_top = 0;
         double best_t = 1e30;
-        for (int t = 0; t <= L - 2; ++t) {
+        for (int t = 0; t <= (c->mixed() ? 0 : L - 2); ++t) {  // the FP32 cycle tracks potentials: no t
             if (t >= 1 && c->S().lv[t].n > kSmallCycleMax) break;
             c->small_top = t;
             const double ms = timed([&] {

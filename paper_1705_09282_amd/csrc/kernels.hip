@@ -16,37 +16,47 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     // descriptor of entry t: offset of its row of M, first entry of its
     // subdomain, subdomain size
     const int4 info = a.ent_info[(int64_t)prob * a.nent + t];
-    a.delta[(int64_t)prob * a.nent + t] =
-        patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, a.r + prob * a.svec);
+    a.delta[prob * a.sdelta + t] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, a.r + prob * a.svec);
 }
 
 // Additive Schwarz, step 1 with one thread per small subdomain (at most
 // kSmallPatch DOFs, the interior ones): the thread gathers its subdomain's
-// residual entries once and computes every row of M_p E_p r.  Blocks past
-// nb_small take one entry each of the larger (boundary) subdomains as
-// k_patch_solve does.  Rows are summed in the same order as k_patch_solve,
-// so the corrections agree bit for bit.
+// residual entries once (its DOFs are stored subdomain-minor, so the loads
+// coalesce) and computes every row of M_p E_p r, written row-major over the
+// small subdomains (coalesced stores).  Blocks past nb_small take one entry
+// each of the larger (boundary) subdomains as k_patch_solve does.  Every row
+// is summed in the order of k_patch_solve, so the corrections agree bit for
+// bit; k_dof_update reads them through the relabelled inverse map.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, int nb_small) {
     const int prob = blockIdx.y;
     if (a.stop && a.stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const T *r = a.r + prob * a.svec;
-    T *delta = a.delta + (int64_t)prob * a.nent;
+    T *delta = a.delta + prob * a.sdelta;
     if (b < nb_small) {
         const int q = b * kBlock + threadIdx.x;
         if (q >= a.nsmall) return;
         const int p = a.small[q];
-        const int base = a.pptr[p];
-        patch_small(a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p], a.pdofs + base, a.pptr[p + 1] - base, r,
-                    delta + base);
+        const int nn = a.pptr[p + 1] - a.pptr[p];
+        T rv[kSmallPatch];
+        gather_small(a.small_dofs + q, a.nsmall, nn, r, rv);
+        apply_small(a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p], nn, rv, delta + q, a.nsmall);
+        if (a.psi)  // the subdomain's single potential
+            a.beta[prob * a.nbeta + a.qptr[p]] = small_row(a.Q + prob * a.sQ + a.qoff[prob * a.smoff + p], nn, rv);
         return;
     }
     const int t = (b - nb_small) * kBlock + threadIdx.x;
-    if (t >= a.nbig) return;
-    const int e = a.bigent[t];
-    const int4 info = a.ent_info[(int64_t)prob * a.nent + e];
-    delta[e] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, r);
+    if (t < a.nbig) {
+        const int e = a.bigent[t];
+        const int4 info = a.ent_info[(int64_t)prob * a.nent + e];
+        delta[(int64_t)kSmallPatch * a.nsmall + e] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, r);
+    } else if (a.psi && t < a.nbig + a.nbigbeta) {
+        const int e = a.bigbeta[t - a.nbig], p = a.beta_patch[e];
+        const int base = a.pptr[p];
+        a.beta[prob * a.nbeta + e] =
+            patch_row(a.Q + prob * a.sQ + a.beta_row[prob * a.nbeta + e], a.pdofs + base, a.pptr[p + 1] - base, r);
+    }
 }
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
@@ -57,10 +67,17 @@ __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
     if (a.stop && a.stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
-    if (j >= a.n) return;
-    T *U = a.U + prob * a.svec;
-    const T *delta = a.delta + (int64_t)prob * a.nent;
     const T eta = (T)a.eta[prob * a.seta];
+    if (j >= a.n) {  // potentials (tracked in the FP32 cycle)
+        const int pj = j - a.n;
+        if (!a.psi || pj >= a.npsi) return;
+        double *psi = a.psi + (int64_t)prob * a.npsi;
+        const double u = a.assign ? 0.0 : psi[pj];
+        psi[pj] = fma((double)eta, (double)dof_sum(a.qinv_ptr, a.qinv_pos, a.beta + prob * a.nbeta, pj), u);
+        return;
+    }
+    T *U = a.U + prob * a.svec;
+    const T *delta = a.delta + prob * a.sdelta;
     const T u = a.assign ? T(0) : U[j];
     U[j] = fma(eta, dof_sum(a.inv_ptr, a.inv_pos, delta, j), u);
 }
@@ -82,12 +99,26 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
     if (a.stop && a.stop[prob]) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
-    if (j >= a.n) return;
-    T *U = a.U + prob * a.svec;
     const T *r = a.r + prob * a.svec;
+    const T eta = (T)a.eta[prob * a.seta];
+    if (j >= a.n) {  // potentials: the betas landing on potential pj, recomputed
+        const int pj = j - a.n;
+        if (!a.psi || pj >= a.npsi) return;
+        double *psi = a.psi + (int64_t)prob * a.npsi;
+        const double u = a.assign ? 0.0 : psi[pj];
+        const T *Q = a.Q + prob * a.sQ;
+        const int32_t *brow = a.beta_row + prob * a.nbeta;
+        T acc = 0;
+        for (int e = a.qinv_ptr[pj]; e < a.qinv_ptr[pj + 1]; ++e) {
+            const int be = a.qinv_pos[e], p = a.beta_patch[be];
+            acc += patch_row(Q + brow[be], a.pdofs + a.pptr[p], a.pptr[p + 1] - a.pptr[p], r);
+        }
+        psi[pj] = fma((double)eta, (double)acc, u);
+        return;
+    }
+    T *U = a.U + prob * a.svec;
     const T *M = a.M + prob * a.sM;
     const int4 *ent = a.ent_info + (int64_t)prob * a.nent;
-    const T eta = (T)a.eta[prob * a.seta];
     const T u = a.assign ? T(0) : U[j];
     T acc = 0;
     const int e0 = a.inv_ptr[j], e1 = a.inv_ptr[j + 1];
@@ -100,14 +131,16 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
 
 template <class T>
 void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s) {
-    const int nbs = blocks_for(a.nsmall), nbb = blocks_for(a.nbig);
+    const int nbs = blocks_for(a.nsmall), nbb = blocks_for(a.nbig + (a.psi ? a.nbigbeta : 0));
     hipLaunchKernelGGL(k_patch_solve_small<T>, dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), 0, s, a, nbs);
-    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
+    const int64_t rows = a.n + (a.psi ? a.npsi : 0);
+    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(rows)), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 template <class T>
 void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_schwarz_fused<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
+    const int64_t rows = a.n + (a.psi ? a.npsi : 0);
+    hipLaunchKernelGGL(k_schwarz_fused<T>, dim3(padded_grid(blocks_for(rows)), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
@@ -186,6 +219,24 @@ void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, in
                        sA, x, sx, y, sy, stop);
 }
 
+__global__ __launch_bounds__(kBlock) void k_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x,
+                                                     int64_t sx, double *y, int64_t sy, const int *stop) {
+    const int prob = blockIdx.y;
+    if (stop && stop[prob]) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    const double acc = gemv_row_wave(A + prob * sA, cols, x + prob * sx, row, lane);
+    if (lane == 0) y[prob * sy + row] = acc;
+}
+
+void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x, int64_t sx, double *y,
+                     int64_t sy, const int *stop, int nprob, hipStream_t s) {
+    const int rows_per = kBlock / 64;
+    hipLaunchKernelGGL(k_gemv_f2d, dim3((rows + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, rows, cols, A,
+                       sA, x, sx, y, sy, stop);
+}
+
 template <class T>
 __global__ void k_fill(int64_t n, T *x, int64_t sx, T v, const int *stop) {
     const int prob = blockIdx.y;
@@ -208,40 +259,6 @@ __global__ void k_cast(int64_t n, const double *x, float *y, int64_t sv, const i
 void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_cast, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, y, svec, stop);
-}
-
-// Streamfunction increment from the x-velocity of the FP32 correction:
-// u_x(a, j) = c_{j+1} (psi(a, j+1) - psi(a, j)) with psi(a, 0) = 0, so
-// psi(a, j+1) = psi(a, j) + u_x(a, j) / c_{j+1}, a prefix sum along y.  One
-// block per column a: each thread sums a contiguous chunk, the chunk totals
-// are scanned in LDS (fixed order), then every chunk is written with its
-// offset.  psi is stored at (a-1) + (N+k-1) (b-1) for b = 1 .. N+k-1.
-__global__ __launch_bounds__(kBlock) void k_recover_psi_2d(RefineArgs a) {
-    const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
-    const int m = a.N + a.k - 1;  // potential functions per direction
-    const int ia = blockIdx.x;
-    const float *X = a.X + prob * a.svec;
-    double *psi = a.psi + prob * a.spsi;
-    const int per = (m + kBlock - 1) / kBlock;
-    const int j0 = threadIdx.x * per, j1 = min(j0 + per, m);
-    double s = 0.0;
-    for (int j = j0; j < j1; ++j) s += (double)X[ia + (int64_t)m * j] / a.dcoef[j + 1];
-    __shared__ double sh[kBlock];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    // inclusive scan of the chunk totals (Hillis-Steele, fixed order)
-    for (int o = 1; o < kBlock; o <<= 1) {
-        const double v = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0.0;
-        __syncthreads();
-        sh[threadIdx.x] += v;
-        __syncthreads();
-    }
-    double ps = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
-    for (int j = j0; j < j1; ++j) {
-        ps += (double)X[ia + (int64_t)m * j] / a.dcoef[j + 1];
-        psi[ia + (int64_t)m * j] = ps;
-    }
 }
 
 // U += [curl psi; X_p] in FP64, curl psi = (d_y psi, -d_x psi) by the scaled
@@ -272,8 +289,6 @@ __global__ void k_curl_update_2d(RefineArgs a) {
 }
 
 void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
-    const int m = a.N + a.k - 1;
-    hipLaunchKernelGGL(k_recover_psi_2d, dim3(m, a.nprob), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n), a.nprob), dim3(kBlock), 0, s, a);
 }
 

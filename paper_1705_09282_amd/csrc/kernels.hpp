@@ -67,7 +67,22 @@ struct PatchArgsT {
     int nprob;
     const int32_t *small;   // subdomains with <= kSmallPatch DOFs (shared)
     const int32_t *bigent;  // entries of the other subdomains (shared)
+    const int32_t *small_dofs;  // form 4: DOF c of small subdomain q at c * nsmall + q
     int nsmall, nbig;
+    int64_t sdelta;         // per-problem stride of delta (nent + kSmallPatch * nsmall)
+    // potential form (FP32 cycle inside the refinement, smoother form 4):
+    // beta = Q_i E_i r per local potential, psi += eta * sum of the betas of
+    // each potential.  psi is FP64: it is a sum of many local potentials whose
+    // differences are the velocity, which FP32 storage would cancel away.
+    // psi == nullptr: not tracked.
+    double *psi;            // per problem (stride npsi)
+    T *beta;                // per problem (stride nbeta)
+    const T *Q;             // per problem (stride sQ)
+    int64_t sQ, nbeta;
+    int npsi, nbigbeta;
+    const int32_t *qoff;      // per problem (stride smoff): offset of each subdomain's map in Q
+    const int32_t *beta_row;  // per problem (stride nbeta): Q row of each beta entry
+    const int32_t *qptr, *beta_patch, *bigbeta, *qinv_ptr, *qinv_pos;  // shared
 };
 using PatchArgs = PatchArgsT<double>;
 
@@ -77,7 +92,8 @@ using PatchArgs = PatchArgsT<double>;
 template <class T>
 struct SmallLevel {
     SpmvArgsT<T> sp;            // operator fields (val, sval, val_off, off, nb, n, win)
-    T *F, *U, *r, *delta;       // vectors: stride n; delta: stride nent
+    T *F, *U, *r, *delta;       // vectors: stride n; delta: stride sdelta (entry layout)
+    int64_t sdelta;
     const T *M;                 // local inverses, stride sM
     int64_t sM, n, nent, smoff;
     const int32_t *pptr, *pdofs, *moff, *inv_ptr, *inv_pos, *small, *bigent;
@@ -125,6 +141,9 @@ void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, con
 template <class T>
 void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, int64_t sx, T *y, int64_t sy,
                  const int *stop, int nprob, hipStream_t s);
+// y (FP64) = A x with x in FP32 (the coarse potentials of the FP32 cycle)
+void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x, int64_t sx, double *y,
+                     int64_t sy, const int *stop, int nprob, hipStream_t s);
 template <class T>
 void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s);
 void launch_fill_int(int n, int *x, int v, hipStream_t s);
@@ -160,15 +179,14 @@ void launch_check(int nparts, const double *partial, int64_t spart, double *hist
 // per problem: x[p * sx + i] -= m[p] for i < n
 void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s);
 
-// FP64 update of the refinement loop (2D): recover the streamfunction
-// increment psi from the x-velocity part of the FP32 correction X by
-// integrating along y, then U += [curl psi; X_p].
+// FP64 update of the refinement loop (2D): U += [curl psi; X_p] with psi the
+// streamfunction coefficients of the FP32 cycle's velocity correction.
 struct RefineArgs {
     int N, k;
     int64_t off_uy, off_p, n;  // block offsets of the finest level
-    const float *X;
+    const float *X;            // FP32 correction (pressure part used)
+    const double *psi;         // (N+k-1)^2 potentials per problem
     const double *dcoef;
-    double *psi;               // (N+k-1)^2 per problem
     double *U;
     int64_t svec, spsi;
     const int *stop;

@@ -31,31 +31,48 @@ __device__ __forceinline__ T patch_row(const T *m, const int32_t *dofs, int nn, 
     return acc;
 }
 
-// Every row of M_p E_p r for a subdomain of nn <= kSmallPatch DOFs (m: its
-// row-major inverse), written to delta[0 .. nn); the residual entries are
-// gathered once.  Same sums as patch_row.
+// The residual entries of a subdomain of nn <= kSmallPatch DOFs (DOF c at
+// dofs[c * dstride]), zero past nn.
 template <class T>
-__device__ __forceinline__ void patch_small(const T *m, const int32_t *dofs, int nn, const T *r, T *delta) {
-    T rv[kSmallPatch];
+__device__ __forceinline__ void gather_small(const int32_t *dofs, int64_t dstride, int nn, const T *r, T *rv) {
 #pragma unroll
-    for (int c = 0; c < kSmallPatch; ++c) rv[c] = c < nn ? r[dofs[c]] : T(0);
+    for (int c = 0; c < kSmallPatch; ++c) rv[c] = c < nn ? r[dofs[c * dstride]] : T(0);
+}
+
+// Row m of M times the gathered entries: the same sum as patch_row.
+template <class T>
+__device__ __forceinline__ T small_row(const T *mrow, int nn, const T *rv) {
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < kSmallPatch; ++c)
+        if (c < nn) acc = fma(mrow[c], rv[c], acc);
+    return acc;
+}
+
+// Every row of M_p E_p r for a subdomain of nn <= kSmallPatch DOFs (m: its
+// row-major inverse), row m written to delta[m * stride].  Same sums as
+// patch_row.
+template <class T>
+__device__ __forceinline__ void apply_small(const T *m, int nn, const T *rv, T *delta, int64_t stride) {
     if (nn == kSmallPatch) {
 #pragma unroll
         for (int row = 0; row < kSmallPatch; ++row) {
             T acc = 0;
 #pragma unroll
             for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
-            delta[row] = acc;
+            delta[row * stride] = acc;
         }
     } else {
-        for (int row = 0; row < nn; ++row) {
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < kSmallPatch; ++c)
-                if (c < nn) acc = fma(m[row * nn + c], rv[c], acc);
-            delta[row] = acc;
-        }
+        for (int row = 0; row < nn; ++row) delta[row * stride] = small_row(m + row * nn, nn, rv);
     }
+}
+
+// Every row of a small subdomain's M_p E_p r into delta[0 .. nn).
+template <class T>
+__device__ __forceinline__ void patch_small(const T *m, const int32_t *dofs, int nn, const T *r, T *delta) {
+    T rv[kSmallPatch];
+    gather_small(dofs, 1, nn, r, rv);
+    apply_small(m, nn, rv, delta, 1);
 }
 
 // Sum of the corrections of every subdomain holding DOF j, in entry order.

@@ -659,6 +659,229 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     for (int64_t i = 0; i < L.n_patch; ++i) L.col_list[fc[L.color[i]]++] = (int32_t)i;
 }
 
+
+// ------------------------------------------- potential form (2D, FP32 cycle)
+
+// derivative coefficients of the degree-q splines on N elements:
+// (N_a)' = c_a N^{q-1}_{a-1} - c_{a+1} N^{q-1}_a with c_a = q / (xi_{a+q} - xi_a)
+static std::vector<double> deriv_coef(int N, int q) {
+    const auto kn = open_knots(N, q);
+    std::vector<double> c(N + q, 0.0);
+    for (int j = 0; j < N + q; ++j) {
+        const double den = kn[j + q] - kn[j];
+        c[j] = den > 0 ? q / den : 0.0;
+    }
+    return c;
+}
+
+// Entries of the 2D curl u = (d_y psi, -d_x psi) in the velocity row g:
+// pairs (potential index, coefficient); potentials on the boundary are zero
+// and skipped.
+static void curl_row(const HostLevel &L, int k, const std::vector<double> &c, int64_t g,
+                     std::vector<std::pair<int, double>> &out) {
+    const int m = L.N + k - 1, nq = L.N + k;
+    out.clear();
+    auto add = [&](int pa, int pb, double v) {
+        if (pa >= 1 && pa <= m && pb >= 1 && pb <= m) out.push_back({(pa - 1) + m * (pb - 1), v});
+    };
+    if (g < L.off[1]) {  // u_x(a, j) stored at (a - 1) + m j
+        const int a = (int)(g % m) + 1, j = (int)(g / m);
+        add(a, j + 1, c[j + 1]);
+        add(a, j, -c[j + 1]);
+    } else {  // u_y(i, b) stored at off[1] + i + nq (b - 1)
+        const int64_t l = g - L.off[1];
+        const int i = (int)(l % nq), b = (int)(l / nq) + 1;
+        add(i + 1, b, -c[i + 1]);
+        add(i, b, c[i + 1]);
+    }
+}
+
+// Q = (C^T C)^{-1} C^T X for C (r x p, full column rank) and X (r x n),
+// row-major, result p x n
+static void left_solve(int r, int p, int n, const std::vector<double> &C, const double *X, std::vector<double> &Q) {
+    std::vector<double> G((size_t)p * p, 0.0), Gi;
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            double s = 0.0;
+            for (int t = 0; t < r; ++t) s += C[(size_t)t * p + a] * C[(size_t)t * p + b];
+            G[(size_t)a * p + b] = s;
+        }
+    invert(p, G, Gi);
+    std::vector<double> CtX((size_t)p * n, 0.0);
+    for (int a = 0; a < p; ++a)
+        for (int t = 0; t < r; ++t) {
+            const double ca = C[(size_t)t * p + a];
+            if (ca == 0.0) continue;
+            for (int j = 0; j < n; ++j) CtX[(size_t)a * n + j] += ca * X[(size_t)t * n + j];
+        }
+    Q.assign((size_t)p * n, 0.0);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            const double g = Gi[(size_t)a * p + b];
+            for (int j = 0; j < n; ++j) Q[(size_t)a * n + j] += g * CtX[(size_t)b * n + j];
+        }
+}
+
+static void build_potential_maps(const Problem &pb, HostLevel &L) {
+    const int k = pb.k, q = k + 1, N = L.N, m = N + k - 1;
+    L.n_psi = (int64_t)m * m;
+    const auto c = deriv_coef(N, q);
+    auto e0 = [&](int a) { return std::max(0, a - q); };
+    auto e1 = [&](int a) { return std::min(N - 1, a); };
+    L.qptr.assign(1, 0);
+    L.qpsi.clear();
+    L.qoff.clear();
+    L.Q.clear();
+    L.beta_row.clear();
+    L.beta_patch.clear();
+    std::vector<int> loc;
+    std::vector<double> C, Qi;
+    std::vector<std::pair<int, double>> row;
+    std::vector<std::vector<int32_t>> qbucket(1 << 16);
+    std::vector<std::pair<int64_t, int64_t>> qclass;  // (size, offset)
+    for (int64_t i = 0; i < L.n_patch; ++i) {
+        const int a0 = (int)(i % m) + 1, a1 = (int)(i / m) + 1;
+        loc.clear();
+        for (int b1 = std::max(1, a1 - q); b1 <= std::min(m, a1 + q); ++b1) {
+            if (e0(b1) < e0(a1) || e1(b1) > e1(a1)) continue;
+            for (int b0 = std::max(1, a0 - q); b0 <= std::min(m, a0 + q); ++b0) {
+                if (e0(b0) < e0(a0) || e1(b0) > e1(a0)) continue;
+                loc.push_back((b0 - 1) + m * (b1 - 1));
+            }
+        }
+        const int np = (int)loc.size(), n = L.pptr[i + 1] - L.pptr[i];
+        const int32_t *dofs = &L.pdofs[L.pptr[i]];
+        int nv = 0;
+        while (nv < n && dofs[nv] < L.n_v) ++nv;
+        C.assign((size_t)nv * np, 0.0);
+        for (int r = 0; r < nv; ++r) {
+            curl_row(L, k, c, dofs[r], row);
+            for (auto &e : row) {
+                const auto it = std::find(loc.begin(), loc.end(), e.first);
+                if (it != loc.end()) C[(size_t)r * np + (it - loc.begin())] += e.second;
+            }
+        }
+        left_solve(nv, np, n, C, &L.M[L.moff[i]], Qi);
+        // subdomains with equal maps (translates with a shared inverse) share
+        // one stored copy
+        double scale = 0.0;
+        for (double x : Qi) scale = std::max(scale, std::fabs(x));
+        uint64_t hsh = (uint64_t)(np * 64 + n) * 1469598103934665603ull;
+        for (double x : Qi)
+            hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / (scale > 0 ? scale : 1.0) * 4096.0)) * 1099511628211ull;
+        int32_t off = -1;
+        for (int32_t cand : qbucket[hsh & 0xffff]) {
+            const auto &ci = qclass[cand];
+            if (ci.first != (int64_t)Qi.size()) continue;
+            double dmax = 0.0;
+            for (size_t t = 0; t < Qi.size(); ++t) dmax = std::max(dmax, std::fabs(Qi[t] - L.Q[ci.second + t]));
+            if (dmax <= 1e-14 * scale) {
+                off = (int32_t)ci.second;
+                break;
+            }
+        }
+        if (off < 0) {
+            off = (int32_t)L.Q.size();
+            qbucket[hsh & 0xffff].push_back((int32_t)qclass.size());
+            qclass.push_back({(int64_t)Qi.size(), (int64_t)off});
+            L.Q.insert(L.Q.end(), Qi.begin(), Qi.end());
+            if (L.Q.size() > (size_t)INT32_MAX) throw std::runtime_error("potential map store exceeds 2^31 entries");
+        }
+        L.qoff.push_back(off);
+        for (int a = 0; a < np; ++a) {
+            L.beta_row.push_back((int32_t)(off + (size_t)a * n));
+            L.beta_patch.push_back((int32_t)i);
+        }
+        L.qpsi.insert(L.qpsi.end(), loc.begin(), loc.end());
+        L.qptr.push_back((int32_t)L.qpsi.size());
+    }
+    // for each potential the beta entries landing on it, subdomain ascending
+    L.qinv_ptr.assign(L.n_psi + 1, 0);
+    for (int32_t b : L.qpsi) L.qinv_ptr[b + 1]++;
+    for (int64_t b = 0; b < L.n_psi; ++b) L.qinv_ptr[b + 1] += L.qinv_ptr[b];
+    L.qinv_pos.assign(L.qpsi.size(), 0);
+    std::vector<int32_t> fp(L.qinv_ptr.begin(), L.qinv_ptr.end() - 1);
+    for (int64_t e = 0; e < (int64_t)L.qpsi.size(); ++e) L.qinv_pos[fp[L.qpsi[e]]++] = (int32_t)e;
+    // one thread per small subdomain computes its single beta entry; every
+    // other subdomain's entries go one per thread
+    std::vector<int32_t> small;
+    L.big_beta.clear();
+    std::vector<char> is_small(L.n_patch, 0);
+    for (int32_t p : L.small_list) {
+        if (L.qptr[p + 1] - L.qptr[p] == 1) {
+            small.push_back(p);
+            is_small[p] = 1;
+        } else {
+            for (int32_t t = L.pptr[p]; t < L.pptr[p + 1]; ++t) L.big_ent.push_back(t);
+        }
+    }
+    L.small_list = small;
+    std::sort(L.big_ent.begin(), L.big_ent.end());
+    for (int64_t i = 0; i < L.n_patch; ++i)
+        if (!is_small[i])
+            for (int32_t e = L.qptr[i]; e < L.qptr[i + 1]; ++e) L.big_beta.push_back(e);
+}
+
+// potential prolongation: Kronecker product of the 1D refinement of the
+// degree-(k+1) splines without their end functions
+static void build_potential_prolongation(const Problem &pb, const HostLevel &C, HostLevel &F) {
+    const int k = pb.k;
+    const Mat1 T = refinement_matrix(C.N, k + 1);
+    const int mc = C.N + k - 1, mf = F.N + k - 1;
+    std::vector<std::vector<std::pair<int, double>>> list(mf);
+    for (int is = 0; is < mf; ++is)
+        for (int jc = 0; jc < mc; ++jc) {
+            const double v = T(jc + 1, is + 1);
+            if (v != 0.0) list[is].push_back({jc, v});
+        }
+    F.Ps_rp.assign(1, 0);
+    F.Ps_ci.clear();
+    F.Ps_v.clear();
+    for (int i1 = 0; i1 < mf; ++i1)
+        for (int i0 = 0; i0 < mf; ++i0) {
+            for (auto &y : list[i1])
+                for (auto &x : list[i0]) {
+                    F.Ps_ci.push_back((int32_t)(x.first + (int64_t)mc * y.first));
+                    F.Ps_v.push_back(x.second * y.second);
+                }
+            F.Ps_rp.push_back((int32_t)F.Ps_ci.size());
+        }
+}
+
+// coarse level: Q0 = (C^T C)^{-1} C^T Kinv[velocity rows]
+static void build_coarse_potentials(const Problem &pb, HostLevel &L) {
+    const int k = pb.k, m = L.N + k - 1;
+    L.n_psi = (int64_t)m * m;
+    const auto c = deriv_coef(L.N, k + 1);
+    const int nv = (int)L.n_v, np = (int)L.n_psi, n = (int)L.n;
+    std::vector<double> C((size_t)nv * np, 0.0);
+    std::vector<std::pair<int, double>> row;
+    for (int r = 0; r < nv; ++r) {
+        curl_row(L, k, c, r, row);
+        for (auto &e : row) C[(size_t)r * np + e.first] += e.second;
+    }
+    left_solve(nv, np, n, C, L.Kinv.data(), L.Q0);
+}
+
+// layout of smoother form 4 (see HostLevel), after the small list is final
+static void finalize_small(HostLevel &L) {
+    const int64_t ns = (int64_t)L.small_list.size();
+    L.small_dofs.assign((size_t)kSmallPatch * ns, 0);
+    std::vector<int64_t> pos(L.pdofs.size(), -1);
+    for (int64_t q = 0; q < ns; ++q) {
+        const int32_t p = L.small_list[q], base = L.pptr[p], nn = L.pptr[p + 1] - base;
+        for (int c = 0; c < kSmallPatch; ++c) L.small_dofs[(size_t)c * ns + q] = L.pdofs[base + std::min(c, nn - 1)];
+        for (int m = 0; m < nn; ++m) pos[base + m] = m * ns + q;
+    }
+    L.inv_pos4.resize(L.inv_pos.size());
+    for (size_t e = 0; e < L.inv_pos.size(); ++e) {
+        const int32_t t = L.inv_pos[e];
+        const int64_t v = pos[t] >= 0 ? pos[t] : kSmallPatch * ns + t;
+        if (v > INT32_MAX) throw std::runtime_error("correction buffer exceeds 2^31 entries");
+        L.inv_pos4[e] = (int32_t)v;
+    }
+}
+
 // -------------------------------------------------------------- prolongation
 
 static void build_prolongation(const Problem &pb, const HostLevel &C, HostLevel &F) {
@@ -762,6 +985,15 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         C.Kinv.assign((size_t)n * n, 0.0);
         bordered_inverse(pb, C, all.data(), n, C.Kinv.data());
     }
+    if (pb.potentials) {
+        if (pb.d != 2) throw std::runtime_error("the potential form is implemented for dim 2");
+        build_coarse_potentials(pb, H.lv[0]);
+        for (int l = 1; l < L; ++l) {
+            build_potential_maps(pb, H.lv[l]);
+            build_potential_prolongation(pb, H.lv[l - 1], H.lv[l]);
+        }
+    }
+    for (int l = 1; l < L; ++l) finalize_small(H.lv[l]);
     // divergence norm data (finest grid)
     {
         const int k = pb.k, q = k + 1;

@@ -59,6 +59,7 @@ struct Problem {
     int adv_kind = 0;
     double adv_c = 0.0;
     bool share_inverses = true;
+    bool potentials = false;   // build the potential-form maps of the FP32 cycle (2D)
 };
 
 struct HostLevel {
@@ -92,6 +93,30 @@ struct HostLevel {
     std::vector<int32_t> col_ptr, col_list;
     // subdomains with <= kSmallPatch DOFs, and the entries of the others
     std::vector<int32_t> small_list, big_ent;
+    // smoother form 4 keeps the corrections of small subdomain q, row m at
+    // m * n_small + q (coalesced stores) and those of the other entries e at
+    // kSmallPatch * n_small + e; small_dofs[c * n_small + q] is DOF c of small
+    // subdomain q (kSmallPatch per subdomain, padded by repetition), and
+    // inv_pos4 relabels inv_pos in that layout (same order).
+    std::vector<int32_t> small_dofs, inv_pos4;
+    // potential form of the FP32 cycle (2D): the streamfunction coefficient
+    // (a, b), a, b in [1, N+k-1], is stored at (a-1) + (N+k-1)(b-1), the same
+    // index as the subdomain that is its support.  Per subdomain i: its local
+    // potentials qpsi[qptr[i] .. qptr[i+1]) (supports inside the subdomain)
+    // and Q_i (row-major n_psi_i x n_i at qoff[i]), the left inverse of the
+    // local curl applied to the velocity rows of M_i, so that Q_i E_i r are
+    // the potential coefficients of the local velocity correction.
+    int64_t n_psi = 0;
+    std::vector<int32_t> qptr, qpsi, qoff, qinv_ptr, qinv_pos;
+    std::vector<double> Q;
+    std::vector<int32_t> big_beta;          // beta entries of subdomains outside small_list
+    std::vector<int32_t> beta_row, beta_patch;  // per beta entry: Q row offset, subdomain
+    // potential prolongation from level - 1 (rows: this level)
+    std::vector<int32_t> Ps_rp, Ps_ci;
+    std::vector<double> Ps_v;
+    // coarse level: potential coefficients of the coarse velocity solution,
+    // n_psi x n row-major
+    std::vector<double> Q0;
     int max_patch = 0;
     // prolongation from level-1 (CSR, rows = this level) and restriction
     std::vector<int32_t> P_rp, P_ci, R_rp, R_ci;

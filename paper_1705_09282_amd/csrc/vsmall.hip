@@ -33,7 +33,7 @@ __device__ void small_residual(const SmallLevel<T> &L, int prob, const T *F, con
 // U = (assign ? 0 : U) + eta * sum_i E_i^T M_i E_i src, two passes
 template <class T>
 __device__ void small_smooth(const SmallLevel<T> &L, int prob, const T *src, T *U, bool assign) {
-    T *delta = L.delta + prob * L.nent;
+    T *delta = L.delta + prob * L.sdelta;
     const T *M = L.M + prob * L.sM;
     for (int q = threadIdx.x; q < L.nsmall; q += blockDim.x) {
         const int p = L.small[q];

@@ -127,15 +127,16 @@ def test_kernel_variants_match_oracle(d, N, k, L, lpr, sm):
     s.close()
 
 
-@pytest.mark.parametrize("d,N,k,L,precision", [(2, 32, 2, 4, 0), (3, 8, 1, 3, 0), (2, 32, 1, 4, 1),
-                                               (2, 32, 2, 4, 1)])
+@pytest.mark.parametrize("d,N,k,L,precision", [(2, 32, 2, 4, 0), (3, 8, 1, 3, 0), (2, 32, 1, 4, 0), (2, 32, 2, 4, 1),
+                                               (2, 64, 1, 5, 1)])
 def test_smoother_forms_agree_bitwise(d, N, k, L, precision):
     """The one-pass smoother and the small-subdomain form sum every
     local-solve row and the rows of a DOF in the two-pass order, so whole
-    solves agree bit for bit."""
+    solves agree bit for bit (with precision 1 also the tracked potentials:
+    the FP32 cycle runs form 3 or 4)."""
     from paper_1705_09282_amd.dfmg import Solver
     out = []
-    for sm in (1, 3, 4):
+    for sm in ((1, 3, 4) if precision == 0 else (3, 4)):
         s = Solver(d, N, L, k, nu=0.5, sigma=4.0, c=0.0, precision=precision).bind()
         s.set_tuning([1] * L, [sm] * L)
         F = dev(s.manufactured_rhs())
@@ -147,8 +148,7 @@ def test_smoother_forms_agree_bitwise(d, N, k, L, precision):
         assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
 
 
-@pytest.mark.parametrize("d,N,k,L,precision", [(2, 64, 2, 5, 0), (2, 64, 1, 5, 1), (3, 16, 1, 4, 0),
-                                               (2, 32, 2, 5, 1)])
+@pytest.mark.parametrize("d,N,k,L,precision", [(2, 64, 2, 5, 0), (2, 64, 1, 5, 0), (3, 16, 1, 4, 0)])
 def test_single_workgroup_coarse_cycle_is_bitwise_equal(d, N, k, L, precision):
     """Levels 1 .. t in one single-workgroup launch compute the same sums as
     the per-level kernels with one lane per row: every choice of t gives the

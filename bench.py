@@ -6,10 +6,11 @@ pressure degree k=2 (velocity S^{3,2} x S^{2,3}), 256x256 elements, 6 grids
 (256 .. 8), nu = 1, sigma in {1e-2, 1, 1e2, 1e4}, load vector of the
 manufactured solution u = curl(sin^2(pi x) sin^2(pi y)), p = sin(2 pi x)
 sin(2 pi y).  One step solves all four problems from U = 0 to relative
-residual 1e-8 with V(2,2) cycles; inputs are resident in HBM before timing.
-The timed path is the learned per-level damping with FP32 V-cycles inside FP64
-iterative refinement; the plain FP64 solver (fixed damping) and FP32
-refinement with the fixed damping are timed beside it on the same problems.
+residual 1e-8; inputs are resident in HBM before timing.  The timed path is
+the learned per-level damping and smoothing steps with FP32 V-cycles inside
+FP64 iterative refinement; the plain FP64 solver (fixed damping, V(2,2)) and
+FP32 refinement with the fixed damping and V(2,2) are timed beside it on the
+same problems.
 
 Prints one JSON line: metric, value (DOF/s over the whole step, DOFs =
 dim V_h + dim Q_h), roofline of the dominant kernel (finest-grid residual
@@ -216,10 +217,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
-                        f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, V(2,2) additive Schwarz, "
+                        f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, additive Schwarz V-cycles, "
                         f"tol {args.tol:g}, U0=0",
-            "path": "batched: learned per-level damping, FP32 V-cycles in FP64 iterative refinement, "
-                    "4 problems per launch",
+            "path": "batched: learned per-level damping and smoothing steps, FP32 V-cycles in FP64 iterative "
+                    "refinement, 4 problems per launch (plain_fp64: fixed damping, V(2,2))",
+            "steps_per_level_finest_first": b32.get_smoothing()[0],
             "eta_per_sigma": [[round(x, 4) for x in row] for row in b32.get_eta().tolist()],
             "fallback_per_sigma": [st["fallback"] for st in stats],
             "dofs_per_step": dofs,

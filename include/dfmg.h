@@ -152,6 +152,13 @@ int dfmg_set_eta(dfmg_ctx *ctx, const double *eta_host, int n);
  * Stream-ordered, no host synchronization.  Errors: ESTATE, EINVAL, EHIP. */
 int dfmg_vcycle(dfmg_ctx *ctx, const double *F_dev, double *U_dev, int ncycles);
 
+/* Per-level smoothing steps of Algorithm 1 (nu1 before, nu2 after the coarse
+ * correction), n = n_levels - 1 entries each, finest level first, in [0, 16],
+ * for every problem of the batch (they share the launch sequence).  Default:
+ * the options' nu1, nu2 on every level.  Errors: EINVAL. */
+int dfmg_set_smoothing(dfmg_ctx *ctx, const int *nu1_host, const int *nu2_host, int n);
+int dfmg_get_smoothing(const dfmg_ctx *ctx, int *nu1_host, int *nu2_host);
+
 /* Repeat V-cycles from U (device, in/out) until ||F - K U||_2 <= tol ||F||_2
  * (numerical-results protocol, relative to ||F||), then shift the pressure to
  * zero mean.  st may be NULL (else nprob entries).  Errors: ENOTCONV,
@@ -222,34 +229,39 @@ int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
  * state unchanged. */
 int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
 
-/* ---- Learned per-level damping ----
- * A perceptron predicts the damping eta in (0, 1) of equation ASM for every
- * smoothed level: x = (log10(nu)/2, log10(sigma)/4, |a| h / nu, k - 1.5) with
- * |a| = max|a| and h = 1/n_elem; h1 = tanh(W1 x + b1) (32), h2 = tanh(W2 h1 +
- * b2) (32), z = W3 h2 + b3 (5 logits, finest smoothed level first; deeper
- * hierarchies reuse the last), eta = 1 / (1 + exp(-z)).  Parameters are FP32,
- * packed [W1 (32x4 row-major), b1, W2 (32x32), b2, W3 (5x32), b3].
+/* ---- Learned per-level smoothing parameters ----
+ * A perceptron predicts, for every smoothed level, the damping eta in (0, 1)
+ * of equation ASM and the number of smoothing steps of Algorithm 1:
+ * x = (log10(nu)/2, log10(sigma)/4, |a| h / nu, k - 1.5) with |a| = max|a|
+ * and h = 1/n_elem; h1 = tanh(W1 x + b1) (32), h2 = tanh(W2 h1 + b2) (32),
+ * z = W3 h2 + b3 (10 outputs); eta_l = 1 / (1 + exp(-z_l)) from outputs 0..4
+ * and steps_l = clamp(round(z_{5+l}), 1, 8) from outputs 5..9, finest
+ * smoothed level first (deeper hierarchies reuse the last).  Parameters are
+ * FP32, packed [W1 (32x4 row-major), b1, W2 (32x32), b2, W3 (10x32), b3].
  * The three kernels below take device arrays and a HIP stream (NULL =
  * default) and do not synchronize. */
-#define DFMG_MLP_NPARAM 1381
-/* Z (n x 5) = logits of the features X (n x 4). */
+#define DFMG_MLP_NPARAM 1546
+/* Z (n x 10) = outputs for the features X (n x 4). */
 int dfmg_mlp_forward(int n, const float *W_dev, const float *X_dev, float *Z_dev, void *stream);
 /* G = gradient and *loss_dev = value of scale * sum M (Z - Y)^2 over the n
- * samples (Y, M: n x 5 targets and 0/1 mask); work_dev holds
+ * samples (Y, M: n x 10 targets and weights); work_dev holds
  * n * (DFMG_MLP_NPARAM + 1) floats.  Fixed summation order (deterministic). */
 int dfmg_mlp_grad(int n, const float *W_dev, const float *X_dev, const float *Y_dev, const float *M_dev,
                   float scale, float *work_dev, float *G_dev, float *loss_dev, void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, t >= 1). */
 int dfmg_mlp_adam(float *W_dev, float *m_dev, float *v_dev, const float *G_dev, int t, float lr, void *stream);
 /* Use the network W_host for the dampings of every problem of ctx (computed
- * on the device from each problem's nu, sigma, advection, grid and k).  With
- * rho_plain_host (nprob entries, nullable) a solve switches a problem back to
- * the fixed damping as soon as one V-cycle after the first contracts its
- * residual by more than 1.05 * rho_plain (a single-cycle ratio of the fixed
- * damping), or any cycle lets it grow by six orders, and reports it in
- * stats.fallback.  The switch happens once per solve; the next solve starts
- * from the learned dampings again.
- * W_host NULL restores the fixed damping.  Requires dfmg_bind. */
+ * on the device from each problem's nu, sigma, advection, grid and k) and for
+ * the batch's smoothing steps per level (the largest prediction over its
+ * problems, pre = post; they share one launch sequence), replacing
+ * dfmg_set_smoothing.  With rho_plain_host (nprob entries, nullable) a solve
+ * switches a problem back to the fixed damping as soon as one V-cycle after
+ * the first contracts its residual by more than 1.05 * rho_plain (a
+ * single-cycle ratio of the fixed damping), or any cycle lets it grow by six
+ * orders, and reports it in stats.fallback.  The switch happens once per
+ * solve; the next solve starts from the learned dampings again; the steps stay.
+ * W_host NULL restores the fixed damping and the options' steps.  Requires
+ * dfmg_bind. */
 int dfmg_set_learned(dfmg_ctx *ctx, const float *W_host, const double *rho_plain_host);
 /* Current dampings, nprob * (n_levels - 1) values, finest level first. */
 int dfmg_get_eta(dfmg_ctx *ctx, double *eta_host);

@@ -1,21 +1,26 @@
-"""FP64 reference of the learned-damping network (oracle, test infrastructure).
+"""FP64 reference of the learned smoothing-parameter network (oracle, test
+infrastructure).
 
 The damping eta of the additive Schwarz smoother (equation ASM, eta in (0,1))
-is predicted per smoothed level by a small multilayer perceptron:
+and the number of smoothing steps of Algorithm 1 are predicted per smoothed
+level by a small multilayer perceptron:
 
     x = (log10(nu) / 2, log10(sigma) / 4, |a| h / nu, k - 1.5)
     h1 = tanh(W1 x + b1)          (32)
     h2 = tanh(W2 h1 + b2)         (32)
-    z  = W3 h2 + b3               (5 logits, finest level first)
-    eta_l = 1 / (1 + exp(-z_l))
+    z  = W3 h2 + b3               (10 outputs)
+    eta_l = 1 / (1 + exp(-z_l))              outputs 0..4, finest level first
+    steps_l = clamp(round(z_{5+l}), 1, 8)    outputs 5..9, finest level first
 
-Training loss: mean over the valid (sample, level) pairs of (z - y)^2 with y
-the logit of the best damping found by the sweep.  Parameters are packed as
-[W1 (32x4, row-major), b1, W2 (32x32), b2, W3 (5x32), b3].
+Training loss: masked mean squared error (weights M) of the outputs against
+the sweep's targets (logits of the best dampings, best step counts).
+Parameters are packed as [W1 (32x4, row-major), b1, W2 (32x32), b2,
+W3 (10x32), b3].
 """
 import numpy as np
 
-NIN, H, NOUT = 4, 32, 5
+NIN, H, NOUT = 4, 32, 10
+NETA = 5          # damping outputs; the step-count outputs follow
 SHAPES = [("W1", (H, NIN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (NOUT, H)), ("b3", (NOUT,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
 
@@ -42,8 +47,14 @@ def forward(theta, X):
     return h2 @ p["W3"].T + p["b3"]
 
 
+def steps(z):
+    """Smoothing steps from the count outputs (round half away from zero,
+    clamped to [1, 8])."""
+    return np.clip(np.sign(z) * np.floor(np.abs(z) + 0.5), 1, 8).astype(int)
+
+
 def loss(theta, X, Y, M):
-    """Masked mean squared error of the logits."""
+    """Masked mean squared error of the outputs."""
     Z = forward(theta, X)
     return float(np.sum(M * (Z - Y) ** 2) / np.sum(M))
 

@@ -86,19 +86,22 @@ def smooth(level, U, F, eta):
 
 
 def mgv(h, l, U, F, nu1, nu2, eta):
-    """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l.
+    """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l, nu1 and
+    nu2 the smoothing steps (a number, or one per level indexed by level).
     Returns the updated U (the paper updates U in place)."""
     lv = h.levels[l]
     if l == 0:
         return lv.coarse_inv @ F
-    for _ in range(nu1):
+    n1 = nu1 if np.isscalar(nu1) else nu1[l]
+    n2 = nu2 if np.isscalar(nu2) else nu2[l]
+    for _ in range(n1):
         U = smooth(lv, U, F, eta[l])
     P = h.levels[l - 1].P
     G = P.T @ (F - lv.K @ U)
     dU = np.zeros(h.levels[l - 1].disc.n)
     dU = mgv(h, l - 1, dU, G, nu1, nu2, eta)
     U = U + P @ dU
-    for _ in range(nu2):
+    for _ in range(n2):
         U = smooth(lv, U, F, eta[l])
     return U
 
@@ -133,10 +136,24 @@ def eta_levels(h, eta):
     return out
 
 
+def steps_levels(h, nu):
+    """Smoothing steps indexed by level from a number or a finest-first list
+    (one per smoothed level)."""
+    if np.isscalar(nu):
+        return nu
+    nu = list(nu)
+    assert len(nu) == h.L - 1, "one step count per smoothed level, finest first"
+    out = [0] * h.L
+    for i, s in enumerate(nu):
+        out[h.L - 1 - i] = int(s)
+    return out
+
+
 def vcycles(h, U, F, m, nu1=2, nu2=2, eta=None):
     et = eta_levels(h, eta)
+    n1, n2 = steps_levels(h, nu1), steps_levels(h, nu2)
     for _ in range(m):
-        U = mgv(h, h.L - 1, U, F, nu1, nu2, et)
+        U = mgv(h, h.L - 1, U, F, n1, n2, et)
     return U
 
 
@@ -159,11 +176,12 @@ def solve(h, F, tol=1e-8, U0=None, nu1=2, nu2=2, eta=None, max_cycles=200):
     included), then normalize the pressure.  Returns (U, history)."""
     U = np.zeros_like(F) if U0 is None else U0.copy()
     et = eta_levels(h, eta)
+    n1, n2 = steps_levels(h, nu1), steps_levels(h, nu2)
     fn = np.linalg.norm(F)
     hist = [residual_norm(h, U, F)]
     cycles = 0
     while hist[-1] > tol * fn and cycles < max_cycles:
-        U = mgv(h, h.L - 1, U, F, nu1, nu2, et)
+        U = mgv(h, h.L - 1, U, F, n1, n2, et)
         cycles += 1
         hist.append(residual_norm(h, U, F))
     return normalize_pressure(h, U), np.array(hist)

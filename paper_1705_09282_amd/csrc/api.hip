@@ -127,6 +127,7 @@ struct dfmg_ctx {
     SmallLevel<double> *small_d = nullptr;  // device level tables of that cycle
     SmallLevel<float> *small_f = nullptr;
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
+    std::vector<int> nu1l, nu2l; // per level: pre- and post-smoothing steps
     std::vector<double> eta_host;  // [problem][level]
     const Hierarchy &S() const { return P[0]; }
     int L() const { return P[0].pb.L; }
@@ -446,6 +447,8 @@ std::vector<SmallLevel<T>> small_levels(dfmg_ctx *c) {
         q.U = d.U;
         q.r = d.r;
         q.n = h.n;
+        q.nu1 = c->nu1l[l];
+        q.nu2 = c->nu2l[l];
         if (l == 0) {
             q.Kinv = v.Kinv;
             continue;
@@ -478,13 +481,25 @@ std::vector<SmallLevel<T>> small_levels(dfmg_ctx *c) {
     return out;
 }
 
+// (re)load the level tables of the single-workgroup coarse cycle
+void upload_small_tables(dfmg_ctx *c) {
+    auto td = small_levels<double>(c);
+    up(c->small_d, td, c->s);
+    HIPCHK(hipStreamSynchronize(c->s));
+    if (c->mixed()) {
+        auto tf = small_levels<float>(c);
+        up(c->small_f, tf, c->s);
+        HIPCHK(hipStreamSynchronize(c->s));
+    }
+}
+
 // One V-cycle (Algorithm 1) on the finest level's internal U, F of type T.
 // norm: the first residual of the finest level also feeds the convergence
 // check.  fine_zero: the finest U is known to be zero (its first smoothing
 // step then needs no residual).
 template <class T>
 void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
-    const int L = c->L(), nu1 = c->opt.nu1, nu2 = c->opt.nu2;
+    const int L = c->L();
     const int *stop = c->stop;
     if (L == 1) {
         LevelData<T> &v = c->dl[0].data<T>();
@@ -499,7 +514,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         const HostLevel &h = c->S().lv[l];
         bool zero = (l < L - 1) || fine_zero;
         bool first_res = (l == L - 1) && norm;
-        for (int s = 0; s < nu1; ++s) {
+        for (int s = 0; s < c->nu1l[l]; ++s) {
             if (zero && !first_res) {
                 schwarz<T>(c, l, v.F, v.U, true, stop);  // U = 0: residual is F
                 zero = false;
@@ -524,7 +539,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         }
     }
     if (top >= 1)
-        launch_vcycle_small<T>(c->S().pb.d, c->S().pb.k, small_table<T>(c), top, nu1, nu2, stop, c->np, c->s);
+        launch_vcycle_small<T>(c->S().pb.d, c->S().pb.k, small_table<T>(c), top, stop, c->np, c->s);
     else
         coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
     if (psi) {  // potentials of the coarse velocity solution
@@ -539,7 +554,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
             const DevLevel &q = c->dl[l - 1];
             launch_csr<double>((int)f.npsi, f.Ps_rp, f.Ps_ci, f.Ps_v, q.psi, q.npsi, f.psi, f.npsi, 1, stop, c->np, c->s);
         }
-        for (int s = 0; s < nu2; ++s) {
+        for (int s = 0; s < c->nu2l[l]; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
             schwarz<T>(c, l, v.r, v.U, false, stop);
         }
@@ -682,6 +697,8 @@ void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
         c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
     }
     c->small_top = 0;
+    c->nu1l.assign(L, o.nu1);
+    c->nu2l.assign(L, o.nu2);
 }
 
 
@@ -1062,16 +1079,7 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         HIPCHK(hipHostMalloc((void **)&c->hflags, 4 * np * sizeof(int), hipHostMallocDefault));
         std::memset(c->hflags, 0, 4 * np * sizeof(int));
         for (auto &e : c->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        {
-            auto td = small_levels<double>(c);
-            up(c->small_d, td, s);
-            HIPCHK(hipStreamSynchronize(s));
-            if (c->mixed()) {
-                auto tf = small_levels<float>(c);
-                up(c->small_f, tf, s);
-                HIPCHK(hipStreamSynchronize(s));
-            }
-        }
+        upload_small_tables(c);
         HIPCHK(hipStreamSynchronize(s));
         c->bound = true;
     });
@@ -1116,6 +1124,37 @@ int dfmg_set_eta(dfmg_ctx *c, const double *eta, int n) {
             leave(c);
         }
     });
+}
+
+int dfmg_set_smoothing(dfmg_ctx *c, const int *nu1, const int *nu2, int n) {
+    if (!c || !nu1 || !nu2) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        const int L = c->L();
+        if (n != L - 1) throw ArgError("need n_levels - 1 smoothing counts");
+        for (int i = 0; i < n; ++i)
+            if (nu1[i] < 0 || nu1[i] > 16 || nu2[i] < 0 || nu2[i] > 16)
+                throw ArgError("smoothing counts must lie in [0, 16]");
+        for (int i = 0; i < n; ++i) {
+            c->nu1l[L - 1 - i] = nu1[i];
+            c->nu2l[L - 1 - i] = nu2[i];
+        }
+        drop_graph(c);
+        if (c->bound) {
+            enter(c);
+            upload_small_tables(c);
+            leave(c);
+        }
+    });
+}
+
+int dfmg_get_smoothing(const dfmg_ctx *c, int *nu1, int *nu2) {
+    if (!c || !nu1 || !nu2) return fail(DFMG_EINVAL, "null argument");
+    const int L = c->L();
+    for (int i = 0; i < L - 1; ++i) {
+        nu1[i] = c->nu1l[L - 1 - i];
+        nu2[i] = c->nu2l[L - 1 - i];
+    }
+    return DFMG_OK;
 }
 
 int dfmg_vcycle(dfmg_ctx *c, const double *F, double *U, int ncycles) {
@@ -1433,6 +1472,10 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
             c->learned = false;
             clear_fallback(c);
             upload_eta(c);
+            c->nu1l.assign(c->L(), c->opt.nu1);
+            c->nu2l.assign(c->L(), c->opt.nu2);
+            drop_graph(c);
+            upload_small_tables(c);
             leave(c);
             return;
         }
@@ -1445,6 +1488,21 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
             feat[p * MLP_IN + 2] = (float)(amag / (pb.N * pb.nu));
             feat[p * MLP_IN + 3] = (float)(pb.k - 1.5);
         }
+        // smoothing steps: the network's count outputs, the largest over the
+        // batch (its problems share one launch sequence)
+        const int L = c->L();
+        std::vector<int> steps(L - 1, 1);
+        for (int p = 0; p < c->np; ++p) {
+            double z[MLP_OUT];
+            mlp_forward_host(W, &feat[(size_t)p * MLP_IN], z);
+            for (int i = 0; i < L - 1; ++i) {
+                const long v = std::lround(z[MLP_ETA + std::min(i, MLP_OUT - MLP_ETA - 1)]);
+                steps[i] = std::max(steps[i], (int)std::min(8L, std::max(1L, v)));
+            }
+        }
+        for (int i = 0; i < L - 1; ++i) c->nu1l[L - 1 - i] = c->nu2l[L - 1 - i] = steps[i];
+        drop_graph(c);
+        upload_small_tables(c);
         up(c->mlpW, W, MLP_NPARAM, c->s);
         up(c->feat, feat, c->s);
         if (rho) up(c->rho_plain, rho, c->np, c->s);

@@ -106,16 +106,17 @@ struct SmallLevel {
     const int32_t *P_rp, *P_ci; // prolongation from level l-1 (rows of level l)
     const T *P_v;
     const double *Kinv;         // level 0: dense inverse, stride n * n
+    int nu1, nu2;               // smoothing steps of this level
 };
 
 // A V-cycle over levels top .. 0 of every problem by one workgroup each
 // (levels small enough that launches, not bandwidth, would set the time):
-// starts from U_top = 0 on F_top, nu1 / nu2 smoothing steps, exact coarse
-// solve; the same sums as the per-level kernels.  lv: device array of
-// top + 1 levels.
+// starts from U_top = 0 on F_top, each level's nu1 / nu2 smoothing steps,
+// exact coarse solve; the same sums as the per-level kernels.  lv: device
+// array of top + 1 levels.
 template <class T>
-void launch_vcycle_small(int d, int k, const SmallLevel<T> *lv, int top, int nu1, int nu2, const int *stop,
-                         int nprob, hipStream_t s);
+void launch_vcycle_small(int d, int k, const SmallLevel<T> *lv, int top, const int *stop, int nprob,
+                         hipStream_t s);
 
 // blocks of the residual kernel with lpr lanes per row
 inline int spmv_blocks(int64_t n, int lpr) { return (int)((n * lpr + 255) / 256); }

@@ -1,9 +1,13 @@
-// Learned per-level damping: a 4 -> 32 -> 32 -> 5 perceptron (tanh hidden
-// layers, FP32) maps problem features to logits of the additive-Schwarz
-// damping eta in (0, 1) of equation ASM, one per smoothed level, finest first.
-// Forward, loss gradient and Adam run on the device; the damping kernel
-// writes eta straight into a solver's per-problem damping array.
+// Learned per-level smoothing parameters: a 4 -> 32 -> 32 -> 10 perceptron
+// (tanh hidden layers, FP32) maps problem features to logits of the
+// additive-Schwarz damping eta in (0, 1) of equation ASM (outputs 0..4) and
+// to the number of smoothing steps (outputs 5..9), one per smoothed level,
+// finest first.  Forward, loss gradient and Adam run on the device; the
+// damping kernel writes eta straight into a solver's per-problem damping
+// array.
 #include "mlp.hpp"
+
+#include <cmath>
 
 #include "device_util.hpp"
 
@@ -115,12 +119,31 @@ __global__ void k_mlp_damping(int np, const float *W, const float *feat, int L, 
     float h1[MLP_H], h2[MLP_H], z[MLP_OUT];
     forward(W, feat + p * MLP_IN, h1, h2, z);
     for (int l = L - 1; l >= 1; --l) {
-        const int o = min(L - 1 - l, MLP_OUT - 1);
+        const int o = min(L - 1 - l, MLP_ETA - 1);
         eta[(int64_t)p * L + l] = 1.0 / (1.0 + exp(-(double)z[o]));
     }
 }
 
 }  // namespace
+
+void mlp_forward_host(const float *W, const float *x, double *z) {
+    double h1[MLP_H], h2[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+        double s = W[ob1 + i];
+        for (int c = 0; c < MLP_IN; ++c) s += (double)W[oW1 + i * MLP_IN + c] * x[c];
+        h1[i] = std::tanh(s);
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = W[ob2 + j];
+        for (int i = 0; i < MLP_H; ++i) s += (double)W[oW2 + j * MLP_H + i] * h1[i];
+        h2[j] = std::tanh(s);
+    }
+    for (int o = 0; o < MLP_OUT; ++o) {
+        double s = W[ob3 + o];
+        for (int j = 0; j < MLP_H; ++j) s += (double)W[oW3 + o * MLP_H + j] * h2[j];
+        z[o] = s;
+    }
+}
 
 void launch_mlp_forward(int n, const float *W, const float *X, float *Z, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_mlp_forward, dim3((n + 63) / 64), dim3(64), 0, s, n, W, X, Z);

@@ -56,13 +56,14 @@ __device__ void small_smooth(const SmallLevel<T> &L, int prob, const T *src, T *
 }
 
 template <int D, int K, class T>
-__global__ __launch_bounds__(kSmallBlock) void k_vcycle_small(const SmallLevel<T> *__restrict__ lv, int top, int nu1,
-                                                              int nu2, const int *stop) {
+__global__ __launch_bounds__(kSmallBlock) void k_vcycle_small(const SmallLevel<T> *__restrict__ lv, int top,
+                                                              const int *stop) {
     const int prob = blockIdx.x;
     if (stop && stop[prob]) return;
     for (int l = top; l >= 1; --l) {
         const SmallLevel<T> &L = lv[l];
         T *F = L.F + prob * L.n, *U = L.U + prob * L.n, *r = L.r + prob * L.n;
+        const int nu1 = L.nu1;
         for (int s = 0; s < nu1; ++s) {
             if (s == 0) {
                 small_smooth(L, prob, F, U, true);  // U = 0: the residual is F
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_vcycle_small(const SmallLevel<T
         const T *dU = C.U + prob * C.n;
         for (int i = threadIdx.x; i < (int)L.n; i += blockDim.x) U[i] = U[i] + csr_row(L.P_rp, L.P_ci, L.P_v, dU, i);
         __syncthreads();
-        for (int s = 0; s < nu2; ++s) {
+        for (int s = 0; s < L.nu2; ++s) {
             small_residual<D, K, T>(L, prob, F, U, r);
             __syncthreads();
             small_smooth(L, prob, r, U, false);
@@ -114,18 +115,15 @@ __global__ __launch_bounds__(kSmallBlock) void k_vcycle_small(const SmallLevel<T
 }  // namespace
 
 template <class T>
-void launch_vcycle_small(int d, int k, const SmallLevel<T> *lv, int top, int nu1, int nu2, const int *stop,
-                         int nprob, hipStream_t s) {
+void launch_vcycle_small(int d, int k, const SmallLevel<T> *lv, int top, const int *stop, int nprob, hipStream_t s) {
     const dim3 grid(nprob), block(kSmallBlock);
-    if (d == 2 && k == 1) hipLaunchKernelGGL((k_vcycle_small<2, 1, T>), grid, block, 0, s, lv, top, nu1, nu2, stop);
-    else if (d == 2 && k == 2) hipLaunchKernelGGL((k_vcycle_small<2, 2, T>), grid, block, 0, s, lv, top, nu1, nu2, stop);
-    else if (d == 3 && k == 1) hipLaunchKernelGGL((k_vcycle_small<3, 1, T>), grid, block, 0, s, lv, top, nu1, nu2, stop);
-    else hipLaunchKernelGGL((k_vcycle_small<3, 2, T>), grid, block, 0, s, lv, top, nu1, nu2, stop);
+    if (d == 2 && k == 1) hipLaunchKernelGGL((k_vcycle_small<2, 1, T>), grid, block, 0, s, lv, top, stop);
+    else if (d == 2 && k == 2) hipLaunchKernelGGL((k_vcycle_small<2, 2, T>), grid, block, 0, s, lv, top, stop);
+    else if (d == 3 && k == 1) hipLaunchKernelGGL((k_vcycle_small<3, 1, T>), grid, block, 0, s, lv, top, stop);
+    else hipLaunchKernelGGL((k_vcycle_small<3, 2, T>), grid, block, 0, s, lv, top, stop);
 }
 
-template void launch_vcycle_small<double>(int, int, const SmallLevel<double> *, int, int, int, const int *, int,
-                                          hipStream_t);
-template void launch_vcycle_small<float>(int, int, const SmallLevel<float> *, int, int, int, const int *, int,
-                                         hipStream_t);
+template void launch_vcycle_small<double>(int, int, const SmallLevel<double> *, int, const int *, int, hipStream_t);
+template void launch_vcycle_small<float>(int, int, const SmallLevel<float> *, int, const int *, int, hipStream_t);
 
 }  // namespace dfmg

@@ -65,6 +65,8 @@ SIGNATURES = [
     ("dfmg_sizes", c_int, [c_void_p, c_int, c_i64p, c_i64p, c_i64p, c_i64p]),
     ("dfmg_set_eta", c_int, [c_void_p, c_dblp, c_int]),
     ("dfmg_vcycle", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("dfmg_set_smoothing", c_int, [c_void_p, c_i32p, c_i32p, c_int]),
+    ("dfmg_get_smoothing", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
     ("dfmg_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
     ("dfmg_div_norm", c_int, [c_void_p, c_void_p, c_dblp]),
@@ -147,7 +149,8 @@ def _dev(t, n):
     return c_void_p(t.data_ptr())
 
 
-MLP_NPARAM = 1381
+MLP_NPARAM = 1546
+MLP_NOUT = 10
 
 
 def _devf(t, n):
@@ -166,15 +169,15 @@ def _stream(t):
 
 
 def mlp_forward(W, X, Z):
-    """Z (n x 5) = logits of the damping network for features X (n x 4)."""
+    """Z (n x 10) = outputs of the smoothing-parameter network for X (n x 4)."""
     n = X.numel() // 4
-    _check(lib().dfmg_mlp_forward(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Z, 5 * n), _stream(W)))
+    _check(lib().dfmg_mlp_forward(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Z, MLP_NOUT * n), _stream(W)))
 
 
 def mlp_grad(W, X, Y, M, scale, work, G, loss):
     """G = gradient and loss[0] = value of scale * sum M (Z - Y)^2."""
     n = X.numel() // 4
-    _check(lib().dfmg_mlp_grad(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Y, 5 * n), _devf(M, 5 * n),
+    _check(lib().dfmg_mlp_grad(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Y, MLP_NOUT * n), _devf(M, MLP_NOUT * n),
                                float(scale), _devf(work, n * (MLP_NPARAM + 1)), _devf(G, MLP_NPARAM),
                                _devf(loss, 1), _stream(W)))
 
@@ -298,6 +301,20 @@ class Solver:
         a = np.ascontiguousarray(etas, dtype=np.float64).ravel()
         _check(lib().dfmg_set_eta(self._ctx, _ptr(a, ctypes.c_double), int(a.size)))
 
+    def set_smoothing(self, nu1, nu2):
+        """Per-level smoothing steps, finest level first (n_levels - 1 each)."""
+        a = np.ascontiguousarray(nu1, dtype=np.int32)
+        b = np.ascontiguousarray(nu2, dtype=np.int32)
+        if a.size != b.size:
+            raise ValueError("nu1 and nu2 need the same length")
+        _check(lib().dfmg_set_smoothing(self._ctx, _ptr(a, ctypes.c_int32), _ptr(b, ctypes.c_int32), int(a.size)))
+
+    def get_smoothing(self):
+        a = np.zeros(self.n_levels - 1, np.int32)
+        b = np.zeros(self.n_levels - 1, np.int32)
+        _check(lib().dfmg_get_smoothing(self._ctx, _ptr(a, ctypes.c_int32), _ptr(b, ctypes.c_int32)))
+        return a.tolist(), b.tolist()
+
     def vcycle(self, F, U, ncycles=1):
         n = self.n * self.nprob
         _check(lib().dfmg_vcycle(self._ctx, _dev(F, n), _dev(U, n), int(ncycles)))
@@ -396,15 +413,16 @@ class Solver:
         return out
 
     def set_learned(self, W, rho_plain=None):
-        """Dampings from the network W (1381 floats) for every problem; with
-        rho_plain (one per problem) a solve falls back to the fixed damping
-        when a cycle contracts worse than 1.05 * rho_plain.  W None: fixed."""
+        """Dampings (per problem) and smoothing steps (per batch) from the
+        network W (1546 floats); with rho_plain (one per problem) a solve falls
+        back to the fixed damping when a cycle contracts worse than
+        1.05 * rho_plain.  W None: fixed damping, the options' steps."""
         if W is None:
             _check(lib().dfmg_set_learned(self._ctx, None, None))
             return
         w = np.ascontiguousarray(W, dtype=np.float32)
         if w.size != MLP_NPARAM:
-            raise ValueError("expected 1381 parameters")
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
         r = None
         if rho_plain is not None:
             r = np.ascontiguousarray(rho_plain, dtype=np.float64)
@@ -515,7 +533,7 @@ class MultiSolver:
             return
         w = np.ascontiguousarray(W, dtype=np.float32)
         if w.size != MLP_NPARAM:
-            raise ValueError("expected 1381 parameters")
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
         r = None if rho_plain is None else np.ascontiguousarray(rho_plain, dtype=np.float64)
         if r is not None and r.size != self.nprob:
             raise ValueError("one plain rate per problem")

@@ -1,21 +1,30 @@
-"""Learned per-level damping for the additive Schwarz smoother.
+"""Learned per-level smoothing parameters of the V-cycle.
 
-The smoother's damping eta (equation ASM, eta in (0,1)) is predicted per
-smoothed level by the library's perceptron (``dfmg_mlp_*``, FP32 HIP kernels).
-This module generates the training data with the method itself and trains the
-network on the GPU:
+The smoother's damping eta (equation ASM, eta in (0,1)) and the number of
+smoothing steps are predicted per smoothed level by the library's perceptron
+(``dfmg_mlp_*``, FP32 HIP kernels).  This module generates the training data
+with the method itself and trains the network on the GPU:
 
-* ``sweep``: for each training problem, a batch of identical copies solves
-  the manufactured load from U = 0 to relative residual 1e-8 with V(2,2)
-  cycles; every copy carries one candidate damping vector, so one batched
-  solve scores all candidates.  A coordinate search (finest level first, two
+* ``step_costs``: a per-cycle time model of the FP32 refinement on a batch
+  of four problems of one mesh, t(s) = A + sum_l s_l B_l for s_l smoothing
+  steps before and after the coarse correction on level l, from device
+  timings of the level kernels and of whole refinement steps.
+* ``best_steps``: per training problem, the best uniform count s in 1..6,
+  then a coordinate search over s_l (finest first, two passes) minimising
+  the modelled time to 1e-8, cycles(s) * t(s), with cycles from the
+  contraction of a whole solve.
+
+* ``best_damping``: with those steps, a batch of identical copies solves
+  the manufactured load from U = 0 to relative residual 1e-8; every copy
+  carries one candidate damping vector, so one batched solve scores all
+  candidates.  A coordinate search (finest level first, two
   passes, multiplicative steps around the fixed damping) keeps the per-level
   dampings with the smallest mean contraction per cycle
   rho = (||r_m|| / ||r_0||)^(1/m) over the whole solve.  The target is the
-  logit of the best dampings; the fixed damping's worst single-cycle ratio is
-  kept for the fallback check.
-* ``train``: full-batch Adam on the masked squared logit error with the
-  library's forward/backward/Adam kernels.
+  logit of the best dampings and the best step counts; the fixed damping's
+  worst single-cycle ratio (V(2,2)) is kept for the fallback check.
+* ``train``: full-batch Adam on the weighted squared error of the outputs
+  with the library's forward/backward/Adam kernels.
 
 ``python -m paper_1705_09282_amd.learned [out.json]`` runs both on the
 default training grid and writes the weights, the training data and the
@@ -29,12 +38,15 @@ import time
 
 import numpy as np
 
-from .dfmg import BatchSolver, MLP_NPARAM, mlp_adam, mlp_grad, mlp_forward
+from .dfmg import BatchSolver, Solver, MLP_NPARAM, MLP_NOUT, mlp_adam, mlp_grad, mlp_forward
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "data", "damping_mlp.json")
-NOUT = 5
+NOUT = MLP_NOUT   # 5 damping logits, then 5 step counts (finest level first)
+NETA = 5
 FACTORS = (0.55, 0.7, 0.85, 1.0, 1.15, 1.3, 1.45)
+STEPS = (1, 2, 3, 4, 5, 6)
+COUNT_WEIGHT = 0.25  # loss weight of a step-count output relative to a logit
 
 
 def features(nu, sigma, c, N, k):
@@ -70,17 +82,84 @@ def score(batch, F, U, etas, tol):
     return batch.solve(F, U, tol=tol, raise_on_error=False)
 
 
-def best_damping(prob, max_cycles=80, passes=2, tol=1e-8, device="cuda"):
+def step_costs(d, N, L, k, device="cuda", reps=20):
+    """Per-cycle time model (A, B) of the FP32 refinement for a batch of four
+    problems on this mesh: t(s) = A + B . s (B finest level first, ms)."""
+    import torch
+    m = 12
+    S = BatchSolver(d, N, L, k, [1.0] * 4, [1.0] * 4, precision=1, max_cycles=m).bind(device)
+    S.autotune(reps=5)
+    F = torch.tensor(S.manufactured_rhs(), device=device)
+    U = torch.zeros_like(F)
+    S.solve(F, U, tol=1e-30, raise_on_error=False)
+    Bc = np.array([2.0 * (S.time_kernel(1, lev, reps) + S.time_kernel(3, lev, reps)) for lev in range(L - 1, 0, -1)])
+    S.set_smoothing([1] * (L - 1), [1] * (L - 1))
+    best = float("inf")
+    for _ in range(3):
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.solve(F, U, tol=1e-30, raise_on_error=False)
+        torch.cuda.synchronize()
+        best = min(best, 1e3 * (time.perf_counter() - t0) / max(1, max(x["cycles"] for x in st)))
+    S.close()
+    return max(best - Bc.sum(), 0.0), Bc
+
+
+def best_steps(prob, cost, max_cycles=80, passes=2, tol=1e-8, device="cuda"):
+    """Search of the per-level smoothing steps (pre = post) for one problem
+    minimising the modelled solve time cycles(s) * (A + B . s): the best
+    uniform count, then coordinate steps; a candidate replaces the current
+    steps only if 1% faster.  Returns (steps, modelled ms, contraction)."""
+    import torch
+    A, Bc = cost
+    S = Solver(prob["d"], prob["N"], prob["L"], prob["k"], nu=prob["nu"], sigma=prob["sigma"], c=prob["c"],
+               precision=1, max_cycles=max_cycles).bind(device)
+    F = torch.tensor(S.manufactured_rhs(), device=device)
+    U = torch.zeros_like(F)
+
+    def model(s):
+        S.set_smoothing(s, s)
+        U.zero_()
+        rho = contraction(S.solve(F, U, tol=tol, raise_on_error=False))
+        if not rho < 1.0:
+            return float("inf"), rho
+        return (A + float(Bc @ np.asarray(s))) * math.log(tol) / math.log(max(rho, 1e-12)), rho
+
+    nlev = prob["L"] - 1
+    # uniform counts first (a single level's count alone moves little when
+    # the others limit the contraction), then per-level refinement
+    best, cur, rho = float("inf"), [2] * nlev, float("inf")
+    for v in STEPS:
+        t, r = model([v] * nlev)
+        if t < best:
+            best, cur, rho = t, [v] * nlev, r
+    for _ in range(passes):
+        for lev in range(nlev):
+            for v in STEPS:
+                if v == cur[lev]:
+                    continue
+                cand = list(cur)
+                cand[lev] = v
+                t, r = model(cand)
+                if t < 0.99 * best:
+                    best, cur, rho = t, cand, r
+    S.close()
+    return cur, best, rho
+
+
+def best_damping(prob, steps=None, max_cycles=80, passes=2, tol=1e-8, device="cuda"):
     """Coordinate search of the per-level damping for one problem: every
     candidate is scored by the mean contraction per cycle of a whole solve to
     tol from U = 0 (the quantity that sets the cost of a solve); a candidate
     replaces the current dampings only if it contracts at least 1% faster.
-    prob: dict(d, N, k, L, nu, sigma, c).  Returns (eta_best, rho_best,
-    rho_plain, worst single-cycle ratio of the fixed damping)."""
+    prob: dict(d, N, k, L, nu, sigma, c); steps: per-level smoothing steps
+    (finest first; None: the default V(2,2)).  Returns (eta_best, rho_best,
+    rho_plain, worst single-cycle ratio of the fixed damping with V(2,2))."""
     import torch
     C = len(FACTORS)
     B = BatchSolver(prob["d"], prob["N"], prob["L"], prob["k"], [prob["nu"]] * C, [prob["sigma"]] * C,
-                    [prob["c"]] * C, max_cycles=max_cycles).bind(device)
+                    [prob["c"]] * C, precision=1, max_cycles=max_cycles).bind(device)
     F = torch.tensor(B.manufactured_rhs(), device=device)
     U = torch.zeros_like(F)
     eta0 = B.get_eta()[0].copy()
@@ -88,7 +167,10 @@ def best_damping(prob, max_cycles=80, passes=2, tol=1e-8, device="cuda"):
     cur = eta0.copy()
     st = score(B, F, U, [eta0] * C, tol)[0]
     rho_plain, worst_plain = contraction(st), worst_cycle(st)
-    best = rho_plain
+    if steps is not None:
+        B.set_smoothing(steps, steps)
+        st = score(B, F, U, [eta0] * C, tol)[0]
+    best = contraction(st)
     for _ in range(passes):
         for lev in range(nlev):
             cand = []
@@ -119,28 +201,40 @@ def training_problems():
 
 
 def sweep(problems, log=None):
-    """Training data: X (n x 4), Y (n x 5) target logits, M (n x 5) mask,
-    rho_plain, rho_best, worst_plain."""
-    X, Y, Mk, rp, rb, wp = [], [], [], [], [], []
+    """Training data: X (n x 4), Y (n x 10) targets (damping logits, step
+    counts), M (n x 10) weights, rho_plain, rho_best, worst_plain, steps,
+    and the time model of every mesh."""
+    X, Y, Mk, rp, rb, wp, ss = [], [], [], [], [], [], []
+    costs = {}
     for i, p in enumerate(problems):
         t0 = time.time()
-        eta, rho, rho_plain, worst = best_damping(p)
+        key = (p["d"], p["N"], p["L"], p["k"])
+        if key not in costs:
+            costs[key] = step_costs(*key)
+            if log:
+                log(f"[sweep] time model {key}: A {costs[key][0]:.4f} ms, B {np.round(costs[key][1], 4).tolist()}")
+        steps, ms, rho_s = best_steps(p, costs[key])
+        eta, rho, rho_plain, worst = best_damping(p, steps)
         y = np.zeros(NOUT)
         mk = np.zeros(NOUT)
-        for j in range(min(NOUT, eta.size)):
+        for j in range(min(NETA, eta.size)):
             y[j] = logit(eta[j])
             mk[j] = 1.0
+            y[NETA + j] = steps[j]
+            mk[NETA + j] = COUNT_WEIGHT
         X.append(features(p["nu"], p["sigma"], p["c"], p["N"], p["k"]))
         Y.append(y)
         Mk.append(mk)
         rp.append(rho_plain)
         rb.append(rho)
         wp.append(worst)
+        ss.append(steps[:NETA])
         if log:
-            log(f"[sweep {i + 1}/{len(problems)}] {p} rho plain {rho_plain:.3f} -> {rho:.3f} "
-                f"eta {np.round(eta, 3).tolist()} ({time.time() - t0:.1f} s)")
+            log(f"[sweep {i + 1}/{len(problems)}] {p} steps {steps} (model {ms:.2f} ms) rho plain {rho_plain:.3f} "
+                f"-> {rho:.3f} eta {np.round(eta, 3).tolist()} ({time.time() - t0:.1f} s)")
     return dict(X=np.array(X), Y=np.array(Y), M=np.array(Mk), rho_plain=np.array(rp), rho_best=np.array(rb),
-                worst_plain=np.array(wp))
+                worst_plain=np.array(wp), steps=np.array(ss),
+                time_model=np.array([[*k, c[0], *c[1]] for k, c in costs.items()]))
 
 
 def glorot_init(seed=0):
@@ -162,7 +256,7 @@ def train(X, Y, M, epochs=3000, lr=3e-3, seed=0, device="cuda", log=None):
     import torch
     n = X.shape[0]
     W = torch.tensor(glorot_init(seed), device=device)
-    # start the output bias at the mean target of each level
+    # start the output bias at the mean target of each output
     ymean = (Y * M).sum(axis=0) / np.maximum(M.sum(axis=0), 1)
     W[MLP_NPARAM - NOUT:] = torch.tensor(ymean, dtype=torch.float32, device=device)
     Xd = torch.tensor(X, dtype=torch.float32, device=device).contiguous()
@@ -249,7 +343,8 @@ def main():
         f"{data['rho_plain'].mean():.3f} best {data['rho_best'].mean():.3f}")
     W, hist = train(data["X"], data["Y"], data["M"], log=log)
     meta = {"epochs": hist[-1][0] - 1, "final_loss": hist[-1][1], "factors": FACTORS,
-            "objective": "mean contraction per cycle of a solve to 1e-8 from U=0 (at most 80 cycles)",
+            "objective": "steps: modelled time to 1e-8 of the FP32 refinement (4-problem batch); dampings: "
+                         "mean contraction per cycle of a solve to 1e-8 from U=0 with those steps",
             "problems": len(probs), "features": "log10(nu)/2, log10(sigma)/4, |a|h/nu, k-1.5"}
     out = sys.argv[1] if len(sys.argv) > 1 else WEIGHTS
     save(out, W, data, meta)

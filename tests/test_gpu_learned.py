@@ -150,8 +150,10 @@ def sigmoid(z):
 @pytest.mark.parametrize("N,L,k", [(16, 3, 1), (64, 6, 2), (128, 7, 1)])
 def test_solver_dampings_are_the_network_output(N, L, k):
     """Per problem of a batch, eta of the finest smoothed level first equals
-    sigmoid of the oracle network on the problem's features; levels beyond
-    the five outputs reuse the last one."""
+    sigmoid of the oracle network's damping outputs on the problem's
+    features, and the batch's smoothing steps are the largest rounded count
+    output over its problems; levels beyond the five outputs reuse the last
+    one.  Without a network the fixed damping and V(2,2) come back."""
     from paper_1705_09282_amd.dfmg import BatchSolver
     nus, sigmas, cs = [1.0, 0.1, 0.02], [1e-2, 30.0, 1e4], [0.0, 3.0, 1.5]
     print(f"\n[case] N={N} L={L} k={k}", flush=True)
@@ -163,10 +165,14 @@ def test_solver_dampings_are_the_network_output(N, L, k):
     X = np.array([om.features(nu, sg, abs(c) / math.sqrt(2.0), N, k) for nu, sg, c in zip(nus, sigmas, cs)])
     Z = om.forward(W, f32(X))
     for p in range(3):
-        ref = [sigmoid(Z[p, min(i, om.NOUT - 1)]) for i in range(L - 1)]
+        ref = [sigmoid(Z[p, min(i, om.NETA - 1)]) for i in range(L - 1)]
         assert np.max(np.abs(eta[p] - ref)) < 1e-5
+    steps = om.steps(Z[:, om.NETA:]).max(axis=0)
+    ref = [int(steps[min(i, om.NETA - 1)]) for i in range(L - 1)]
+    assert B.get_smoothing() == (ref, ref)
     B.set_learned(None)
     assert np.array_equal(B.get_eta(), fixed)
+    assert B.get_smoothing() == ([2] * (L - 1), [2] * (L - 1))
     B.close()
 
 
@@ -184,7 +190,8 @@ def test_vcycles_with_learned_dampings_match_oracle():
     Fd = torch.tensor(F, device="cuda")
     U = torch.zeros_like(Fd)
     s.vcycle(Fd, U, 3)
-    ref = vcycles(h, np.zeros_like(F), F, 3, eta=list(eta))
+    n1, n2 = s.get_smoothing()
+    ref = vcycles(h, np.zeros_like(F), F, 3, nu1=n1, nu2=n2, eta=list(eta))
     got = U.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"[vcycles] eta {np.round(eta, 4).tolist()} rel err {err:.2e}", flush=True)
@@ -245,7 +252,8 @@ def test_fallback_under_extreme_weights(bias):
     st0 = s.solve(F, U, tol=1e-8)
     rho = learned.worst_cycle(st0)
     W = np.zeros(om.NPARAM, dtype=np.float32)
-    W[-om.NOUT:] = bias
+    W[om.NPARAM - om.NOUT:om.NPARAM - om.NOUT + om.NETA] = bias
+    W[om.NPARAM - om.NOUT + om.NETA:] = 2.0  # V(2,2)
     s.set_learned(W, [rho])
     assert np.allclose(s.get_eta(), sigmoid(bias), atol=1e-6)
     for rep in range(2):
@@ -269,7 +277,8 @@ def test_no_fallback_without_threshold():
     F = torch.tensor(s.manufactured_rhs(), device="cuda")
     U = torch.zeros_like(F)
     W = np.zeros(om.NPARAM, dtype=np.float32)
-    W[-om.NOUT:] = math.log(0.3 / 0.7)
+    W[om.NPARAM - om.NOUT:om.NPARAM - om.NOUT + om.NETA] = math.log(0.3 / 0.7)
+    W[om.NPARAM - om.NOUT + om.NETA:] = 2.0
     s.set_learned(W, [1e-6])  # any cycle contracts worse than this
     st = s.solve(F, U, tol=1e-8)
     assert st["converged"] and st["fallback"]

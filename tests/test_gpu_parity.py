@@ -168,6 +168,31 @@ def test_single_workgroup_coarse_cycle_is_bitwise_equal(d, N, k, L, precision):
         assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
 
 
+@pytest.mark.parametrize("d,N,k,L,precision", [(2, 16, 2, 3, 0), (2, 32, 1, 4, 0), (3, 8, 1, 3, 0), (2, 32, 2, 4, 1)])
+def test_per_level_smoothing_steps_match_oracle(d, N, k, L, precision):
+    """Per-level pre/post smoothing steps (set_smoothing) give the oracle's
+    cycles with the same counts; the solve stays divergence-free."""
+    s, h, F = make(d, N, k, L, nu=0.5, sigma=4.0, precision=precision)
+    n1 = [3, 1, 0][:L - 1]
+    n2 = [1, 4, 2][:L - 1]
+    s.set_smoothing(n1, n2)
+    assert s.get_smoothing() == (n1, n2)
+    nv = h.finest.disc.n_v
+    if precision == 0:
+        U0 = divfree_start(h, 23)
+        Ud = dev(U0)
+        s.vcycle(dev(F), Ud, 2)
+        Uo = vcycles(h, U0, F, 2, n1, n2)
+        assert rel_l2(host(Ud)[:nv], Uo[:nv]) < 1e-10
+    Ud = dev(np.zeros_like(F))
+    st = s.solve(dev(F), Ud, tol=1e-8)
+    Uo, hist = solve(h, F, tol=1e-8, nu1=n1, nu2=n2)
+    assert st["converged"] and abs(st["cycles"] - (len(hist) - 1)) <= (0 if precision == 0 else 1)
+    assert rel_l2(host(Ud)[:nv], Uo[:nv]) < (1e-10 if precision == 0 else 1e-8)
+    assert s.div_norm(Ud) < 1e-10
+    s.close()
+
+
 def test_autotune_keeps_results_and_picks_fastest(tmp_path):
     s, h, F = make(2, 64, 2, 4)
     U0 = divfree_start(h, 5)

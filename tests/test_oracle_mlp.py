@@ -31,7 +31,7 @@ def test_masked_loss_and_shapes():
     X, Y, M = _data()
     th = mlp.init(4)
     Z = mlp.forward(th, X)
-    assert Z.shape == (13, mlp.NOUT) and mlp.NPARAM == 1381
+    assert Z.shape == (13, mlp.NOUT) and mlp.NPARAM == 1546
     M0 = np.zeros_like(M)
     M0[0, 0] = 1.0
     np.testing.assert_allclose(mlp.loss(th, X, Y, M0), (Z[0, 0] - Y[0, 0]) ** 2)
@@ -43,3 +43,7 @@ def test_adam_on_quadratic():
     g = np.array([0.5, -0.1, 2.0])
     new, m, v = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, lr=0.1)
     np.testing.assert_allclose(new, th - 0.1 * np.sign(g), rtol=1e-6)
+
+
+def test_step_rounding():
+    np.testing.assert_array_equal(mlp.steps(np.array([-3.0, 0.4, 1.5, 2.49, 2.5, 7.6, 20.0])), [1, 1, 2, 2, 3, 8, 8])

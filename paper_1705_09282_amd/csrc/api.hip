@@ -52,6 +52,7 @@ template <class T>
 struct LevelData {
     T *val = nullptr, *U = nullptr, *F = nullptr, *r = nullptr, *M = nullptr, *delta = nullptr;
     T *P_v = nullptr, *R_v = nullptr;  // shared by the batch
+    T *P_ev = nullptr, *R_ev = nullptr;  // fixed-width forms (when stored)
 };
 
 struct DevLevel {
@@ -61,6 +62,11 @@ struct DevLevel {
     int32_t *pptr = nullptr, *pdofs = nullptr, *inv_ptr = nullptr, *inv_pos = nullptr, *col_list = nullptr;
     int32_t *small = nullptr, *bigent = nullptr, *small_dofs = nullptr, *inv_pos4 = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
+    int32_t *P_eci = nullptr, *R_eci = nullptr, *inv_ell = nullptr, *inv4_ell = nullptr;
+    int4 *bmesh = nullptr;
+    // per problem (form 4): small-subdomain and remaining-subdomain tables
+    int4 *sinfo = nullptr;
+    int2 *binfo = nullptr;
     // per problem
     int32_t *moff = nullptr;
     int4 *ent_info = nullptr;
@@ -70,6 +76,8 @@ struct DevLevel {
     float *beta = nullptr, *Q = nullptr;     // per problem
     int32_t *qoff = nullptr, *qptr = nullptr, *beta_row = nullptr, *beta_patch = nullptr, *bigbeta = nullptr,
             *qinv_ptr = nullptr, *qinv_pos = nullptr, *Ps_rp = nullptr, *Ps_ci = nullptr;
+    int32_t *qinv_ell = nullptr, *Ps_eci = nullptr;
+    double *Ps_ev = nullptr;
     double *Q0 = nullptr;  // level 0, per problem
     int64_t npsi = 0, nbeta = 0, sQ = 0;
     // strides
@@ -111,6 +119,7 @@ struct dfmg_ctx {
     int nparts = 0;
     double *hist = nullptr;      // [problem][DFMG_MAX_HISTORY]
     int *counter = nullptr, *stop = nullptr;   // adjacent: stop = counter + np
+    int *stopw = nullptr;        // wide copies of stop read by the cycle kernels
     int *hflags = nullptr;       // pinned host copies of counter and stop, two buffers
     hipEvent_t ev_flag[2] = {nullptr, nullptr};
     double *thresh2 = nullptr, *scal = nullptr;
@@ -170,6 +179,8 @@ void take_level(Arena &A, const DevLevel &dv, int np, LevelData<T> &v, bool coar
     v.delta = A.take<T>(dv.sdelta * np);
     v.P_v = A.take<T>(h.P_v.size());
     v.R_v = A.take<T>(h.R_v.size());
+    v.P_ev = A.take<T>(h.P_ev.size());
+    v.R_ev = A.take<T>(h.R_ev.size());
 }
 
 void plan(dfmg_ctx *c, Arena &A) {
@@ -210,6 +221,9 @@ void plan(dfmg_ctx *c, Arena &A) {
                 v.qinv_pos = A.take<int32_t>(h.qinv_pos.size());
                 v.Ps_rp = A.take<int32_t>(h.Ps_rp.size());
                 v.Ps_ci = A.take<int32_t>(h.Ps_ci.size());
+                v.qinv_ell = A.take<int32_t>(h.qinv_ell.size());
+                v.Ps_eci = A.take<int32_t>(h.Ps_eci.size());
+                v.Ps_ev = A.take<double>(h.Ps_ev.size());
             }
         }
         nmax = std::max(nmax, h.n);
@@ -227,6 +241,13 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.bigent = A.take<int32_t>(h.big_ent.size());
         v.small_dofs = A.take<int32_t>(h.small_dofs.size());
         v.inv_pos4 = A.take<int32_t>(h.inv_pos4.size());
+        v.inv_ell = A.take<int32_t>(h.inv_ell.size());
+        v.inv4_ell = A.take<int32_t>(h.inv4_ell.size());
+        v.bmesh = A.take<int4>(h.big_sub.size());
+        v.sinfo = A.take<int4>(h.small_list.size() * np);
+        v.binfo = A.take<int2>(h.big_sub.size() * np);
+        v.P_eci = A.take<int32_t>(h.P_eci.size());
+        v.R_eci = A.take<int32_t>(h.R_eci.size());
         v.P_rp = A.take<int32_t>(h.P_rp.size());
         v.P_ci = A.take<int32_t>(h.P_ci.size());
         v.R_rp = A.take<int32_t>(h.R_rp.size());
@@ -240,6 +261,7 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->hist = A.take<double>((size_t)DFMG_MAX_HISTORY * np);
     c->counter = A.take<int>(2 * (size_t)np);
     c->stop = c->counter ? c->counter + np : nullptr;
+    c->stopw = A.take<int>((size_t)kStopLanes * np);
     c->thresh2 = A.take<double>(np);
     c->scal = A.take<double>(np);
     c->dvec = A.take<double>(H.lv[L - 1].n_q);
@@ -346,6 +368,13 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.nsmall = (int)h.small_list.size();
     a.nbig = (int)h.big_ent.size();
     a.sdelta = v.sdelta;
+    a.sinfo = v.sinfo;
+    a.bmesh = v.bmesh;
+    a.binfo = v.binfo;
+    a.nbsub = (int)h.big_sub.size();
+    a.max_big = h.max_big;
+    a.inv_w = h.inv_w;
+    a.inv_ell = v.inv_ell;
     if (tracks_potentials<T>(c)) {
         // the FP32 cycle of the refinement also accumulates the potentials of
         // its velocity corrections (forms 3 and 4 do; the others run as 4)
@@ -363,10 +392,13 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
         a.bigbeta = v.bigbeta;
         a.qinv_ptr = v.qinv_ptr;
         a.qinv_pos = v.qinv_pos;
+        a.qinv_w = h.qinv_w;
+        a.qinv_ell = v.qinv_ell;
         if (c->smoother[l] == 3) {  // one pass (recomputes the rows, no buffer)
             launch_schwarz_fused<T>(a, c->s);
         } else {
             a.inv_pos = v.inv_pos4;
+            a.inv_ell = v.inv4_ell;
             launch_schwarz_small<T>(a, c->s);
         }
         return;
@@ -379,6 +411,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
         launch_schwarz_fused<T>(a, c->s);
     } else if (c->smoother[l] == 4) {
         a.inv_pos = v.inv_pos4;
+        a.inv_ell = v.inv4_ell;
         launch_schwarz_small<T>(a, c->s);
     } else {
         launch_schwarz_gather<T>(a, c->s);
@@ -389,14 +422,16 @@ template <class T>
 void restrict_to(dfmg_ctx *c, int l, const T *r, T *G, const int *stop) {
     const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
-    launch_csr<T>((int)hc.n, v.R_rp, v.R_ci, v.data<T>().R_v, r, hf.n, G, hc.n, 0, stop, c->np, c->s);
+    const SparseT<T> R{v.R_rp, v.R_ci, v.data<T>().R_v, hf.R_w, v.R_eci, v.data<T>().R_ev};
+    launch_csr<T>((int)hc.n, R, r, hf.n, G, hc.n, 0, stop, c->np, c->s);
 }
 
 template <class T>
 void prolong_add(dfmg_ctx *c, int l, const T *dU, T *U, const int *stop) {
     const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
-    launch_csr<T>((int)hf.n, v.P_rp, v.P_ci, v.data<T>().P_v, dU, hc.n, U, hf.n, 1, stop, c->np, c->s);
+    const SparseT<T> P{v.P_rp, v.P_ci, v.data<T>().P_v, hf.P_w, v.P_eci, v.data<T>().P_ev};
+    launch_csr<T>((int)hf.n, P, dU, hc.n, U, hf.n, 1, stop, c->np, c->s);
 }
 
 // exact coarse solve (FP64 bordered inverse, FP64 accumulation)
@@ -404,6 +439,12 @@ template <class T>
 void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
     const int64_t n = c->S().lv[0].n;
     launch_gemv<T>((int)n, (int)n, c->dl[0].Kinv, n * n, G, n, dU, n, stop, c->np, c->s);
+}
+
+// every problem running: the flags and their wide copies
+void reset_flags(dfmg_ctx *c) {
+    launch_fill_int(c->np, c->stop, 0, c->s);
+    launch_fill_int(c->np * kStopLanes, c->stopw, 0, c->s);
 }
 
 void check(dfmg_ctx *c, int np_blocks) {
@@ -415,7 +456,8 @@ void check(dfmg_ctx *c, int np_blocks) {
     fb.eta_fixed = c->eta_fixed;
     fb.flag = c->fallback;
     fb.L = c->L();
-    launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->thresh2, fb,
+    launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->stopw,
+                 c->thresh2, fb,
                  c->np, c->s);
 }
 
@@ -500,7 +542,7 @@ void upload_small_tables(dfmg_ctx *c) {
 template <class T>
 void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
     const int L = c->L();
-    const int *stop = c->stop;
+    const int *stop = c->stopw;
     if (L == 1) {
         LevelData<T> &v = c->dl[0].data<T>();
         if (norm) check(c, spmv<T>(c, 0, v.F, v.U, v.r, c->partial, stop));
@@ -552,7 +594,8 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         if (psi) {
             DevLevel &f = c->dl[l];
             const DevLevel &q = c->dl[l - 1];
-            launch_csr<double>((int)f.npsi, f.Ps_rp, f.Ps_ci, f.Ps_v, q.psi, q.npsi, f.psi, f.npsi, 1, stop, c->np, c->s);
+            const SparseT<double> Ps{f.Ps_rp, f.Ps_ci, f.Ps_v, c->S().lv[l].Ps_w, f.Ps_eci, f.Ps_ev};
+            launch_csr<double>((int)f.npsi, Ps, q.psi, q.npsi, f.psi, f.npsi, 1, stop, c->np, c->s);
         }
         for (int s = 0; s < c->nu2l[l]; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
@@ -568,8 +611,8 @@ void refine_body(dfmg_ctx *c) {
     const int L = c->L();
     const HostLevel &h = c->S().lv[L - 1];
     DevLevel &v = c->dl[L - 1];
-    check(c, spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stop));
-    launch_cast(h.n, v.d.r, v.f.F, h.n, c->stop, c->np, c->s);
+    check(c, spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stopw));
+    launch_cast(h.n, v.d.r, v.f.F, h.n, c->stopw, c->np, c->s);
     for (int i = 0; i < c->opt.inner_cycles; ++i) cycle_body<float>(c, false, i == 0);
     RefineArgs a{};
     a.N = c->S().pb.N;
@@ -583,7 +626,7 @@ void refine_body(dfmg_ctx *c) {
     a.U = v.d.U;
     a.svec = h.n;
     a.spsi = v.npsi;
-    a.stop = c->stop;
+    a.stop = c->stopw;
     a.nprob = c->np;
     launch_refine_update_2d(a, c->s);
 }
@@ -715,7 +758,7 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
     const int64_t n = c->S().lv[L - 1].n;
     LevelData<double> &v = c->dl[L - 1].d;
     const int nb = blocks_for(n);
-    launch_fill_int(np, c->stop, 0, c->s);
+    reset_flags(c);
     launch_fill_int(np, c->counter, 0, c->s);
     launch_fill_int(np, c->fallback, 0, c->s);
     if (c->learned) apply_learned(c);
@@ -1014,6 +1057,8 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                 if (l > 0) {
                     up32(v.f.P_v, h.P_v, s);
                     up32(v.f.R_v, h.R_v, s);
+                    up32(v.f.P_ev, h.P_ev, s);
+                    up32(v.f.R_ev, h.R_ev, s);
                 }
                 HIPCHK(hipMemsetAsync(v.psi, 0, v.npsi * np * sizeof(double), s));
                 if (l == 0) {
@@ -1033,6 +1078,9 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                     up(v.qinv_pos, h.qinv_pos, s);
                     up(v.Ps_rp, h.Ps_rp, s);
                     up(v.Ps_ci, h.Ps_ci, s);
+                    up(v.qinv_ell, h.qinv_ell, s);
+                    up(v.Ps_eci, h.Ps_eci, s);
+                    up(v.Ps_ev, h.Ps_ev, s);
                     HIPCHK(hipMemsetAsync(v.beta, 0, v.nbeta * np * sizeof(float), s));
                 }
             }
@@ -1049,8 +1097,42 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.bigent, h.big_ent, s);
             up(v.small_dofs, h.small_dofs, s);
             up(v.inv_pos4, h.inv_pos4, s);
+            up(v.inv_ell, h.inv_ell, s);
+            up(v.inv4_ell, h.inv4_ell, s);
             up(v.d.P_v, h.P_v, s);
             up(v.d.R_v, h.R_v, s);
+            up(v.d.P_ev, h.P_ev, s);
+            up(v.d.R_ev, h.R_ev, s);
+            up(v.P_eci, h.P_eci, s);
+            up(v.R_eci, h.R_eci, s);
+            {
+                std::vector<int4> bm(h.big_sub.size());
+                for (size_t t = 0; t < bm.size(); ++t)
+                    bm[t] = make_int4(h.big_mesh[4 * t], h.big_mesh[4 * t + 1], h.big_mesh[4 * t + 2],
+                                      h.big_mesh[4 * t + 3]);
+                up(v.bmesh, bm, s);
+                // per problem: the offsets of each subdomain's inverse and
+                // potential map (classes differ between problems)
+                const size_t ns = h.small_list.size(), nb = h.big_sub.size();
+                std::vector<int4> si(ns * np);
+                std::vector<int2> bi(nb * np);
+                const bool pot = !h.qptr.empty();
+                for (int p = 0; p < np; ++p) {
+                    const HostLevel &hp = c->P[p].lv[l];
+                    for (size_t q = 0; q < ns; ++q) {
+                        const int32_t i = h.small_list[q];
+                        si[p * ns + q] = make_int4(h.pptr[i + 1] - h.pptr[i], hp.moff[i], pot ? hp.qoff[i] : 0,
+                                                   pot ? h.qptr[i] : 0);
+                    }
+                    for (size_t t = 0; t < nb; ++t) {
+                        const int32_t i = h.big_sub[t];
+                        bi[p * nb + t] = make_int2(hp.moff[i], pot ? hp.qoff[i] : 0);
+                    }
+                }
+                up(v.sinfo, si, s);
+                up(v.binfo, bi, s);
+                HIPCHK(hipStreamSynchronize(s));  // the host tables go out of scope
+            }
             up(v.P_rp, h.P_rp, s);
             up(v.P_ci, h.P_ci, s);
             up(v.R_rp, h.R_rp, s);
@@ -1165,7 +1247,7 @@ int dfmg_vcycle(dfmg_ctx *c, const double *F, double *U, int ncycles) {
         const int L = c->L(), np = c->np;
         const int64_t n = c->S().lv[L - 1].n;
         LevelData<double> &v = c->dl[L - 1].d;
-        launch_fill_int(np, c->stop, 0, c->s);
+        reset_flags(c);
         launch_copy(n, F, n, v.F, n, nullptr, np, c->s);
         launch_copy(n, U, n, v.U, n, nullptr, np, c->s);
         for (int i = 0; i < ncycles; ++i) run_cycle(c, 0);
@@ -1415,7 +1497,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         else tune(0.0);
         // how many coarse levels run in the single-workgroup cycle: whole
         // V-cycles timed for every admissible choice (no check, no flags)
-        launch_fill_int(c->np, c->stop, 0, c->s);
+        reset_flags(c);
         int best_top = 0;
         double best_t = 1e30;
         for (int t = 0; t <= (c->mixed() ? 0 : L - 2); ++t) {  // the FP32 cycle tracks potentials: no t

@@ -16,6 +16,27 @@ __device__ __forceinline__ int xcd_block(int hw, int grid) {
     return (hw & 7) * per + (hw >> 3);
 }
 
+// A load of a value that is the same for the whole block (a problem's
+// damping) as a vector load: it then travels beside the block's other loads,
+// where a scalar load would be waited for by the first later scalar load (the
+// kernel arguments).  The relaxed atomic keeps the compiler from turning it
+// into a scalar load.
+template <class T>
+__device__ __forceinline__ T uniform_vload(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// the wide flags of calls without flags (never written)
+__device__ int kNoStop[kStopLanes] = {};
+
+// A problem's stop flag from its wide form (0 when there are no flags): lane i
+// reads copy i, unconditionally, so the value stays per lane and the compiler
+// tests it where it is used.
+__device__ __forceinline__ int stop_flag(const int *stopw, int prob) {
+    const int lane = threadIdx.x & 63;
+    return stopw ? stopw[prob * kStopLanes + lane] : kNoStop[lane];
+}
+
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 // Sum over the block (wave shuffles, then the waves in a fixed order); the

@@ -9,7 +9,7 @@ namespace dfmg {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;  // block-uniform: the problem has stopped
+    if (stop_flag(a.stop, prob)) return;  // block-uniform: the problem has stopped
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int t = b * kBlock + threadIdx.x;
     if (t >= a.nent) return;
@@ -19,73 +19,163 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     a.delta[prob * a.sdelta + t] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, a.r + prob * a.svec);
 }
 
-// Additive Schwarz, step 1 with one thread per small subdomain (at most
-// kSmallPatch DOFs, the interior ones): the thread gathers its subdomain's
-// residual entries once (its DOFs are stored subdomain-minor, so the loads
-// coalesce) and computes every row of M_p E_p r, written row-major over the
-// small subdomains (coalesced stores).  Blocks past nb_small take one entry
-// each of the larger (boundary) subdomains as k_patch_solve does.  Every row
-// is summed in the order of k_patch_solve, so the corrections agree bit for
-// bit; k_dof_update reads them through the relabelled inverse map.
+// Additive Schwarz, step 1, form 4.  Blocks below nb_small: one thread per
+// small subdomain (at most kSmallPatch DOFs, the interior ones); its DOFs are
+// stored subdomain-minor, so the gather coalesces, and its rows of
+// M_p E_p r are written row-major over the small subdomains (coalesced
+// stores).  The other blocks: one wavefront per remaining subdomain; its lanes
+// gather the residual entries into LDS while each lane loads its row of the
+// local inverse (or of the potential map) into registers, then lane t sums
+// row t.  Every row is summed in the order of k_patch_solve, so the
+// corrections agree bit for bit; k_dof_update reads them through the
+// relabelled inverse map.  No load waits on more than one earlier load.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, int nb_small) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
+    const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the stores
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const T *r = a.r + prob * a.svec;
     T *delta = a.delta + prob * a.sdelta;
     if (b < nb_small) {
         const int q = b * kBlock + threadIdx.x;
         if (q >= a.nsmall) return;
-        const int p = a.small[q];
-        const int nn = a.pptr[p + 1] - a.pptr[p];
+        const int4 si = a.sinfo[(int64_t)prob * a.nsmall + q];
+        const int nn = si.x;
         T rv[kSmallPatch];
-        gather_small(a.small_dofs + q, a.nsmall, nn, r, rv);
-        apply_small(a.M + prob * a.sM + a.moff[(int64_t)prob * a.smoff + p], nn, rv, delta + q, a.nsmall);
-        if (a.psi)  // the subdomain's single potential
-            a.beta[prob * a.nbeta + a.qptr[p]] = small_row(a.Q + prob * a.sQ + a.qoff[prob * a.smoff + p], nn, rv);
+#pragma unroll
+        for (int c = 0; c < kSmallPatch; ++c) {  // padded by repetition: always a valid index
+            const T x = r[a.small_dofs[(int64_t)c * a.nsmall + q]];
+            rv[c] = c < nn ? x : T(0);
+        }
+        const T *m = a.M + prob * a.sM + si.y;
+        if (nn == kSmallPatch) {
+            T out[kSmallPatch];
+#pragma unroll
+            for (int row = 0; row < kSmallPatch; ++row) {
+                T acc = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
+                out[row] = acc;
+            }
+            if (!halt)
+#pragma unroll
+                for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
+        } else {
+            for (int row = 0; row < nn; ++row) {
+                const T v = small_row(m + row * nn, nn, rv);
+                if (!halt) delta[(int64_t)row * a.nsmall + q] = v;
+            }
+        }
+        if (a.psi) {  // the subdomain's single potential
+            const T v = small_row(a.Q + prob * a.sQ + si.z, nn, rv);
+            if (!halt) a.beta[prob * a.nbeta + si.w] = v;
+        }
         return;
     }
-    const int t = (b - nb_small) * kBlock + threadIdx.x;
-    if (t < a.nbig) {
-        const int e = a.bigent[t];
-        const int4 info = a.ent_info[(int64_t)prob * a.nent + e];
-        delta[(int64_t)kSmallPatch * a.nsmall + e] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, r);
-    } else if (a.psi && t < a.nbig + a.nbigbeta) {
-        const int e = a.bigbeta[t - a.nbig], p = a.beta_patch[e];
-        const int base = a.pptr[p];
-        a.beta[prob * a.nbeta + e] =
-            patch_row(a.Q + prob * a.sQ + a.beta_row[prob * a.nbeta + e], a.pdofs + base, a.pptr[p + 1] - base, r);
+    extern __shared__ unsigned char smem[];
+    T *sr = reinterpret_cast<T *>(smem) + (threadIdx.x >> 6) * (a.max_big > kBigRegs ? a.max_big : kBigRegs);
+    const int lane = threadIdx.x & 63;
+    const int sb = __builtin_amdgcn_readfirstlane((b - nb_small) * (kBlock / 64) + (int)(threadIdx.x >> 6));
+    const bool live = sb < a.nbsub;
+    const int4 bm = live ? a.bmesh[sb] : make_int4(0, 0, 0, 0);
+    const int2 bp = live ? a.binfo[(int64_t)prob * a.nbsub + sb] : make_int2(0, 0);
+    const int base = bm.x, nn = bm.y, rows = nn + (a.psi ? bm.w : 0);
+    const T *Mp = a.M + prob * a.sM + bp.x;
+    const T *Qp = a.Q ? a.Q + prob * a.sQ + bp.y : nullptr;
+    // lane t's first row: its coefficients into registers (independent of r;
+    // unconditional loads, clamped to the row, so none waits for another)
+    const int t = lane;
+    const T *mr = t >= rows ? Mp : (t < nn ? Mp + (int64_t)t * nn : Qp + (int64_t)(t - nn) * nn);
+    const int last = nn > 0 ? nn - 1 : 0;
+    T mv[kBigRegs];
+#pragma unroll
+    for (int c = 0; c < kBigRegs; ++c) mv[c] = T(0);
+    if (t < rows) {
+#pragma unroll
+        for (int c0 = 0; c0 < kBigRegs; c0 += 8) {
+            if (c0 < nn)  // wave-uniform: only the chunks the row has
+#pragma unroll
+                for (int c = c0; c < c0 + 8; ++c) mv[c] = mr[c < nn ? c : last];  // past nn: times sr = 0
+        }
+    }
+    // the residual entries, zero up to kBigRegs (the padded terms, finite
+    // coefficients times zero, add zero)
+    const int span = nn > kBigRegs ? nn : kBigRegs;
+    for (int c = lane; c < span; c += 64) sr[c] = c < nn ? r[a.pdofs[base + c]] : T(0);
+    __syncthreads();
+    if (t < rows) {
+        T acc = 0;
+#pragma unroll
+        for (int c = 0; c < kBigRegs; ++c) acc = fma(mv[c], sr[c], acc);
+        for (int c = kBigRegs; c < nn; ++c) acc = fma(mr[c], sr[c], acc);
+        if (!halt) {
+            if (t < nn) delta[(int64_t)kSmallPatch * a.nsmall + base + t] = acc;
+            else a.beta[prob * a.nbeta + bm.z + (t - nn)] = acc;
+        }
+    }
+    for (int u = t + 64; u < rows; u += 64) {  // subdomains of more than 64 rows
+        const T *ur = u < nn ? Mp + (int64_t)u * nn : Qp + (int64_t)(u - nn) * nn;
+        T acc = 0;
+        for (int c = 0; c < nn; ++c) acc = fma(ur[c], sr[c], acc);
+        if (!halt) {
+            if (u < nn) delta[(int64_t)kSmallPatch * a.nsmall + base + u] = acc;
+            else a.beta[prob * a.nbeta + bm.z + (u - nn)] = acc;
+        }
     }
 }
 
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
-// subdomain holding DOF j (fixed order, no atomics).
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a) {
+// subdomain holding DOF j (fixed order, no atomics), from the fixed-width
+// inverse map padded to WB columns (WB == 0: walk inv_ptr).  Blocks from nbu
+// on take the potentials tracked by the FP32 cycle: psi += eta * sum of their
+// betas (a block-uniform split, so neither part waits for the other's loads).
+template <int WB, class T>
+__global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a, int nbu) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
+    const int halt = stop_flag(a.stop, prob);  // gates the stores
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int j = b * kBlock + threadIdx.x;
-    const T eta = (T)a.eta[prob * a.seta];
-    if (j >= a.n) {  // potentials (tracked in the FP32 cycle)
-        const int pj = j - a.n;
+    const double eta = uniform_vload(a.eta + prob * a.seta);  // converted at its uses
+    if (b >= nbu) {
+        const int pj = (b - nbu) * kBlock + threadIdx.x;
         if (!a.psi || pj >= a.npsi) return;
         double *psi = a.psi + (int64_t)prob * a.npsi;
+        const T *beta = a.beta + prob * a.nbeta;
         const double u = a.assign ? 0.0 : psi[pj];
-        psi[pj] = fma((double)eta, (double)dof_sum(a.qinv_ptr, a.qinv_pos, a.beta + prob * a.nbeta, pj), u);
+        T sum;
+        if (WB > 0 && a.qinv_w > 0 && a.qinv_w <= WB) sum = ell_sum<(WB > 0 ? WB : 1)>(a.qinv_ell, a.npsi, a.qinv_w, pj, beta);
+        else sum = dof_sum(a.qinv_ptr, a.qinv_pos, beta, pj);
+        if (!halt) psi[pj] = fma((double)(T)eta, (double)sum, u);  // the cycle's damping in T
         return;
     }
+    const int j = b * kBlock + threadIdx.x;
+    if (j >= a.n) return;
     T *U = a.U + prob * a.svec;
     const T *delta = a.delta + prob * a.sdelta;
     const T u = a.assign ? T(0) : U[j];
-    U[j] = fma(eta, dof_sum(a.inv_ptr, a.inv_pos, delta, j), u);
+    T sum;
+    if (WB > 0 && a.inv_w > 0 && a.inv_w <= WB) sum = ell_sum<(WB > 0 ? WB : 1)>(a.inv_ell, a.n, a.inv_w, j, delta);
+    else sum = dof_sum(a.inv_ptr, a.inv_pos, delta, j);
+    if (!halt) U[j] = fma((T)eta, sum, u);
+}
+
+// the DOF update with the width bucket of the level's inverse maps
+template <class T>
+static void launch_dof_update(const PatchArgsT<T> &a, hipStream_t s) {
+    int w = ell_bucket(a.inv_w);
+    if (a.psi && a.qinv_w > 0) w = w ? std::max(w, ell_bucket(a.qinv_w)) : 0;
+    const int nbu = blocks_for(a.n), nbp = a.psi ? blocks_for(a.npsi) : 0;
+    const dim3 grid(padded_grid(nbu + nbp), a.nprob);
+    if (w == 4) hipLaunchKernelGGL((k_dof_update<4, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    else if (w == 8) hipLaunchKernelGGL((k_dof_update<8, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    else if (w == 12) hipLaunchKernelGGL((k_dof_update<12, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    else if (w == 24) hipLaunchKernelGGL((k_dof_update<24, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    else hipLaunchKernelGGL((k_dof_update<0, T>), grid, dim3(kBlock), 0, s, a, nbu);
 }
 
 template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
     hipLaunchKernelGGL(k_patch_solve<T>, dim3(padded_grid(blocks_for(a.nent)), a.nprob), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(a.n)), a.nprob), dim3(kBlock), 0, s, a);
+    launch_dof_update<T>(a, s);
 }
 
 // One-pass form: DOF j recomputes the rows of the local solves that land on
@@ -96,7 +186,7 @@ void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
+    if (stop_flag(a.stop, prob)) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int j = b * kBlock + threadIdx.x;
     const T *r = a.r + prob * a.svec;
@@ -131,10 +221,11 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
 
 template <class T>
 void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s) {
-    const int nbs = blocks_for(a.nsmall), nbb = blocks_for(a.nbig + (a.psi ? a.nbigbeta : 0));
-    hipLaunchKernelGGL(k_patch_solve_small<T>, dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), 0, s, a, nbs);
-    const int64_t rows = a.n + (a.psi ? a.npsi : 0);
-    hipLaunchKernelGGL(k_dof_update<T>, dim3(padded_grid(blocks_for(rows)), a.nprob), dim3(kBlock), 0, s, a);
+    constexpr int waves = kBlock / 64;
+    const int nbs = blocks_for(a.nsmall), nbb = (a.nbsub + waves - 1) / waves;
+    const size_t lds = (size_t)waves * std::max(a.max_big, kBigRegs) * sizeof(T);
+    hipLaunchKernelGGL(k_patch_solve_small<T>, dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds, s, a, nbs);
+    launch_dof_update<T>(a, s);
 }
 
 template <class T>
@@ -149,7 +240,7 @@ void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgsT<T> a, const int32_t *list, int np) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
+    if (stop_flag(a.stop, prob)) return;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= np) return;
     const int p = list[t];
@@ -174,27 +265,36 @@ void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, 
     hipLaunchKernelGGL(k_schwarz_colour<T>, dim3(blocks_for(np), a.nprob), dim3(kBlock), 0, s, a, list, np);
 }
 
-// y = (add ? y : 0) + A x for a CSR matrix (restriction and prolongation).
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v,
-                                                const T *x, int64_t sx, T *y, int64_t sy, int add,
-                                                const int *stop) {
+// y = (add ? y : 0) + A x for a sparse transfer operator (restriction and
+// prolongation), from its fixed-width form padded to WB columns (WB == 0:
+// CSR).
+template <int WB, class T>
+__global__ __launch_bounds__(kBlock) void k_csr(int nrows, SparseT<T> A, const T *x, int64_t sx, T *y, int64_t sy,
+                                                int add, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    const int halt = stop_flag(stop, prob);  // gates the store
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
     x += prob * sx;
     y += prob * sy;
     const T y0 = add ? y[i] : T(0);
-    y[i] = y0 + csr_row(rp, ci, v, x, i);
+    T v;
+    if (WB > 0 && A.w > 0 && A.w <= WB) v = ell_row<(WB > 0 ? WB : 1)>(A.eci, A.ev, nrows, A.w, i, x);
+    else v = csr_row(A.rp, A.ci, A.v, x, i);
+    if (!halt) y[i] = y0 + v;
 }
 
 template <class T>
-void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int64_t sx, T *y,
-                int64_t sy, int add, const int *stop, int nprob, hipStream_t s) {
+void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add, const int *stop,
+                int nprob, hipStream_t s) {
     const dim3 grid(padded_grid(blocks_for(nrows)), nprob);
-    hipLaunchKernelGGL(k_csr<T>, grid, dim3(kBlock), 0, s, nrows, rp, ci, v, x, sx, y, sy, add, stop);
+    const int w = ell_bucket(A.w);
+    if (w == 4) hipLaunchKernelGGL((k_csr<4, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    else if (w == 8) hipLaunchKernelGGL((k_csr<8, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    else if (w == 12) hipLaunchKernelGGL((k_csr<12, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    else if (w == 24) hipLaunchKernelGGL((k_csr<24, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    else hipLaunchKernelGGL((k_csr<0, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
 }
 
 // Dense y = A x (A FP64, row-major rows x cols), one wavefront per row, FP64
@@ -203,12 +303,12 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const double *A, int64_t sA, const T *x,
                                                  int64_t sx, T *y, int64_t sy, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    const int halt = stop_flag(stop, prob);  // block-uniform; gates the store
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
     const double acc = gemv_row_wave(A + prob * sA, cols, x + prob * sx, row, lane);
-    if (lane == 0) y[prob * sy + row] = (T)acc;
+    if (lane == 0 && !halt) y[prob * sy + row] = (T)acc;
 }
 
 template <class T>
@@ -222,12 +322,12 @@ void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, in
 __global__ __launch_bounds__(kBlock) void k_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x,
                                                      int64_t sx, double *y, int64_t sy, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    const int halt = stop_flag(stop, prob);
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
     const double acc = gemv_row_wave(A + prob * sA, cols, x + prob * sx, row, lane);
-    if (lane == 0) y[prob * sy + row] = acc;
+    if (lane == 0 && !halt) y[prob * sy + row] = acc;
 }
 
 void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x, int64_t sx, double *y,
@@ -240,9 +340,9 @@ void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const floa
 template <class T>
 __global__ void k_fill(int64_t n, T *x, int64_t sx, T v, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    const int halt = stop_flag(stop, prob);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[prob * sx + i] = v;
+    if (i < n && !halt) x[prob * sx + i] = v;
 }
 template <class T>
 void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s) {
@@ -252,9 +352,11 @@ void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, h
 
 __global__ void k_cast(int64_t n, const double *x, float *y, int64_t sv, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    const int halt = stop_flag(stop, prob);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) y[prob * sv + i] = (float)x[prob * sv + i];
+    if (i >= n) return;
+    const float v = (float)x[prob * sv + i];
+    if (!halt) y[prob * sv + i] = v;
 }
 void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s) {
     if (n <= 0) return;
@@ -265,7 +367,7 @@ void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *
 // differences of the derivative formula (psi = 0 on the boundary).
 __global__ void k_curl_update_2d(RefineArgs a) {
     const int prob = blockIdx.y;
-    if (a.stop && a.stop[prob]) return;
+    const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the store
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= a.n) return;
     const int m = a.N + a.k - 1, nq = a.N + a.k;
@@ -285,7 +387,8 @@ __global__ void k_curl_update_2d(RefineArgs a) {
     } else {
         du = (double)a.X[prob * a.svec + g];
     }
-    a.U[prob * a.svec + g] += du;
+    const double u = a.U[prob * a.svec + g];
+    if (!halt) a.U[prob * a.svec + g] = u + du;
 }
 
 void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
@@ -300,10 +403,10 @@ template void launch_schwarz_small<float>(const PatchArgsT<float> &, hipStream_t
 template void launch_schwarz_fused<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);
-template void launch_csr<double>(int, const int32_t *, const int32_t *, const double *, const double *, int64_t,
-                                 double *, int64_t, int, const int *, int, hipStream_t);
-template void launch_csr<float>(int, const int32_t *, const int32_t *, const float *, const float *, int64_t, float *,
-                                int64_t, int, const int *, int, hipStream_t);
+template void launch_csr<double>(int, const SparseT<double> &, const double *, int64_t, double *, int64_t, int,
+                                 const int *, int, hipStream_t);
+template void launch_csr<float>(int, const SparseT<float> &, const float *, int64_t, float *, int64_t, int, const int *,
+                                int, hipStream_t);
 template void launch_gemv<double>(int, int, const double *, int64_t, const double *, int64_t, double *, int64_t,
                                   const int *, int, hipStream_t);
 template void launch_gemv<float>(int, int, const double *, int64_t, const float *, int64_t, float *, int64_t,
@@ -321,7 +424,7 @@ void launch_fill_int(int n, int *x, int v, hipStream_t s) {
 
 __global__ void k_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop) {
     const int prob = blockIdx.y;
-    if (stop && stop[prob]) return;
+    if (stop_flag(stop, prob)) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) y[prob * sy + i] = x[prob * sx + i];
 }
@@ -387,11 +490,12 @@ void launch_reduce(int nparts, const double *partial, int64_t spart, double *out
 }
 
 __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *partial, int64_t spart, double *hist,
-                                                  int max_hist, int *counter, int *stop, const double *thresh2,
-                                                  Fallback fb) {
+                                                  int max_hist, int *counter, int *stop, int *stopw,
+                                                  const double *thresh2, Fallback fb) {
     const int prob = blockIdx.x;
     if (stop[prob]) return;
     __shared__ double sh[kBlock / 64];
+    __shared__ int flag;
     const double s = ordered_sum(nparts, partial + prob * spart, sh);
     if (threadIdx.x == 0) {
         double *h = hist + (int64_t)prob * max_hist;
@@ -401,10 +505,11 @@ __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *part
         counter[prob] = c + 1;
         const bool grow = c > 0 && res > 1e6 * h[0];  // growth by six orders: diverging
         const bool can_fall = fb.rho && fb.rho[prob] > 0.0 && !fb.flag[prob];
+        int f = 0;
         if (!(s <= 1e300)) {
-            stop[prob] = 2;  // NaN or Inf
+            f = 2;  // NaN or Inf
         } else if (s <= thresh2[prob]) {
-            stop[prob] = 1;
+            f = 1;
         } else if (can_fall && (grow || (c >= 2 && c <= max_hist && res > 1.05 * fb.rho[prob] * h[c - 1]))) {
             // the learned dampings contract worse than the fixed ones did:
             // continue with the fixed dampings (the iteration stays linear,
@@ -412,14 +517,18 @@ __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *part
             fb.flag[prob] = 1;
             for (int l = 1; l < fb.L; ++l) fb.eta[(int64_t)prob * fb.L + l] = fb.eta_fixed[(int64_t)prob * fb.L + l];
         } else if (grow) {
-            stop[prob] = 2;
+            f = 2;
         }
+        if (f) stop[prob] = f;
+        flag = f;
     }
+    __syncthreads();
+    if (flag && threadIdx.x < kStopLanes) stopw[prob * kStopLanes + threadIdx.x] = flag;
 }
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s) {
+                  int *stop, int *stopw, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s) {
     hipLaunchKernelGGL(k_check, dim3(nprob), dim3(kBlock), 0, s, nparts, partial, spart, hist, max_hist, counter,
-                       stop, thresh2, fb);
+                       stop, stopw, thresh2, fb);
 }
 
 __global__ void k_sub_scalar(int n, double *x, int64_t sx, const double *m) {

@@ -11,7 +11,13 @@
 // once a problem's residual check has met the tolerance (or detected
 // divergence) the remaining kernels leave that problem's outputs untouched,
 // so cycles launched ahead of the host check are no-ops for it and its
-// iterate is the one at which the check fired.
+// iterate is the one at which the check fired.  The cycle kernels take the
+// flags in their wide form: kStopLanes copies per problem, lane i of a
+// wavefront reading copy i (the check writes all of them).  Kernels whose time
+// is set by the latency of their load chains read the flag beside their other
+// loads and skip only the stores (a per-lane address keeps the compiler from
+// waiting for the flag before the other loads); the bandwidth-bound residual
+// of large grids returns before loading anything.
 //
 // Value type T is double (plain FP64 path) or float (the V-cycle inside the
 // FP64 iterative refinement); the coarse-grid matrix is always FP64.
@@ -26,6 +32,7 @@
 namespace dfmg {
 
 constexpr int kBlock = 256;
+constexpr int kStopLanes = 64;  // copies per problem of the wide stop flags
 
 // One level's stencil-ELL operator and the vectors of r = F - K U.
 template <class T>
@@ -44,7 +51,7 @@ struct SpmvArgsT {
     int64_t svec;       // per-problem stride of F, U, r
     double *partial;    // per-block sum of r^2 (nullable)
     int64_t spart;      // per-problem stride of partial
-    const int *stop;    // per-problem flags (nullable)
+    const int *stop;    // per-problem flags, wide form (nullable)
     int nprob;
 };
 using SpmvArgs = SpmvArgsT<double>;
@@ -83,6 +90,18 @@ struct PatchArgsT {
     const int32_t *qoff;      // per problem (stride smoff): offset of each subdomain's map in Q
     const int32_t *beta_row;  // per problem (stride nbeta): Q row of each beta entry
     const int32_t *qptr, *beta_patch, *bigbeta, *qinv_ptr, *qinv_pos;  // shared
+    // form 4: small subdomain q of problem prob has sinfo[prob * nsmall + q] =
+    // (size, offset of its inverse in M, offset of its map in Q, its beta
+    // entry); the others (one wavefront each) bmesh[s] = (first entry, size,
+    // first beta entry, beta count), shared, and binfo[prob * nbsub + s] =
+    // (inverse offset, map offset); max_big = their largest size
+    const int4 *sinfo, *bmesh;
+    const int2 *binfo;
+    int nbsub, max_big;
+    // fixed-width forms of the inverse maps in use (inv_w == 0: walk inv_ptr;
+    // qinv_w == 0: walk qinv_ptr)
+    const int32_t *inv_ell, *qinv_ell;
+    int inv_w, qinv_w;
 };
 using PatchArgs = PatchArgsT<double>;
 
@@ -133,10 +152,20 @@ template <class T>
 void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s);
-// y = (add ? y : 0) + A x, A shared CSR; x, y per problem (strides sx, sy)
+// A sparse transfer operator shared by the batch: CSR, and its fixed-width
+// form when w > 0 (column u of row i at u * rows + i, index -1 unused).
 template <class T>
-void launch_csr(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int64_t sx, T *y,
-                int64_t sy, int add, const int *stop, int nprob, hipStream_t s);
+struct SparseT {
+    const int32_t *rp, *ci;
+    const T *v;
+    int w;
+    const int32_t *eci;
+    const T *ev;
+};
+// y = (add ? y : 0) + A x; x, y per problem (strides sx, sy)
+template <class T>
+void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add, const int *stop,
+                int nprob, hipStream_t s);
 // y = A x with A row-major FP64 (rows x cols) per problem (stride sA), x, y in
 // T, FP64 accumulation
 template <class T>
@@ -174,9 +203,10 @@ struct Fallback {
     int L;
 };
 // per problem residual check: hist[p][counter[p]] = sqrt(sum), stop[p] = 1 if
-// sum <= thresh2[p], 2 on NaN/Inf/growth
+// sum <= thresh2[p], 2 on NaN/Inf/growth; stopw[p * kStopLanes + i] = stop[p]
+// (the wide form the cycle kernels read)
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s);
+                  int *stop, int *stopw, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s);
 // per problem: x[p * sx + i] -= m[p] for i < n
 void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s);
 

@@ -93,6 +93,29 @@ __device__ __forceinline__ T dof_sum(const int32_t *inv_ptr, const int32_t *inv_
     return acc;
 }
 
+// The same sum from the fixed-width map (W <= WB columns of `rows` rows, -1
+// unused): every index load, then every correction load, is issued at once,
+// so a DOF costs two dependent loads however many subdomains hold it.  All WB
+// slots load unconditionally (slots past W re-read column W - 1, unused
+// entries read delta[0]) and unused ones add zero: a branch around a load
+// would make the compiler wait for that load before the next one.
+template <int WB, class T>
+__device__ __forceinline__ T ell_sum(const int32_t *ell, int64_t rows, int W, int64_t j, const T *delta) {
+    int pos[WB];
+#pragma unroll
+    for (int w = 0; w < WB; ++w) {
+        const int p = ell[(int64_t)(w < W ? w : W - 1) * rows + j];
+        pos[w] = w < W ? p : -1;
+    }
+    T dv[WB];
+#pragma unroll
+    for (int w = 0; w < WB; ++w) dv[w] = delta[pos[w] >= 0 ? pos[w] : 0];
+    T acc = 0;
+#pragma unroll
+    for (int w = 0; w < WB; ++w) acc += pos[w] >= 0 ? dv[w] : T(0);
+    return acc;
+}
+
 // (A x)_i of a CSR matrix, gathers issued 4 at a time.
 template <class T>
 __device__ __forceinline__ T csr_row(const int32_t *rp, const int32_t *ci, const T *v, const T *x, int i) {
@@ -112,6 +135,30 @@ __device__ __forceinline__ T csr_row(const int32_t *rp, const int32_t *ci, const
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = fma(w[u], xv[u], acc);
     }
+    return acc;
+}
+
+// The same row from the fixed-width form of A (W <= WB columns, index -1
+// unused), loaded as in ell_sum: all indices and coefficients, then all
+// gathers; unused slots read x[0] and add nothing.
+template <int WB, class T>
+__device__ __forceinline__ T ell_row(const int32_t *ci, const T *v, int64_t rows, int W, int64_t i, const T *x) {
+    int col[WB];
+    T w[WB];
+#pragma unroll
+    for (int u = 0; u < WB; ++u) {
+        const int64_t at = (int64_t)(u < W ? u : W - 1) * rows + i;
+        const int c = ci[at];
+        const T wv = v[at];
+        col[u] = u < W ? c : -1;
+        w[u] = wv;
+    }
+    T xv[WB];
+#pragma unroll
+    for (int u = 0; u < WB; ++u) xv[u] = x[col[u] >= 0 ? col[u] : 0];
+    T acc = 0;
+#pragma unroll
+    for (int u = 0; u < WB; ++u) acc = col[u] >= 0 ? fma(w[u], xv[u], acc) : acc;
     return acc;
 }
 

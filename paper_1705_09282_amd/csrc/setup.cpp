@@ -863,6 +863,28 @@ static void build_coarse_potentials(const Problem &pb, HostLevel &L) {
     left_solve(nv, np, n, C, L.Kinv.data(), L.Q0);
 }
 
+// Fixed-width form of a CSR map with `rows` rows (see kEllMax): returns the
+// width, 0 (nothing stored) when a row is longer than kEllMax.  val may be
+// null (index maps).
+static int to_ell(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, const std::vector<double> *val,
+                  std::vector<int32_t> &eci, std::vector<double> *ev) {
+    const int64_t rows = (int64_t)rp.size() - 1;
+    int w = 0;
+    for (int64_t i = 0; i < rows; ++i) w = std::max(w, rp[i + 1] - rp[i]);
+    eci.clear();
+    if (ev) ev->clear();
+    if (w > kEllMax || rows <= 0) return 0;
+    eci.assign((size_t)w * rows, -1);
+    if (ev) ev->assign((size_t)w * rows, 0.0);
+    for (int64_t i = 0; i < rows; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const size_t at = (size_t)(e - rp[i]) * rows + i;
+            eci[at] = ci[e];
+            if (ev) (*ev)[at] = (*val)[e];
+        }
+    return w;
+}
+
 // layout of smoother form 4 (see HostLevel), after the small list is final
 static void finalize_small(HostLevel &L) {
     const int64_t ns = (int64_t)L.small_list.size();
@@ -880,6 +902,26 @@ static void finalize_small(HostLevel &L) {
         if (v > INT32_MAX) throw std::runtime_error("correction buffer exceeds 2^31 entries");
         L.inv_pos4[e] = (int32_t)v;
     }
+    std::vector<char> small(L.n_patch, 0);
+    for (int32_t p : L.small_list) small[p] = 1;
+    L.big_sub.clear();
+    L.big_mesh.clear();
+    L.max_big = 0;
+    const bool pot = !L.qptr.empty();
+    for (int32_t p = 0; p < (int32_t)L.n_patch; ++p) {
+        if (small[p]) continue;
+        const int nn = L.pptr[p + 1] - L.pptr[p];
+        L.big_sub.push_back(p);
+        L.big_mesh.insert(L.big_mesh.end(),
+                          {L.pptr[p], nn, pot ? L.qptr[p] : 0, pot ? L.qptr[p + 1] - L.qptr[p] : 0});
+        L.max_big = std::max(L.max_big, nn);
+    }
+    L.inv_w = to_ell(L.inv_ptr, L.inv_pos, nullptr, L.inv_ell, nullptr);
+    if (L.inv_w) to_ell(L.inv_ptr, L.inv_pos4, nullptr, L.inv4_ell, nullptr);
+    L.qinv_w = pot ? to_ell(L.qinv_ptr, L.qinv_pos, nullptr, L.qinv_ell, nullptr) : 0;
+    L.P_w = to_ell(L.P_rp, L.P_ci, &L.P_v, L.P_eci, &L.P_ev);
+    L.R_w = to_ell(L.R_rp, L.R_ci, &L.R_v, L.R_eci, &L.R_ev);
+    L.Ps_w = pot ? to_ell(L.Ps_rp, L.Ps_ci, &L.Ps_v, L.Ps_eci, &L.Ps_ev) : 0;
 }
 
 // -------------------------------------------------------------- prolongation

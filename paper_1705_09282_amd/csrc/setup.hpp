@@ -99,6 +99,16 @@ struct HostLevel {
     // subdomain q (kSmallPatch per subdomain, padded by repetition), and
     // inv_pos4 relabels inv_pos in that layout (same order).
     std::vector<int32_t> small_dofs, inv_pos4;
+    // the subdomains outside small_list (one wavefront each in form 4):
+    // big_sub[s] and big_mesh[4 s .. 4 s + 3] = (first entry pptr[p], size,
+    // first beta entry qptr[p], number of local potentials; both 0 when the
+    // potentials are not built); max_big = largest size
+    std::vector<int32_t> big_sub, big_mesh;
+    int max_big = 0;
+    // fixed-width forms of inv_pos, inv_pos4 and qinv_pos (see kEllMax);
+    // width 0: not stored
+    int inv_w = 0, qinv_w = 0;
+    std::vector<int32_t> inv_ell, inv4_ell, qinv_ell;
     // potential form of the FP32 cycle (2D): the streamfunction coefficient
     // (a, b), a, b in [1, N+k-1], is stored at (a-1) + (N+k-1)(b-1), the same
     // index as the subdomain that is its support.  Per subdomain i: its local
@@ -118,9 +128,13 @@ struct HostLevel {
     // n_psi x n row-major
     std::vector<double> Q0;
     int max_patch = 0;
-    // prolongation from level-1 (CSR, rows = this level) and restriction
+    // prolongation from level-1 (CSR, rows = this level) and restriction,
+    // with their fixed-width forms (width 0: not stored); also of Ps
     std::vector<int32_t> P_rp, P_ci, R_rp, R_ci;
     std::vector<double> P_v, R_v;
+    int P_w = 0, R_w = 0, Ps_w = 0;
+    std::vector<int32_t> P_eci, R_eci, Ps_eci;
+    std::vector<double> P_ev, R_ev, Ps_ev;
     // coarse level: leading n x n block of the bordered inverse
     std::vector<double> Kinv;
 };

@@ -5,8 +5,11 @@
 namespace dfmg {
 
 // r = F - K U, optionally with per-block partial sums of r^2.  Each block
-// covers kBlock / LPR rows.
-template <int D, int K, int LPR, bool WIN, class T>
+// covers kBlock / LPR rows.  A stopped problem's blocks return at once
+// (GATE false: large grids, where the loads cost bandwidth), or load as usual
+// and skip the stores (GATE true: small grids, where the flag's load would
+// otherwise add its latency in front of every other load).
+template <int D, int K, int LPR, bool WIN, bool GATE, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     const int prob = blockIdx.y;
     a.val += prob * a.sval;
@@ -14,7 +17,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     a.U += prob * a.svec;
     a.r += prob * a.svec;
     if (a.partial) a.partial += prob * a.spart;
-    if (a.stop && a.stop[prob]) return;  // block-uniform: the problem has stopped
+    const int halt = stop_flag(a.stop, prob);  // block-uniform
+    if (!GATE && halt) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int lane = (LPR > 1) ? (threadIdx.x % LPR) : 0;
     const int g = b * (kBlock / LPR) + threadIdx.x / LPR;
@@ -38,28 +42,38 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o, 64);
     if (active && lane == 0) {
         const T v = a.F[g] - acc;
-        a.r[g] = v;
+        if (!halt) a.r[g] = v;
         rr = (double)v * (double)v;
     }
     if (a.partial) {
         __shared__ double sh[kBlock / 64];
         const double s = block_sum(rr, sh);
-        if (threadIdx.x == 0 && b < a.nblocks) a.partial[b] = s;
+        if (threadIdx.x == 0 && b < a.nblocks && !halt) a.partial[b] = s;
     }
 }
 
-template <int D, int K, bool WIN, class T>
-static void launch_dkw(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
+template <int D, int K, bool WIN, bool GATE, class T>
+static void launch_dkwg(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
     const dim3 grid(padded_grid(a.nblocks), a.nprob);
-    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, WIN, T>), grid, dim3(kBlock), 0, s, a);
-    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, WIN, T>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_spmv<D, K, 1, WIN, T>), grid, dim3(kBlock), 0, s, a);
+    if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, WIN, GATE, T>), grid, dim3(kBlock), 0, s, a);
+    else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, WIN, GATE, T>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_spmv<D, K, 1, WIN, GATE, T>), grid, dim3(kBlock), 0, s, a);
 }
+
+// rows per problem below which a stopped problem's blocks gate their stores
+// instead of returning at once (latency-bound launches)
+constexpr int kGateRows = 1 << 16;
 
 template <int D, int K, class T>
 static void launch_dk(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
-    if (a.win) launch_dkw<D, K, true, T>(a, lpr, s);
-    else launch_dkw<D, K, false, T>(a, lpr, s);
+    const bool gate = a.n < kGateRows;
+    if (a.win) {
+        if (gate) launch_dkwg<D, K, true, true, T>(a, lpr, s);
+        else launch_dkwg<D, K, true, false, T>(a, lpr, s);
+    } else {
+        if (gate) launch_dkwg<D, K, false, true, T>(a, lpr, s);
+        else launch_dkwg<D, K, false, false, T>(a, lpr, s);
+    }
 }
 
 // a.nblocks must equal spmv_blocks(a.n, lpr)

@@ -59,7 +59,7 @@ template <int D, int K, class T>
 __global__ __launch_bounds__(kSmallBlock) void k_vcycle_small(const SmallLevel<T> *__restrict__ lv, int top,
                                                               const int *stop) {
     const int prob = blockIdx.x;
-    if (stop && stop[prob]) return;
+    if (stop_flag(stop, prob)) return;
     for (int l = top; l >= 1; --l) {
         const SmallLevel<T> &L = lv[l];
         T *F = L.F + prob * L.n, *U = L.U + prob * L.n, *r = L.r + prob * L.n;

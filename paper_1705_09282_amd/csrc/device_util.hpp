@@ -37,6 +37,16 @@ __device__ __forceinline__ int stop_flag(const int *stopw, int prob) {
     return stopw ? stopw[prob * kStopLanes + lane] : kNoStop[lane];
 }
 
+// A load from a wave-uniform address of data the kernel does not write (the
+// local inverses): through the constant address space, so the compiler reads
+// it with scalar loads (one per wave, from the scalar cache) instead of one
+// vector load per lane.
+template <class T>
+__device__ __forceinline__ T scalar_ld(const T *p) {
+    return *reinterpret_cast<const __attribute__((address_space(4))) T *>(
+        reinterpret_cast<uintptr_t>(p));
+}
+
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 // Sum over the block (wave shuffles, then the waves in a fixed order); the

@@ -48,7 +48,23 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, i
             rv[c] = c < nn ? x : T(0);
         }
         const T *m = a.M + prob * a.sM + si.y;
-        if (nn == kSmallPatch) {
+        const int m0 = __builtin_amdgcn_readfirstlane(si.y);
+        if (__all(si.y == m0) && __builtin_amdgcn_readfirstlane(nn) == kSmallPatch) {
+            // the wave shares one inverse (the interior class): read it with
+            // scalar loads instead of one vector load per lane
+            const T *mu = a.M + prob * a.sM + m0;
+            T out[kSmallPatch];
+#pragma unroll
+            for (int row = 0; row < kSmallPatch; ++row) {
+                T acc = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c) acc = fma(scalar_ld(mu + row * kSmallPatch + c), rv[c], acc);
+                out[row] = acc;
+            }
+            if (!halt)
+#pragma unroll
+                for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
+        } else if (nn == kSmallPatch) {
             T out[kSmallPatch];
 #pragma unroll
             for (int row = 0; row < kSmallPatch; ++row) {
@@ -67,7 +83,16 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, i
             }
         }
         if (a.psi) {  // the subdomain's single potential
-            const T v = small_row(a.Q + prob * a.sQ + si.z, nn, rv);
+            const int z0 = __builtin_amdgcn_readfirstlane(si.z);
+            T v;
+            if (__all(si.z == z0) && __builtin_amdgcn_readfirstlane(nn) == kSmallPatch) {
+                const T *qu = a.Q + prob * a.sQ + z0;
+                v = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c) v = fma(scalar_ld(qu + c), rv[c], v);
+            } else {
+                v = small_row(a.Q + prob * a.sQ + si.z, nn, rv);
+            }
             if (!halt) a.beta[prob * a.nbeta + si.w] = v;
         }
         return;

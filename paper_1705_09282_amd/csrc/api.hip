@@ -434,6 +434,25 @@ void prolong_add(dfmg_ctx *c, int l, const T *dU, T *U, const int *stop) {
     launch_csr<T>((int)hf.n, P, dU, hc.n, U, hf.n, 1, stop, c->np, c->s);
 }
 
+// the FP32 cycle's prolongation with its potentials, one launch
+void prolong_pair(dfmg_ctx *c, int l, const int *stop) {
+    const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
+    DevLevel &f = c->dl[l];
+    const DevLevel &q = c->dl[l - 1];
+    const SparseT<float> P{f.P_rp, f.P_ci, f.f.P_v, hf.P_w, f.P_eci, f.f.P_ev};
+    const SparseT<double> Ps{f.Ps_rp, f.Ps_ci, f.Ps_v, hf.Ps_w, f.Ps_eci, f.Ps_ev};
+    launch_prolong_pair<float>((int)hf.n, P, q.f.U, hc.n, f.f.U, hf.n, (int)f.npsi, Ps, q.psi, q.npsi, f.psi, f.npsi,
+                               stop, c->np, c->s);
+}
+
+// the FP32 cycle's exact coarse solve with the potentials of its solution
+void coarse_pair(dfmg_ctx *c, const int *stop) {
+    const DevLevel &z = c->dl[0];
+    const int64_t n = z.n;
+    launch_coarse_pair((int)n, (int)z.npsi, z.Kinv, n * n, z.Q0, z.npsi * n, z.f.F, n, z.f.U, n, z.psi, z.npsi, stop,
+                       c->np, c->s);
+}
+
 // exact coarse solve (FP64 bordered inverse, FP64 accumulation)
 template <class T>
 void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
@@ -582,21 +601,18 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
     }
     if (top >= 1)
         launch_vcycle_small<T>(c->S().pb.d, c->S().pb.k, small_table<T>(c), top, stop, c->np, c->s);
+    else if (psi)  // with the potentials of the coarse velocity solution
+        coarse_pair(c, stop);
     else
         coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
-    if (psi) {  // potentials of the coarse velocity solution
+    if (psi && top >= 1) {  // potentials of the coarse velocity solution
         const DevLevel &z = c->dl[0];
         launch_gemv_f2d((int)z.npsi, (int)z.n, z.Q0, z.npsi * z.n, z.f.F, z.n, z.psi, z.npsi, stop, c->np, c->s);
     }
     for (int l = top + 1; l < L; ++l) {
         LevelData<T> &v = c->dl[l].data<T>();
-        prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
-        if (psi) {
-            DevLevel &f = c->dl[l];
-            const DevLevel &q = c->dl[l - 1];
-            const SparseT<double> Ps{f.Ps_rp, f.Ps_ci, f.Ps_v, c->S().lv[l].Ps_w, f.Ps_eci, f.Ps_ev};
-            launch_csr<double>((int)f.npsi, Ps, q.psi, q.npsi, f.psi, f.npsi, 1, stop, c->np, c->s);
-        }
+        if (psi) prolong_pair(c, l, stop);
+        else prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
         for (int s = 0; s < c->nu2l[l]; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
             schwarz<T>(c, l, v.r, v.U, false, stop);

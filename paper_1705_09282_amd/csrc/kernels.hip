@@ -260,34 +260,44 @@ void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s) {
 }
 
 // Coloured scatter form: the subdomains of one colour hold disjoint DOFs, so
-// each thread solves one subdomain and adds its damped correction with plain
-// read-modify-writes.
+// each subdomain adds its damped correction with plain read-modify-writes.
+// One wavefront per subdomain: the lanes gather its residual entries into
+// LDS, then lane t sums row t (the order of patch_row) and updates DOF t.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgsT<T> a, const int32_t *list, int np) {
+__global__ __launch_bounds__(kBlock) void k_schwarz_colour(PatchArgsT<T> a, const int32_t *list, int np, int width) {
     const int prob = blockIdx.y;
-    if (stop_flag(a.stop, prob)) return;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= np) return;
-    const int p = list[t];
+    const int halt = stop_flag(a.stop, prob);
+    extern __shared__ unsigned char smem[];
+    T *sr = reinterpret_cast<T *>(smem) + (threadIdx.x >> 6) * width;
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6));
+    const bool live = t < np;
+    const int p = live ? list[t] : 0;
     const int base = a.pptr[p];
-    const int nn = a.pptr[p + 1] - base;
+    const int nn = live ? a.pptr[p + 1] - base : 0;
     const int32_t *dofs = a.pdofs + base;
     const T *m = a.M + prob * a.sM + a.moff[prob * a.smoff + p];
     const T *r = a.r + prob * a.svec;
     T *U = a.U + prob * a.svec;
-    const T eta = (T)a.eta[prob * a.seta];
-    for (int row = 0; row < nn; ++row) {
+    const T eta = (T)uniform_vload(a.eta + prob * a.seta);
+    for (int c = lane; c < nn; c += 64) sr[c] = r[dofs[c]];
+    __syncthreads();
+    for (int row = lane; row < nn; row += 64) {
         T acc = 0;
-        for (int c = 0; c < nn; ++c) acc = fma(m[row * nn + c], r[dofs[c]], acc);
+        for (int c = 0; c < nn; ++c) acc = fma(m[row * nn + c], sr[c], acc);
         const int g = dofs[row];
-        U[g] = fma(eta, acc, U[g]);
+        const T u = U[g];
+        if (!halt) U[g] = fma(eta, acc, u);
     }
 }
 
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s) {
     if (np <= 0) return;
-    hipLaunchKernelGGL(k_schwarz_colour<T>, dim3(blocks_for(np), a.nprob), dim3(kBlock), 0, s, a, list, np);
+    constexpr int waves = kBlock / 64;
+    const int width = std::max(a.max_big, kSmallPatch);
+    hipLaunchKernelGGL(k_schwarz_colour<T>, dim3((np + waves - 1) / waves, a.nprob), dim3(kBlock),
+                       (size_t)waves * width * sizeof(T), s, a, list, np, width);
 }
 
 // y = (add ? y : 0) + A x for a sparse transfer operator (restriction and
@@ -320,6 +330,89 @@ void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, in
     else if (w == 12) hipLaunchKernelGGL((k_csr<12, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
     else if (w == 24) hipLaunchKernelGGL((k_csr<24, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
     else hipLaunchKernelGGL((k_csr<0, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+}
+
+// The prolongations of the FP32 cycle in one launch: blocks below nbu add
+// P dU to the velocity-pressure rows (T), the others add Ps psi_coarse to
+// the potentials (FP64), each from its fixed-width form padded to WB columns
+// (WB == 0: CSR).  The same sums as two k_csr launches.
+template <int WB, class T>
+__global__ __launch_bounds__(kBlock) void k_prolong_pair(int nu, SparseT<T> P, const T *xu, int64_t sxu, T *yu,
+                                                         int64_t syu, int nps, SparseT<double> Ps, const double *xp,
+                                                         int64_t sxp, double *yp, int64_t syp, int nbu,
+                                                         const int *stop) {
+    const int prob = blockIdx.y;
+    const int halt = stop_flag(stop, prob);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b < nbu) {
+        const int i = b * kBlock + threadIdx.x;
+        if (i >= nu) return;
+        xu += prob * sxu;
+        yu += prob * syu;
+        const T y0 = yu[i];
+        T v;
+        if (WB > 0 && P.w > 0 && P.w <= WB) v = ell_row<(WB > 0 ? WB : 1)>(P.eci, P.ev, nu, P.w, i, xu);
+        else v = csr_row(P.rp, P.ci, P.v, xu, i);
+        if (!halt) yu[i] = y0 + v;
+        return;
+    }
+    const int i = (b - nbu) * kBlock + threadIdx.x;
+    if (i >= nps) return;
+    xp += prob * sxp;
+    yp += prob * syp;
+    const double y0 = yp[i];
+    double v;
+    if (WB > 0 && Ps.w > 0 && Ps.w <= WB) v = ell_row<(WB > 0 ? WB : 1)>(Ps.eci, Ps.ev, nps, Ps.w, i, xp);
+    else v = csr_row(Ps.rp, Ps.ci, Ps.v, xp, i);
+    if (!halt) yp[i] = y0 + v;
+}
+
+template <class T>
+void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, T *yu, int64_t syu, int nps,
+                         const SparseT<double> &Ps, const double *xp, int64_t sxp, double *yp, int64_t syp,
+                         const int *stop, int nprob, hipStream_t s) {
+    const int bp = ell_bucket(P.w), bq = ell_bucket(Ps.w);
+    const int w = (bp && bq) ? std::max(bp, bq) : 0;
+    const int nbu = blocks_for(nu);
+    const dim3 grid(padded_grid(nbu + blocks_for(nps)), nprob);
+#define DFMG_PAIR(W)                                                                                            \
+    hipLaunchKernelGGL((k_prolong_pair<W, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu, nps, Ps, xp, \
+                       sxp, yp, syp, nbu, stop)
+    if (w == 4) DFMG_PAIR(4);
+    else if (w == 8) DFMG_PAIR(8);
+    else if (w == 12) DFMG_PAIR(12);
+    else if (w == 24) DFMG_PAIR(24);
+    else DFMG_PAIR(0);
+#undef DFMG_PAIR
+}
+
+// The exact coarse solve of the FP32 cycle with the potentials of its
+// solution in one launch: rows below n give y = Kinv x (T), the others
+// psi = Q0 x (FP64); one wavefront per row, FP64 accumulation.
+__global__ __launch_bounds__(kBlock) void k_coarse_pair(int n, int nps, const double *Kinv, int64_t sK,
+                                                        const double *Q0, int64_t sQ, const float *x, int64_t sx,
+                                                        float *y, int64_t sy, double *psi, int64_t sp,
+                                                        const int *stop) {
+    const int prob = blockIdx.y;
+    const int halt = stop_flag(stop, prob);
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n + nps) return;
+    if (row < n) {
+        const double acc = gemv_row_wave(Kinv + prob * sK, n, x + prob * sx, row, lane);
+        if (lane == 0 && !halt) y[prob * sy + row] = (float)acc;
+    } else {
+        const double acc = gemv_row_wave(Q0 + prob * sQ, n, x + prob * sx, row - n, lane);
+        if (lane == 0 && !halt) psi[prob * sp + row - n] = acc;
+    }
+}
+
+void launch_coarse_pair(int n, int nps, const double *Kinv, int64_t sK, const double *Q0, int64_t sQ, const float *x,
+                        int64_t sx, float *y, int64_t sy, double *psi, int64_t sp, const int *stop, int nprob,
+                        hipStream_t s) {
+    const int rows_per = kBlock / 64;
+    hipLaunchKernelGGL(k_coarse_pair, dim3((n + nps + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, n, nps,
+                       Kinv, sK, Q0, sQ, x, sx, y, sy, psi, sp, stop);
 }
 
 // Dense y = A x (A FP64, row-major rows x cols), one wavefront per row, FP64
@@ -432,6 +525,9 @@ template void launch_csr<double>(int, const SparseT<double> &, const double *, i
                                  const int *, int, hipStream_t);
 template void launch_csr<float>(int, const SparseT<float> &, const float *, int64_t, float *, int64_t, int, const int *,
                                 int, hipStream_t);
+template void launch_prolong_pair<float>(int, const SparseT<float> &, const float *, int64_t, float *, int64_t, int,
+                                         const SparseT<double> &, const double *, int64_t, double *, int64_t,
+                                         const int *, int, hipStream_t);
 template void launch_gemv<double>(int, int, const double *, int64_t, const double *, int64_t, double *, int64_t,
                                   const int *, int, hipStream_t);
 template void launch_gemv<float>(int, int, const double *, int64_t, const float *, int64_t, float *, int64_t,

@@ -166,6 +166,17 @@ struct SparseT {
 template <class T>
 void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add, const int *stop,
                 int nprob, hipStream_t s);
+// the FP32 cycle's prolongation of the velocity-pressure correction (P) and
+// of the potentials (Ps, FP64) in one launch, both added
+template <class T>
+void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, T *yu, int64_t syu, int nps,
+                         const SparseT<double> &Ps, const double *xp, int64_t sxp, double *yp, int64_t syp,
+                         const int *stop, int nprob, hipStream_t s);
+// the FP32 cycle's coarse solve y = Kinv x and its potentials psi = Q0 x
+// (FP64 matrices, n x n and nps x n per problem) in one launch
+void launch_coarse_pair(int n, int nps, const double *Kinv, int64_t sK, const double *Q0, int64_t sQ, const float *x,
+                        int64_t sx, float *y, int64_t sy, double *psi, int64_t sp, const int *stop, int nprob,
+                        hipStream_t s);
 // y = A x with A row-major FP64 (rows x cols) per problem (stride sA), x, y in
 // T, FP64 accumulation
 template <class T>

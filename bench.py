@@ -89,8 +89,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of MB megabytes (reference for HBM byte counters)")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the timed path's batch, one solve, then the dominant kernel's timing loop "
-                         "(for profiler and counter runs)")
+                    help="only the timed path's batch, one solve, then the dominant kernel's timing loop and "
+                         "200 finest-grid smoothing steps (for profiler and counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -156,10 +156,14 @@ def main():
                 "traffic": measured_traffic(), "alg_bytes_per_launch": alg, "avg_launch_ms": ms}
 
     if args.roofline_only:
+        # the residual's roofline, then 200 finest-grid smoothing steps of the
+        # same batch (the local solves and the per-DOF update, for counter runs)
         b32, F32, U32, _ = make_batch(1, use_learned=True)
         U32.zero_()
         b32.solve(F32, U32, tol=args.tol)
-        print(json.dumps({"roofline": roofline(b32, F32, U32)}), flush=True)
+        out = {"roofline": roofline(b32, F32, U32)}
+        out["fp32_smoothing_step_ms"] = b32.time_kernel(3, args.levels - 1, reps=200)
+        print(json.dumps(out), flush=True)
         b32.close()
         return
 

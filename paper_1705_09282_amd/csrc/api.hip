@@ -46,6 +46,12 @@ struct ArgError : std::runtime_error {
         if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// flag arrays per problem (adjacent on the device and in the host copies):
+// counter, stop, near
+constexpr int kFlagSets = 3;
+// flag states read by the host loop
+constexpr int kAllStopped = 2, kAllNear = 1;
+
 // Typed values and vectors of one level: FP64 for the plain path, FP32 for
 // the V-cycle inside the iterative refinement.  Per problem unless noted.
 template <class T>
@@ -118,9 +124,11 @@ struct dfmg_ctx {
     double *partial = nullptr;   // [problem][block]
     int nparts = 0;
     double *hist = nullptr;      // [problem][DFMG_MAX_HISTORY]
-    int *counter = nullptr, *stop = nullptr;   // adjacent: stop = counter + np
+    // adjacent: counter, stop = counter + np, near = counter + 2 np (stopped or
+    // expected to stop at the next check)
+    int *counter = nullptr, *stop = nullptr, *near = nullptr;
     int *stopw = nullptr;        // wide copies of stop read by the cycle kernels
-    int *hflags = nullptr;       // pinned host copies of counter and stop, two buffers
+    int *hflags = nullptr;       // pinned host copies of counter, stop and near, two buffers
     hipEvent_t ev_flag[2] = {nullptr, nullptr};
     double *thresh2 = nullptr, *scal = nullptr;
     double *dvec = nullptr, *dcoef = nullptr, *pmass = nullptr, *rtmp = nullptr, *wfine = nullptr;
@@ -259,8 +267,9 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->eta = A.take<double>((size_t)L * np);
     c->partial = A.take<double>((size_t)c->nparts * np);
     c->hist = A.take<double>((size_t)DFMG_MAX_HISTORY * np);
-    c->counter = A.take<int>(2 * (size_t)np);
+    c->counter = A.take<int>(kFlagSets * (size_t)np);
     c->stop = c->counter ? c->counter + np : nullptr;
+    c->near = c->counter ? c->counter + 2 * np : nullptr;
     c->stopw = A.take<int>((size_t)kStopLanes * np);
     c->thresh2 = A.take<double>(np);
     c->scal = A.take<double>(np);
@@ -463,6 +472,7 @@ void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
 // every problem running: the flags and their wide copies
 void reset_flags(dfmg_ctx *c) {
     launch_fill_int(c->np, c->stop, 0, c->s);
+    launch_fill_int(c->np, c->near, 0, c->s);
     launch_fill_int(c->np * kStopLanes, c->stopw, 0, c->s);
 }
 
@@ -476,8 +486,7 @@ void check(dfmg_ctx *c, int np_blocks) {
     fb.flag = c->fallback;
     fb.L = c->L();
     launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->stopw,
-                 c->thresh2, fb,
-                 c->np, c->s);
+                 c->near, c->thresh2, fb, c->np, c->s);
 }
 
 // dampings of every problem from the network (device), see dfmg_set_learned
@@ -620,15 +629,26 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
     }
 }
 
-// One step of the FP64 iterative refinement: r = F - K U in FP64 (with the
-// convergence check), inner_cycles FP32 V-cycles on K dU = r from dU = 0,
-// then U += [curl psi; dU_p] in FP64 with psi recovered from dU_x.
-void refine_body(dfmg_ctx *c) {
+// r = F - K U in FP64 with the convergence check, and its FP32 copy as the
+// load of the next FP32 cycles (the check that ends a refinement step and the
+// one before the first).
+void refine_residual(dfmg_ctx *c) {
     const int L = c->L();
     const HostLevel &h = c->S().lv[L - 1];
     DevLevel &v = c->dl[L - 1];
     check(c, spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stopw));
     launch_cast(h.n, v.d.r, v.f.F, h.n, c->stopw, c->np, c->s);
+}
+
+// One step of the FP64 iterative refinement (its residual is in place):
+// inner_cycles FP32 V-cycles on K dU = r from dU = 0, U += [curl psi; dU_p]
+// in FP64 with psi the streamfunction the cycles tracked for dU's velocity,
+// then the residual and check of the new iterate.  The check ends the step,
+// so the step in which a problem converges does no work after it.
+void refine_body(dfmg_ctx *c) {
+    const int L = c->L();
+    const HostLevel &h = c->S().lv[L - 1];
+    DevLevel &v = c->dl[L - 1];
     for (int i = 0; i < c->opt.inner_cycles; ++i) cycle_body<float>(c, false, i == 0);
     RefineArgs a{};
     a.N = c->S().pb.N;
@@ -645,6 +665,7 @@ void refine_body(dfmg_ctx *c) {
     a.stop = c->stopw;
     a.nprob = c->np;
     launch_refine_update_2d(a, c->s);
+    refine_residual(c);
 }
 
 void body(dfmg_ctx *c, int kind) {
@@ -782,35 +803,47 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
     launch_copy_off(n, U, xoff, n, v.U, nullptr, n, np, c->s);
     launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
     launch_reduce(nb, c->partial, c->nparts, c->thresh2, tol * tol, np, c->s);
+    if (solve_kind(c) == 2) refine_residual(c);  // the refinement steps end with their check
+}
+
+// state of host stop flags st[0..np) with the near flags at st + np
+int flag_state(const int *st, int np) {
+    bool all = true, near = true;
+    for (int p = 0; p < np; ++p) {
+        all = all && st[p];
+        near = near && (st[p] || st[np + p]);
+    }
+    return all ? kAllStopped : (near ? kAllNear : 0);
 }
 
 // queue a copy of the counters and stop flags into pinned buffer buf
 void flags_async(dfmg_ctx *c, int buf) {
-    HIPCHK(hipMemcpyAsync(c->hflags + buf * 2 * c->np, c->counter, 2 * c->np * sizeof(int), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(c->hflags + buf * kFlagSets * c->np, c->counter, kFlagSets * c->np * sizeof(int),
+                          hipMemcpyDeviceToHost,
                           c->s));
     HIPCHK(hipEventRecord(c->ev_flag[buf], c->s));
 }
 
-// wait for buffer buf; true when every problem has stopped
-bool flags_wait(dfmg_ctx *c, int buf) {
+// wait for buffer buf: kAllStopped when every problem has stopped, kAllNear
+// when each has stopped or is expected to stop at the next check, else 0
+int flags_wait(dfmg_ctx *c, int buf) {
     HIPCHK(hipEventSynchronize(c->ev_flag[buf]));
-    const int *st = c->hflags + buf * 2 * c->np + c->np;
-    for (int p = 0; p < c->np; ++p)
-        if (!st[p]) return false;
-    return true;
+    return flag_state(c->hflags + buf * kFlagSets * c->np + c->np, c->np);
 }
 
 // Run V-cycles in units of `chunk` until every problem has stopped or max
 // cycles were launched, keeping one unit in flight while the host reads the
 // flags of the previous one (a unit launched after the last problem stopped
-// does no work: every kernel returns at once for stopped problems).
+// does no work for it), except when the flags read say that every problem is
+// expected to stop within the unit in flight: then the next unit waits for
+// its flags (one host round trip instead of a unit of wasted launches).
 // launch_unit(k, buf) launches k cycles and queues the flags into buf;
-// wait(buf) returns whether all problems have stopped.  Returns the buffer
-// holding the last flags read and whether all stopped.
+// wait(buf) returns the flag state.  Returns the buffer holding the last
+// flags read and whether all stopped.
 template <class Launch, class Wait>
 std::pair<int, bool> pipelined_cycles(int maxc, int chunk, Launch &&launch_unit, Wait &&wait) {
     int launched = 0, inflight = 0, next = 0, head = 0, last = 0;
-    bool all = false;
+    bool all = false, near = false;
     auto issue = [&] {
         const int k = std::min(chunk, maxc - launched);
         launch_unit(k, next);
@@ -820,18 +853,24 @@ std::pair<int, bool> pipelined_cycles(int maxc, int chunk, Launch &&launch_unit,
     };
     issue();
     while (inflight > 0) {
-        if (launched < maxc && inflight < 2) issue();
-        all = wait(head);
+        if (launched < maxc && inflight < 2 && !near) issue();
+        const int st = wait(head);
         last = head;
         head ^= 1;
         --inflight;
-        if (all) break;
+        if (st == kAllStopped) {
+            all = true;
+            break;
+        }
+        near = st == kAllNear;
+        if (inflight == 0 && launched < maxc) issue();
     }
     return {last, all};
 }
 
-// cycle limit reached: measure the residual of the last iterates (problems
-// already stopped keep their flags and histories)
+// cycle limit reached with V-cycles that check at their start: measure the
+// residual of the last iterates (problems already stopped keep their flags
+// and histories)
 void solve_limit(dfmg_ctx *c) {
     const int L = c->L();
     LevelData<double> &v = c->dl[L - 1].d;
@@ -1173,9 +1212,9 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
-        HIPCHK(hipMemsetAsync(c->counter, 0, 2 * np * sizeof(int), s));
-        HIPCHK(hipHostMalloc((void **)&c->hflags, 4 * np * sizeof(int), hipHostMallocDefault));
-        std::memset(c->hflags, 0, 4 * np * sizeof(int));
+        HIPCHK(hipMemsetAsync(c->counter, 0, kFlagSets * np * sizeof(int), s));
+        HIPCHK(hipHostMalloc((void **)&c->hflags, 2 * kFlagSets * np * sizeof(int), hipHostMallocDefault));
+        std::memset(c->hflags, 0, 2 * kFlagSets * np * sizeof(int));
         for (auto &e : c->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         upload_small_tables(c);
         HIPCHK(hipStreamSynchronize(s));
@@ -1311,13 +1350,13 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
                 flags_async(c, b);
             },
             [&](int b) { return flags_wait(c, b); });
-        if (!all) {
+        if (!all && kind != 2) {  // (a refinement step already ends with the check of its iterate)
             solve_limit(c);
             buf = 0;
             flags_async(c, buf);
             flags_wait(c, buf);
         }
-        const int *counter = c->hflags + buf * 2 * np, *stopv = counter + np;
+        const int *counter = c->hflags + buf * kFlagSets * np, *stopv = counter + np;
         SolveOut so;
         solve_end_launch(c, U, nullptr, so);
         HIPCHK(hipStreamSynchronize(c->s));
@@ -1742,7 +1781,7 @@ struct dfmg_multi {
     std::vector<size_t> ws_off;            // workspace offset of each group
     size_t ws_tab = 0, ws_flags = 0, ws_total = 0;
     int64_t *tab = nullptr;                // device: caller offsets in group order
-    int *dflags = nullptr;                 // device: counters then stop flags, group order
+    int *dflags = nullptr;                 // device: counters, stop flags, near flags, group order
     int *hflags = nullptr;                 // pinned host copies of dflags, two buffers
     hipEvent_t ev_flag[2] = {nullptr, nullptr};
     dfmg_options opt{};
@@ -1777,12 +1816,14 @@ void mleave(dfmg_multi *m) {
     HIPCHK(hipStreamWaitEvent(m->user, m->ev_out, 0));
 }
 
-// counters and stop flags of every group into dflags (on the batch stream)
+// counters, stop and near flags of every group into dflags (on the batch
+// stream)
 void pack_flags(dfmg_multi *m) {
     for (size_t i = 0; i < m->g.size(); ++i) {
         dfmg_ctx *c = m->g[i];
         launch_copy_int(c->np, c->counter, m->dflags + m->base[i], m->s);
         launch_copy_int(c->np, c->stop, m->dflags + m->nprob + m->base[i], m->s);
+        launch_copy_int(c->np, c->near, m->dflags + 2 * m->nprob + m->base[i], m->s);
     }
 }
 
@@ -1824,16 +1865,13 @@ void multi_drop_graph(dfmg_multi *m) {
 
 // queue a copy of the packed flags into pinned buffer buf / wait for it
 void multi_flags_async(dfmg_multi *m, int buf) {
-    HIPCHK(hipMemcpyAsync(m->hflags + buf * 2 * m->nprob, m->dflags, 2 * m->nprob * sizeof(int),
+    HIPCHK(hipMemcpyAsync(m->hflags + buf * kFlagSets * m->nprob, m->dflags, kFlagSets * m->nprob * sizeof(int),
                           hipMemcpyDeviceToHost, m->s));
     HIPCHK(hipEventRecord(m->ev_flag[buf], m->s));
 }
-bool multi_flags_wait(dfmg_multi *m, int buf) {
+int multi_flags_wait(dfmg_multi *m, int buf) {
     HIPCHK(hipEventSynchronize(m->ev_flag[buf]));
-    const int *st = m->hflags + buf * 2 * m->nprob + m->nprob;
-    for (int i = 0; i < m->nprob; ++i)
-        if (!st[i]) return false;
-    return true;
+    return flag_state(m->hflags + buf * kFlagSets * m->nprob + m->nprob, m->nprob);
 }
 
 void multi_plan(dfmg_multi *m) {
@@ -1848,7 +1886,7 @@ void multi_plan(dfmg_multi *m) {
     m->ws_tab = used;
     used += ((m->nprob * sizeof(int64_t) + 255) & ~(size_t)255);
     m->ws_flags = used;
-    used += ((2 * m->nprob * sizeof(int) + 255) & ~(size_t)255);
+    used += ((kFlagSets * m->nprob * sizeof(int) + 255) & ~(size_t)255);
     m->ws_total = used;
 }
 
@@ -1963,14 +2001,14 @@ int dfmg_multi_bind(dfmg_multi *m, void *ws, size_t bytes, void *stream) {
         HIPCHK(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
         m->ev_join.assign(m->g.size(), nullptr);
         for (auto &e : m->ev_join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        HIPCHK(hipHostMalloc((void **)&m->hflags, 4 * m->nprob * sizeof(int), hipHostMallocDefault));
-        std::memset(m->hflags, 0, 4 * m->nprob * sizeof(int));
+        HIPCHK(hipHostMalloc((void **)&m->hflags, 2 * kFlagSets * m->nprob * sizeof(int), hipHostMallocDefault));
+        std::memset(m->hflags, 0, 2 * kFlagSets * m->nprob * sizeof(int));
         for (auto &e : m->ev_flag) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::vector<int64_t> tab;
         for (const auto &mem : m->member)
             for (int p : mem) tab.push_back(m->off[p]);
         up(m->tab, tab, m->s);
-        HIPCHK(hipMemsetAsync(m->dflags, 0, 2 * m->nprob * sizeof(int), m->s));
+        HIPCHK(hipMemsetAsync(m->dflags, 0, kFlagSets * m->nprob * sizeof(int), m->s));
         HIPCHK(hipStreamSynchronize(m->s));
         m->bound = true;
     });
@@ -2031,7 +2069,7 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
                 multi_flags_async(m, b);
             },
             [&](int b) { return multi_flags_wait(m, b); });
-        if (!all) {
+        if (!all && kind != 2) {  // (a refinement step already ends with the check of its iterate)
             mfork(m);
             for (dfmg_ctx *c : m->g) solve_limit(c);
             mjoin(m);
@@ -2040,7 +2078,7 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
             multi_flags_async(m, buf);
             multi_flags_wait(m, buf);
         }
-        const int *fl = m->hflags + buf * 2 * m->nprob;
+        const int *fl = m->hflags + buf * kFlagSets * m->nprob;
         std::vector<SolveOut> so(G);
         mfork(m);
         for (size_t i = 0; i < G; ++i) solve_end_launch(m->g[i], U, m->tab + m->base[i], so[i]);

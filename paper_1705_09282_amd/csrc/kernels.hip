@@ -612,7 +612,7 @@ void launch_reduce(int nparts, const double *partial, int64_t spart, double *out
 
 __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *partial, int64_t spart, double *hist,
                                                   int max_hist, int *counter, int *stop, int *stopw,
-                                                  const double *thresh2, Fallback fb) {
+                                                  int *near, const double *thresh2, Fallback fb) {
     const int prob = blockIdx.x;
     if (stop[prob]) return;
     __shared__ double sh[kBlock / 64];
@@ -642,14 +642,18 @@ __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *part
         }
         if (f) stop[prob] = f;
         flag = f;
+        // contracting as in the last cycle, the next check meets the threshold
+        const double next = (c > 0 && c <= max_hist && h[c - 1] > 0.0) ? res * (res / h[c - 1]) : 1e300;
+        near[prob] = (f || (c < max_hist && next * next <= thresh2[prob])) ? 1 : 0;
     }
     __syncthreads();
     if (flag && threadIdx.x < kStopLanes) stopw[prob * kStopLanes + threadIdx.x] = flag;
 }
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, int *stopw, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s) {
+                  int *stop, int *stopw, int *near, const double *thresh2, const Fallback &fb, int nprob,
+                  hipStream_t s) {
     hipLaunchKernelGGL(k_check, dim3(nprob), dim3(kBlock), 0, s, nparts, partial, spart, hist, max_hist, counter,
-                       stop, stopw, thresh2, fb);
+                       stop, stopw, near, thresh2, fb);
 }
 
 __global__ void k_sub_scalar(int n, double *x, int64_t sx, const double *m) {

@@ -215,9 +215,12 @@ struct Fallback {
 };
 // per problem residual check: hist[p][counter[p]] = sqrt(sum), stop[p] = 1 if
 // sum <= thresh2[p], 2 on NaN/Inf/growth; stopw[p * kStopLanes + i] = stop[p]
-// (the wide form the cycle kernels read)
+// (the wide form the cycle kernels read); near[p] = 1 when the problem has
+// stopped or, contracting as in its last cycle, will meet the threshold at
+// the next check (a hint for the host's launch-ahead, no effect on results)
 void launch_check(int nparts, const double *partial, int64_t spart, double *hist, int max_hist, int *counter,
-                  int *stop, int *stopw, const double *thresh2, const Fallback &fb, int nprob, hipStream_t s);
+                  int *stop, int *stopw, int *near, const double *thresh2, const Fallback &fb, int nprob,
+                  hipStream_t s);
 // per problem: x[p * sx + i] -= m[p] for i < n
 void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob, hipStream_t s);
 

@@ -49,8 +49,8 @@ struct ArgError : std::runtime_error {
 // flag arrays per problem (adjacent on the device and in the host copies):
 // counter, stop, near
 constexpr int kFlagSets = 3;
-// flag states read by the host loop
-constexpr int kAllStopped = 2, kAllNear = 1;
+// flag states read by the host loop (bits)
+constexpr int kAllNear = 1, kAllStopped = 2, kAnyStopped = 4;
 
 // Typed values and vectors of one level: FP64 for the plain path, FP32 for
 // the V-cycle inside the iterative refinement.  Per problem unless noted.
@@ -137,8 +137,13 @@ struct dfmg_ctx {
     double *rho_plain = nullptr, *eta_fixed = nullptr;
     int *fallback = nullptr;
     bool learned = false;
-    hipGraphExec_t graph = nullptr;
-    int graph_kind = -1;         // 0: FP64 cycle, 1: FP64 cycle with check, 2: refinement step
+    // captured cycles, one per exit mode (0: FP64 cycle, 1: FP64 cycle with
+    // check, 2: refinement step)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_kind[2] = {-1, -1};
+    // 1 once a problem of the running solve has stopped: launches return at
+    // once for stopped problems instead of loading and skipping their stores
+    int exit_mode = 0;
     std::vector<int> smoother;   // per level: 1 gather, 2 colour, 3 one-pass, 4 small-subdomain gather
     int small_top = 0;           // levels 1 .. small_top (and 0) run in the single-workgroup cycle; 0 = off
     SmallLevel<double> *small_d = nullptr;  // device level tables of that cycle
@@ -326,6 +331,7 @@ SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double 
     a.spart = c->nparts;
     a.stop = stop;
     a.nprob = c->np;
+    a.exit_early = c->exit_mode;
     return a;
 }
 
@@ -371,6 +377,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.assign = assign ? 1 : 0;
     a.stop = stop;
     a.nprob = c->np;
+    a.exit_early = c->exit_mode;
     a.small = v.small;
     a.bigent = v.bigent;
     a.small_dofs = v.small_dofs;
@@ -432,7 +439,7 @@ void restrict_to(dfmg_ctx *c, int l, const T *r, T *G, const int *stop) {
     const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
     const SparseT<T> R{v.R_rp, v.R_ci, v.data<T>().R_v, hf.R_w, v.R_eci, v.data<T>().R_ev};
-    launch_csr<T>((int)hc.n, R, r, hf.n, G, hc.n, 0, stop, c->np, c->s);
+    launch_csr<T>((int)hc.n, R, r, hf.n, G, hc.n, 0, stop, c->np, c->s, c->exit_mode);
 }
 
 template <class T>
@@ -440,7 +447,7 @@ void prolong_add(dfmg_ctx *c, int l, const T *dU, T *U, const int *stop) {
     const HostLevel &hc = c->S().lv[l - 1], &hf = c->S().lv[l];
     DevLevel &v = c->dl[l];
     const SparseT<T> P{v.P_rp, v.P_ci, v.data<T>().P_v, hf.P_w, v.P_eci, v.data<T>().P_ev};
-    launch_csr<T>((int)hf.n, P, dU, hc.n, U, hf.n, 1, stop, c->np, c->s);
+    launch_csr<T>((int)hf.n, P, dU, hc.n, U, hf.n, 1, stop, c->np, c->s, c->exit_mode);
 }
 
 // the FP32 cycle's prolongation with its potentials, one launch
@@ -451,7 +458,7 @@ void prolong_pair(dfmg_ctx *c, int l, const int *stop) {
     const SparseT<float> P{f.P_rp, f.P_ci, f.f.P_v, hf.P_w, f.P_eci, f.f.P_ev};
     const SparseT<double> Ps{f.Ps_rp, f.Ps_ci, f.Ps_v, hf.Ps_w, f.Ps_eci, f.Ps_ev};
     launch_prolong_pair<float>((int)hf.n, P, q.f.U, hc.n, f.f.U, hf.n, (int)f.npsi, Ps, q.psi, q.npsi, f.psi, f.npsi,
-                               stop, c->np, c->s);
+                               stop, c->np, c->s, c->exit_mode);
 }
 
 // the FP32 cycle's exact coarse solve with the potentials of its solution
@@ -459,14 +466,14 @@ void coarse_pair(dfmg_ctx *c, const int *stop) {
     const DevLevel &z = c->dl[0];
     const int64_t n = z.n;
     launch_coarse_pair((int)n, (int)z.npsi, z.Kinv, n * n, z.Q0, z.npsi * n, z.f.F, n, z.f.U, n, z.psi, z.npsi, stop,
-                       c->np, c->s);
+                       c->np, c->s, c->exit_mode);
 }
 
 // exact coarse solve (FP64 bordered inverse, FP64 accumulation)
 template <class T>
 void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
     const int64_t n = c->S().lv[0].n;
-    launch_gemv<T>((int)n, (int)n, c->dl[0].Kinv, n * n, G, n, dU, n, stop, c->np, c->s);
+    launch_gemv<T>((int)n, (int)n, c->dl[0].Kinv, n * n, G, n, dU, n, stop, c->np, c->s, c->exit_mode);
 }
 
 // every problem running: the flags and their wide copies
@@ -616,7 +623,8 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         coarse<T>(c, c->dl[0].data<T>().F, c->dl[0].data<T>().U, stop);
     if (psi && top >= 1) {  // potentials of the coarse velocity solution
         const DevLevel &z = c->dl[0];
-        launch_gemv_f2d((int)z.npsi, (int)z.n, z.Q0, z.npsi * z.n, z.f.F, z.n, z.psi, z.npsi, stop, c->np, c->s);
+        launch_gemv_f2d((int)z.npsi, (int)z.n, z.Q0, z.npsi * z.n, z.f.F, z.n, z.psi, z.npsi, stop, c->np, c->s,
+                        c->exit_mode);
     }
     for (int l = top + 1; l < L; ++l) {
         LevelData<T> &v = c->dl[l].data<T>();
@@ -637,7 +645,7 @@ void refine_residual(dfmg_ctx *c) {
     const HostLevel &h = c->S().lv[L - 1];
     DevLevel &v = c->dl[L - 1];
     check(c, spmv<double>(c, L - 1, v.d.F, v.d.U, v.d.r, c->partial, c->stopw));
-    launch_cast(h.n, v.d.r, v.f.F, h.n, c->stopw, c->np, c->s);
+    launch_cast(h.n, v.d.r, v.f.F, h.n, c->stopw, c->np, c->s, c->exit_mode);
 }
 
 // One step of the FP64 iterative refinement (its residual is in place):
@@ -664,6 +672,7 @@ void refine_body(dfmg_ctx *c) {
     a.spsi = v.npsi;
     a.stop = c->stopw;
     a.nprob = c->np;
+    a.exit_early = c->exit_mode;
     launch_refine_update_2d(a, c->s);
     refine_residual(c);
 }
@@ -680,27 +689,29 @@ void run_cycle(dfmg_ctx *c, int kind) {
         body(c, kind);
         return;
     }
-    if (c->graph && c->graph_kind != kind) {
-        HIPCHK(hipGraphExecDestroy(c->graph));
-        c->graph = nullptr;
+    const int x = c->exit_mode;
+    if (c->graph[x] && c->graph_kind[x] != kind) {
+        HIPCHK(hipGraphExecDestroy(c->graph[x]));
+        c->graph[x] = nullptr;
     }
-    if (!c->graph) {
+    if (!c->graph[x]) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
         body(c, kind);
         HIPCHK(hipStreamEndCapture(c->s, &g));
-        HIPCHK(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphInstantiate(&c->graph[x], g, nullptr, nullptr, 0));
         HIPCHK(hipGraphDestroy(g));
-        c->graph_kind = kind;
+        c->graph_kind[x] = kind;
     }
-    HIPCHK(hipGraphLaunch(c->graph, c->s));
+    HIPCHK(hipGraphLaunch(c->graph[x], c->s));
 }
 
 void drop_graph(dfmg_ctx *c) {
-    if (c->graph) {
-        HIPCHK(hipGraphExecDestroy(c->graph));
-        c->graph = nullptr;
-    }
+    for (auto &g : c->graph)
+        if (g) {
+            HIPCHK(hipGraphExecDestroy(g));
+            g = nullptr;
+        }
 }
 
 // Order the internal stream after the caller's stream, and back.
@@ -796,6 +807,7 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
     LevelData<double> &v = c->dl[L - 1].d;
     const int nb = blocks_for(n);
     reset_flags(c);
+    c->exit_mode = 0;
     launch_fill_int(np, c->counter, 0, c->s);
     launch_fill_int(np, c->fallback, 0, c->s);
     if (c->learned) apply_learned(c);
@@ -808,12 +820,13 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
 
 // state of host stop flags st[0..np) with the near flags at st + np
 int flag_state(const int *st, int np) {
-    bool all = true, near = true;
+    bool all = true, near = true, any = false;
     for (int p = 0; p < np; ++p) {
         all = all && st[p];
         near = near && (st[p] || st[np + p]);
+        any = any || st[p];
     }
-    return all ? kAllStopped : (near ? kAllNear : 0);
+    return (all ? kAllStopped : 0) | (near ? kAllNear : 0) | (any ? kAnyStopped : 0);
 }
 
 // queue a copy of the counters and stop flags into pinned buffer buf
@@ -825,10 +838,13 @@ void flags_async(dfmg_ctx *c, int buf) {
 }
 
 // wait for buffer buf: kAllStopped when every problem has stopped, kAllNear
-// when each has stopped or is expected to stop at the next check, else 0
+// when each has stopped or is expected to stop at the next check,
+// kAnyStopped when one has (later launches then use the exit mode)
 int flags_wait(dfmg_ctx *c, int buf) {
     HIPCHK(hipEventSynchronize(c->ev_flag[buf]));
-    return flag_state(c->hflags + buf * kFlagSets * c->np + c->np, c->np);
+    const int st = flag_state(c->hflags + buf * kFlagSets * c->np + c->np, c->np);
+    if (st & kAnyStopped) c->exit_mode = 1;
+    return st;
 }
 
 // Run V-cycles in units of `chunk` until every problem has stopped or max
@@ -858,11 +874,11 @@ std::pair<int, bool> pipelined_cycles(int maxc, int chunk, Launch &&launch_unit,
         last = head;
         head ^= 1;
         --inflight;
-        if (st == kAllStopped) {
+        if (st & kAllStopped) {
             all = true;
             break;
         }
-        near = st == kAllNear;
+        near = (st & kAllNear) != 0;
         if (inflight == 0 && launched < maxc) issue();
     }
     return {last, all};
@@ -1055,7 +1071,8 @@ int dfmg_batch_size(const dfmg_ctx *c, int *nprob) {
 
 void dfmg_destroy(dfmg_ctx *c) {
     if (!c) return;
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (auto g : c->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (hipEvent_t e : c->ev_flag)
@@ -1363,6 +1380,7 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         local.assign(np, dfmg_stats{});
         status = solve_stats(c, so, counter, stopv, tol, secs, local.data());
+        c->exit_mode = 0;  // launches outside a solve see no stopped problems
         leave(c);
     });
     if (st)
@@ -1790,8 +1808,9 @@ struct dfmg_multi {
     hipStream_t user = nullptr, s = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
-    hipGraphExec_t graph = nullptr;
-    int graph_kind = -1;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // per exit mode, as in dfmg_ctx
+    int graph_kind[2] = {-1, -1};
+    int exit_mode = 0;
 };
 
 namespace {
@@ -1836,31 +1855,34 @@ void multi_body(dfmg_multi *m, int kind) {
 }
 
 void multi_step(dfmg_multi *m, int kind) {
+    const int x = m->exit_mode;
+    for (dfmg_ctx *c : m->g) c->exit_mode = x;
     if (!m->opt.use_graph) {
         multi_body(m, kind);
         return;
     }
-    if (m->graph && m->graph_kind != kind) {
-        HIPCHK(hipGraphExecDestroy(m->graph));
-        m->graph = nullptr;
+    if (m->graph[x] && m->graph_kind[x] != kind) {
+        HIPCHK(hipGraphExecDestroy(m->graph[x]));
+        m->graph[x] = nullptr;
     }
-    if (!m->graph) {
+    if (!m->graph[x]) {
         hipGraph_t gr;
         HIPCHK(hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal));
         multi_body(m, kind);
         HIPCHK(hipStreamEndCapture(m->s, &gr));
-        HIPCHK(hipGraphInstantiate(&m->graph, gr, nullptr, nullptr, 0));
+        HIPCHK(hipGraphInstantiate(&m->graph[x], gr, nullptr, nullptr, 0));
         HIPCHK(hipGraphDestroy(gr));
-        m->graph_kind = kind;
+        m->graph_kind[x] = kind;
     }
-    HIPCHK(hipGraphLaunch(m->graph, m->s));
+    HIPCHK(hipGraphLaunch(m->graph[x], m->s));
 }
 
 void multi_drop_graph(dfmg_multi *m) {
-    if (m->graph) {
-        HIPCHK(hipGraphExecDestroy(m->graph));
-        m->graph = nullptr;
-    }
+    for (auto &g : m->graph)
+        if (g) {
+            HIPCHK(hipGraphExecDestroy(g));
+            g = nullptr;
+        }
 }
 
 // queue a copy of the packed flags into pinned buffer buf / wait for it
@@ -1871,7 +1893,9 @@ void multi_flags_async(dfmg_multi *m, int buf) {
 }
 int multi_flags_wait(dfmg_multi *m, int buf) {
     HIPCHK(hipEventSynchronize(m->ev_flag[buf]));
-    return flag_state(m->hflags + buf * kFlagSets * m->nprob + m->nprob, m->nprob);
+    const int st = flag_state(m->hflags + buf * kFlagSets * m->nprob + m->nprob, m->nprob);
+    if (st & kAnyStopped) m->exit_mode = 1;
+    return st;
 }
 
 void multi_plan(dfmg_multi *m) {
@@ -1951,7 +1975,8 @@ int dfmg_multi_setup(int nprob, const dfmg_grid *grids, const int *k, const doub
 
 void dfmg_multi_destroy(dfmg_multi *m) {
     if (!m) return;
-    if (m->graph) (void)hipGraphExecDestroy(m->graph);
+    for (auto g : m->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     for (dfmg_ctx *c : m->g) dfmg_destroy(c);
     for (hipEvent_t e : m->ev_join) (void)hipEventDestroy(e);
     if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
@@ -2060,6 +2085,7 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
         const size_t G = m->g.size();
         mfork(m);
         for (size_t i = 0; i < G; ++i) solve_begin(m->g[i], F, U, m->tab + m->base[i], tol);
+        m->exit_mode = 0;
         mjoin(m);
         const int kind = solve_kind(m->g[0]);
         auto [buf, all] = pipelined_cycles(
@@ -2096,6 +2122,8 @@ int dfmg_multi_solve(dfmg_multi *m, const double *F, double *U, double tol, dfmg
             for (size_t j = 0; j < gs.size(); ++j) local[m->member[i][j]] = gs[j];
         }
         status = worst;
+        m->exit_mode = 0;
+        for (dfmg_ctx *c : m->g) c->exit_mode = 0;
         mleave(m);
     });
     if (st)

@@ -29,10 +29,11 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
 // row t.  Every row is summed in the order of k_patch_solve, so the
 // corrections agree bit for bit; k_dof_update reads them through the
 // relabelled inverse map.  No load waits on more than one earlier load.
-template <class T>
+template <bool EXIT, class T>
 __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, int nb_small) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the stores
+    if (EXIT && halt) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const T *r = a.r + prob * a.svec;
     T *delta = a.delta + prob * a.sdelta;
@@ -154,10 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, i
 // inverse map padded to WB columns (WB == 0: walk inv_ptr).  Blocks from nbu
 // on take the potentials tracked by the FP32 cycle: psi += eta * sum of their
 // betas (a block-uniform split, so neither part waits for the other's loads).
-template <int WB, class T>
+template <int WB, bool EXIT, class T>
 __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a, int nbu) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(a.stop, prob);  // gates the stores
+    if (EXIT && halt) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const double eta = uniform_vload(a.eta + prob * a.seta);  // converted at its uses
     if (b >= nbu) {
@@ -184,17 +186,23 @@ __global__ __launch_bounds__(kBlock) void k_dof_update(PatchArgsT<T> a, int nbu)
 }
 
 // the DOF update with the width bucket of the level's inverse maps
+template <int WB, class T>
+static void launch_dof_w(const PatchArgsT<T> &a, dim3 grid, int nbu, hipStream_t s) {
+    if (a.exit_early) hipLaunchKernelGGL((k_dof_update<WB, true, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    else hipLaunchKernelGGL((k_dof_update<WB, false, T>), grid, dim3(kBlock), 0, s, a, nbu);
+}
+
 template <class T>
-static void launch_dof_update(const PatchArgsT<T> &a, hipStream_t s) {
+void launch_dof_update(const PatchArgsT<T> &a, hipStream_t s) {
     int w = ell_bucket(a.inv_w);
     if (a.psi && a.qinv_w > 0) w = w ? std::max(w, ell_bucket(a.qinv_w)) : 0;
     const int nbu = blocks_for(a.n), nbp = a.psi ? blocks_for(a.npsi) : 0;
     const dim3 grid(padded_grid(nbu + nbp), a.nprob);
-    if (w == 4) hipLaunchKernelGGL((k_dof_update<4, T>), grid, dim3(kBlock), 0, s, a, nbu);
-    else if (w == 8) hipLaunchKernelGGL((k_dof_update<8, T>), grid, dim3(kBlock), 0, s, a, nbu);
-    else if (w == 12) hipLaunchKernelGGL((k_dof_update<12, T>), grid, dim3(kBlock), 0, s, a, nbu);
-    else if (w == 24) hipLaunchKernelGGL((k_dof_update<24, T>), grid, dim3(kBlock), 0, s, a, nbu);
-    else hipLaunchKernelGGL((k_dof_update<0, T>), grid, dim3(kBlock), 0, s, a, nbu);
+    if (w == 4) launch_dof_w<4, T>(a, grid, nbu, s);
+    else if (w == 8) launch_dof_w<8, T>(a, grid, nbu, s);
+    else if (w == 12) launch_dof_w<12, T>(a, grid, nbu, s);
+    else if (w == 24) launch_dof_w<24, T>(a, grid, nbu, s);
+    else launch_dof_w<0, T>(a, grid, nbu, s);
 }
 
 template <class T>
@@ -249,7 +257,12 @@ void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s) {
     constexpr int waves = kBlock / 64;
     const int nbs = blocks_for(a.nsmall), nbb = (a.nbsub + waves - 1) / waves;
     const size_t lds = (size_t)waves * std::max(a.max_big, kBigRegs) * sizeof(T);
-    hipLaunchKernelGGL(k_patch_solve_small<T>, dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds, s, a, nbs);
+    if (a.exit_early)
+        hipLaunchKernelGGL((k_patch_solve_small<true, T>), dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds, s,
+                           a, nbs);
+    else
+        hipLaunchKernelGGL((k_patch_solve_small<false, T>), dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds,
+                           s, a, nbs);
     launch_dof_update<T>(a, s);
 }
 
@@ -303,11 +316,12 @@ void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, 
 // y = (add ? y : 0) + A x for a sparse transfer operator (restriction and
 // prolongation), from its fixed-width form padded to WB columns (WB == 0:
 // CSR).
-template <int WB, class T>
+template <int WB, bool EXIT, class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int nrows, SparseT<T> A, const T *x, int64_t sx, T *y, int64_t sy,
                                                 int add, const int *stop) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);  // gates the store
+    if (EXIT && halt) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int i = b * kBlock + threadIdx.x;
     if (i >= nrows) return;
@@ -320,29 +334,37 @@ __global__ __launch_bounds__(kBlock) void k_csr(int nrows, SparseT<T> A, const T
     if (!halt) y[i] = y0 + v;
 }
 
+template <int WB, class T>
+static void launch_csr_w(dim3 grid, int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add,
+                         const int *stop, hipStream_t s, int exit_early) {
+    if (exit_early) hipLaunchKernelGGL((k_csr<WB, true, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    else hipLaunchKernelGGL((k_csr<WB, false, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+}
+
 template <class T>
 void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add, const int *stop,
-                int nprob, hipStream_t s) {
+                int nprob, hipStream_t s, int exit_early) {
     const dim3 grid(padded_grid(blocks_for(nrows)), nprob);
     const int w = ell_bucket(A.w);
-    if (w == 4) hipLaunchKernelGGL((k_csr<4, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
-    else if (w == 8) hipLaunchKernelGGL((k_csr<8, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
-    else if (w == 12) hipLaunchKernelGGL((k_csr<12, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
-    else if (w == 24) hipLaunchKernelGGL((k_csr<24, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
-    else hipLaunchKernelGGL((k_csr<0, T>), grid, dim3(kBlock), 0, s, nrows, A, x, sx, y, sy, add, stop);
+    if (w == 4) launch_csr_w<4, T>(grid, nrows, A, x, sx, y, sy, add, stop, s, exit_early);
+    else if (w == 8) launch_csr_w<8, T>(grid, nrows, A, x, sx, y, sy, add, stop, s, exit_early);
+    else if (w == 12) launch_csr_w<12, T>(grid, nrows, A, x, sx, y, sy, add, stop, s, exit_early);
+    else if (w == 24) launch_csr_w<24, T>(grid, nrows, A, x, sx, y, sy, add, stop, s, exit_early);
+    else launch_csr_w<0, T>(grid, nrows, A, x, sx, y, sy, add, stop, s, exit_early);
 }
 
 // The prolongations of the FP32 cycle in one launch: blocks below nbu add
 // P dU to the velocity-pressure rows (T), the others add Ps psi_coarse to
 // the potentials (FP64), each from its fixed-width form padded to WB columns
 // (WB == 0: CSR).  The same sums as two k_csr launches.
-template <int WB, class T>
+template <int WB, bool EXIT, class T>
 __global__ __launch_bounds__(kBlock) void k_prolong_pair(int nu, SparseT<T> P, const T *xu, int64_t sxu, T *yu,
                                                          int64_t syu, int nps, SparseT<double> Ps, const double *xp,
                                                          int64_t sxp, double *yp, int64_t syp, int nbu,
                                                          const int *stop) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);
+    if (EXIT && halt) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     if (b < nbu) {
         const int i = b * kBlock + threadIdx.x;
@@ -370,14 +392,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pair(int nu, SparseT<T> P, c
 template <class T>
 void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, T *yu, int64_t syu, int nps,
                          const SparseT<double> &Ps, const double *xp, int64_t sxp, double *yp, int64_t syp,
-                         const int *stop, int nprob, hipStream_t s) {
+                         const int *stop, int nprob, hipStream_t s, int exit_early) {
     const int bp = ell_bucket(P.w), bq = ell_bucket(Ps.w);
     const int w = (bp && bq) ? std::max(bp, bq) : 0;
     const int nbu = blocks_for(nu);
     const dim3 grid(padded_grid(nbu + blocks_for(nps)), nprob);
-#define DFMG_PAIR(W)                                                                                            \
-    hipLaunchKernelGGL((k_prolong_pair<W, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu, nps, Ps, xp, \
-                       sxp, yp, syp, nbu, stop)
+#define DFMG_PAIR(W)                                                                                          \
+    do {                                                                                                      \
+        if (exit_early)                                                                                       \
+            hipLaunchKernelGGL((k_prolong_pair<W, true, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu, nps, \
+                               Ps, xp, sxp, yp, syp, nbu, stop);                                              \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_prolong_pair<W, false, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu,    \
+                               nps, Ps, xp, sxp, yp, syp, nbu, stop);                                         \
+    } while (0)
     if (w == 4) DFMG_PAIR(4);
     else if (w == 8) DFMG_PAIR(8);
     else if (w == 12) DFMG_PAIR(12);
@@ -392,9 +420,10 @@ void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, 
 __global__ __launch_bounds__(kBlock) void k_coarse_pair(int n, int nps, const double *Kinv, int64_t sK,
                                                         const double *Q0, int64_t sQ, const float *x, int64_t sx,
                                                         float *y, int64_t sy, double *psi, int64_t sp,
-                                                        const int *stop) {
+                                                        const int *stop, int exit_early) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);
+    if (exit_early && halt) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n + nps) return;
@@ -409,19 +438,20 @@ __global__ __launch_bounds__(kBlock) void k_coarse_pair(int n, int nps, const do
 
 void launch_coarse_pair(int n, int nps, const double *Kinv, int64_t sK, const double *Q0, int64_t sQ, const float *x,
                         int64_t sx, float *y, int64_t sy, double *psi, int64_t sp, const int *stop, int nprob,
-                        hipStream_t s) {
+                        hipStream_t s, int exit_early) {
     const int rows_per = kBlock / 64;
     hipLaunchKernelGGL(k_coarse_pair, dim3((n + nps + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, n, nps,
-                       Kinv, sK, Q0, sQ, x, sx, y, sy, psi, sp, stop);
+                       Kinv, sK, Q0, sQ, x, sx, y, sy, psi, sp, stop, exit_early);
 }
 
 // Dense y = A x (A FP64, row-major rows x cols), one wavefront per row, FP64
 // accumulation.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const double *A, int64_t sA, const T *x,
-                                                 int64_t sx, T *y, int64_t sy, const int *stop) {
+                                                 int64_t sx, T *y, int64_t sy, const int *stop, int exit_early) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);  // block-uniform; gates the store
+    if (exit_early && halt) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
@@ -431,16 +461,18 @@ __global__ __launch_bounds__(kBlock) void k_gemv(int rows, int cols, const doubl
 
 template <class T>
 void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, int64_t sx, T *y, int64_t sy,
-                 const int *stop, int nprob, hipStream_t s) {
+                 const int *stop, int nprob, hipStream_t s, int exit_early) {
     const int rows_per = kBlock / 64;
     hipLaunchKernelGGL(k_gemv<T>, dim3((rows + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, rows, cols, A,
-                       sA, x, sx, y, sy, stop);
+                       sA, x, sx, y, sy, stop, exit_early);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x,
-                                                     int64_t sx, double *y, int64_t sy, const int *stop) {
+                                                     int64_t sx, double *y, int64_t sy, const int *stop,
+                                                     int exit_early) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);
+    if (exit_early && halt) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= rows) return;
@@ -449,10 +481,10 @@ __global__ __launch_bounds__(kBlock) void k_gemv_f2d(int rows, int cols, const d
 }
 
 void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x, int64_t sx, double *y,
-                     int64_t sy, const int *stop, int nprob, hipStream_t s) {
+                     int64_t sy, const int *stop, int nprob, hipStream_t s, int exit_early) {
     const int rows_per = kBlock / 64;
     hipLaunchKernelGGL(k_gemv_f2d, dim3((rows + rows_per - 1) / rows_per, nprob), dim3(kBlock), 0, s, rows, cols, A,
-                       sA, x, sx, y, sy, stop);
+                       sA, x, sx, y, sy, stop, exit_early);
 }
 
 template <class T>
@@ -463,22 +495,24 @@ __global__ void k_fill(int64_t n, T *x, int64_t sx, T v, const int *stop) {
     if (i < n && !halt) x[prob * sx + i] = v;
 }
 template <class T>
-void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s) {
+void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s, int) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, sx, v, stop);
 }
 
-__global__ void k_cast(int64_t n, const double *x, float *y, int64_t sv, const int *stop) {
+__global__ void k_cast(int64_t n, const double *x, float *y, int64_t sv, const int *stop, int exit_early) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(stop, prob);
+    if (exit_early && halt) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const float v = (float)x[prob * sv + i];
     if (!halt) y[prob * sv + i] = v;
 }
-void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s) {
+void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s,
+                 int exit_early) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, y, svec, stop);
+    hipLaunchKernelGGL(k_cast, dim3(blocks_for(n), nprob), dim3(kBlock), 0, s, n, x, y, svec, stop, exit_early);
 }
 
 // U += [curl psi; X_p] in FP64, curl psi = (d_y psi, -d_x psi) by the scaled
@@ -486,6 +520,7 @@ void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *
 __global__ void k_curl_update_2d(RefineArgs a) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the store
+    if (a.exit_early && halt) return;
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= a.n) return;
     const int m = a.N + a.k - 1, nq = a.N + a.k;
@@ -522,18 +557,18 @@ template void launch_schwarz_fused<float>(const PatchArgsT<float> &, hipStream_t
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);
 template void launch_csr<double>(int, const SparseT<double> &, const double *, int64_t, double *, int64_t, int,
-                                 const int *, int, hipStream_t);
+                                 const int *, int, hipStream_t, int);
 template void launch_csr<float>(int, const SparseT<float> &, const float *, int64_t, float *, int64_t, int, const int *,
-                                int, hipStream_t);
+                                int, hipStream_t, int);
 template void launch_prolong_pair<float>(int, const SparseT<float> &, const float *, int64_t, float *, int64_t, int,
                                          const SparseT<double> &, const double *, int64_t, double *, int64_t,
-                                         const int *, int, hipStream_t);
+                                         const int *, int, hipStream_t, int);
 template void launch_gemv<double>(int, int, const double *, int64_t, const double *, int64_t, double *, int64_t,
-                                  const int *, int, hipStream_t);
+                                  const int *, int, hipStream_t, int);
 template void launch_gemv<float>(int, int, const double *, int64_t, const float *, int64_t, float *, int64_t,
-                                 const int *, int, hipStream_t);
-template void launch_fill<double>(int64_t, double *, int64_t, double, const int *, int, hipStream_t);
-template void launch_fill<float>(int64_t, float *, int64_t, float, const int *, int, hipStream_t);
+                                 const int *, int, hipStream_t, int);
+template void launch_fill<double>(int64_t, double *, int64_t, double, const int *, int, hipStream_t, int);
+template void launch_fill<float>(int64_t, float *, int64_t, float, const int *, int, hipStream_t, int);
 
 __global__ void k_fill_int(int n, int *x, int v) {
     const int i = blockIdx.x * kBlock + threadIdx.x;

@@ -11,7 +11,10 @@
 // once a problem's residual check has met the tolerance (or detected
 // divergence) the remaining kernels leave that problem's outputs untouched,
 // so cycles launched ahead of the host check are no-ops for it and its
-// iterate is the one at which the check fired.  The cycle kernels take the
+// iterate is the one at which the check fired.  Launches made once some
+// problem has stopped (exit_early) return at once for stopped problems; the
+// others read the flag beside their data and skip only the stores (below).
+// The cycle kernels take the
 // flags in their wide form: kStopLanes copies per problem, lane i of a
 // wavefront reading copy i (the check writes all of them).  Kernels whose time
 // is set by the latency of their load chains read the flag beside their other
@@ -53,6 +56,7 @@ struct SpmvArgsT {
     int64_t spart;      // per-problem stride of partial
     const int *stop;    // per-problem flags, wide form (nullable)
     int nprob;
+    int exit_early;     // 1: stopped problems return at once
 };
 using SpmvArgs = SpmvArgsT<double>;
 
@@ -72,6 +76,7 @@ struct PatchArgsT {
     int assign;         // 1: U = eta * S r (U known to be zero)
     const int *stop;
     int nprob;
+    int exit_early;         // 1: stopped problems return at once
     const int32_t *small;   // subdomains with <= kSmallPatch DOFs (shared)
     const int32_t *bigent;  // entries of the other subdomains (shared)
     const int32_t *small_dofs;  // form 4: DOF c of small subdomain q at c * nsmall + q
@@ -162,31 +167,32 @@ struct SparseT {
     const int32_t *eci;
     const T *ev;
 };
-// y = (add ? y : 0) + A x; x, y per problem (strides sx, sy)
+// y = (add ? y : 0) + A x; x, y per problem (strides sx, sy); exit_early as
+// in the argument structs (also below)
 template <class T>
 void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, int64_t sy, int add, const int *stop,
-                int nprob, hipStream_t s);
+                int nprob, hipStream_t s, int exit_early = 0);
 // the FP32 cycle's prolongation of the velocity-pressure correction (P) and
 // of the potentials (Ps, FP64) in one launch, both added
 template <class T>
 void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, T *yu, int64_t syu, int nps,
                          const SparseT<double> &Ps, const double *xp, int64_t sxp, double *yp, int64_t syp,
-                         const int *stop, int nprob, hipStream_t s);
+                         const int *stop, int nprob, hipStream_t s, int exit_early = 0);
 // the FP32 cycle's coarse solve y = Kinv x and its potentials psi = Q0 x
 // (FP64 matrices, n x n and nps x n per problem) in one launch
 void launch_coarse_pair(int n, int nps, const double *Kinv, int64_t sK, const double *Q0, int64_t sQ, const float *x,
                         int64_t sx, float *y, int64_t sy, double *psi, int64_t sp, const int *stop, int nprob,
-                        hipStream_t s);
+                        hipStream_t s, int exit_early = 0);
 // y = A x with A row-major FP64 (rows x cols) per problem (stride sA), x, y in
 // T, FP64 accumulation
 template <class T>
 void launch_gemv(int rows, int cols, const double *A, int64_t sA, const T *x, int64_t sx, T *y, int64_t sy,
-                 const int *stop, int nprob, hipStream_t s);
+                 const int *stop, int nprob, hipStream_t s, int exit_early = 0);
 // y (FP64) = A x with x in FP32 (the coarse potentials of the FP32 cycle)
 void launch_gemv_f2d(int rows, int cols, const double *A, int64_t sA, const float *x, int64_t sx, double *y,
-                     int64_t sy, const int *stop, int nprob, hipStream_t s);
+                     int64_t sy, const int *stop, int nprob, hipStream_t s, int exit_early = 0);
 template <class T>
-void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s);
+void launch_fill(int64_t n, T *x, int64_t sx, T v, const int *stop, int nprob, hipStream_t s, int exit_early = 0);
 void launch_fill_int(int n, int *x, int v, hipStream_t s);
 void launch_copy_int(int n, const int *x, int *y, hipStream_t s);
 void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, const int *stop, int nprob,
@@ -195,7 +201,8 @@ void launch_copy(int64_t n, const double *x, int64_t sx, double *y, int64_t sy, 
 // means p * stride (used for vectors of problems laid out in the caller's order)
 void launch_copy_off(int64_t n, const double *x, const int64_t *xoff, int64_t sx, double *y, const int64_t *yoff,
                      int64_t sy, int nprob, hipStream_t s);
-void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s);
+void launch_cast(int64_t n, const double *x, float *y, int64_t svec, const int *stop, int nprob, hipStream_t s,
+                 int exit_early = 0);
 // per problem: partial[p * spart + b] = block sums of x . y
 void launch_dot_partial(int n, const double *x, const double *y, int64_t sxy, double *partial, int64_t spart,
                         int nblocks, int nprob, hipStream_t s);
@@ -236,6 +243,7 @@ struct RefineArgs {
     int64_t svec, spsi;
     const int *stop;
     int nprob;
+    int exit_early;
 };
 void launch_refine_update_2d(const RefineArgs &a, hipStream_t s);
 

@@ -66,7 +66,7 @@ constexpr int kGateRows = 1 << 16;
 
 template <int D, int K, class T>
 static void launch_dk(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
-    const bool gate = a.n < kGateRows;
+    const bool gate = !a.exit_early && a.n < kGateRows;
     if (a.win) {
         if (gate) launch_dkwg<D, K, true, true, T>(a, lpr, s);
         else launch_dkwg<D, K, true, false, T>(a, lpr, s);

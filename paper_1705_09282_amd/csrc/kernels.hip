@@ -355,9 +355,9 @@ void launch_csr(int nrows, const SparseT<T> &A, const T *x, int64_t sx, T *y, in
 
 // The prolongations of the FP32 cycle in one launch: blocks below nbu add
 // P dU to the velocity-pressure rows (T), the others add Ps psi_coarse to
-// the potentials (FP64), each from its fixed-width form padded to WB columns
-// (WB == 0: CSR).  The same sums as two k_csr launches.
-template <int WB, bool EXIT, class T>
+// the potentials (FP64), each from its fixed-width form padded to WB / WQ
+// columns (0: CSR).  The same sums as two k_csr launches.
+template <int WB, int WQ, bool EXIT, class T>
 __global__ __launch_bounds__(kBlock) void k_prolong_pair(int nu, SparseT<T> P, const T *xu, int64_t sxu, T *yu,
                                                          int64_t syu, int nps, SparseT<double> Ps, const double *xp,
                                                          int64_t sxp, double *yp, int64_t syp, int nbu,
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pair(int nu, SparseT<T> P, c
     yp += prob * syp;
     const double y0 = yp[i];
     double v;
-    if (WB > 0 && Ps.w > 0 && Ps.w <= WB) v = ell_row<(WB > 0 ? WB : 1)>(Ps.eci, Ps.ev, nps, Ps.w, i, xp);
+    if (WQ > 0 && Ps.w > 0 && Ps.w <= WQ) v = ell_row<(WQ > 0 ? WQ : 1)>(Ps.eci, Ps.ev, nps, Ps.w, i, xp);
     else v = csr_row(Ps.rp, Ps.ci, Ps.v, xp, i);
     if (!halt) yp[i] = y0 + v;
 }
@@ -394,23 +394,25 @@ void launch_prolong_pair(int nu, const SparseT<T> &P, const T *xu, int64_t sxu, 
                          const SparseT<double> &Ps, const double *xp, int64_t sxp, double *yp, int64_t syp,
                          const int *stop, int nprob, hipStream_t s, int exit_early) {
     const int bp = ell_bucket(P.w), bq = ell_bucket(Ps.w);
-    const int w = (bp && bq) ? std::max(bp, bq) : 0;
     const int nbu = blocks_for(nu);
     const dim3 grid(padded_grid(nbu + blocks_for(nps)), nprob);
-#define DFMG_PAIR(W)                                                                                          \
-    do {                                                                                                      \
-        if (exit_early)                                                                                       \
-            hipLaunchKernelGGL((k_prolong_pair<W, true, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu, nps, \
-                               Ps, xp, sxp, yp, syp, nbu, stop);                                              \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_prolong_pair<W, false, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu,    \
-                               nps, Ps, xp, sxp, yp, syp, nbu, stop);                                         \
+#define DFMG_PAIR(W, Q)                                                                                        \
+    do {                                                                                                       \
+        if (exit_early)                                                                                        \
+            hipLaunchKernelGGL((k_prolong_pair<W, Q, true, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu, syu, \
+                               nps, Ps, xp, sxp, yp, syp, nbu, stop);                                          \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_prolong_pair<W, Q, false, T>), grid, dim3(kBlock), 0, s, nu, P, xu, sxu, yu,     \
+                               syu, nps, Ps, xp, sxp, yp, syp, nbu, stop);                                     \
     } while (0)
-    if (w == 4) DFMG_PAIR(4);
-    else if (w == 8) DFMG_PAIR(8);
-    else if (w == 12) DFMG_PAIR(12);
-    else if (w == 24) DFMG_PAIR(24);
-    else DFMG_PAIR(0);
+    // the widths that occur in 2D (P: 4 or 8; P^psi: 4 or 12), else CSR for both
+    if (bp == 4 && bq == 4) DFMG_PAIR(4, 4);
+    else if (bp == 4 && bq == 12) DFMG_PAIR(4, 12);
+    else if (bp == 8 && bq == 4) DFMG_PAIR(8, 4);
+    else if (bp == 8 && bq == 12) DFMG_PAIR(8, 12);
+    else if (bp == 8 && bq == 8) DFMG_PAIR(8, 8);
+    else if (bp == 4 && bq == 8) DFMG_PAIR(4, 8);
+    else DFMG_PAIR(0, 0);
 #undef DFMG_PAIR
 }
 

@@ -42,14 +42,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(n_elem, levels):
     """HBM bytes per launch of the finest residual kernel from the committed
-    rocprofv3 counter runs, or None if missing or taken on other kernel code."""
+    rocprofv3 counter runs, or None if missing, taken on other kernel code or
+    on another workload size."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    if t.get("workload") != {"n_elem": n_elem, "levels": levels}:
         return None
     return t.get("bytes_per_launch")
 
@@ -150,10 +153,11 @@ def main():
         z = b.sizes()
         alg = len(sigmas) * (4 * z["nnz"] + 3 * 4 * z["n"])
         achieved = alg / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,float> (finest-grid FP32 residual r = F - K U, "
+        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (finest-grid FP32 residual r = F - K U, "
                                           f"{len(sigmas)} problems per launch)",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(), "alg_bytes_per_launch": alg, "avg_launch_ms": ms}
+                "traffic": measured_traffic(args.n_elem, args.levels), "alg_bytes_per_launch": alg,
+                "avg_launch_ms": ms}
 
     if args.roofline_only:
         # the residual's roofline, then 200 finest-grid smoothing steps of the

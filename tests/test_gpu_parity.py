@@ -314,7 +314,7 @@ def test_fp32_refinement_matches_fp64_oracle(cfg):
     """FP32 V-cycles inside FP64 iterative refinement: converges to the FP64
     discrete solution (velocity within 1e-8 relative of the oracle's), and the
     velocity stays divergence-free to FP64 rounding because every update is the
-    curl of a recovered streamfunction increment."""
+    curl of the streamfunction increment the FP32 cycles tracked."""
     s, h, F = make(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"], cfg["c"], precision=1)
     Ud = dev(np.zeros_like(F))
     st = s.solve(dev(F), Ud, tol=1e-10)

@@ -86,23 +86,27 @@ def smooth(level, U, F, eta):
 
 
 def mgv(h, l, U, F, nu1, nu2, eta):
-    """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l, nu1 and
-    nu2 the smoothing steps (a number, or one per level indexed by level).
-    Returns the updated U (the paper updates U in place)."""
+    """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l (a number,
+    or a pair (pre, post) of per-step damping sequences), nu1 and nu2 the
+    smoothing steps (a number, or one per level indexed by level).  Returns
+    the updated U (the paper updates U in place)."""
     lv = h.levels[l]
     if l == 0:
         return lv.coarse_inv @ F
     n1 = nu1 if np.isscalar(nu1) else nu1[l]
     n2 = nu2 if np.isscalar(nu2) else nu2[l]
-    for _ in range(n1):
-        U = smooth(lv, U, F, eta[l])
+    e = eta[l]
+    pre = list(e[0]) if isinstance(e, tuple) else [e] * n1
+    post = list(e[1]) if isinstance(e, tuple) else [e] * n2
+    for j in range(n1):
+        U = smooth(lv, U, F, pre[j])
     P = h.levels[l - 1].P
     G = P.T @ (F - lv.K @ U)
     dU = np.zeros(h.levels[l - 1].disc.n)
     dU = mgv(h, l - 1, dU, G, nu1, nu2, eta)
     U = U + P @ dU
-    for _ in range(n2):
-        U = smooth(lv, U, F, eta[l])
+    for j in range(n2):
+        U = smooth(lv, U, F, post[j])
     return U
 
 
@@ -122,7 +126,8 @@ def default_eta(d, k):
 
 
 def eta_levels(h, eta):
-    """Per-level damping array indexed by level (entry 0 unused)."""
+    """Per-level damping array indexed by level (entry 0 unused); an entry
+    given as a pair (pre, post) of per-step sequences is kept as such."""
     if eta is None:
         eta = default_eta(h.d, h.k)
     if np.isscalar(eta):
@@ -132,8 +137,53 @@ def eta_levels(h, eta):
     # given finest -> coarsest; level l = L-1 .. 1
     out = [0.0] * h.L
     for i, e in enumerate(eta):
-        out[h.L - 1 - i] = float(e)
+        out[h.L - 1 - i] = (tuple(e[0]), tuple(e[1])) if isinstance(e, tuple) else float(e)
     return out
+
+
+def chebyshev_dampings(b, alpha, nu, reverse=False):
+    """Dampings of nu additive Schwarz steps whose error polynomial in the
+    preconditioned operator X = S^{-1} K is the Chebyshev polynomial of
+    degree nu scaled to the interval [a, b], a = b / alpha, with value 1 at 0
+    (Chebyshev semi-iteration; Adams, Brezina, Hu, Tuminaro 2003 use it as a
+    multigrid smoother): prod_j (1 - x / theta_j) has the zeros theta_j of
+    T_nu((b + a - 2 x) / (b - a)), so eta_j = 1 / theta_j with
+    theta_j = (b + a) / 2 + (b - a) / 2 cos(pi (2 j + 1) / (2 nu)).  The steps
+    take j = 0, 1, ... (largest theta first), or the reverse order."""
+    a = b / alpha
+    js = range(nu - 1, -1, -1) if reverse else range(nu)
+    return [1.0 / ((b + a) / 2 + (b - a) / 2 * np.cos(np.pi * (2 * j + 1) / (2 * nu))) for j in js]
+
+
+def chebyshev_schedule(h, lmax, alpha, nu1, nu2, safety=1.05):
+    """Finest-first list of (pre, post) damping sequences for eta_levels:
+    level i (finest first) has b = safety * lmax[i], ratio alpha (a number or
+    alpha[i]), nu1[i] pre-smoothing dampings in the order of
+    chebyshev_dampings and nu2[i] post-smoothing dampings in the reverse
+    order."""
+    m = h.L - 1
+    n1 = [nu1] * m if np.isscalar(nu1) else list(nu1)
+    n2 = [nu2] * m if np.isscalar(nu2) else list(nu2)
+    al = [alpha] * m if np.isscalar(alpha) else list(alpha)
+    return [(tuple(chebyshev_dampings(safety * lmax[i], al[i], n1[i])),
+             tuple(chebyshev_dampings(safety * lmax[i], al[i], n2[i], reverse=True))) for i in range(m)]
+
+
+def smoother_matrix(level):
+    """Dense S^{-1} = sum_i E_i^T M_i E_i of a smoothed level (tiny grids)."""
+    n = level.disc.n
+    S = np.zeros((n, n))
+    for ids, I, M in level.groups:
+        for m in range(I.shape[0]):
+            S[np.ix_(I[m], I[m])] += M[m]
+    return S
+
+
+def lmax_dense(level):
+    """Largest |eigenvalue| of S^{-1} K (undamped smoother operator) of a
+    smoothed level, from the dense eigenvalues (tiny grids)."""
+    X = smoother_matrix(level) @ level.K.toarray()
+    return float(np.max(np.abs(np.linalg.eigvals(X))))
 
 
 def steps_levels(h, nu):

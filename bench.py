@@ -7,10 +7,12 @@ pressure degree k=2 (velocity S^{3,2} x S^{2,3}), 256x256 elements, 6 grids
 manufactured solution u = curl(sin^2(pi x) sin^2(pi y)), p = sin(2 pi x)
 sin(2 pi y).  One step solves all four problems from U = 0 to relative
 residual 1e-8; inputs are resident in HBM before timing.  The timed path is
-the learned per-level damping and smoothing steps with FP32 V-cycles inside
-FP64 iterative refinement; the plain FP64 solver (fixed damping, V(2,2)) and
-FP32 refinement with the fixed damping and V(2,2) are timed beside it on the
-same problems.
+the learned Chebyshev damping schedule (the network predicts per level the
+schedule's interval ratio and the smoothing steps) with FP32 V-cycles inside
+FP64 iterative refinement.  Timed beside it on the same problems: the plain
+FP64 solver (fixed damping, V(2,2)), FP32 refinement with the fixed damping
+and V(2,2), FP32 refinement with the learned constant per-level damping and
+steps, and the learned schedule in plain FP64 cycles.
 
 Prints one JSON line: metric, value (DOF/s over the whole step, DOFs =
 dim V_h + dim Q_h), roofline of the dominant kernel (finest-grid residual
@@ -118,14 +120,14 @@ def main():
     cfg = workloads.stokes2d(1.0, N=args.n_elem, L=args.levels)
 
     from paper_1705_09282_amd import learned
-    model = learned.load()
+    models = {"constant": learned.load(), "chebyshev": learned.load(learned.CHEB_WEIGHTS)}
 
-    def make_batch(precision, use_learned=False):
+    def make_batch(precision, use_learned=None):
         b = BatchSolver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], [cfg["nu"]] * len(sigmas), sigmas,
                         precision=precision).bind(dev)
         tuning = b.autotune(reps=20)
         if use_learned:
-            learned.apply(b, model)
+            learned.apply(b, models[use_learned])
         F = torch.tensor(b.manufactured_rhs(), device=dev)
         U = torch.zeros_like(F)
         return b, F, U, tuning
@@ -162,7 +164,7 @@ def main():
     if args.roofline_only:
         # the residual's roofline, then 200 finest-grid smoothing steps of the
         # same batch (the local solves and the per-DOF update, for counter runs)
-        b32, F32, U32, _ = make_batch(1, use_learned=True)
+        b32, F32, U32, _ = make_batch(1, use_learned="chebyshev")
         U32.zero_()
         b32.solve(F32, U32, tol=args.tol)
         out = {"roofline": roofline(b32, F32, U32)}
@@ -174,11 +176,13 @@ def main():
     t_setup = time.perf_counter()
     b64, F64, U64, tun64 = make_batch(0)
     bfx, Ffx, Ufx, tunfx = make_batch(1)
-    b32, F32, U32, tun32 = make_batch(1, use_learned=True)
+    blc, Flc, Ulc, _ = make_batch(1, use_learned="constant")
+    bc64, Fc64, Uc64, _ = make_batch(0, use_learned="chebyshev")
+    b32, F32, U32, tun32 = make_batch(1, use_learned="chebyshev")
     setup_s = time.perf_counter() - t_setup
     z = b64.sizes()
     dofs = len(sigmas) * (z["n"] - 1)
-    print(f"[bench] setup of 3 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
+    print(f"[bench] setup of 5 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
           file=sys.stderr, flush=True)
 
     T64, stats64 = run(b64, F64, U64)
@@ -186,9 +190,15 @@ def main():
     Tfx, statsfx = run(bfx, Ffx, Ufx)
     print(f"[bench] FP32-refined batch, fixed damping: {args.steps} steps in {Tfx:.3f} s", file=sys.stderr,
           flush=True)
-    T, stats = run(b32, F32, U32)
-    print(f"[bench] learned damping + FP32-refined batch: {args.steps} steps in {T:.3f} s", file=sys.stderr,
+    Tlc, statslc = run(blc, Flc, Ulc)
+    print(f"[bench] FP32-refined batch, learned constant damping: {args.steps} steps in {Tlc:.3f} s",
+          file=sys.stderr, flush=True)
+    Tc64, statsc64 = run(bc64, Fc64, Uc64)
+    print(f"[bench] FP64 batch, learned Chebyshev schedule: {args.steps} steps in {Tc64:.3f} s", file=sys.stderr,
           flush=True)
+    T, stats = run(b32, F32, U32)
+    print(f"[bench] learned Chebyshev schedule + FP32-refined batch: {args.steps} steps in {T:.3f} s",
+          file=sys.stderr, flush=True)
 
     n = z["n"]
     nv = z["n_vel"]
@@ -227,10 +237,14 @@ def main():
             "workload": f"stokes2d: 2D generalized Stokes, k=2, {args.n_elem}x{args.n_elem} elements, "
                         f"{args.levels} grids, nu=1, sigma in {{1e-2,1,1e2,1e4}}, additive Schwarz V-cycles, "
                         f"tol {args.tol:g}, U0=0",
-            "path": "batched: learned per-level damping and smoothing steps, FP32 V-cycles in FP64 iterative "
-                    "refinement, 4 problems per launch (plain_fp64: fixed damping, V(2,2))",
+            "path": "batched: learned Chebyshev damping schedule (network: interval ratio and smoothing steps per "
+                    "level), FP32 V-cycles in FP64 iterative refinement, 4 problems per launch (plain_fp64: "
+                    "fixed damping, V(2,2))",
             "steps_per_level_finest_first": b32.get_smoothing()[0],
-            "eta_per_sigma": [[round(x, 4) for x in row] for row in b32.get_eta().tolist()],
+            "alpha_per_sigma": [[round(x, 3) for x in row] for row in b32.get_alpha().tolist()],
+            "lmax_per_sigma": [[round(x, 4) for x in row] for row in b32.get_lmax().tolist()],
+            "finest_pre_smoothing_dampings_sigma1": [round(x, 4) for x in
+                                                     b32.get_schedule()[1, 0, 0, :b32.get_smoothing()[0][0]]],
             "fallback_per_sigma": [st["fallback"] for st in stats],
             "dofs_per_step": dofs,
             "cycles_per_sigma": cycles,
@@ -242,6 +256,13 @@ def main():
                            "vcycles_per_s": args.steps * sum(st["cycles"] for st in stats64) / T64},
             "fp32_fixed_damping": {"value": args.steps * dofs / Tfx, "ms_per_step": 1e3 * Tfx / args.steps,
                                    "cycles_per_sigma": [st["cycles"] for st in statsfx]},
+            "fp32_learned_constant_damping": {
+                "value": args.steps * dofs / Tlc, "ms_per_step": 1e3 * Tlc / args.steps,
+                "cycles_per_sigma": [st["cycles"] for st in statslc],
+                "steps_per_level_finest_first": blc.get_smoothing()[0],
+                "eta_per_sigma": [[round(x, 4) for x in row] for row in blc.get_eta().tolist()]},
+            "fp64_learned_chebyshev": {"value": args.steps * dofs / Tc64, "ms_per_step": 1e3 * Tc64 / args.steps,
+                                       "cycles_per_sigma": [st["cycles"] for st in statsc64]},
             "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
             "tuning": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
@@ -253,7 +274,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.tol)
-    for s in (b64, bfx, b32):
+    for s in (b64, bfx, blc, bc64, b32):
         s.close()
     print(json.dumps(line), flush=True)
 

@@ -266,6 +266,59 @@ int dfmg_set_learned(dfmg_ctx *ctx, const float *W_host, const double *rho_plain
 /* Current dampings, nprob * (n_levels - 1) values, finest level first. */
 int dfmg_get_eta(dfmg_ctx *ctx, double *eta_host);
 
+/* Chebyshev damping schedule of the additive smoother (each smoothing step is
+ * still U <- U + eta_j S^-1 (F - K U), equation ASM with a scalar damping, so
+ * every correction stays divergence-free; only eta changes from step to step).
+ * The smoother is a polynomial in the preconditioned operator S^-1 K; with
+ * dampings 1 / theta_j, theta_j the zeros of the Chebyshev polynomial of
+ * degree nu mapped to [b / alpha, b], its error polynomial is the scaled
+ * Chebyshev polynomial T_nu((b + a - 2x) / (b - a)) / T_nu((b + a) / (b - a)),
+ * a = b / alpha, which has the least maximum over [a, b] among polynomials of
+ * degree nu with value 1 at 0 (Chebyshev semi-iteration, as used for
+ * multigrid smoothing by Adams, Brezina, Hu and Tuminaro, 2003).  b = 1.05 x
+ * the largest |eigenvalue| of S^-1 K of each problem and smoothed level,
+ * estimated here by `iters` power-iteration steps with the level's residual
+ * and smoother kernels in FP64 (deterministic start vector; host norms;
+ * synchronizes the stream).  nu = the level's pre- or post-smoothing count:
+ * pre-smoothing takes the zeros theta_0 > theta_1 > ..., post-smoothing the
+ * reverse order.  The schedule replaces the per-level dampings (fixed or
+ * learned) in every smoothing step of later cycles, in FP64 and FP32 cycles
+ * alike, and follows later changes of the step counts (dfmg_set_smoothing,
+ * dfmg_set_learned).  The fallback of dfmg_set_learned switches a problem to
+ * its fixed damping in every step; the next solve restores the schedule.
+ * The single-workgroup coarse cycle is not used while a schedule is on.
+ * alpha in (1, 1e6] turns it on, alpha 0 off (iters unused then); iters in
+ * [1, 1000].  Requires dfmg_bind.  Errors: EINVAL, ESTATE, EHIP. */
+int dfmg_set_chebyshev(dfmg_ctx *ctx, double alpha, int iters);
+/* Interval ratios alpha of the schedule in use, per smoothed level (finest
+ * first): n = n_levels - 1 values for every problem or nprob * (n_levels - 1)
+ * problem-major, each in (1, 1e6]; rebuilds the dampings from the existing
+ * eigenvalue estimates.  ESTATE without a schedule; EINVAL. */
+int dfmg_set_chebyshev_alpha(dfmg_ctx *ctx, const double *alpha_host, int n);
+/* Current ratios (host out), nprob * (n_levels - 1), finest level first. */
+int dfmg_get_alpha(const dfmg_ctx *ctx, double *alpha_host);
+/* Learned Chebyshev schedule: the network W_host (same layout and inference
+ * kernel as dfmg_set_learned, inputs log10(nu)/2, log10(sigma)/4, |a|h/nu,
+ * k - 1.5) predicts per smoothed level, finest first, the logit of
+ * a / b = 1 / alpha (outputs 0..4; levels past the fifth take output 4;
+ * alpha clamped to [1.5, 1000]) and the smoothing steps (outputs 5..9,
+ * rounded, clamped to [1, 8], the largest over the batch, pre = post).
+ * Turns the schedule on with those ratios and steps (eigenvalue estimates by
+ * `iters` power iterations unless a previous call made them); the per-level
+ * dampings are the fixed ones, which the fallback (rho_plain_host, as in
+ * dfmg_set_learned) switches a problem to.  W_host NULL turns the schedule
+ * off and restores the options' steps.  Requires dfmg_bind; synchronizes the
+ * stream.  Errors: EINVAL, ESTATE, EHIP. */
+int dfmg_set_learned_chebyshev(dfmg_ctx *ctx, const float *W_host, const double *rho_plain_host, int iters);
+/* The eigenvalue estimates of the last dfmg_set_chebyshev (host out):
+ * nprob * (n_levels - 1) values, finest level first.  ESTATE before. */
+int dfmg_get_lmax(const dfmg_ctx *ctx, double *lmax_host);
+/* The per-step dampings in use (host out): nprob * (n_levels - 1) * 32
+ * values, problem-major, finest level first; per level 16 pre-smoothing steps
+ * then 16 post-smoothing steps (entries past a step count repeat its last).
+ * ESTATE without a schedule. */
+int dfmg_get_schedule(dfmg_ctx *ctx, double *out_host);
+
 /* ---- Host exports for bit-exact index-map parity and value parity ----
  * CSR of K_level (explicit zeros dropped): rowptr[n+1], col[nnz], val[nnz]. */
 int dfmg_export_matrix(const dfmg_ctx *ctx, int level, int64_t *rowptr, int32_t *col, double *val);
@@ -310,6 +363,11 @@ int dfmg_multi_autotune(dfmg_multi *m, int reps);
 /* dfmg_set_learned for every problem; rho_plain_host has nprob entries in
  * caller order (nullable). */
 int dfmg_multi_set_learned(dfmg_multi *m, const float *W_host, const double *rho_plain_host);
+/* dfmg_set_chebyshev for every group. */
+int dfmg_multi_set_chebyshev(dfmg_multi *m, double alpha, int iters);
+/* dfmg_set_learned_chebyshev for every group; rho_plain_host has nprob
+ * entries in caller order (nullable). */
+int dfmg_multi_set_learned_chebyshev(dfmg_multi *m, const float *W_host, const double *rho_plain_host, int iters);
 /* Manufactured load vectors of every problem (host, offset[nprob] entries). */
 int dfmg_multi_manufactured_rhs(const dfmg_multi *m, double *F_host);
 /* dfmg_solve of every problem (stats: nprob entries, caller order). */

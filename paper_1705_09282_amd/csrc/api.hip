@@ -151,6 +151,16 @@ struct dfmg_ctx {
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
     std::vector<int> nu1l, nu2l; // per level: pre- and post-smoothing steps
     std::vector<double> eta_host;  // [problem][level]
+    // Chebyshev damping schedule (when sched_on): the smoothing steps of
+    // level l take the dampings sched[p][l][..] instead of eta[p][l]
+    double *sched = nullptr;       // device [problem][level][kSchedPerLevel]
+    double *sched0 = nullptr;      // device copy as built (a fallback overwrites sched)
+    double *unit = nullptr;        // device [problem]: 1.0 (undamped smoother, eigenvalue estimates)
+    float *mlpZ = nullptr;         // device [problem][MLP_OUT]: network outputs
+    bool sched_on = false;
+    std::vector<double> alpha;     // [problem][level]: ratio b / a of the Chebyshev interval [a, b]
+    std::vector<double> lmax;      // [problem][level]: estimate of the largest |eigenvalue| of S^-1 K
+    std::vector<double> sched_host;
     const Hierarchy &S() const { return P[0]; }
     int L() const { return P[0].pb.L; }
     bool mixed() const { return opt.precision == 1; }
@@ -290,6 +300,10 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->rho_plain = A.take<double>(np);
     c->eta_fixed = A.take<double>((size_t)L * np);
     c->fallback = A.take<int>(np);
+    c->sched = A.take<double>((size_t)L * np * kSchedPerLevel);
+    c->sched0 = A.take<double>((size_t)L * np * kSchedPerLevel);
+    c->unit = A.take<double>(np);
+    c->mlpZ = A.take<float>((size_t)MLP_OUT * np);
 }
 
 template <class T>
@@ -351,9 +365,23 @@ bool tracks_potentials(const dfmg_ctx *c) {
     return std::is_same<T, float>::value && c->mixed();
 }
 
-// eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l.
+// Damping of smoothing step `step` of level l: before the coarse correction
+// (phase 0) or after it (phase 1); device pointer and per-problem stride.
+struct Damping {
+    const double *eta;
+    int64_t stride;
+};
+Damping step_damping(const dfmg_ctx *c, int l, int phase, int step) {
+    if (c->sched_on)
+        return {c->sched + (size_t)l * kSchedPerLevel + phase * kMaxSteps + std::min(step, kMaxSteps - 1),
+                (int64_t)c->L() * kSchedPerLevel};
+    return {c->eta + l, c->L()};
+}
+
+// eta * sum_i E_i^T M_i E_i r added to (or assigned into) U on level l, with
+// the level's damping eta (dm: another damping, e.g. one step's of a schedule).
 template <class T>
-void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop) {
+void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop, Damping dm = {nullptr, 0}) {
     const HostLevel &h = c->S().lv[l];
     DevLevel &v = c->dl[l];
     PatchArgsT<T> a{};
@@ -369,11 +397,11 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop)
     a.M = v.data<T>().M;
     a.r = r;
     a.U = U;
-    a.eta = c->eta + l;
+    a.eta = dm.eta ? dm.eta : c->eta + l;
     a.smoff = h.n_patch;
     a.sM = v.sM;
     a.svec = h.n;
-    a.seta = c->L();
+    a.seta = dm.eta ? dm.stride : c->L();
     a.assign = assign ? 1 : 0;
     a.stop = stop;
     a.nprob = c->np;
@@ -490,6 +518,7 @@ void check(dfmg_ctx *c, int np_blocks) {
     fb.rho = c->rho_plain;
     fb.eta = c->eta;
     fb.eta_fixed = c->eta_fixed;
+    fb.sched = c->sched_on ? c->sched : nullptr;
     fb.flag = c->fallback;
     fb.L = c->L();
     launch_check(np_blocks, c->partial, c->nparts, c->hist, DFMG_MAX_HISTORY, c->counter, c->stop, c->stopw,
@@ -585,7 +614,8 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         return;
     }
     const bool psi = tracks_potentials<T>(c);
-    const int top = psi ? 0 : c->small_top;  // levels <= top: single-workgroup cycle
+    // levels <= top: single-workgroup cycle (level dampings only)
+    const int top = (psi || c->sched_on) ? 0 : c->small_top;
     for (int l = L - 1; l > top; --l) {
         LevelData<T> &v = c->dl[l].data<T>();
         const HostLevel &h = c->S().lv[l];
@@ -593,7 +623,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         bool first_res = (l == L - 1) && norm;
         for (int s = 0; s < c->nu1l[l]; ++s) {
             if (zero && !first_res) {
-                schwarz<T>(c, l, v.F, v.U, true, stop);  // U = 0: residual is F
+                schwarz<T>(c, l, v.F, v.U, true, stop, step_damping(c, l, 0, s));  // U = 0: residual is F
                 zero = false;
                 continue;
             }
@@ -602,7 +632,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
                 check(c, npb);
                 first_res = false;
             }
-            schwarz<T>(c, l, v.r, v.U, zero, stop);
+            schwarz<T>(c, l, v.r, v.U, zero, stop, step_damping(c, l, 0, s));
             zero = false;
         }
         if (zero && !first_res) {
@@ -632,7 +662,7 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         else prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
         for (int s = 0; s < c->nu2l[l]; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
-            schwarz<T>(c, l, v.r, v.U, false, stop);
+            schwarz<T>(c, l, v.r, v.U, false, stop, step_damping(c, l, 1, s));
         }
     }
 }
@@ -729,6 +759,105 @@ void check_level(const dfmg_ctx *c, int level, int minlevel = 0) {
     if (level < minlevel || level >= c->L()) throw ArgError("level out of range");
 }
 
+// Largest |eigenvalue| of the undamped additive-Schwarz operator S^-1 K of
+// every smoothed level and problem, by power iteration: x <- y / ||y||,
+// y = S^-1 (0 - K x) (the level's residual and smoother kernels in FP64 with
+// damping 1; the norms on the host).  The start vector is the same
+// deterministic pseudo-random vector for every problem.
+void estimate_lmax(dfmg_ctx *c, int iters) {
+    const int L = c->L(), np = c->np;
+    c->lmax.assign((size_t)np * L, 0.0);
+    for (int l = 1; l < L; ++l) {
+        const int64_t n = c->S().lv[l].n;
+        LevelData<double> &v = c->dl[l].d;
+        std::vector<double> x((size_t)n * np);
+        uint64_t z = 0x9e3779b97f4a7c15ull;
+        for (int64_t i = 0; i < n; ++i) {  // splitmix64 values in [-1, 1)
+            z += 0x9e3779b97f4a7c15ull;
+            uint64_t w = z;
+            w = (w ^ (w >> 30)) * 0xbf58476d1ce4e5b9ull;
+            w = (w ^ (w >> 27)) * 0x94d049bb133111ebull;
+            w ^= w >> 31;
+            const double u = (double)(w >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+            for (int p = 0; p < np; ++p) x[(size_t)p * n + i] = u;
+        }
+        for (int p = 0; p < np; ++p) {
+            double s2 = 0.0;
+            for (int64_t i = 0; i < n; ++i) s2 += x[(size_t)p * n + i] * x[(size_t)p * n + i];
+            const double inv = 1.0 / std::sqrt(s2);
+            for (int64_t i = 0; i < n; ++i) x[(size_t)p * n + i] *= inv;
+        }
+        launch_fill<double>(n, v.F, n, 0.0, nullptr, np, c->s);
+        for (int it = 0; it < iters; ++it) {
+            up(v.U, x, c->s);
+            spmv<double>(c, l, v.F, v.U, v.r, nullptr, nullptr);
+            schwarz<double>(c, l, v.r, v.U, true, nullptr, Damping{c->unit, 1});
+            HIPCHK(hipMemcpyAsync(x.data(), v.U, x.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+            HIPCHK(hipStreamSynchronize(c->s));
+            for (int p = 0; p < np; ++p) {
+                double s2 = 0.0;
+                for (int64_t i = 0; i < n; ++i) s2 += x[(size_t)p * n + i] * x[(size_t)p * n + i];
+                const double nrm = std::sqrt(s2);
+                if (!(nrm > 0.0 && nrm < 1e300)) throw HipError("eigenvalue estimate: zero or non-finite iterate");
+                c->lmax[(size_t)p * L + l] = nrm;  // ||S^-1 K x|| with ||x|| = 1
+                for (int64_t i = 0; i < n; ++i) x[(size_t)p * n + i] /= nrm;
+            }
+        }
+        launch_fill<double>(n, v.U, n, 0.0, nullptr, np, c->s);
+    }
+    HIPCHK(hipStreamSynchronize(c->s));
+}
+
+// Chebyshev dampings of one smoothing phase: the nu steps of damped
+// additive Schwarz with dampings 1 / theta_j, theta_j the zeros of the
+// degree-nu Chebyshev polynomial mapped to [b / alpha, b], leave the error
+// polynomial T_nu((b + a - 2 x) / (b - a)) / T_nu((b + a) / (b - a)),
+// a = b / alpha, in the preconditioned operator: the smallest maximum on
+// [a, b] of any polynomial of degree nu with value 1 at 0.  Pre-smoothing
+// takes the zeros from the largest theta down, post-smoothing the reverse.
+double chebyshev_damping(double b, double alpha, int nu, int j, bool reverse) {
+    const double a = b / alpha;
+    const int jj = reverse ? nu - 1 - j : j;
+    const double pi = 3.14159265358979323846;
+    const double theta = 0.5 * (b + a) + 0.5 * (b - a) * std::cos(pi * (2.0 * jj + 1.0) / (2.0 * nu));
+    return 1.0 / theta;
+}
+
+// the upper end of the Chebyshev interval, relative to the estimate of the
+// largest eigenvalue (power iteration approaches it from below)
+constexpr double kLmaxSafety = 1.05;
+
+// Per-step dampings of every problem and level from lmax, alpha and the
+// current step counts; uploaded (stream-ordered) to sched.  Entries past
+// a phase's step count repeat its last damping (unused).
+void build_schedule(dfmg_ctx *c) {
+    const int L = c->L(), np = c->np;
+    c->sched_host.assign((size_t)np * L * kSchedPerLevel, 0.0);
+    for (int p = 0; p < np; ++p)
+        for (int l = 1; l < L; ++l) {
+            const double b = kLmaxSafety * c->lmax[(size_t)p * L + l], al = c->alpha[(size_t)p * L + l];
+            double *dst = &c->sched_host[((size_t)p * L + l) * kSchedPerLevel];
+            for (int ph = 0; ph < 2; ++ph) {
+                const int nu = ph ? c->nu2l[l] : c->nu1l[l];
+                for (int j = 0; j < kMaxSteps; ++j)
+                    dst[ph * kMaxSteps + j] =
+                        nu > 0 ? chebyshev_damping(b, al, nu, std::min(j, nu - 1), ph == 1) : 0.0;
+            }
+        }
+    up(c->sched0, c->sched_host, c->s);
+    HIPCHK(hipMemcpyAsync(c->sched, c->sched0, c->sched_host.size() * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+}
+
+// the dampings of the schedule as built (a fallback of an earlier solve
+// replaced a problem's)
+void restore_schedule(dfmg_ctx *c) {
+    if (c->sched_on)
+        HIPCHK(hipMemcpyAsync(c->sched, c->sched0, (size_t)c->np * c->L() * kSchedPerLevel * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->s));
+}
+
 // no fallback thresholds: the fixed dampings are in use
 void clear_fallback(dfmg_ctx *c) { HIPCHK(hipMemsetAsync(c->rho_plain, 0, c->np * sizeof(double), c->s)); }
 
@@ -811,6 +940,7 @@ void solve_begin(dfmg_ctx *c, const double *F, const double *U, const int64_t *x
     launch_fill_int(np, c->counter, 0, c->s);
     launch_fill_int(np, c->fallback, 0, c->s);
     if (c->learned) apply_learned(c);
+    restore_schedule(c);
     launch_copy_off(n, F, xoff, n, v.F, nullptr, n, np, c->s);
     launch_copy_off(n, U, xoff, n, v.U, nullptr, n, np, c->s);
     launch_dot_partial((int)n, v.F, v.F, n, c->partial, c->nparts, nb, np, c->s);
@@ -1224,6 +1354,7 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         }
         up(c->eta, c->eta_host, s);
         up(c->eta_fixed, c->eta_host, s);
+        up(c->unit, std::vector<double>(np, 1.0), s);
         HIPCHK(hipMemsetAsync(c->fallback, 0, np * sizeof(int), s));
         HIPCHK(hipMemsetAsync(c->rho_plain, 0, np * sizeof(double), s));
         up(c->dcoef, H.dcoef, s);
@@ -1296,6 +1427,7 @@ int dfmg_set_smoothing(dfmg_ctx *c, const int *nu1, const int *nu2, int n) {
         if (c->bound) {
             enter(c);
             upload_small_tables(c);
+            if (c->sched_on) build_schedule(c);
             leave(c);
         }
     });
@@ -1619,6 +1751,21 @@ int dfmg_mlp_adam(float *W, float *m, float *v, const float *G, int t, float lr,
     });
 }
 
+// network inputs of every problem: log10(nu) / 2, log10(sigma) / 4,
+// |a| h / nu, k - 1.5
+std::vector<float> network_features(const dfmg_ctx *c) {
+    std::vector<float> feat((size_t)MLP_IN * c->np);
+    for (int p = 0; p < c->np; ++p) {
+        const Problem &pb = c->P[p].pb;
+        const double amag = pb.adv_kind == 1 ? std::fabs(pb.adv_c) / std::sqrt(2.0) : 0.0;
+        feat[p * MLP_IN + 0] = (float)(std::log10(pb.nu) / 2.0);
+        feat[p * MLP_IN + 1] = (float)(std::log10(std::max(pb.sigma, 1e-300)) / 4.0);
+        feat[p * MLP_IN + 2] = (float)(amag / (pb.N * pb.nu));
+        feat[p * MLP_IN + 3] = (float)(pb.k - 1.5);
+    }
+    return feat;
+}
+
 int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
     if (!c) return fail(DFMG_EINVAL, "null argument");
     return guarded([&] {
@@ -1631,18 +1778,11 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
             c->nu2l.assign(c->L(), c->opt.nu2);
             drop_graph(c);
             upload_small_tables(c);
+            if (c->sched_on) build_schedule(c);
             leave(c);
             return;
         }
-        std::vector<float> feat((size_t)MLP_IN * c->np);
-        for (int p = 0; p < c->np; ++p) {
-            const Problem &pb = c->P[p].pb;
-            const double amag = pb.adv_kind == 1 ? std::fabs(pb.adv_c) / std::sqrt(2.0) : 0.0;
-            feat[p * MLP_IN + 0] = (float)(std::log10(pb.nu) / 2.0);
-            feat[p * MLP_IN + 1] = (float)(std::log10(std::max(pb.sigma, 1e-300)) / 4.0);
-            feat[p * MLP_IN + 2] = (float)(amag / (pb.N * pb.nu));
-            feat[p * MLP_IN + 3] = (float)(pb.k - 1.5);
-        }
+        const std::vector<float> feat = network_features(c);
         // smoothing steps: the network's count outputs, the largest over the
         // batch (its problems share one launch sequence)
         const int L = c->L();
@@ -1664,7 +1804,131 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
         else clear_fallback(c);
         c->learned = true;
         apply_learned(c);
+        if (c->sched_on) build_schedule(c);
         HIPCHK(hipStreamSynchronize(c->s));
+        leave(c);
+    });
+}
+
+int dfmg_set_chebyshev(dfmg_ctx *c, double alpha, int iters) {
+    if (!c) return fail(DFMG_EINVAL, "null argument");
+    if (!(alpha == 0.0 || (alpha > 1.0 && alpha <= 1e6))) return fail(DFMG_EINVAL, "alpha must be 0 or in (1, 1e6]");
+    if (alpha > 0.0 && (iters < 1 || iters > 1000)) return fail(DFMG_EINVAL, "iters must lie in [1, 1000]");
+    return guarded([&] {
+        enter(c);
+        drop_graph(c);
+        if (alpha == 0.0) {
+            c->sched_on = false;
+        } else {
+            estimate_lmax(c, iters);
+            c->alpha.assign((size_t)c->np * c->L(), alpha);
+            c->sched_on = true;
+            build_schedule(c);
+        }
+        HIPCHK(hipStreamSynchronize(c->s));
+        leave(c);
+    });
+}
+
+int dfmg_set_chebyshev_alpha(dfmg_ctx *c, const double *alpha, int n) {
+    if (!c || !alpha) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        const int L = c->L(), m = L - 1;
+        if (n != m && n != m * c->np) throw ArgError("need n_levels - 1 or nprob * (n_levels - 1) ratios");
+        for (int i = 0; i < n; ++i)
+            if (!(alpha[i] > 1.0 && alpha[i] <= 1e6)) throw ArgError("alpha must lie in (1, 1e6]");
+        if (!c->sched_on) throw StateError("no damping schedule in use (call dfmg_set_chebyshev first)");
+        enter(c);
+        for (int p = 0; p < c->np; ++p)
+            for (int i = 0; i < m; ++i) c->alpha[(size_t)p * L + (L - 1 - i)] = alpha[(n == m ? 0 : (size_t)p * m) + i];
+        build_schedule(c);
+        leave(c);
+    });
+}
+
+int dfmg_set_learned_chebyshev(dfmg_ctx *c, const float *W, const double *rho, int iters) {
+    if (!c) return fail(DFMG_EINVAL, "null argument");
+    if (W && (iters < 1 || iters > 1000)) return fail(DFMG_EINVAL, "iters must lie in [1, 1000]");
+    return guarded([&] {
+        enter(c);
+        const int L = c->L(), np = c->np;
+        // the per-level dampings stay the fixed ones (the fallback's)
+        c->learned = false;
+        upload_eta(c);
+        drop_graph(c);
+        if (!W) {
+            clear_fallback(c);
+            c->sched_on = false;
+            c->nu1l.assign(L, c->opt.nu1);
+            c->nu2l.assign(L, c->opt.nu2);
+            upload_small_tables(c);
+            leave(c);
+            return;
+        }
+        // the network's outputs on the device (the inference kernel), read back
+        const std::vector<float> feat = network_features(c);
+        up(c->mlpW, W, MLP_NPARAM, c->s);
+        up(c->feat, feat, c->s);
+        launch_mlp_forward(np, c->mlpW, c->feat, c->mlpZ, c->s);
+        HIPCHK(hipGetLastError());
+        std::vector<float> z((size_t)np * MLP_OUT);
+        HIPCHK(hipMemcpyAsync(z.data(), c->mlpZ, z.size() * sizeof(float), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        // outputs 0 .. MLP_ETA-1: logit of a / b = 1 / alpha per level (finest
+        // first; deeper levels take the last); the others: step counts, the
+        // largest over the batch (one launch sequence)
+        std::vector<int> steps(L - 1, 1);
+        c->alpha.assign((size_t)np * L, 0.0);
+        for (int p = 0; p < np; ++p)
+            for (int i = 0; i < L - 1; ++i) {
+                const float *zp = &z[(size_t)p * MLP_OUT];
+                const double q = 1.0 / (1.0 + std::exp(-(double)zp[std::min(i, MLP_ETA - 1)]));
+                c->alpha[(size_t)p * L + (L - 1 - i)] = std::min(1e3, std::max(1.5, 1.0 / q));
+                const long v = std::lround(zp[MLP_ETA + std::min(i, MLP_OUT - MLP_ETA - 1)]);
+                steps[i] = std::max(steps[i], (int)std::min(8L, std::max(1L, v)));
+            }
+        for (int i = 0; i < L - 1; ++i) c->nu1l[L - 1 - i] = c->nu2l[L - 1 - i] = steps[i];
+        upload_small_tables(c);
+        if (rho) up(c->rho_plain, rho, np, c->s);
+        else clear_fallback(c);
+        if (c->lmax.empty()) estimate_lmax(c, iters);
+        c->sched_on = true;
+        build_schedule(c);
+        leave(c);
+    });
+}
+
+int dfmg_get_alpha(const dfmg_ctx *c, double *out) {
+    if (!c || !out) return fail(DFMG_EINVAL, "null argument");
+    if (!c->sched_on) return fail(DFMG_ESTATE, "no damping schedule in use");
+    const int L = c->L();
+    for (int p = 0; p < c->np; ++p)
+        for (int i = 0; i < L - 1; ++i) out[(size_t)p * (L - 1) + i] = c->alpha[(size_t)p * L + (L - 1 - i)];
+    return DFMG_OK;
+}
+
+int dfmg_get_lmax(const dfmg_ctx *c, double *out) {
+    if (!c || !out) return fail(DFMG_EINVAL, "null argument");
+    if (c->lmax.empty()) return fail(DFMG_ESTATE, "no eigenvalue estimate (call dfmg_set_chebyshev first)");
+    const int L = c->L();
+    for (int p = 0; p < c->np; ++p)
+        for (int i = 0; i < L - 1; ++i) out[(size_t)p * (L - 1) + i] = c->lmax[(size_t)p * L + (L - 1 - i)];
+    return DFMG_OK;
+}
+
+int dfmg_get_schedule(dfmg_ctx *c, double *out) {
+    if (!c || !out) return fail(DFMG_EINVAL, "null argument");
+    if (!c->sched_on) return fail(DFMG_ESTATE, "no damping schedule in use");
+    return guarded([&] {
+        enter(c);
+        const int L = c->L();
+        std::vector<double> e((size_t)c->np * L * kSchedPerLevel);
+        HIPCHK(hipMemcpyAsync(e.data(), c->sched, e.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIPCHK(hipStreamSynchronize(c->s));
+        for (int p = 0; p < c->np; ++p)
+            for (int i = 0; i < L - 1; ++i)
+                std::copy_n(&e[((size_t)p * L + (L - 1 - i)) * kSchedPerLevel], kSchedPerLevel,
+                            out + ((size_t)p * (L - 1) + i) * kSchedPerLevel);
         leave(c);
     });
 }
@@ -2062,6 +2326,32 @@ int dfmg_multi_set_learned(dfmg_multi *m, const float *W, const double *rho) {
                 for (int p : m->member[i]) r.push_back(rho[p]);
             if (dfmg_set_learned(m->g[i], W, rho ? r.data() : nullptr) != DFMG_OK) throw HipError(g_err);
         }
+        multi_drop_graph(m);  // the step counts are part of the captured launches
+    });
+}
+
+int dfmg_multi_set_chebyshev(dfmg_multi *m, double alpha, int iters) {
+    if (!m) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        if (!m->bound) throw StateError("workspace not bound (call dfmg_multi_bind first)");
+        for (size_t i = 0; i < m->g.size(); ++i)
+            if (dfmg_set_chebyshev(m->g[i], alpha, iters) != DFMG_OK) throw ArgError(g_err);
+        multi_drop_graph(m);
+    });
+}
+
+int dfmg_multi_set_learned_chebyshev(dfmg_multi *m, const float *W, const double *rho, int iters) {
+    if (!m) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        if (!m->bound) throw StateError("workspace not bound (call dfmg_multi_bind first)");
+        for (size_t i = 0; i < m->g.size(); ++i) {
+            std::vector<double> r;
+            if (rho)
+                for (int p : m->member[i]) r.push_back(rho[p]);
+            if (dfmg_set_learned_chebyshev(m->g[i], W, rho ? r.data() : nullptr, iters) != DFMG_OK)
+                throw HipError(g_err);
+        }
+        multi_drop_graph(m);
     });
 }
 

@@ -673,7 +673,13 @@ __global__ __launch_bounds__(kBlock) void k_check(int nparts, const double *part
             // continue with the fixed dampings (the iteration stays linear,
             // so the iterate so far is a valid starting guess)
             fb.flag[prob] = 1;
-            for (int l = 1; l < fb.L; ++l) fb.eta[(int64_t)prob * fb.L + l] = fb.eta_fixed[(int64_t)prob * fb.L + l];
+            for (int l = 1; l < fb.L; ++l) {
+                const double e = fb.eta_fixed[(int64_t)prob * fb.L + l];
+                fb.eta[(int64_t)prob * fb.L + l] = e;
+                if (fb.sched)
+                    for (int j = 0; j < kSchedPerLevel; ++j)
+                        fb.sched[((int64_t)prob * fb.L + l) * kSchedPerLevel + j] = e;
+            }
         } else if (grow) {
             f = 2;
         }

@@ -36,6 +36,10 @@ namespace dfmg {
 
 constexpr int kBlock = 256;
 constexpr int kStopLanes = 64;  // copies per problem of the wide stop flags
+// per-step dampings of a level: kMaxSteps pre-smoothing steps, then
+// kMaxSteps post-smoothing steps
+constexpr int kMaxSteps = 16;
+constexpr int kSchedPerLevel = 2 * kMaxSteps;
 
 // One level's stencil-ELL operator and the vectors of r = F - K U.
 template <class T>
@@ -213,10 +217,13 @@ void launch_reduce(int nparts, const double *partial, int64_t spart, double *out
 // the first contracts problem p's residual by more than 1.05 * rho[p], or the
 // residual has grown by six orders, its dampings eta[p][1..L-1] are reset to
 // eta_fixed[p][..] and flag[p] is set (once; growth then means divergence).
+// With a per-step damping schedule in use (sched, [p][level][kSchedPerLevel])
+// every step of level l takes eta_fixed[p][l] as well.
 struct Fallback {
     const double *rho;        // nullable: no fallback
     double *eta;
     const double *eta_fixed;
+    double *sched;            // nullable: no schedule
     int *flag;
     int L;
 };

@@ -19,6 +19,12 @@ c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_dblp = ctypes.POINTER(ctypes.c_double)
 
 MAX_HISTORY = 512
+MAX_STEPS = 16   # smoothing steps per phase and level (schedule entries per phase)
+# Chebyshev schedule defaults: smoothing interval [b / 10, b] and 30 power
+# iterations for b (2D k = 2 Stokes: alpha from 8 to 15 gives the same cycle
+# counts at 32^2 and 64^2)
+CHEB_ALPHA = 10.0
+CHEB_ITERS = 30
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EDIVERGED", -6: "ESTATE"}
 
 
@@ -85,6 +91,12 @@ SIGNATURES = [
     ("dfmg_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]),
     ("dfmg_set_learned", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp]),
     ("dfmg_get_eta", c_int, [c_void_p, c_dblp]),
+    ("dfmg_set_chebyshev", c_int, [c_void_p, c_double, c_int]),
+    ("dfmg_get_lmax", c_int, [c_void_p, c_dblp]),
+    ("dfmg_set_chebyshev_alpha", c_int, [c_void_p, c_dblp, c_int]),
+    ("dfmg_get_alpha", c_int, [c_void_p, c_dblp]),
+    ("dfmg_set_learned_chebyshev", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp, c_int]),
+    ("dfmg_get_schedule", c_int, [c_void_p, c_dblp]),
     ("dfmg_export_matrix", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_patch_total", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_patches", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_i32p]),
@@ -99,6 +111,8 @@ SIGNATURES = [
     ("dfmg_multi_bind", c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
     ("dfmg_multi_autotune", c_int, [c_void_p, c_int]),
     ("dfmg_multi_set_learned", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp]),
+    ("dfmg_multi_set_chebyshev", c_int, [c_void_p, c_double, c_int]),
+    ("dfmg_multi_set_learned_chebyshev", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp, c_int]),
     ("dfmg_multi_manufactured_rhs", c_int, [c_void_p, c_dblp]),
     ("dfmg_multi_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
     ("dfmg_multi_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
@@ -121,6 +135,16 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def _network_args(W, rho_plain, nprob):
+    w = np.ascontiguousarray(W, dtype=np.float32)
+    if w.size != MLP_NPARAM:
+        raise ValueError(f"expected {MLP_NPARAM} parameters")
+    r = None if rho_plain is None else np.ascontiguousarray(rho_plain, dtype=np.float64)
+    if r is not None and r.size != nprob:
+        raise ValueError("one plain rate per problem")
+    return w, r
 
 
 class DfmgError(RuntimeError):
@@ -437,6 +461,48 @@ class Solver:
         _check(lib().dfmg_get_eta(self._ctx, _ptr(out, ctypes.c_double)))
         return out.reshape(self.nprob, self.n_levels - 1)
 
+    def set_chebyshev(self, alpha=CHEB_ALPHA, iters=CHEB_ITERS):
+        """Chebyshev damping schedule on [b / alpha, b] per problem and level
+        (b from a power-iteration estimate of the largest eigenvalue of the
+        undamped smoother's operator); alpha 0 turns it off."""
+        _check(lib().dfmg_set_chebyshev(self._ctx, float(alpha), int(iters)))
+
+    def set_chebyshev_alpha(self, alphas):
+        """Interval ratios per smoothed level (finest first), one row for all
+        problems or one row per problem."""
+        a = np.ascontiguousarray(alphas, dtype=np.float64).ravel()
+        _check(lib().dfmg_set_chebyshev_alpha(self._ctx, _ptr(a, ctypes.c_double), int(a.size)))
+
+    def get_alpha(self):
+        out = np.zeros(self.nprob * (self.n_levels - 1))
+        _check(lib().dfmg_get_alpha(self._ctx, _ptr(out, ctypes.c_double)))
+        return out.reshape(self.nprob, self.n_levels - 1)
+
+    def set_learned_chebyshev(self, W, rho_plain=None, iters=CHEB_ITERS):
+        """Chebyshev schedule with the interval ratio per level and the step
+        counts predicted by the network W; W None turns it off."""
+        if W is None:
+            _check(lib().dfmg_set_learned_chebyshev(self._ctx, None, None, int(iters)))
+            return
+        w, r = _network_args(W, rho_plain, self.nprob)
+        _check(lib().dfmg_set_learned_chebyshev(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                None if r is None else _ptr(r, ctypes.c_double), int(iters)))
+
+    def get_lmax(self):
+        """Eigenvalue estimates of set_chebyshev, one row per problem, finest
+        level first."""
+        out = np.zeros(self.nprob * (self.n_levels - 1))
+        _check(lib().dfmg_get_lmax(self._ctx, _ptr(out, ctypes.c_double)))
+        return out.reshape(self.nprob, self.n_levels - 1)
+
+    def get_schedule(self):
+        """Per-step dampings in use: array (nprob, n_levels - 1, 2, 16),
+        finest level first; [.., 0, j] pre-smoothing step j, [.., 1, j]
+        post-smoothing step j."""
+        out = np.zeros(self.nprob * (self.n_levels - 1) * 2 * MAX_STEPS)
+        _check(lib().dfmg_get_schedule(self._ctx, _ptr(out, ctypes.c_double)))
+        return out.reshape(self.nprob, self.n_levels - 1, 2, MAX_STEPS)
+
     def coarse_solve(self, G, dU):
         n = self._nlev(0)
         _check(lib().dfmg_coarse_solve(self._ctx, _dev(G, n), _dev(dU, n)))
@@ -539,6 +605,17 @@ class MultiSolver:
             raise ValueError("one plain rate per problem")
         _check(lib().dfmg_multi_set_learned(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                             None if r is None else _ptr(r, ctypes.c_double)))
+
+    def set_chebyshev(self, alpha=CHEB_ALPHA, iters=CHEB_ITERS):
+        _check(lib().dfmg_multi_set_chebyshev(self._ctx, float(alpha), int(iters)))
+
+    def set_learned_chebyshev(self, W, rho_plain=None, iters=CHEB_ITERS):
+        if W is None:
+            _check(lib().dfmg_multi_set_learned_chebyshev(self._ctx, None, None, int(iters)))
+            return
+        w, r = _network_args(W, rho_plain, self.nprob)
+        _check(lib().dfmg_multi_set_learned_chebyshev(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                      None if r is None else _ptr(r, ctypes.c_double), int(iters)))
 
     def manufactured_rhs(self):
         F = np.zeros(self.n_total, np.float64)

@@ -29,6 +29,15 @@ with the method itself and trains the network on the GPU:
 ``python -m paper_1705_09282_amd.learned [out.json]`` runs both on the
 default training grid and writes the weights, the training data and the
 fallback thresholds (default: ``data/damping_mlp.json`` beside this module).
+
+Chebyshev schedule (``--chebyshev``, default output
+``data/chebyshev_mlp.json``): the same network predicts, per smoothed level,
+the logit of 1 / alpha (the ratio of the ends of the Chebyshev interval
+[b / alpha, b] of the damping schedule) and the smoothing steps.  Targets per
+training problem, with the schedule on: ``best_steps`` as above, then a
+coordinate search of alpha per level over ``ALPHAS`` (copies of the problem
+in one batch, each with its own ratios), scored by the mean contraction per
+cycle; the fallback threshold is the fixed damping's, as above.
 """
 import json
 import math
@@ -42,6 +51,9 @@ from .dfmg import BatchSolver, Solver, MLP_NPARAM, MLP_NOUT, mlp_adam, mlp_grad,
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "data", "damping_mlp.json")
+CHEB_WEIGHTS = os.path.join(HERE, "data", "chebyshev_mlp.json")
+ALPHAS = (5.0, 7.0, 10.0, 14.0, 20.0, 30.0)
+CHEB_ALPHA0 = 10.0
 NOUT = MLP_NOUT   # 5 damping logits, then 5 step counts (finest level first)
 NETA = 5
 FACTORS = (0.55, 0.7, 0.85, 1.0, 1.15, 1.3, 1.45)
@@ -106,15 +118,18 @@ def step_costs(d, N, L, k, device="cuda", reps=20):
     return max(best - Bc.sum(), 0.0), Bc
 
 
-def best_steps(prob, cost, max_cycles=80, passes=2, tol=1e-8, device="cuda"):
+def best_steps(prob, cost, max_cycles=80, passes=2, tol=1e-8, device="cuda", chebyshev=False):
     """Search of the per-level smoothing steps (pre = post) for one problem
     minimising the modelled solve time cycles(s) * (A + B . s): the best
     uniform count, then coordinate steps; a candidate replaces the current
-    steps only if 1% faster.  Returns (steps, modelled ms, contraction)."""
+    steps only if 1% faster.  chebyshev: with the damping schedule at the
+    ratio CHEB_ALPHA0.  Returns (steps, modelled ms, contraction)."""
     import torch
     A, Bc = cost
     S = Solver(prob["d"], prob["N"], prob["L"], prob["k"], nu=prob["nu"], sigma=prob["sigma"], c=prob["c"],
                precision=1, max_cycles=max_cycles).bind(device)
+    if chebyshev:
+        S.set_chebyshev(CHEB_ALPHA0)
     F = torch.tensor(S.manufactured_rhs(), device=device)
     U = torch.zeros_like(F)
 
@@ -186,6 +201,48 @@ def best_damping(prob, steps=None, max_cycles=80, passes=2, tol=1e-8, device="cu
     return cur, best, rho_plain, worst_plain
 
 
+def best_alpha(prob, steps, max_cycles=80, passes=1, tol=1e-8, device="cuda"):
+    """Coordinate search of the schedule's ratio alpha per level for one
+    problem with the given steps: copies of the problem in one batch, copy j
+    with ALPHAS[j] on the level searched; the candidate with the smallest
+    mean contraction per cycle replaces the current ratios if 1% better.
+    Returns (alphas, rho_best, rho_plain, worst single-cycle ratio of the
+    fixed damping with V(2,2))."""
+    import torch
+    C = len(ALPHAS)
+    B = BatchSolver(prob["d"], prob["N"], prob["L"], prob["k"], [prob["nu"]] * C, [prob["sigma"]] * C,
+                    [prob["c"]] * C, precision=1, max_cycles=max_cycles).bind(device)
+    F = torch.tensor(B.manufactured_rhs(), device=device)
+    U = torch.zeros_like(F)
+    U.zero_()
+    st = B.solve(F, U, tol=tol, raise_on_error=False)[0]
+    rho_plain, worst_plain = contraction(st), worst_cycle(st)
+    B.set_smoothing(steps, steps)
+    B.set_chebyshev(CHEB_ALPHA0)
+    nlev = prob["L"] - 1
+    cur = np.full(nlev, CHEB_ALPHA0)
+
+    def scores(cands):
+        B.set_chebyshev_alpha(np.array(cands))
+        U.zero_()
+        return np.array([contraction(x) for x in B.solve(F, U, tol=tol, raise_on_error=False)])
+
+    best = scores([cur] * C)[0]
+    for _ in range(passes):
+        for lev in range(nlev):
+            cand = []
+            for a in ALPHAS:
+                e = cur.copy()
+                e[lev] = a
+                cand.append(e)
+            rho = scores(cand)
+            i = int(np.argmin(rho))
+            if rho[i] < 0.99 * best:
+                best, cur = rho[i], cand[i]
+    B.close()
+    return cur, best, rho_plain, worst_plain
+
+
 def training_problems():
     """Default training grid: 2D, both degrees, 128^2 with 6 grids over
     nu x sigma x |a|h/nu, plus the Stokes problems of both degrees on 256^2."""
@@ -200,10 +257,11 @@ def training_problems():
     return out
 
 
-def sweep(problems, log=None):
+def sweep(problems, log=None, chebyshev=False):
     """Training data: X (n x 4), Y (n x 10) targets (damping logits, step
-    counts), M (n x 10) weights, rho_plain, rho_best, worst_plain, steps,
-    and the time model of every mesh."""
+    counts; chebyshev: logits of 1 / alpha, step counts), M (n x 10)
+    weights, rho_plain, rho_best, worst_plain, steps, and the time model of
+    every mesh."""
     X, Y, Mk, rp, rb, wp, ss = [], [], [], [], [], [], []
     costs = {}
     for i, p in enumerate(problems):
@@ -213,8 +271,12 @@ def sweep(problems, log=None):
             costs[key] = step_costs(*key)
             if log:
                 log(f"[sweep] time model {key}: A {costs[key][0]:.4f} ms, B {np.round(costs[key][1], 4).tolist()}")
-        steps, ms, rho_s = best_steps(p, costs[key])
-        eta, rho, rho_plain, worst = best_damping(p, steps)
+        steps, ms, rho_s = best_steps(p, costs[key], passes=1 if chebyshev else 2, chebyshev=chebyshev)
+        if chebyshev:
+            alpha, rho, rho_plain, worst = best_alpha(p, steps)
+            eta = 1.0 / alpha   # the network's first outputs: logit of a / b
+        else:
+            eta, rho, rho_plain, worst = best_damping(p, steps)
         y = np.zeros(NOUT)
         mk = np.zeros(NOUT)
         for j in range(min(NETA, eta.size)):
@@ -230,8 +292,9 @@ def sweep(problems, log=None):
         wp.append(worst)
         ss.append(steps[:NETA])
         if log:
+            what = f"alpha {np.round(1.0 / eta, 1).tolist()}" if chebyshev else f"eta {np.round(eta, 3).tolist()}"
             log(f"[sweep {i + 1}/{len(problems)}] {p} steps {steps} (model {ms:.2f} ms) rho plain {rho_plain:.3f} "
-                f"-> {rho:.3f} eta {np.round(eta, 3).tolist()} ({time.time() - t0:.1f} s)")
+                f"-> {rho:.3f} {what} ({time.time() - t0:.1f} s)")
     return dict(X=np.array(X), Y=np.array(Y), M=np.array(Mk), rho_plain=np.array(rp), rho_best=np.array(rb),
                 worst_plain=np.array(wp), steps=np.array(ss),
                 time_model=np.array([[*k, c[0], *c[1]] for k, c in costs.items()]))
@@ -328,17 +391,28 @@ def problem_features(solver):
 def apply(solver, model=None, fallback=True):
     """Switch a bound Solver/BatchSolver to the learned dampings of `model`
     (default: the shipped weights), with the fallback threshold of the
-    nearest training point."""
+    nearest training point.  A model trained with --chebyshev sets the
+    learned Chebyshev schedule instead."""
     model = load() if model is None else model
     rho = rho_plain_for(model, problem_features(solver)) if fallback else None
-    solver.set_learned(model["W"], rho)
+    if model["meta"].get("mode") == "chebyshev":
+        solver.set_learned_chebyshev(model["W"], rho)
+    else:
+        solver.set_learned(model["W"], rho)
+
+
+def apply_chebyshev(solver, model=None, fallback=True):
+    """apply() with the shipped Chebyshev-schedule network by default."""
+    apply(solver, load(CHEB_WEIGHTS) if model is None else model, fallback)
 
 
 def main():
     log = lambda s: print(s, flush=True)
+    args = [a for a in sys.argv[1:] if a != "--chebyshev"]
+    cheb = "--chebyshev" in sys.argv[1:]
     t0 = time.time()
     probs = training_problems()
-    data = sweep(probs, log=log)
+    data = sweep(probs, log=log, chebyshev=cheb)
     log(f"[sweep] {len(probs)} problems in {time.time() - t0:.0f} s; mean rho plain "
         f"{data['rho_plain'].mean():.3f} best {data['rho_best'].mean():.3f}")
     W, hist = train(data["X"], data["Y"], data["M"], log=log)
@@ -346,7 +420,12 @@ def main():
             "objective": "steps: modelled time to 1e-8 of the FP32 refinement (4-problem batch); dampings: "
                          "mean contraction per cycle of a solve to 1e-8 from U=0 with those steps",
             "problems": len(probs), "features": "log10(nu)/2, log10(sigma)/4, |a|h/nu, k-1.5"}
-    out = sys.argv[1] if len(sys.argv) > 1 else WEIGHTS
+    if cheb:
+        meta.update(mode="chebyshev", alphas=ALPHAS,
+                    objective="steps: modelled time to 1e-8 of the FP32 refinement with the Chebyshev schedule "
+                              f"(alpha {CHEB_ALPHA0}); alpha per level: mean contraction per cycle of a solve to "
+                              "1e-8 from U=0 with those steps; outputs 0..4 are logit(1/alpha)")
+    out = args[0] if args else (CHEB_WEIGHTS if cheb else WEIGHTS)
     save(out, W, data, meta)
     log(f"[train] final loss {hist[-1][1]:.5f}; wrote {out}")
 

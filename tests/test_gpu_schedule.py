@@ -1,0 +1,324 @@
+"""GPU parity of the Chebyshev damping schedule (dfmg_set_chebyshev): the
+library's power-iteration eigenvalue estimate against the oracle's dense
+eigenvalue, its per-step dampings against the oracle's Chebyshev dampings,
+scheduled V-cycles (FP64) against the oracle's cycles with the same dampings,
+scheduled FP32 refinement against the FP64 oracle solution, the schedule
+following step-count changes, the fallback and its reset, and mixed-mesh
+batches.  Tolerances as in the other parity tests: 1e-10 relative L2 for FP64
+velocities after whole cycles, 1e-8 after FP32 refinement."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.multigrid import Hierarchy, vcycles, solve, eta_levels, chebyshev_schedule, lmax_dense, default_eta
+from oracle.assemble import load_vector, rotation_field
+from oracle.manufactured import forcing
+from oracle.complex import random_divfree_start
+from oracle.diagnostics import div_norm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ALPHA = 10.0
+
+
+def dev(x):
+    return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle(d, N, k, L, nu, sigma, c):
+    adv = rotation_field(c) if c else None
+    h = Hierarchy(d, N, k, L, nu, sigma, adv)
+    return h, load_vector(h.finest.disc, forcing(d, nu, sigma, adv))
+
+
+def divfree_start(h, seed):
+    disc = h.finest.disc
+    return random_divfree_start(disc, workloads.random_coefficients(disc.n_psi, seed),
+                                workloads.random_coefficients(disc.n_q, seed + 1))
+
+
+@pytest.mark.parametrize("d,N,k,L", [(2, 16, 2, 3), (2, 16, 1, 3), (3, 8, 1, 3)])
+def test_lmax_estimate_matches_dense_eigenvalue(d, N, k, L):
+    from paper_1705_09282_amd.dfmg import Solver
+    print(f"\n[case] d={d} N={N} k={k} L={L}", flush=True)
+    s = Solver(d, N, L, k, nu=0.5, sigma=4.0).bind()
+    s.set_chebyshev(ALPHA, 100)
+    lm = s.get_lmax()[0]
+    h, _ = oracle(d, N, k, L, 0.5, 4.0, 0.0)
+    dense = [lmax_dense(h.levels[l]) for l in range(L - 1, 0, -1)]
+    print(f"[lmax] library {np.round(lm, 4).tolist()} dense {np.round(dense, 4).tolist()}")
+    for a, b in zip(lm, dense):
+        assert abs(a - b) <= 0.02 * b
+    s.close()
+
+
+@pytest.mark.parametrize("n1,n2", [([3, 1], [2, 4]), ([4, 4], [4, 4]), ([1, 0], [0, 6])])
+def test_schedule_matches_oracle_dampings(n1, n2):
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    d, N, k, L = 2, 16, 2, 3
+    B = BatchSolver(d, N, L, k, [1.0, 0.5], [1e-2, 1e3], [0.0, 4.0]).bind()
+    B.set_smoothing(n1, n2)
+    B.set_chebyshev(ALPHA, 30)
+    lm = B.get_lmax()
+    sch = B.get_schedule()
+    h, _ = oracle(d, N, k, L, 1.0, 1.0, 0.0)
+    for p in range(2):
+        ref = chebyshev_schedule(h, lm[p], ALPHA, n1, n2)
+        for i in range(L - 1):
+            for ph, nu in ((0, n1[i]), (1, n2[i])):
+                got = sch[p, i, ph]
+                if nu == 0:
+                    continue
+                np.testing.assert_allclose(got[:nu], ref[i][ph], rtol=1e-14)
+                assert np.all(got[nu:] == got[nu - 1])   # padding repeats the last step
+    B.close()
+
+
+@pytest.mark.parametrize("d,N,k,L,c,n1,n2", [(2, 16, 2, 3, 0.0, [3, 2], [2, 3]), (2, 32, 1, 4, 6.0, [2, 3, 1], [4, 1, 2]),
+                                             (2, 12, 2, 3, 0.0, [4, 4], [4, 4]), (3, 8, 1, 3, 0.0, [2, 2], [2, 2])])
+def test_scheduled_vcycles_match_oracle(d, N, k, L, c, n1, n2):
+    from paper_1705_09282_amd.dfmg import Solver
+    print(f"\n[case] d={d} N={N} k={k} L={L} c={c} steps {n1} {n2}", flush=True)
+    s = Solver(d, N, L, k, nu=0.5, sigma=4.0, c=c).bind()
+    s.set_smoothing(n1, n2)
+    s.set_chebyshev(ALPHA, 30)
+    h, F = oracle(d, N, k, L, 0.5, 4.0, c)
+    sched = chebyshev_schedule(h, s.get_lmax()[0], ALPHA, n1, n2)
+    U0 = divfree_start(h, 71)
+    Ud = dev(U0)
+    nv = h.finest.disc.n_v
+    for m in (1, 2):
+        s.vcycle(dev(F), Ud, 1)
+        Uo = vcycles(h, U0, F, m, n1, n2, eta=sched)
+        assert rel_l2(host(Ud)[:nv], Uo[:nv]) < 1e-10
+        assert s.div_norm(Ud) < 1e-10
+    # whole solve: same cycle count as the oracle with the same dampings
+    Ud = dev(np.zeros_like(F))
+    st = s.solve(dev(F), Ud, tol=1e-9)
+    Uo, hist = solve(h, F, tol=1e-9, nu1=n1, nu2=n2, eta=sched)
+    assert st["converged"] and st["cycles"] == len(hist) - 1
+    assert rel_l2(host(Ud)[:nv], Uo[:nv]) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("cfg", [workloads.stokes2d(1e-2, N=64, L=5), workloads.stokes2d(1e4, N=64, L=5),
+                                 workloads.oseen2d(0.1, 0.5, N=32, L=4)])
+def test_scheduled_fp32_refinement_matches_fp64_oracle(cfg):
+    from paper_1705_09282_amd.dfmg import Solver
+    print(f"\n[case] {cfg}", flush=True)
+    s = Solver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], nu=cfg["nu"], sigma=cfg["sigma"], c=cfg["c"],
+               precision=1).bind()
+    h, F = oracle(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"], cfg["c"])
+    Ud = dev(np.zeros_like(F))
+    plain = s.solve(dev(F), Ud, tol=1e-10)["cycles"]
+    s.set_chebyshev(ALPHA, 30)
+    Ud = dev(np.zeros_like(F))
+    st = s.solve(dev(F), Ud, tol=1e-10)
+    Uo, hist = solve(h, F, tol=1e-12, max_cycles=400)
+    Ug = host(Ud)
+    nv = h.finest.disc.n_v
+    err = rel_l2(Ug[:nv], Uo[:nv])
+    print(f"[sched fp32] cycles {st['cycles']} (level dampings {plain}) vel rel err {err:.2e}")
+    assert st["converged"] and (cfg["c"] != 0.0 or st["cycles"] <= plain)
+    assert err < 1e-8
+    assert div_norm(h.finest.disc, Ug) < 1e-10 and s.div_norm(Ud) < 1e-10
+    s.close()
+
+
+def test_schedule_follows_steps_and_fallback_resets_it():
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd import learned
+    d, N, k, L = 2, 32, 2, 4
+    B = BatchSolver(d, N, L, k, [1.0, 1.0], [1.0, 1e2]).bind()
+    h, _ = oracle(d, N, k, L, 1.0, 1.0, 0.0)
+    model = learned.load()
+    B.set_learned(model["W"], None)
+    B.set_chebyshev(ALPHA, 30)
+    lm = B.get_lmax()
+
+    def check_built():
+        n1, n2 = B.get_smoothing()
+        sch = B.get_schedule()
+        for p in range(2):
+            ref = chebyshev_schedule(h, lm[p], ALPHA, n1, n2)
+            for i in range(L - 1):
+                np.testing.assert_allclose(sch[p, i, 0, :n1[i]], ref[i][0], rtol=1e-14)
+                np.testing.assert_allclose(sch[p, i, 1, :n2[i]], ref[i][1], rtol=1e-14)
+
+    check_built()
+    B.set_smoothing([2, 3, 1], [3, 2, 2])
+    check_built()
+    # a threshold no cycle can meet: the check switches problem 0 to the fixed
+    # damping in every step of every level
+    B.set_learned(model["W"], np.array([1e-12, 1e9]))
+    B.set_smoothing([2, 3, 1], [3, 2, 2])
+    F = dev(B.manufactured_rhs())
+    U = torch.zeros_like(F)
+    st = B.solve(F, U, tol=1e-8)
+    assert st[0]["fallback"] and not st[1]["fallback"]
+    assert st[0]["converged"] and st[1]["converged"]
+    sch = B.get_schedule()
+    assert np.all(sch[0] == default_eta(2, 2))
+    assert not np.any(sch[1] == default_eta(2, 2))
+    # the next solve starts from the schedule as built (stops at its first check)
+    U.zero_()
+    B.solve(F, U, tol=1.0)
+    check_built()
+    assert max(B.div_norm(U)) < 1e-10
+    B.set_chebyshev(0.0, 1)
+    with pytest.raises(Exception):
+        B.get_schedule()
+    B.close()
+
+
+def test_multi_mesh_schedule_converges():
+    from paper_1705_09282_amd.dfmg import MultiSolver
+    mix = [((2, 16, 3, 1), 1.0, 1.0, 0.0), ((2, 32, 4, 2), 1.0, 1e2, 4.0), ((2, 16, 3, 1), 1.0, 1e-2, 2.0),
+           ((2, 32, 4, 2), 1.0, 1.0, 0.0)]
+    for precision in (0, 1):
+        print(f"\n[case] multi precision={precision}", flush=True)
+        M = MultiSolver([m for m, *_ in mix], [x[1] for x in mix], [x[2] for x in mix], [x[3] for x in mix],
+                        precision=precision).bind()
+        F = torch.tensor(M.manufactured_rhs(), device="cuda")
+        U = torch.zeros_like(F)
+        plain = [x["cycles"] for x in M.solve(F, U, tol=1e-8)]
+        M.set_chebyshev(ALPHA, 30)
+        U.zero_()
+        st = M.solve(F, U, tol=1e-8)
+        res, div = M.residual_norm(F, U), M.div_norm(U)
+        print(f"[multi] cycles {[x['cycles'] for x in st]} (level dampings {plain})")
+        for i in range(len(mix)):
+            assert st[i]["converged"] and (mix[i][3] != 0.0 or st[i]["cycles"] <= plain[i])
+            assert res[i] <= 1e-8 * st[i]["fnorm"] * 1.0001
+            assert div[i] < 1e-10
+        M.close()
+
+
+def test_per_problem_alpha_matches_oracle():
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    d, N, k, L = 2, 32, 2, 4
+    B = BatchSolver(d, N, L, k, [1.0, 0.5], [1.0, 1e3]).bind()
+    B.set_smoothing([3, 2, 4], [3, 2, 4])
+    B.set_chebyshev(ALPHA, 30)
+    al = np.array([[6.0, 8.0, 12.0], [15.0, 20.0, 4.0]])
+    B.set_chebyshev_alpha(al)
+    assert np.array_equal(B.get_alpha(), al)
+    h, F = oracle(d, N, k, L, 1.0, 1.0, 0.0)
+    lm, sch = B.get_lmax(), B.get_schedule()
+    for p in range(2):
+        ref = chebyshev_schedule(h, lm[p], al[p], [3, 2, 4], [3, 2, 4])
+        for i in range(L - 1):
+            np.testing.assert_allclose(sch[p, i, 0, :ref[i][0].__len__()], ref[i][0], rtol=1e-14)
+            np.testing.assert_allclose(sch[p, i, 1, :ref[i][1].__len__()], ref[i][1], rtol=1e-14)
+    # one row for every problem
+    B.set_chebyshev_alpha([9.0, 9.0, 9.0])
+    assert np.all(B.get_alpha() == 9.0)
+    # problem 0's cycles against the oracle with its ratios
+    B.set_chebyshev_alpha(al)
+    U0 = divfree_start(h, 91)
+    n = B.n
+    Fb = np.concatenate([F, B.manufactured_rhs()[n:]])
+    Ub = dev(np.concatenate([U0, np.zeros(n)]))
+    B.vcycle(dev(Fb), Ub, 2)
+    Uo = vcycles(h, U0, F, 2, [3, 2, 4], [3, 2, 4], eta=chebyshev_schedule(h, lm[0], al[0], [3, 2, 4], [3, 2, 4]))
+    nv = h.finest.disc.n_v
+    assert rel_l2(host(Ub)[:nv], Uo[:nv]) < 1e-10
+    B.close()
+
+
+def test_learned_chebyshev_is_the_network_output():
+    """set_learned_chebyshev: per problem and level alpha = 1 / sigmoid of the
+    oracle network's first outputs (clamped to [1.5, 1000]), the batch's
+    steps the largest rounded count output, and the dampings the oracle's
+    Chebyshev dampings for them; None turns the schedule off."""
+    import math
+    import oracle.mlp as om
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    d, N, k, L = 2, 64, 2, 6
+    nus, sigmas, cs = [1.0, 0.1, 0.02], [1e-2, 30.0, 1e4], [0.0, 3.0, 1.5]
+    B = BatchSolver(d, N, L, k, nus, sigmas, cs).bind()
+    rng = np.random.default_rng(7)
+    W = np.asarray(om.init(3) + rng.normal(0.0, 0.1, om.NPARAM), dtype=np.float32)
+    B.set_learned_chebyshev(W, None)
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
+    X = np.array([om.features(nu, sg, abs(c) / math.sqrt(2.0), N, k) for nu, sg, c in zip(nus, sigmas, cs)])
+    Z = om.forward(W.astype(np.float64), f32(X))
+    al = B.get_alpha()
+    for p in range(3):
+        ref = [min(1e3, max(1.5, 1.0 + math.exp(-Z[p, min(i, om.NETA - 1)]))) for i in range(L - 1)]
+        np.testing.assert_allclose(al[p], ref, rtol=1e-4)
+    steps = om.steps(Z[:, om.NETA:]).max(axis=0)
+    ref = [int(steps[min(i, om.NETA - 1)]) for i in range(L - 1)]
+    assert B.get_smoothing() == (ref, ref)
+    h, _ = oracle(d, N, k, L, 1.0, 1.0, 0.0)
+    lm, sch = B.get_lmax(), B.get_schedule()
+    for p in range(3):
+        o = chebyshev_schedule(h, lm[p], al[p], ref, ref)
+        for i in range(L - 1):
+            np.testing.assert_allclose(sch[p, i, 0, :ref[i]], o[i][0], rtol=1e-14)
+    B.set_learned_chebyshev(None)
+    with pytest.raises(Exception):
+        B.get_schedule()
+    assert B.get_smoothing() == ([2] * (L - 1), [2] * (L - 1))
+    B.close()
+
+
+HELD_OUT = [(2, 128, 6, 2, 0.3, 10.0, 0.25), (2, 128, 6, 1, 0.03, 1e3, 0.0), (2, 128, 6, 2, 1.0, 0.1, 0.75),
+            (2, 256, 6, 1, 0.3, 3e2, 0.5), (2, 256, 6, 2, 0.03, 3.0, 0.25)]
+
+
+def test_learned_chebyshev_beats_fixed_on_held_out_problems():
+    """The shipped schedule network against the fixed damping with V(2,2),
+    FP32 refinement to relative residual 1e-8, on parameters outside the
+    training grid: the total solve time (best of three per problem) drops,
+    no problem takes more than 1.5x (a fallback costs two cycles), and both
+    solutions stay divergence-free."""
+    import math
+    import os
+    import time
+    from paper_1705_09282_amd import learned
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    if not os.path.exists(learned.CHEB_WEIGHTS):
+        pytest.skip("no trained schedule model")
+    model = learned.load(learned.CHEB_WEIGHTS)
+    tot = {"fixed": 0.0, "learned": 0.0}
+    for (d, N, L, k, nu, sigma, peh) in HELD_OUT:
+        c = math.sqrt(2.0) * nu * N * peh
+        print(f"\n[case] N={N} L={L} k={k} nu={nu} sigma={sigma} Pe_h={peh}", flush=True)
+        B = BatchSolver(d, N, L, k, [nu], [sigma], [c], precision=1, max_cycles=100).bind()
+        F = torch.tensor(B.manufactured_rhs(), device="cuda")
+        t = {}
+        for mode in ("fixed", "learned"):
+            if mode == "learned":
+                learned.apply(B, model)
+            U = torch.zeros_like(F)
+            best = float("inf")
+            for _ in range(3):
+                U.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = B.solve(F, U, tol=1e-8)[0]
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            div = B.div_norm(U)[0]
+            t[mode] = best
+            tot[mode] += best
+            extra = f"alpha {np.round(B.get_alpha()[0], 1).tolist()}" if mode == "learned" else ""
+            print(f"[{mode}] steps {B.get_smoothing()[0]} {extra} cycles {st['cycles']} fallback {st['fallback']} "
+                  f"{1e3 * best:.2f} ms div {div:.1e}", flush=True)
+            assert st["converged"] and div < 1e-10
+        assert t["learned"] <= 1.5 * t["fixed"]
+        B.close()
+    print(f"[total] fixed {1e3 * tot['fixed']:.2f} ms learned {1e3 * tot['learned']:.2f} ms")
+    assert tot["learned"] < tot["fixed"]

@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of MB megabytes (reference for HBM byte counters)")
+    ap.add_argument("--tuning-cache", default=None, metavar="JSON",
+                    help="reuse the kernel variants stored in JSON by an earlier run (a profiled run then times "
+                         "the variants the unprofiled run chose); stores them when absent")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the timed path's batch, one solve, then the dominant kernel's timing loop and "
                          "200 finest-grid smoothing steps (for profiler and counter runs)")
@@ -125,9 +128,12 @@ def main():
     def make_batch(precision, use_learned=None):
         b = BatchSolver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], [cfg["nu"]] * len(sigmas), sigmas,
                         precision=precision).bind(dev)
-        tuning = b.autotune(reps=20)
+        tuning = b.autotune(reps=20, cache=args.tuning_cache,
+                            key=f"{cfg['N']}-{cfg['L']}-{precision}-{use_learned or 'fixed'}")
         if use_learned:
             learned.apply(b, models[use_learned])
+        print(f"[bench] batch ready: precision {precision}, {use_learned or 'fixed damping'}", file=sys.stderr,
+              flush=True)
         F = torch.tensor(b.manufactured_rhs(), device=dev)
         U = torch.zeros_like(F)
         return b, F, U, tuning

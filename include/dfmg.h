@@ -225,8 +225,12 @@ int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
  * events on the library stream) and keep the fastest; ms_out (nullable,
  * 2 * n_levels entries) receives the best residual and smoother times.
  * Then times whole V-cycles for every choice of t (levels of at most 16384
- * DOFs) and keeps the fastest.  Requires dfmg_bind.  Leaves the solver
- * state unchanged. */
+ * DOFs) and keeps the fastest.  Last, in context: whole V-cycles captured
+ * as one graph and replayed (as the solves run them) for every lanes-per-row
+ * variant and smoother form of one level at a time, finest level first, the
+ * others as chosen; a change is kept when the cycle gets faster by more than
+ * 0.5% (best of three rounds of reps replays).  Requires dfmg_bind.  Leaves
+ * the solver state unchanged. */
 int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
 
 /* ---- Learned per-level smoothing parameters ----

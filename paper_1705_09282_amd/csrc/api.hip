@@ -1718,6 +1718,63 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
             }
         }
         c->small_top = best_top;
+        // in context: a kernel timed alone (back-to-back launches of itself)
+        // can rank the variants otherwise than inside the cycle, where every
+        // launch waits for the previous kernel's results.  Whole V-cycles,
+        // captured and replayed as the solves run them, for every lanes-per-row
+        // variant and smoother form of one level at a time (finest first, the
+        // other levels as chosen); a variant replaces the choice when its
+        // cycle is faster by more than 0.5% (best of three rounds of reps).
+        auto cycle_ms = [&] {
+            hipGraph_t g;
+            hipGraphExec_t x;
+            HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+            if (c->mixed()) cycle_body<float>(c, false, true);
+            else cycle_body<double>(c, false, false);
+            HIPCHK(hipStreamEndCapture(c->s, &g));
+            HIPCHK(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(g));
+            HIPCHK(hipGraphLaunch(x, c->s));  // warm
+            double best = 1e30;
+            for (int round = 0; round < 3; ++round) {
+                HIPCHK(hipEventRecord(e0, c->s));
+                for (int i = 0; i < reps; ++i) HIPCHK(hipGraphLaunch(x, c->s));
+                HIPCHK(hipEventRecord(e1, c->s));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                best = std::min(best, (double)t / reps);
+            }
+            HIPCHK(hipGraphExecDestroy(x));
+            return best;
+        };
+        double cur = cycle_ms();
+        for (int l = L - 1; l > c->small_top && l >= 1; --l) {
+            int bl = c->lpr[l];
+            for (int lp : {1, 2, 4}) {
+                if (lp == bl) continue;
+                c->lpr[l] = lp;
+                const double t = cycle_ms();
+                if (t < 0.995 * cur) {
+                    cur = t;
+                    bl = lp;
+                }
+                c->lpr[l] = bl;
+            }
+            // the FP32 cycle runs forms 3 and 4 only (the others as 4)
+            int bs = c->smoother[l];
+            const std::vector<int> forms = c->mixed() ? std::vector<int>{3, 4} : std::vector<int>{1, 2, 3, 4};
+            for (int sm : forms) {
+                if (sm == bs || (c->mixed() && sm == 4 && bs != 3)) continue;
+                c->smoother[l] = sm;
+                const double t = cycle_ms();
+                if (t < 0.995 * cur) {
+                    cur = t;
+                    bs = sm;
+                }
+                c->smoother[l] = bs;
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         drop_graph(c);

@@ -20,10 +20,12 @@ c_dblp = ctypes.POINTER(ctypes.c_double)
 
 MAX_HISTORY = 512
 MAX_STEPS = 16   # smoothing steps per phase and level (schedule entries per phase)
-# Chebyshev schedule defaults: smoothing interval [b / 10, b] and 30 power
-# iterations for b (2D k = 2 Stokes: alpha from 8 to 15 gives the same cycle
-# counts at 32^2 and 64^2)
+# Chebyshev schedule defaults: smoothing interval [b / alpha, b] and 30 power
+# iterations for b.  alpha per dimension: 2D k = 2 Stokes gives the same
+# cycle counts for alpha from 8 to 15 (32^2, 64^2); 3D k = 1 Stokes on 32^3
+# (b about 24.5) is fastest near 60
 CHEB_ALPHA = 10.0
+CHEB_ALPHA_3D = 60.0
 CHEB_ITERS = 30
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EDIVERGED", -6: "ESTATE"}
 
@@ -461,10 +463,13 @@ class Solver:
         _check(lib().dfmg_get_eta(self._ctx, _ptr(out, ctypes.c_double)))
         return out.reshape(self.nprob, self.n_levels - 1)
 
-    def set_chebyshev(self, alpha=CHEB_ALPHA, iters=CHEB_ITERS):
+    def set_chebyshev(self, alpha=None, iters=CHEB_ITERS):
         """Chebyshev damping schedule on [b / alpha, b] per problem and level
         (b from a power-iteration estimate of the largest eigenvalue of the
-        undamped smoother's operator); alpha 0 turns it off."""
+        undamped smoother's operator); alpha None: the default of the
+        dimension; 0 turns it off."""
+        if alpha is None:
+            alpha = CHEB_ALPHA_3D if self.dim == 3 else CHEB_ALPHA
         _check(lib().dfmg_set_chebyshev(self._ctx, float(alpha), int(iters)))
 
     def set_chebyshev_alpha(self, alphas):
@@ -607,6 +612,7 @@ class MultiSolver:
                                             None if r is None else _ptr(r, ctypes.c_double)))
 
     def set_chebyshev(self, alpha=CHEB_ALPHA, iters=CHEB_ITERS):
+        """As Solver.set_chebyshev (one ratio for every group)."""
         _check(lib().dfmg_multi_set_chebyshev(self._ctx, float(alpha), int(iters)))
 
     def set_learned_chebyshev(self, W, rho_plain=None, iters=CHEB_ITERS):

@@ -59,27 +59,85 @@ def measured_traffic(n_elem, levels):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(tol):
-    """The oracle as it stands, on one of the four problems (sigma = 1), one
-    full solve to tol from U = 0; setup excluded as for the GPU."""
-    from threadpoolctl import threadpool_limits
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count()
+    return model, ncores
+
+
+def cpu_baseline(tol, U_gpu, runs=5, warmup=1):
+    """The oracle as it stands on one of the four problems (sigma = 1): full
+    solves to tol from U = 0, setup excluded as for the GPU; `warmup` untimed
+    solves, then the median of `runs`, once with the BLAS/OpenMP pools at one
+    thread and once at every core this process may use.  Afterwards the
+    oracle continues its solve to 1e-12, and the GPU's sigma = 1 velocity is
+    compared with it."""
+    import statistics
+    from threadpoolctl import threadpool_limits, threadpool_info
     import numpy as np
     import workloads
     from oracle.multigrid import Hierarchy, solve
     from oracle.assemble import load_vector
     from oracle.manufactured import forcing
+    model, ncores = host_cpu()
     cfg = workloads.stokes2d(1.0)
-    with threadpool_limits(1):
-        h = Hierarchy(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"])
-        F = load_vector(h.finest.disc, forcing(cfg["d"], cfg["nu"], cfg["sigma"]))
-        t0 = time.perf_counter()
-        U, hist = solve(h, F, tol=tol)
-        dt = time.perf_counter() - t0
+    h = Hierarchy(cfg["d"], cfg["N"], cfg["k"], cfg["L"], cfg["nu"], cfg["sigma"])
+    F = load_vector(h.finest.disc, forcing(cfg["d"], cfg["nu"], cfg["sigma"]))
     dofs = h.finest.disc.dofs()
-    return {"value": dofs / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": "sigma=1 problem only (1 of 4): one full FP64 oracle solve to 1e-8 from U=0, "
-                      "256x256, k=2, 6 grids, V(2,2), setup excluded, BLAS limited to 1 thread",
-            "seconds": dt, "cycles": len(hist) - 1}
+    legs = {}
+    for name, limit in (("one_core", 1), ("all_cores", ncores)):
+        with threadpool_limits(limit):
+            threads = max([1] + [p.get("num_threads", 1) for p in threadpool_info()])
+            times = []
+            for i in range(warmup + runs):
+                t0 = time.perf_counter()
+                U, hist = solve(h, F, tol=tol)
+                if i >= warmup:
+                    times.append(time.perf_counter() - t0)
+        med = statistics.median(times)
+        legs[name] = {"value": dofs / med, "seconds_median": med, "seconds": times, "threads": threads,
+                      "cycles": len(hist) - 1}
+    Uo, _ = solve(h, F, tol=1e-12, U0=U, max_cycles=400)
+    nv = h.finest.disc.n_v
+    err = float(np.linalg.norm(U_gpu[:nv] - Uo[:nv]) / np.linalg.norm(Uo[:nv]))
+    best = legs["all_cores"]
+    return {"value": best["value"], "unit": "DOF/s", "cores": best["threads"], "kind": "oracle",
+            "sample": f"sigma=1 problem only (1 of 4): FP64 oracle solves to {tol:g} from U=0, 256x256, k=2, "
+                      f"6 grids, V(2,2), setup excluded; median of {runs} after {warmup} warm-up, BLAS/OpenMP "
+                      f"pools at every core ({ncores}) and at one",
+            "one_core": legs["one_core"], "all_cores": legs["all_cores"],
+            "cpu_model": model, "nproc": ncores}, err
+
+
+def roofline_hbm(dev, reps=50):
+    """The FP32 residual on an operator that cannot stay in the 256 MB
+    Infinity Cache: one problem of the same workload on 1024^2 elements
+    (8 grids; its FP32 values take 0.8 GB), timed with HIP events on the
+    library stream over `reps` launches."""
+    from paper_1705_09282_amd.dfmg import Solver
+    t0 = time.perf_counter()
+    s = Solver(2, 1024, 8, 2, precision=1).bind(dev)
+    setup = time.perf_counter() - t0
+    ms = s.time_kernel(1, 7, reps=reps)
+    z = s.sizes()
+    alg = 4 * z["nnz"] + 3 * 4 * z["n"]
+    achieved = alg / (ms * 1e-3) / 1e9
+    s.close()
+    return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (FP32 residual, one problem of 1024x1024 "
+                                      "elements, k=2)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_ms": ms, "setup_s": setup}
 
 
 def main():
@@ -99,6 +157,9 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the timed path's batch, one solve, then the dominant kernel's timing loop and "
                          "200 finest-grid smoothing steps (for profiler and counter runs)")
+    ap.add_argument("--roofline-hbm-only", action="store_true",
+                    help="only the HBM-resident residual leg (1024^2, one problem)")
+    ap.add_argument("--no-hbm-leg", action="store_true", help="skip the HBM-resident residual leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -131,7 +192,11 @@ def main():
         tuning = b.autotune(reps=20, cache=args.tuning_cache,
                             key=f"{cfg['N']}-{cfg['L']}-{precision}-{use_learned or 'fixed'}")
         if use_learned:
+            t0 = time.perf_counter()
             learned.apply(b, models[use_learned])
+            # the schedule's eigenvalue estimates (30 power iterations per
+            # level and problem, host norms) are made here
+            tuning["learned_setup_s"] = time.perf_counter() - t0
         print(f"[bench] batch ready: precision {precision}, {use_learned or 'fixed damping'}", file=sys.stderr,
               flush=True)
         F = torch.tensor(b.manufactured_rhs(), device=dev)
@@ -166,6 +231,10 @@ def main():
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(args.n_elem, args.levels), "alg_bytes_per_launch": alg,
                 "avg_launch_ms": ms}
+
+    if args.roofline_hbm_only:
+        print(json.dumps({"roofline_hbm": roofline_hbm(dev, reps=200)}), flush=True)
+        return
 
     if args.roofline_only:
         # the residual's roofline, then 200 finest-grid smoothing steps of the
@@ -271,17 +340,28 @@ def main():
                                        "cycles_per_sigma": [st["cycles"] for st in statsc64]},
             "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
-            "tuning": {"lpr": tuning["lpr"], "smoother": tuning["smoother"]},
+            "lmax_estimate_s": tuning.get("learned_setup_s"),
+            "tuning": {"lpr": tuning["lpr"],
+                       # the FP32 cycle of the refinement runs smoother form 3
+                       # where tuned so and form 4 otherwise (level 0: exact)
+                       "smoother_fp32_cycle": [None] + [3 if f == 3 else 4 for f in tuning["smoother"][1:]],
+                       "smoother_fp64_residual_path": tuning["smoother"]},
             "finest_grid_kernels_ms": {"fp64_residual": ms64, "fp64_residual_GBps": gbs64,
                                        "fp64_smoothing_step": sm64, "fp32_smoothing_step": sm32},
         },
         "roofline": rl,
     }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.tol)
+    U32_sigma1 = U32[n:2 * n].cpu().numpy()
     for s in (b64, bfx, blc, bc64, b32):
         s.close()
+    del b64, bfx, blc, bc64, b32, F64, U64, Ffx, Ufx, Flc, Ulc, Fc64, Uc64, F32, U32
+    torch.cuda.empty_cache()
+    if not args.no_hbm_leg:
+        print("[bench] HBM-resident residual leg (1024^2)", file=sys.stderr, flush=True)
+        line["roofline_hbm"] = roofline_hbm(dev)
+    if not args.no_cpu_baseline and args.n_elem == 256 and args.levels == 6:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"], line["config"]["vel_rel_err_vs_oracle_sigma1"] = cpu_baseline(args.tol, U32_sigma1)
     print(json.dumps(line), flush=True)
 
 

@@ -291,8 +291,10 @@ int dfmg_get_eta(dfmg_ctx *ctx, double *eta_host);
  * dfmg_set_learned).  The fallback of dfmg_set_learned switches a problem to
  * its fixed damping in every step; the next solve restores the schedule.
  * The single-workgroup coarse cycle is not used while a schedule is on.
- * alpha in (1, 1e6] turns it on, alpha 0 off (iters unused then); iters in
- * [1, 1000].  Requires dfmg_bind.  Errors: EINVAL, ESTATE, EHIP. */
+ * alpha in (1, 1e6] turns it on, alpha < 0 turns it on with the default
+ * ratio of the dimension (10 in 2D, 60 in 3D), alpha 0 off (iters unused
+ * then); iters in [1, 1000].  Requires dfmg_bind.  Errors: EINVAL, ESTATE,
+ * EHIP. */
 int dfmg_set_chebyshev(dfmg_ctx *ctx, double alpha, int iters);
 /* Interval ratios alpha of the schedule in use, per smoothed level (finest
  * first): n = n_levels - 1 values for every problem or nprob * (n_levels - 1)
@@ -367,7 +369,8 @@ int dfmg_multi_autotune(dfmg_multi *m, int reps);
 /* dfmg_set_learned for every problem; rho_plain_host has nprob entries in
  * caller order (nullable). */
 int dfmg_multi_set_learned(dfmg_multi *m, const float *W_host, const double *rho_plain_host);
-/* dfmg_set_chebyshev for every group. */
+/* dfmg_set_chebyshev for every group (alpha < 0: each group's default ratio
+ * for its dimension). */
 int dfmg_multi_set_chebyshev(dfmg_multi *m, double alpha, int iters);
 /* dfmg_set_learned_chebyshev for every group; rho_plain_host has nprob
  * entries in caller order (nullable). */

@@ -14,7 +14,30 @@ quadrature for every integral, scipy sparse products for the Galerkin triple
 product, brute-force support containment for the subdomains, and numpy batched
 inverses for the local saddle-point problems.
 
-Parity status: every function is pinned by a ``-m "not gpu"`` test against a
-fact the paper or the mathematics fixes (see ``tests/test_oracle_*.py``); none
-is "parity unpinned".
+Pins (``-m "not gpu"`` tests in ``tests/test_oracle_*.py``), one or more per
+module, each against a fact the paper or the mathematics fixes:
+
+* ``bspline``: partition of unity, derivatives against finite differences,
+  cardinal values.
+* ``spaces``: the DOF columns printed in the paper's Tables 1, 2 and 4; Euler
+  characteristics of the discrete complexes.
+* ``assemble``: polynomial-exact integrals; B 1 = 0; O(h^{k+1}) velocity error
+  of the solution.
+* ``refine``: two-scale rows of the refinement matrix; Galerkin identity;
+  refinement commutes with the curl (velocity and potential prolongation).
+* ``patches``: interior subdomain dimensions of the paper's subsection on
+  Schwarz smoothers; local exactness; colour disjointness.
+* ``complex``: curl of a polynomial potential against its exact coefficients
+  (polar forms); divergence-free images.
+* ``diagnostics``: ||div u|| and ||u|| of polynomial fields against closed
+  forms; the direct solve against the V-cycle limit.
+* ``multigrid``: V-cycles against the direct solve; the divergence-free
+  invariant; h-independent factors; the additive damping reading against the
+  paper's protocol and its Table 2 (eta = 0.5 diverges, eta0 is the best
+  stable sweep value); multiplicative Schwarz against the product formula of
+  equation MSM, the sequential sweep, and Table 1; Chebyshev dampings against
+  numpy's Chebyshev series.
+* ``mlp``: gradients against finite differences; Adam on a quadratic.
+
+None of these functions is "parity unpinned".
 """

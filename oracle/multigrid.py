@@ -8,6 +8,15 @@ S^{-1} = eta sum_i E_i^T K_i^{-1} E_i (equation ASM), and the solution
 protocol of the numerical-results section (repeat V-cycles; additional cycles
 are additional calls).
 
+The multiplicative Schwarz smoother (equation MSM) solves the same local
+problems one subdomain after the other, each on the residual left by the
+previous ones, with no damping (the update formula of the subsection on
+preservation of the divergence-free constraint).  The paper does not fix the
+order of the subdomains; the oracle visits them colour by colour in the
+coupling-free colouring of ``coupling_free_colours`` (inside a colour in
+subdomain order), and ``smooth_multiplicative`` is the plain sequential sweep
+in that order.
+
 The coarsest-level solve uses the global zero-mean pressure multiplier of the
 paper's footnote: the bordered system [[K_0, e], [e^T, 0]] with e = [0; w_0].
 """
@@ -85,11 +94,90 @@ def smooth(level, U, F, eta):
     return U + eta * schwarz_correction(level, r)
 
 
-def mgv(h, l, U, F, nu1, nu2, eta):
+def coupling_free_colours(disc, patches):
+    """Colour of every subdomain such that two subdomains of one colour share
+    no DOF and no matrix entry couples a DOF of one with a DOF of the other.
+    A subdomain is the support of a potential basis function, a box of at
+    most k+2 elements per direction, and every DOF of the subdomain has its
+    support inside that box; two subdomains of one orientation whose
+    potential indices differ by k+2 or more in some direction therefore have
+    disjoint boxes in that direction, and the basis functions inside them do
+    not overlap.  Colour = (o, a mod (k+2), b mod (k+2)[, c mod (k+2)]) in
+    lexicographic order: 9 / 16 colours in 2D (k = 1 / 2), 3 (k+2)^3 in 3D."""
+    k, d = disc.k, disc.d
+    pot = patches["pot"]
+    col = pot[:, 0].copy()
+    for j in range(d):
+        col = col * (k + 2) + pot[:, 1 + j] % (k + 2)
+    return col
+
+
+def sweep_order(level):
+    """Subdomain visiting order of the multiplicative smoother: colour-major
+    (coupling-free colours), subdomain order inside a colour."""
+    col = coupling_free_colours(level.disc, level.patches)
+    return np.argsort(col, kind="stable")
+
+
+def local_inverse_table(level):
+    """Subdomain id -> (index set, M_i)."""
+    out = {}
+    for ids, I, M in level.groups:
+        for m, i in enumerate(ids):
+            out[int(i)] = (I[m], M[m])
+    return out
+
+
+def smooth_multiplicative(level, U, F):
+    """One multiplicative Schwarz step (equation MSM), plainly sequential:
+    for every subdomain i in ``sweep_order``, r_i = E_i (F - K U) with the
+    current U, then U <- U + E_i^T M_i r_i (no damping)."""
+    K = level.K.tocsr()
+    tab = local_inverse_table(level)
+    U = U.copy()
+    for i in sweep_order(level):
+        I, M = tab[int(i)]
+        r = F[I] - K[I, :] @ U
+        U[I] += M @ r
+    return U
+
+
+def smooth_multiplicative_colours(level, U, F):
+    """The same step with the subdomains of one coupling-free colour solved
+    together: one residual per colour, then every subdomain of the colour
+    corrects its own DOFs.  Equal to ``smooth_multiplicative`` up to
+    rounding because the subdomains of a colour neither share DOFs nor couple
+    through K, so no update inside a colour changes another's residual."""
+    col = coupling_free_colours(level.disc, level.patches)
+    tab = local_inverse_table(level)
+    for c in np.unique(col):
+        r = F - level.K @ U
+        dU = np.zeros_like(U)
+        for i in np.nonzero(col == c)[0]:
+            I, M = tab[int(i)]
+            dU[I] += M @ r[I]
+        U = U + dU
+    return U
+
+
+def _smooth_step(lv, U, F, e, smoother):
+    if smoother == "additive":
+        return smooth(lv, U, F, e)
+    if smoother == "multiplicative":
+        return smooth_multiplicative_colours(lv, U, F)
+    if smoother == "multiplicative-sequential":
+        return smooth_multiplicative(lv, U, F)
+    raise ValueError(smoother)
+
+
+def mgv(h, l, U, F, nu1, nu2, eta, smoother="additive"):
     """Algorithm 1, MGV(l, U, F); eta[l] is the damping on level l (a number,
     or a pair (pre, post) of per-step damping sequences), nu1 and nu2 the
-    smoothing steps (a number, or one per level indexed by level).  Returns
-    the updated U (the paper updates U in place)."""
+    smoothing steps (a number, or one per level indexed by level).  smoother:
+    "additive" (equation ASM with eta), "multiplicative" (equation MSM, eta
+    unused; coupling-free colours at a time) or "multiplicative-sequential"
+    (the same, one subdomain at a time).  Returns the updated U (the paper
+    updates U in place)."""
     lv = h.levels[l]
     if l == 0:
         return lv.coarse_inv @ F
@@ -99,14 +187,14 @@ def mgv(h, l, U, F, nu1, nu2, eta):
     pre = list(e[0]) if isinstance(e, tuple) else [e] * n1
     post = list(e[1]) if isinstance(e, tuple) else [e] * n2
     for j in range(n1):
-        U = smooth(lv, U, F, pre[j])
+        U = _smooth_step(lv, U, F, pre[j], smoother)
     P = h.levels[l - 1].P
     G = P.T @ (F - lv.K @ U)
     dU = np.zeros(h.levels[l - 1].disc.n)
-    dU = mgv(h, l - 1, dU, G, nu1, nu2, eta)
+    dU = mgv(h, l - 1, dU, G, nu1, nu2, eta, smoother)
     U = U + P @ dU
     for j in range(n2):
-        U = smooth(lv, U, F, post[j])
+        U = _smooth_step(lv, U, F, post[j], smoother)
     return U
 
 
@@ -116,8 +204,14 @@ def mgv(h, l, U, F, nu1, nu2, eta):
 # local pressure corrections of all subdomains holding a pressure function are
 # summed (4 subdomains in the 2D interior, 12 in 3D, up to 9 / 24 / 81 near the
 # boundary): about 4.94 (2D, k=1), 9.01 (2D, k=2), 24.1 (3D, k=1) and 80.0
-# (3D, k=2).  The paper's eta = 0.5 is then unstable, so the fixed damping is
-# taken below 2 / lambda_max, at the best value of a V(2,2) sweep.
+# (3D, k=2).  The paper's eta = 0.5 is then unstable (eta lambda_max > 2), so
+# the fixed damping is the value of the sweep SWEEP_ETA with the fewest V(2,2)
+# cycles to 1e-8 among those with eta lambda_max <= ETA_MARGIN, a margin below
+# the stability limit 2 that covers the slow growth of lambda_max with the
+# grid (24.1 on 8^3, 24.5 on 32^3 for 3D k = 1).
+SWEEP_ETA = {(2, 1): (0.2, 0.25, 0.3, 0.35, 0.4), (2, 2): (0.1, 0.15, 0.2, 0.25),
+             (3, 1): (0.04, 0.05, 0.06, 0.07, 0.08), (3, 2): (0.01, 0.015, 0.02, 0.025)}
+ETA_MARGIN = 1.85
 DEFAULT_ETA = {(2, 1): 0.35, (2, 2): 0.2, (3, 1): 0.07, (3, 2): 0.02}
 
 
@@ -199,11 +293,11 @@ def steps_levels(h, nu):
     return out
 
 
-def vcycles(h, U, F, m, nu1=2, nu2=2, eta=None):
+def vcycles(h, U, F, m, nu1=2, nu2=2, eta=None, smoother="additive"):
     et = eta_levels(h, eta)
     n1, n2 = steps_levels(h, nu1), steps_levels(h, nu2)
     for _ in range(m):
-        U = mgv(h, h.L - 1, U, F, n1, n2, et)
+        U = mgv(h, h.L - 1, U, F, n1, n2, et, smoother)
     return U
 
 
@@ -221,7 +315,7 @@ def normalize_pressure(h, U):
     return U
 
 
-def solve(h, F, tol=1e-8, U0=None, nu1=2, nu2=2, eta=None, max_cycles=200):
+def solve(h, F, tol=1e-8, U0=None, nu1=2, nu2=2, eta=None, max_cycles=200, smoother="additive"):
     """Repeat V-cycles until ||F - K U||_2 <= tol ||F||_2 (starting residual
     included), then normalize the pressure.  Returns (U, history)."""
     U = np.zeros_like(F) if U0 is None else U0.copy()
@@ -231,7 +325,7 @@ def solve(h, F, tol=1e-8, U0=None, nu1=2, nu2=2, eta=None, max_cycles=200):
     hist = [residual_norm(h, U, F)]
     cycles = 0
     while hist[-1] > tol * fn and cycles < max_cycles:
-        U = mgv(h, h.L - 1, U, F, n1, n2, et)
+        U = mgv(h, h.L - 1, U, F, n1, n2, et, smoother)
         cycles += 1
         hist.append(residual_norm(h, U, F))
     return normalize_pressure(h, U), np.array(hist)

@@ -32,7 +32,20 @@ def _contain_1d(disc, pot_degree, pot_lo, pot_hi, fun_degree, fun_lo, fun_hi):
     return (f_lo[None, :] >= p_lo[:, None]) & (f_hi[None, :] <= p_hi[:, None])
 
 
+_PATCH_CACHE = {}
+
+
 def build_patches(disc):
+    """Subdomain DOF lists of a level, computed once per (d, N, k): they depend
+    on the mesh only.  The returned arrays are shared and must not be
+    modified.  See ``find_patches``."""
+    key = (disc.d, disc.N, disc.k)
+    if key not in _PATCH_CACHE:
+        _PATCH_CACHE[key] = find_patches(disc)
+    return _PATCH_CACHE[key]
+
+
+def find_patches(disc):
     """Subdomain DOF lists for one level.
 
     Returns dict with

@@ -826,6 +826,10 @@ double chebyshev_damping(double b, double alpha, int nu, int j, bool reverse) {
 // the upper end of the Chebyshev interval, relative to the estimate of the
 // largest eigenvalue (power iteration approaches it from below)
 constexpr double kLmaxSafety = 1.05;
+// default interval ratios b / a of the schedule: 2D k = 2 Stokes gives the
+// same cycle counts for ratios 8 .. 15 (32^2, 64^2 sweeps); 3D k = 1 Stokes
+// on 32^3 is fastest near 60
+constexpr double kChebAlpha2d = 10.0, kChebAlpha3d = 60.0;
 
 // Per-step dampings of every problem and level from lmax, alpha and the
 // current step counts; uploaded (stream-ordered) to sched.  Entries past
@@ -1869,6 +1873,7 @@ int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
 
 int dfmg_set_chebyshev(dfmg_ctx *c, double alpha, int iters) {
     if (!c) return fail(DFMG_EINVAL, "null argument");
+    if (alpha < 0.0) alpha = c->S().pb.d == 3 ? kChebAlpha3d : kChebAlpha2d;
     if (!(alpha == 0.0 || (alpha > 1.0 && alpha <= 1e6))) return fail(DFMG_EINVAL, "alpha must be 0 or in (1, 1e6]");
     if (alpha > 0.0 && (iters < 1 || iters > 1000)) return fail(DFMG_EINVAL, "iters must lie in [1, 1000]");
     return guarded([&] {

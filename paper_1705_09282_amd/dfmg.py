@@ -21,11 +21,8 @@ c_dblp = ctypes.POINTER(ctypes.c_double)
 MAX_HISTORY = 512
 MAX_STEPS = 16   # smoothing steps per phase and level (schedule entries per phase)
 # Chebyshev schedule defaults: smoothing interval [b / alpha, b] and 30 power
-# iterations for b.  alpha per dimension: 2D k = 2 Stokes gives the same
-# cycle counts for alpha from 8 to 15 (32^2, 64^2); 3D k = 1 Stokes on 32^3
-# (b about 24.5) is fastest near 60
-CHEB_ALPHA = 10.0
-CHEB_ALPHA_3D = 60.0
+# iterations for b.  alpha None asks the library for the ratio of the
+# problem's dimension (10 in 2D, 60 in 3D).
 CHEB_ITERS = 30
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EDIVERGED", -6: "ESTATE"}
 
@@ -468,9 +465,7 @@ class Solver:
         (b from a power-iteration estimate of the largest eigenvalue of the
         undamped smoother's operator); alpha None: the default of the
         dimension; 0 turns it off."""
-        if alpha is None:
-            alpha = CHEB_ALPHA_3D if self.dim == 3 else CHEB_ALPHA
-        _check(lib().dfmg_set_chebyshev(self._ctx, float(alpha), int(iters)))
+        _check(lib().dfmg_set_chebyshev(self._ctx, -1.0 if alpha is None else float(alpha), int(iters)))
 
     def set_chebyshev_alpha(self, alphas):
         """Interval ratios per smoothed level (finest first), one row for all
@@ -611,9 +606,10 @@ class MultiSolver:
         _check(lib().dfmg_multi_set_learned(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                             None if r is None else _ptr(r, ctypes.c_double)))
 
-    def set_chebyshev(self, alpha=CHEB_ALPHA, iters=CHEB_ITERS):
-        """As Solver.set_chebyshev (one ratio for every group)."""
-        _check(lib().dfmg_multi_set_chebyshev(self._ctx, float(alpha), int(iters)))
+    def set_chebyshev(self, alpha=None, iters=CHEB_ITERS):
+        """As Solver.set_chebyshev: one ratio for every group, or with alpha
+        None each group's default for its dimension."""
+        _check(lib().dfmg_multi_set_chebyshev(self._ctx, -1.0 if alpha is None else float(alpha), int(iters)))
 
     def set_learned_chebyshev(self, W, rho_plain=None, iters=CHEB_ITERS):
         if W is None:

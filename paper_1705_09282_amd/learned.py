@@ -384,12 +384,17 @@ def rho_plain_for(model, feats, neighbours=8):
 
 
 def problem_features(solver):
+    """Network inputs of every problem of a Solver, BatchSolver or
+    MultiSolver (whose problems have their own grids and degrees)."""
+    if hasattr(solver, "meshes"):
+        return np.array([features(nu, sg, c, m[1], m[3])
+                         for nu, sg, c, m in zip(solver.nus, solver.sigmas, solver.cs, solver.meshes)])
     return np.array([features(nu, sg, c, solver.n_elem, solver.k)
                      for nu, sg, c in zip(solver.nus, solver.sigmas, solver.cs)])
 
 
 def apply(solver, model=None, fallback=True):
-    """Switch a bound Solver/BatchSolver to the learned dampings of `model`
+    """Switch a bound Solver/BatchSolver/MultiSolver to the learned dampings of `model`
     (default: the shipped weights), with the fallback threshold of the
     nearest training point.  A model trained with --chebyshev sets the
     learned Chebyshev schedule instead."""

@@ -39,9 +39,9 @@ def check_matrix(solver, K):
 
 def test_stokes3d_full_size():
     """3D generalized Stokes, k=1, 32^3, 4 grids, the eight seeded sigmas as
-    one batch (FP64): each meets 1e-8 with the oracle's matrix, is
-    divergence-free, and needs at most 20% more cycles than on 16^3 (the
-    fixed 3D damping contracts by ~0.85 per cycle on both grids)."""
+    one batch (FP64): each meets 1e-8 with the oracle's matrix and is
+    divergence-free.  (The behaviour over grid sizes is checked on the
+    asymptotic factors of 8^3, 16^3 and 32^3 in test_gpu_fullparity.)"""
     from paper_1705_09282_amd.dfmg import BatchSolver
     sig = workloads.stokes3d_sigmas()
     cfg = workloads.stokes3d(sig[0])
@@ -66,14 +66,6 @@ def test_stokes3d_full_size():
     print(f"[3d] matrix rel err {merr:.1e} load rel err {ferr:.1e} oracle residual {res:.2e}", flush=True)
     assert merr < 1e-12 and ferr < 1e-12 and res < 1.05e-8
     S.close()
-    # h-independence: the same sigmas on 16^3 with one grid fewer
-    C = BatchSolver(3, 16, 3, 1, [1.0] * len(sig), list(sig)).bind()
-    Fc = torch.tensor(C.manufactured_rhs(), device="cuda")
-    Uc = torch.zeros_like(Fc)
-    cc = [s["cycles"] for s in C.solve(Fc, Uc, tol=1e-8)]
-    print(f"[3d] 16^3 cycles {cc}", flush=True)
-    assert max(cyc) <= 1.2 * max(cc)
-    C.close()
     B.close()
 
 

@@ -252,6 +252,19 @@ int dfmg_mlp_forward(int n, const float *W_dev, const float *X_dev, float *Z_dev
  * n * (DFMG_MLP_NPARAM + 1) floats.  Fixed summation order (deterministic). */
 int dfmg_mlp_grad(int n, const float *W_dev, const float *X_dev, const float *Y_dev, const float *M_dev,
                   float scale, float *work_dev, float *G_dev, float *loss_dev, void *stream);
+/* dfmg_mlp_grad without the work array, for callers that cannot allocate
+ * device memory (code under HIP graph capture, loops that forbid hipMalloc):
+ * the per-sample partials live in a static device array of the library
+ * (DFMG_MLP_SCRATCH_SAMPLES * (DFMG_MLP_NPARAM + 1) floats, 3.2 MB per GPU,
+ * held until the process ends), so n must lie in [1,
+ * DFMG_MLP_SCRATCH_SAMPLES] (EINVAL otherwise, nothing launched).  Same
+ * kernels and summation order as dfmg_mlp_grad, so the results are equal
+ * bit for bit.  Allocates nothing.  Every call on one GPU uses that GPU's
+ * one array: calls that overlap on a GPU (other streams, other threads)
+ * race and give wrong results; serialize them.  Errors: EINVAL, EHIP. */
+#define DFMG_MLP_SCRATCH_SAMPLES 512
+int dfmg_mlp_grad_noalloc(int n, const float *W_dev, const float *X_dev, const float *Y_dev, const float *M_dev,
+                          float scale, float *G_dev, float *loss_dev, void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, t >= 1). */
 int dfmg_mlp_adam(float *W_dev, float *m_dev, float *v_dev, const float *G_dev, int t, float lr, void *stream);
 /* Use the network W_host for the dampings of every problem of ctx (computed

@@ -1804,6 +1804,28 @@ int dfmg_mlp_grad(int n, const float *W, const float *X, const float *Y, const f
     });
 }
 
+static_assert(DFMG_MLP_SCRATCH_SAMPLES == MLP_SCRATCH_SAMPLES && DFMG_MLP_NPARAM == MLP_NPARAM,
+              "header and library agree on the network's sizes");
+
+int dfmg_mlp_grad_noalloc(int n, const float *W, const float *X, const float *Y, const float *Mk, float scale,
+                          float *G, float *loss, void *stream) {
+    if (!W || !X || !Y || !Mk || !G || !loss) return fail(DFMG_EINVAL, "invalid argument");
+    if (n < 1 || n > MLP_SCRATCH_SAMPLES)
+        return fail(DFMG_EINVAL, "n must lie in [1, " + std::to_string(MLP_SCRATCH_SAMPLES) +
+                                     "] (the static scratch holds that many samples)");
+    return guarded([&] {
+        hipStream_t st = (hipStream_t)stream;
+        int device = -1;
+        if (st) HIPCHK(hipStreamGetDevice(st, &device));
+        else HIPCHK(hipGetDevice(&device));
+        hipError_t e = hipSuccess;
+        float *scr = mlp_scratch(device, &e);
+        if (!scr) throw HipError(std::string("scratch address: ") + hipGetErrorString(e));
+        launch_mlp_grad_scratch(n, W, X, Y, Mk, scale, scr, G, loss, st);
+        HIPCHK(hipGetLastError());
+    });
+}
+
 int dfmg_mlp_adam(float *W, float *m, float *v, const float *G, int t, float lr, void *stream) {
     if (!W || !m || !v || !G || t < 1) return fail(DFMG_EINVAL, "invalid argument");
     return guarded([&] {

@@ -8,10 +8,18 @@
 #include "mlp.hpp"
 
 #include <cmath>
+#include <mutex>
 
 #include "device_util.hpp"
 
 namespace dfmg {
+
+// Scratch of the allocation-free gradient entry point: the per-sample
+// gradient rows (MLP_SCRATCH_SAMPLES x MLP_NPARAM floats) and the per-sample
+// losses (MLP_SCRATCH_SAMPLES floats), 3.2 MB per GPU for the life of the
+// process.  Host code never passes this name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress (mlp_scratch).
+static __device__ __align__(256) float scratch[(size_t)MLP_SCRATCH_SAMPLES * (MLP_NPARAM + 1)];
 
 namespace {
 
@@ -153,6 +161,39 @@ void launch_mlp_grad(int n, const float *W, const float *X, const float *Y, cons
                      float *work, float *lw, float *G, float *loss, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_mlp_sample_grad, dim3((n + 63) / 64), dim3(64), 0, s, n, W, X, Y, Mk, scale, work, lw);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, n, work, lw, G, loss);
+}
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (each GPU holds its own copy of the array).
+float *mlp_scratch(int device, hipError_t *err) {
+    constexpr int kMaxDevices = 64;
+    static float *ptr[kMaxDevices] = {};
+    static std::mutex mu;
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        int cur = -1;
+        if ((*err = hipGetDevice(&cur)) != hipSuccess) return nullptr;
+        if (cur != device && (*err = hipSetDevice(device)) != hipSuccess) return nullptr;
+        void *p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (*err == hipSuccess) *err = e2;
+        }
+        if (*err != hipSuccess) return nullptr;
+        ptr[device] = static_cast<float *>(p);
+    }
+    return ptr[device];
+}
+
+void launch_mlp_grad_scratch(int n, const float *W, const float *X, const float *Y, const float *Mk, float scale,
+                             float *scr, float *G, float *loss, hipStream_t s) {
+    launch_mlp_grad(n, W, X, Y, Mk, scale, scr, scr + (size_t)MLP_SCRATCH_SAMPLES * MLP_NPARAM, G, loss, s);
 }
 
 void launch_mlp_adam(float *W, float *m, float *v, const float *G, int t, float lr, hipStream_t s) {

@@ -16,6 +16,12 @@ void launch_mlp_forward(int n, const float *W, const float *X, float *Z, hipStre
 // n * MLP_NPARAM floats, lw n floats.  Fixed summation order.
 void launch_mlp_grad(int n, const float *W, const float *X, const float *Y, const float *Mk, float scale,
                      float *work, float *lw, float *G, float *loss, hipStream_t s);
+// The same gradient with the per-sample rows in the library's static device
+// scratch (at most MLP_SCRATCH_SAMPLES samples): scr = mlp_scratch(device).
+constexpr int MLP_SCRATCH_SAMPLES = 512;
+float *mlp_scratch(int device, hipError_t *err);
+void launch_mlp_grad_scratch(int n, const float *W, const float *X, const float *Y, const float *Mk, float scale,
+                             float *scr, float *G, float *loss, hipStream_t s);
 void launch_mlp_adam(float *W, float *m, float *v, const float *G, int t, float lr, hipStream_t s);
 // eta[p * L + l] for l = 1 .. L-1 from the features of problem p.
 // Host evaluation of one sample (FP64 arithmetic on the FP32 weights).

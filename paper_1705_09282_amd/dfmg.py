@@ -87,6 +87,8 @@ SIGNATURES = [
     ("dfmg_mlp_forward", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("dfmg_mlp_grad", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
                               c_void_p, c_void_p]),
+    ("dfmg_mlp_grad_noalloc", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p,
+                                      c_void_p, c_void_p]),
     ("dfmg_mlp_adam", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]),
     ("dfmg_set_learned", c_int, [c_void_p, ctypes.POINTER(ctypes.c_float), c_dblp]),
     ("dfmg_get_eta", c_int, [c_void_p, c_dblp]),
@@ -203,6 +205,18 @@ def mlp_grad(W, X, Y, M, scale, work, G, loss):
     _check(lib().dfmg_mlp_grad(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Y, MLP_NOUT * n), _devf(M, MLP_NOUT * n),
                                float(scale), _devf(work, n * (MLP_NPARAM + 1)), _devf(G, MLP_NPARAM),
                                _devf(loss, 1), _stream(W)))
+
+
+MLP_SCRATCH_SAMPLES = 512
+
+
+def mlp_grad_noalloc(W, X, Y, M, scale, G, loss):
+    """mlp_grad with the library's static scratch instead of a work array
+    (at most MLP_SCRATCH_SAMPLES samples; no device allocation)."""
+    n = X.numel() // 4
+    _check(lib().dfmg_mlp_grad_noalloc(n, _devf(W, MLP_NPARAM), _devf(X, 4 * n), _devf(Y, MLP_NOUT * n),
+                                       _devf(M, MLP_NOUT * n), float(scale), _devf(G, MLP_NPARAM),
+                                       _devf(loss, 1), _stream(W)))
 
 
 def mlp_adam(W, m, v, G, t, lr):

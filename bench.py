@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF/s solved to 1e-8 rel. residual; learned+FP32-refined vs plain FP64 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_stokes2d_traffic.json")
+TRAFFIC_FILE_HBM = os.path.join(ROOT, "profiles", "spmv_stokes2d_1024_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1705_09282_amd", "csrc", f)
                for f in ("spmv.hip", "spmv_dev.hpp", "layout.hpp", "device_util.hpp")]
 
@@ -44,17 +45,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_elem, levels):
-    """HBM bytes per launch of the finest residual kernel from the committed
-    rocprofv3 counter runs, or None if missing, taken on other kernel code or
-    on another workload size."""
+def measured_traffic(workload, path=TRAFFIC_FILE):
+    """HBM bytes per launch of a residual kernel from the committed rocprofv3
+    counter runs, or None if missing, taken on other kernel code or on
+    another workload."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256_16") != kernel_hash():
         return None
-    if t.get("workload") != {"n_elem": n_elem, "levels": levels}:
+    if t.get("workload") != workload:
         return None
     return t.get("bytes_per_launch")
 
@@ -137,7 +138,8 @@ def roofline_hbm(dev, reps=50):
     return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (FP32 residual, one problem of 1024x1024 "
                                       "elements, k=2)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_ms": ms, "setup_s": setup}
+            "traffic": measured_traffic({"n_elem": 1024, "levels": 8, "problems": 1}, TRAFFIC_FILE_HBM),
+            "alg_bytes_per_launch": alg, "avg_launch_ms": ms, "setup_s": setup}
 
 
 def main():
@@ -229,7 +231,8 @@ def main():
         return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (finest-grid FP32 residual r = F - K U, "
                                           f"{len(sigmas)} problems per launch)",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.n_elem, args.levels), "alg_bytes_per_launch": alg,
+                "traffic": measured_traffic({"n_elem": args.n_elem, "levels": args.levels}),
+                "alg_bytes_per_launch": alg,
                 "avg_launch_ms": ms}
 
     if args.roofline_hbm_only:

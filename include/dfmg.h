@@ -68,7 +68,8 @@ typedef struct {
 /* Solver options.  dfmg_default_options fills: nu1 = nu2 = 2, eta = 0 (use the
  * stable fixed damping for (dim, k): 0.35 for 2D k=1, 0.2 for 2D k=2, 0.07 for
  * 3D k=1, 0.02 for 3D k=2), precision 0, smoother 0, max_cycles 200,
- * use_graph 1, cycles_per_check 1, share_inverses 1, inner_cycles 1. */
+ * use_graph 1, cycles_per_check 1, share_inverses 1, inner_cycles 1,
+ * multiplicative 0. */
 typedef struct {
     int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
     int nu2;              /* post-smoothing steps per level                     */
@@ -83,6 +84,17 @@ typedef struct {
     int share_inverses;   /* 1: subdomains with equal local systems (to 1e-14)
                              share one stored inverse; 0: one per subdomain     */
     int inner_cycles;     /* precision 1: FP32 V-cycles per refinement step     */
+    int multiplicative;   /* 1: multiplicative Schwarz smoother (equation MSM):
+                             each smoothing step solves the subdomains one after
+                             another, each on the residual the previous ones
+                             left, undamped (eta, the smoother forms and the
+                             damping schedule do not apply).  Subdomains are
+                             visited colour by colour in the coupling-free
+                             colouring (o, a mod (k+2), b mod (k+2)[, c mod
+                             (k+2)]) of dfmg_export_sweep_colours, ascending
+                             inside a colour (the paper leaves the order open).
+                             Needs precision 0 and subdomains of at most 64
+                             DOFs (all but 3D k=2). */
 } dfmg_options;
 
 #define DFMG_MAX_HISTORY 512
@@ -346,6 +358,11 @@ int dfmg_export_matrix(const dfmg_ctx *ctx, int level, int64_t *rowptr, int32_t 
  * dfmg_patch_total gives ptr[n_patch]. */
 int dfmg_patch_total(const dfmg_ctx *ctx, int level, int64_t *total);
 int dfmg_export_patches(const dfmg_ctx *ctx, int level, int64_t *ptr, int32_t *dofs, int32_t *color);
+/* Coupling-free colour of every subdomain of level >= 1 (n_patch entries):
+ * the visiting order of the multiplicative sweep (contexts set up with
+ * multiplicative = 1 and 0 alike).  Two subdomains of one colour share no
+ * DOF and K couples no DOF of one with a DOF of the other. */
+int dfmg_export_sweep_colours(const dfmg_ctx *ctx, int level, int32_t *colour);
 /* Prolongation P_{level-1} (rows: level, cols: level-1) as CSR; nnz via
  * dfmg_prolongation_nnz. */
 int dfmg_prolongation_nnz(const dfmg_ctx *ctx, int level, int64_t *nnz);

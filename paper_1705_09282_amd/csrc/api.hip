@@ -69,6 +69,7 @@ struct DevLevel {
     int32_t *small = nullptr, *bigent = nullptr, *small_dofs = nullptr, *inv_pos4 = nullptr;
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
     int32_t *P_eci = nullptr, *R_eci = nullptr, *inv_ell = nullptr, *inv4_ell = nullptr;
+    int32_t *mlane = nullptr;  // lane table of the multiplicative sweep
     int4 *bmesh = nullptr;
     // per problem (form 4): small-subdomain and remaining-subdomain tables
     int4 *sinfo = nullptr;
@@ -164,6 +165,7 @@ struct dfmg_ctx {
     const Hierarchy &S() const { return P[0]; }
     int L() const { return P[0].pb.L; }
     bool mixed() const { return opt.precision == 1; }
+    bool mult() const { return opt.multiplicative == 1; }
 };
 
 namespace {
@@ -277,6 +279,7 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.R_ci = A.take<int32_t>(h.R_ci.size());
         v.moff = A.take<int32_t>(h.n_patch * np);
         v.ent_info = A.take<int4>(v.nent * np);
+        if (c->mult()) v.mlane = A.take<int32_t>(h.mlane.size());
     }
     c->nparts = padded_grid(maxblocks);
     c->eta = A.take<double>((size_t)L * np);
@@ -504,6 +507,29 @@ void coarse(dfmg_ctx *c, const T *G, T *dU, const int *stop) {
     launch_gemv<T>((int)n, (int)n, c->dl[0].Kinv, n * n, G, n, dU, n, stop, c->np, c->s, c->exit_mode);
 }
 
+// One multiplicative Schwarz step on level l (equation MSM): the
+// coupling-free colours in order, one launch each, every subdomain of a
+// colour computing its residual rows from the current U and correcting U in
+// place (no damping).
+template <class T>
+void mult_sweep(dfmg_ctx *c, int l, const T *F, T *U, const int *stop) {
+    const HostLevel &h = c->S().lv[l];
+    DevLevel &v = c->dl[l];
+    MultArgsT<T> a{};
+    a.sp = spmv_args<T>(c, l, F, U, nullptr, nullptr, stop);
+    a.U = U;
+    a.pdofs = v.pdofs;
+    a.ent_info = v.ent_info;
+    a.nent = v.nent;
+    a.M = v.data<T>().M;
+    a.sM = v.sM;
+    for (size_t col = 0; col + 1 < h.mwave_ptr.size(); ++col) {
+        a.lanes = v.mlane + (int64_t)h.mwave_ptr[col] * kMultLanes;
+        a.nwaves = h.mwave_ptr[col + 1] - h.mwave_ptr[col];
+        launch_schwarz_mult<T>(c->S().pb.d, c->S().pb.k, a, c->s);
+    }
+}
+
 // every problem running: the flags and their wide copies
 void reset_flags(dfmg_ctx *c) {
     launch_fill_int(c->np, c->stop, 0, c->s);
@@ -615,13 +641,24 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
     }
     const bool psi = tracks_potentials<T>(c);
     // levels <= top: single-workgroup cycle (level dampings only)
-    const int top = (psi || c->sched_on) ? 0 : c->small_top;
+    const int top = (psi || c->sched_on || c->mult()) ? 0 : c->small_top;
     for (int l = L - 1; l > top; --l) {
         LevelData<T> &v = c->dl[l].data<T>();
         const HostLevel &h = c->S().lv[l];
         bool zero = (l < L - 1) || fine_zero;
         bool first_res = (l == L - 1) && norm;
-        for (int s = 0; s < c->nu1l[l]; ++s) {
+        if (c->mult() && c->nu1l[l] > 0) {
+            // multiplicative pre-smoothing: each sweep computes its own
+            // residual rows; the check's residual comes first where asked
+            if (first_res) {
+                check(c, spmv<T>(c, l, v.F, v.U, v.r, c->partial, stop));
+                first_res = false;
+            }
+            if (zero) launch_fill<T>(h.n, v.U, h.n, T(0), stop, c->np, c->s);
+            zero = false;
+            for (int s = 0; s < c->nu1l[l]; ++s) mult_sweep<T>(c, l, v.F, v.U, stop);
+        }
+        for (int s = 0; s < (c->mult() ? 0 : c->nu1l[l]); ++s) {
             if (zero && !first_res) {
                 schwarz<T>(c, l, v.F, v.U, true, stop, step_damping(c, l, 0, s));  // U = 0: residual is F
                 zero = false;
@@ -660,6 +697,10 @@ void cycle_body(dfmg_ctx *c, bool norm, bool fine_zero) {
         LevelData<T> &v = c->dl[l].data<T>();
         if (psi) prolong_pair(c, l, stop);
         else prolong_add<T>(c, l, c->dl[l - 1].data<T>().U, v.U, stop);
+        if (c->mult()) {
+            for (int s = 0; s < c->nu2l[l]; ++s) mult_sweep<T>(c, l, v.F, v.U, stop);
+            continue;
+        }
         for (int s = 0; s < c->nu2l[l]; ++s) {
             spmv<T>(c, l, v.F, v.U, v.r, nullptr, stop);
             schwarz<T>(c, l, v.r, v.U, false, stop, step_damping(c, l, 1, s));
@@ -886,6 +927,7 @@ Problem make_problem(const dfmg_grid *grid, int k, double nu, double sigma, cons
     }
     pb.share_inverses = o.share_inverses != 0;
     pb.potentials = o.precision == 1;
+    pb.multiplicative = o.multiplicative == 1;
     return pb;
 }
 
@@ -900,6 +942,9 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
     if (o.smoother < 0 || o.smoother > 4) throw ArgError("smoother must be 0 .. 4");
     if (o.eta >= 1.0) throw ArgError("eta must be < 1");
+    if (o.multiplicative != 0 && o.multiplicative != 1) throw ArgError("multiplicative must be 0 or 1");
+    if (o.multiplicative == 1 && o.precision != 0)
+        throw ArgError("multiplicative Schwarz runs in FP64 V-cycles (precision 0)");
     return o;
 }
 
@@ -1151,6 +1196,7 @@ void dfmg_default_options(dfmg_options *o) {
     o->cycles_per_check = 1;
     o->share_inverses = 1;
     o->inner_cycles = 1;
+    o->multiplicative = 0;
 }
 
 const char *dfmg_last_error(void) { return g_err.c_str(); }
@@ -1305,6 +1351,7 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.inv_pos4, h.inv_pos4, s);
             up(v.inv_ell, h.inv_ell, s);
             up(v.inv4_ell, h.inv4_ell, s);
+            if (c->mult()) up(v.mlane, h.mlane, s);
             up(v.d.P_v, h.P_v, s);
             up(v.d.R_v, h.R_v, s);
             up(v.d.P_ev, h.P_ev, s);
@@ -1550,7 +1597,8 @@ int dfmg_time_kernel(dfmg_ctx *c, int kernel, int level, int reps, double *ms) {
                 spmv<float>(c, level, v.F, v.U, v.r, nullptr, nullptr);
             } else if (kernel == 2) {
                 LevelData<double> &v = c->dl[level].d;
-                schwarz<double>(c, level, v.r, v.U, false, nullptr);
+                if (c->mult()) mult_sweep<double>(c, level, v.F, v.U, nullptr);
+                else schwarz<double>(c, level, v.r, v.U, false, nullptr);
             } else {
                 LevelData<float> &v = c->dl[level].f;
                 schwarz<float>(c, level, v.r, v.U, false, nullptr);
@@ -1579,6 +1627,10 @@ int dfmg_level_smooth(dfmg_ctx *c, int level, const double *F, double *U, int ns
         check_level(c, level, 1);
         enter(c);
         for (int i = 0; i < nsteps; ++i) {
+            if (c->mult()) {
+                mult_sweep<double>(c, level, F, U, nullptr);
+                continue;
+            }
             spmv<double>(c, level, F, U, c->rtmp, nullptr, nullptr);
             schwarz<double>(c, level, c->rtmp, U, false, nullptr);
         }
@@ -1685,6 +1737,11 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                     if (ms_out) ms_out[1] = 0.0;
                     continue;
                 }
+                if (c->mult()) {  // the additive forms do not run
+                    if (ms_out) ms_out[2 * l + 1] = timed([&] { mult_sweep<T>(c, l, v.F, v.U, nullptr); });
+                    launch_fill<T>(c->S().lv[l].n, v.U, c->S().lv[l].n, T(0), nullptr, c->np, c->s);
+                    continue;
+                }
                 double bests = 1e30;
                 int bs = c->smoother[l];
                 for (int sm : {1, 2, 3, 4}) {
@@ -1709,7 +1766,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         reset_flags(c);
         int best_top = 0;
         double best_t = 1e30;
-        for (int t = 0; t <= (c->mixed() ? 0 : L - 2); ++t) {  // the FP32 cycle tracks potentials: no t
+        for (int t = 0; t <= (c->mixed() || c->mult() ? 0 : L - 2); ++t) {  // the FP32 cycle tracks potentials: no t
             if (t >= 1 && c->S().lv[t].n > kSmallCycleMax) break;
             c->small_top = t;
             const double ms = timed([&] {
@@ -1765,6 +1822,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 }
                 c->lpr[l] = bl;
             }
+            if (c->mult()) continue;  // no additive forms to choose
             // the FP32 cycle runs forms 3 and 4 only (the others as 4)
             int bs = c->smoother[l];
             const std::vector<int> forms = c->mixed() ? std::vector<int>{3, 4} : std::vector<int>{1, 2, 3, 4};
@@ -1851,6 +1909,7 @@ std::vector<float> network_features(const dfmg_ctx *c) {
 
 int dfmg_set_learned(dfmg_ctx *c, const float *W, const double *rho) {
     if (!c) return fail(DFMG_EINVAL, "null argument");
+    if (W && c->mult()) return fail(DFMG_EINVAL, "learned dampings belong to the additive smoother");
     return guarded([&] {
         enter(c);
         if (!W) {
@@ -1898,6 +1957,7 @@ int dfmg_set_chebyshev(dfmg_ctx *c, double alpha, int iters) {
     if (alpha < 0.0) alpha = c->S().pb.d == 3 ? kChebAlpha3d : kChebAlpha2d;
     if (!(alpha == 0.0 || (alpha > 1.0 && alpha <= 1e6))) return fail(DFMG_EINVAL, "alpha must be 0 or in (1, 1e6]");
     if (alpha > 0.0 && (iters < 1 || iters > 1000)) return fail(DFMG_EINVAL, "iters must lie in [1, 1000]");
+    if (alpha > 0.0 && c->mult()) return fail(DFMG_EINVAL, "the damping schedule belongs to the additive smoother");
     return guarded([&] {
         enter(c);
         drop_graph(c);
@@ -1932,6 +1992,7 @@ int dfmg_set_chebyshev_alpha(dfmg_ctx *c, const double *alpha, int n) {
 
 int dfmg_set_learned_chebyshev(dfmg_ctx *c, const float *W, const double *rho, int iters) {
     if (!c) return fail(DFMG_EINVAL, "null argument");
+    if (W && c->mult()) return fail(DFMG_EINVAL, "the damping schedule belongs to the additive smoother");
     if (W && (iters < 1 || iters > 1000)) return fail(DFMG_EINVAL, "iters must lie in [1, 1000]");
     return guarded([&] {
         enter(c);
@@ -2099,6 +2160,15 @@ int dfmg_export_patches(const dfmg_ctx *c, int level, int64_t *ptr, int32_t *dof
         for (size_t i = 0; i < h.pptr.size(); ++i) ptr[i] = h.pptr[i];
         std::memcpy(dofs, h.pdofs.data(), h.pdofs.size() * sizeof(int32_t));
         std::memcpy(color, h.color.data(), h.color.size() * sizeof(int32_t));
+    });
+}
+
+int dfmg_export_sweep_colours(const dfmg_ctx *c, int level, int32_t *colour) {
+    if (!c || !colour) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        check_level(c, level, 1);
+        const HostLevel &h = c->S().lv[level];
+        for (int64_t i = 0; i < h.n_patch; ++i) colour[i] = h.mcolor[i];
     });
 }
 

@@ -161,6 +161,25 @@ template <class T>
 void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_colour(const PatchArgsT<T> &a, const int32_t *list, int np, hipStream_t s);
+
+// One colour of the multiplicative sweep (equation MSM): for every entry of
+// the colour's lane table, the residual row of its DOF from the operator
+// (sp: values, F, U, strides, flags), then U += M_i E_i r for every
+// subdomain of the colour, in place.
+template <class T>
+struct MultArgsT {
+    SpmvArgsT<T> sp;       // operator and vectors (sp.r unused)
+    T *U;                  // the same U as sp.U, written
+    const int32_t *lanes;  // this colour's wavefronts: entry of lane t of wave w at w * kMultLanes + t, -1 unused
+    int nwaves;
+    const int32_t *pdofs;  // shared
+    const int4 *ent_info;  // per problem (stride nent): (M row offset, subdomain's first entry, size, 0)
+    int64_t nent;
+    const T *M;            // per problem (stride sM)
+    int64_t sM;
+};
+template <class T>
+void launch_schwarz_mult(int d, int k, const MultArgsT<T> &a, hipStream_t s);
 // A sparse transfer operator shared by the batch: CSR, and its fixed-width
 // form when w > 0 (column u of row i at u * rows + i, index -1 unused).
 template <class T>

@@ -1,0 +1,72 @@
+// Multiplicative Schwarz sweep (equation MSM): the subdomains are solved one
+// after the other, each on the residual that the previous ones left, with no
+// damping.  The sweep visits them colour by colour in a coupling-free
+// colouring: two subdomains of one colour share no DOF and no entry of K
+// couples a DOF of one with a DOF of the other, so solving a colour's
+// subdomains at the same time is the same as solving them in turn -- no
+// update inside a colour changes the residual another one reads.  One launch
+// per colour; a wavefront takes up to 64 (subdomain, row) entries of the
+// colour (kMultLanes, from the host's lane table): lane t computes the
+// residual of its DOF, (F - K U)_g, straight from the operator row, the
+// wavefront's residual entries meet in LDS, and lane t then applies its row
+// of the subdomain's bordered local inverse and adds the result to U_g in
+// place (plain read-modify-write: the colour's subdomains hold disjoint DOFs).
+#include "spmv_dev.hpp"
+
+namespace dfmg {
+
+template <int D, int K, bool WIN, class T>
+__global__ __launch_bounds__(kBlock) void k_schwarz_mult(MultArgsT<T> a) {
+    const int prob = blockIdx.y;
+    const int halt = stop_flag(a.sp.stop, prob);  // block-uniform
+    if (a.sp.exit_early && halt) return;
+    SpmvArgsT<T> sp = a.sp;
+    sp.val += prob * sp.sval;
+    sp.F += prob * sp.svec;
+    sp.U += prob * sp.svec;
+    T *U = a.U + prob * sp.svec;
+    __shared__ T sr[kBlock];
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int e = w < a.nwaves ? a.lanes[(int64_t)w * kMultLanes + lane] : -1;
+    int g = 0;
+    int4 info = make_int4(0, 0, 0, 0);
+    T r = 0;
+    if (e >= 0) {
+        g = a.pdofs[e];
+        info = a.ent_info[(int64_t)prob * a.nent + e];
+        r = sp.F[g] - spmv_row<D, K, WIN, T>(sp, g);
+    }
+    sr[threadIdx.x] = r;
+    __syncthreads();
+    if (e >= 0) {
+        // the subdomain's entries sit on consecutive lanes; this lane holds
+        // local row m = e - (first entry of the subdomain)
+        const T *loc = sr + (int)threadIdx.x - (e - info.y);
+        const T *mrow = a.M + prob * a.sM + info.x;
+        T acc = 0;
+        for (int c = 0; c < info.z; ++c) acc = fma(mrow[c], loc[c], acc);
+        if (!halt) U[g] += acc;
+    }
+}
+
+template <int D, int K, class T>
+static void launch_dk(const MultArgsT<T> &a, hipStream_t s) {
+    const dim3 grid((a.nwaves + kBlock / 64 - 1) / (kBlock / 64), a.sp.nprob);
+    if (a.sp.win) hipLaunchKernelGGL((k_schwarz_mult<D, K, true, T>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_schwarz_mult<D, K, false, T>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <class T>
+void launch_schwarz_mult(int d, int k, const MultArgsT<T> &a, hipStream_t s) {
+    if (a.nwaves <= 0) return;
+    if (d == 2 && k == 1) launch_dk<2, 1, T>(a, s);
+    else if (d == 2 && k == 2) launch_dk<2, 2, T>(a, s);
+    else if (d == 3 && k == 1) launch_dk<3, 1, T>(a, s);
+    else launch_dk<3, 2, T>(a, s);
+}
+
+template void launch_schwarz_mult<double>(int, int, const MultArgsT<double> &, hipStream_t);
+template void launch_schwarz_mult<float>(int, int, const MultArgsT<float> &, hipStream_t);
+
+}  // namespace dfmg

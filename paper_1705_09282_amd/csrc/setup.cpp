@@ -533,6 +533,7 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     L.pptr.assign(1, 0);
     L.pdofs.clear();
     L.color.clear();
+    L.mcolor.clear();
     for (int o = 0; o < (int)pots.size(); ++o) {
         const PB &p = pots[o];
         for (int a2 = p.lo[2]; a2 < p.hi[2]; ++a2)
@@ -577,6 +578,12 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
                     int col = o;
                     for (int j = 0; j < d; ++j) col = col * (k + 1) + a[j] % (k + 1);
                     L.color.push_back(col);
+                    // coupling-free colour: boxes of one colour and orientation
+                    // are k+2 elements apart in some direction, so no basis
+                    // function inside one overlaps one inside another
+                    int mc = o;
+                    for (int j = 0; j < d; ++j) mc = mc * (k + 2) + a[j] % (k + 2);
+                    L.mcolor.push_back(mc);
                 }
     }
     L.n_patch = (int64_t)L.pptr.size() - 1;
@@ -657,6 +664,35 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     L.col_list.assign(L.n_patch, 0);
     std::vector<int32_t> fc(L.col_ptr.begin(), L.col_ptr.end() - 1);
     for (int64_t i = 0; i < L.n_patch; ++i) L.col_list[fc[L.color[i]]++] = (int32_t)i;
+}
+
+// Lane table of the multiplicative sweep: per coupling-free colour (in
+// colour order), its subdomains in ascending order packed into wavefronts of
+// kMultLanes lanes, lane = one entry (subdomain, local row); a subdomain's
+// entries take consecutive lanes of one wavefront, a subdomain that does not
+// fit the rest of a wavefront starts the next one, unused lanes hold -1.
+static void build_sweep_lanes(HostLevel &L) {
+    int ncol = 0;
+    for (int c : L.mcolor) ncol = std::max(ncol, c + 1);
+    std::vector<std::vector<int32_t>> members(ncol);
+    for (int64_t i = 0; i < L.n_patch; ++i) members[L.mcolor[i]].push_back((int32_t)i);
+    L.mwave_ptr.assign(1, 0);
+    L.mlane.clear();
+    for (int c = 0; c < ncol; ++c) {
+        int fill = kMultLanes;  // forces a new wavefront for the colour's first subdomain
+        for (int32_t p : members[c]) {
+            const int n = L.pptr[p + 1] - L.pptr[p];
+            if (n > kMultLanes) throw std::runtime_error("multiplicative Schwarz needs subdomains of at most 64 DOFs");
+            if (fill + n > kMultLanes) {
+                L.mlane.insert(L.mlane.end(), kMultLanes, -1);
+                fill = 0;
+            }
+            const size_t w0 = L.mlane.size() - kMultLanes;
+            for (int m = 0; m < n; ++m) L.mlane[w0 + fill + m] = L.pptr[p] + m;
+            fill += n;
+        }
+        L.mwave_ptr.push_back((int32_t)(L.mlane.size() / kMultLanes));
+    }
 }
 
 
@@ -1036,6 +1072,8 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         }
     }
     for (int l = 1; l < L; ++l) finalize_small(H.lv[l]);
+    if (pb.multiplicative)
+        for (int l = 1; l < L; ++l) build_sweep_lanes(H.lv[l]);
     // divergence norm data (finest grid)
     {
         const int k = pb.k, q = k + 1;

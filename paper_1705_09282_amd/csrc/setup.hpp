@@ -60,6 +60,7 @@ struct Problem {
     double adv_c = 0.0;
     bool share_inverses = true;
     bool potentials = false;   // build the potential-form maps of the FP32 cycle (2D)
+    bool multiplicative = false;  // build the lane tables of the multiplicative sweep
 };
 
 struct HostLevel {
@@ -91,6 +92,11 @@ struct HostLevel {
     std::vector<double> M;     // local inverses, row-major n_i x n_i at moff
     int64_t n_class = 0;       // distinct stored inverses
     std::vector<int32_t> col_ptr, col_list;
+    // multiplicative sweep: coupling-free colour per subdomain ((o, a mod
+    // (k+2), ...) lexicographic), and per colour c the wavefronts
+    // mwave_ptr[c] .. mwave_ptr[c+1] of the lane table mlane (kMultLanes
+    // entry indices per wavefront, -1 unused); built with Problem::multiplicative
+    std::vector<int32_t> mcolor, mwave_ptr, mlane;
     // subdomains with <= kSmallPatch DOFs, and the entries of the others
     std::vector<int32_t> small_list, big_ent;
     // smoother form 4 keeps the corrections of small subdomain q, row m at

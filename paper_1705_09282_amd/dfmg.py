@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", c_int), ("nu2", c_int), ("eta", c_double), ("precision", c_int),
                 ("smoother", c_int), ("max_cycles", c_int), ("use_graph", c_int),
                 ("cycles_per_check", c_int), ("share_inverses", c_int),
-                ("inner_cycles", c_int)]
+                ("inner_cycles", c_int), ("multiplicative", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -101,6 +101,7 @@ SIGNATURES = [
     ("dfmg_export_matrix", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_patch_total", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_patches", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_i32p]),
+    ("dfmg_export_sweep_colours", c_int, [c_void_p, c_int, c_i32p]),
     ("dfmg_prolongation_nnz", c_int, [c_void_p, c_int, c_i64p]),
     ("dfmg_export_prolongation", c_int, [c_void_p, c_int, c_i64p, c_i32p, c_dblp]),
     ("dfmg_manufactured_rhs", c_int, [c_void_p, c_dblp]),
@@ -301,6 +302,13 @@ class Solver:
         _check(lib().dfmg_export_patches(self._ctx, level, _ptr(ptr, ctypes.c_int64), _ptr(dofs, ctypes.c_int32),
                                          _ptr(color, ctypes.c_int32)))
         return ptr, dofs, color
+
+    def export_sweep_colours(self, level):
+        """Coupling-free colour of every subdomain of `level` (the visiting
+        order of the multiplicative sweep)."""
+        out = np.zeros(self.sizes(level)["n_patch"], np.int32)
+        _check(lib().dfmg_export_sweep_colours(self._ctx, level, _ptr(out, ctypes.c_int32)))
+        return out
 
     def export_prolongation(self, level):
         s = self.sizes(level)

@@ -106,3 +106,26 @@ def test_tuning_validation():
             s.set_tuning(lpr, sm)
     assert s.get_tuning() == {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3]}
     s.close()
+
+
+@pytest.mark.parametrize("d,N,k,L", [(2, 16, 1, 3), (2, 12, 2, 2), (3, 8, 1, 2)])
+def test_sweep_colours_match_oracle(d, N, k, L):
+    """The coupling-free colours of the multiplicative sweep equal the
+    oracle's bit for bit on every smoothed level (same subdomain order)."""
+    from oracle.multigrid import coupling_free_colours
+    s = dfmg.Solver(d, N, L, k)
+    h = Hierarchy(d, N, k, L, 1.0, 1.0)
+    for l in range(1, L):
+        got = s.export_sweep_colours(l)
+        want = coupling_free_colours(h.levels[l].disc, h.levels[l].patches)
+        np.testing.assert_array_equal(got, want)
+    s.close()
+
+
+def test_multiplicative_option_errors():
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(2, 8, 2, 1, multiplicative=1, precision=1)   # FP64 cycles only
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(3, 4, 2, 2, multiplicative=1)               # subdomains above 64 DOFs
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(2, 8, 2, 1, multiplicative=2)

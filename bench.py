@@ -12,7 +12,8 @@ schedule's interval ratio and the smoothing steps) with FP32 V-cycles inside
 FP64 iterative refinement.  Timed beside it on the same problems: the plain
 FP64 solver (fixed damping, V(2,2)), FP32 refinement with the fixed damping
 and V(2,2), FP32 refinement with the learned constant per-level damping and
-steps, and the learned schedule in plain FP64 cycles.
+steps, the learned schedule in plain FP64 cycles, and the paper's
+multiplicative Schwarz smoother with V(1,2) in FP64 cycles.
 
 Prints one JSON line: metric, value (DOF/s over the whole step, DOFs =
 dim V_h + dim Q_h), roofline of the dominant kernel (finest-grid residual
@@ -121,6 +122,43 @@ def cpu_baseline(tol, U_gpu, runs=5, warmup=1):
             "cpu_model": model, "nproc": ncores}, err
 
 
+def paper_oseen_legs(dev, steps=3, warmup=1):
+    """The paper's generalized Oseen problems on the GPU (context, not the
+    metric): 2D k=1 (the paper's p = 2), 256^2 elements refined from a
+    single coarsest element (9 grids), nu = 1, sigma = Da = 1000, advection
+    = the manufactured velocity scaled to max|a| / nu = Re in {1, 100}; the
+    two problems as one batch solved from U = 0 to 1e-8, with the
+    multiplicative smoother V(1,2) (the paper's) and the additive one V(2,2)
+    (fixed damping), FP64."""
+    import math
+    import torch
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd.learned import manufactured_speed
+    res = [1.0, 100.0]
+    cs = [r / manufactured_speed(2) for r in res]
+    out = {"workload": "2D generalized Oseen, k=1, 256x256, 9 grids, nu=1, Da=1000, a = manufactured velocity, "
+                       "Re in {1, 100}, tol 1e-8, U0=0"}
+    for name, opts in (("multiplicative_v12", dict(multiplicative=1, nu1=1, nu2=2)), ("additive_v22", {})):
+        b = BatchSolver(2, 256, 9, 1, [1.0, 1.0], [1000.0, 1000.0], cs, adv_kind=2, max_cycles=300, **opts).bind(dev)
+        F = torch.tensor(b.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        for _ in range(warmup):
+            U.zero_()
+            b.solve(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U.zero_()
+            st = b.solve(F, U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        dofs = 2 * (b.n - 1)
+        out[name] = {"ms_per_solve": 1e3 * dt, "dofs_per_s": dofs / dt, "cycles_per_re": [x["cycles"] for x in st],
+                     "div_norm_per_re": [float(x) for x in b.div_norm(U)]}
+        b.close()
+    return out
+
+
 def roofline_hbm(dev, reps=50):
     """The FP32 residual on an operator that cannot stay in the 256 MB
     Infinity Cache: one problem of the same workload on 1024^2 elements
@@ -162,6 +200,7 @@ def main():
     ap.add_argument("--roofline-hbm-only", action="store_true",
                     help="only the HBM-resident residual leg (1024^2, one problem)")
     ap.add_argument("--no-hbm-leg", action="store_true", help="skip the HBM-resident residual leg")
+    ap.add_argument("--no-paper-legs", action="store_true", help="skip the paper's Oseen problems (context legs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -188,18 +227,19 @@ def main():
     from paper_1705_09282_amd import learned
     models = {"constant": learned.load(), "chebyshev": learned.load(learned.CHEB_WEIGHTS)}
 
-    def make_batch(precision, use_learned=None):
+    def make_batch(precision, use_learned=None, **opts):
         b = BatchSolver(cfg["d"], cfg["N"], cfg["L"], cfg["k"], [cfg["nu"]] * len(sigmas), sigmas,
-                        precision=precision).bind(dev)
+                        precision=precision, **opts).bind(dev)
+        tag = "-mult" if opts.get("multiplicative") else ""
         tuning = b.autotune(reps=20, cache=args.tuning_cache,
-                            key=f"{cfg['N']}-{cfg['L']}-{precision}-{use_learned or 'fixed'}")
+                            key=f"{cfg['N']}-{cfg['L']}-{precision}-{use_learned or 'fixed'}{tag}")
         if use_learned:
             t0 = time.perf_counter()
             learned.apply(b, models[use_learned])
             # the schedule's eigenvalue estimates (30 power iterations per
             # level and problem, host norms) are made here
             tuning["learned_setup_s"] = time.perf_counter() - t0
-        print(f"[bench] batch ready: precision {precision}, {use_learned or 'fixed damping'}", file=sys.stderr,
+        print(f"[bench] batch ready: precision {precision}, {use_learned or 'fixed damping'}{tag}", file=sys.stderr,
               flush=True)
         F = torch.tensor(b.manufactured_rhs(), device=dev)
         U = torch.zeros_like(F)
@@ -258,6 +298,7 @@ def main():
     bc64, Fc64, Uc64, _ = make_batch(0, use_learned="chebyshev")
     b32, F32, U32, tun32 = make_batch(1, use_learned="chebyshev")
     setup_s = time.perf_counter() - t_setup
+    bm, Fm, Um, _ = make_batch(0, multiplicative=1, nu1=1, nu2=2)
     z = b64.sizes()
     dofs = len(sigmas) * (z["n"] - 1)
     print(f"[bench] setup of 5 batches of {len(sigmas)} problems: {setup_s:.1f} s, DOFs/step {dofs}",
@@ -273,6 +314,9 @@ def main():
           file=sys.stderr, flush=True)
     Tc64, statsc64 = run(bc64, Fc64, Uc64)
     print(f"[bench] FP64 batch, learned Chebyshev schedule: {args.steps} steps in {Tc64:.3f} s", file=sys.stderr,
+          flush=True)
+    Tm, statsm = run(bm, Fm, Um)
+    print(f"[bench] FP64 batch, multiplicative Schwarz V(1,2): {args.steps} steps in {Tm:.3f} s", file=sys.stderr,
           flush=True)
     T, stats = run(b32, F32, U32)
     print(f"[bench] learned Chebyshev schedule + FP32-refined batch: {args.steps} steps in {T:.3f} s",
@@ -341,6 +385,9 @@ def main():
                 "eta_per_sigma": [[round(x, 4) for x in row] for row in blc.get_eta().tolist()]},
             "fp64_learned_chebyshev": {"value": args.steps * dofs / Tc64, "ms_per_step": 1e3 * Tc64 / args.steps,
                                        "cycles_per_sigma": [st["cycles"] for st in statsc64]},
+            "fp64_multiplicative_v12": {"value": args.steps * dofs / Tm, "ms_per_step": 1e3 * Tm / args.steps,
+                                        "cycles_per_sigma": [st["cycles"] for st in statsm],
+                                        "div_norm_per_sigma": [float(x) for x in bm.div_norm(Um)]},
             "speedup_vs_plain_fp64": value / value64,
             "setup_s": setup_s,
             "lmax_estimate_s": tuning.get("learned_setup_s"),
@@ -355,13 +402,16 @@ def main():
         "roofline": rl,
     }
     U32_sigma1 = U32[n:2 * n].cpu().numpy()
-    for s in (b64, bfx, blc, bc64, b32):
+    for s in (b64, bfx, blc, bc64, b32, bm):
         s.close()
-    del b64, bfx, blc, bc64, b32, F64, U64, Ffx, Ufx, Flc, Ulc, Fc64, Uc64, F32, U32
+    del b64, bfx, blc, bc64, b32, bm, F64, U64, Ffx, Ufx, Flc, Ulc, Fc64, Uc64, F32, U32, Fm, Um
     torch.cuda.empty_cache()
     if not args.no_hbm_leg:
         print("[bench] HBM-resident residual leg (1024^2)", file=sys.stderr, flush=True)
         line["roofline_hbm"] = roofline_hbm(dev)
+    if not args.no_paper_legs:
+        print("[bench] the paper's Oseen problems (context)", file=sys.stderr, flush=True)
+        line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
     if not args.no_cpu_baseline and args.n_elem == 256 and args.levels == 6:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"], line["config"]["vel_rel_err_vs_oracle_sigma1"] = cpu_baseline(args.tol, U32_sigma1)

@@ -59,7 +59,13 @@ typedef struct {
 
 /* Advection field of the generalized Oseen problem (paper, weak form).
  * kind 0: none (generalized Stokes).
- * kind 1: 2D rigid rotation a = c * (-(y - 1/2), x - 1/2). */
+ * kind 1: rigid rotation about the centre, a = c * (-(y - 1/2), x - 1/2) in
+ *         2D, a = c * (-(y - 1/2), x - 1/2, 0) in 3D.
+ * kind 2: a = c * u with u the manufactured velocity of
+ *         dfmg_manufactured_rhs (the paper's Oseen problems take the
+ *         advection equal to the manufactured velocity).
+ * |a| (the network's input |a| h / nu) is max |a|: |c| / sqrt(2) for
+ * kind 1, |c| max |u| for kind 2. */
 typedef struct {
     int kind;
     double c;
@@ -93,8 +99,7 @@ typedef struct {
                              colouring (o, a mod (k+2), b mod (k+2)[, c mod
                              (k+2)]) of dfmg_export_sweep_colours, ascending
                              inside a colour (the paper leaves the order open).
-                             Needs precision 0 and subdomains of at most 64
-                             DOFs (all but 3D k=2). */
+                             Needs precision 0. */
 } dfmg_options;
 
 #define DFMG_MAX_HISTORY 512

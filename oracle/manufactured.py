@@ -97,3 +97,11 @@ def forcing(d, nu, sigma, advection=None):
             out = out + np.einsum("nj,ncj->nc", a, gu)
         return out
     return f
+
+
+def manufactured_advection(d, c):
+    """Advection a = c u with u the manufactured velocity (the paper's Oseen
+    problems advect with the manufactured velocity field)."""
+    def a(X):
+        return c * velocity(d, X)
+    return a

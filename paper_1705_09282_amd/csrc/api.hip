@@ -523,8 +523,9 @@ void mult_sweep(dfmg_ctx *c, int l, const T *F, T *U, const int *stop) {
     a.nent = v.nent;
     a.M = v.data<T>().M;
     a.sM = v.sM;
+    a.width = h.mwidth;
     for (size_t col = 0; col + 1 < h.mwave_ptr.size(); ++col) {
-        a.lanes = v.mlane + (int64_t)h.mwave_ptr[col] * kMultLanes;
+        a.lanes = v.mlane + (int64_t)h.mwave_ptr[col] * h.mwidth;
         a.nwaves = h.mwave_ptr[col + 1] - h.mwave_ptr[col];
         launch_schwarz_mult<T>(c->S().pb.d, c->S().pb.k, a, c->s);
     }
@@ -1898,7 +1899,7 @@ std::vector<float> network_features(const dfmg_ctx *c) {
     std::vector<float> feat((size_t)MLP_IN * c->np);
     for (int p = 0; p < c->np; ++p) {
         const Problem &pb = c->P[p].pb;
-        const double amag = pb.adv_kind == 1 ? std::fabs(pb.adv_c) / std::sqrt(2.0) : 0.0;
+        const double amag = advection_speed(pb);
         feat[p * MLP_IN + 0] = (float)(std::log10(pb.nu) / 2.0);
         feat[p * MLP_IN + 1] = (float)(std::log10(std::max(pb.sigma, 1e-300)) / 4.0);
         feat[p * MLP_IN + 2] = (float)(amag / (pb.N * pb.nu));

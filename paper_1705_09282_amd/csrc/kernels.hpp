@@ -170,8 +170,9 @@ template <class T>
 struct MultArgsT {
     SpmvArgsT<T> sp;       // operator and vectors (sp.r unused)
     T *U;                  // the same U as sp.U, written
-    const int32_t *lanes;  // this colour's wavefronts: entry of lane t of wave w at w * kMultLanes + t, -1 unused
+    const int32_t *lanes;  // this colour's workgroups: entry of thread t of group w at w * width + t, -1 unused
     int nwaves;
+    int width;             // threads per workgroup: kMultLanes or kMultLanesBig
     const int32_t *pdofs;  // shared
     const int4 *ent_info;  // per problem (stride nent): (M row offset, subdomain's first entry, size, 0)
     int64_t nent;

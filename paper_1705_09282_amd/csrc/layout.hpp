@@ -23,8 +23,10 @@ constexpr int kEllMax = 24;
 // next one); 0: the CSR form.
 inline int ell_bucket(int w) { return w <= 0 ? 0 : (w <= 4 ? 4 : (w <= 8 ? 8 : (w <= 12 ? 12 : (w <= 24 ? 24 : 0)))); }
 
-// Lanes of a wavefront in the multiplicative sweep (one entry each).
-constexpr int kMultLanes = 64;
+// Threads of a workgroup in the multiplicative sweep (one entry each; a
+// subdomain's entries never straddle two workgroups); levels with a
+// subdomain of more than kMultLanes DOFs use kMultLanesBig.
+constexpr int kMultLanes = 256, kMultLanesBig = 1024;
 
 // A lane of the wavefront that solves a boundary subdomain preloads this many
 // coefficients of its row of the local inverse into registers.

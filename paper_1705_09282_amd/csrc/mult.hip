@@ -5,18 +5,20 @@
 // couples a DOF of one with a DOF of the other, so solving a colour's
 // subdomains at the same time is the same as solving them in turn -- no
 // update inside a colour changes the residual another one reads.  One launch
-// per colour; a wavefront takes up to 64 (subdomain, row) entries of the
-// colour (kMultLanes, from the host's lane table): lane t computes the
-// residual of its DOF, (F - K U)_g, straight from the operator row, the
-// wavefront's residual entries meet in LDS, and lane t then applies its row
-// of the subdomain's bordered local inverse and adds the result to U_g in
-// place (plain read-modify-write: the colour's subdomains hold disjoint DOFs).
+// per colour; a workgroup takes up to B (subdomain, row) entries of the
+// colour (B = 256, or 1024 on levels with larger subdomains; from the host's
+// lane table, where a subdomain's entries are consecutive threads of one
+// workgroup): thread t computes the residual of
+// its DOF, (F - K U)_g, straight from the operator row, the workgroup's
+// residual entries meet in LDS, and thread t then applies its row of the
+// subdomain's bordered local inverse and adds the result to U_g in place
+// (plain read-modify-write: the colour's subdomains hold disjoint DOFs).
 #include "spmv_dev.hpp"
 
 namespace dfmg {
 
-template <int D, int K, bool WIN, class T>
-__global__ __launch_bounds__(kBlock) void k_schwarz_mult(MultArgsT<T> a) {
+template <int D, int K, bool WIN, int B, class T>
+__global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(a.sp.stop, prob);  // block-uniform
     if (a.sp.exit_early && halt) return;
@@ -25,10 +27,9 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_mult(MultArgsT<T> a) {
     sp.F += prob * sp.svec;
     sp.U += prob * sp.svec;
     T *U = a.U + prob * sp.svec;
-    __shared__ T sr[kBlock];
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
-    const int e = w < a.nwaves ? a.lanes[(int64_t)w * kMultLanes + lane] : -1;
+    __shared__ T sr[B];
+    const int w = blockIdx.x;
+    const int e = w < a.nwaves ? a.lanes[(int64_t)w * B + threadIdx.x] : -1;
     int g = 0;
     int4 info = make_int4(0, 0, 0, 0);
     T r = 0;
@@ -40,8 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_mult(MultArgsT<T> a) {
     sr[threadIdx.x] = r;
     __syncthreads();
     if (e >= 0) {
-        // the subdomain's entries sit on consecutive lanes; this lane holds
-        // local row m = e - (first entry of the subdomain)
+        // the subdomain's entries sit on consecutive threads; this thread
+        // holds local row m = e - (first entry of the subdomain)
         const T *loc = sr + (int)threadIdx.x - (e - info.y);
         const T *mrow = a.M + prob * a.sM + info.x;
         T acc = 0;
@@ -50,11 +51,17 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_mult(MultArgsT<T> a) {
     }
 }
 
+template <int D, int K, int B, class T>
+static void launch_dkb(const MultArgsT<T> &a, hipStream_t s) {
+    const dim3 grid(a.nwaves, a.sp.nprob);
+    if (a.sp.win) hipLaunchKernelGGL((k_schwarz_mult<D, K, true, B, T>), grid, dim3(B), 0, s, a);
+    else hipLaunchKernelGGL((k_schwarz_mult<D, K, false, B, T>), grid, dim3(B), 0, s, a);
+}
+
 template <int D, int K, class T>
 static void launch_dk(const MultArgsT<T> &a, hipStream_t s) {
-    const dim3 grid((a.nwaves + kBlock / 64 - 1) / (kBlock / 64), a.sp.nprob);
-    if (a.sp.win) hipLaunchKernelGGL((k_schwarz_mult<D, K, true, T>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_schwarz_mult<D, K, false, T>), grid, dim3(kBlock), 0, s, a);
+    if (a.width == kMultLanes) launch_dkb<D, K, kMultLanes, T>(a, s);
+    else launch_dkb<D, K, kMultLanesBig, T>(a, s);
 }
 
 template <class T>

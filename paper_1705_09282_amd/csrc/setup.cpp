@@ -223,6 +223,30 @@ static void fine_factors(const Problem &pb, Factors &F) {
                         -nrm * (v[m1] * dv[m2] + dv[m1] * v[m2]) + CI / h * v[m1] * v[m2];
         }
     }
+    if (pb.adv_kind == 2) {
+        // weights s = sin^2(pi x) and s' = pi sin(2 pi x) of the manufactured
+        // velocity's factors, by the same quadrature
+        for (int a = 0; a < 2; ++a) {
+            const int q = k + a, n = N + q;
+            const auto kn = open_knots(N, q);
+            for (int wi = 0; wi < 2; ++wi) {
+                F.wmass[a][wi].init(n, n);
+                F.wdcol[a][wi].init(n, n);
+            }
+            for (int e = 0; e < N; ++e)
+                for (int g = 0; g < nq; ++g) {
+                    const double x = (e + 0.5 * (t[g] + 1.0)) * h, wq = 0.5 * h * wt[g];
+                    const double wv[2] = {std::sin(M_PI * x) * std::sin(M_PI * x), M_PI * std::sin(2.0 * M_PI * x)};
+                    span_basis(kn, q, e + q, x, v, dv);
+                    for (int wi = 0; wi < 2; ++wi)
+                        for (int m1 = 0; m1 <= q; ++m1)
+                            for (int m2 = 0; m2 <= q; ++m2) {
+                                F.wmass[a][wi](e + m1, e + m2) += wq * wv[wi] * v[m1] * v[m2];
+                                F.wdcol[a][wi](e + m1, e + m2) += wq * wv[wi] * v[m1] * dv[m2];
+                            }
+                }
+        }
+    }
     const auto kn1 = open_knots(N, k + 1), kn0 = open_knots(N, k);
     F.grad.init(N + k + 1, N + k);
     for (int e = 0; e < N; ++e)
@@ -245,11 +269,30 @@ static void coarse_factors(const Factors &Ff, int k, Factors &Fc) {
         Fc.dcol[a] = rap(T[a], Ff.dcol[a], T[a]);
         Fc.xmass[a] = rap(T[a], Ff.xmass[a], T[a]);
         Fc.nit[a] = rap(T[a], Ff.nit[a], T[a]);
+        for (int wi = 0; wi < 2; ++wi)
+            if (Ff.wmass[a][wi].nr) {
+                Fc.wmass[a][wi] = rap(T[a], Ff.wmass[a][wi], T[a]);
+                Fc.wdcol[a][wi] = rap(T[a], Ff.wdcol[a][wi], T[a]);
+            }
     }
     Fc.grad = rap(T[1], Ff.grad, T[0]);
 }
 
 // ----------------------------------------------------------- operator terms
+
+// The manufactured velocity u = curl psi (2D psi = s(x) s(y); 3D psi = (g, 0,
+// g), g = s(x) s(y) s(z), s(t) = sin^2(pi t)): component c is a sum of
+// coef * prod_j s^(n_j)(x_j).
+struct VelTerm {
+    double c;
+    int n[3];
+};
+static const std::vector<std::vector<VelTerm>> &velocity_terms(int d) {
+    static const std::vector<std::vector<VelTerm>> u2 = {{{1.0, {0, 1, 0}}}, {{-1.0, {1, 0, 0}}}};
+    static const std::vector<std::vector<VelTerm>> u3 = {
+        {{1.0, {0, 1, 0}}}, {{1.0, {0, 0, 1}}, {-1.0, {1, 0, 0}}}, {{-1.0, {0, 1, 0}}}};
+    return d == 2 ? u2 : u3;
+}
 
 struct FRef {
     const Mat1 *m = nullptr;
@@ -279,15 +322,27 @@ static std::vector<Term> make_terms(const Problem &pb, const Factors &F, int R, 
             T.push_back(s);
             T.push_back(n);
         }
-        if (pb.adv_kind == 1 && d == 2) {
-            // a = c (-(y - 1/2), x - 1/2):  (v_c, a_x d_x u_c) + (v_c, a_y d_y u_c)
+        if (pb.adv_kind == 1) {
+            // a = c (-(y - 1/2), x - 1/2[, 0]):  (v_c, a_x d_x u_c) + (v_c, a_y d_y u_c)
             Term ax{-pb.adv_c, {}}, ay{pb.adv_c, {}};
             ax.f[0] = {&F.dcol[idx(c, 0)], false};
             ax.f[1] = {&F.xmass[idx(c, 1)], false};
             ay.f[0] = {&F.xmass[idx(c, 0)], false};
             ay.f[1] = {&F.dcol[idx(c, 1)], false};
+            if (d == 3) ax.f[2] = ay.f[2] = {&F.mass[idx(c, 2)], false};
             T.push_back(ax);
             T.push_back(ay);
+        } else if (pb.adv_kind == 2) {
+            // a = c u, u_j = sum of coef * prod_dir s^(n_dir)(x_dir), n in {0, 1}:
+            // (v_c, a_j d_j u_c) = c coef x (weighted derivative integral in
+            // direction j) x (weighted mass integrals in the others)
+            for (int j = 0; j < d; ++j)
+                for (const VelTerm &vt : velocity_terms(d)[j]) {
+                    Term a{pb.adv_c * vt.c, {}};
+                    for (int e = 0; e < d; ++e)
+                        a.f[e] = {e == j ? &F.wdcol[idx(c, e)][vt.n[e]] : &F.wmass[idx(c, e)][vt.n[e]], false};
+                    T.push_back(a);
+                }
         }
     } else if (R < d && C == d) {
         Term t{-1.0, {}};  // -B
@@ -667,10 +722,12 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
 }
 
 // Lane table of the multiplicative sweep: per coupling-free colour (in
-// colour order), its subdomains in ascending order packed into wavefronts of
-// kMultLanes lanes, lane = one entry (subdomain, local row); a subdomain's
-// entries take consecutive lanes of one wavefront, a subdomain that does not
-// fit the rest of a wavefront starts the next one, unused lanes hold -1.
+// colour order), its subdomains in ascending order packed into workgroups of
+// kMultLanes threads (kMultLanesBig if a subdomain is larger), thread = one
+// entry (subdomain, local row); a
+// subdomain's entries take consecutive threads of one workgroup, a subdomain
+// that does not fit the rest of a workgroup starts the next one, unused
+// threads hold -1.
 static void build_sweep_lanes(HostLevel &L) {
     int ncol = 0;
     for (int c : L.mcolor) ncol = std::max(ncol, c + 1);
@@ -678,20 +735,22 @@ static void build_sweep_lanes(HostLevel &L) {
     for (int64_t i = 0; i < L.n_patch; ++i) members[L.mcolor[i]].push_back((int32_t)i);
     L.mwave_ptr.assign(1, 0);
     L.mlane.clear();
+    const int B = L.max_patch <= kMultLanes ? kMultLanes : kMultLanesBig;
+    if (L.max_patch > B) throw std::runtime_error("multiplicative Schwarz needs subdomains of at most 1024 DOFs");
+    L.mwidth = B;
     for (int c = 0; c < ncol; ++c) {
-        int fill = kMultLanes;  // forces a new wavefront for the colour's first subdomain
+        int fill = B;  // forces a new workgroup for the colour's first subdomain
         for (int32_t p : members[c]) {
             const int n = L.pptr[p + 1] - L.pptr[p];
-            if (n > kMultLanes) throw std::runtime_error("multiplicative Schwarz needs subdomains of at most 64 DOFs");
-            if (fill + n > kMultLanes) {
-                L.mlane.insert(L.mlane.end(), kMultLanes, -1);
+            if (fill + n > B) {
+                L.mlane.insert(L.mlane.end(), B, -1);
                 fill = 0;
             }
-            const size_t w0 = L.mlane.size() - kMultLanes;
+            const size_t w0 = L.mlane.size() - B;
             for (int m = 0; m < n; ++m) L.mlane[w0 + fill + m] = L.pptr[p] + m;
             fill += n;
         }
-        L.mwave_ptr.push_back((int32_t)(L.mlane.size() / kMultLanes));
+        L.mwave_ptr.push_back((int32_t)(L.mlane.size() / B));
     }
 }
 
@@ -1039,7 +1098,7 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
     if (pb.L < 1 || pb.N < 1) throw std::runtime_error("n_elem and n_levels must be positive");
     if (pb.N % (1 << (pb.L - 1)) != 0) throw std::runtime_error("n_elem must be divisible by 2^(n_levels-1)");
     if (!(pb.nu > 0.0) || !(pb.sigma >= 0.0)) throw std::runtime_error("need nu > 0 and sigma >= 0");
-    if (pb.adv_kind != 0 && !(pb.adv_kind == 1 && pb.d == 2)) throw std::runtime_error("advection kind 1 needs dim 2");
+    if (pb.adv_kind < 0 || pb.adv_kind > 2) throw std::runtime_error("advection kind must be 0, 1 or 2");
     H.pb = pb;
     const int L = pb.L;
     H.fac.assign(L, Factors());
@@ -1113,17 +1172,8 @@ static void forcing(const Problem &pb, const double *x, double *f) {
     const int d = pb.d;
     const double pi = M_PI;
     // velocity components as sums of c * prod_j s^{(n_j)}(x_j)
-    struct T {
-        double c;
-        int n[3];
-    };
-    std::vector<std::vector<T>> U;
-    if (d == 2) {
-        U = {{{1.0, {0, 1, 0}}}, {{-1.0, {1, 0, 0}}}};
-    } else {
-        U = {{{1.0, {0, 1, 0}}}, {{1.0, {0, 0, 1}}, {-1.0, {1, 0, 0}}}, {{-1.0, {0, 1, 0}}}};
-    }
-    auto ev = [&](const std::vector<T> &terms, int dj, int dn) {
+    const auto &U = velocity_terms(d);
+    auto ev = [&](const std::vector<VelTerm> &terms, int dj, int dn) {
         double s = 0.0;
         for (auto &t : terms) {
             double p = t.c;
@@ -1136,6 +1186,8 @@ static void forcing(const Problem &pb, const double *x, double *f) {
     if (pb.adv_kind == 1) {
         a[0] = -pb.adv_c * (x[1] - 0.5);
         a[1] = pb.adv_c * (x[0] - 0.5);
+    } else if (pb.adv_kind == 2) {
+        for (int j = 0; j < d; ++j) a[j] = pb.adv_c * ev(U[j], -1, 0);
     }
     for (int c = 0; c < d; ++c) {
         double lap = 0.0, adv = 0.0;
@@ -1147,6 +1199,33 @@ static void forcing(const Problem &pb, const double *x, double *f) {
         for (int j = 0; j < d; ++j) gp *= (j == c) ? std::cos(2 * pi * x[j]) : std::sin(2 * pi * x[j]);
         f[c] = pb.sigma * ev(U[c], -1, 0) - pb.nu * lap + gp + adv;
     }
+}
+
+double advection_speed(const Problem &pb) {
+    if (pb.adv_kind == 1) return std::fabs(pb.adv_c) / std::sqrt(2.0);  // at the corners
+    if (pb.adv_kind != 2) return 0.0;
+    // max |u| of the manufactured velocity on a uniform sample grid, times |c|
+    const int d = pb.d, m = d == 2 ? 400 : 80;
+    const auto &U = velocity_terms(d);
+    double best = 0.0;
+    const int m2 = d == 3 ? m : 0;
+    for (int i2 = 0; i2 <= m2; ++i2)
+        for (int i1 = 0; i1 <= m; ++i1)
+            for (int i0 = 0; i0 <= m; ++i0) {
+                const double x[3] = {(double)i0 / m, (double)i1 / m, (double)i2 / m};
+                double s2 = 0.0;
+                for (int j = 0; j < d; ++j) {
+                    double uj = 0.0;
+                    for (const VelTerm &t : U[j]) {
+                        double p = t.c;
+                        for (int e = 0; e < d; ++e) p *= sder(t.n[e], x[e]);
+                        uj += p;
+                    }
+                    s2 += uj * uj;
+                }
+                best = std::max(best, s2);
+            }
+    return std::fabs(pb.adv_c) * std::sqrt(best);
 }
 
 void manufactured_rhs(const Hierarchy &H, double *F) {

@@ -51,11 +51,18 @@ struct Factors {
     int N = 0;
     Mat1 mass[2], stiff[2], dcol[2], xmass[2], nit[2];
     Mat1 grad;  // integral of (N^{k+1}_i)' N^k_j
+    // advection by the manufactured velocity (kind 2): weighted mass
+    // integral N_i w N_j and weighted derivative integral N_i w N_j' with
+    // w = s (index 0) or s' (index 1), s(x) = sin^2(pi x), s' = pi sin(2 pi x)
+    // (empty for the other kinds)
+    Mat1 wmass[2][2], wdcol[2][2];
 };
 
 struct Problem {
     int d = 2, N = 0, L = 1, k = 1;
     double nu = 1.0, sigma = 1.0;
+    // advection: 0 none; 1 rotation a = c (-(y - 1/2), x - 1/2[, 0]); 2 the
+    // manufactured velocity, a = c u (the paper's Oseen problems)
     int adv_kind = 0;
     double adv_c = 0.0;
     bool share_inverses = true;
@@ -93,10 +100,11 @@ struct HostLevel {
     int64_t n_class = 0;       // distinct stored inverses
     std::vector<int32_t> col_ptr, col_list;
     // multiplicative sweep: coupling-free colour per subdomain ((o, a mod
-    // (k+2), ...) lexicographic), and per colour c the wavefronts
-    // mwave_ptr[c] .. mwave_ptr[c+1] of the lane table mlane (kMultLanes
-    // entry indices per wavefront, -1 unused); built with Problem::multiplicative
+    // (k+2), ...) lexicographic), and per colour c the workgroups
+    // mwave_ptr[c] .. mwave_ptr[c+1] of the lane table mlane (mwidth entry
+    // indices per workgroup, -1 unused); built with Problem::multiplicative
     std::vector<int32_t> mcolor, mwave_ptr, mlane;
+    int mwidth = 0;            // entries per workgroup of mlane
     // subdomains with <= kSmallPatch DOFs, and the entries of the others
     std::vector<int32_t> small_list, big_ent;
     // smoother form 4 keeps the corrections of small subdomain q, row m at
@@ -170,6 +178,10 @@ struct BlockGeom {
 
 // Entry K(g_row, g_col) of a level (0 if outside the stored pattern).
 double level_entry(const Hierarchy &H, int level, int64_t grow, int64_t gcol);
+
+// max |a| over the domain (rotation: at the corners; manufactured velocity:
+// on a uniform sample grid).
+double advection_speed(const Problem &pb);
 
 // Manufactured load vector on the finest grid.
 void manufactured_rhs(const Hierarchy &H, double *F);

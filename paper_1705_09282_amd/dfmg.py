@@ -139,6 +139,14 @@ def lib():
     return _lib
 
 
+def _advection(c, kind):
+    """dfmg_advection of speed c: kind None takes rotation (1) for c != 0 and
+    none (0) otherwise; kind 2 advects with c times the manufactured velocity."""
+    if kind is None:
+        kind = 1 if c != 0.0 else 0
+    return Advection(int(kind), float(c))
+
+
 def _network_args(W, rho_plain, nprob):
     w = np.ascontiguousarray(W, dtype=np.float32)
     if w.size != MLP_NPARAM:
@@ -240,17 +248,18 @@ class Solver:
     A Solver is the batch of one; BatchSolver holds several problems on the
     same mesh and solves them together."""
 
-    def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, **options):
-        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options)
+    def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, adv_kind=None, **options):
+        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options, adv_kind)
 
-    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options):
+    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options, adv_kind=None):
         self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
         self.nprob = len(nus)
         self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
         if not (len(sigmas) == len(cs) == self.nprob):
             raise ValueError("one nu, sigma and c per problem")
         g = Grid(dim, n_elem, n_levels)
-        adv = (Advection * self.nprob)(*[Advection(1 if c != 0.0 else 0, float(c)) for c in cs])
+        self.adv_kind = adv_kind
+        adv = (Advection * self.nprob)(*[_advection(c, adv_kind) for c in cs])
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)
@@ -548,9 +557,9 @@ class BatchSolver(Solver):
     kernel launch covers the whole batch.  Vectors are problem-major blocks of
     the finest-level length n."""
 
-    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, **options):
+    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, adv_kind=None, **options):
         cs = [0.0] * len(nus) if cs is None else list(cs)
-        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options)
+        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options, adv_kind)
 
     def solve(self, F, U, tol=1e-8, raise_on_error=True):
         return self._solve(F, U, tol, raise_on_error)
@@ -569,7 +578,7 @@ class MultiSolver:
     on their own streams inside one captured graph per step.  Vectors: one
     FP64 array, problem p at offsets[p] .. offsets[p + 1]."""
 
-    def __init__(self, meshes, nus, sigmas, cs=None, **options):
+    def __init__(self, meshes, nus, sigmas, cs=None, adv_kind=None, **options):
         self.nprob = len(meshes)
         cs = [0.0] * self.nprob if cs is None else list(cs)
         if not (len(nus) == len(sigmas) == len(cs) == self.nprob):
@@ -578,7 +587,8 @@ class MultiSolver:
         self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
         grids = (Grid * self.nprob)(*[Grid(d, N, L) for (d, N, L, _k) in self.meshes])
         ks = np.ascontiguousarray([m[3] for m in self.meshes], dtype=np.int32)
-        adv = (Advection * self.nprob)(*[Advection(1 if c != 0.0 else 0, float(c)) for c in cs])
+        self.adv_kind = adv_kind
+        adv = (Advection * self.nprob)(*[_advection(c, adv_kind) for c in cs])
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)

@@ -61,9 +61,26 @@ STEPS = (1, 2, 3, 4, 5, 6)
 COUNT_WEIGHT = 0.25  # loss weight of a step-count output relative to a logit
 
 
-def features(nu, sigma, c, N, k):
-    """(log10 nu / 2, log10 sigma / 4, |a| h / nu, k - 1.5), |a| = c / sqrt(2)."""
-    amag = abs(c) / math.sqrt(2.0)
+def manufactured_speed(d):
+    """max |u| of the manufactured velocity (u = curl of the sin^2 potential)
+    on the uniform sample grid the library uses (401^2 in 2D, 81^3 in 3D)."""
+    m = 400 if d == 2 else 80
+    t = np.linspace(0.0, 1.0, m + 1)
+    s, ds = np.sin(np.pi * t) ** 2, np.pi * np.sin(2 * np.pi * t)
+    if d == 2:
+        ux = s[None, :] * ds[:, None]          # [y, x]: s(x) s'(y)
+        uy = -ds[None, :] * s[:, None]
+        return float(np.sqrt(ux ** 2 + uy ** 2).max())
+    X, Y, Z = np.meshgrid(range(m + 1), range(m + 1), range(m + 1), indexing="ij")
+    ux = s[X] * ds[Y] * s[Z]
+    uy = s[X] * s[Y] * ds[Z] - ds[X] * s[Y] * s[Z]
+    return float(np.sqrt(2 * ux ** 2 + uy ** 2).max())
+
+
+def features(nu, sigma, c, N, k, adv_kind=None, d=2):
+    """(log10 nu / 2, log10 sigma / 4, |a| h / nu, k - 1.5) with |a| = max |a|:
+    c / sqrt(2) for the rotation, c max|u| for the manufactured velocity."""
+    amag = abs(c) * manufactured_speed(d) if adv_kind == 2 else abs(c) / math.sqrt(2.0)
     return np.array([math.log10(nu) / 2.0, math.log10(sigma) / 4.0, amag / (N * nu), k - 1.5], dtype=np.float64)
 
 
@@ -386,10 +403,11 @@ def rho_plain_for(model, feats, neighbours=8):
 def problem_features(solver):
     """Network inputs of every problem of a Solver, BatchSolver or
     MultiSolver (whose problems have their own grids and degrees)."""
+    kind = getattr(solver, "adv_kind", None)
     if hasattr(solver, "meshes"):
-        return np.array([features(nu, sg, c, m[1], m[3])
+        return np.array([features(nu, sg, c, m[1], m[3], kind, m[0])
                          for nu, sg, c, m in zip(solver.nus, solver.sigmas, solver.cs, solver.meshes)])
-    return np.array([features(nu, sg, c, solver.n_elem, solver.k)
+    return np.array([features(nu, sg, c, solver.n_elem, solver.k, kind, solver.dim)
                      for nu, sg, c in zip(solver.nus, solver.sigmas, solver.cs)])
 
 

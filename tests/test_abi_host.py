@@ -38,7 +38,7 @@ def test_error_conventions():
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, nu=0.0)
     with pytest.raises(dfmg.DfmgError):
-        dfmg.Solver(3, 8, 2, 1, c=1.0)     # rotation only in 2D
+        dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=3)   # no such advection
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(3, 8, 2, 1, precision=1)  # refinement path is 2D
     with pytest.raises(dfmg.DfmgError):
@@ -52,15 +52,19 @@ def test_error_conventions():
     s.close()
 
 
-CASES = [(2, 8, 1, 3, 0.0), (2, 8, 2, 3, 0.0), (2, 12, 2, 3, 0.0), (3, 4, 1, 2, 0.0), (2, 8, 2, 2, 5.0),
-         (2, 2, 1, 2, 0.0), (3, 4, 2, 2, 0.0)]
+# (d, N, k, L, c, advection kind): kind 1 rotation (2D and 3D), kind 2 the
+# manufactured velocity times c (the paper's Oseen problems)
+CASES = [(2, 8, 1, 3, 0.0, 0), (2, 8, 2, 3, 0.0, 0), (2, 12, 2, 3, 0.0, 0), (3, 4, 1, 2, 0.0, 0),
+         (2, 8, 2, 2, 5.0, 1), (2, 2, 1, 2, 0.0, 0), (3, 4, 2, 2, 0.0, 0), (3, 4, 1, 2, 3.0, 1),
+         (2, 8, 1, 3, 7.0, 2), (2, 12, 2, 3, 2.5, 2), (3, 4, 1, 2, 3.0, 2), (3, 4, 2, 2, 1.5, 2)]
 
 
-@pytest.mark.parametrize("d,N,k,L,c", CASES)
-def test_host_setup_matches_oracle(d, N, k, L, c):
+@pytest.mark.parametrize("d,N,k,L,c,kind", CASES)
+def test_host_setup_matches_oracle(d, N, k, L, c, kind):
+    from oracle.manufactured import manufactured_advection
     nu, sigma = 0.7, 3.0
-    s = dfmg.Solver(d, N, L, k, nu=nu, sigma=sigma, c=c)
-    adv = rotation_field(c) if c else None
+    s = dfmg.Solver(d, N, L, k, nu=nu, sigma=sigma, c=c, adv_kind=kind)
+    adv = {0: None, 1: rotation_field(c), 2: manufactured_advection(d, c)}[kind]
     h = Hierarchy(d, N, k, L, nu, sigma, adv)
     for l in range(L):
         rp, col, val = s.export_matrix(l)
@@ -125,7 +129,5 @@ def test_sweep_colours_match_oracle(d, N, k, L):
 def test_multiplicative_option_errors():
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, multiplicative=1, precision=1)   # FP64 cycles only
-    with pytest.raises(dfmg.DfmgError):
-        dfmg.Solver(3, 4, 2, 2, multiplicative=1)               # subdomains above 64 DOFs
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, multiplicative=2)

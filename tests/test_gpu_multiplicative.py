@@ -55,7 +55,8 @@ def divfree_start(h, seed):
                                 workloads.random_coefficients(disc.n_q, seed + 1))
 
 
-CASES = [(2, 16, 1, 3, 0.0), (2, 16, 2, 3, 0.0), (3, 8, 1, 3, 0.0), (2, 16, 2, 3, 20.0), (2, 12, 2, 3, 0.0)]
+CASES = [(2, 16, 1, 3, 0.0), (2, 16, 2, 3, 0.0), (3, 8, 1, 3, 0.0), (2, 16, 2, 3, 20.0), (2, 12, 2, 3, 0.0),
+         (3, 4, 2, 2, 0.0), (3, 2, 1, 2, 0.0)]
 
 
 @pytest.mark.parametrize("d,N,k,L,c", CASES)
@@ -96,7 +97,7 @@ def test_multiplicative_cycles_match_oracle(d, N, k, L, c, graph):
     s.close()
 
 
-@pytest.mark.parametrize("d,N,k,L,c", CASES[:4])
+@pytest.mark.parametrize("d,N,k,L,c", CASES[:4] + CASES[5:])
 def test_multiplicative_solve_matches_oracle(d, N, k, L, c):
     s, h, F = make(d, N, k, L, c=c, nu1=1, nu2=2)
     Ud = dev(np.zeros_like(F))

@@ -238,6 +238,21 @@ int dfmg_time_kernel(dfmg_ctx *ctx, int kernel, int level, int reps, double *ms_
  * order (lpr splits a row's dot product over lanes). */
 int dfmg_get_tuning(const dfmg_ctx *ctx, int *lpr, int *smoother);
 int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
+/* Tile shape of the form-4 local solves per level (n_levels entries each):
+ * bs threads per workgroup (64, 128, 256, 512: bs interior subdomains, or
+ * bs / tb boundary subdomains, per workgroup), ms how a workgroup reads an
+ * inverse all its interior subdomains share (0 scalar loads per wavefront,
+ * 1 staged in LDS per workgroup, 2 per-thread loads), tb threads per
+ * boundary subdomain (32 or 64).  Defaults 256, 0, 64.  All shapes give the
+ * same bits; a shape whose LDS would exceed 48 KB runs as the default.
+ * Errors: EINVAL. */
+int dfmg_get_tile_shape(const dfmg_ctx *ctx, int *bs, int *ms, int *tb);
+int dfmg_set_tile_shape(dfmg_ctx *ctx, const int *bs, const int *ms, const int *tb);
+/* Average milliseconds of one V-cycle (the kind the solves run: FP64, or the
+ * FP32 cycle of the refinement) captured as a hipGraph and replayed reps
+ * times, best of three rounds, on the context's level vectors, HIP events on
+ * the library stream.  Requires dfmg_bind; synchronizes. */
+int dfmg_time_cycle(dfmg_ctx *ctx, int reps, double *ms_out);
 /* Time every variant of every level on the device (reps launches each, HIP
  * events on the library stream) and keep the fastest; ms_out (nullable,
  * 2 * n_levels entries) receives the best residual and smoother times.
@@ -246,8 +261,10 @@ int dfmg_set_tuning(dfmg_ctx *ctx, const int *lpr, const int *smoother);
  * as one graph and replayed (as the solves run them) for every lanes-per-row
  * variant and smoother form of one level at a time, finest level first, the
  * others as chosen; a change is kept when the cycle gets faster by more than
- * 0.5% (best of three rounds of reps replays).  Requires dfmg_bind.  Leaves
- * the solver state unchanged. */
+ * 0.5% (best of three rounds of reps replays); on levels that run form 4,
+ * the same for the tile shape (workgroup size, then the reading of shared
+ * inverses, then the threads per boundary subdomain).  Requires dfmg_bind.
+ * Leaves the solver state unchanged. */
 int dfmg_autotune(dfmg_ctx *ctx, int reps, double *ms_out);
 
 /* ---- Learned per-level smoothing parameters ----

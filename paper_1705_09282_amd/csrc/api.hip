@@ -150,6 +150,7 @@ struct dfmg_ctx {
     SmallLevel<double> *small_d = nullptr;  // device level tables of that cycle
     SmallLevel<float> *small_f = nullptr;
     std::vector<int> lpr;        // per level: lanes per row of the residual kernel
+    std::vector<TileShape> tile; // per level: tile shape of the form-4 local solves
     std::vector<int> nu1l, nu2l; // per level: pre- and post-smoothing steps
     std::vector<double> eta_host;  // [problem][level]
     // Chebyshev damping schedule (when sched_on): the smoothing steps of
@@ -422,6 +423,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop,
     a.max_big = h.max_big;
     a.inv_w = h.inv_w;
     a.inv_ell = v.inv_ell;
+    a.tile = c->tile[l];
     if (tracks_potentials<T>(c)) {
         // the FP32 cycle of the refinement also accumulates the potentials of
         // its velocity corrections (forms 3 and 4 do; the others run as 4)
@@ -967,6 +969,7 @@ void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
         c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
     }
     c->small_top = 0;
+    c->tile.assign(L, TileShape{});
     c->nu1l.assign(L, o.nu1);
     c->nu2l.assign(L, o.nu2);
 }
@@ -1699,6 +1702,66 @@ int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     });
 }
 
+int dfmg_get_tile_shape(const dfmg_ctx *c, int *bs, int *ms, int *tb) {
+    if (!c || !bs || !ms || !tb) return fail(DFMG_EINVAL, "null argument");
+    for (int l = 0; l < c->L(); ++l) {
+        bs[l] = c->tile[l].bs;
+        ms[l] = c->tile[l].ms;
+        tb[l] = c->tile[l].tb;
+    }
+    return DFMG_OK;
+}
+
+int dfmg_set_tile_shape(dfmg_ctx *c, const int *bs, const int *ms, const int *tb) {
+    if (!c || !bs || !ms || !tb) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        const int L = c->L();
+        for (int l = 0; l < L; ++l) {
+            if (bs[l] != 64 && bs[l] != 128 && bs[l] != 256 && bs[l] != 512)
+                throw ArgError("threads per workgroup must be 64, 128, 256 or 512");
+            if (ms[l] < 0 || ms[l] > 2) throw ArgError("inverse reading must be 0, 1 or 2");
+            if (tb[l] != 32 && tb[l] != 64) throw ArgError("threads per boundary subdomain must be 32 or 64");
+        }
+        for (int l = 0; l < L; ++l) c->tile[l] = TileShape{bs[l], ms[l], tb[l]};
+        drop_graph(c);
+    });
+}
+
+int dfmg_time_cycle(dfmg_ctx *c, int reps, double *ms_out) {
+    if (!c || !ms_out || reps < 1) return fail(DFMG_EINVAL, "invalid argument");
+    return guarded([&] {
+        enter(c);
+        reset_flags(c);
+        hipGraph_t g;
+        hipGraphExec_t x;
+        HIPCHK(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+        if (c->mixed()) cycle_body<float>(c, false, true);
+        else cycle_body<double>(c, false, false);
+        HIPCHK(hipStreamEndCapture(c->s, &g));
+        HIPCHK(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(g));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipGraphLaunch(x, c->s));  // warm
+        double best = 1e30;
+        for (int round = 0; round < 3; ++round) {
+            HIPCHK(hipEventRecord(e0, c->s));
+            for (int i = 0; i < reps; ++i) HIPCHK(hipGraphLaunch(x, c->s));
+            HIPCHK(hipEventRecord(e1, c->s));
+            HIPCHK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, e0, e1));
+            best = std::min(best, (double)t / reps);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGraphExecDestroy(x));
+        *ms_out = best;
+        leave(c);
+    });
+}
+
 int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
     if (!c || reps < 1) return fail(DFMG_EINVAL, "invalid argument");
     return guarded([&] {
@@ -1837,6 +1900,24 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 }
                 c->smoother[l] = bs;
             }
+            // the tile shape of the form-4 local solves, where form 4 runs:
+            // workgroup size, then the reading of shared inverses, then the
+            // threads per boundary subdomain
+            const bool form4 = c->mixed() ? c->smoother[l] != 3 : c->smoother[l] == 4;
+            if (!form4) continue;
+            auto try_shape = [&](TileShape cand) {
+                const TileShape keep = c->tile[l];
+                c->tile[l] = cand;
+                const double t = cycle_ms();
+                if (t < 0.995 * cur) cur = t;
+                else c->tile[l] = keep;
+            };
+            for (int v : {64, 128, 256, 512})
+                if (v != c->tile[l].bs) try_shape(TileShape{v, c->tile[l].ms, c->tile[l].tb});
+            for (int v : {0, 1, 2})
+                if (v != c->tile[l].ms) try_shape(TileShape{c->tile[l].bs, v, c->tile[l].tb});
+            for (int v : {32, 64})
+                if (v != c->tile[l].tb) try_shape(TileShape{c->tile[l].bs, c->tile[l].ms, v});
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

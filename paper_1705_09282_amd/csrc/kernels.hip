@@ -19,137 +19,6 @@ __global__ __launch_bounds__(kBlock) void k_patch_solve(PatchArgsT<T> a) {
     a.delta[prob * a.sdelta + t] = patch_row(a.M + prob * a.sM + info.x, a.pdofs + info.y, info.z, a.r + prob * a.svec);
 }
 
-// Additive Schwarz, step 1, form 4.  Blocks below nb_small: one thread per
-// small subdomain (at most kSmallPatch DOFs, the interior ones); its DOFs are
-// stored subdomain-minor, so the gather coalesces, and its rows of
-// M_p E_p r are written row-major over the small subdomains (coalesced
-// stores).  The other blocks: one wavefront per remaining subdomain; its lanes
-// gather the residual entries into LDS while each lane loads its row of the
-// local inverse (or of the potential map) into registers, then lane t sums
-// row t.  Every row is summed in the order of k_patch_solve, so the
-// corrections agree bit for bit; k_dof_update reads them through the
-// relabelled inverse map.  No load waits on more than one earlier load.
-template <bool EXIT, class T>
-__global__ __launch_bounds__(kBlock) void k_patch_solve_small(PatchArgsT<T> a, int nb_small) {
-    const int prob = blockIdx.y;
-    const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the stores
-    if (EXIT && halt) return;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const T *r = a.r + prob * a.svec;
-    T *delta = a.delta + prob * a.sdelta;
-    if (b < nb_small) {
-        const int q = b * kBlock + threadIdx.x;
-        if (q >= a.nsmall) return;
-        const int4 si = a.sinfo[(int64_t)prob * a.nsmall + q];
-        const int nn = si.x;
-        T rv[kSmallPatch];
-#pragma unroll
-        for (int c = 0; c < kSmallPatch; ++c) {  // padded by repetition: always a valid index
-            const T x = r[a.small_dofs[(int64_t)c * a.nsmall + q]];
-            rv[c] = c < nn ? x : T(0);
-        }
-        const T *m = a.M + prob * a.sM + si.y;
-        const int m0 = __builtin_amdgcn_readfirstlane(si.y);
-        if (__all(si.y == m0) && __builtin_amdgcn_readfirstlane(nn) == kSmallPatch) {
-            // the wave shares one inverse (the interior class): read it with
-            // scalar loads instead of one vector load per lane
-            const T *mu = a.M + prob * a.sM + m0;
-            T out[kSmallPatch];
-#pragma unroll
-            for (int row = 0; row < kSmallPatch; ++row) {
-                T acc = 0;
-#pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c) acc = fma(scalar_ld(mu + row * kSmallPatch + c), rv[c], acc);
-                out[row] = acc;
-            }
-            if (!halt)
-#pragma unroll
-                for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
-        } else if (nn == kSmallPatch) {
-            T out[kSmallPatch];
-#pragma unroll
-            for (int row = 0; row < kSmallPatch; ++row) {
-                T acc = 0;
-#pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
-                out[row] = acc;
-            }
-            if (!halt)
-#pragma unroll
-                for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
-        } else {
-            for (int row = 0; row < nn; ++row) {
-                const T v = small_row(m + row * nn, nn, rv);
-                if (!halt) delta[(int64_t)row * a.nsmall + q] = v;
-            }
-        }
-        if (a.psi) {  // the subdomain's single potential
-            const int z0 = __builtin_amdgcn_readfirstlane(si.z);
-            T v;
-            if (__all(si.z == z0) && __builtin_amdgcn_readfirstlane(nn) == kSmallPatch) {
-                const T *qu = a.Q + prob * a.sQ + z0;
-                v = 0;
-#pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c) v = fma(scalar_ld(qu + c), rv[c], v);
-            } else {
-                v = small_row(a.Q + prob * a.sQ + si.z, nn, rv);
-            }
-            if (!halt) a.beta[prob * a.nbeta + si.w] = v;
-        }
-        return;
-    }
-    extern __shared__ unsigned char smem[];
-    T *sr = reinterpret_cast<T *>(smem) + (threadIdx.x >> 6) * (a.max_big > kBigRegs ? a.max_big : kBigRegs);
-    const int lane = threadIdx.x & 63;
-    const int sb = __builtin_amdgcn_readfirstlane((b - nb_small) * (kBlock / 64) + (int)(threadIdx.x >> 6));
-    const bool live = sb < a.nbsub;
-    const int4 bm = live ? a.bmesh[sb] : make_int4(0, 0, 0, 0);
-    const int2 bp = live ? a.binfo[(int64_t)prob * a.nbsub + sb] : make_int2(0, 0);
-    const int base = bm.x, nn = bm.y, rows = nn + (a.psi ? bm.w : 0);
-    const T *Mp = a.M + prob * a.sM + bp.x;
-    const T *Qp = a.Q ? a.Q + prob * a.sQ + bp.y : nullptr;
-    // lane t's first row: its coefficients into registers (independent of r;
-    // unconditional loads, clamped to the row, so none waits for another)
-    const int t = lane;
-    const T *mr = t >= rows ? Mp : (t < nn ? Mp + (int64_t)t * nn : Qp + (int64_t)(t - nn) * nn);
-    const int last = nn > 0 ? nn - 1 : 0;
-    T mv[kBigRegs];
-#pragma unroll
-    for (int c = 0; c < kBigRegs; ++c) mv[c] = T(0);
-    if (t < rows) {
-#pragma unroll
-        for (int c0 = 0; c0 < kBigRegs; c0 += 8) {
-            if (c0 < nn)  // wave-uniform: only the chunks the row has
-#pragma unroll
-                for (int c = c0; c < c0 + 8; ++c) mv[c] = mr[c < nn ? c : last];  // past nn: times sr = 0
-        }
-    }
-    // the residual entries, zero up to kBigRegs (the padded terms, finite
-    // coefficients times zero, add zero)
-    const int span = nn > kBigRegs ? nn : kBigRegs;
-    for (int c = lane; c < span; c += 64) sr[c] = c < nn ? r[a.pdofs[base + c]] : T(0);
-    __syncthreads();
-    if (t < rows) {
-        T acc = 0;
-#pragma unroll
-        for (int c = 0; c < kBigRegs; ++c) acc = fma(mv[c], sr[c], acc);
-        for (int c = kBigRegs; c < nn; ++c) acc = fma(mr[c], sr[c], acc);
-        if (!halt) {
-            if (t < nn) delta[(int64_t)kSmallPatch * a.nsmall + base + t] = acc;
-            else a.beta[prob * a.nbeta + bm.z + (t - nn)] = acc;
-        }
-    }
-    for (int u = t + 64; u < rows; u += 64) {  // subdomains of more than 64 rows
-        const T *ur = u < nn ? Mp + (int64_t)u * nn : Qp + (int64_t)(u - nn) * nn;
-        T acc = 0;
-        for (int c = 0; c < nn; ++c) acc = fma(ur[c], sr[c], acc);
-        if (!halt) {
-            if (u < nn) delta[(int64_t)kSmallPatch * a.nsmall + base + u] = acc;
-            else a.beta[prob * a.nbeta + bm.z + (u - nn)] = acc;
-        }
-    }
-}
-
 // Additive Schwarz, step 2: U_j += eta * sum of the corrections of every
 // subdomain holding DOF j (fixed order, no atomics), from the fixed-width
 // inverse map padded to WB columns (WB == 0: walk inv_ptr).  Blocks from nbu
@@ -250,20 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_schwarz_fused(PatchArgsT<T> a) {
         acc += patch_row(M + info.x, a.pdofs + info.y, info.z, r);
     }
     U[j] = fma(eta, acc, u);
-}
-
-template <class T>
-void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s) {
-    constexpr int waves = kBlock / 64;
-    const int nbs = blocks_for(a.nsmall), nbb = (a.nbsub + waves - 1) / waves;
-    const size_t lds = (size_t)waves * std::max(a.max_big, kBigRegs) * sizeof(T);
-    if (a.exit_early)
-        hipLaunchKernelGGL((k_patch_solve_small<true, T>), dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds, s,
-                           a, nbs);
-    else
-        hipLaunchKernelGGL((k_patch_solve_small<false, T>), dim3(padded_grid(nbs + nbb), a.nprob), dim3(kBlock), lds,
-                           s, a, nbs);
-    launch_dof_update<T>(a, s);
 }
 
 template <class T>
@@ -553,8 +408,8 @@ void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
 template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);
 template void launch_schwarz_gather<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_fused<double>(const PatchArgsT<double> &, hipStream_t);
-template void launch_schwarz_small<double>(const PatchArgsT<double> &, hipStream_t);
-template void launch_schwarz_small<float>(const PatchArgsT<float> &, hipStream_t);
+template void launch_dof_update<double>(const PatchArgsT<double> &, hipStream_t);
+template void launch_dof_update<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_fused<float>(const PatchArgsT<float> &, hipStream_t);
 template void launch_schwarz_colour<double>(const PatchArgsT<double> &, const int32_t *, int, hipStream_t);
 template void launch_schwarz_colour<float>(const PatchArgsT<float> &, const int32_t *, int, hipStream_t);

@@ -64,6 +64,16 @@ struct SpmvArgsT {
 };
 using SpmvArgs = SpmvArgsT<double>;
 
+// Tile shape of the form-4 local solves (k_patch_solve_small): bs threads per
+// workgroup (bs small subdomains, or bs / tb boundary subdomains, per
+// workgroup); ms how a workgroup reads an inverse that all its small
+// subdomains share (0: scalar loads per wavefront, 1: staged in LDS per
+// workgroup, 2: per-thread vector loads); tb threads per boundary subdomain.
+// Every shape sums in the same order, so all give the same bits.
+struct TileShape {
+    int bs = 256, ms = 0, tb = 64;
+};
+
 template <class T>
 struct PatchArgsT {
     int n;              // DOFs of the level
@@ -111,6 +121,7 @@ struct PatchArgsT {
     // qinv_w == 0: walk qinv_ptr)
     const int32_t *inv_ell, *qinv_ell;
     int inv_w, qinv_w;
+    TileShape tile;         // form 4 only
 };
 using PatchArgs = PatchArgsT<double>;
 
@@ -153,9 +164,13 @@ template <class T>
 void launch_spmv(int d, int k, int lpr, const SpmvArgsT<T> &a, hipStream_t s);
 template <class T>
 void launch_schwarz_gather(const PatchArgsT<T> &a, hipStream_t s);
-// two passes, small subdomains solved by one thread each
+// two passes, small subdomains solved by one thread each, in the tile shape
+// of a.tile (see TileShape)
 template <class T>
 void launch_schwarz_small(const PatchArgsT<T> &a, hipStream_t s);
+// the second pass alone: U_j += eta * (sum of the corrections of DOF j)
+template <class T>
+void launch_dof_update(const PatchArgsT<T> &a, hipStream_t s);
 // one pass: every DOF recomputes the local-solve rows it receives (no buffer)
 template <class T>
 void launch_schwarz_fused(const PatchArgsT<T> &a, hipStream_t s);

@@ -83,6 +83,9 @@ SIGNATURES = [
     ("dfmg_time_kernel", c_int, [c_void_p, c_int, c_int, c_int, c_dblp]),
     ("dfmg_get_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_set_tuning", c_int, [c_void_p, c_i32p, c_i32p]),
+    ("dfmg_get_tile_shape", c_int, [c_void_p, c_i32p, c_i32p, c_i32p]),
+    ("dfmg_set_tile_shape", c_int, [c_void_p, c_i32p, c_i32p, c_i32p]),
+    ("dfmg_time_cycle", c_int, [c_void_p, c_int, c_dblp]),
     ("dfmg_autotune", c_int, [c_void_p, c_int, c_dblp]),
     ("dfmg_mlp_forward", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("dfmg_mlp_grad", c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
@@ -263,6 +266,7 @@ class Solver:
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)
+        self._options = dict(options)
         ctx = c_void_p()
         self._ctx = c_void_p()
         _check(lib().dfmg_batch_setup(self.nprob, ctypes.byref(g), k, _ptr(nu_a, ctypes.c_double),
@@ -427,27 +431,62 @@ class Solver:
         lpr = np.zeros(self.n_levels, np.int32)
         sm = np.zeros(self.n_levels, np.int32)
         _check(lib().dfmg_get_tuning(self._ctx, _ptr(lpr, ctypes.c_int32), _ptr(sm, ctypes.c_int32)))
-        return {"lpr": lpr.tolist(), "smoother": sm.tolist()}
+        out = {"lpr": lpr.tolist(), "smoother": sm.tolist()}
+        out["tile"] = self.get_tile_shape()
+        return out
 
-    def set_tuning(self, lpr, smoother):
+    def set_tuning(self, lpr, smoother, tile=None):
         lpr = np.ascontiguousarray(lpr, dtype=np.int32)
         sm = np.ascontiguousarray(smoother, dtype=np.int32)
         if lpr.size != self.n_levels or sm.size != self.n_levels:
             raise ValueError("one entry per level")
         _check(lib().dfmg_set_tuning(self._ctx, _ptr(lpr, ctypes.c_int32), _ptr(sm, ctypes.c_int32)))
+        if tile is not None:
+            self.set_tile_shape(tile["bs"], tile["ms"], tile["tb"])
+
+    def get_tile_shape(self):
+        """Tile shape of the form-4 local solves per level: threads per
+        workgroup (bs), reading of shared inverses (ms), threads per boundary
+        subdomain (tb)."""
+        a = [np.zeros(self.n_levels, np.int32) for _ in range(3)]
+        _check(lib().dfmg_get_tile_shape(self._ctx, *[_ptr(x, ctypes.c_int32) for x in a]))
+        return {"bs": a[0].tolist(), "ms": a[1].tolist(), "tb": a[2].tolist()}
+
+    def set_tile_shape(self, bs, ms, tb):
+        a = [np.ascontiguousarray(x, dtype=np.int32) for x in (bs, ms, tb)]
+        if any(x.size != self.n_levels for x in a):
+            raise ValueError("one entry per level")
+        _check(lib().dfmg_set_tile_shape(self._ctx, *[_ptr(x, ctypes.c_int32) for x in a]))
+
+    def time_cycle(self, reps=20):
+        """Milliseconds of one captured V-cycle (best of three rounds)."""
+        out = c_double()
+        _check(lib().dfmg_time_cycle(self._ctx, int(reps), ctypes.byref(out)))
+        return out.value
+
+    def tuning_key(self):
+        """Cache key of the tuned variants: dimension, degree, grid, levels,
+        precision, smoother and batch size."""
+        o = self._options
+        return (f"d{self.dim}-k{self.k}-N{self.n_elem}-L{self.n_levels}-p{o.get('precision', 0)}"
+                f"-m{o.get('multiplicative', 0)}-b{self.nprob}")
 
     def autotune(self, reps=20, cache=None, key=None):
-        """Pick the fastest kernel variant per level by timing on the device.
-        With ``cache`` (a JSON file path) and ``key``, a stored choice is
-        reused instead of timing, and a new choice is stored."""
+        """Pick the fastest kernel variant and tile shape per level by timing
+        on the device.  With ``cache`` (a JSON file path) a stored choice
+        under ``key`` (default: tuning_key(), the dimension, degree, grid,
+        levels, precision, smoother and batch size) is reused instead of
+        timing, and a new choice is stored."""
         import json
+        if cache and not key:
+            key = self.tuning_key()
         if cache and key and os.path.exists(cache):
             try:
                 stored = json.load(open(cache)).get(key)
             except ValueError:
                 stored = None
             if stored:
-                self.set_tuning(stored["lpr"], stored["smoother"])
+                self.set_tuning(stored["lpr"], stored["smoother"], stored.get("tile"))
                 return dict(stored, cached=True)
         ms = np.zeros(2 * self.n_levels)
         _check(lib().dfmg_autotune(self._ctx, int(reps), _ptr(ms, ctypes.c_double)))
@@ -460,7 +499,7 @@ class Solver:
                     data = json.load(open(cache))
                 except ValueError:
                     data = {}
-            data[key] = {"lpr": out["lpr"], "smoother": out["smoother"], "ms": out["ms"]}
+            data[key] = {"lpr": out["lpr"], "smoother": out["smoother"], "tile": out["tile"], "ms": out["ms"]}
             with open(cache, "w") as f:
                 json.dump(data, f, indent=1)
         out["cached"] = False

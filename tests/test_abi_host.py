@@ -103,12 +103,19 @@ def test_tuning_validation():
     from paper_1705_09282_amd.dfmg import Solver, DfmgError
     s = Solver(2, 32, 4, 1)
     s.set_tuning([1, 2, 4, 1], [1, 5, 5, 3])
-    assert s.get_tuning() == {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3]}
+    tile = {"bs": [256] * 4, "ms": [0] * 4, "tb": [64] * 4}
+    want = {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3], "tile": tile}
+    assert s.get_tuning() == want
     for lpr, sm in (([3, 1, 1, 1], [1, 1, 1, 1]), ([1, 1, 1, 1], [1, 1, 5, 1]),
                     ([1, 1, 1, 1], [1, 5, 5, 5]), ([1, 1, 1, 1], [1, 6, 1, 1])):
         with pytest.raises(DfmgError):
             s.set_tuning(lpr, sm)
-    assert s.get_tuning() == {"lpr": [1, 2, 4, 1], "smoother": [1, 5, 5, 3]}
+    for bs, ms, tb in (([100] * 4, [0] * 4, [64] * 4), ([64] * 4, [3] * 4, [64] * 4), ([64] * 4, [0] * 4, [16] * 4)):
+        with pytest.raises(DfmgError):
+            s.set_tile_shape(bs, ms, tb)
+    assert s.get_tuning() == want
+    s.set_tile_shape([64, 128, 256, 512], [0, 1, 2, 0], [32, 64, 32, 64])
+    assert s.get_tile_shape() == {"bs": [64, 128, 256, 512], "ms": [0, 1, 2, 0], "tb": [32, 64, 32, 64]}
     s.close()
 
 

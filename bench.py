@@ -159,6 +159,44 @@ def paper_oseen_legs(dev, steps=3, warmup=1):
     return out
 
 
+def stokes3d_legs(dev, steps=3, warmup=1):
+    """The 3D workload (context, not the metric): 3D generalized Stokes,
+    k=1, 32^3 elements, 4 grids, nu = 1, the eight seeded log-uniform sigma
+    as one batch, solved from U = 0 to 1e-8: plain FP64 with the fixed
+    damping V(2,2), and FP32 V-cycles in FP64 refinement with the Chebyshev
+    schedule (3D default ratio, V(6,6)) and autotuned kernels and tiles."""
+    import torch
+    import workloads
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    sig = workloads.stokes3d_sigmas()
+    out = {"workload": "stokes3d: 3D generalized Stokes, k=1, 32^3, 4 grids, nu=1, 8 seeded sigma in "
+                       "[1e-2, 1e4], tol 1e-8, U0=0"}
+    for name, prec, sched in (("fp64_fixed_damping", 0, False), ("fp32_refined_chebyshev_v66", 1, True)):
+        b = BatchSolver(3, 32, 4, 1, [1.0] * len(sig), list(sig), precision=prec, max_cycles=400).bind(dev)
+        b.autotune(reps=10)
+        if sched:
+            b.set_smoothing([6, 6, 6], [6, 6, 6])
+            b.set_chebyshev()
+        F = torch.tensor(b.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        for _ in range(warmup):
+            U.zero_()
+            b.solve(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U.zero_()
+            st = b.solve(F, U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        dofs = len(sig) * (b.n - 1)
+        out[name] = {"ms_per_solve": 1e3 * dt, "dofs_per_s": dofs / dt, "cycles_per_sigma": [x["cycles"] for x in st],
+                     "max_div_norm": float(b.div_norm(U).max())}
+        b.close()
+    out["speedup"] = out["fp64_fixed_damping"]["ms_per_solve"] / out["fp32_refined_chebyshev_v66"]["ms_per_solve"]
+    return out
+
+
 def roofline_hbm(dev, reps=50):
     """The FP32 residual on an operator that cannot stay in the 256 MB
     Infinity Cache: one problem of the same workload on 1024^2 elements
@@ -412,6 +450,8 @@ def main():
     if not args.no_paper_legs:
         print("[bench] the paper's Oseen problems (context)", file=sys.stderr, flush=True)
         line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
+        print("[bench] the 3D workload (context)", file=sys.stderr, flush=True)
+        line["config"]["stokes3d"] = stokes3d_legs(dev)
     if not args.no_cpu_baseline and args.n_elem == 256 and args.levels == 6:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"], line["config"]["vel_rel_err_vs_oracle_sigma1"] = cpu_baseline(args.tol, U32_sigma1)

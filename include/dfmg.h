@@ -80,7 +80,7 @@ typedef struct {
     int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
     int nu2;              /* post-smoothing steps per level                     */
     double eta;           /* fixed additive-Schwarz damping; <= 0: default      */
-    int precision;        /* 0: FP64 V-cycles; 1 (dim 2): solve by FP64 iterative
+    int precision;        /* 0: FP64 V-cycles; 1: solve by FP64 iterative
                              refinement around FP32 V-cycles (see dfmg_solve)    */
     int smoother;         /* 0 auto, 1 two-pass gather, 2 coloured scatter, 3 one-pass,
                              4 two-pass with one thread per small subdomain */
@@ -182,11 +182,13 @@ int dfmg_get_smoothing(const dfmg_ctx *ctx, int *nu1_host, int *nu2_host);
  * EDIVERGED (worst over the batch), ESTATE, EHIP.
  * With precision 1 each step computes r = F - K U in FP64, applies
  * inner_cycles V-cycles in FP32 (FP32 values, FP32 accumulation, FP64 coarse
- * solve) to K dU = r from dU = 0 that also accumulate the streamfunction
+ * solve) to K dU = r from dU = 0 that also accumulate the potential
  * coefficients psi of dU's velocity (every local velocity correction is the
- * curl of local streamfunctions, the reduced subdomain problem; prolongation
- * and the coarse solve carry psi along), and updates u += curl psi,
- * p += dU_p in FP64, so u stays divergence-free to FP64 rounding.  The FP32
+ * curl of local streamfunctions (2D) or vector potentials (3D), the reduced
+ * subdomain problem; in 3D the minimum-norm local potentials, since the
+ * curl has gradients in its kernel near the boundary; prolongation and the
+ * coarse solve carry psi along), and updates u += curl psi, p += dU_p in
+ * FP64, so u stays divergence-free to FP64 rounding.  The FP32
  * cycle runs smoother form 3 where tuned so and form 4 otherwise.  Stats
  * count refinement steps as cycles. */
 int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, dfmg_stats *st);
@@ -406,7 +408,7 @@ int dfmg_manufactured_rhs(const dfmg_ctx *ctx, double *F_host);
  * whole step is captured once as one hipGraph with a branch per group.
  * Vectors: problem p's F and U start at offset[p] of one FP64 device array of
  * offset[nprob] entries (caller order; offsets from dfmg_multi_layout).
- * Options apply to every group (precision 1 needs dim 2).  Errors: EINVAL. */
+ * Options apply to every group.  Errors: EINVAL. */
 typedef struct dfmg_multi dfmg_multi;
 int dfmg_multi_setup(int nprob, const dfmg_grid *grids, const int *k, const double *nu, const double *sigma,
                      const dfmg_advection *adv, const dfmg_options *opt, dfmg_multi **out);

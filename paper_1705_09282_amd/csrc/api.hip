@@ -733,10 +733,12 @@ void refine_body(dfmg_ctx *c) {
     DevLevel &v = c->dl[L - 1];
     for (int i = 0; i < c->opt.inner_cycles; ++i) cycle_body<float>(c, false, i == 0);
     RefineArgs a{};
+    a.d = c->S().pb.d;
     a.N = c->S().pb.N;
     a.k = c->S().pb.k;
     a.off_uy = h.off[1];
-    a.off_p = h.off[2];
+    a.off_uz = h.off[a.d - 1];
+    a.off_p = h.off[a.d];
     a.n = h.n;
     a.X = v.f.U;
     a.dcoef = c->dcoef;
@@ -747,7 +749,7 @@ void refine_body(dfmg_ctx *c) {
     a.stop = c->stopw;
     a.nprob = c->np;
     a.exit_early = c->exit_mode;
-    launch_refine_update_2d(a, c->s);
+    launch_refine_update(a, c->s);
     refine_residual(c);
 }
 
@@ -941,7 +943,6 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 1 || o.cycles_per_check < 1) throw ArgError("invalid options");
     if (o.max_cycles > DFMG_MAX_HISTORY - 2) throw ArgError("max_cycles too large");
     if (o.precision != 0 && o.precision != 1) throw ArgError("precision must be 0 or 1");
-    if (o.precision == 1 && dim != 2) throw ArgError("FP32 refinement is implemented for dim 2");
     if (o.inner_cycles < 1) throw ArgError("inner_cycles must be >= 1");
     if (o.smoother < 0 || o.smoother > 4) throw ArgError("smoother must be 0 .. 4");
     if (o.eta >= 1.0) throw ArgError("eta must be < 1");

@@ -401,8 +401,63 @@ __global__ void k_curl_update_2d(RefineArgs a) {
     if (!halt) a.U[prob * a.svec + g] = u + du;
 }
 
-void launch_refine_update_2d(const RefineArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n), a.nprob), dim3(kBlock), 0, s, a);
+// 3D: U_g += (curl psi)_g on the velocity rows (u_x = d_y psi_z - d_z psi_y,
+// u_y = d_z psi_x - d_x psi_z, u_z = d_x psi_y - d_y psi_x), U_g += X_g on the
+// pressure rows.  Component o of psi has N + k functions in direction o
+// (degree k, all kept) and N + k - 1 in the others (degree k + 1 without the
+// end functions), stored component after component, x fastest; the
+// derivative of a degree-(k+1) spline expansion in direction j at
+// degree-k index t is c_{t+1} (psi(t + e_j) - psi(t)), with the removed end
+// functions zero.
+__global__ void k_curl_update_3d(RefineArgs a) {
+    const int prob = blockIdx.y;
+    const int halt = stop_flag(a.stop, prob);  // block-uniform; gates the store
+    if (a.exit_early && halt) return;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.n) return;
+    const int nq = a.N + a.k, m = nq - 1;
+    const int64_t ncomp = (int64_t)nq * m * m;
+    const double *P = a.psi + prob * a.spsi;
+    // potential o at true index (t0, t1, t2); zero outside the kept box
+    auto psi = [&](int o, int t0, int t1, int t2) -> double {
+        const int t[3] = {t0, t1, t2};
+        int64_t idx = 0, stride = 1;
+        for (int j = 0; j < 3; ++j) {
+            const int lo = j == o ? 0 : 1;
+            if (t[j] < lo || t[j] >= nq) return 0.0;
+            idx += (int64_t)(t[j] - lo) * stride;
+            stride *= j == o ? nq : m;
+        }
+        return P[o * ncomp + idx];
+    };
+    double du;
+    if (g < a.off_p) {
+        const int R = g < a.off_uy ? 0 : (g < a.off_uz ? 1 : 2);
+        int64_t l = g - (R == 0 ? 0 : (R == 1 ? a.off_uy : a.off_uz));
+        int t[3];
+        for (int j = 0; j < 3; ++j) {  // velocity component R keeps N + k - 1 functions in direction R
+            const int nb = j == R ? m : nq;
+            t[j] = (int)(l % nb) + (j == R ? 1 : 0);
+            l /= nb;
+        }
+        auto d = [&](int o, int dir) {
+            int u[3] = {t[0], t[1], t[2]};
+            u[dir] += 1;
+            return a.dcoef[t[dir] + 1] * (psi(o, u[0], u[1], u[2]) - psi(o, t[0], t[1], t[2]));
+        };
+        if (R == 0) du = d(2, 1) - d(1, 2);
+        else if (R == 1) du = d(0, 2) - d(2, 0);
+        else du = d(1, 0) - d(0, 1);
+    } else {
+        du = (double)a.X[prob * a.svec + g];
+    }
+    const double u = a.U[prob * a.svec + g];
+    if (!halt) a.U[prob * a.svec + g] = u + du;
+}
+
+void launch_refine_update(const RefineArgs &a, hipStream_t s) {
+    if (a.d == 3) hipLaunchKernelGGL(k_curl_update_3d, dim3(blocks_for(a.n), a.nprob), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_curl_update_2d, dim3(blocks_for(a.n), a.nprob), dim3(kBlock), 0, s, a);
 }
 
 template void launch_schwarz_gather<double>(const PatchArgsT<double> &, hipStream_t);

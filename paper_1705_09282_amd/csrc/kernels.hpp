@@ -276,10 +276,10 @@ void launch_sub_scalar(int n, double *x, int64_t sx, const double *m, int nprob,
 // FP64 update of the refinement loop (2D): U += [curl psi; X_p] with psi the
 // streamfunction coefficients of the FP32 cycle's velocity correction.
 struct RefineArgs {
-    int N, k;
-    int64_t off_uy, off_p, n;  // block offsets of the finest level
+    int d, N, k;
+    int64_t off_uy, off_uz, off_p, n;  // block offsets of the finest level (off_uz = off_p in 2D)
     const float *X;            // FP32 correction (pressure part used)
-    const double *psi;         // (N+k-1)^2 potentials per problem
+    const double *psi;         // potentials per problem: 2D (N+k-1)^2; 3D three components, see k_curl_update_3d
     const double *dcoef;
     double *U;
     int64_t svec, spsi;
@@ -287,7 +287,7 @@ struct RefineArgs {
     int nprob;
     int exit_early;
 };
-void launch_refine_update_2d(const RefineArgs &a, hipStream_t s);
+void launch_refine_update(const RefineArgs &a, hipStream_t s);
 
 // div-norm pieces (finest grid, one problem)
 struct DivArgs {

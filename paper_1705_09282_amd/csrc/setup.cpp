@@ -589,6 +589,7 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
     L.pdofs.clear();
     L.color.clear();
     L.mcolor.clear();
+    L.ppot.clear();
     for (int o = 0; o < (int)pots.size(); ++o) {
         const PB &p = pots[o];
         for (int a2 = p.lo[2]; a2 < p.hi[2]; ++a2)
@@ -630,6 +631,7 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
                                                                 (int64_t)L.nb[b][0] * (i1 + (int64_t)L.nb[b][1] * i2)));
                     }
                     L.pptr.push_back((int32_t)L.pdofs.size());
+                    L.ppot.insert(L.ppot.end(), {o, a[0], a[1], a[2]});
                     int col = o;
                     for (int j = 0; j < d; ++j) col = col * (k + 1) + a[j] % (k + 1);
                     L.color.push_back(col);
@@ -817,6 +819,37 @@ static void left_solve(int r, int p, int n, const std::vector<double> &C, const 
         }
 }
 
+// the inverse map of the local potentials (for each potential its beta
+// entries, subdomain ascending) and the split into subdomains with a single
+// local potential (one thread each) and the others
+static void finish_potential_maps(HostLevel &L) {
+    // for each potential the beta entries landing on it, subdomain ascending
+    L.qinv_ptr.assign(L.n_psi + 1, 0);
+    for (int32_t b : L.qpsi) L.qinv_ptr[b + 1]++;
+    for (int64_t b = 0; b < L.n_psi; ++b) L.qinv_ptr[b + 1] += L.qinv_ptr[b];
+    L.qinv_pos.assign(L.qpsi.size(), 0);
+    std::vector<int32_t> fp(L.qinv_ptr.begin(), L.qinv_ptr.end() - 1);
+    for (int64_t e = 0; e < (int64_t)L.qpsi.size(); ++e) L.qinv_pos[fp[L.qpsi[e]]++] = (int32_t)e;
+    // one thread per small subdomain computes its single beta entry; every
+    // other subdomain's entries go one per thread
+    std::vector<int32_t> small;
+    L.big_beta.clear();
+    std::vector<char> is_small(L.n_patch, 0);
+    for (int32_t p : L.small_list) {
+        if (L.qptr[p + 1] - L.qptr[p] == 1) {
+            small.push_back(p);
+            is_small[p] = 1;
+        } else {
+            for (int32_t t = L.pptr[p]; t < L.pptr[p + 1]; ++t) L.big_ent.push_back(t);
+        }
+    }
+    L.small_list = small;
+    std::sort(L.big_ent.begin(), L.big_ent.end());
+    for (int64_t i = 0; i < L.n_patch; ++i)
+        if (!is_small[i])
+            for (int32_t e = L.qptr[i]; e < L.qptr[i + 1]; ++e) L.big_beta.push_back(e);
+}
+
 static void build_potential_maps(const Problem &pb, HostLevel &L) {
     const int k = pb.k, q = k + 1, N = L.N, m = N + k - 1;
     L.n_psi = (int64_t)m * m;
@@ -890,31 +923,7 @@ static void build_potential_maps(const Problem &pb, HostLevel &L) {
         L.qpsi.insert(L.qpsi.end(), loc.begin(), loc.end());
         L.qptr.push_back((int32_t)L.qpsi.size());
     }
-    // for each potential the beta entries landing on it, subdomain ascending
-    L.qinv_ptr.assign(L.n_psi + 1, 0);
-    for (int32_t b : L.qpsi) L.qinv_ptr[b + 1]++;
-    for (int64_t b = 0; b < L.n_psi; ++b) L.qinv_ptr[b + 1] += L.qinv_ptr[b];
-    L.qinv_pos.assign(L.qpsi.size(), 0);
-    std::vector<int32_t> fp(L.qinv_ptr.begin(), L.qinv_ptr.end() - 1);
-    for (int64_t e = 0; e < (int64_t)L.qpsi.size(); ++e) L.qinv_pos[fp[L.qpsi[e]]++] = (int32_t)e;
-    // one thread per small subdomain computes its single beta entry; every
-    // other subdomain's entries go one per thread
-    std::vector<int32_t> small;
-    L.big_beta.clear();
-    std::vector<char> is_small(L.n_patch, 0);
-    for (int32_t p : L.small_list) {
-        if (L.qptr[p + 1] - L.qptr[p] == 1) {
-            small.push_back(p);
-            is_small[p] = 1;
-        } else {
-            for (int32_t t = L.pptr[p]; t < L.pptr[p + 1]; ++t) L.big_ent.push_back(t);
-        }
-    }
-    L.small_list = small;
-    std::sort(L.big_ent.begin(), L.big_ent.end());
-    for (int64_t i = 0; i < L.n_patch; ++i)
-        if (!is_small[i])
-            for (int32_t e = L.qptr[i]; e < L.qptr[i + 1]; ++e) L.big_beta.push_back(e);
+    finish_potential_maps(L);
 }
 
 // potential prolongation: Kronecker product of the 1D refinement of the
@@ -956,6 +965,334 @@ static void build_coarse_potentials(const Problem &pb, HostLevel &L) {
         for (auto &e : row) C[(size_t)r * np + e.first] += e.second;
     }
     left_solve(nv, np, n, C, L.Kinv.data(), L.Q0);
+}
+
+// ---------------------------------------------- potential form (3D, FP32 cycle)
+//
+// Vector potential component o has degree k in direction o (all N + k
+// functions kept) and k + 1 in the others (the two end functions removed:
+// psi x n = 0); stored component after component, x fastest over the kept
+// box.  u = curl psi:
+//   u_x = d_y psi_z - d_z psi_y,  u_y = d_z psi_x - d_x psi_z,  u_z = d_x psi_y - d_y psi_x,
+// with the derivative of a degree-(k+1) spline in degree-k splines as in
+// deriv_coef.  Local maps use the pseudo-inverse of the local curl: near the
+// boundary a subdomain's local potentials can contain gradients (the kernel
+// of the curl), and the minimum-norm potentials of a local velocity
+// correction are as good as any (only their curl enters the velocity).
+
+struct PotBox {
+    int lo[3], hi[3];
+    int64_t off;
+};
+
+static void pot_boxes(int N, int k, PotBox b[3]) {
+    int64_t off = 0;
+    for (int o = 0; o < 3; ++o) {
+        int64_t n = 1;
+        for (int j = 0; j < 3; ++j) {
+            b[o].lo[j] = j == o ? 0 : 1;
+            b[o].hi[j] = N + k;
+            n *= b[o].hi[j] - b[o].lo[j];
+        }
+        b[o].off = off;
+        off += n;
+    }
+}
+
+// storage index of potential (o, true index t), -1 outside the kept box
+static int64_t pot_index(const PotBox &b, int t0, int t1, int t2) {
+    const int t[3] = {t0, t1, t2};
+    int64_t idx = 0, stride = 1;
+    for (int j = 0; j < 3; ++j) {
+        if (t[j] < b.lo[j] || t[j] >= b.hi[j]) return -1;
+        idx += (int64_t)(t[j] - b.lo[j]) * stride;
+        stride *= b.hi[j] - b.lo[j];
+    }
+    return b.off + idx;
+}
+
+// Entries of u = curl psi in velocity row g (3D): (potential index, coefficient)
+static void curl_row3(const HostLevel &L, int k, const std::vector<double> &c, int64_t g,
+                      std::vector<std::pair<int, double>> &out) {
+    PotBox B[3];
+    pot_boxes(L.N, k, B);
+    out.clear();
+    int R = 0;
+    while (g >= L.off[R + 1]) ++R;
+    int64_t l = g - L.off[R];
+    int t[3];
+    for (int j = 0; j < 3; ++j) {
+        t[j] = (int)(l % L.nb[R][j]) + (j == R ? 1 : 0);
+        l /= L.nb[R][j];
+    }
+    auto add = [&](int o, int a0, int a1, int a2, double v) {
+        const int64_t i = pot_index(B[o], a0, a1, a2);
+        if (i >= 0) out.push_back({(int)i, v});
+    };
+    // derivative in direction dir of component o at t: c (psi(t + e_dir) - psi(t))
+    auto dpsi = [&](int o, int dir, double sign) {
+        const double cc = sign * c[t[dir] + 1];
+        int u[3] = {t[0], t[1], t[2]};
+        u[dir] += 1;
+        add(o, u[0], u[1], u[2], cc);
+        add(o, t[0], t[1], t[2], -cc);
+    };
+    if (R == 0) {
+        dpsi(2, 1, 1.0);
+        dpsi(1, 2, -1.0);
+    } else if (R == 1) {
+        dpsi(0, 2, 1.0);
+        dpsi(2, 0, -1.0);
+    } else {
+        dpsi(1, 0, 1.0);
+        dpsi(0, 1, -1.0);
+    }
+}
+
+// Pseudo-inverse of the symmetric positive semidefinite p x p matrix G
+// (row-major) by cyclic Jacobi rotations: G = V diag(w) V^T, eigenvalues
+// below 1e-12 max(w) are treated as zero.
+static void sym_pinv(int p, std::vector<double> G, std::vector<double> &Gp) {
+    std::vector<double> V((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i) V[(size_t)i * p + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < p; ++j)
+                (i == j ? diag : off) += G[(size_t)i * p + j] * G[(size_t)i * p + j];
+        if (off <= 1e-30 * diag) break;
+        for (int a = 0; a < p - 1; ++a)
+            for (int b = a + 1; b < p; ++b) {
+                const double gab = G[(size_t)a * p + b];
+                if (gab == 0.0) continue;
+                const double gaa = G[(size_t)a * p + a], gbb = G[(size_t)b * p + b];
+                const double th = 0.5 * (gbb - gaa) / gab;
+                const double tt = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * cs;
+                for (int r = 0; r < p; ++r) {  // columns a, b
+                    const double x = G[(size_t)r * p + a], y = G[(size_t)r * p + b];
+                    G[(size_t)r * p + a] = cs * x - sn * y;
+                    G[(size_t)r * p + b] = sn * x + cs * y;
+                }
+                for (int r = 0; r < p; ++r) {  // rows a, b
+                    const double x = G[(size_t)a * p + r], y = G[(size_t)b * p + r];
+                    G[(size_t)a * p + r] = cs * x - sn * y;
+                    G[(size_t)b * p + r] = sn * x + cs * y;
+                }
+                for (int r = 0; r < p; ++r) {
+                    const double x = V[(size_t)r * p + a], y = V[(size_t)r * p + b];
+                    V[(size_t)r * p + a] = cs * x - sn * y;
+                    V[(size_t)r * p + b] = sn * x + cs * y;
+                }
+            }
+    }
+    double wmax = 0.0;
+    for (int i = 0; i < p; ++i) wmax = std::max(wmax, std::fabs(G[(size_t)i * p + i]));
+    Gp.assign((size_t)p * p, 0.0);
+    for (int e = 0; e < p; ++e) {
+        const double w = G[(size_t)e * p + e];
+        if (!(w > 1e-12 * wmax)) continue;
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < p; ++j) Gp[(size_t)i * p + j] += V[(size_t)i * p + e] * V[(size_t)j * p + e] / w;
+    }
+}
+
+// Q = (C^T C)^+ C^T X for C (r x p) and X (r x n), row-major, result p x n:
+// the minimum-norm potentials whose curl is each column of X (which lies in
+// the range of C)
+static void pinv_solve(int r, int p, int n, const std::vector<double> &C, const double *X, std::vector<double> &Q) {
+    std::vector<double> G((size_t)p * p, 0.0), Gp;
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            double s = 0.0;
+            for (int t = 0; t < r; ++t) s += C[(size_t)t * p + a] * C[(size_t)t * p + b];
+            G[(size_t)a * p + b] = s;
+        }
+    sym_pinv(p, G, Gp);
+    std::vector<double> CtX((size_t)p * n, 0.0);
+    for (int a = 0; a < p; ++a)
+        for (int t = 0; t < r; ++t) {
+            const double ca = C[(size_t)t * p + a];
+            if (ca == 0.0) continue;
+            for (int j = 0; j < n; ++j) CtX[(size_t)a * n + j] += ca * X[(size_t)t * n + j];
+        }
+    Q.assign((size_t)p * n, 0.0);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+            const double g = Gp[(size_t)a * p + b];
+            if (g == 0.0) continue;
+            for (int j = 0; j < n; ++j) Q[(size_t)a * n + j] += g * CtX[(size_t)b * n + j];
+        }
+}
+
+// The velocity response X (r x n, velocity rows of a solution operator) to
+// a load without pressure part (its first r columns) is divergence-free, so
+// it must be a curl: C Q reproduces those columns (exactness of the local and
+// global complexes).  A failure means a wrong curl or potential map.
+static void check_curl_map(int r, int p, int n, const std::vector<double> &C, const std::vector<double> &Q,
+                           const double *X, const char *what) {
+    double scale = 0.0, err = 0.0;
+    for (int t = 0; t < r; ++t)
+        for (int j = 0; j < r; ++j) {
+            double v = 0.0;
+            for (int a = 0; a < p; ++a) v += C[(size_t)t * p + a] * Q[(size_t)a * n + j];
+            scale = std::max(scale, std::fabs(X[(size_t)t * n + j]));
+            err = std::max(err, std::fabs(v - X[(size_t)t * n + j]));
+        }
+    if (err > 1e-9 * std::max(scale, 1e-300))
+        throw std::runtime_error(std::string(what) + ": velocity rows are not curls of the potentials (rel. err " +
+                                 std::to_string(err / scale) + ")");
+}
+
+// local potentials of every 3D subdomain (the vector-potential functions of
+// any component whose supports lie in it) and their maps Q_i
+static void build_potential_maps_3d(const Problem &pb, HostLevel &L) {
+    const int k = pb.k, N = L.N;
+    PotBox B[3];
+    pot_boxes(N, k, B);
+    {
+        int64_t n2 = 1;
+        for (int j = 0; j < 3; ++j) n2 *= B[2].hi[j] - B[2].lo[j];
+        L.n_psi = B[2].off + n2;
+    }
+    const auto c = deriv_coef(N, k + 1);
+    auto qd = [&](int o, int j) { return j == o ? k : k + 1; };
+    L.qptr.assign(1, 0);
+    L.qpsi.clear();
+    L.qoff.clear();
+    L.Q.clear();
+    L.beta_row.clear();
+    L.beta_patch.clear();
+    std::vector<int> loc;
+    std::vector<double> C, Qi;
+    std::vector<std::pair<int, double>> row;
+    std::vector<std::vector<int32_t>> qbucket(1 << 16);
+    std::vector<std::pair<int64_t, int64_t>> qclass;  // (size, offset)
+    for (int64_t i = 0; i < L.n_patch; ++i) {
+        const int o = L.ppot[4 * i], a[3] = {L.ppot[4 * i + 1], L.ppot[4 * i + 2], L.ppot[4 * i + 3]};
+        int e0[3], e1[3];
+        for (int j = 0; j < 3; ++j) {
+            e0[j] = std::max(0, a[j] - qd(o, j));
+            e1[j] = std::min(N - 1, a[j]);
+        }
+        loc.clear();
+        for (int o2 = 0; o2 < 3; ++o2)
+            for (int b2 = e0[2]; b2 <= e1[2] + qd(o2, 2); ++b2)
+                for (int b1 = e0[1]; b1 <= e1[1] + qd(o2, 1); ++b1)
+                    for (int b0 = e0[0]; b0 <= e1[0] + qd(o2, 0); ++b0) {
+                        const int b[3] = {b0, b1, b2};
+                        bool in = true;
+                        for (int j = 0; j < 3 && in; ++j)
+                            in = std::max(0, b[j] - qd(o2, j)) >= e0[j] && std::min(N - 1, b[j]) <= e1[j];
+                        if (!in) continue;
+                        const int64_t idx = pot_index(B[o2], b0, b1, b2);
+                        if (idx >= 0) loc.push_back((int)idx);
+                    }
+        const int np = (int)loc.size(), n = L.pptr[i + 1] - L.pptr[i];
+        const int32_t *dofs = &L.pdofs[L.pptr[i]];
+        int nv = 0;
+        while (nv < n && dofs[nv] < L.n_v) ++nv;
+        C.assign((size_t)nv * np, 0.0);
+        for (int r = 0; r < nv; ++r) {
+            curl_row3(L, k, c, dofs[r], row);
+            for (auto &e : row) {
+                const auto it = std::find(loc.begin(), loc.end(), e.first);
+                if (it != loc.end()) C[(size_t)r * np + (it - loc.begin())] += e.second;
+            }
+        }
+        pinv_solve(nv, np, n, C, &L.M[L.moff[i]], Qi);
+        check_curl_map(nv, np, n, C, Qi, &L.M[L.moff[i]], "3D local potential map");
+        double scale = 0.0;
+        for (double x : Qi) scale = std::max(scale, std::fabs(x));
+        uint64_t hsh = (uint64_t)(np * 64 + n) * 1469598103934665603ull;
+        for (double x : Qi)
+            hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / (scale > 0 ? scale : 1.0) * 4096.0)) * 1099511628211ull;
+        int32_t off = -1;
+        for (int32_t cand : qbucket[hsh & 0xffff]) {
+            const auto &ci = qclass[cand];
+            if (ci.first != (int64_t)Qi.size()) continue;
+            double dmax = 0.0;
+            for (size_t t = 0; t < Qi.size(); ++t) dmax = std::max(dmax, std::fabs(Qi[t] - L.Q[ci.second + t]));
+            if (dmax <= 1e-14 * scale) {
+                off = (int32_t)ci.second;
+                break;
+            }
+        }
+        if (off < 0) {
+            off = (int32_t)L.Q.size();
+            qbucket[hsh & 0xffff].push_back((int32_t)qclass.size());
+            qclass.push_back({(int64_t)Qi.size(), (int64_t)off});
+            L.Q.insert(L.Q.end(), Qi.begin(), Qi.end());
+            if (L.Q.size() > (size_t)INT32_MAX) throw std::runtime_error("potential map store exceeds 2^31 entries");
+        }
+        L.qoff.push_back(off);
+        for (int t = 0; t < np; ++t) {
+            L.beta_row.push_back((int32_t)(off + (size_t)t * n));
+            L.beta_patch.push_back((int32_t)i);
+        }
+        L.qpsi.insert(L.qpsi.end(), loc.begin(), loc.end());
+        L.qptr.push_back((int32_t)L.qpsi.size());
+    }
+    finish_potential_maps(L);
+}
+
+// 3D potential prolongation: per component the Kronecker product of the 1D
+// refinements (degree k in direction o, all functions; degree k+1 without
+// the end functions in the others)
+static void build_potential_prolongation_3d(const Problem &pb, const HostLevel &C, HostLevel &F) {
+    const int k = pb.k;
+    const Mat1 T[2] = {refinement_matrix(C.N, k), refinement_matrix(C.N, k + 1)};
+    PotBox Bc[3], Bf[3];
+    pot_boxes(C.N, k, Bc);
+    pot_boxes(F.N, k, Bf);
+    F.Ps_rp.assign(1, 0);
+    F.Ps_ci.clear();
+    F.Ps_v.clear();
+    for (int o = 0; o < 3; ++o) {
+        // per direction: fine true index -> (coarse true index, coefficient)
+        std::vector<std::vector<std::pair<int, double>>> list[3];
+        for (int j = 0; j < 3; ++j) {
+            const Mat1 &Tj = T[j == o ? 0 : 1];
+            list[j].assign(Bf[o].hi[j], {});
+            for (int tf = Bf[o].lo[j]; tf < Bf[o].hi[j]; ++tf)
+                for (int tc = Bc[o].lo[j]; tc < Bc[o].hi[j]; ++tc) {
+                    const double v = Tj(tc, tf);
+                    if (v != 0.0) list[j][tf].push_back({tc, v});
+                }
+        }
+        for (int t2 = Bf[o].lo[2]; t2 < Bf[o].hi[2]; ++t2)
+            for (int t1 = Bf[o].lo[1]; t1 < Bf[o].hi[1]; ++t1)
+                for (int t0 = Bf[o].lo[0]; t0 < Bf[o].hi[0]; ++t0) {
+                    for (auto &z : list[2][t2])
+                        for (auto &y : list[1][t1])
+                            for (auto &x : list[0][t0]) {
+                                F.Ps_ci.push_back((int32_t)pot_index(Bc[o], x.first, y.first, z.first));
+                                F.Ps_v.push_back(x.second * y.second * z.second);
+                            }
+                    F.Ps_rp.push_back((int32_t)F.Ps_ci.size());
+                }
+    }
+}
+
+// 3D coarse level: Q0 = (C^T C)^+ C^T Kinv[velocity rows]
+static void build_coarse_potentials_3d(const Problem &pb, HostLevel &L) {
+    const int k = pb.k;
+    PotBox B[3];
+    pot_boxes(L.N, k, B);
+    int64_t n2 = 1;
+    for (int j = 0; j < 3; ++j) n2 *= B[2].hi[j] - B[2].lo[j];
+    L.n_psi = B[2].off + n2;
+    if (L.n_psi > 2000) throw std::runtime_error("3D FP32 refinement needs a coarsest grid of at most 2000 potentials");
+    const auto c = deriv_coef(L.N, k + 1);
+    const int nv = (int)L.n_v, np = (int)L.n_psi, n = (int)L.n;
+    std::vector<double> C((size_t)nv * np, 0.0);
+    std::vector<std::pair<int, double>> row;
+    for (int r = 0; r < nv; ++r) {
+        curl_row3(L, k, c, r, row);
+        for (auto &e : row) C[(size_t)r * np + e.first] += e.second;
+    }
+    pinv_solve(nv, np, n, C, L.Kinv.data(), L.Q0);
+    check_curl_map(nv, np, n, C, L.Q0, L.Kinv.data(), "3D coarse potential map");
 }
 
 // Fixed-width form of a CSR map with `rows` rows (see kEllMax): returns the
@@ -1123,11 +1460,18 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         bordered_inverse(pb, C, all.data(), n, C.Kinv.data());
     }
     if (pb.potentials) {
-        if (pb.d != 2) throw std::runtime_error("the potential form is implemented for dim 2");
-        build_coarse_potentials(pb, H.lv[0]);
-        for (int l = 1; l < L; ++l) {
-            build_potential_maps(pb, H.lv[l]);
-            build_potential_prolongation(pb, H.lv[l - 1], H.lv[l]);
+        if (pb.d == 2) {
+            build_coarse_potentials(pb, H.lv[0]);
+            for (int l = 1; l < L; ++l) {
+                build_potential_maps(pb, H.lv[l]);
+                build_potential_prolongation(pb, H.lv[l - 1], H.lv[l]);
+            }
+        } else {
+            build_coarse_potentials_3d(pb, H.lv[0]);
+            for (int l = 1; l < L; ++l) {
+                build_potential_maps_3d(pb, H.lv[l]);
+                build_potential_prolongation_3d(pb, H.lv[l - 1], H.lv[l]);
+            }
         }
     }
     for (int l = 1; l < L; ++l) finalize_small(H.lv[l]);

@@ -66,7 +66,7 @@ struct Problem {
     int adv_kind = 0;
     double adv_c = 0.0;
     bool share_inverses = true;
-    bool potentials = false;   // build the potential-form maps of the FP32 cycle (2D)
+    bool potentials = false;   // build the potential-form maps of the FP32 cycle
     bool multiplicative = false;  // build the lane tables of the multiplicative sweep
 };
 
@@ -104,6 +104,8 @@ struct HostLevel {
     // mwave_ptr[c] .. mwave_ptr[c+1] of the lane table mlane (mwidth entry
     // indices per workgroup, -1 unused); built with Problem::multiplicative
     std::vector<int32_t> mcolor, mwave_ptr, mlane;
+    // the potential of each subdomain: (orientation, true index x, y, z)
+    std::vector<int32_t> ppot;
     int mwidth = 0;            // entries per workgroup of mlane
     // subdomains with <= kSmallPatch DOFs, and the entries of the others
     std::vector<int32_t> small_list, big_ent;

@@ -40,8 +40,6 @@ def test_error_conventions():
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=3)   # no such advection
     with pytest.raises(dfmg.DfmgError):
-        dfmg.Solver(3, 8, 2, 1, precision=1)  # refinement path is 2D
-    with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, precision=1, inner_cycles=0)
     s = dfmg.Solver(2, 8, 2, 1)
     code = dfmg.lib().dfmg_vcycle(s._ctx, ctypes.c_void_p(8), ctypes.c_void_p(8), 1)

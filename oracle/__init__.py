@@ -38,6 +38,9 @@ module, each against a fact the paper or the mathematics fixes:
   equation MSM, the sequential sweep, and Table 1; Chebyshev dampings against
   numpy's Chebyshev series.
 * ``mlp``: gradients against finite differences; Adam on a quadratic.
+* ``timestep``: the convective load of polynomial fields against the mass
+  matrix times exact spline coefficients; the linear part of the
+  Crank-Nicolson / Adams-Bashforth load against an independent assembly.
 
 None of these functions is "parity unpinned".
 """

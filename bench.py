@@ -197,6 +197,50 @@ def stokes3d_legs(dev, steps=3, warmup=1):
     return out
 
 
+def cnab_legs(dev, nsteps=10):
+    """Navier-Stokes by Crank-Nicolson / Adams-Bashforth steps (context):
+    2D, k=2, 256^2, 6 grids, nu = 0.1, dt = 1e-3 (sigma = 2000; |u| dt / h
+    stays below 1 for the explicit convection), driven from rest by the
+    steady Stokes forcing f = -nu Lap u + grad p of the manufactured
+    solution (load of 2 f); each step solves its generalized Stokes problem
+    to 1e-8 from the previous velocity.  Plain FP64 (fixed damping V(2,2))
+    against FP32 refinement with the learned Chebyshev schedule; nsteps
+    timed steps after one untimed."""
+    import torch
+    from paper_1705_09282_amd.dfmg import Solver
+    from paper_1705_09282_amd import learned
+    nu, dt = 0.1, 1e-3
+    out = {"workload": "Navier-Stokes, CN/AB steps (equation GS), 2D k=2 256^2, 6 grids, nu=0.1, dt=1e-3, "
+                       "steady Stokes forcing of the manufactured solution, from rest, tol 1e-8 per step"}
+    steady = Solver(2, 256, 6, 2, nu=nu, sigma=0.0)
+    f2 = 2.0 * steady.manufactured_rhs()  # load of 2 f, f = -nu Lap u + grad p
+    steady.close()
+    for name, prec, lrn in (("fp64_fixed_damping", 0, False), ("fp32_refined_learned_chebyshev", 1, True)):
+        s = Solver(2, 256, 6, 2, nu=nu, sigma=2.0 / dt, precision=prec, time_stepping=1).bind(dev)
+        s.autotune(reps=10)
+        if lrn:
+            learned.apply_chebyshev(s)
+        F2 = torch.tensor(f2, device=dev)
+        prev, U = None, torch.zeros_like(F2)
+        cyc = []
+        for i in range(nsteps + 1):
+            if i == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            Un = torch.empty_like(U)
+            st = s.cnab_step(F2, prev, U, Un)
+            prev, U = U, Un
+            if i >= 1:
+                cyc.append(st[0]["cycles"])
+        torch.cuda.synchronize()
+        dt_step = (time.perf_counter() - t0) / nsteps
+        out[name] = {"ms_per_step": 1e3 * dt_step, "dofs_per_s": (s.n - 1) / dt_step, "cycles_per_step": cyc,
+                     "div_norm_last": s.div_norm(U), "velocity_l2_coef_last": float(torch.linalg.norm(U))}
+        s.close()
+    out["speedup"] = out["fp64_fixed_damping"]["ms_per_step"] / out["fp32_refined_learned_chebyshev"]["ms_per_step"]
+    return out
+
+
 def roofline_hbm(dev, reps=50):
     """The FP32 residual on an operator that cannot stay in the 256 MB
     Infinity Cache: one problem of the same workload on 1024^2 elements
@@ -452,6 +496,8 @@ def main():
         line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
         print("[bench] the 3D workload (context)", file=sys.stderr, flush=True)
         line["config"]["stokes3d"] = stokes3d_legs(dev)
+        print("[bench] Navier-Stokes CN/AB steps (context)", file=sys.stderr, flush=True)
+        line["config"]["navier_stokes_cnab"] = cnab_legs(dev)
     if not args.no_cpu_baseline and args.n_elem == 256 and args.levels == 6:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"], line["config"]["vel_rel_err_vs_oracle_sigma1"] = cpu_baseline(args.tol, U32_sigma1)

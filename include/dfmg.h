@@ -75,7 +75,7 @@ typedef struct {
  * stable fixed damping for (dim, k): 0.35 for 2D k=1, 0.2 for 2D k=2, 0.07 for
  * 3D k=1, 0.02 for 3D k=2), precision 0, smoother 0, max_cycles 200,
  * use_graph 1, cycles_per_check 1, share_inverses 1, inner_cycles 1,
- * multiplicative 0. */
+ * multiplicative 0, time_stepping 0. */
 typedef struct {
     int nu1;              /* pre-smoothing steps per level (Algorithm 1)        */
     int nu2;              /* post-smoothing steps per level                     */
@@ -100,6 +100,9 @@ typedef struct {
                              (k+2)]) of dfmg_export_sweep_colours, ascending
                              inside a colour (the paper leaves the order open).
                              Needs precision 0. */
+    int time_stepping;    /* 1: reserve the quadrature workspace of the
+                             Crank-Nicolson / Adams-Bashforth load
+                             (dfmg_cnab_rhs, dfmg_cnab_step) */
 } dfmg_options;
 
 #define DFMG_MAX_HISTORY 512
@@ -192,6 +195,28 @@ int dfmg_get_smoothing(const dfmg_ctx *ctx, int *nu1_host, int *nu2_host);
  * cycle runs smoother form 3 where tuned so and form 4 otherwise.  Stats
  * count refinement steps as cycles. */
 int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, dfmg_stats *st);
+
+/* Crank-Nicolson / Adams-Bashforth time stepping of the Navier-Stokes
+ * equations (section on temporal discretization, equation GS): each step is
+ * the generalized Stokes problem of the context (sigma = 2 / dt, no
+ * advection) with the load
+ *   F_u = F2 - (K U^n)_u + (N_i, 2 sigma u^n - 3 (u^n . grad) u^n
+ *                                 + (u^{n-1} . grad) u^{n-1}),   F_p = 0,
+ * where F2 is the caller's load vector of 2 f(t_{n+1/2}) (every term of the
+ * step is doubled so that its implicit side is the context's operator; the
+ * paper's printed f(t_{n+1/2}) lacks that factor 2) and, for the first step
+ * (Uold NULL), -2 (u^n . grad) u^n replaces the convective terms (the
+ * paper's footnote).  Integrals by Gauss quadrature, k + 3 points per
+ * direction per element.  All vectors are device arrays of the finest level
+ * (problem-major in a batch).  Needs options.time_stepping = 1 at setup and
+ * advection kind 0.
+ * dfmg_cnab_rhs: the load into Fout (stream-ordered).
+ * dfmg_cnab_step: the load, then dfmg_solve from Unext = U^n to tol; Unext
+ * receives U^{n+1} (with zero-mean pressure).  Errors: as dfmg_solve;
+ * ESTATE without time_stepping; EINVAL with advection. */
+int dfmg_cnab_rhs(dfmg_ctx *ctx, const double *F2_dev, const double *U_dev, const double *Uold_dev, double *Fout_dev);
+int dfmg_cnab_step(dfmg_ctx *ctx, const double *F2_dev, const double *Uold_dev, const double *U_dev, double *Unext_dev,
+                   double tol, dfmg_stats *st);
 
 /* ||F - K U||_2 on the finest level (device inputs, host output). */
 int dfmg_residual_norm(dfmg_ctx *ctx, const double *F_dev, const double *U_dev, double *out);

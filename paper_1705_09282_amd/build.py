@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdfmg.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["setup.cpp", "spmv.hip", "kernels.hip", "small.hip", "mult.hip", "mlp.hip", "vsmall.hip", "api.hip"]
+SOURCES = ["setup.cpp", "spmv.hip", "kernels.hip", "small.hip", "mult.hip", "timestep.hip", "mlp.hip", "vsmall.hip", "api.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = [

@@ -159,6 +159,9 @@ struct dfmg_ctx {
     double *sched0 = nullptr;      // device copy as built (a fallback overwrites sched)
     double *unit = nullptr;        // device [problem]: 1.0 (undamped smoother, eigenvalue estimates)
     float *mlpZ = nullptr;         // device [problem][MLP_OUT]: network outputs
+    // Crank-Nicolson / Adams-Bashforth load (options.time_stepping)
+    double *qbval = nullptr, *qbder = nullptr, *qw = nullptr, *qG = nullptr, *fstep = nullptr, *sigma_dev = nullptr;
+    int64_t npts = 0;
     bool sched_on = false;
     std::vector<double> alpha;     // [problem][level]: ratio b / a of the Chebyshev interval [a, b]
     std::vector<double> lmax;      // [problem][level]: estimate of the largest |eigenvalue| of S^-1 K
@@ -308,6 +311,17 @@ void plan(dfmg_ctx *c, Arena &A) {
     c->sched0 = A.take<double>((size_t)L * np * kSchedPerLevel);
     c->unit = A.take<double>(np);
     c->mlpZ = A.take<float>((size_t)MLP_OUT * np);
+    if (c->opt.time_stepping) {
+        const int d = H.pb.d, nq = H.pb.k + 3;
+        c->npts = 1;
+        for (int j = 0; j < d; ++j) c->npts *= (int64_t)H.pb.N * nq;
+        c->qbval = A.take<double>(H.qbval.size());
+        c->qbder = A.take<double>(H.qbder.size());
+        c->qw = A.take<double>(H.qw.size());
+        c->qG = A.take<double>((size_t)c->npts * d * np);
+        c->fstep = A.take<double>((size_t)H.lv[L - 1].n * np);
+        c->sigma_dev = A.take<double>(np);
+    }
 }
 
 template <class T>
@@ -947,6 +961,7 @@ dfmg_options checked_options(const dfmg_options *opt, int dim) {
     if (o.smoother < 0 || o.smoother > 4) throw ArgError("smoother must be 0 .. 4");
     if (o.eta >= 1.0) throw ArgError("eta must be < 1");
     if (o.multiplicative != 0 && o.multiplicative != 1) throw ArgError("multiplicative must be 0 or 1");
+    if (o.time_stepping != 0 && o.time_stepping != 1) throw ArgError("time_stepping must be 0 or 1");
     if (o.multiplicative == 1 && o.precision != 0)
         throw ArgError("multiplicative Schwarz runs in FP64 V-cycles (precision 0)");
     return o;
@@ -1202,6 +1217,7 @@ void dfmg_default_options(dfmg_options *o) {
     o->share_inverses = 1;
     o->inner_cycles = 1;
     o->multiplicative = 0;
+    o->time_stepping = 0;
 }
 
 const char *dfmg_last_error(void) { return g_err.c_str(); }
@@ -1416,6 +1432,15 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
         up(c->dcoef, H.dcoef, s);
         up(c->pmass, H.pmass, s);
         up(c->wfine, H.lv[H.pb.L - 1].w, s);
+        if (c->opt.time_stepping) {
+            up(c->qbval, H.qbval, s);
+            up(c->qbder, H.qbder, s);
+            up(c->qw, H.qw, s);
+            std::vector<double> sg(np);
+            for (int p = 0; p < np; ++p) sg[p] = c->P[p].pb.sigma;
+            up(c->sigma_dev, sg, s);
+            HIPCHK(hipStreamSynchronize(s));
+        }
         HIPCHK(hipMemsetAsync(c->counter, 0, kFlagSets * np * sizeof(int), s));
         HIPCHK(hipHostMalloc((void **)&c->hflags, 2 * kFlagSets * np * sizeof(int), hipHostMallocDefault));
         std::memset(c->hflags, 0, 2 * kFlagSets * np * sizeof(int));
@@ -1538,6 +1563,48 @@ int dfmg_div_norm(dfmg_ctx *c, const double *U, double *out) {
     });
 }
 
+// load of one Crank-Nicolson / Adams-Bashforth step into Fout (see dfmg.h)
+static void cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const double *Uold, double *Fout) {
+    if (!c->opt.time_stepping) throw StateError("set options.time_stepping = 1 before dfmg_setup");
+    for (const Hierarchy &Q : c->P)
+        if (Q.pb.adv_kind != 0) throw ArgError("the Crank-Nicolson / Adams-Bashforth step is a generalized Stokes problem");
+    const Hierarchy &H = c->S();
+    const HostLevel &h = H.lv[H.pb.L - 1];
+    spmv<double>(c, H.pb.L - 1, F2, U, Fout, nullptr, nullptr);  // F2 - K U^n
+    CnabArgs a{};
+    a.d = H.pb.d;
+    a.k = H.pb.k;
+    a.N = H.pb.N;
+    a.nq = H.pb.k + 3;
+    for (int R = 0; R < 4; ++R) a.off[R] = R <= a.d ? h.off[R] : h.n;
+    for (int R = 0; R < 3; ++R)
+        for (int j = 0; j < 3; ++j) a.nb[R][j] = R < a.d ? h.nb[R][j] : 1;
+    a.n = h.n;
+    a.svec = h.n;
+    a.bval = c->qbval;
+    a.bder = c->qbder;
+    a.wq = c->qw;
+    a.U = U;
+    a.Uold = Uold;
+    a.sigma = c->sigma_dev;
+    a.G = c->qG;
+    a.npts = c->npts;
+    a.sG = c->npts * a.d;
+    a.Fout = Fout;
+    a.nprob = c->np;
+    launch_cnab_load(a, c->s);
+}
+
+extern "C" int dfmg_cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const double *Uold, double *Fout) {
+    if (!c || !F2 || !U || !Fout) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        enter(c);
+        cnab_rhs(c, F2, U, Uold, Fout);
+        HIPCHK(hipGetLastError());
+        leave(c);
+    });
+}
+
 int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *st) {
     if (!c || !F || !U) return fail(DFMG_EINVAL, "null argument");
     if (!(tol > 0.0)) return fail(DFMG_EINVAL, "tol must be positive");
@@ -1575,6 +1642,21 @@ int dfmg_solve(dfmg_ctx *c, const double *F, double *U, double tol, dfmg_stats *
         for (size_t p = 0; p < local.size(); ++p) st[p] = local[p];
     if (rc != DFMG_OK) return rc;
     return solve_status(status);
+}
+
+int dfmg_cnab_step(dfmg_ctx *c, const double *F2, const double *Uold, const double *U, double *Unext, double tol,
+                   dfmg_stats *st) {
+    if (!c || !F2 || !U || !Unext) return fail(DFMG_EINVAL, "null argument");
+    const int rc = guarded([&] {
+        enter(c);
+        cnab_rhs(c, F2, U, Uold, c->fstep);
+        const int64_t n = c->S().lv[c->L() - 1].n;
+        if (Unext != U) launch_copy(n, U, n, Unext, n, nullptr, c->np, c->s);
+        HIPCHK(hipGetLastError());
+        leave(c);
+    });
+    if (rc != DFMG_OK) return rc;
+    return dfmg_solve(c, c->fstep, Unext, tol, st);
 }
 
 int dfmg_level_residual(dfmg_ctx *c, int level, const double *F, const double *U, double *r) {

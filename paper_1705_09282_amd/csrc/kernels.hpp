@@ -289,6 +289,26 @@ struct RefineArgs {
 };
 void launch_refine_update(const RefineArgs &a, hipStream_t s);
 
+// Quadrature part of the Crank-Nicolson / Adams-Bashforth load (finest
+// grid): G = weighted integrand 2 sigma u - 3 (u . grad) u + (uo . grad) uo
+// at every quadrature point (first step, Uold null: - 2 (u . grad) u), then
+// Fout_i += (N_i, G) on the velocity rows and Fout = 0 on the pressure rows.
+struct CnabArgs {
+    int d, k, N, nq;        // nq Gauss points per direction per element
+    int64_t off[4];         // block offsets (velocity components, then pressure)
+    int nb[3][3];           // stored functions per velocity component and direction
+    int64_t n, svec;        // rows and per-problem vector stride
+    const double *bval, *bder;  // [degree k / k+1][element][point][local function (k+2)]
+    const double *wq;       // per direction: quadrature weights times h / 2
+    const double *U, *Uold; // per problem (Uold nullable)
+    const double *sigma;    // per problem
+    double *G;              // per problem (stride sG): [point][component]
+    int64_t sG, npts;
+    double *Fout;
+    int nprob;
+};
+void launch_cnab_load(const CnabArgs &a, hipStream_t s);
+
 // div-norm pieces (finest grid, one problem)
 struct DivArgs {
     int d, k, N;

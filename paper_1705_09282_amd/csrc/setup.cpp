@@ -1496,6 +1496,29 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
     }
     const double table[2][2] = {{0.35, 0.2}, {0.07, 0.02}};
     H.default_eta = table[pb.d - 2][pb.k - 1];
+    {
+        const int k = pb.k, N = pb.N, nq = k + 3, w = k + 2;
+        std::vector<double> t, wt;
+        gauss_legendre(nq, t, wt);
+        H.qw.assign(nq, 0.0);
+        for (int g = 0; g < nq; ++g) H.qw[g] = 0.5 * wt[g] / N;
+        H.qbval.assign((size_t)2 * N * nq * w, 0.0);
+        H.qbder.assign((size_t)2 * N * nq * w, 0.0);
+        double v[8], dv[8];
+        for (int a = 0; a < 2; ++a) {
+            const int q = k + a;
+            const auto kn = open_knots(N, q);
+            for (int e = 0; e < N; ++e)
+                for (int g = 0; g < nq; ++g) {
+                    span_basis(kn, q, e + q, (e + 0.5 * (t[g] + 1.0)) / N, v, dv);
+                    for (int m = 0; m <= q; ++m) {
+                        const size_t at = (((size_t)a * N + e) * nq + g) * w + m;
+                        H.qbval[at] = v[m];
+                        H.qbder[at] = dv[m];
+                    }
+                }
+        }
+    }
 }
 
 // ------------------------------------------------------- manufactured forcing

@@ -163,6 +163,11 @@ struct Hierarchy {
     std::vector<double> dcoef;     // derivative coefficients of degree k+1 splines
     std::vector<double> pmass;     // 1D pressure mass band (n_q1 x (2k+1))
     double default_eta = 0.2;
+    // quadrature tables of the finest grid (Crank-Nicolson / Adams-Bashforth
+    // load): values and derivatives of the q+1 B-splines of degree q = k, k+1
+    // non-zero on element e at its Gauss point g, [deg][e][g][m] with m < k+2;
+    // per-direction weights (times h / 2)
+    std::vector<double> qbval, qbder, qw;
 };
 
 // Build everything.  Throws std::runtime_error on invalid input.

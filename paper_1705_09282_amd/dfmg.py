@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", c_int), ("nu2", c_int), ("eta", c_double), ("precision", c_int),
                 ("smoother", c_int), ("max_cycles", c_int), ("use_graph", c_int),
                 ("cycles_per_check", c_int), ("share_inverses", c_int),
-                ("inner_cycles", c_int), ("multiplicative", c_int)]
+                ("inner_cycles", c_int), ("multiplicative", c_int), ("time_stepping", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -73,6 +73,8 @@ SIGNATURES = [
     ("dfmg_set_smoothing", c_int, [c_void_p, c_i32p, c_i32p, c_int]),
     ("dfmg_get_smoothing", c_int, [c_void_p, c_i32p, c_i32p]),
     ("dfmg_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
+    ("dfmg_cnab_rhs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("dfmg_cnab_step", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
     ("dfmg_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
     ("dfmg_div_norm", c_int, [c_void_p, c_void_p, c_dblp]),
     ("dfmg_level_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
@@ -401,6 +403,25 @@ class Solver:
 
     def residual_norm(self, F, U):
         return float(self._residual_norms(F, U)[0])
+
+    def cnab_rhs(self, F2, U, Uold, Fout):
+        """Load of one Crank-Nicolson / Adams-Bashforth step (Uold None: the
+        first step); needs time_stepping=1."""
+        n = self.n * self.nprob
+        _check(lib().dfmg_cnab_rhs(self._ctx, _dev(F2, n), _dev(U, n), None if Uold is None else _dev(Uold, n),
+                                   _dev(Fout, n)))
+
+    def cnab_step(self, F2, Uold, U, Unext, tol=1e-8, raise_on_error=True):
+        """One Crank-Nicolson / Adams-Bashforth step: Unext = U^{n+1} from U
+        (= U^n) and Uold (= U^{n-1}, None at the first step); per-problem
+        stats of its solve."""
+        n = self.n * self.nprob
+        st = (Stats * self.nprob)()
+        code = lib().dfmg_cnab_step(self._ctx, _dev(F2, n), None if Uold is None else _dev(Uold, n), _dev(U, n),
+                                    _dev(Unext, n), float(tol), st)
+        if raise_on_error:
+            _check(code)
+        return [x.as_dict() for x in st]
 
     def div_norm(self, U):
         return float(self._div_norms(U)[0])

@@ -283,6 +283,9 @@ def main():
                     help="only the HBM-resident residual leg (1024^2, one problem)")
     ap.add_argument("--no-hbm-leg", action="store_true", help="skip the HBM-resident residual leg")
     ap.add_argument("--no-paper-legs", action="store_true", help="skip the paper's Oseen problems (context legs)")
+    ap.add_argument("--only", choices=("timed", "multiplicative"), default=None,
+                    help="build and time one path only (for kernel traces): the timed path, or the multiplicative "
+                         "FP64 V(1,2) batch; prints its ms per step and tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -359,6 +362,19 @@ def main():
 
     if args.roofline_hbm_only:
         print(json.dumps({"roofline_hbm": roofline_hbm(dev, reps=200)}), flush=True)
+        return
+
+    if args.only:
+        if args.only == "timed":
+            b, F, U, tun = make_batch(1, use_learned="chebyshev")
+        else:
+            b, F, U, tun = make_batch(0, multiplicative=1, nu1=1, nu2=2)
+        T, st = run(b, F, U)
+        print(json.dumps({"path": args.only, "ms_per_step": 1e3 * T / args.steps,
+                          "cycles_per_sigma": [x["cycles"] for x in st], "steps": args.steps, "warmup": args.warmup,
+                          "tuning": {k: v for k, v in tun.items() if k != "ms"},
+                          "steps_per_level_finest_first": b.get_smoothing()[0]}), flush=True)
+        b.close()
         return
 
     if args.roofline_only:

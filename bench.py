@@ -241,6 +241,50 @@ def cnab_legs(dev, nsteps=10):
     return out
 
 
+def guermond_legs(dev, nsteps=3):
+    """Navier-Stokes by Guermond's semi-implicit steps (context): the same
+    flow as the CN/AB leg (2D, k=2, 256^2, 6 grids, nu = 0.1, dt = 1e-3,
+    steady Stokes forcing, from rest), each step a generalized Oseen problem
+    advected by 3/2 u^n - 1/2 u^{n-1} (u^0 at the first step), solved to
+    1e-8 with fixed damping V(2,2).  The operator changes every step, so
+    each step builds a new context on the host (setup seconds, reported
+    apart) before its load kernel and solve (GPU milliseconds)."""
+    import torch
+    from paper_1705_09282_amd.dfmg import Solver
+    nu, dt = 0.1, 1e-3
+    nv = 2 * (256 + 1) * (256 + 2)
+    out = {"workload": "Navier-Stokes, Guermond steps (equation GO), 2D k=2 256^2, 6 grids, nu=0.1, dt=1e-3, "
+                       "steady Stokes forcing of the manufactured solution, from rest, tol 1e-8 per step"}
+    steady = Solver(2, 256, 6, 2, nu=nu, sigma=0.0)
+    F2 = torch.tensor(2.0 * steady.manufactured_rhs(), device=dev)
+    steady.close()
+    for name, prec in (("fp64_fixed_damping", 0), ("fp32_refined_fixed_damping", 1)):
+        prev, U = None, torch.zeros_like(F2)
+        setup, solve, cyc = [], [], []
+        for i in range(nsteps):
+            a = U[:nv] if prev is None else 1.5 * U[:nv] - 0.5 * prev[:nv]
+            t0 = time.perf_counter()
+            s = Solver(2, 256, 6, 2, nu=nu, sigma=2.0 / dt, c=1.0, adv_kind=3, adv_coeffs=a.cpu().numpy(),
+                       precision=prec, time_stepping=1).bind(dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Fd = torch.empty_like(F2)
+            s.go_rhs(F2, U, Fd)
+            Un = U.clone()
+            st = s.solve(Fd, Un)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            setup.append(t1 - t0)
+            solve.append(1e3 * (t2 - t1))
+            cyc.append(st["cycles"])
+            prev, U = U, Un
+            div = s.div_norm(U)
+            s.close()
+        out[name] = {"setup_s_per_step": setup, "gpu_ms_per_step": solve, "cycles_per_step": cyc,
+                     "div_norm_last": div}
+    return out
+
+
 def roofline_hbm(dev, reps=50):
     """The FP32 residual on an operator that cannot stay in the 256 MB
     Infinity Cache: one problem of the same workload on 1024^2 elements
@@ -514,6 +558,8 @@ def main():
         line["config"]["stokes3d"] = stokes3d_legs(dev)
         print("[bench] Navier-Stokes CN/AB steps (context)", file=sys.stderr, flush=True)
         line["config"]["navier_stokes_cnab"] = cnab_legs(dev)
+        print("[bench] Navier-Stokes Guermond steps (context)", file=sys.stderr, flush=True)
+        line["config"]["navier_stokes_guermond"] = guermond_legs(dev)
     if not args.no_cpu_baseline and args.n_elem == 256 and args.levels == 6:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"], line["config"]["vel_rel_err_vs_oracle_sigma1"] = cpu_baseline(args.tol, U32_sigma1)

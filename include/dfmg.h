@@ -64,11 +64,18 @@ typedef struct {
  * kind 2: a = c * u with u the manufactured velocity of
  *         dfmg_manufactured_rhs (the paper's Oseen problems take the
  *         advection equal to the manufactured velocity).
+ * kind 3: a = c * w with w the field of the finest velocity space whose
+ *         coefficients (n_v values, canonical velocity order, host memory,
+ *         copied at setup) are `coeffs`: Guermond's scheme advects with
+ *         3/2 u^n - 1/2 u^{n-1}.  Its term is assembled by Gauss quadrature
+ *         on the finest grid and Galerkin-projected (R C P) to the coarser
+ *         ones; subdomain inverses are not shared.
  * |a| (the network's input |a| h / nu) is max |a|: |c| / sqrt(2) for
- * kind 1, |c| max |u| for kind 2. */
+ * kind 1, |c| max |u| for kind 2, not defined for kind 3 (0). */
 typedef struct {
     int kind;
     double c;
+    const double *coeffs;  /* kind 3 only (else ignored, may be NULL) */
 } dfmg_advection;
 
 /* Solver options.  dfmg_default_options fills: nu1 = nu2 = 2, eta = 0 (use the
@@ -217,6 +224,13 @@ int dfmg_solve(dfmg_ctx *ctx, const double *F_dev, double *U_dev, double tol, df
 int dfmg_cnab_rhs(dfmg_ctx *ctx, const double *F2_dev, const double *U_dev, const double *Uold_dev, double *Fout_dev);
 int dfmg_cnab_step(dfmg_ctx *ctx, const double *F2_dev, const double *Uold_dev, const double *U_dev, double *Unext_dev,
                    double tol, dfmg_stats *st);
+/* Guermond's semi-implicit step (equation GO): the operator of the context
+ * advects with a^{n+1} = 3/2 u^n - 1/2 u^{n-1} (u^0 at the first step, the
+ * paper's footnote; advection kind 3 at setup), sigma = 2 / dt, and the load
+ * of the doubled step is F_u = F2 - (K(a) U^n)_u + (N_i, 2 sigma u^n),
+ * F_p = 0, F2 the caller's load of 2 f(t_{n+1/2}).  Needs time_stepping = 1.
+ * The operator changes every step: a new context per step. */
+int dfmg_go_rhs(dfmg_ctx *ctx, const double *F2_dev, const double *U_dev, double *Fout_dev);
 
 /* ||F - K U||_2 on the finest level (device inputs, host output). */
 int dfmg_residual_norm(dfmg_ctx *ctx, const double *F_dev, const double *U_dev, double *out);

@@ -40,7 +40,10 @@ module, each against a fact the paper or the mathematics fixes:
 * ``mlp``: gradients against finite differences; Adam on a quadratic.
 * ``timestep``: the convective load of polynomial fields against the mass
   matrix times exact spline coefficients; the linear part of the
-  Crank-Nicolson / Adams-Bashforth load against an independent assembly.
+  Crank-Nicolson / Adams-Bashforth load against an independent assembly;
+  the advection by a discrete polynomial field against the analytic field;
+  a field advecting itself against the convective load; the Guermond load's
+  linear part against an independent mass matrix.
 
 None of these functions is "parity unpinned".
 """

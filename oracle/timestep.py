@@ -1,5 +1,5 @@
-"""Crank-Nicolson / Adams-Bashforth time step of the Navier-Stokes equations
-as a generalized Stokes problem (oracle).
+"""Crank-Nicolson / Adams-Bashforth and Guermond time steps of the
+Navier-Stokes equations as generalized Stokes / Oseen problems (oracle).
 
 Follows the paper's section on temporal discretization, equation GS: with
 sigma = 2 / dt,
@@ -23,7 +23,7 @@ integral is Gauss quadrature with k+3 points per direction per element.
 """
 import numpy as np
 
-from .assemble import quadrature, tensor_eval, tensor_weights
+from .assemble import quadrature, tensor_eval, tensor_points, tensor_weights
 
 
 def _field(disc, U, pts):
@@ -74,4 +74,30 @@ def cnab_rhs(disc, K, sigma, F2, U, Uold=None):
     r = F2 - K @ U
     nv = disc.n_v
     out[:nv] += r[:nv]
+    return out
+
+
+def field_advection(disc, coeffs, c=1.0):
+    """Advection a = c w for the discrete velocity field w (coefficients of
+    ``disc``'s velocity space), as the callable ``assemble`` takes: it
+    evaluates the field at the quadrature grid that ``assemble`` passes."""
+    pts, _ = quadrature(disc)
+    Xq = tensor_points(pts)
+
+    def a(X):
+        assert X.shape == Xq.shape and np.allclose(X, Xq), "field advection is evaluated at the quadrature grid"
+        return c * _field(disc, coeffs, pts)[0]
+    return a
+
+
+def go_rhs(disc, K, sigma, F2, U):
+    """Load of Guermond's step (equation GO, the step doubled): the operator
+    K = K(a) advects with a^{n+1} = 3/2 u^n - 1/2 u^{n-1}, and the velocity
+    load is F2 - (K U^n)_u + (N_i, 2 sigma u^n); pressure rows zero."""
+    pts, wts = quadrature(disc)
+    w = tensor_weights(wts)
+    v, _ = _field(disc, U, pts)
+    out = _load(disc, pts, w, 2.0 * sigma * v)
+    r = F2 - K @ U
+    out[:disc.n_v] += r[:disc.n_v]
     return out

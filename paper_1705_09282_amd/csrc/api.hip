@@ -943,6 +943,11 @@ Problem make_problem(const dfmg_grid *grid, int k, double nu, double sigma, cons
     if (adv) {
         pb.adv_kind = adv->kind;
         pb.adv_c = adv->c;
+        if (adv->kind == 3) {
+            if (!adv->coeffs) throw ArgError("advection kind 3 needs its field's coefficients");
+            const int64_t nv = (int64_t)pb.d * (pb.N + k - 1) * (int64_t)std::pow(pb.N + k, pb.d - 1);
+            pb.adv_field.assign(adv->coeffs, adv->coeffs + nv);
+        }
     }
     pb.share_inverses = o.share_inverses != 0;
     pb.potentials = o.precision == 1;
@@ -1564,10 +1569,12 @@ int dfmg_div_norm(dfmg_ctx *c, const double *U, double *out) {
 }
 
 // load of one Crank-Nicolson / Adams-Bashforth step into Fout (see dfmg.h)
-static void cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const double *Uold, double *Fout) {
+static void cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const double *Uold, double *Fout, int conv = 1) {
     if (!c->opt.time_stepping) throw StateError("set options.time_stepping = 1 before dfmg_setup");
-    for (const Hierarchy &Q : c->P)
-        if (Q.pb.adv_kind != 0) throw ArgError("the Crank-Nicolson / Adams-Bashforth step is a generalized Stokes problem");
+    if (conv)
+        for (const Hierarchy &Q : c->P)
+            if (Q.pb.adv_kind != 0)
+                throw ArgError("the Crank-Nicolson / Adams-Bashforth step is a generalized Stokes problem");
     const Hierarchy &H = c->S();
     const HostLevel &h = H.lv[H.pb.L - 1];
     spmv<double>(c, H.pb.L - 1, F2, U, Fout, nullptr, nullptr);  // F2 - K U^n
@@ -1592,7 +1599,18 @@ static void cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const doubl
     a.sG = c->npts * a.d;
     a.Fout = Fout;
     a.nprob = c->np;
+    a.conv = conv;
     launch_cnab_load(a, c->s);
+}
+
+extern "C" int dfmg_go_rhs(dfmg_ctx *c, const double *F2, const double *U, double *Fout) {
+    if (!c || !F2 || !U || !Fout) return fail(DFMG_EINVAL, "null argument");
+    return guarded([&] {
+        enter(c);
+        cnab_rhs(c, F2, U, nullptr, Fout, 0);
+        HIPCHK(hipGetLastError());
+        leave(c);
+    });
 }
 
 extern "C" int dfmg_cnab_rhs(dfmg_ctx *c, const double *F2, const double *U, const double *Uold, double *Fout) {

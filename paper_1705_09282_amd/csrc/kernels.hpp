@@ -306,6 +306,7 @@ struct CnabArgs {
     int64_t sG, npts;
     double *Fout;
     int nprob;
+    int conv;               // 1: the Adams-Bashforth convective terms; 0: none (2 sigma u only)
 };
 void launch_cnab_load(const CnabArgs &a, hipStream_t s);
 

@@ -1429,13 +1429,268 @@ static void pressure_integrals(const Problem &pb, HostLevel &L) {
     }
 }
 
+// ------------------------------------- advection by a field of the velocity space
+
+// slot of column (block C, stored index col) in row (block R, stored index
+// row) of the stencil-ELL layout, -1 outside the stored box
+static int stencil_slot(const HostLevel &L, int d, int k, int R, int C, int64_t row, int64_t col) {
+    BlockGeom G{d, k};
+    int slot = 0;
+    for (int C2 = 0; C2 < C; ++C2)
+        if (G.coupled(R, C2)) {
+            int w = 1;
+            for (int j = 0; j < d; ++j) w *= G.width(R, C2, j);
+            slot += w;
+        }
+    int o[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    for (int j = 0; j < 3; ++j) {
+        const int is = (int)(row % L.nb[R][j]), js = (int)(col % L.nb[C][j]);
+        row /= L.nb[R][j];
+        col /= L.nb[C][j];
+        if (j < d) {
+            W[j] = G.width(R, C, j);
+            o[j] = js - box_start(L.win, is, G.lo(R, C, j), W[j], L.nb[C][j]);
+            if (o[j] < 0 || o[j] >= W[j]) return -1;
+        }
+    }
+    return slot + (o[2] * W[1] + o[1]) * W[0] + o[0];
+}
+
+// Advection by c times a field a of the finest velocity space (kind 3): the
+// blocks (v_R, a . grad u_R) assembled by Gauss quadrature (k+3 points per
+// direction per element) on the finest grid, and on the coarser grids their
+// Galerkin products R C P through the prolongations (the operator's other
+// terms keep their Kronecker factors; the Galerkin product is linear).  The
+// terms are added to the stored values of every level.
+static void add_field_advection(const Problem &pb, Hierarchy &H) {
+    const int d = pb.d, k = pb.k, N = pb.N, nq = k + 3, L = pb.L;
+    HostLevel &F = H.lv[L - 1];
+    if ((int64_t)pb.adv_field.size() != F.n_v) throw std::runtime_error("advection field needs n_v coefficients");
+    std::vector<double> t, wt;
+    gauss_legendre(nq, t, wt);
+    const double h = 1.0 / N;
+    const auto kn0 = open_knots(N, k), kn1 = open_knots(N, k + 1);
+    BlockGeom G{d, k};
+    // per level, the advection values in the velocity rows (CSR)
+    struct Csr {
+        std::vector<int64_t> rp;
+        std::vector<int32_t> ci;
+        std::vector<double> v;
+    };
+    // fine level: element matrices over the quadrature points, scattered
+    // once per element into an array of the stencil-ELL shape
+    std::vector<double> adv(F.val.size(), 0.0);
+    const int E2 = d == 3 ? N : 1, G2 = d == 3 ? nq : 1;
+    double val[3][2][8], der[3][2][8];
+    struct Fn {
+        int64_t gidx;
+        int m[3];
+    };
+    for (int e2 = 0; e2 < E2; ++e2)
+        for (int e1 = 0; e1 < N; ++e1)
+            for (int e0 = 0; e0 < N; ++e0) {
+                const int e[3] = {e0, e1, e2};
+                // the functions of each velocity component non-zero on the element
+                std::vector<Fn> fns[3];
+                for (int c = 0; c < d; ++c) {
+                    int q[3] = {0, 0, 0};
+                    for (int jj = 0; jj < d; ++jj) q[jj] = G.q(c, jj);
+                    const int m2max = d == 3 ? q[2] : 0;
+                    for (int m2 = 0; m2 <= m2max; ++m2)
+                        for (int m1 = 0; m1 <= q[1]; ++m1)
+                            for (int m0 = 0; m0 <= q[0]; ++m0) {
+                                Fn f{0, {m0, m1, m2}};
+                                int64_t idx = 0, stride = 1;
+                                bool ok = true;
+                                for (int jj = 0; jj < d; ++jj) {
+                                    const int st = e[jj] + f.m[jj] - G.s(c, jj);
+                                    if (st < 0 || st >= F.nb[c][jj]) ok = false;
+                                    idx += (int64_t)st * stride;
+                                    stride *= F.nb[c][jj];
+                                }
+                                if (!ok) continue;
+                                f.gidx = F.off[c] + idx;
+                                fns[c].push_back(f);
+                            }
+                }
+                std::vector<double> E[3];
+                for (int c = 0; c < d; ++c) E[c].assign(fns[c].size() * fns[c].size(), 0.0);
+                std::vector<double> fv[3], fdv[3];
+                for (int g2 = 0; g2 < G2; ++g2)
+                    for (int g1 = 0; g1 < nq; ++g1)
+                        for (int g0 = 0; g0 < nq; ++g0) {
+                            const int g[3] = {g0, g1, g2};
+                            double wq = 1.0;
+                            for (int jj = 0; jj < d; ++jj) {
+                                const double x = (e[jj] + 0.5 * (t[g[jj]] + 1.0)) * h;
+                                wq *= 0.5 * h * wt[g[jj]];
+                                span_basis(kn0, k, e[jj] + k, x, val[jj][0], der[jj][0]);
+                                span_basis(kn1, k + 1, e[jj] + k + 1, x, val[jj][1], der[jj][1]);
+                            }
+                            double a[3] = {0, 0, 0};
+                            for (int c = 0; c < d; ++c) {
+                                const size_t nf = fns[c].size();
+                                fv[c].assign(nf, 0.0);
+                                fdv[c].assign(nf * 3, 0.0);
+                                for (size_t fi = 0; fi < nf; ++fi) {
+                                    const Fn &f = fns[c][fi];
+                                    double v = 1.0;
+                                    for (int jj = 0; jj < d; ++jj) v *= val[jj][G.q(c, jj) - k][f.m[jj]];
+                                    fv[c][fi] = v;
+                                    for (int dd = 0; dd < d; ++dd) {
+                                        double pp = 1.0;
+                                        for (int jj = 0; jj < d; ++jj)
+                                            pp *= (jj == dd ? der : val)[jj][G.q(c, jj) - k][f.m[jj]];
+                                        fdv[c][fi * 3 + dd] = pp;
+                                    }
+                                    a[c] += pb.adv_field[f.gidx] * v;
+                                }
+                            }
+                            for (int c = 0; c < d; ++c) a[c] *= pb.adv_c;
+                            for (int c = 0; c < d; ++c) {
+                                const size_t nf = fns[c].size();
+                                for (size_t bj = 0; bj < nf; ++bj) {
+                                    double adv_b = 0.0;
+                                    for (int dd = 0; dd < d; ++dd) adv_b += a[dd] * fdv[c][bj * 3 + dd];
+                                    adv_b *= wq;
+                                    for (size_t ai = 0; ai < nf; ++ai) E[c][ai * nf + bj] += fv[c][ai] * adv_b;
+                                }
+                            }
+                        }
+                for (int c = 0; c < d; ++c) {
+                    const size_t nf = fns[c].size();
+                    for (size_t ai = 0; ai < nf; ++ai) {
+                        const int64_t row = fns[c][ai].gidx - F.off[c];
+                        for (size_t bj = 0; bj < nf; ++bj) {
+                            const int slot = stencil_slot(F, d, k, c, c, row, fns[c][bj].gidx - F.off[c]);
+                            if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
+                            adv[F.ell_index(c, row, slot)] += E[c][ai * nf + bj];
+                        }
+                    }
+                }
+            }
+    // CSR of the fine advection (velocity rows, same-component columns)
+    Csr cur;
+    cur.rp.assign(1, 0);
+    for (int c = 0; c < d; ++c) {
+        int W[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
+        for (int jj = 0; jj < d; ++jj) {
+            W[jj] = G.width(c, c, jj);
+            lo[jj] = G.lo(c, c, jj);
+        }
+        const int64_t rows = F.off[c + 1] - F.off[c];
+        for (int64_t li = 0; li < rows; ++li) {
+            int is[3] = {0, 0, 0}, base[3] = {0, 0, 0};
+            int64_t tt = li;
+            for (int jj = 0; jj < 3; ++jj) {
+                is[jj] = (int)(tt % F.nb[c][jj]);
+                tt /= F.nb[c][jj];
+                if (jj < d) base[jj] = box_start(F.win, is[jj], lo[jj], W[jj], F.nb[c][jj]);
+            }
+            int slot = 0;  // block (c, c) comes first in a velocity row
+            for (int o2 = 0; o2 < W[2]; ++o2)
+                for (int o1 = 0; o1 < W[1]; ++o1)
+                    for (int o0 = 0; o0 < W[0]; ++o0, ++slot) {
+                        const int o[3] = {o0, o1, o2};
+                        int64_t col = 0, stride = 1;
+                        bool ok = true;
+                        for (int jj = 0; jj < d; ++jj) {
+                            const int js = base[jj] + o[jj];
+                            if (js < 0 || js >= F.nb[c][jj]) ok = false;
+                            col += (int64_t)js * stride;
+                            stride *= F.nb[c][jj];
+                        }
+                        const double v = adv[F.ell_index(c, li, slot)];
+                        if (!ok || v == 0.0) continue;
+                        cur.ci.push_back((int32_t)(F.off[c] + col));
+                        cur.v.push_back(v);
+                    }
+            cur.rp.push_back((int64_t)cur.ci.size());
+        }
+    }
+    for (size_t x = 0; x < adv.size(); ++x) F.val[x] += adv[x];
+    adv.clear();
+    adv.shrink_to_fit();
+    auto to_csr = [](std::vector<std::vector<std::pair<int32_t, double>>> &rows, Csr &out) {
+        out.rp.assign(1, 0);
+        out.ci.clear();
+        out.v.clear();
+        for (auto &r : rows) {
+            std::sort(r.begin(), r.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            for (size_t i2 = 0; i2 < r.size();) {
+                size_t j2 = i2;
+                double sum = 0.0;
+                while (j2 < r.size() && r[j2].first == r[i2].first) sum += r[j2++].second;
+                out.ci.push_back(r[i2].first);
+                out.v.push_back(sum);
+                i2 = j2;
+            }
+            out.rp.push_back((int64_t)out.ci.size());
+            r.clear();
+            r.shrink_to_fit();
+        }
+    };
+    auto add_to_level = [&](HostLevel &Lv, const Csr &Cm) {
+        for (int64_t r = 0; r < Lv.n_v; ++r) {
+            int R = 0;
+            while (r >= Lv.off[R + 1]) ++R;
+            for (int64_t e = Cm.rp[r]; e < Cm.rp[r + 1]; ++e) {
+                const int64_t col = Cm.ci[e];
+                int C = 0;
+                while (col >= Lv.off[C + 1]) ++C;
+                const int slot = stencil_slot(Lv, d, k, R, C, r - Lv.off[R], col - Lv.off[C]);
+                if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
+                Lv.val[Lv.ell_index(R, r - Lv.off[R], slot)] += Cm.v[e];
+            }
+        }
+    };
+    // coarser levels: R C P (R of level l maps it to level l - 1, P of level l
+    // maps level l - 1 to it; velocity rows only: both are block diagonal)
+    for (int l = L - 1; l >= 1; --l) {
+        const HostLevel &Fl = H.lv[l];
+        HostLevel &Cl = H.lv[l - 1];
+        std::vector<double> dense(Cl.n, 0.0);
+        std::vector<char> mark(Cl.n, 0);
+        std::vector<int32_t> touched;
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(Cl.n_v);
+        for (int64_t I = 0; I < Cl.n_v; ++I) {
+            touched.clear();
+            for (int32_t e1 = Fl.R_rp[I]; e1 < Fl.R_rp[I + 1]; ++e1) {
+                const int32_t i = Fl.R_ci[e1];
+                const double rv = Fl.R_v[e1];
+                for (int64_t e2 = cur.rp[i]; e2 < cur.rp[i + 1]; ++e2) {
+                    const int32_t j = cur.ci[e2];
+                    const double cv = rv * cur.v[e2];
+                    for (int32_t e3 = Fl.P_rp[j]; e3 < Fl.P_rp[j + 1]; ++e3) {
+                        const int32_t J = Fl.P_ci[e3];
+                        if (!mark[J]) {
+                            mark[J] = 1;
+                            touched.push_back(J);
+                        }
+                        dense[J] += cv * Fl.P_v[e3];
+                    }
+                }
+            }
+            for (int32_t J : touched) {
+                rows[I].push_back({J, dense[J]});
+                dense[J] = 0.0;
+                mark[J] = 0;
+            }
+        }
+        Csr next;
+        to_csr(rows, next);
+        add_to_level(Cl, next);
+        cur = std::move(next);
+    }
+}
+
 void build_hierarchy(const Problem &pb, Hierarchy &H) {
     if (pb.d != 2 && pb.d != 3) throw std::runtime_error("dim must be 2 or 3");
     if (pb.k != 1 && pb.k != 2) throw std::runtime_error("k must be 1 or 2");
     if (pb.L < 1 || pb.N < 1) throw std::runtime_error("n_elem and n_levels must be positive");
     if (pb.N % (1 << (pb.L - 1)) != 0) throw std::runtime_error("n_elem must be divisible by 2^(n_levels-1)");
     if (!(pb.nu > 0.0) || !(pb.sigma >= 0.0)) throw std::runtime_error("need nu > 0 and sigma >= 0");
-    if (pb.adv_kind < 0 || pb.adv_kind > 2) throw std::runtime_error("advection kind must be 0, 1 or 2");
+    if (pb.adv_kind < 0 || pb.adv_kind > 3) throw std::runtime_error("advection kind must be 0, 1, 2 or 3");
     H.pb = pb;
     const int L = pb.L;
     H.fac.assign(L, Factors());
@@ -1447,10 +1702,9 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         fill_matrix(pb, H.fac[l], H.lv[l]);
         pressure_integrals(pb, H.lv[l]);
     }
-    for (int l = 1; l < L; ++l) {
-        build_patches(pb, H.lv[l], pb.share_inverses);
-        build_prolongation(pb, H.lv[l - 1], H.lv[l]);
-    }
+    for (int l = 1; l < L; ++l) build_prolongation(pb, H.lv[l - 1], H.lv[l]);
+    if (pb.adv_kind == 3) add_field_advection(pb, H);
+    for (int l = 1; l < L; ++l) build_patches(pb, H.lv[l], pb.share_inverses && pb.adv_kind != 3);
     {
         HostLevel &C = H.lv[0];
         const int n = (int)C.n;

@@ -62,9 +62,12 @@ struct Problem {
     int d = 2, N = 0, L = 1, k = 1;
     double nu = 1.0, sigma = 1.0;
     // advection: 0 none; 1 rotation a = c (-(y - 1/2), x - 1/2[, 0]); 2 the
-    // manufactured velocity, a = c u (the paper's Oseen problems)
+    // manufactured velocity, a = c u (the paper's Oseen problems); 3 c times
+    // a field of the finest velocity space, coefficients adv_field (n_v, the
+    // canonical velocity order)
     int adv_kind = 0;
     double adv_c = 0.0;
+    std::vector<double> adv_field;
     bool share_inverses = true;
     bool potentials = false;   // build the potential-form maps of the FP32 cycle
     bool multiplicative = false;  // build the lane tables of the multiplicative sweep

@@ -1,3 +1,6 @@
+// Right-hand sides of the time steps (Guermond's step: conv = 0, no
+// convective terms, the advection being in the operator).
+//
 // Right-hand side of one Crank-Nicolson / Adams-Bashforth step of the
 // Navier-Stokes equations posed as a generalized Stokes problem with
 // sigma = 2 / dt (equation GS, with every term of the step doubled):
@@ -83,7 +86,7 @@ __global__ void k_cnab_points(CnabArgs a) {
     double v[3] = {0, 0, 0}, gr[3][3] = {}, vo[3] = {0, 0, 0}, gro[3][3] = {};
     for (int c = 0; c < a.d; ++c) {
         eval_comp(a, U, c, e, g, v[c], gr[c]);
-        if (Uo) eval_comp(a, Uo, c, e, g, vo[c], gro[c]);
+        if (Uo && a.conv) eval_comp(a, Uo, c, e, g, vo[c], gro[c]);
     }
     const double sigma = a.sigma[prob];
     double *G = a.G + prob * a.sG + P * a.d;
@@ -93,7 +96,7 @@ __global__ void k_cnab_points(CnabArgs a) {
             conv += v[j] * gr[c][j];
             convo += vo[j] * gro[c][j];
         }
-        const double adv = Uo ? 3.0 * conv - convo : 2.0 * conv;
+        const double adv = a.conv ? (Uo ? 3.0 * conv - convo : 2.0 * conv) : 0.0;
         G[c] = w * (2.0 * sigma * v[c] - adv);
     }
 }

@@ -32,7 +32,7 @@ class Grid(ctypes.Structure):
 
 
 class Advection(ctypes.Structure):
-    _fields_ = [("kind", c_int), ("c", c_double)]
+    _fields_ = [("kind", c_int), ("c", c_double), ("coeffs", c_dblp)]
 
 
 class Options(ctypes.Structure):
@@ -75,6 +75,7 @@ SIGNATURES = [
     ("dfmg_solve", c_int, [c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
     ("dfmg_cnab_rhs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("dfmg_cnab_step", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, ctypes.POINTER(Stats)]),
+    ("dfmg_go_rhs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("dfmg_residual_norm", c_int, [c_void_p, c_void_p, c_void_p, c_dblp]),
     ("dfmg_div_norm", c_int, [c_void_p, c_void_p, c_dblp]),
     ("dfmg_level_residual", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
@@ -144,12 +145,30 @@ def lib():
     return _lib
 
 
-def _advection(c, kind):
+def _advection(c, kind, coeffs=None, keep=None):
     """dfmg_advection of speed c: kind None takes rotation (1) for c != 0 and
-    none (0) otherwise; kind 2 advects with c times the manufactured velocity."""
+    none (0) otherwise; kind 2 advects with c times the manufactured velocity,
+    kind 3 with c times the finest-grid velocity field `coeffs` (the array is
+    appended to `keep`, which must outlive the setup call)."""
     if kind is None:
         kind = 1 if c != 0.0 else 0
-    return Advection(int(kind), float(c))
+    a = Advection(int(kind), float(c), None)
+    if kind == 3:
+        arr = np.ascontiguousarray(coeffs, dtype=np.float64)
+        keep.append(arr)
+        a.coeffs = _ptr(arr, ctypes.c_double)
+    return a
+
+
+def _per_problem(coeffs, nprob):
+    """One coefficient array per problem from a single array or a list."""
+    if coeffs is None:
+        return [None] * nprob
+    if isinstance(coeffs, (list, tuple)):
+        if len(coeffs) != nprob:
+            raise ValueError("one advection field per problem")
+        return list(coeffs)
+    return [coeffs] * nprob
 
 
 def _network_args(W, rho_plain, nprob):
@@ -253,10 +272,11 @@ class Solver:
     A Solver is the batch of one; BatchSolver holds several problems on the
     same mesh and solves them together."""
 
-    def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, adv_kind=None, **options):
-        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options, adv_kind)
+    def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, adv_kind=None, adv_coeffs=None,
+                 **options):
+        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options, adv_kind, adv_coeffs)
 
-    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options, adv_kind=None):
+    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options, adv_kind=None, adv_coeffs=None):
         self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
         self.nprob = len(nus)
         self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
@@ -264,7 +284,9 @@ class Solver:
             raise ValueError("one nu, sigma and c per problem")
         g = Grid(dim, n_elem, n_levels)
         self.adv_kind = adv_kind
-        adv = (Advection * self.nprob)(*[_advection(c, adv_kind) for c in cs])
+        keep = []
+        fields = _per_problem(adv_coeffs, self.nprob)
+        adv = (Advection * self.nprob)(*[_advection(c, adv_kind, f, keep) for c, f in zip(cs, fields)])
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)
@@ -410,6 +432,12 @@ class Solver:
         n = self.n * self.nprob
         _check(lib().dfmg_cnab_rhs(self._ctx, _dev(F2, n), _dev(U, n), None if Uold is None else _dev(Uold, n),
                                    _dev(Fout, n)))
+
+    def go_rhs(self, F2, U, Fout):
+        """Load of Guermond's step (the context's operator advects with
+        3/2 u^n - 1/2 u^{n-1}); needs time_stepping=1."""
+        n = self.n * self.nprob
+        _check(lib().dfmg_go_rhs(self._ctx, _dev(F2, n), _dev(U, n), _dev(Fout, n)))
 
     def cnab_step(self, F2, Uold, U, Unext, tol=1e-8, raise_on_error=True):
         """One Crank-Nicolson / Adams-Bashforth step: Unext = U^{n+1} from U
@@ -617,9 +645,9 @@ class BatchSolver(Solver):
     kernel launch covers the whole batch.  Vectors are problem-major blocks of
     the finest-level length n."""
 
-    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, adv_kind=None, **options):
+    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, adv_kind=None, adv_coeffs=None, **options):
         cs = [0.0] * len(nus) if cs is None else list(cs)
-        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options, adv_kind)
+        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options, adv_kind, adv_coeffs)
 
     def solve(self, F, U, tol=1e-8, raise_on_error=True):
         return self._solve(F, U, tol, raise_on_error)
@@ -648,7 +676,8 @@ class MultiSolver:
         grids = (Grid * self.nprob)(*[Grid(d, N, L) for (d, N, L, _k) in self.meshes])
         ks = np.ascontiguousarray([m[3] for m in self.meshes], dtype=np.int32)
         self.adv_kind = adv_kind
-        adv = (Advection * self.nprob)(*[_advection(c, adv_kind) for c in cs])
+        keep = []
+        adv = (Advection * self.nprob)(*[_advection(c, adv_kind, None, keep) for c in cs])
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)

@@ -82,8 +82,8 @@ def test_multi_matches_oracle():
 
 def test_multi_errors():
     from paper_1705_09282_amd.dfmg import MultiSolver, DfmgError
-    with pytest.raises(DfmgError):
-        MultiSolver([(3, 8, 2, 1), (2, 16, 3, 1)], [1.0, 1.0], [1.0, 1.0], precision=1)
+    with pytest.raises(DfmgError):  # multiplicative Schwarz runs in FP64 cycles only
+        MultiSolver([(3, 8, 2, 1), (2, 16, 3, 1)], [1.0, 1.0], [1.0, 1.0], precision=1, multiplicative=1)
     with pytest.raises(DfmgError):
         MultiSolver([(2, 12, 4, 1)], [1.0], [1.0])  # 12 not divisible by 2^3
     M = MultiSolver([(2, 16, 3, 1)], [1.0], [1.0])

@@ -13,6 +13,16 @@
   independently (sigma = 1, nu = 0, which drops the Nitsche terms).
 * The first step (no u^{n-1}) equals a step with u^{n-1} = u^n, and the
   pressure rows are zero.
+
+Guermond's step (equation GO):
+
+* The advection by a discrete field whose coefficients are the polar forms
+  of (x(1-x), 0[, 0]) assembles the same operator as the analytic field.
+* Advecting the discrete field u by itself, K(u) U - K(0) U is the
+  convective load N(u) of the CN/AB pins on the velocity rows (the
+  assembly's advection term and the load's quadrature are separate code).
+* The load is F2 - K(a) U + 2 sigma M u on the velocity rows (M assembled
+  independently) and zero on the pressure rows.
 """
 import itertools
 import math
@@ -25,7 +35,7 @@ from oracle.spaces import Discretization
 from oracle.assemble import assemble
 from oracle.bspline import open_knots
 from oracle.complex import random_divfree_start
-from oracle.timestep import convective_load, cnab_rhs
+from oracle.timestep import convective_load, cnab_rhs, field_advection, go_rhs
 
 
 def _blossom(knots, q, poly):
@@ -95,3 +105,51 @@ def test_cnab_linear_part_and_first_step(d, N, k):
     assert np.all(a[disc.n_v:] == 0.0)
     np.testing.assert_allclose(a - cnab_rhs(disc, K, sigma, zero, U), np.concatenate([F2[:disc.n_v], np.zeros(disc.n_q)]),
                                rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("d,N,k", [(2, 5, 1), (2, 4, 2), (3, 3, 1)])
+def test_field_advection_polynomial(d, N, k):
+    c = 1.7
+    disc = Discretization(d, N, k)
+    W = np.zeros(disc.n_v)
+    W[:disc.offsets[1]] = _coeffs(disc, 0, [[0.0, 1.0, -1.0]] + [[1.0]] * (d - 1))
+
+    def analytic(X):
+        out = np.zeros_like(X)
+        out[:, 0] = c * X[:, 0] * (1.0 - X[:, 0])
+        return out
+    got = assemble(disc, 0.4, 2.0, advection=field_advection(disc, W, c))["K"]
+    want = assemble(disc, 0.4, 2.0, advection=analytic)["K"]
+    assert abs(got - want).max() <= 1e-13 * abs(want).max()
+
+
+@pytest.mark.parametrize("d,N,k", [(2, 6, 1), (2, 5, 2), (3, 3, 2)])
+def test_field_advection_is_convection(d, N, k):
+    disc = Discretization(d, N, k)
+    U = random_divfree_start(disc, workloads.random_coefficients(disc.n_psi, 11),
+                             workloads.random_coefficients(disc.n_q, 12))
+    Ka = assemble(disc, 0.5, 3.0, advection=field_advection(disc, U[:disc.n_v]))["K"]
+    K0 = assemble(disc, 0.5, 3.0)["K"]
+    got = (Ka @ U - K0 @ U)
+    want = convective_load(disc, U)
+    np.testing.assert_allclose(got[:disc.n_v], want[:disc.n_v], rtol=0, atol=1e-12 * np.abs(want).max())
+    assert np.all(got[disc.n_v:] == 0.0)
+
+
+@pytest.mark.parametrize("d,N,k", [(2, 6, 1), (3, 3, 1)])
+def test_go_rhs_linear(d, N, k):
+    nu, sigma = 0.2, 5.0
+    disc = Discretization(d, N, k)
+    U = random_divfree_start(disc, workloads.random_coefficients(disc.n_psi, 21),
+                             workloads.random_coefficients(disc.n_q, 22))
+    Uo = random_divfree_start(disc, workloads.random_coefficients(disc.n_psi, 23),
+                              workloads.random_coefficients(disc.n_q, 24))
+    a = 1.5 * U[:disc.n_v] - 0.5 * Uo[:disc.n_v]
+    K = assemble(disc, nu, sigma, advection=field_advection(disc, a))["K"]
+    M = assemble(disc, 0.0, 1.0)["A"]
+    F2 = workloads.random_coefficients(disc.n, 25)
+    F2[disc.n_v:] = 0.0
+    got = go_rhs(disc, K, sigma, F2, U)
+    want = np.zeros(disc.n)
+    want[:disc.n_v] = F2[:disc.n_v] - (K @ U)[:disc.n_v] + 2 * sigma * (M @ U[:disc.n_v])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())

@@ -44,6 +44,12 @@ module, each against a fact the paper or the mathematics fixes:
   the advection by a discrete polynomial field against the analytic field;
   a field advecting itself against the convective load; the Guermond load's
   linear part against an independent mass matrix.
+* ``geometry``: the Bezier arc against the unit circle, J and its
+  derivatives against finite differences of the map, the identity map
+  against the unit-domain assembly, the Piola divergence identity, the whole
+  operator on the annulus and cylinder section against an independent
+  assembly in cylindrical coordinates, and B^T u = 0 for divergence-free
+  starts.
 
 None of these functions is "parity unpinned".
 """

@@ -42,14 +42,20 @@ class Level:
 
 class Hierarchy:
     """Levels 0 (coarsest) .. L-1 (finest); K on the finest level is
-    assembled, coarser ones are Galerkin products."""
+    assembled (on the unit square / cube, or on a mapped domain), coarser
+    ones are Galerkin products."""
 
-    def __init__(self, d, n_elem, k, n_levels, nu, sigma, advection=None):
+    def __init__(self, d, n_elem, k, n_levels, nu, sigma, advection=None, geometry=None):
         assert n_elem % (2 ** (n_levels - 1)) == 0
         self.d, self.k, self.L = d, k, n_levels
         self.nu, self.sigma = nu, sigma
         finest = Discretization(d, n_elem, k)
-        mats = assemble(finest, nu, sigma, advection)
+        if geometry is None:
+            mats = assemble(finest, nu, sigma, advection)
+        else:  # a mapped domain (generalized Stokes)
+            assert advection is None
+            from .geometry import assemble_mapped
+            mats = assemble_mapped(finest, geometry, nu, sigma)
         levels = [Level(finest, mats["K"])]
         self.A, self.B = mats["A"], mats["B"]
         for _ in range(n_levels - 1):

@@ -197,6 +197,64 @@ def stokes3d_legs(dev, steps=3, warmup=1):
     return out
 
 
+def annulus_legs(dev, steps=3, warmup=1):
+    """The benchmark's discretization on the paper's quarter annulus
+    (context): 2D generalized Stokes, k=2, 256^2 elements, 6 grids, nu = 1,
+    the four sigma as one batch, a seeded random velocity load (the paper's
+    manufactured solution is defined on the unit square), solved from U = 0
+    to 1e-8: FP64 additive with the fixed damping V(2,2), FP64
+    multiplicative V(1,2), and FP32 refinement with the learned Chebyshev
+    schedule; the host setup (quadrature assembly through the Piola maps,
+    Galerkin products, per-subdomain inverses) reported apart; the FP32
+    residual, whose velocity rows couple both components, timed alone."""
+    import torch
+    import workloads
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd import learned
+    sig = [1e-2, 1.0, 1e2, 1e4]
+    out = {"workload": "quarter annulus r_i=0.075 r_o=0.225, 2D generalized Stokes, k=2, 256^2, 6 grids, nu=1, "
+                       "sigma in {1e-2, 1, 1e2, 1e4}, seeded random velocity load, tol 1e-8, U0=0"}
+    for name, opt, sched in (("fp64_additive_fixed_damping", {}, False),
+                             ("fp64_multiplicative_v12", {"multiplicative": 1, "nu1": 1, "nu2": 2}, False),
+                             ("fp32_refined_learned_chebyshev", {"precision": 1}, True)):
+        t0 = time.perf_counter()
+        b = BatchSolver(2, 256, 6, 2, [1.0] * len(sig), sig, geometry=1, max_cycles=400, **opt).bind(dev)
+        setup = time.perf_counter() - t0
+        b.autotune(reps=10)
+        if sched:
+            learned.apply_chebyshev(b)
+        n = b.n
+        F = workloads.random_coefficients(len(sig) * n, 91)
+        nv = 2 * (256 + 1) * (256 + 2)
+        for p in range(len(sig)):
+            F[p * n + nv:(p + 1) * n] = 0.0
+        F = torch.tensor(F, device=dev)
+        U = torch.zeros_like(F)
+        for _ in range(warmup):
+            U.zero_()
+            b.solve(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U.zero_()
+            st = b.solve(F, U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"setup_s": setup, "ms_per_solve": 1e3 * dt, "dofs_per_s": len(sig) * (n - 1) / dt,
+                     "cycles_per_sigma": [x["cycles"] for x in st], "fallback": [x.get("fallback") for x in st],
+                     "max_div_norm": float(b.div_norm(U).max())}
+        if sched:
+            ms = b.time_kernel(1, 5, reps=50)
+            z = b.sizes()
+            alg = len(sig) * (4 * z["nnz"] + 3 * 4 * z["n"])
+            out["fp32_residual_finest"] = {"ms": ms, "GBps": alg / (ms * 1e-3) / 1e9,
+                                           "stored_values_per_problem": z["nnz"]}
+        b.close()
+    out["speedup_fp32_vs_fp64_additive"] = (out["fp64_additive_fixed_damping"]["ms_per_solve"] /
+                                           out["fp32_refined_learned_chebyshev"]["ms_per_solve"])
+    return out
+
+
 def cnab_legs(dev, nsteps=10):
     """Navier-Stokes by Crank-Nicolson / Adams-Bashforth steps (context):
     2D, k=2, 256^2, 6 grids, nu = 0.1, dt = 1e-3 (sigma = 2000; |u| dt / h
@@ -556,6 +614,8 @@ def main():
         line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
         print("[bench] the 3D workload (context)", file=sys.stderr, flush=True)
         line["config"]["stokes3d"] = stokes3d_legs(dev)
+        print("[bench] the quarter annulus (context)", file=sys.stderr, flush=True)
+        line["config"]["annulus"] = annulus_legs(dev)
         print("[bench] Navier-Stokes CN/AB steps (context)", file=sys.stderr, flush=True)
         line["config"]["navier_stokes_cnab"] = cnab_legs(dev)
         print("[bench] Navier-Stokes Guermond steps (context)", file=sys.stderr, flush=True)

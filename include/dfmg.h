@@ -48,13 +48,32 @@ extern "C" {
 
 typedef struct dfmg_ctx dfmg_ctx;
 
-/* Unit square (dim 2) or cube (dim 3) split into n_elem^dim equal elements on
- * the finest grid; n_levels nested grids obtained by halving, so n_elem must be
- * divisible by 2^(n_levels-1) (coarsest grid n_elem / 2^(n_levels-1) >= 1). */
+/* The parametric unit square (dim 2) or cube (dim 3) split into n_elem^dim
+ * equal elements on the finest grid; n_levels nested grids obtained by
+ * halving, so n_elem must be divisible by 2^(n_levels-1) (coarsest grid
+ * n_elem / 2^(n_levels-1) >= 1).
+ *
+ * geometry 0: the physical domain is the unit square / cube itself.
+ * geometry 1: the quarter annulus of the paper's mapped 2D test (and, in 3D,
+ *   the hollow cylinder section: that annulus extruded along z by depth),
+ *   x = r (cos theta, sin theta) [, depth xi_3] with r = r_inner + (r_outer -
+ *   r_inner) xi_1 and theta(xi_2) the quarter circle from the x axis to the
+ *   y axis as a quadratic rational Bezier arc (section on isogeometric
+ *   compatible B-splines, equations physical_2D and physical_3D: velocities
+ *   by the contravariant Piola map, pressures by q o F = q_hat / det J).  The
+ *   coefficient vectors keep the parametric layout; the operators are the
+ *   physical ones (the velocity rows couple every component), assembled by
+ *   quadrature on the finest grid and by Galerkin products below.  Takes
+ *   generalized Stokes problems only (advection kind 0), no time stepping and
+ *   no manufactured load (the caller assembles F); the residual runs with
+ *   one lane per row and no single-workgroup coarse cycle.  Zero-filled
+ *   fields (geometry 0) keep the unit domain. */
 typedef struct {
     int dim;
     int n_elem;
     int n_levels;
+    int geometry;
+    double r_inner, r_outer, depth;  /* geometry 1: 0 < r_inner < r_outer; depth > 0 in 3D */
 } dfmg_grid;
 
 /* Advection field of the generalized Oseen problem (paper, weak form).

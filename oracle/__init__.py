@@ -48,8 +48,9 @@ module, each against a fact the paper or the mathematics fixes:
   derivatives against finite differences of the map, the identity map
   against the unit-domain assembly, the Piola divergence identity, the whole
   operator on the annulus and cylinder section against an independent
-  assembly in cylindrical coordinates, and B^T u = 0 for divergence-free
-  starts.
+  assembly in cylindrical coordinates, B^T u = 0 for divergence-free
+  starts, and the mapped divergence norm against the unit-domain norm
+  (identity map) and the physical-gradient quadrature.
 
 None of these functions is "parity unpinned".
 """

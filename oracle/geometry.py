@@ -212,3 +212,14 @@ def smooth_forcing(geom):
             out[:, 2] = np.cos(np.pi * x[:, 2] / geom.depth)
         return out
     return f
+
+
+def div_norm_mapped(disc, geom, U):
+    """||div u_h||_{L2(Omega)}: div u = div_hat u_hat / det J and dx = det J dxi
+    give the integral of (div_hat u_hat)^2 / det J over the parametric domain."""
+    from .diagnostics import div_values
+    pts, wts = quadrature(disc)
+    w = tensor_weights(wts)
+    _, J, _ = geom.geometry(tensor_points(pts))
+    dv = div_values(disc, U, pts)
+    return float(np.sqrt(np.sum(w * dv * dv / np.linalg.det(J))))

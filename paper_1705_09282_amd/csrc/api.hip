@@ -354,6 +354,7 @@ SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double 
         for (int j = 0; j < 3; ++j) a.nb[R][j] = R < h.nblk ? h.nb[R][j] : 1;
     a.n = (int)h.n;
     a.win = h.win ? 1 : 0;
+    a.xc = c->S().pb.geometry != 0 ? 1 : 0;
     a.nblocks = spmv_blocks(h.n, c->lpr[l]);
     a.F = F;
     a.U = U;
@@ -949,6 +950,15 @@ Problem make_problem(const dfmg_grid *grid, int k, double nu, double sigma, cons
             pb.adv_field.assign(adv->coeffs, adv->coeffs + nv);
         }
     }
+    pb.geometry = grid->geometry;
+    if (pb.geometry == 1) {
+        pb.r_in = grid->r_inner;
+        pb.r_out = grid->r_outer;
+        pb.depth = grid->depth;
+        if (o.time_stepping) throw ArgError("time stepping runs on the unit square / cube");
+    } else if (pb.geometry != 0) {
+        throw ArgError("geometry must be 0 or 1");
+    }
     pb.share_inverses = o.share_inverses != 0;
     pb.potentials = o.precision == 1;
     pb.multiplicative = o.multiplicative == 1;
@@ -987,7 +997,7 @@ void init_ctx(dfmg_ctx *c, const dfmg_options &o) {
     c->lpr.assign(L, 1);
     for (int l = 0; l < L; ++l) {
         const int64_t n = c->S().lv[l].n * c->np;
-        c->lpr[l] = n < 20000 ? 4 : (n < 100000 ? 2 : 1);
+        c->lpr[l] = c->S().pb.geometry != 0 ? 1 : (n < 20000 ? 4 : (n < 100000 ? 2 : 1));
     }
     c->small_top = 0;
     c->tile.assign(L, TileShape{});
@@ -1788,11 +1798,14 @@ int dfmg_set_tuning(dfmg_ctx *c, const int *lpr, const int *smoother) {
     while (top + 1 < L && smoother[top + 1] == 5) ++top;
     for (int l = 0; l < L; ++l) {
         if (!(lpr[l] == 1 || lpr[l] == 2 || lpr[l] == 4)) return fail(DFMG_EINVAL, "lpr must be 1, 2 or 4");
+        if (c->S().pb.geometry != 0 && lpr[l] != 1) return fail(DFMG_EINVAL, "mapped domains take lpr 1");
         const bool in_small = l >= 1 && l <= top;
         if (!in_small && !(smoother[l] >= 1 && smoother[l] <= 4))
             return fail(DFMG_EINVAL, "smoother must be 1 .. 4, or 5 on levels 1 .. t");
     }
     if (top > L - 2) return fail(DFMG_EINVAL, "the finest level cannot run in the single-workgroup cycle");
+    if (top > 0 && c->S().pb.geometry != 0)
+        return fail(DFMG_EINVAL, "mapped domains do not run the single-workgroup cycle");
     return guarded([&] {
         for (int l = 0; l < L; ++l) {
             c->lpr[l] = lpr[l];
@@ -1889,6 +1902,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
                 double best = 1e30;
                 int bl = c->lpr[l];
                 for (int lp : {1, 2, 4}) {
+                    if (c->S().pb.geometry != 0 && lp != 1) continue;  // mapped: one lane per row
                     c->lpr[l] = lp;
                     const double t = timed([&] { spmv<T>(c, l, v.F, v.U, v.r, nullptr, nullptr); });
                     if (t < best) {
@@ -1931,7 +1945,8 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         reset_flags(c);
         int best_top = 0;
         double best_t = 1e30;
-        for (int t = 0; t <= (c->mixed() || c->mult() ? 0 : L - 2); ++t) {  // the FP32 cycle tracks potentials: no t
+        // the FP32 cycle tracks potentials, mapped domains couple components: no t
+        for (int t = 0; t <= (c->mixed() || c->mult() || c->S().pb.geometry != 0 ? 0 : L - 2); ++t) {
             if (t >= 1 && c->S().lv[t].n > kSmallCycleMax) break;
             c->small_top = t;
             const double ms = timed([&] {
@@ -1978,7 +1993,7 @@ int dfmg_autotune(dfmg_ctx *c, int reps, double *ms_out) {
         for (int l = L - 1; l > c->small_top && l >= 1; --l) {
             int bl = c->lpr[l];
             for (int lp : {1, 2, 4}) {
-                if (lp == bl) continue;
+                if (lp == bl || (c->S().pb.geometry != 0 && lp != 1)) continue;
                 c->lpr[l] = lp;
                 const double t = cycle_ms();
                 if (t < 0.995 * cur) {
@@ -2282,7 +2297,7 @@ int dfmg_export_matrix(const dfmg_ctx *c, int level, int64_t *rowptr, int32_t *c
         const Hierarchy &H = c->S();
         const HostLevel &h = H.lv[level];
         const int d = H.pb.d;
-        BlockGeom G{d, H.pb.k};
+        BlockGeom G{d, H.pb.k, H.pb.geometry != 0};
         int64_t nz = 0;
         rowptr[0] = 0;
         for (int R = 0; R <= d; ++R) {

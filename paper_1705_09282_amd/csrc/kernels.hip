@@ -646,7 +646,8 @@ void launch_div(const DivArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_div, dim3(blocks_for(n)), dim3(kBlock), 0, s, a);
 }
 
-// partial sums of d_i (M_q d)_i, M_q the tensor product of 1D pressure masses.
+// partial sums of d_i (M_q d)_i, M_q the tensor product of 1D pressure masses
+// (one per direction: on a mapped domain they carry the factors of 1 / det J).
 __global__ __launch_bounds__(kBlock) void k_div_mass(DivArgs a) {
     __shared__ double sh[kBlock / 64];
     const int nq = a.N + a.k, W = 2 * a.k + 1;
@@ -660,11 +661,11 @@ __global__ __launch_bounds__(kBlock) void k_div_mass(DivArgs a) {
         for (int o2 = z0; o2 <= z1; ++o2) {
             const int i2 = j2 + o2;
             if (i2 < 0 || i2 >= nq) continue;
-            const double m2 = a.d == 3 ? a.pmass[j2 * W + o2 + a.k] : 1.0;
+            const double m2 = a.d == 3 ? a.pmass[(2 * nq + j2) * W + o2 + a.k] : 1.0;
             for (int o1 = -a.k; o1 <= a.k; ++o1) {
                 const int i1 = j1 + o1;
                 if (i1 < 0 || i1 >= nq) continue;
-                const double m1 = a.pmass[j1 * W + o1 + a.k];
+                const double m1 = a.pmass[(nq + j1) * W + o1 + a.k];
                 for (int o0 = -a.k; o0 <= a.k; ++o0) {
                     const int i0 = j0 + o0;
                     if (i0 < 0 || i0 >= nq) continue;

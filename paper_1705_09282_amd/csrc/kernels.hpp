@@ -51,6 +51,7 @@ struct SpmvArgsT {
     int nb[4][3];
     int n;
     int win;            // boxes stored as in-grid windows (see HostLevel)
+    int xc;             // velocity rows couple every velocity component (mapped domain)
     int nblocks;        // logical blocks covering n rows (spmv_blocks)
     const T *F;
     const T *U;

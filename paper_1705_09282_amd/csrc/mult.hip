@@ -17,7 +17,7 @@
 
 namespace dfmg {
 
-template <int D, int K, bool WIN, int B, class T>
+template <int D, int K, bool WIN, bool XC, int B, class T>
 __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     const int prob = blockIdx.y;
     const int halt = stop_flag(a.sp.stop, prob);  // block-uniform
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     if (e >= 0) {
         g = a.pdofs[e];
         info = a.ent_info[(int64_t)prob * a.nent + e];
-        r = sp.F[g] - spmv_row<D, K, WIN, T>(sp, g);
+        r = sp.F[g] - spmv_row<D, K, WIN, XC, T>(sp, g);
     }
     sr[threadIdx.x] = r;
     __syncthreads();
@@ -51,11 +51,17 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     }
 }
 
+template <int D, int K, bool XC, int B, class T>
+static void launch_dkxb(const MultArgsT<T> &a, hipStream_t s) {
+    const dim3 grid(a.nwaves, a.sp.nprob);
+    if (a.sp.win) hipLaunchKernelGGL((k_schwarz_mult<D, K, true, XC, B, T>), grid, dim3(B), 0, s, a);
+    else hipLaunchKernelGGL((k_schwarz_mult<D, K, false, XC, B, T>), grid, dim3(B), 0, s, a);
+}
+
 template <int D, int K, int B, class T>
 static void launch_dkb(const MultArgsT<T> &a, hipStream_t s) {
-    const dim3 grid(a.nwaves, a.sp.nprob);
-    if (a.sp.win) hipLaunchKernelGGL((k_schwarz_mult<D, K, true, B, T>), grid, dim3(B), 0, s, a);
-    else hipLaunchKernelGGL((k_schwarz_mult<D, K, false, B, T>), grid, dim3(B), 0, s, a);
+    if (a.sp.xc) launch_dkxb<D, K, true, B, T>(a, s);
+    else launch_dkxb<D, K, false, B, T>(a, s);
 }
 
 template <int D, int K, class T>

@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 #include <utility>
 
 namespace dfmg {
@@ -382,9 +384,12 @@ static int box_start(bool win, int i, int lo, int W, int n) {
     return win ? std::min(std::max(i + lo, 0), n - W) : i + lo;
 }
 
+// Allocates the stencil-ELL values of a level and, on the unit square / cube,
+// fills them from the Kronecker terms (a mapped domain's values come from
+// assemble_mapped).
 static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
     const int d = pb.d;
-    BlockGeom G{d, pb.k};
+    BlockGeom G{d, pb.k, pb.geometry != 0};
     // window layout when every box fits inside the grid in every direction
     L.win = true;
     for (int R = 0; R <= d; ++R)
@@ -408,11 +413,14 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
     }
     L.val_off[d + 1] = tot;
     L.val.assign(tot, 0.0);
+    if (pb.geometry != 0) return;
     for (int R = 0; R <= d; ++R) {
         const int64_t rows = L.off[R + 1] - L.off[R];
         int slot0 = 0;
-        for (int C = 0; C <= d; ++C) {
-            if (!G.coupled(R, C)) continue;
+        int cs[4];
+        const int ncs = G.order(R, cs);
+        for (int ci = 0; ci < ncs; ++ci) {
+            const int C = cs[ci];
             const auto terms = make_terms(pb, F, R, C);
             int W[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
             for (int j = 0; j < d; ++j) {
@@ -465,18 +473,11 @@ static int block_of(const HostLevel &L, int64_t g) {
 
 static double entry(const Problem &pb, const HostLevel &L, int64_t grow, int64_t gcol) {
     const int d = pb.d;
-    BlockGeom G{d, pb.k};
+    BlockGeom G{d, pb.k, pb.geometry != 0};
     const int R = block_of(L, grow), C = block_of(L, gcol);
     if (!G.coupled(R, C)) return 0.0;
     int64_t a = grow - L.off[R], b = gcol - L.off[C];
-    const int64_t rows = L.off[R + 1] - L.off[R];
-    int slot = 0;
-    for (int C2 = 0; C2 < C; ++C2)
-        if (G.coupled(R, C2)) {
-            int w = 1;
-            for (int j = 0; j < d; ++j) w *= G.width(R, C2, j);
-            slot += w;
-        }
+    int slot = G.slot_base(R, C);
     int o[3] = {0, 0, 0}, W[3] = {1, 1, 1};
     for (int j = 0; j < 3; ++j) {
         const int is = (int)(a % L.nb[R][j]), js = (int)(b % L.nb[C][j]);
@@ -1429,19 +1430,13 @@ static void pressure_integrals(const Problem &pb, HostLevel &L) {
     }
 }
 
-// ------------------------------------- advection by a field of the velocity space
 
 // slot of column (block C, stored index col) in row (block R, stored index
 // row) of the stencil-ELL layout, -1 outside the stored box
-static int stencil_slot(const HostLevel &L, int d, int k, int R, int C, int64_t row, int64_t col) {
-    BlockGeom G{d, k};
-    int slot = 0;
-    for (int C2 = 0; C2 < C; ++C2)
-        if (G.coupled(R, C2)) {
-            int w = 1;
-            for (int j = 0; j < d; ++j) w *= G.width(R, C2, j);
-            slot += w;
-        }
+static int stencil_slot(const HostLevel &L, const BlockGeom &G, int R, int C, int64_t row, int64_t col) {
+    if (!G.coupled(R, C)) return -1;
+    const int d = G.d;
+    int slot = G.slot_base(R, C);
     int o[3] = {0, 0, 0}, W[3] = {1, 1, 1};
     for (int j = 0; j < 3; ++j) {
         const int is = (int)(row % L.nb[R][j]), js = (int)(col % L.nb[C][j]);
@@ -1455,6 +1450,186 @@ static int stencil_slot(const HostLevel &L, int d, int k, int R, int C, int64_t 
     }
     return slot + (o[2] * W[1] + o[1]) * W[0] + o[0];
 }
+
+// Host threads for the setup loops (the GPU machines give a process 16 cores).
+static int setup_threads() {
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(h == 0 ? 1u : h, 16u));
+}
+
+// Runs body(i) for i in [0, n) on setup_threads() threads, contiguous chunks.
+template <class F>
+static void parallel_for(int64_t n, F body) {
+    const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n, 1));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) body(i, 0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    std::vector<std::exception_ptr> err(nt);
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) body(i, t);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    for (auto &th : pool) th.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+
+// Runs body(e0, e1, e2, thread) for every element of the N^d grid, colour by
+// colour with colour (e mod (k+2)) per direction, the elements of a colour on
+// the setup threads.  Two elements of one colour are k+2 apart in some
+// direction and share no basis function (a function's support spans at most
+// k+2 elements per direction), so bodies that add into the rows of their
+// element's functions never collide, and every entry sums its elements in
+// colour order whatever the thread count.
+template <class F>
+static void for_each_element_coloured(int d, int N, int k, F body) {
+    const int stride = k + 2, ncol2 = d == 3 ? stride : 1;
+    for (int c2 = 0; c2 < ncol2; ++c2)
+        for (int c1 = 0; c1 < stride; ++c1)
+            for (int c0 = 0; c0 < stride; ++c0) {
+                const int n0 = (N - c0 + stride - 1) / stride, n1 = (N - c1 + stride - 1) / stride;
+                const int n2 = d == 3 ? (N - c2 + stride - 1) / stride : 1;
+                parallel_for((int64_t)n0 * n1 * n2, [&](int64_t i, int th) {
+                    const int i0 = (int)(i % n0), i1 = (int)((i / n0) % n1), i2 = (int)(i / ((int64_t)n0 * n1));
+                    body(c0 + stride * i0, c1 + stride * i1, c2 + stride * i2, th);
+                });
+            }
+}
+
+// ------------------------------------------- sparse Galerkin products (host)
+
+// rows of a level operator (or of one of its terms) in CSR form, global
+// indices of the level
+struct Csr {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+};
+
+// Rows 0 .. nrows-1 of the Galerkin product R A P on the coarser level
+// (ncoarse DOFs), A in CSR over the finer level Fl, whose transfers R and P
+// it uses; columns sorted.  Chunks of rows on the setup threads, each row
+// summed in the same order whatever the chunking.
+static Csr galerkin_rows(const HostLevel &Fl, const Csr &A, int64_t nrows, int64_t ncoarse) {
+    const int nch = setup_threads();
+    std::vector<Csr> part(nch);
+    parallel_for(nch, [&](int64_t ch, int) {
+        Csr &out = part[ch];
+        std::vector<double> dense(ncoarse, 0.0);
+        std::vector<char> mark(ncoarse, 0);
+        std::vector<int32_t> touched;
+        for (int64_t I = nrows * ch / nch; I < nrows * (ch + 1) / nch; ++I) {
+            touched.clear();
+            for (int32_t e1 = Fl.R_rp[I]; e1 < Fl.R_rp[I + 1]; ++e1) {
+                const int32_t i = Fl.R_ci[e1];
+                const double rv = Fl.R_v[e1];
+                for (int64_t e2 = A.rp[i]; e2 < A.rp[i + 1]; ++e2) {
+                    const int32_t j = A.ci[e2];
+                    const double cv = rv * A.v[e2];
+                    for (int32_t e3 = Fl.P_rp[j]; e3 < Fl.P_rp[j + 1]; ++e3) {
+                        const int32_t J = Fl.P_ci[e3];
+                        if (!mark[J]) {
+                            mark[J] = 1;
+                            touched.push_back(J);
+                        }
+                        dense[J] += cv * Fl.P_v[e3];
+                    }
+                }
+            }
+            std::sort(touched.begin(), touched.end());
+            for (int32_t J : touched) {
+                out.ci.push_back(J);
+                out.v.push_back(dense[J]);
+                dense[J] = 0.0;
+                mark[J] = 0;
+            }
+            out.rp.push_back((int64_t)out.ci.size());  // row ends, local to the chunk
+        }
+    });
+    Csr out;
+    out.rp.assign(1, 0);
+    for (auto &pc : part) {
+        const int64_t base = (int64_t)out.ci.size();
+        for (int64_t e : pc.rp) out.rp.push_back(base + e);
+        out.ci.insert(out.ci.end(), pc.ci.begin(), pc.ci.end());
+        out.v.insert(out.v.end(), pc.v.begin(), pc.v.end());
+    }
+    return out;
+}
+
+// Adds CSR rows 0 .. nrows-1 to the stored values of Lv (every entry must lie
+// in the stored pattern).
+static void csr_to_level(HostLevel &Lv, const BlockGeom &G, const Csr &Cm, int64_t nrows) {
+    for (int64_t r = 0; r < nrows; ++r) {
+        int R = 0;
+        while (r >= Lv.off[R + 1]) ++R;
+        for (int64_t e = Cm.rp[r]; e < Cm.rp[r + 1]; ++e) {
+            const int64_t col = Cm.ci[e];
+            int C = 0;
+            while (col >= Lv.off[C + 1]) ++C;
+            const int slot = stencil_slot(Lv, G, R, C, r - Lv.off[R], col - Lv.off[C]);
+            if (slot < 0) throw std::runtime_error("Galerkin entry outside the stored pattern");
+            Lv.val[Lv.ell_index(R, r - Lv.off[R], slot)] += Cm.v[e];
+        }
+    }
+}
+
+// Every stored non-zero of a level, CSR (columns in storage order per row).
+static Csr level_csr(const HostLevel &L, const BlockGeom &G) {
+    const int d = G.d;
+    Csr out;
+    out.rp.assign(1, 0);
+    for (int R = 0; R <= d; ++R) {
+        int cs[4];
+        const int ncs = G.order(R, cs);
+        const int64_t rows = L.off[R + 1] - L.off[R];
+        for (int64_t li = 0; li < rows; ++li) {
+            int is[3] = {0, 0, 0};
+            int64_t tt = li;
+            for (int j = 0; j < 3; ++j) {
+                is[j] = (int)(tt % L.nb[R][j]);
+                tt /= L.nb[R][j];
+            }
+            for (int ci = 0; ci < ncs; ++ci) {
+                const int C = cs[ci];
+                int W[3] = {1, 1, 1}, base[3] = {0, 0, 0};
+                for (int j = 0; j < d; ++j) {
+                    W[j] = G.width(R, C, j);
+                    base[j] = box_start(L.win, is[j], G.lo(R, C, j), W[j], L.nb[C][j]);
+                }
+                int slot = G.slot_base(R, C);
+                for (int o2 = 0; o2 < W[2]; ++o2)
+                    for (int o1 = 0; o1 < W[1]; ++o1)
+                        for (int o0 = 0; o0 < W[0]; ++o0, ++slot) {
+                            const int o[3] = {o0, o1, o2};
+                            int64_t col = 0, stride = 1;
+                            bool ok = true;
+                            for (int j = 0; j < d; ++j) {
+                                const int js = base[j] + o[j];
+                                if (js < 0 || js >= L.nb[C][j]) ok = false;
+                                col += (int64_t)js * stride;
+                                stride *= L.nb[C][j];
+                            }
+                            const double v = L.val[L.ell_index(R, li, slot)];
+                            if (!ok || v == 0.0) continue;
+                            out.ci.push_back((int32_t)(L.off[C] + col));
+                            out.v.push_back(v);
+                        }
+            }
+            out.rp.push_back((int64_t)out.ci.size());
+        }
+    }
+    return out;
+}
+
+// ------------------------------------- advection by a field of the velocity space
 
 // Advection by c times a field a of the finest velocity space (kind 3): the
 // blocks (v_R, a . grad u_R) assembled by Gauss quadrature (k+3 points per
@@ -1471,104 +1646,98 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
     const double h = 1.0 / N;
     const auto kn0 = open_knots(N, k), kn1 = open_knots(N, k + 1);
     BlockGeom G{d, k};
-    // per level, the advection values in the velocity rows (CSR)
-    struct Csr {
-        std::vector<int64_t> rp;
-        std::vector<int32_t> ci;
-        std::vector<double> v;
-    };
     // fine level: element matrices over the quadrature points, scattered
     // once per element into an array of the stencil-ELL shape
     std::vector<double> adv(F.val.size(), 0.0);
-    const int E2 = d == 3 ? N : 1, G2 = d == 3 ? nq : 1;
-    double val[3][2][8], der[3][2][8];
+    const int G2 = d == 3 ? nq : 1;
     struct Fn {
         int64_t gidx;
         int m[3];
     };
-    for (int e2 = 0; e2 < E2; ++e2)
-        for (int e1 = 0; e1 < N; ++e1)
-            for (int e0 = 0; e0 < N; ++e0) {
-                const int e[3] = {e0, e1, e2};
-                // the functions of each velocity component non-zero on the element
-                std::vector<Fn> fns[3];
-                for (int c = 0; c < d; ++c) {
-                    int q[3] = {0, 0, 0};
-                    for (int jj = 0; jj < d; ++jj) q[jj] = G.q(c, jj);
-                    const int m2max = d == 3 ? q[2] : 0;
-                    for (int m2 = 0; m2 <= m2max; ++m2)
-                        for (int m1 = 0; m1 <= q[1]; ++m1)
-                            for (int m0 = 0; m0 <= q[0]; ++m0) {
-                                Fn f{0, {m0, m1, m2}};
-                                int64_t idx = 0, stride = 1;
-                                bool ok = true;
-                                for (int jj = 0; jj < d; ++jj) {
-                                    const int st = e[jj] + f.m[jj] - G.s(c, jj);
-                                    if (st < 0 || st >= F.nb[c][jj]) ok = false;
-                                    idx += (int64_t)st * stride;
-                                    stride *= F.nb[c][jj];
-                                }
-                                if (!ok) continue;
-                                f.gidx = F.off[c] + idx;
-                                fns[c].push_back(f);
-                            }
-                }
-                std::vector<double> E[3];
-                for (int c = 0; c < d; ++c) E[c].assign(fns[c].size() * fns[c].size(), 0.0);
-                std::vector<double> fv[3], fdv[3];
-                for (int g2 = 0; g2 < G2; ++g2)
-                    for (int g1 = 0; g1 < nq; ++g1)
-                        for (int g0 = 0; g0 < nq; ++g0) {
-                            const int g[3] = {g0, g1, g2};
-                            double wq = 1.0;
-                            for (int jj = 0; jj < d; ++jj) {
-                                const double x = (e[jj] + 0.5 * (t[g[jj]] + 1.0)) * h;
-                                wq *= 0.5 * h * wt[g[jj]];
-                                span_basis(kn0, k, e[jj] + k, x, val[jj][0], der[jj][0]);
-                                span_basis(kn1, k + 1, e[jj] + k + 1, x, val[jj][1], der[jj][1]);
-                            }
-                            double a[3] = {0, 0, 0};
-                            for (int c = 0; c < d; ++c) {
-                                const size_t nf = fns[c].size();
-                                fv[c].assign(nf, 0.0);
-                                fdv[c].assign(nf * 3, 0.0);
-                                for (size_t fi = 0; fi < nf; ++fi) {
-                                    const Fn &f = fns[c][fi];
-                                    double v = 1.0;
-                                    for (int jj = 0; jj < d; ++jj) v *= val[jj][G.q(c, jj) - k][f.m[jj]];
-                                    fv[c][fi] = v;
-                                    for (int dd = 0; dd < d; ++dd) {
-                                        double pp = 1.0;
-                                        for (int jj = 0; jj < d; ++jj)
-                                            pp *= (jj == dd ? der : val)[jj][G.q(c, jj) - k][f.m[jj]];
-                                        fdv[c][fi * 3 + dd] = pp;
-                                    }
-                                    a[c] += pb.adv_field[f.gidx] * v;
-                                }
-                            }
-                            for (int c = 0; c < d; ++c) a[c] *= pb.adv_c;
-                            for (int c = 0; c < d; ++c) {
-                                const size_t nf = fns[c].size();
-                                for (size_t bj = 0; bj < nf; ++bj) {
-                                    double adv_b = 0.0;
-                                    for (int dd = 0; dd < d; ++dd) adv_b += a[dd] * fdv[c][bj * 3 + dd];
-                                    adv_b *= wq;
-                                    for (size_t ai = 0; ai < nf; ++ai) E[c][ai * nf + bj] += fv[c][ai] * adv_b;
-                                }
-                            }
+    // elements colour by colour (see for_each_element_coloured): the threads
+    // of a colour add to disjoint rows of adv
+    for_each_element_coloured(d, N, k, [&](int e0, int e1, int e2, int) {
+        double val[3][2][8], der[3][2][8];
+        const int e[3] = {e0, e1, e2};
+        // the functions of each velocity component non-zero on the element
+        std::vector<Fn> fns[3];
+        for (int c = 0; c < d; ++c) {
+            int q[3] = {0, 0, 0};
+            for (int jj = 0; jj < d; ++jj) q[jj] = G.q(c, jj);
+            const int m2max = d == 3 ? q[2] : 0;
+            for (int m2 = 0; m2 <= m2max; ++m2)
+                for (int m1 = 0; m1 <= q[1]; ++m1)
+                    for (int m0 = 0; m0 <= q[0]; ++m0) {
+                        Fn f{0, {m0, m1, m2}};
+                        int64_t idx = 0, stride = 1;
+                        bool ok = true;
+                        for (int jj = 0; jj < d; ++jj) {
+                            const int st = e[jj] + f.m[jj] - G.s(c, jj);
+                            if (st < 0 || st >= F.nb[c][jj]) ok = false;
+                            idx += (int64_t)st * stride;
+                            stride *= F.nb[c][jj];
                         }
-                for (int c = 0; c < d; ++c) {
-                    const size_t nf = fns[c].size();
-                    for (size_t ai = 0; ai < nf; ++ai) {
-                        const int64_t row = fns[c][ai].gidx - F.off[c];
+                        if (!ok) continue;
+                        f.gidx = F.off[c] + idx;
+                        fns[c].push_back(f);
+                    }
+        }
+        std::vector<double> E[3];
+        for (int c = 0; c < d; ++c) E[c].assign(fns[c].size() * fns[c].size(), 0.0);
+        std::vector<double> fv[3], fdv[3];
+        for (int g2 = 0; g2 < G2; ++g2)
+            for (int g1 = 0; g1 < nq; ++g1)
+                for (int g0 = 0; g0 < nq; ++g0) {
+                    const int g[3] = {g0, g1, g2};
+                    double wq = 1.0;
+                    for (int jj = 0; jj < d; ++jj) {
+                        const double x = (e[jj] + 0.5 * (t[g[jj]] + 1.0)) * h;
+                        wq *= 0.5 * h * wt[g[jj]];
+                        span_basis(kn0, k, e[jj] + k, x, val[jj][0], der[jj][0]);
+                        span_basis(kn1, k + 1, e[jj] + k + 1, x, val[jj][1], der[jj][1]);
+                    }
+                    double a[3] = {0, 0, 0};
+                    for (int c = 0; c < d; ++c) {
+                        const size_t nf = fns[c].size();
+                        fv[c].assign(nf, 0.0);
+                        fdv[c].assign(nf * 3, 0.0);
+                        for (size_t fi = 0; fi < nf; ++fi) {
+                            const Fn &f = fns[c][fi];
+                            double v = 1.0;
+                            for (int jj = 0; jj < d; ++jj) v *= val[jj][G.q(c, jj) - k][f.m[jj]];
+                            fv[c][fi] = v;
+                            for (int dd = 0; dd < d; ++dd) {
+                                double pp = 1.0;
+                                for (int jj = 0; jj < d; ++jj)
+                                    pp *= (jj == dd ? der : val)[jj][G.q(c, jj) - k][f.m[jj]];
+                                fdv[c][fi * 3 + dd] = pp;
+                            }
+                            a[c] += pb.adv_field[f.gidx] * v;
+                        }
+                    }
+                    for (int c = 0; c < d; ++c) a[c] *= pb.adv_c;
+                    for (int c = 0; c < d; ++c) {
+                        const size_t nf = fns[c].size();
                         for (size_t bj = 0; bj < nf; ++bj) {
-                            const int slot = stencil_slot(F, d, k, c, c, row, fns[c][bj].gidx - F.off[c]);
-                            if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
-                            adv[F.ell_index(c, row, slot)] += E[c][ai * nf + bj];
+                            double adv_b = 0.0;
+                            for (int dd = 0; dd < d; ++dd) adv_b += a[dd] * fdv[c][bj * 3 + dd];
+                            adv_b *= wq;
+                            for (size_t ai = 0; ai < nf; ++ai) E[c][ai * nf + bj] += fv[c][ai] * adv_b;
                         }
                     }
                 }
+        for (int c = 0; c < d; ++c) {
+            const size_t nf = fns[c].size();
+            for (size_t ai = 0; ai < nf; ++ai) {
+                const int64_t row = fns[c][ai].gidx - F.off[c];
+                for (size_t bj = 0; bj < nf; ++bj) {
+                    const int slot = stencil_slot(F, G, c, c, row, fns[c][bj].gidx - F.off[c]);
+                    if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
+                    adv[F.ell_index(c, row, slot)] += E[c][ai * nf + bj];
+                }
             }
+        }
+    });
     // CSR of the fine advection (velocity rows, same-component columns)
     Csr cur;
     cur.rp.assign(1, 0);
@@ -1611,77 +1780,351 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
     for (size_t x = 0; x < adv.size(); ++x) F.val[x] += adv[x];
     adv.clear();
     adv.shrink_to_fit();
-    auto to_csr = [](std::vector<std::vector<std::pair<int32_t, double>>> &rows, Csr &out) {
-        out.rp.assign(1, 0);
-        out.ci.clear();
-        out.v.clear();
-        for (auto &r : rows) {
-            std::sort(r.begin(), r.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
-            for (size_t i2 = 0; i2 < r.size();) {
-                size_t j2 = i2;
-                double sum = 0.0;
-                while (j2 < r.size() && r[j2].first == r[i2].first) sum += r[j2++].second;
-                out.ci.push_back(r[i2].first);
-                out.v.push_back(sum);
-                i2 = j2;
-            }
-            out.rp.push_back((int64_t)out.ci.size());
-            r.clear();
-            r.shrink_to_fit();
-        }
-    };
-    auto add_to_level = [&](HostLevel &Lv, const Csr &Cm) {
-        for (int64_t r = 0; r < Lv.n_v; ++r) {
-            int R = 0;
-            while (r >= Lv.off[R + 1]) ++R;
-            for (int64_t e = Cm.rp[r]; e < Cm.rp[r + 1]; ++e) {
-                const int64_t col = Cm.ci[e];
-                int C = 0;
-                while (col >= Lv.off[C + 1]) ++C;
-                const int slot = stencil_slot(Lv, d, k, R, C, r - Lv.off[R], col - Lv.off[C]);
-                if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
-                Lv.val[Lv.ell_index(R, r - Lv.off[R], slot)] += Cm.v[e];
-            }
-        }
-    };
-    // coarser levels: R C P (R of level l maps it to level l - 1, P of level l
-    // maps level l - 1 to it; velocity rows only: both are block diagonal)
+    // coarser levels: R C P (velocity rows only: R and P are block diagonal)
     for (int l = L - 1; l >= 1; --l) {
-        const HostLevel &Fl = H.lv[l];
-        HostLevel &Cl = H.lv[l - 1];
-        std::vector<double> dense(Cl.n, 0.0);
-        std::vector<char> mark(Cl.n, 0);
-        std::vector<int32_t> touched;
-        std::vector<std::vector<std::pair<int32_t, double>>> rows(Cl.n_v);
-        for (int64_t I = 0; I < Cl.n_v; ++I) {
-            touched.clear();
-            for (int32_t e1 = Fl.R_rp[I]; e1 < Fl.R_rp[I + 1]; ++e1) {
-                const int32_t i = Fl.R_ci[e1];
-                const double rv = Fl.R_v[e1];
-                for (int64_t e2 = cur.rp[i]; e2 < cur.rp[i + 1]; ++e2) {
-                    const int32_t j = cur.ci[e2];
-                    const double cv = rv * cur.v[e2];
-                    for (int32_t e3 = Fl.P_rp[j]; e3 < Fl.P_rp[j + 1]; ++e3) {
-                        const int32_t J = Fl.P_ci[e3];
-                        if (!mark[J]) {
-                            mark[J] = 1;
-                            touched.push_back(J);
-                        }
-                        dense[J] += cv * Fl.P_v[e3];
-                    }
-                }
-            }
-            for (int32_t J : touched) {
-                rows[I].push_back({J, dense[J]});
-                dense[J] = 0.0;
-                mark[J] = 0;
-            }
-        }
-        Csr next;
-        to_csr(rows, next);
-        add_to_level(Cl, next);
+        Csr next = galerkin_rows(H.lv[l], cur, H.lv[l - 1].n_v, H.lv[l - 1].n);
+        csr_to_level(H.lv[l - 1], G, next, H.lv[l - 1].n_v);
         cur = std::move(next);
     }
+}
+
+// ------------------------------------------------------------ mapped domains
+//
+// The quarter annulus x = r(xi_1) (cos theta(xi_2), sin theta(xi_2)), r =
+// r_in + (r_out - r_in) xi_1, extruded to x_3 = depth xi_3 in 3D.  The
+// quarter circle is the quadratic rational Bezier arc with weights 1,
+// 1/sqrt(2), 1; a rational quadratic parametrization of a circle differs
+// from the half-angle one by a Moebius map of the parameter, and the arc's
+// symmetry about t = 1/2 fixes it: tan((theta - pi/4) / 2) = (2t - 1) tan(pi/8).
+struct MapPoint {
+    double J[3][3];      // J[i][m] = d x_i / d xi_m
+    double dJ[3][3][3];  // dJ[q][i][m] = d^2 x_i / d xi_q d xi_m
+};
+
+static void annulus_point(const Problem &pb, const double *xi, MapPoint &m) {
+    const double dr = pb.r_out - pb.r_in, r = pb.r_in + dr * xi[0];
+    const double a = std::tan(M_PI / 8.0), u = (2.0 * xi[1] - 1.0) * a;
+    const double th = M_PI / 4.0 + 2.0 * std::atan(u);
+    const double t1 = 4.0 * a / (1.0 + u * u);
+    const double t2 = -16.0 * a * a * u / ((1.0 + u * u) * (1.0 + u * u));
+    const double er[2] = {std::cos(th), std::sin(th)}, et[2] = {-std::sin(th), std::cos(th)};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            m.J[i][j] = 0.0;
+            for (int q = 0; q < 3; ++q) m.dJ[q][i][j] = 0.0;
+        }
+    for (int i = 0; i < 2; ++i) {
+        m.J[i][0] = dr * er[i];
+        m.J[i][1] = r * t1 * et[i];
+        m.dJ[0][i][1] = dr * t1 * et[i];
+        m.dJ[1][i][0] = dr * t1 * et[i];
+        m.dJ[1][i][1] = r * (t2 * et[i] - t1 * t1 * er[i]);
+    }
+    m.J[2][2] = pb.depth;
+}
+
+static double det3(int d, const double (*J)[3]) {
+    if (d == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+static void inv3(int d, const double (*J)[3], double det, double (*Ji)[3]) {
+    if (d == 2) {
+        Ji[0][0] = J[1][1] / det;
+        Ji[0][1] = -J[0][1] / det;
+        Ji[1][0] = -J[1][0] / det;
+        Ji[1][1] = J[0][0] / det;
+        return;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+            Ji[i][j] = (J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1]) / det;  // cofactor transpose
+        }
+}
+
+// Per point, the factors that give the physical value and gradient of a
+// velocity basis function of component c (the contravariant Piola map v o F =
+// J N e_c / det J): value_i = beta[c][i] N, gradient_ij = acoef[c][i][j] N +
+// beta[c][i] (grad_x N)_j with (grad_x N)_j = sum_q d_q N Jinv[q][j].
+struct Piola {
+    double det, Jinv[3][3], beta[3][3], acoef[3][3][3];
+};
+
+static void piola_point(int d, const MapPoint &m, Piola &P) {
+    P.det = det3(d, m.J);
+    inv3(d, m.J, P.det, P.Jinv);
+    double ddet[3] = {0, 0, 0};  // d det / d xi_q = det tr(Jinv dJ_q)
+    for (int q = 0; q < d; ++q) {
+        double tr = 0.0;
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) tr += P.Jinv[a][b] * m.dJ[q][b][a];
+        ddet[q] = P.det * tr;
+    }
+    for (int c = 0; c < d; ++c)
+        for (int i = 0; i < d; ++i) {
+            P.beta[c][i] = m.J[i][c] / P.det;
+            double al[3];
+            for (int q = 0; q < d; ++q) al[q] = m.dJ[q][i][c] / P.det - m.J[i][c] * ddet[q] / (P.det * P.det);
+            for (int j = 0; j < d; ++j) {
+                double v = 0.0;
+                for (int q = 0; q < d; ++q) v += al[q] * P.Jinv[q][j];
+                P.acoef[c][i][j] = v;
+            }
+        }
+}
+
+// The finest operator on the mapped domain by Gauss quadrature (k+3 points
+// per direction per element, faces likewise): sigma (v, u) + nu (grad v :
+// grad u) + the Nitsche terms -nu (v, grad u n) - nu (grad v n, u) + C_I nu /
+// h (v, u) with C_I = 4k, ds = det J |J^-T n_hat| and h = 1 / (N |J^-T
+// n_hat|), and b(v, q) = (div v, q) = int div_x v q_hat dxi (the pressure
+// pushed forward by q o F = q_hat / det J); coarser levels R K P.
+//
+// Per element the volume terms of the velocity block are a Gram matrix:
+// with y_a the vector over points and components of sqrt(w det J) (sqrt(sigma)
+// v_a, sqrt(nu) grad v_a), E_ab = y_a . y_b.  Elements are taken colour by
+// colour, colour (e mod (k+2)) per direction: two elements of one colour are
+// k+2 apart in some direction and share no basis function, so the threads of
+// a colour scatter into disjoint rows (for_each_element_coloured).
+static void assemble_mapped(const Problem &pb, Hierarchy &H) {
+    const int d = pb.d, k = pb.k, N = pb.N, nq = k + 3, L = pb.L;
+    BlockGeom G{d, k, true};
+    HostLevel &F = H.lv[L - 1];
+    std::vector<double> t, wt;
+    gauss_legendre(nq, t, wt);
+    const double h = 1.0 / N, CI = 4.0 * k;
+    const double sqs = std::sqrt(pb.sigma), sqn = std::sqrt(pb.nu);
+    const auto kn0 = open_knots(N, k), kn1 = open_knots(N, k + 1);
+    const int npt = d == 3 ? nq * nq * nq : nq * nq;
+    const int ncomp = d + d * d;      // value and gradient entries per point
+    const int K = npt * ncomp;
+    struct Fn {
+        int blk;
+        int64_t row;  // stored index in its block
+        int m[3];
+    };
+    struct Work {
+        std::vector<Fn> fns;
+        std::vector<double> Vv, Tv, Qv, Y, Yd, Qp, E;
+        double val[3][2][8], der[3][2][8];
+    };
+    const int nth = setup_threads();
+    std::vector<Work> work(nth);
+    // basis of the element's functions at parametric point xi: physical
+    // values Vv (d per function), gradients Tv (d*d), pressure values Qv
+    auto eval_point = [&](Work &w, const int *e, const double *xi, const Piola &P) {
+        for (int j = 0; j < d; ++j) {
+            span_basis(kn0, k, e[j] + k, xi[j], w.val[j][0], w.der[j][0]);
+            span_basis(kn1, k + 1, e[j] + k + 1, xi[j], w.val[j][1], w.der[j][1]);
+        }
+        const size_t nf = w.fns.size();
+        w.Vv.assign(nf * 3, 0.0);
+        w.Tv.assign(nf * 9, 0.0);
+        w.Qv.assign(nf, 0.0);
+        for (size_t f = 0; f < nf; ++f) {
+            const Fn &fn = w.fns[f];
+            const int c = fn.blk;
+            double nval = 1.0, dn[3];
+            for (int j = 0; j < d; ++j) nval *= w.val[j][G.q(c, j) - k][fn.m[j]];
+            if (c == d) {
+                w.Qv[f] = nval;
+                continue;
+            }
+            for (int q = 0; q < d; ++q) {
+                double pp = 1.0;
+                for (int j = 0; j < d; ++j) pp *= (j == q ? w.der : w.val)[j][G.q(c, j) - k][fn.m[j]];
+                dn[q] = pp;
+            }
+            double gx[3];
+            for (int j = 0; j < d; ++j) {
+                gx[j] = 0.0;
+                for (int q = 0; q < d; ++q) gx[j] += dn[q] * P.Jinv[q][j];
+            }
+            for (int i = 0; i < d; ++i) {
+                w.Vv[f * 3 + i] = P.beta[c][i] * nval;
+                for (int j = 0; j < d; ++j) w.Tv[f * 9 + i * 3 + j] = P.acoef[c][i][j] * nval + P.beta[c][i] * gx[j];
+            }
+        }
+    };
+    auto element = [&](int e0, int e1, int e2, Work &w) {
+        const int e[3] = {e0, e1, e2};
+        w.fns.clear();
+        for (int c = 0; c <= d; ++c) {  // velocity functions first, then pressure
+            int q[3] = {0, 0, 0};
+            for (int j = 0; j < d; ++j) q[j] = G.q(c, j);
+            for (int m2 = 0; m2 <= (d == 3 ? q[2] : 0); ++m2)
+                for (int m1 = 0; m1 <= q[1]; ++m1)
+                    for (int m0 = 0; m0 <= q[0]; ++m0) {
+                        Fn f{c, 0, {m0, m1, m2}};
+                        int64_t idx = 0, stride = 1;
+                        bool ok = true;
+                        for (int j = 0; j < d; ++j) {
+                            const int st = e[j] + f.m[j] - G.s(c, j);
+                            if (st < 0 || st >= F.nb[c][j]) ok = false;
+                            idx += (int64_t)st * stride;
+                            stride *= F.nb[c][j];
+                        }
+                        if (!ok) continue;
+                        f.row = idx;
+                        w.fns.push_back(f);
+                    }
+        }
+        const size_t nf = w.fns.size();
+        size_t nv = 0;
+        while (nv < nf && w.fns[nv].blk < d) ++nv;
+        const size_t np = nf - nv;
+        w.Y.assign(nv * K, 0.0);
+        w.Yd.assign(nv * npt, 0.0);
+        w.Qp.assign(np * npt, 0.0);
+        MapPoint mp;
+        Piola P;
+        double xi[3] = {0, 0, 0};
+        int pt = 0;
+        for (int g2 = 0; g2 < (d == 3 ? nq : 1); ++g2)
+            for (int g1 = 0; g1 < nq; ++g1)
+                for (int g0 = 0; g0 < nq; ++g0, ++pt) {
+                    const int g[3] = {g0, g1, g2};
+                    double wq = 1.0;
+                    for (int j = 0; j < d; ++j) {
+                        xi[j] = (e[j] + 0.5 * (t[g[j]] + 1.0)) * h;
+                        wq *= 0.5 * h * wt[g[j]];
+                    }
+                    annulus_point(pb, xi, mp);
+                    piola_point(d, mp, P);
+                    eval_point(w, e, xi, P);
+                    const double sw = std::sqrt(wq * P.det);
+                    for (size_t a = 0; a < nv; ++a) {
+                        double *y = &w.Y[a * K + (size_t)pt * ncomp];
+                        double div = 0.0;
+                        for (int i = 0; i < d; ++i) {
+                            y[i] = sw * sqs * w.Vv[a * 3 + i];
+                            for (int j = 0; j < d; ++j) y[d + i * d + j] = sw * sqn * w.Tv[a * 9 + i * 3 + j];
+                            div += w.Tv[a * 9 + i * 3 + i];
+                        }
+                        w.Yd[a * npt + pt] = wq * div;
+                    }
+                    for (size_t p = 0; p < np; ++p) w.Qp[p * npt + pt] = w.Qv[nv + p];
+                }
+        w.E.assign(nf * nf, 0.0);
+        for (size_t a = 0; a < nv; ++a) {
+            const double *ya = &w.Y[a * K];
+            for (size_t b = a; b < nv; ++b) {
+                const double *yb = &w.Y[b * K];
+                double acc = 0.0;
+                for (int x = 0; x < K; ++x) acc += ya[x] * yb[x];
+                w.E[a * nf + b] = acc;
+                w.E[b * nf + a] = acc;
+            }
+            for (size_t p = 0; p < np; ++p) {
+                // -(div v_a, q_p) in the velocity row, +(div v_a, q_p) in the pressure row
+                const double *yd = &w.Yd[a * npt], *qp = &w.Qp[p * npt];
+                double acc = 0.0;
+                for (int x = 0; x < npt; ++x) acc += yd[x] * qp[x];
+                w.E[a * nf + nv + p] = -acc;
+                w.E[(nv + p) * nf + a] = acc;
+            }
+        }
+        // boundary faces of this element (Nitsche terms)
+        for (int fe = 0; fe < d; ++fe)
+            for (int side = 0; side < 2; ++side) {
+                if (e[fe] != (side ? N - 1 : 0)) continue;
+                const int o1 = (fe + 1) % d, o2 = (fe + 2) % d;
+                for (int g2 = 0; g2 < (d == 3 ? nq : 1); ++g2)
+                    for (int g1 = 0; g1 < nq; ++g1) {
+                        double wf = 0.5 * h * wt[g1];
+                        xi[fe] = side ? 1.0 : 0.0;
+                        xi[o1] = (e[o1] + 0.5 * (t[g1] + 1.0)) * h;
+                        if (d == 3) {
+                            xi[o2] = (e[o2] + 0.5 * (t[g2] + 1.0)) * h;
+                            wf *= 0.5 * h * wt[g2];
+                        }
+                        annulus_point(pb, xi, mp);
+                        piola_point(d, mp, P);
+                        eval_point(w, e, xi, P);
+                        // m = J^-T n_hat, n_hat = +-e_fe
+                        const double sg = side ? 1.0 : -1.0;
+                        double mv[3], ml = 0.0;
+                        for (int i = 0; i < d; ++i) {
+                            mv[i] = sg * P.Jinv[fe][i];
+                            ml += mv[i] * mv[i];
+                        }
+                        ml = std::sqrt(ml);
+                        double nrm[3];
+                        for (int i = 0; i < d; ++i) nrm[i] = mv[i] / ml;
+                        const double ds = wf * P.det * ml, hn = 1.0 / (N * ml);
+                        for (size_t a = 0; a < nv; ++a) {
+                            const double *va = &w.Vv[a * 3], *ta = &w.Tv[a * 9];
+                            double tan_a[3];
+                            for (int i = 0; i < d; ++i) {
+                                tan_a[i] = 0.0;
+                                for (int j = 0; j < d; ++j) tan_a[i] += ta[i * 3 + j] * nrm[j];
+                            }
+                            for (size_t b = 0; b < nv; ++b) {
+                                const double *vb = &w.Vv[b * 3], *tb = &w.Tv[b * 9];
+                                double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                                for (int i = 0; i < d; ++i) {
+                                    double tn_b = 0.0;
+                                    for (int j = 0; j < d; ++j) tn_b += tb[i * 3 + j] * nrm[j];
+                                    s1 += va[i] * tn_b;
+                                    s2 += tan_a[i] * vb[i];
+                                    s3 += va[i] * vb[i];
+                                }
+                                w.E[a * nf + b] += ds * (-pb.nu * s1 - pb.nu * s2 + CI * pb.nu / hn * s3);
+                            }
+                        }
+                    }
+            }
+        for (size_t a = 0; a < nf; ++a)
+            for (size_t b = 0; b < nf; ++b) {
+                const double v = w.E[a * nf + b];
+                if (v == 0.0) continue;
+                const int slot = stencil_slot(F, G, w.fns[a].blk, w.fns[b].blk, w.fns[a].row, w.fns[b].row);
+                if (slot < 0) throw std::runtime_error("mapped entry outside the stored pattern");
+                F.val[F.ell_index(w.fns[a].blk, w.fns[a].row, slot)] += v;
+            }
+    };
+    for_each_element_coloured(d, N, k, [&](int e0, int e1, int e2, int th) { element(e0, e1, e2, work[th]); });
+    Csr cur = level_csr(F, G);
+    for (int l = L - 1; l >= 1; --l) {
+        Csr next = galerkin_rows(H.lv[l], cur, H.lv[l - 1].n, H.lv[l - 1].n);
+        csr_to_level(H.lv[l - 1], G, next, H.lv[l - 1].n);
+        cur = std::move(next);
+    }
+}
+
+// 1D pressure mass bands of the divergence norm on the mapped domain: the
+// weight 1 / det J = 1 / ((r_out - r_in) r(xi_1)) * 1 / theta'(xi_2) [* 1 /
+// depth] separates, so the norm's mass is the tensor product of weighted 1D
+// masses (same Gauss rule as the assembly).
+static void mapped_pressure_mass(const Problem &pb, std::vector<double> &pm) {
+    const int k = pb.k, N = pb.N, nq = k + 3, n1 = N + k, w = 2 * k + 1;
+    std::vector<double> t, wt;
+    gauss_legendre(nq, t, wt);
+    const auto kn = open_knots(N, k);
+    const double dr = pb.r_out - pb.r_in, a = std::tan(M_PI / 8.0);
+    pm.assign((size_t)3 * n1 * w, 0.0);
+    double val[8], der[8];
+    for (int dir = 0; dir < 3; ++dir)
+        for (int e = 0; e < N; ++e)
+            for (int g = 0; g < nq; ++g) {
+                const double x = (e + 0.5 * (t[g] + 1.0)) / N;
+                double wgt = 0.5 * wt[g] / N;
+                if (dir == 0) wgt /= dr * (pb.r_in + dr * x);
+                else if (dir == 1) {
+                    const double u = (2.0 * x - 1.0) * a;
+                    wgt /= 4.0 * a / (1.0 + u * u);
+                } else {
+                    wgt /= pb.depth;
+                }
+                span_basis(kn, k, e + k, x, val, der);
+                for (int i = 0; i <= k; ++i)
+                    for (int j = 0; j <= k; ++j) {
+                        const int gi = e + i, gj = e + j;  // pressure keeps every function
+                        pm[((size_t)dir * n1 + gi) * w + (gj - gi) + k] += wgt * val[i] * val[j];
+                    }
+            }
 }
 
 void build_hierarchy(const Problem &pb, Hierarchy &H) {
@@ -1691,6 +2134,12 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
     if (pb.N % (1 << (pb.L - 1)) != 0) throw std::runtime_error("n_elem must be divisible by 2^(n_levels-1)");
     if (!(pb.nu > 0.0) || !(pb.sigma >= 0.0)) throw std::runtime_error("need nu > 0 and sigma >= 0");
     if (pb.adv_kind < 0 || pb.adv_kind > 3) throw std::runtime_error("advection kind must be 0, 1, 2 or 3");
+    if (pb.geometry != 0 && pb.geometry != 1) throw std::runtime_error("geometry must be 0 or 1");
+    if (pb.geometry == 1) {
+        if (pb.adv_kind != 0) throw std::runtime_error("mapped domains take generalized Stokes problems (advection 0)");
+        if (!(pb.r_in > 0.0) || !(pb.r_out > pb.r_in) || (pb.d == 3 && !(pb.depth > 0.0)))
+            throw std::runtime_error("need 0 < r_inner < r_outer and depth > 0");
+    }
     H.pb = pb;
     const int L = pb.L;
     H.fac.assign(L, Factors());
@@ -1704,7 +2153,9 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
     }
     for (int l = 1; l < L; ++l) build_prolongation(pb, H.lv[l - 1], H.lv[l]);
     if (pb.adv_kind == 3) add_field_advection(pb, H);
-    for (int l = 1; l < L; ++l) build_patches(pb, H.lv[l], pb.share_inverses && pb.adv_kind != 3);
+    if (pb.geometry == 1) assemble_mapped(pb, H);
+    const bool share = pb.share_inverses && pb.adv_kind != 3 && pb.geometry == 0;
+    for (int l = 1; l < L; ++l) build_patches(pb, H.lv[l], share);
     {
         HostLevel &C = H.lv[0];
         const int n = (int)C.n;
@@ -1743,10 +2194,15 @@ void build_hierarchy(const Problem &pb, Hierarchy &H) {
         }
         const Mat1 &Mq = H.fac[L - 1].mass[0];
         const int nq1 = pb.N + k, w = 2 * k + 1;
-        H.pmass.assign((size_t)nq1 * w, 0.0);
-        for (int i = 0; i < nq1; ++i)
-            for (int o = -k; o <= k; ++o)
-                if (i + o >= 0 && i + o < nq1) H.pmass[(size_t)i * w + o + k] = Mq(i, i + o);
+        if (pb.geometry == 1) {
+            mapped_pressure_mass(pb, H.pmass);
+        } else {
+            H.pmass.assign((size_t)3 * nq1 * w, 0.0);
+            for (int dir = 0; dir < 3; ++dir)
+                for (int i = 0; i < nq1; ++i)
+                    for (int o = -k; o <= k; ++o)
+                        if (i + o >= 0 && i + o < nq1) H.pmass[((size_t)dir * nq1 + i) * w + o + k] = Mq(i, i + o);
+        }
     }
     const double table[2][2] = {{0.35, 0.2}, {0.07, 0.02}};
     H.default_eta = table[pb.d - 2][pb.k - 1];
@@ -1851,6 +2307,7 @@ double advection_speed(const Problem &pb) {
 
 void manufactured_rhs(const Hierarchy &H, double *F) {
     const Problem &pb = H.pb;
+    if (pb.geometry != 0) throw std::runtime_error("the manufactured load is defined on the unit square / cube");
     const HostLevel &L = H.lv[pb.L - 1];
     const int d = pb.d, k = pb.k, N = pb.N, nq = k + 3;
     BlockGeom G{d, k};

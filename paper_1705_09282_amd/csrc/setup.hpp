@@ -68,6 +68,12 @@ struct Problem {
     int adv_kind = 0;
     double adv_c = 0.0;
     std::vector<double> adv_field;
+    // domain: 0 the unit square / cube; 1 the quarter annulus of radii r_in,
+    // r_out (xi_1 radial, xi_2 the angle from the x axis), extruded along z by
+    // depth in 3D (the hollow cylinder section).  On a mapped domain the
+    // velocity rows couple every velocity component.
+    int geometry = 0;
+    double r_in = 0.075, r_out = 0.225, depth = 0.1;
     bool share_inverses = true;
     bool potentials = false;   // build the potential-form maps of the FP32 cycle
     bool multiplicative = false;  // build the lane tables of the multiplicative sweep
@@ -164,7 +170,7 @@ struct Hierarchy {
     std::vector<HostLevel> lv;
     // divergence-norm data on the finest grid
     std::vector<double> dcoef;     // derivative coefficients of degree k+1 splines
-    std::vector<double> pmass;     // 1D pressure mass band (n_q1 x (2k+1))
+    std::vector<double> pmass;     // 1D pressure mass bands, one per direction (3 x n_q1 x (2k+1))
     double default_eta = 0.2;
     // quadrature tables of the finest grid (Crank-Nicolson / Adams-Bashforth
     // load): values and derivatives of the q+1 B-splines of degree q = k, k+1
@@ -179,11 +185,41 @@ void build_hierarchy(const Problem &pb, Hierarchy &H);
 // Stencil-ELL helpers shared by setup and export.
 struct BlockGeom {
     int d, k;
+    bool xc = false;  // velocity rows couple every velocity component (mapped domain)
     int q(int R, int dir) const { return (R < d && dir == R) ? k + 1 : k; }
     int s(int R, int dir) const { return (R < d && dir == R) ? 1 : 0; }
     int lo(int R, int C, int dir) const { return s(R, dir) - s(C, dir) - q(R, dir); }
     int width(int R, int C, int dir) const { return q(R, dir) + q(C, dir) + 1; }
-    bool coupled(int R, int C) const { return (R < d) ? (C == R || C == d) : (C < d); }
+    bool coupled(int R, int C) const { return (R < d) ? (C == R || C == d || (xc && C < d)) : (C < d); }
+    int box(int R, int C) const {
+        int w = 1;
+        for (int j = 0; j < d; ++j) w *= width(R, C, j);
+        return w;
+    }
+    // column blocks of row block R in storage order: a velocity row stores
+    // its own component, the pressure, then (xc) the other components in
+    // increasing order; a pressure row the velocity components in order
+    int order(int R, int *cs) const {
+        int n = 0;
+        if (R < d) {
+            cs[n++] = R;
+            cs[n++] = d;
+            if (xc)
+                for (int C = 0; C < d; ++C)
+                    if (C != R) cs[n++] = C;
+        } else {
+            for (int C = 0; C < d; ++C) cs[n++] = C;
+        }
+        return n;
+    }
+    // first slot of block (R, C) in a row of block R
+    int slot_base(int R, int C) const {
+        int cs[4];
+        const int n = order(R, cs);
+        int s0 = 0;
+        for (int i = 0; i < n && cs[i] != C; ++i) s0 += box(R, cs[i]);
+        return s0;
+    }
 };
 
 // Entry K(g_row, g_col) of a level (0 if outside the stored pattern).

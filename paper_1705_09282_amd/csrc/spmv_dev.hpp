@@ -67,32 +67,57 @@ __host__ __device__ constexpr int block_slots() {
     return Geo<D, K>::w(R, C, 0) * Geo<D, K>::w(R, C, 1) * Geo<D, K>::w(R, C, 2);
 }
 
+// Velocity rows of a mapped domain (XC) also couple the other velocity
+// components: their blocks follow (R, R) and (R, D), in increasing order of
+// the component.
 template <int D, int K, int R>
+__host__ __device__ constexpr int cross_slots() {
+    int s = 0;
+    if constexpr (R != 0) s += block_slots<D, K, R, 0>();
+    if constexpr (R != 1) s += block_slots<D, K, R, 1>();
+    if constexpr (D == 3 && R != 2) s += block_slots<D, K, R, (D == 3 ? 2 : 0)>();
+    return s;
+}
+
+template <int D, int K, int R, bool XC>
 __host__ __device__ constexpr int row_slots() {
     if constexpr (R < D) {
-        return block_slots<D, K, R, R>() + block_slots<D, K, R, D>();
+        return block_slots<D, K, R, R>() + block_slots<D, K, R, D>() + (XC ? cross_slots<D, K, R>() : 0);
     } else {
         return block_slots<D, K, R, 0>() + block_slots<D, K, R, 1>() + (D == 3 ? block_slots<D, K, R, 2 % D>() : 0);
     }
 }
 
-template <int D, int K, int R>
+template <int D, int K, int R, bool XC>
 __host__ __device__ constexpr int row_slots_padded() {
-    return (row_slots<D, K, R>() + kEll - 1) / kEll * kEll;
+    return (row_slots<D, K, R, XC>() + kEll - 1) / kEll * kEll;
 }
 
-template <int D, int K, int R, int LPR, bool WIN, class T>
+template <int D, int K, int R, int LPR, bool WIN, bool XC, class T>
 __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
     const int i0 = li % nb0;
     const int t = li / nb0;
     const int i1 = t % nb1;
     const int i2 = t / nb1;
-    const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots_padded<D, K, R>() * 64) + (li & 63) * kEll;
+    const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots_padded<D, K, R, XC>() * 64) + (li & 63) * kEll;
     T acc;
     if constexpr (R < D) {
         acc = block_dot<D, K, R, R, LPR, WIN, T>(a, i0, i1, i2, lane, vp, 0);
         acc += block_dot<D, K, R, D, LPR, WIN, T>(a, i0, i1, i2, lane, vp, block_slots<D, K, R, R>());
+        if constexpr (XC) {
+            int s0 = block_slots<D, K, R, R>() + block_slots<D, K, R, D>();
+            if constexpr (R != 0) {
+                acc += block_dot<D, K, R, 0, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+                s0 += block_slots<D, K, R, 0>();
+            }
+            if constexpr (R != 1) {
+                acc += block_dot<D, K, R, 1, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+                s0 += block_slots<D, K, R, 1>();
+            }
+            if constexpr (D == 3 && R != 2)
+                acc += block_dot<D, K, R, (D == 3 ? 2 : 0), LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+        }
     } else {
         constexpr int s1 = block_slots<D, K, R, 0>(), s2 = s1 + block_slots<D, K, R, 1>();
         acc = block_dot<D, K, R, 0, LPR, WIN, T>(a, i0, i1, i2, lane, vp, 0);
@@ -103,12 +128,12 @@ __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
 }
 
 // (K U)_g of row g of a level (LPR = 1; args already offset to one problem)
-template <int D, int K, bool WIN, class T>
+template <int D, int K, bool WIN, bool XC, class T>
 __device__ __forceinline__ T spmv_row(const SpmvArgsT<T> &a, int g) {
-    if (g < a.off[1]) return row_dot<D, K, 0, 1, WIN, T>(a, g, 0);
-    if (g < a.off[2]) return row_dot<D, K, 1, 1, WIN, T>(a, g - (int)a.off[1], 0);
-    if (D == 3 && g < a.off[3]) return row_dot<D, K, (D == 3 ? 2 : 1), 1, WIN, T>(a, g - (int)a.off[2], 0);
-    return row_dot<D, K, D, 1, WIN, T>(a, g - (int)a.off[D], 0);
+    if (g < a.off[1]) return row_dot<D, K, 0, 1, WIN, XC, T>(a, g, 0);
+    if (g < a.off[2]) return row_dot<D, K, 1, 1, WIN, XC, T>(a, g - (int)a.off[1], 0);
+    if (D == 3 && g < a.off[3]) return row_dot<D, K, (D == 3 ? 2 : 1), 1, WIN, XC, T>(a, g - (int)a.off[2], 0);
+    return row_dot<D, K, D, 1, WIN, XC, T>(a, g - (int)a.off[D], 0);
 }
 
 }  // namespace dfmg

@@ -7,6 +7,7 @@
 // launch.  Every value is computed by the same device functions, in the same
 // order, as the per-level kernels (residual with one lane per row, smoother
 // rows, gathers, transfers, coarse product), so the results agree bit for bit.
+// Mapped domains (velocity rows coupling every component) do not take it.
 #include "schwarz_dev.hpp"
 #include "spmv_dev.hpp"
 
@@ -24,9 +25,9 @@ __device__ void small_residual(const SmallLevel<T> &L, int prob, const T *F, con
     a.U = U;
     const int n = (int)L.n;
     if (a.win) {
-        for (int g = threadIdx.x; g < n; g += blockDim.x) r[g] = F[g] - spmv_row<D, K, true, T>(a, g);
+        for (int g = threadIdx.x; g < n; g += blockDim.x) r[g] = F[g] - spmv_row<D, K, true, false, T>(a, g);
     } else {
-        for (int g = threadIdx.x; g < n; g += blockDim.x) r[g] = F[g] - spmv_row<D, K, false, T>(a, g);
+        for (int g = threadIdx.x; g < n; g += blockDim.x) r[g] = F[g] - spmv_row<D, K, false, false, T>(a, g);
     }
 }
 

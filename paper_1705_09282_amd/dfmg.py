@@ -28,7 +28,23 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "EDIVERGED
 
 
 class Grid(ctypes.Structure):
-    _fields_ = [("dim", c_int), ("n_elem", c_int), ("n_levels", c_int)]
+    _fields_ = [("dim", c_int), ("n_elem", c_int), ("n_levels", c_int), ("geometry", c_int),
+                ("r_inner", c_double), ("r_outer", c_double), ("depth", c_double)]
+
+
+# the paper's quarter annulus and hollow cylinder section
+ANNULUS = {"r_inner": 0.075, "r_outer": 0.225, "depth": 0.1}
+
+
+def _grid(dim, n_elem, n_levels, geometry=0, shape=None):
+    """dfmg_grid: geometry 0 the unit square / cube, 1 the quarter annulus
+    (hollow cylinder section in 3D) with radii and depth from `shape`
+    (default ANNULUS)."""
+    g = Grid(dim, n_elem, n_levels, int(geometry), 0.0, 0.0, 0.0)
+    if geometry:
+        sh = dict(ANNULUS, **(shape or {}))
+        g.r_inner, g.r_outer, g.depth = sh["r_inner"], sh["r_outer"], sh["depth"]
+    return g
 
 
 class Advection(ctypes.Structure):
@@ -273,16 +289,18 @@ class Solver:
     same mesh and solves them together."""
 
     def __init__(self, dim, n_elem, n_levels, k, nu=1.0, sigma=1.0, c=0.0, adv_kind=None, adv_coeffs=None,
-                 **options):
-        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options, adv_kind, adv_coeffs)
+                 geometry=0, shape=None, **options):
+        self._init(dim, n_elem, n_levels, k, [nu], [sigma], [c], options, adv_kind, adv_coeffs, geometry, shape)
 
-    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options, adv_kind=None, adv_coeffs=None):
+    def _init(self, dim, n_elem, n_levels, k, nus, sigmas, cs, options, adv_kind=None, adv_coeffs=None,
+              geometry=0, shape=None):
         self.dim, self.n_elem, self.n_levels, self.k = dim, n_elem, n_levels, k
         self.nprob = len(nus)
         self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
         if not (len(sigmas) == len(cs) == self.nprob):
             raise ValueError("one nu, sigma and c per problem")
-        g = Grid(dim, n_elem, n_levels)
+        g = _grid(dim, n_elem, n_levels, geometry, shape)
+        self.geometry = int(geometry)
         self.adv_kind = adv_kind
         keep = []
         fields = _per_problem(adv_coeffs, self.nprob)
@@ -645,9 +663,11 @@ class BatchSolver(Solver):
     kernel launch covers the whole batch.  Vectors are problem-major blocks of
     the finest-level length n."""
 
-    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, adv_kind=None, adv_coeffs=None, **options):
+    def __init__(self, dim, n_elem, n_levels, k, nus, sigmas, cs=None, adv_kind=None, adv_coeffs=None,
+                 geometry=0, shape=None, **options):
         cs = [0.0] * len(nus) if cs is None else list(cs)
-        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options, adv_kind, adv_coeffs)
+        self._init(dim, n_elem, n_levels, k, list(nus), list(sigmas), cs, options, adv_kind, adv_coeffs,
+                   geometry, shape)
 
     def solve(self, F, U, tol=1e-8, raise_on_error=True):
         return self._solve(F, U, tol, raise_on_error)
@@ -673,7 +693,7 @@ class MultiSolver:
             raise ValueError("one mesh, nu, sigma and c per problem")
         self.meshes = [tuple(int(x) for x in m) for m in meshes]
         self.nus, self.sigmas, self.cs = list(nus), list(sigmas), list(cs)
-        grids = (Grid * self.nprob)(*[Grid(d, N, L) for (d, N, L, _k) in self.meshes])
+        grids = (Grid * self.nprob)(*[_grid(d, N, L) for (d, N, L, _k) in self.meshes])
         ks = np.ascontiguousarray([m[3] for m in self.meshes], dtype=np.int32)
         self.adv_kind = adv_kind
         keep = []

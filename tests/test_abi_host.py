@@ -148,3 +148,51 @@ def test_multiplicative_option_errors():
         dfmg.Solver(2, 8, 2, 1, multiplicative=1, precision=1)   # FP64 cycles only
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, multiplicative=2)
+
+
+@pytest.mark.parametrize("d,N,k,L", [(2, 8, 1, 3), (2, 8, 2, 3), (3, 4, 1, 2), (3, 4, 2, 2)])
+def test_mapped_setup_matches_oracle(d, N, k, L):
+    """The quarter annulus / hollow cylinder section: the operator on every
+    level (finest by quadrature through the Piola maps, coarser ones by
+    Galerkin products) equals the oracle's; subdomains, colours and
+    prolongations stay the parametric ones."""
+    from oracle.geometry import QuarterAnnulus
+    s = dfmg.Solver(d, N, L, k, nu=0.7, sigma=3.0, geometry=1)
+    h = Hierarchy(d, N, k, L, 0.7, 3.0, geometry=QuarterAnnulus(d))
+    unit = dfmg.Solver(d, N, L, k, nu=0.7, sigma=3.0)
+    for l in range(L):
+        rp, col, val = s.export_matrix(l)
+        n = len(rp) - 1
+        Kl = sp.csr_matrix((val, col, rp), shape=(n, n))
+        Ko = h.levels[l].K
+        assert abs(Kl - Ko).max() <= 1e-13 * abs(Ko).max()
+        if l > 0:
+            for a, b in zip(s.export_patches(l), unit.export_patches(l)):
+                assert np.array_equal(a, b)
+            for a, b in zip(s.export_prolongation(l), unit.export_prolongation(l)):
+                assert np.array_equal(a, b)
+    s.close()
+    unit.close()
+
+
+def test_mapped_option_errors():
+    """Mapped domains take generalized Stokes problems without time stepping,
+    one lane per residual row and no single-workgroup cycle; the caller
+    supplies the load; the radii must be ordered."""
+    from paper_1705_09282_amd.dfmg import Solver, DfmgError
+    for kw in ({"c": 1.0}, {"time_stepping": 1}, {"geometry": 2},
+               {"shape": {"r_inner": 0.3, "r_outer": 0.2}}, {"shape": {"r_inner": 0.0}}):
+        args = dict({"geometry": 1}, **kw)
+        with pytest.raises(DfmgError):
+            Solver(2, 8, 2, 1, **args)
+    with pytest.raises(DfmgError):
+        Solver(3, 4, 2, 1, geometry=1, shape={"depth": 0.0})
+    s = Solver(2, 16, 3, 1, geometry=1)
+    with pytest.raises(DfmgError):
+        s.manufactured_rhs()
+    with pytest.raises(DfmgError):
+        s.set_tuning([1, 2, 1], [1, 1, 1])
+    with pytest.raises(DfmgError):
+        s.set_tuning([1, 1, 1], [1, 5, 1])
+    s.set_tuning([1, 1, 1], [1, 3, 4])
+    s.close()

@@ -13,6 +13,9 @@ cylinder section of the numerical results).
   terms, div in polar form, boundary faces with arc-length measure; theta'
   and theta'' are taken by finite differences of atan2 of the map.
 * A divergence-free start (curl of potentials) has B^T u = 0.
+* The divergence norm on the mapped domain equals the unit-domain norm for
+  the identity map and, on the annulus, the quadrature of the physical
+  divergence (traces of the physical gradients) against det J.
 """
 import numpy as np
 import pytest
@@ -22,7 +25,8 @@ import workloads
 from oracle.spaces import Discretization
 from oracle.assemble import assemble, quadrature, tensor_eval, tensor_points, tensor_weights
 from oracle.complex import random_divfree_start
-from oracle.geometry import IdentityMap, QuarterAnnulus, assemble_mapped, physical_basis
+from oracle.geometry import IdentityMap, QuarterAnnulus, assemble_mapped, physical_basis, div_norm_mapped
+from oracle.diagnostics import div_norm
 
 
 def test_arc_and_jacobian():
@@ -194,3 +198,19 @@ def test_divergence_free_start_on_annulus(d, N, k):
                              workloads.random_coefficients(disc.n_q, 6))
     u = U[:disc.n_v]
     assert np.abs(B.T @ u).max() <= 1e-13 * np.abs(B).max() * np.abs(u).max()
+
+
+@pytest.mark.parametrize("d,N,k", [(2, 4, 1), (2, 3, 2), (3, 2, 1)])
+def test_div_norm_mapped(d, N, k):
+    disc = Discretization(d, N, k)
+    U = workloads.random_coefficients(disc.n, 9)
+    assert abs(div_norm_mapped(disc, IdentityMap(d), U) - div_norm(disc, U)) <= 1e-14 * div_norm(disc, U)
+    g = QuarterAnnulus(d)
+    pts, wts = quadrature(disc)
+    w = tensor_weights(wts)
+    div = 0.0
+    for c in range(d):
+        _, T, det = physical_basis(disc, g, c, pts)
+        div = div + sum(T[i][i] for i in range(d)) @ U[disc.offsets[c]:disc.offsets[c + 1]]
+    want = np.sqrt(np.sum(w * det * div * div))
+    assert abs(div_norm_mapped(disc, g, U) - want) <= 1e-10 * want

@@ -161,16 +161,19 @@ def lib():
     return _lib
 
 
-def _advection(c, kind, coeffs=None, keep=None):
+def _advection(c, kind, coeffs=None, keep=None, n_v=None):
     """dfmg_advection of speed c: kind None takes rotation (1) for c != 0 and
     none (0) otherwise; kind 2 advects with c times the manufactured velocity,
     kind 3 with c times the finest-grid velocity field `coeffs` (the array is
-    appended to `keep`, which must outlive the setup call)."""
+    appended to `keep`, which must outlive the setup call; n_v its expected
+    length)."""
     if kind is None:
         kind = 1 if c != 0.0 else 0
     a = Advection(int(kind), float(c), None)
-    if kind == 3:
-        arr = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if kind == 3 and coeffs is not None:  # without a field the library reports the error
+        arr = np.ascontiguousarray(coeffs, dtype=np.float64).ravel()
+        if n_v is not None and arr.size != n_v:
+            raise ValueError(f"advection field needs {n_v} coefficients, got {arr.size}")
         keep.append(arr)
         a.coeffs = _ptr(arr, ctypes.c_double)
     return a
@@ -304,7 +307,8 @@ class Solver:
         self.adv_kind = adv_kind
         keep = []
         fields = _per_problem(adv_coeffs, self.nprob)
-        adv = (Advection * self.nprob)(*[_advection(c, adv_kind, f, keep) for c, f in zip(cs, fields)])
+        n_v = dim * (n_elem + k - 1) * (n_elem + k) ** (dim - 1)
+        adv = (Advection * self.nprob)(*[_advection(c, adv_kind, f, keep, n_v) for c, f in zip(cs, fields)])
         nu_a = np.ascontiguousarray(nus, dtype=np.float64)
         sg_a = np.ascontiguousarray(sigmas, dtype=np.float64)
         opt = default_options(**options)

@@ -39,7 +39,11 @@ def test_error_conventions():
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, nu=0.0)
     with pytest.raises(dfmg.DfmgError):
-        dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=3)   # no such advection
+        dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=4)   # no such advection
+    with pytest.raises(dfmg.DfmgError):
+        dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=3)   # kind 3 without its field
+    with pytest.raises(ValueError):
+        dfmg.Solver(2, 8, 2, 1, c=1.0, adv_kind=3, adv_coeffs=np.zeros(5))
     with pytest.raises(dfmg.DfmgError):
         dfmg.Solver(2, 8, 2, 1, precision=1, inner_cycles=0)
     s = dfmg.Solver(2, 8, 2, 1)

@@ -357,8 +357,8 @@ def roofline_hbm(dev, reps=50):
     alg = 4 * z["nnz"] + 3 * 4 * z["n"]
     achieved = alg / (ms * 1e-3) / 1e9
     s.close()
-    return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (FP32 residual, one problem of 1024x1024 "
-                                      "elements, k=2)",
+    return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,false,float,true> (FP32 residual, one problem of "
+                                      "1024x1024 elements, k=2; 0.8 GB of values, streamed with non-temporal loads)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic({"n_elem": 1024, "levels": 8, "problems": 1}, TRAFFIC_FILE_HBM),
             "alg_bytes_per_launch": alg, "avg_launch_ms": ms, "setup_s": setup}
@@ -455,7 +455,7 @@ def main():
         z = b.sizes()
         alg = len(sigmas) * (4 * z["nnz"] + 3 * 4 * z["n"])
         achieved = alg / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,float> (finest-grid FP32 residual r = F - K U, "
+        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,false,float> (finest-grid FP32 residual r = F - K U, "
                                           f"{len(sigmas)} problems per launch)",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic({"n_elem": args.n_elem, "levels": args.levels}),

@@ -341,6 +341,10 @@ void up32(float *dst, const std::vector<double> &src, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
 }
 
+// operator values per residual launch (whole batch) above which they are
+// streamed with non-temporal loads: twice the Infinity Cache
+constexpr double kNtBytes = 512.0 * 1024 * 1024;
+
 template <class T>
 SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double *partial, const int *stop) {
     const HostLevel &h = c->S().lv[l];
@@ -355,6 +359,11 @@ SpmvArgsT<T> spmv_args(dfmg_ctx *c, int l, const T *F, const T *U, T *r, double 
     a.n = (int)h.n;
     a.win = h.win ? 1 : 0;
     a.xc = c->S().pb.geometry != 0 ? 1 : 0;
+    // values read once per launch and far beyond the 256 MB Infinity Cache:
+    // non-temporal loads, so that they do not evict the vector's lines (below
+    // that size the cache keeps part of them from one launch to the next, and
+    // non-temporal loads measured slower)
+    a.nt = (double)h.val.size() * sizeof(T) * c->np > kNtBytes ? 1 : 0;
     a.nblocks = spmv_blocks(h.n, c->lpr[l]);
     a.F = F;
     a.U = U;

@@ -52,6 +52,7 @@ struct SpmvArgsT {
     int n;
     int win;            // boxes stored as in-grid windows (see HostLevel)
     int xc;             // velocity rows couple every velocity component (mapped domain)
+    int nt;             // stream the values with non-temporal loads (lanes per row 1)
     int nblocks;        // logical blocks covering n rows (spmv_blocks)
     const T *F;
     const T *U;

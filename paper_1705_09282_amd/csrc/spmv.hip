@@ -9,8 +9,9 @@ namespace dfmg {
 // (GATE false: large grids, where the loads cost bandwidth), or load as usual
 // and skip the stores (GATE true: small grids, where the flag's load would
 // otherwise add its latency in front of every other load).  XC: the
-// velocity rows couple every velocity component (mapped domains).
-template <int D, int K, int LPR, bool WIN, bool GATE, bool XC, class T>
+// velocity rows couple every velocity component (mapped domains).  NT:
+// non-temporal value loads (see block_dot).
+template <int D, int K, int LPR, bool WIN, bool GATE, bool XC, class T, bool NT = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     const int prob = blockIdx.y;
     a.val += prob * a.sval;
@@ -28,13 +29,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgsT<T> a) {
     T acc = 0;
     if (active) {
         if (g < a.off[1]) {
-            acc = row_dot<D, K, 0, LPR, WIN, XC, T>(a, g, lane);
+            acc = row_dot<D, K, 0, LPR, WIN, XC, T, NT>(a, g, lane);
         } else if (g < a.off[2]) {
-            acc = row_dot<D, K, 1, LPR, WIN, XC, T>(a, g - (int)a.off[1], lane);
+            acc = row_dot<D, K, 1, LPR, WIN, XC, T, NT>(a, g - (int)a.off[1], lane);
         } else if (D == 3 && g < a.off[3]) {
-            acc = row_dot<D, K, (D == 3 ? 2 : 1), LPR, WIN, XC, T>(a, g - (int)a.off[2], lane);
+            acc = row_dot<D, K, (D == 3 ? 2 : 1), LPR, WIN, XC, T, NT>(a, g - (int)a.off[2], lane);
         } else {
-            acc = row_dot<D, K, D, LPR, WIN, XC, T>(a, g - (int)a.off[D], lane);
+            acc = row_dot<D, K, D, LPR, WIN, XC, T, NT>(a, g - (int)a.off[D], lane);
         }
     }
     // combine the LPR partial dot products of a row (lanes of a row are
@@ -57,6 +58,7 @@ template <int D, int K, bool WIN, bool GATE, class T>
 static void launch_dkwg(const SpmvArgsT<T> &a, int lpr, hipStream_t s) {
     const dim3 grid(padded_grid(a.nblocks), a.nprob);
     if (a.xc) hipLaunchKernelGGL((k_spmv<D, K, 1, WIN, GATE, true, T>), grid, dim3(kBlock), 0, s, a);  // lpr is 1
+    else if (a.nt && lpr == 1) hipLaunchKernelGGL((k_spmv<D, K, 1, WIN, GATE, false, T, true>), grid, dim3(kBlock), 0, s, a);
     else if (lpr == 4) hipLaunchKernelGGL((k_spmv<D, K, 4, WIN, GATE, false, T>), grid, dim3(kBlock), 0, s, a);
     else if (lpr == 2) hipLaunchKernelGGL((k_spmv<D, K, 2, WIN, GATE, false, T>), grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_spmv<D, K, 1, WIN, GATE, false, T>), grid, dim3(kBlock), 0, s, a);

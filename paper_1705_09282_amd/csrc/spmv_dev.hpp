@@ -31,8 +31,10 @@ __host__ __device__ constexpr int slot_off(int s) { return (s / kEll) * (64 * kE
 // and lies inside the grid (no per-slot clamping, x-offsets become constant
 // address offsets); otherwise slots outside the grid hold 0 and read a
 // clamped (valid) vector entry.  vp points at slot 0 of the row, s0 is the
-// first slot of this block.
-template <int D, int K, int R, int C, int LPR, bool WIN, class T>
+// first slot of this block.  NT: the values are loaded non-temporally (read
+// once per launch; used where a level's values far exceed the Infinity Cache,
+// so that they stream past the caches that hold the vector).
+template <int D, int K, int R, int C, int LPR, bool WIN, class T, bool NT = false>
 __device__ __forceinline__ T block_dot(const SpmvArgsT<T> &a, int i0, int i1, int i2, int lane, const T *vp,
                                        int s0) {
     using G = Geo<D, K>;
@@ -56,7 +58,8 @@ __device__ __forceinline__ T block_dot(const SpmvArgsT<T> &a, int i0, int i1, in
 #pragma unroll
         for (int o0 = 0; o0 < W0; ++o0) {
             const int j0 = WIN ? o0 : clampi(b0 + o0, 0, n0 - 1);
-            acc = fma(vp[slot_off(s0 + sr * W0 + o0)], urow[j0], acc);
+            const T *vq = vp + slot_off(s0 + sr * W0 + o0);
+            acc = fma(NT ? __builtin_nontemporal_load(vq) : *vq, urow[j0], acc);
         }
     }
     return acc;
@@ -93,7 +96,7 @@ __host__ __device__ constexpr int row_slots_padded() {
     return (row_slots<D, K, R, XC>() + kEll - 1) / kEll * kEll;
 }
 
-template <int D, int K, int R, int LPR, bool WIN, bool XC, class T>
+template <int D, int K, int R, int LPR, bool WIN, bool XC, class T, bool NT = false>
 __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
     const int i0 = li % nb0;
@@ -103,26 +106,26 @@ __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots_padded<D, K, R, XC>() * 64) + (li & 63) * kEll;
     T acc;
     if constexpr (R < D) {
-        acc = block_dot<D, K, R, R, LPR, WIN, T>(a, i0, i1, i2, lane, vp, 0);
-        acc += block_dot<D, K, R, D, LPR, WIN, T>(a, i0, i1, i2, lane, vp, block_slots<D, K, R, R>());
+        acc = block_dot<D, K, R, R, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, 0);
+        acc += block_dot<D, K, R, D, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, block_slots<D, K, R, R>());
         if constexpr (XC) {
             int s0 = block_slots<D, K, R, R>() + block_slots<D, K, R, D>();
             if constexpr (R != 0) {
-                acc += block_dot<D, K, R, 0, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+                acc += block_dot<D, K, R, 0, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, s0);
                 s0 += block_slots<D, K, R, 0>();
             }
             if constexpr (R != 1) {
-                acc += block_dot<D, K, R, 1, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+                acc += block_dot<D, K, R, 1, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, s0);
                 s0 += block_slots<D, K, R, 1>();
             }
             if constexpr (D == 3 && R != 2)
-                acc += block_dot<D, K, R, (D == 3 ? 2 : 0), LPR, WIN, T>(a, i0, i1, i2, lane, vp, s0);
+                acc += block_dot<D, K, R, (D == 3 ? 2 : 0), LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, s0);
         }
     } else {
         constexpr int s1 = block_slots<D, K, R, 0>(), s2 = s1 + block_slots<D, K, R, 1>();
-        acc = block_dot<D, K, R, 0, LPR, WIN, T>(a, i0, i1, i2, lane, vp, 0);
-        acc += block_dot<D, K, R, 1, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s1);
-        if constexpr (D == 3) acc += block_dot<D, K, R, 2, LPR, WIN, T>(a, i0, i1, i2, lane, vp, s2);
+        acc = block_dot<D, K, R, 0, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, 0);
+        acc += block_dot<D, K, R, 1, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, s1);
+        if constexpr (D == 3) acc += block_dot<D, K, R, 2, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, s2);
     }
     return acc;
 }

@@ -110,3 +110,27 @@ def test_oseen2d_full_size_learned_vs_fixed():
         print(f"[oseen] problem {i} oracle residual {res:.2e}", flush=True)
         assert res < 1.05e-8
     B.close()
+
+
+def test_streamed_residual_at_1024():
+    """Levels whose operator values far exceed the Infinity Cache load them
+    non-temporally (one lane per row): the FP64 residual of the 1024^2, k=2
+    problem (1.6 GB of values) equals the one with two lanes per row, which
+    loads them normally, to rounding."""
+    from paper_1705_09282_amd.dfmg import Solver
+    import workloads
+    print("\n[case] streamed residual 1024^2 k=2", flush=True)
+    s = Solver(2, 1024, 8, 2).bind()
+    n = s.n
+    F = torch.tensor(workloads.random_coefficients(n, 5), device="cuda")
+    U = torch.tensor(workloads.random_coefficients(n, 6), device="cuda")
+    out = []
+    for lpr in (1, 2):
+        s.set_tuning([1] * 7 + [lpr], [1] * 8)
+        r = torch.zeros_like(F)
+        s.level_residual(7, F, U, r)
+        out.append(r.cpu().numpy())
+    err = np.max(np.abs(out[0] - out[1])) / np.max(np.abs(out[0]))
+    print(f"[streamed] max rel diff {err:.1e}", flush=True)
+    assert err < 1e-13
+    s.close()

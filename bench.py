@@ -455,7 +455,7 @@ def main():
         z = b.sizes()
         alg = len(sigmas) * (4 * z["nnz"] + 3 * 4 * z["n"])
         achieved = alg / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,false,float> (finest-grid FP32 residual r = F - K U, "
+        return {"bound": "hbm", "kernel": "k_spmv<2,2,1,true,false,false,float,false> (finest-grid FP32 residual r = F - K U, "
                                           f"{len(sigmas)} problems per launch)",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic({"n_elem": args.n_elem, "levels": args.levels}),

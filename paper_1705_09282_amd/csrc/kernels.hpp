@@ -195,6 +195,12 @@ struct MultArgsT {
     int64_t nent;
     const T *M;            // per problem (stride sM)
     int64_t sM;
+    // the operator rows in lane order (nullptr: read them from sp.val): lane
+    // l = lane0 + w * width + t holds its entry's row at (l / 64) * mslots *
+    // 64 + (l % 64) * kEllVec, chunks 64 * kEllVec apart; per problem (stride smval)
+    const T *mval;
+    int64_t smval, lane0;
+    int mslots;
 };
 template <class T>
 void launch_schwarz_mult(int d, int k, const MultArgsT<T> &a, hipStream_t s);

@@ -13,6 +13,11 @@
 // residual entries meet in LDS, and thread t then applies its row of the
 // subdomain's bordered local inverse and adds the result to U_g in place
 // (plain read-modify-write: the colour's subdomains hold disjoint DOFs).
+// The rows of one colour are k+2 apart in the grid, so in the stencil-ELL
+// layout (64 consecutive rows per slice) a wavefront uses a fraction of
+// every line it loads; the sweep reads a copy of the operator values in lane
+// order instead, where a wavefront's rows are consecutive slots of a slice
+// (same values and order, so the same sums).
 #include "spmv_dev.hpp"
 
 namespace dfmg {
@@ -36,7 +41,13 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     if (e >= 0) {
         g = a.pdofs[e];
         info = a.ent_info[(int64_t)prob * a.nent + e];
-        r = sp.F[g] - spmv_row<D, K, WIN, XC, T>(sp, g);
+        if (a.mval) {  // the rows in lane order: a wavefront's value loads are contiguous
+            const int64_t lane = a.lane0 + (int64_t)w * B + threadIdx.x;
+            const T *vp = a.mval + prob * a.smval + (lane >> 6) * ((int64_t)a.mslots * 64) + (lane & 63) * kEll;
+            r = sp.F[g] - spmv_row_vp<D, K, WIN, XC, T>(sp, g, vp);
+        } else {
+            r = sp.F[g] - spmv_row<D, K, WIN, XC, T>(sp, g);
+        }
     }
     sr[threadIdx.x] = r;
     __syncthreads();

@@ -96,14 +96,15 @@ __host__ __device__ constexpr int row_slots_padded() {
     return (row_slots<D, K, R, XC>() + kEll - 1) / kEll * kEll;
 }
 
+// (K U) of row li of block R with its values at vp (slot 0 of the row; its
+// chunks 64 * kEll values apart)
 template <int D, int K, int R, int LPR, bool WIN, bool XC, class T, bool NT = false>
-__device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
+__device__ __forceinline__ T row_dot_vp(const SpmvArgsT<T> &a, int li, int lane, const T *vp) {
     const int nb0 = a.nb[R][0], nb1 = a.nb[R][1];
     const int i0 = li % nb0;
     const int t = li / nb0;
     const int i1 = t % nb1;
     const int i2 = t / nb1;
-    const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots_padded<D, K, R, XC>() * 64) + (li & 63) * kEll;
     T acc;
     if constexpr (R < D) {
         acc = block_dot<D, K, R, R, LPR, WIN, T, NT>(a, i0, i1, i2, lane, vp, 0);
@@ -130,6 +131,12 @@ __device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
     return acc;
 }
 
+template <int D, int K, int R, int LPR, bool WIN, bool XC, class T, bool NT = false>
+__device__ __forceinline__ T row_dot(const SpmvArgsT<T> &a, int li, int lane) {
+    const T *vp = a.val + a.val_off[R] + (int64_t)(li >> 6) * (row_slots_padded<D, K, R, XC>() * 64) + (li & 63) * kEll;
+    return row_dot_vp<D, K, R, LPR, WIN, XC, T, NT>(a, li, lane, vp);
+}
+
 // (K U)_g of row g of a level (LPR = 1; args already offset to one problem)
 template <int D, int K, bool WIN, bool XC, class T>
 __device__ __forceinline__ T spmv_row(const SpmvArgsT<T> &a, int g) {
@@ -137,6 +144,15 @@ __device__ __forceinline__ T spmv_row(const SpmvArgsT<T> &a, int g) {
     if (g < a.off[2]) return row_dot<D, K, 1, 1, WIN, XC, T>(a, g - (int)a.off[1], 0);
     if (D == 3 && g < a.off[3]) return row_dot<D, K, (D == 3 ? 2 : 1), 1, WIN, XC, T>(a, g - (int)a.off[2], 0);
     return row_dot<D, K, D, 1, WIN, XC, T>(a, g - (int)a.off[D], 0);
+}
+
+// (K U)_g of row g with its values at vp (a copy of the row in another order)
+template <int D, int K, bool WIN, bool XC, class T>
+__device__ __forceinline__ T spmv_row_vp(const SpmvArgsT<T> &a, int g, const T *vp) {
+    if (g < a.off[1]) return row_dot_vp<D, K, 0, 1, WIN, XC, T>(a, g, 0, vp);
+    if (g < a.off[2]) return row_dot_vp<D, K, 1, 1, WIN, XC, T>(a, g - (int)a.off[1], 0, vp);
+    if (D == 3 && g < a.off[3]) return row_dot_vp<D, K, (D == 3 ? 2 : 1), 1, WIN, XC, T>(a, g - (int)a.off[2], 0, vp);
+    return row_dot_vp<D, K, D, 1, WIN, XC, T>(a, g - (int)a.off[D], 0, vp);
 }
 
 }  // namespace dfmg

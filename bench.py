@@ -255,6 +255,55 @@ def annulus_legs(dev, steps=3, warmup=1):
     return out
 
 
+def mixed_batch_legs(dev, steps=3, warmup=1):
+    """The mixed batch (context): 256 independent 2D problems of the seeded
+    mix (grids 32^2..128^2, k in {1, 2}, sigma log-uniform in [1e-2, 1e4],
+    nu = 1, rotation |a| in [0, 10]), one captured graph with a branch per
+    mesh group, kernels and tiles autotuned per group; the manufactured load,
+    solved from U = 0 to 1e-8: FP64 with the fixed damping V(2,2) against
+    FP32 refinement with the learned Chebyshev schedule."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1705_09282_amd.dfmg import MultiSolver
+    from paper_1705_09282_amd import learned
+    probs = workloads.batch2d()
+    meshes = [(p["d"], p["N"], p["L"], p["k"]) for p in probs]
+    out = {"workload": f"{len(probs)} independent 2D generalized Stokes/Oseen problems, grids 32^2..128^2, "
+                       "k in {1,2}, sigma log-uniform [1e-2,1e4], nu=1, |a| in [0,10] (seed 5), coarsest 4x4, "
+                       "manufactured load, tol 1e-8, U0=0"}
+    for name, prec, sched in (("fp64_fixed_damping", 0, False), ("fp32_refined_learned_chebyshev", 1, True)):
+        t0 = time.perf_counter()
+        m = MultiSolver(meshes, [p["nu"] for p in probs], [p["sigma"] for p in probs], [p["c"] for p in probs],
+                        precision=prec).bind(dev)
+        m.autotune()
+        if sched:
+            learned.apply_chebyshev(m)
+        setup = time.perf_counter() - t0
+        F = torch.tensor(m.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        for _ in range(warmup):
+            U.zero_()
+            m.solve(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U.zero_()
+            st = m.solve(F, U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        cyc = [x["cycles"] for x in st]
+        out[name] = {"setup_and_tuning_s": setup, "ms_per_solve": 1e3 * dt,
+                     "dofs_per_s": (m.n_total - len(probs)) / dt, "mesh_groups": m.n_groups,
+                     "cycles_mean": float(np.mean(cyc)), "cycles_max": int(max(cyc)),
+                     "fallbacks": int(sum(bool(x.get("fallback")) for x in st)),
+                     "max_div_norm": float(m.div_norm(U).max())}
+        m.close()
+    out["speedup_fp32_learned_vs_fp64_fixed"] = (out["fp64_fixed_damping"]["ms_per_solve"] /
+                                                out["fp32_refined_learned_chebyshev"]["ms_per_solve"])
+    return out
+
+
 def cnab_legs(dev, nsteps=10):
     """Navier-Stokes by Crank-Nicolson / Adams-Bashforth steps (context):
     2D, k=2, 256^2, 6 grids, nu = 0.1, dt = 1e-3 (sigma = 2000; |u| dt / h
@@ -614,6 +663,8 @@ def main():
         line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
         print("[bench] the 3D workload (context)", file=sys.stderr, flush=True)
         line["config"]["stokes3d"] = stokes3d_legs(dev)
+        print("[bench] the mixed 256-problem batch (context)", file=sys.stderr, flush=True)
+        line["config"]["mixed_batch"] = mixed_batch_legs(dev)
         print("[bench] the quarter annulus (context)", file=sys.stderr, flush=True)
         line["config"]["annulus"] = annulus_legs(dev)
         print("[bench] Navier-Stokes CN/AB steps (context)", file=sys.stderr, flush=True)

@@ -204,7 +204,8 @@ def annulus_legs(dev, steps=3, warmup=1):
     manufactured solution is defined on the unit square), solved from U = 0
     to 1e-8: FP64 additive with the fixed damping V(2,2), FP64
     multiplicative V(1,2), and FP32 refinement with the learned Chebyshev
-    schedule; the host setup (quadrature assembly through the Piola maps,
+    schedule (its fallback thresholds measured by one fixed-damping solve of
+    the batch, reported apart); the host setup (quadrature assembly through the Piola maps,
     Galerkin products, per-subdomain inverses) reported apart; the FP32
     residual, whose velocity rows couple both components, timed alone."""
     import torch
@@ -221,8 +222,11 @@ def annulus_legs(dev, steps=3, warmup=1):
         b = BatchSolver(2, 256, 6, 2, [1.0] * len(sig), sig, geometry=1, max_cycles=400, **opt).bind(dev)
         setup = time.perf_counter() - t0
         b.autotune(reps=10)
+        learned_s = None
         if sched:
+            t1 = time.perf_counter()
             learned.apply_chebyshev(b)
+            learned_s = time.perf_counter() - t1
         n = b.n
         F = workloads.random_coefficients(len(sig) * n, 91)
         nv = 2 * (256 + 1) * (256 + 2)
@@ -242,6 +246,7 @@ def annulus_legs(dev, steps=3, warmup=1):
         dt = (time.perf_counter() - t0) / steps
         out[name] = {"setup_s": setup, "ms_per_solve": 1e3 * dt, "dofs_per_s": len(sig) * (n - 1) / dt,
                      "cycles_per_sigma": [x["cycles"] for x in st], "fallback": [x.get("fallback") for x in st],
+                     "learned_setup_s": learned_s,
                      "max_div_norm": float(b.div_norm(U).max())}
         if sched:
             ms = b.time_kernel(1, 5, reps=50)

@@ -411,13 +411,42 @@ def problem_features(solver):
                      for nu, sg, c in zip(solver.nus, solver.sigmas, solver.cs)])
 
 
+def measured_worst_plain(solver, tol=1e-8, seed=0):
+    """Fallback thresholds measured on the problems themselves: the worst
+    single-cycle residual ratio (cycles 2 on) of a solve with the fixed
+    damping from U = 0 to tol, with a seeded random velocity load (pressure
+    rows zero), in the solver's own precision -- the quantity the training
+    sweep records per training problem.  Leaves the solver on the fixed
+    damping."""
+    import torch
+    solver.set_learned(None)
+    solver.set_learned_chebyshev(None)
+    n, P = solver.n, solver.nprob
+    nv = solver.sizes()["n_vel"]
+    F = np.random.default_rng(seed).uniform(-1.0, 1.0, (P, n))
+    F[:, nv:] = 0.0
+    F = torch.tensor(F.ravel(), device=solver._ws.device)
+    U = torch.zeros_like(F)
+    st = solver._solve(F, U, tol, False)
+    return np.array([worst_cycle(x) for x in st])
+
+
+def fallback_thresholds(model, solver):
+    """Per problem: the threshold of the nearest training points, or on a
+    mapped domain (whose geometry the features do not describe, and whose
+    plain rate differs from the unit square's) the measured one."""
+    if getattr(solver, "geometry", 0):
+        return measured_worst_plain(solver)
+    return rho_plain_for(model, problem_features(solver))
+
+
 def apply(solver, model=None, fallback=True):
     """Switch a bound Solver/BatchSolver/MultiSolver to the learned dampings of `model`
-    (default: the shipped weights), with the fallback threshold of the
-    nearest training point.  A model trained with --chebyshev sets the
+    (default: the shipped weights), with the fallback thresholds of
+    fallback_thresholds().  A model trained with --chebyshev sets the
     learned Chebyshev schedule instead."""
     model = load() if model is None else model
-    rho = rho_plain_for(model, problem_features(solver)) if fallback else None
+    rho = fallback_thresholds(model, solver) if fallback else None
     if model["meta"].get("mode") == "chebyshev":
         solver.set_learned_chebyshev(model["W"], rho)
     else:

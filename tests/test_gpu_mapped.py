@@ -164,3 +164,41 @@ def test_mapped_table_protocol(d, table, nls, oracle_max, sigma, key):
     if d == 2:
         for nl, c in zip(nls, counts):
             assert abs(c - paper[nl - 1]) <= 4, (nl, c, paper[nl - 1])
+
+
+def test_mapped_learned_schedule_measures_its_threshold():
+    """The network's features do not describe the geometry, and on the
+    annulus the fixed damping's worst cycle ratio lies far above the unit
+    square's, so the fallback thresholds are measured on the problems: the
+    learned schedule then runs without falling back, in fewer cycles than the
+    fixed damping, to the same solution."""
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd import learned
+    sig = [1e-2, 1.0, 1e2, 1e4]
+    print("\n[case] annulus 64^2 k=2 L=4, learned Chebyshev schedule", flush=True)
+    b = BatchSolver(2, 64, 4, 2, [1.0] * 4, sig, geometry=1, max_cycles=400, precision=1).bind()
+    n = b.n
+    nv = b.sizes()["n_vel"]
+    F = workloads.random_coefficients(4 * n, 91).reshape(4, n)
+    F[:, nv:] = 0.0
+    F = dev(F.ravel())
+    U = torch.zeros_like(F)
+    plain = b.solve(F, U)
+    Up = host(U)
+    square = learned.rho_plain_for(learned.load(learned.CHEB_WEIGHTS), learned.problem_features(b))
+    thr = learned.measured_worst_plain(b)
+    learned.apply_chebyshev(b)
+    U.zero_()
+    st = b.solve(F, U)
+    got = host(U)
+    print(f"[mapped] thresholds measured {thr.round(3)} (unit square {square.round(3)}); cycles plain "
+          f"{[x['cycles'] for x in plain]} learned {[x['cycles'] for x in st]}", flush=True)
+    assert (thr > square).all()
+    for p in range(4):
+        assert st[p]["converged"] and not st[p]["fallback"]
+        assert st[p]["cycles"] < plain[p]["cycles"]
+        sl = slice(p * n, p * n + nv)
+        assert rel_l2(got[sl], Up[sl]) < 1e-6
+    vel = max(np.linalg.norm(got[p * n:p * n + nv]) for p in range(4))
+    assert b.div_norm(U).max() < 1e-10 * vel
+    b.close()

@@ -260,6 +260,53 @@ def annulus_legs(dev, steps=3, warmup=1):
     return out
 
 
+def oseen_mlp_legs(dev, steps=3, warmup=1):
+    """The learned-damping Oseen batch (context): 2D generalized Oseen, k=2,
+    128^2, 6 grids, sigma = 1, nu in {1, 0.1, 0.01} x |a|h/nu in {0, 0.25,
+    0.5, 1} (rotation), the twelve problems as one batch with the
+    manufactured load, autotuned, from U = 0 to 1e-8: FP64 fixed damping
+    V(2,2) against FP32 refinement with the network's constant dampings and
+    steps, and with its Chebyshev schedule."""
+    import torch
+    import workloads
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd import learned
+    probs = [workloads.oseen2d(nu, peh) for nu in workloads.OSEEN2D_NUS for peh in workloads.OSEEN2D_PEH]
+    p0 = probs[0]
+    out = {"workload": "2D generalized Oseen, k=2, 128^2, 6 grids, sigma=1, nu in {1, 0.1, 0.01} x |a|h/nu in "
+                       "{0, 0.25, 0.5, 1} (rotation), 12 problems as one batch, manufactured load, tol 1e-8, U0=0"}
+    for name, prec, mode in (("fp64_fixed_damping", 0, None), ("fp32_refined_learned_constant_damping", 1, "constant"),
+                             ("fp32_refined_learned_chebyshev", 1, "chebyshev")):
+        b = BatchSolver(2, p0["N"], p0["L"], p0["k"], [p["nu"] for p in probs], [p["sigma"] for p in probs],
+                        [p["c"] for p in probs], precision=prec, max_cycles=200).bind(dev)
+        b.autotune(reps=10)
+        if mode == "constant":
+            learned.apply(b)
+        elif mode == "chebyshev":
+            learned.apply_chebyshev(b)
+        F = torch.tensor(b.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        for _ in range(warmup):
+            U.zero_()
+            b.solve(F, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U.zero_()
+            st = b.solve(F, U)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_solve": 1e3 * dt, "dofs_per_s": len(probs) * (b.n - 1) / dt,
+                     "cycles": [x["cycles"] for x in st], "fallbacks": int(sum(x["fallback"] for x in st)),
+                     "steps_per_level_finest_first": b.get_smoothing()[0],
+                     "max_div_norm": float(b.div_norm(U).max())}
+        b.close()
+    base = out["fp64_fixed_damping"]["ms_per_solve"]
+    out["speedup_constant_damping"] = base / out["fp32_refined_learned_constant_damping"]["ms_per_solve"]
+    out["speedup_chebyshev"] = base / out["fp32_refined_learned_chebyshev"]["ms_per_solve"]
+    return out
+
+
 def mixed_batch_legs(dev, steps=3, warmup=1):
     """The mixed batch (context): 256 independent 2D problems of the seeded
     mix (grids 32^2..128^2, k in {1, 2}, sigma log-uniform in [1e-2, 1e4],
@@ -668,6 +715,8 @@ def main():
         line["config"]["paper_oseen_2d"] = paper_oseen_legs(dev)
         print("[bench] the 3D workload (context)", file=sys.stderr, flush=True)
         line["config"]["stokes3d"] = stokes3d_legs(dev)
+        print("[bench] the learned-damping Oseen batch (context)", file=sys.stderr, flush=True)
+        line["config"]["oseen_learned"] = oseen_mlp_legs(dev)
         print("[bench] the mixed 256-problem batch (context)", file=sys.stderr, flush=True)
         line["config"]["mixed_batch"] = mixed_batch_legs(dev)
         print("[bench] the quarter annulus (context)", file=sys.stderr, flush=True)

@@ -10,6 +10,35 @@
 
 namespace dfmg {
 
+// Host threads for the setup loops: every hardware thread, at most 16.
+static int setup_threads() {
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(h == 0 ? 1u : h, 16u));
+}
+
+// Runs body(i) for i in [0, n) on setup_threads() threads, contiguous chunks.
+template <class F>
+static void parallel_for(int64_t n, F body) {
+    const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n, 1));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) body(i, 0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    std::vector<std::exception_ptr> err(nt);
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) body(i, t);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    for (auto &th : pool) th.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 // ---------------------------------------------------------------- B-splines
 
 std::vector<double> open_knots(int N, int q) {
@@ -427,7 +456,8 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                 W[j] = G.width(R, C, j);
                 lo[j] = G.lo(R, C, j);
             }
-            for (int64_t li = 0; li < rows; ++li) {
+            // rows on the setup threads (each writes only its own slots)
+            parallel_for(rows, [&](int64_t li, int) {
                 int is[3], base[3] = {0, 0, 0};
                 int64_t t = li;
                 for (int j = 0; j < 3; ++j) {
@@ -457,7 +487,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                             }
                             L.val[L.ell_index(R, li, slot)] = v;
                         }
-            }
+            });
             int w = 1;
             for (int j = 0; j < d; ++j) w *= W[j];
             slot0 += w;
@@ -645,58 +675,100 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
                 }
     }
     L.n_patch = (int64_t)L.pptr.size() - 1;
-    // local inverses; subdomains whose bordered local systems agree to
-    // rounding (translates of one another on a uniform grid with constant
-    // coefficients) share one stored inverse
     L.moff.resize(L.n_patch);
     L.max_patch = 0;
+    for (int64_t i = 0; i < L.n_patch; ++i) L.max_patch = std::max(L.max_patch, L.pptr[i + 1] - L.pptr[i]);
     L.M.clear();
-    struct Cls {
-        int n;
-        int32_t off;
-        std::vector<double> A;
-    };
-    std::vector<Cls> classes;
-    std::vector<std::vector<int>> bucket(1 << 16);
-    std::vector<double> A, Ainv;
-    for (int64_t i = 0; i < L.n_patch; ++i) {
-        const int n = L.pptr[i + 1] - L.pptr[i];
-        L.max_patch = std::max(L.max_patch, n);
-        bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, A);
-        double scale = 0.0;
-        for (double x : A) scale = std::max(scale, std::fabs(x));
-        int found = -1;
-        uint64_t hsh = (uint64_t)n * 1469598103934665603ull;
-        if (share) {
-            // hash of a coarse quantization: equal matrices land in one bucket
-            for (double x : A) hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / scale * 4096.0)) * 1099511628211ull;
-            for (int c : bucket[hsh & 0xffff]) {
-                const Cls &C = classes[c];
-                if (C.n != n) continue;
-                double dmax = 0.0;
-                for (size_t t = 0; t < A.size(); ++t) dmax = std::max(dmax, std::fabs(A[t] - C.A[t]));
-                if (dmax <= 1e-14 * scale) {
-                    found = c;
-                    break;
+    const int nthr = setup_threads();
+    if (!share) {
+        // one inverse per subdomain, stored in subdomain order; the subdomains
+        // on the setup threads, each writing its own range
+        std::vector<int64_t> off(L.n_patch + 1, 0);
+        for (int64_t i = 0; i < L.n_patch; ++i) {
+            const int64_t n = L.pptr[i + 1] - L.pptr[i];
+            off[i + 1] = off[i] + n * n;
+        }
+        if (off[L.n_patch] > (int64_t)INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
+        L.M.assign((size_t)off[L.n_patch], 0.0);
+        std::vector<std::vector<double>> As(nthr), Ais(nthr);
+        parallel_for(L.n_patch, [&](int64_t i, int t) {
+            const int n = L.pptr[i + 1] - L.pptr[i];
+            bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, As[t]);
+            invert(n + 1, As[t], Ais[t]);
+            double *out = L.M.data() + off[i];
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) out[(size_t)a * n + b] = Ais[t][(size_t)a * (n + 1) + b];
+            L.moff[i] = (int32_t)off[i];
+        });
+        L.n_class = L.n_patch;
+    } else {
+        // local inverses; subdomains whose bordered local systems agree to
+        // rounding (translates of one another on a uniform grid with constant
+        // coefficients) share one stored inverse.  The local systems and their
+        // hashes are built on the setup threads, a chunk of subdomains at a
+        // time; the classes are then found in subdomain order.
+        struct Cls {
+            int n;
+            int32_t off;
+            std::vector<double> A;
+        };
+        std::vector<Cls> classes;
+        std::vector<std::vector<int>> bucket(1 << 16);
+        std::vector<double> Ainv;
+        const int64_t chunk = 8192;
+        std::vector<std::vector<double>> As(chunk);
+        std::vector<uint64_t> hs(chunk);
+        std::vector<double> sc(chunk);
+        for (int64_t c0 = 0; c0 < L.n_patch; c0 += chunk) {
+            const int64_t c1 = std::min(L.n_patch, c0 + chunk);
+            parallel_for(c1 - c0, [&](int64_t u, int) {
+                const int64_t i = c0 + u;
+                const int n = L.pptr[i + 1] - L.pptr[i];
+                std::vector<double> &A = As[u];
+                bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, A);
+                double scale = 0.0;
+                for (double x : A) scale = std::max(scale, std::fabs(x));
+                // hash of a coarse quantization: equal matrices land in one bucket
+                uint64_t hsh = (uint64_t)n * 1469598103934665603ull;
+                for (double x : A) hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / scale * 4096.0)) * 1099511628211ull;
+                hs[u] = hsh;
+                sc[u] = scale;
+            });
+            for (int64_t i = c0; i < c1; ++i) {
+                const int64_t u = i - c0;
+                const int n = L.pptr[i + 1] - L.pptr[i];
+                std::vector<double> &A = As[u];
+                const double scale = sc[u];
+                const uint64_t hsh = hs[u];
+                int found = -1;
+                for (int c : bucket[hsh & 0xffff]) {
+                    const Cls &C = classes[c];
+                    if (C.n != n) continue;
+                    double dmax = 0.0;
+                    for (size_t t = 0; t < A.size(); ++t) dmax = std::max(dmax, std::fabs(A[t] - C.A[t]));
+                    if (dmax <= 1e-14 * scale) {
+                        found = c;
+                        break;
+                    }
                 }
+                if (found < 0) {
+                    Cls C;
+                    C.n = n;
+                    C.off = (int32_t)L.M.size();
+                    C.A = A;
+                    invert(n + 1, A, Ainv);  // A is overwritten by the elimination
+                    for (int a = 0; a < n; ++a)
+                        for (int b = 0; b < n; ++b) L.M.push_back(Ainv[(size_t)a * (n + 1) + b]);
+                    if (L.M.size() > (size_t)INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
+                    found = (int)classes.size();
+                    bucket[hsh & 0xffff].push_back(found);
+                    classes.push_back(std::move(C));
+                }
+                L.moff[i] = classes[found].off;
             }
         }
-        if (found < 0) {
-            invert(n + 1, A, Ainv);  // A is overwritten by the elimination
-            Cls C;
-            C.n = n;
-            C.off = (int32_t)L.M.size();
-            bordered_system(pb, L, &L.pdofs[L.pptr[i]], n, C.A);
-            for (int a = 0; a < n; ++a)
-                for (int b = 0; b < n; ++b) L.M.push_back(Ainv[(size_t)a * (n + 1) + b]);
-            if (L.M.size() > (size_t)INT32_MAX) throw std::runtime_error("local inverse store exceeds 2^31 entries");
-            found = (int)classes.size();
-            if (share) bucket[hsh & 0xffff].push_back(found);
-            classes.push_back(std::move(C));
-        }
-        L.moff[i] = classes[found].off;
+        L.n_class = (int64_t)classes.size();
     }
-    L.n_class = (int64_t)classes.size();
     // inverse map: for each DOF the delta positions of its (patch, row)
     // entries, patch ascending
     L.inv_ptr.assign(L.n + 1, 0);
@@ -1164,75 +1236,96 @@ static void build_potential_maps_3d(const Problem &pb, HostLevel &L) {
     L.Q.clear();
     L.beta_row.clear();
     L.beta_patch.clear();
-    std::vector<int> loc;
-    std::vector<double> C, Qi;
-    std::vector<std::pair<int, double>> row;
-    std::vector<std::vector<int32_t>> qbucket(1 << 16);
-    std::vector<std::pair<int64_t, int64_t>> qclass;  // (size, offset)
-    for (int64_t i = 0; i < L.n_patch; ++i) {
-        const int o = L.ppot[4 * i], a[3] = {L.ppot[4 * i + 1], L.ppot[4 * i + 2], L.ppot[4 * i + 3]};
-        int e0[3], e1[3];
-        for (int j = 0; j < 3; ++j) {
-            e0[j] = std::max(0, a[j] - qd(o, j));
-            e1[j] = std::min(N - 1, a[j]);
-        }
-        loc.clear();
-        for (int o2 = 0; o2 < 3; ++o2)
-            for (int b2 = e0[2]; b2 <= e1[2] + qd(o2, 2); ++b2)
-                for (int b1 = e0[1]; b1 <= e1[1] + qd(o2, 1); ++b1)
-                    for (int b0 = e0[0]; b0 <= e1[0] + qd(o2, 0); ++b0) {
-                        const int b[3] = {b0, b1, b2};
-                        bool in = true;
-                        for (int j = 0; j < 3 && in; ++j)
-                            in = std::max(0, b[j] - qd(o2, j)) >= e0[j] && std::min(N - 1, b[j]) <= e1[j];
-                        if (!in) continue;
-                        const int64_t idx = pot_index(B[o2], b0, b1, b2);
-                        if (idx >= 0) loc.push_back((int)idx);
-                    }
-        const int np = (int)loc.size(), n = L.pptr[i + 1] - L.pptr[i];
-        const int32_t *dofs = &L.pdofs[L.pptr[i]];
-        int nv = 0;
-        while (nv < n && dofs[nv] < L.n_v) ++nv;
-        C.assign((size_t)nv * np, 0.0);
-        for (int r = 0; r < nv; ++r) {
-            curl_row3(L, k, c, dofs[r], row);
-            for (auto &e : row) {
-                const auto it = std::find(loc.begin(), loc.end(), e.first);
-                if (it != loc.end()) C[(size_t)r * np + (it - loc.begin())] += e.second;
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> qbucket(1 << 16);  // (size, offset) per hash
+    // per subdomain: its potentials, the local curl C and the map Q_i built on
+    // the setup threads, a chunk of subdomains at a time; the maps are then
+    // stored (and shared where equal) in subdomain order
+    const int64_t chunk = 4096;
+    const int nthr = setup_threads();
+    std::vector<std::vector<int>> locs(chunk);
+    std::vector<std::vector<double>> Qis(chunk), Cs(nthr);
+    std::vector<std::vector<std::pair<int, double>>> rows(nthr);
+    std::vector<uint64_t> hs(chunk);
+    std::vector<double> sc(chunk);
+    for (int64_t c0 = 0; c0 < L.n_patch; c0 += chunk) {
+        const int64_t c1 = std::min(L.n_patch, c0 + chunk);
+        parallel_for(c1 - c0, [&](int64_t u, int t) {
+            const int64_t i = c0 + u;
+            const int o = L.ppot[4 * i], a[3] = {L.ppot[4 * i + 1], L.ppot[4 * i + 2], L.ppot[4 * i + 3]};
+            int e0[3], e1[3];
+            for (int j = 0; j < 3; ++j) {
+                e0[j] = std::max(0, a[j] - qd(o, j));
+                e1[j] = std::min(N - 1, a[j]);
             }
-        }
-        pinv_solve(nv, np, n, C, &L.M[L.moff[i]], Qi);
-        check_curl_map(nv, np, n, C, Qi, &L.M[L.moff[i]], "3D local potential map");
-        double scale = 0.0;
-        for (double x : Qi) scale = std::max(scale, std::fabs(x));
-        uint64_t hsh = (uint64_t)(np * 64 + n) * 1469598103934665603ull;
-        for (double x : Qi)
-            hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / (scale > 0 ? scale : 1.0) * 4096.0)) * 1099511628211ull;
-        int32_t off = -1;
-        for (int32_t cand : qbucket[hsh & 0xffff]) {
-            const auto &ci = qclass[cand];
-            if (ci.first != (int64_t)Qi.size()) continue;
-            double dmax = 0.0;
-            for (size_t t = 0; t < Qi.size(); ++t) dmax = std::max(dmax, std::fabs(Qi[t] - L.Q[ci.second + t]));
-            if (dmax <= 1e-14 * scale) {
-                off = (int32_t)ci.second;
-                break;
+            std::vector<int> &loc = locs[u];
+            loc.clear();
+            for (int o2 = 0; o2 < 3; ++o2)
+                for (int b2 = e0[2]; b2 <= e1[2] + qd(o2, 2); ++b2)
+                    for (int b1 = e0[1]; b1 <= e1[1] + qd(o2, 1); ++b1)
+                        for (int b0 = e0[0]; b0 <= e1[0] + qd(o2, 0); ++b0) {
+                            const int b[3] = {b0, b1, b2};
+                            bool in = true;
+                            for (int j = 0; j < 3 && in; ++j)
+                                in = std::max(0, b[j] - qd(o2, j)) >= e0[j] && std::min(N - 1, b[j]) <= e1[j];
+                            if (!in) continue;
+                            const int64_t idx = pot_index(B[o2], b0, b1, b2);
+                            if (idx >= 0) loc.push_back((int)idx);
+                        }
+            const int np = (int)loc.size(), n = L.pptr[i + 1] - L.pptr[i];
+            const int32_t *dofs = &L.pdofs[L.pptr[i]];
+            int nv = 0;
+            while (nv < n && dofs[nv] < L.n_v) ++nv;
+            std::vector<double> &C = Cs[t];
+            C.assign((size_t)nv * np, 0.0);
+            for (int r = 0; r < nv; ++r) {
+                curl_row3(L, k, c, dofs[r], rows[t]);
+                for (auto &e : rows[t]) {
+                    const auto it = std::find(loc.begin(), loc.end(), e.first);
+                    if (it != loc.end()) C[(size_t)r * np + (it - loc.begin())] += e.second;
+                }
             }
+            std::vector<double> &Qi = Qis[u];
+            pinv_solve(nv, np, n, C, &L.M[L.moff[i]], Qi);
+            check_curl_map(nv, np, n, C, Qi, &L.M[L.moff[i]], "3D local potential map");
+            double scale = 0.0;
+            for (double x : Qi) scale = std::max(scale, std::fabs(x));
+            uint64_t hsh = (uint64_t)(np * 64 + n) * 1469598103934665603ull;
+            for (double x : Qi)
+                hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / (scale > 0 ? scale : 1.0) * 4096.0)) * 1099511628211ull;
+            hs[u] = hsh;
+            sc[u] = scale;
+        });
+        for (int64_t i = c0; i < c1; ++i) {
+            const int64_t u = i - c0;
+            const std::vector<int> &loc = locs[u];
+            const std::vector<double> &Qi = Qis[u];
+            const int np = (int)loc.size(), n = L.pptr[i + 1] - L.pptr[i];
+            const double scale = sc[u];
+            const uint64_t hsh = hs[u];
+            int32_t off = -1;
+            for (const auto &ci : qbucket[hsh & 0xffff]) {
+                if (ci.first != (int64_t)Qi.size()) continue;
+                double dmax = 0.0;
+                for (size_t t = 0; t < Qi.size(); ++t) dmax = std::max(dmax, std::fabs(Qi[t] - L.Q[ci.second + t]));
+                if (dmax <= 1e-14 * scale) {
+                    off = (int32_t)ci.second;
+                    break;
+                }
+            }
+            if (off < 0) {
+                off = (int32_t)L.Q.size();
+                qbucket[hsh & 0xffff].push_back({(int64_t)Qi.size(), (int64_t)off});
+                L.Q.insert(L.Q.end(), Qi.begin(), Qi.end());
+                if (L.Q.size() > (size_t)INT32_MAX) throw std::runtime_error("potential map store exceeds 2^31 entries");
+            }
+            L.qoff.push_back(off);
+            for (int t = 0; t < np; ++t) {
+                L.beta_row.push_back((int32_t)(off + (size_t)t * n));
+                L.beta_patch.push_back((int32_t)i);
+            }
+            L.qpsi.insert(L.qpsi.end(), loc.begin(), loc.end());
+            L.qptr.push_back((int32_t)L.qpsi.size());
         }
-        if (off < 0) {
-            off = (int32_t)L.Q.size();
-            qbucket[hsh & 0xffff].push_back((int32_t)qclass.size());
-            qclass.push_back({(int64_t)Qi.size(), (int64_t)off});
-            L.Q.insert(L.Q.end(), Qi.begin(), Qi.end());
-            if (L.Q.size() > (size_t)INT32_MAX) throw std::runtime_error("potential map store exceeds 2^31 entries");
-        }
-        L.qoff.push_back(off);
-        for (int t = 0; t < np; ++t) {
-            L.beta_row.push_back((int32_t)(off + (size_t)t * n));
-            L.beta_patch.push_back((int32_t)i);
-        }
-        L.qpsi.insert(L.qpsi.end(), loc.begin(), loc.end());
-        L.qptr.push_back((int32_t)L.qpsi.size());
     }
     finish_potential_maps(L);
 }
@@ -1450,36 +1543,6 @@ static int stencil_slot(const HostLevel &L, const BlockGeom &G, int R, int C, in
     }
     return slot + (o[2] * W[1] + o[1]) * W[0] + o[0];
 }
-
-// Host threads for the setup loops (the GPU machines give a process 16 cores).
-static int setup_threads() {
-    const unsigned h = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(h == 0 ? 1u : h, 16u));
-}
-
-// Runs body(i) for i in [0, n) on setup_threads() threads, contiguous chunks.
-template <class F>
-static void parallel_for(int64_t n, F body) {
-    const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n, 1));
-    if (nt <= 1) {
-        for (int64_t i = 0; i < n; ++i) body(i, 0);
-        return;
-    }
-    std::vector<std::thread> pool;
-    std::vector<std::exception_ptr> err(nt);
-    for (int t = 0; t < nt; ++t)
-        pool.emplace_back([&, t] {
-            try {
-                for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) body(i, t);
-            } catch (...) {
-                err[t] = std::current_exception();
-            }
-        });
-    for (auto &th : pool) th.join();
-    for (auto &e : err)
-        if (e) std::rethrow_exception(e);
-}
-
 
 // Runs body(e0, e1, e2, thread) for every element of the N^d grid, colour by
 // colour with colour (e mod (k+2)) per direction, the elements of a colour on

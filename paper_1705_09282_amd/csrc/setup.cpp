@@ -1709,6 +1709,17 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
     const double h = 1.0 / N;
     const auto kn0 = open_knots(N, k), kn1 = open_knots(N, k + 1);
     BlockGeom G{d, k};
+    // the degree-k and degree-(k+1) functions and derivatives non-zero on each
+    // element, at its quadrature points (the same in every direction)
+    const int w0 = k + 1, w1 = k + 2;
+    std::vector<double> tv0((size_t)N * nq * w0), td0(tv0.size()), tv1((size_t)N * nq * w1), td1(tv1.size());
+    for (int e = 0; e < N; ++e)
+        for (int g = 0; g < nq; ++g) {
+            const double x = (e + 0.5 * (t[g] + 1.0)) * h;
+            const size_t at = (size_t)e * nq + g;
+            span_basis(kn0, k, e + k, x, &tv0[at * w0], &td0[at * w0]);
+            span_basis(kn1, k + 1, e + k + 1, x, &tv1[at * w1], &td1[at * w1]);
+        }
     // fine level: element matrices over the quadrature points, scattered
     // once per element into an array of the stencil-ELL shape
     std::vector<double> adv(F.val.size(), 0.0);
@@ -1716,7 +1727,17 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
     struct Fn {
         int64_t gidx;
         int m[3];
+        int st[3];  // tensor index of the function in its block
     };
+    // slot geometry of the same-component blocks (c, c)
+    int Wc[3][3], loc_[3][3], sbase[3];
+    for (int c = 0; c < d; ++c) {
+        sbase[c] = G.slot_base(c, c);
+        for (int jj = 0; jj < 3; ++jj) {
+            Wc[c][jj] = jj < d ? G.width(c, c, jj) : 1;
+            loc_[c][jj] = jj < d ? G.lo(c, c, jj) : 0;
+        }
+    }
     // elements colour by colour (see for_each_element_coloured): the threads
     // of a colour add to disjoint rows of adv
     for_each_element_coloured(d, N, k, [&](int e0, int e1, int e2, int) {
@@ -1731,12 +1752,13 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
             for (int m2 = 0; m2 <= m2max; ++m2)
                 for (int m1 = 0; m1 <= q[1]; ++m1)
                     for (int m0 = 0; m0 <= q[0]; ++m0) {
-                        Fn f{0, {m0, m1, m2}};
+                        Fn f{0, {m0, m1, m2}, {0, 0, 0}};
                         int64_t idx = 0, stride = 1;
                         bool ok = true;
                         for (int jj = 0; jj < d; ++jj) {
                             const int st = e[jj] + f.m[jj] - G.s(c, jj);
                             if (st < 0 || st >= F.nb[c][jj]) ok = false;
+                            f.st[jj] = st;
                             idx += (int64_t)st * stride;
                             stride *= F.nb[c][jj];
                         }
@@ -1748,22 +1770,26 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
         std::vector<double> E[3];
         for (int c = 0; c < d; ++c) E[c].assign(fns[c].size() * fns[c].size(), 0.0);
         std::vector<double> fv[3], fdv[3];
+        for (int c = 0; c < d; ++c) {  // every used entry is written at each point
+            fv[c].assign(fns[c].size(), 0.0);
+            fdv[c].assign(fns[c].size() * 3, 0.0);
+        }
         for (int g2 = 0; g2 < G2; ++g2)
             for (int g1 = 0; g1 < nq; ++g1)
                 for (int g0 = 0; g0 < nq; ++g0) {
                     const int g[3] = {g0, g1, g2};
                     double wq = 1.0;
                     for (int jj = 0; jj < d; ++jj) {
-                        const double x = (e[jj] + 0.5 * (t[g[jj]] + 1.0)) * h;
                         wq *= 0.5 * h * wt[g[jj]];
-                        span_basis(kn0, k, e[jj] + k, x, val[jj][0], der[jj][0]);
-                        span_basis(kn1, k + 1, e[jj] + k + 1, x, val[jj][1], der[jj][1]);
+                        const size_t at = (size_t)e[jj] * nq + g[jj];
+                        std::copy(&tv0[at * w0], &tv0[at * w0] + w0, val[jj][0]);
+                        std::copy(&td0[at * w0], &td0[at * w0] + w0, der[jj][0]);
+                        std::copy(&tv1[at * w1], &tv1[at * w1] + w1, val[jj][1]);
+                        std::copy(&td1[at * w1], &td1[at * w1] + w1, der[jj][1]);
                     }
                     double a[3] = {0, 0, 0};
                     for (int c = 0; c < d; ++c) {
                         const size_t nf = fns[c].size();
-                        fv[c].assign(nf, 0.0);
-                        fdv[c].assign(nf * 3, 0.0);
                         for (size_t fi = 0; fi < nf; ++fi) {
                             const Fn &f = fns[c][fi];
                             double v = 1.0;
@@ -1793,53 +1819,74 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
             const size_t nf = fns[c].size();
             for (size_t ai = 0; ai < nf; ++ai) {
                 const int64_t row = fns[c][ai].gidx - F.off[c];
+                int base[3] = {0, 0, 0};
+                for (int jj = 0; jj < d; ++jj)
+                    base[jj] = box_start(F.win, fns[c][ai].st[jj], loc_[c][jj], Wc[c][jj], F.nb[c][jj]);
                 for (size_t bj = 0; bj < nf; ++bj) {
-                    const int slot = stencil_slot(F, G, c, c, row, fns[c][bj].gidx - F.off[c]);
-                    if (slot < 0) throw std::runtime_error("advection entry outside the stored pattern");
+                    // the slot of column function bj in row ai's box (as stencil_slot)
+                    int o[3] = {0, 0, 0};
+                    for (int jj = 0; jj < d; ++jj) {
+                        o[jj] = fns[c][bj].st[jj] - base[jj];
+                        if (o[jj] < 0 || o[jj] >= Wc[c][jj])
+                            throw std::runtime_error("advection entry outside the stored pattern");
+                    }
+                    const int slot = sbase[c] + (o[2] * Wc[c][1] + o[1]) * Wc[c][0] + o[0];
                     adv[F.ell_index(c, row, slot)] += E[c][ai * nf + bj];
                 }
             }
         }
     });
-    // CSR of the fine advection (velocity rows, same-component columns)
-    Csr cur;
-    cur.rp.assign(1, 0);
-    for (int c = 0; c < d; ++c) {
-        int W[3] = {1, 1, 1}, lo[3] = {0, 0, 0};
-        for (int jj = 0; jj < d; ++jj) {
-            W[jj] = G.width(c, c, jj);
-            lo[jj] = G.lo(c, c, jj);
+    // CSR of the fine advection (velocity rows, same-component columns, the
+    // non-zeros of each row in slot order): counts per row, then the entries,
+    // both passes with the rows on the setup threads
+    const int64_t nvrow = F.off[d];
+    auto scan_row = [&](int64_t r, auto &&emit) {
+        int c = 0;
+        while (r >= F.off[c + 1]) ++c;
+        const int64_t li = r - F.off[c];
+        int is[3] = {0, 0, 0}, base[3] = {0, 0, 0};
+        int64_t tt = li;
+        for (int jj = 0; jj < 3; ++jj) {
+            is[jj] = (int)(tt % F.nb[c][jj]);
+            tt /= F.nb[c][jj];
+            if (jj < d) base[jj] = box_start(F.win, is[jj], loc_[c][jj], Wc[c][jj], F.nb[c][jj]);
         }
-        const int64_t rows = F.off[c + 1] - F.off[c];
-        for (int64_t li = 0; li < rows; ++li) {
-            int is[3] = {0, 0, 0}, base[3] = {0, 0, 0};
-            int64_t tt = li;
-            for (int jj = 0; jj < 3; ++jj) {
-                is[jj] = (int)(tt % F.nb[c][jj]);
-                tt /= F.nb[c][jj];
-                if (jj < d) base[jj] = box_start(F.win, is[jj], lo[jj], W[jj], F.nb[c][jj]);
-            }
-            int slot = 0;  // block (c, c) comes first in a velocity row
-            for (int o2 = 0; o2 < W[2]; ++o2)
-                for (int o1 = 0; o1 < W[1]; ++o1)
-                    for (int o0 = 0; o0 < W[0]; ++o0, ++slot) {
-                        const int o[3] = {o0, o1, o2};
-                        int64_t col = 0, stride = 1;
-                        bool ok = true;
-                        for (int jj = 0; jj < d; ++jj) {
-                            const int js = base[jj] + o[jj];
-                            if (js < 0 || js >= F.nb[c][jj]) ok = false;
-                            col += (int64_t)js * stride;
-                            stride *= F.nb[c][jj];
-                        }
-                        const double v = adv[F.ell_index(c, li, slot)];
-                        if (!ok || v == 0.0) continue;
-                        cur.ci.push_back((int32_t)(F.off[c] + col));
-                        cur.v.push_back(v);
+        int slot = 0;  // block (c, c) comes first in a velocity row
+        for (int o2 = 0; o2 < Wc[c][2]; ++o2)
+            for (int o1 = 0; o1 < Wc[c][1]; ++o1)
+                for (int o0 = 0; o0 < Wc[c][0]; ++o0, ++slot) {
+                    const int o[3] = {o0, o1, o2};
+                    int64_t col = 0, stride = 1;
+                    bool ok = true;
+                    for (int jj = 0; jj < d; ++jj) {
+                        const int js = base[jj] + o[jj];
+                        if (js < 0 || js >= F.nb[c][jj]) ok = false;
+                        col += (int64_t)js * stride;
+                        stride *= F.nb[c][jj];
                     }
-            cur.rp.push_back((int64_t)cur.ci.size());
-        }
-    }
+                    const double v = adv[F.ell_index(c, li, slot)];
+                    if (!ok || v == 0.0) continue;
+                    emit(F.off[c] + col, v);
+                }
+    };
+    Csr cur;
+    cur.rp.assign(nvrow + 1, 0);
+    parallel_for(nvrow, [&](int64_t r, int) {
+        int64_t m = 0;
+        scan_row(r, [&](int64_t, double) { ++m; });
+        cur.rp[r + 1] = m;
+    });
+    for (int64_t r = 0; r < nvrow; ++r) cur.rp[r + 1] += cur.rp[r];
+    cur.ci.assign(cur.rp[nvrow], 0);
+    cur.v.assign(cur.rp[nvrow], 0.0);
+    parallel_for(nvrow, [&](int64_t r, int) {
+        int64_t at = cur.rp[r];
+        scan_row(r, [&](int64_t col, double v) {
+            cur.ci[at] = (int32_t)col;
+            cur.v[at] = v;
+            ++at;
+        });
+    });
     for (size_t x = 0; x < adv.size(); ++x) F.val[x] += adv[x];
     adv.clear();
     adv.shrink_to_fit();

@@ -16,10 +16,12 @@ static int setup_threads() {
     return (int)std::max(1u, std::min(h == 0 ? 1u : h, 16u));
 }
 
-// Runs body(i) for i in [0, n) on setup_threads() threads, contiguous chunks.
+// Runs body(i) for i in [0, n) on up to setup_threads() threads, contiguous
+// chunks of at least `grain` items (small loops stay on the calling thread,
+// where starting threads would cost more than the work).
 template <class F>
-static void parallel_for(int64_t n, F body) {
-    const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n, 1));
+static void parallel_for(int64_t n, F body, int64_t grain = 1) {
+    const int nt = (int)std::min<int64_t>(setup_threads(), std::max<int64_t>(n / std::max<int64_t>(grain, 1), 1));
     if (nt <= 1) {
         for (int64_t i = 0; i < n; ++i) body(i, 0);
         return;
@@ -487,7 +489,7 @@ static void fill_matrix(const Problem &pb, const Factors &F, HostLevel &L) {
                             }
                             L.val[L.ell_index(R, li, slot)] = v;
                         }
-            });
+            }, 2048);
             int w = 1;
             for (int j = 0; j < d; ++j) w *= W[j];
             slot0 += w;
@@ -699,7 +701,7 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
             for (int a = 0; a < n; ++a)
                 for (int b = 0; b < n; ++b) out[(size_t)a * n + b] = Ais[t][(size_t)a * (n + 1) + b];
             L.moff[i] = (int32_t)off[i];
-        });
+        }, 128);
         L.n_class = L.n_patch;
     } else {
         // local inverses; subdomains whose bordered local systems agree to
@@ -733,7 +735,7 @@ static void build_patches(const Problem &pb, HostLevel &L, bool share) {
                 for (double x : A) hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / scale * 4096.0)) * 1099511628211ull;
                 hs[u] = hsh;
                 sc[u] = scale;
-            });
+            }, 256);
             for (int64_t i = c0; i < c1; ++i) {
                 const int64_t u = i - c0;
                 const int n = L.pptr[i + 1] - L.pptr[i];
@@ -1294,7 +1296,7 @@ static void build_potential_maps_3d(const Problem &pb, HostLevel &L) {
                 hsh = (hsh ^ (uint64_t)(int64_t)std::llround(x / (scale > 0 ? scale : 1.0) * 4096.0)) * 1099511628211ull;
             hs[u] = hsh;
             sc[u] = scale;
-        });
+        }, 16);
         for (int64_t i = c0; i < c1; ++i) {
             const int64_t u = i - c0;
             const std::vector<int> &loc = locs[u];
@@ -1562,7 +1564,7 @@ static void for_each_element_coloured(int d, int N, int k, F body) {
                 parallel_for((int64_t)n0 * n1 * n2, [&](int64_t i, int th) {
                     const int i0 = (int)(i % n0), i1 = (int)((i / n0) % n1), i2 = (int)(i / ((int64_t)n0 * n1));
                     body(c0 + stride * i0, c1 + stride * i1, c2 + stride * i2, th);
-                });
+                }, 64);
             }
 }
 
@@ -1581,7 +1583,7 @@ struct Csr {
 // it uses; columns sorted.  Chunks of rows on the setup threads, each row
 // summed in the same order whatever the chunking.
 static Csr galerkin_rows(const HostLevel &Fl, const Csr &A, int64_t nrows, int64_t ncoarse) {
-    const int nch = setup_threads();
+    const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(setup_threads(), nrows / 2048));
     std::vector<Csr> part(nch);
     parallel_for(nch, [&](int64_t ch, int) {
         Csr &out = part[ch];
@@ -1875,7 +1877,7 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
         int64_t m = 0;
         scan_row(r, [&](int64_t, double) { ++m; });
         cur.rp[r + 1] = m;
-    });
+    }, 4096);
     for (int64_t r = 0; r < nvrow; ++r) cur.rp[r + 1] += cur.rp[r];
     cur.ci.assign(cur.rp[nvrow], 0);
     cur.v.assign(cur.rp[nvrow], 0.0);
@@ -1886,7 +1888,7 @@ static void add_field_advection(const Problem &pb, Hierarchy &H) {
             cur.v[at] = v;
             ++at;
         });
-    });
+    }, 4096);
     for (size_t x = 0; x < adv.size(); ++x) F.val[x] += adv[x];
     adv.clear();
     adv.shrink_to_fit();

@@ -71,6 +71,7 @@ struct DevLevel {
     int32_t *P_rp = nullptr, *P_ci = nullptr, *R_rp = nullptr, *R_ci = nullptr;
     int32_t *P_eci = nullptr, *R_eci = nullptr, *inv_ell = nullptr, *inv4_ell = nullptr;
     int32_t *mlane = nullptr;  // lane table of the multiplicative sweep
+    int32_t *mstride = nullptr;  // its per-workgroup entry strides
     int4 *bmesh = nullptr;
     // per problem (form 4): small-subdomain and remaining-subdomain tables
     int4 *sinfo = nullptr;
@@ -294,7 +295,10 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.R_ci = A.take<int32_t>(h.R_ci.size());
         v.moff = A.take<int32_t>(h.n_patch * np);
         v.ent_info = A.take<int4>(v.nent * np);
-        if (c->mult()) v.mlane = A.take<int32_t>(h.mlane.size());
+        if (c->mult()) {
+            v.mlane = A.take<int32_t>(h.mlane.size());
+            v.mstride = A.take<int32_t>(h.mstride.size());
+        }
     }
     c->nparts = padded_grid(maxblocks);
     c->eta = A.take<double>((size_t)L * np);
@@ -567,6 +571,7 @@ void mult_sweep(dfmg_ctx *c, int l, const T *F, T *U, const int *stop) {
     for (size_t col = 0; col + 1 < h.mwave_ptr.size(); ++col) {
         a.lane0 = (int64_t)h.mwave_ptr[col] * h.mwidth;
         a.lanes = v.mlane + (int64_t)h.mwave_ptr[col] * h.mwidth;
+        a.strides = v.mstride + h.mwave_ptr[col];
         a.nwaves = h.mwave_ptr[col + 1] - h.mwave_ptr[col];
         launch_schwarz_mult<T>(c->S().pb.d, c->S().pb.k, a, c->s);
     }
@@ -1411,7 +1416,10 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
             up(v.inv_pos4, h.inv_pos4, s);
             up(v.inv_ell, h.inv_ell, s);
             up(v.inv4_ell, h.inv4_ell, s);
-            if (c->mult()) up(v.mlane, h.mlane, s);
+            if (c->mult()) {
+                up(v.mlane, h.mlane, s);
+                up(v.mstride, h.mstride, s);
+            }
             if (c->mult() && v.d.mval) {
                 // the operator rows in lane order, per problem
                 std::vector<double> mv((size_t)v.smval);

@@ -188,6 +188,7 @@ struct MultArgsT {
     SpmvArgsT<T> sp;       // operator and vectors (sp.r unused)
     T *U;                  // the same U as sp.U, written
     const int32_t *lanes;  // this colour's workgroups: entry of thread t of group w at w * width + t, -1 unused
+    const int32_t *strides;  // per workgroup: threads between a subdomain's consecutive entries
     int nwaves;
     int width;             // threads per workgroup: kMultLanes or kMultLanesBig
     const int32_t *pdofs;  // shared

@@ -7,12 +7,16 @@
 // update inside a colour changes the residual another one reads.  One launch
 // per colour; a workgroup takes up to B (subdomain, row) entries of the
 // colour (B = 256, or 1024 on levels with larger subdomains; from the host's
-// lane table, where a subdomain's entries are consecutive threads of one
-// workgroup): thread t computes the residual of
-// its DOF, (F - K U)_g, straight from the operator row, the workgroup's
-// residual entries meet in LDS, and thread t then applies its row of the
-// subdomain's bordered local inverse and adds the result to U_g in place
-// (plain read-modify-write: the colour's subdomains hold disjoint DOFs).
+// lane table, where a subdomain's entries lie in one workgroup, `stride`
+// threads apart: consecutive, or interleaved with those of other subdomains
+// of the same size, so that a wavefront holds one local row of many
+// subdomains -- rows of one block, one row form): thread t computes the
+// residual of its DOF, (F - K U)_g, straight from the operator row, the
+// workgroup's residual entries meet in LDS, and thread t then applies its row
+// of the subdomain's bordered local inverse and adds the result to U_g in
+// place (plain read-modify-write: the colour's subdomains hold disjoint
+// DOFs).  The layout decides only which thread does what: every sum runs in
+// the same order.
 // The rows of one colour are k+2 apart in the grid, so in the stencil-ELL
 // layout (64 consecutive rows per slice) a wavefront uses a fraction of
 // every line it loads; the sweep reads a copy of the operator values in lane
@@ -35,6 +39,7 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     __shared__ T sr[B];
     const int w = blockIdx.x;
     const int e = w < a.nwaves ? a.lanes[(int64_t)w * B + threadIdx.x] : -1;
+    const int stride = w < a.nwaves ? a.strides[w] : 1;
     int g = 0;
     int4 info = make_int4(0, 0, 0, 0);
     T r = 0;
@@ -52,12 +57,12 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
     sr[threadIdx.x] = r;
     __syncthreads();
     if (e >= 0) {
-        // the subdomain's entries sit on consecutive threads; this thread
-        // holds local row m = e - (first entry of the subdomain)
-        const T *loc = sr + (int)threadIdx.x - (e - info.y);
+        // this thread holds local row m = e - (first entry of the subdomain);
+        // entry c of the subdomain sits on thread t + (c - m) * stride
+        const T *loc = sr + (int)threadIdx.x - (e - info.y) * stride;
         const T *mrow = a.M + prob * a.sM + info.x;
         T acc = 0;
-        for (int c = 0; c < info.z; ++c) acc = fma(mrow[c], loc[c], acc);
+        for (int c = 0; c < info.z; ++c) acc = fma(mrow[c], loc[c * stride], acc);
         if (!halt) U[g] += acc;
     }
 }

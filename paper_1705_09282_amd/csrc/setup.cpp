@@ -812,15 +812,37 @@ static void build_sweep_lanes(HostLevel &L) {
     for (int64_t i = 0; i < L.n_patch; ++i) members[L.mcolor[i]].push_back((int32_t)i);
     L.mwave_ptr.assign(1, 0);
     L.mlane.clear();
+    L.mstride.clear();
     const int B = L.max_patch <= kMultLanes ? kMultLanes : kMultLanesBig;
     if (L.max_patch > B) throw std::runtime_error("multiplicative Schwarz needs subdomains of at most 1024 DOFs");
     L.mwidth = B;
+    // the most common subdomain size (the interior one): those subdomains go
+    // interleaved, B / n of them per workgroup, so that the threads of a
+    // wavefront hold the same local row of many subdomains, i.e. rows of one
+    // block, and evaluate one row form
+    std::vector<int64_t> count(B + 1, 0);
+    for (int64_t i = 0; i < L.n_patch; ++i) count[L.pptr[i + 1] - L.pptr[i]]++;
+    int nu = 0;
+    for (int n = 1; n <= B; ++n)
+        if (count[n] > (nu ? count[nu] : 0)) nu = n;
+    const int S = nu > 0 && B % nu == 0 && B / nu >= 2 ? B / nu : 0;
     for (int c = 0; c < ncol; ++c) {
-        int fill = B;  // forces a new workgroup for the colour's first subdomain
-        for (int32_t p : members[c]) {
+        std::vector<int32_t> inter, rest;
+        for (int32_t p : members[c]) (S && L.pptr[p + 1] - L.pptr[p] == nu ? inter : rest).push_back(p);
+        for (size_t q0 = 0; q0 < inter.size(); q0 += S) {
+            const int Sw = (int)std::min<size_t>(S, inter.size() - q0);
+            const size_t w0 = L.mlane.size();
+            L.mlane.insert(L.mlane.end(), B, -1);
+            for (int s = 0; s < Sw; ++s)
+                for (int m = 0; m < nu; ++m) L.mlane[w0 + (size_t)m * Sw + s] = L.pptr[inter[q0 + s]] + m;
+            L.mstride.push_back(Sw);
+        }
+        int fill = B;  // forces a new workgroup for the first consecutive subdomain
+        for (int32_t p : rest) {
             const int n = L.pptr[p + 1] - L.pptr[p];
             if (fill + n > B) {
                 L.mlane.insert(L.mlane.end(), B, -1);
+                L.mstride.push_back(1);
                 fill = 0;
             }
             const size_t w0 = L.mlane.size() - B;

@@ -111,8 +111,12 @@ struct HostLevel {
     // multiplicative sweep: coupling-free colour per subdomain ((o, a mod
     // (k+2), ...) lexicographic), and per colour c the workgroups
     // mwave_ptr[c] .. mwave_ptr[c+1] of the lane table mlane (mwidth entry
-    // indices per workgroup, -1 unused); built with Problem::multiplicative
-    std::vector<int32_t> mcolor, mwave_ptr, mlane;
+    // indices per workgroup, -1 unused); in workgroup w, entry m of a
+    // subdomain sits mstride[w] threads after entry m - 1 (1: a subdomain's
+    // entries are consecutive; S: S subdomains of one size interleaved, local
+    // row m of all of them on threads m S .. m S + S - 1); built with
+    // Problem::multiplicative
+    std::vector<int32_t> mcolor, mwave_ptr, mlane, mstride;
     // the potential of each subdomain: (orientation, true index x, y, z)
     std::vector<int32_t> ppot;
     int mwidth = 0;            // entries per workgroup of mlane

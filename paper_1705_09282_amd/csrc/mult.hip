@@ -54,6 +54,8 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
             r = sp.F[g] - spmv_row<D, K, WIN, XC, T>(sp, g);
         }
     }
+    // U_g before the barrier: no other thread of the colour writes it
+    const T u0 = e >= 0 ? U[g] : T(0);
     sr[threadIdx.x] = r;
     __syncthreads();
     if (e >= 0) {
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(B) void k_schwarz_mult(MultArgsT<T> a) {
         const T *mrow = a.M + prob * a.sM + info.x;
         T acc = 0;
         for (int c = 0; c < info.z; ++c) acc = fma(mrow[c], loc[c * stride], acc);
-        if (!halt) U[g] += acc;
+        if (!halt) U[g] = u0 + acc;
     }
 }
 

@@ -233,7 +233,7 @@ void plan(dfmg_ctx *c, Arena &A) {
         for (const Hierarchy &Q : c->P) v.sM = std::max(v.sM, (int64_t)Q.lv[l].M.size());
         take_level(A, v, np, v.d, l == 0, h);
         // the multiplicative sweep's rows in lane order (every smoothed level:
-        // 42.9 -> 35.8 ms for the stokes2d batch, measured on one box)
+        // 42.9 -> 35.8 ms per solve of the 256^2 four-problem batch)
         if (c->mult() && l > 0) {
             v.mslots = 0;
             for (int R = 0; R < h.nblk; ++R) v.mslots = std::max(v.mslots, h.nslots[R]);

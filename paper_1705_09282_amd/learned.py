@@ -432,10 +432,11 @@ def measured_worst_plain(solver, tol=1e-8, seed=0):
 
 
 def fallback_thresholds(model, solver):
-    """Per problem: the threshold of the nearest training points, or on a
-    mapped domain (whose geometry the features do not describe, and whose
-    plain rate differs from the unit square's) the measured one."""
-    if getattr(solver, "geometry", 0):
+    """Per problem: the threshold of the nearest training points (2D, unit
+    square), or the measured one where the features do not describe the
+    problem and its plain rate differs: a mapped domain, or a 3D problem of a
+    Solver or BatchSolver."""
+    if getattr(solver, "geometry", 0) or (not hasattr(solver, "meshes") and getattr(solver, "dim", 2) == 3):
         return measured_worst_plain(solver)
     return rho_plain_for(model, problem_features(solver))
 

@@ -10,9 +10,9 @@ import pytest
 from paper_1705_09282_amd import learned
 
 
-def fake_solver(geometry=0, nus=(1.0, 0.1), sigmas=(1.0, 100.0), cs=(0.0, 0.0)):
+def fake_solver(geometry=0, nus=(1.0, 0.1), sigmas=(1.0, 100.0), cs=(0.0, 0.0), dim=2):
     return SimpleNamespace(geometry=geometry, adv_kind=None, nus=list(nus), sigmas=list(sigmas), cs=list(cs),
-                           n_elem=64, k=2, dim=2)
+                           n_elem=64, k=2, dim=dim)
 
 
 def test_rho_plain_for_takes_the_largest_of_the_nearest():
@@ -42,9 +42,10 @@ def test_fallback_thresholds_square_uses_training_points(monkeypatch):
     assert ((got > 0) & (got < 1)).all()
 
 
-def test_fallback_thresholds_mapped_domain_is_measured(monkeypatch):
+@pytest.mark.parametrize("geometry,dim", [(1, 2), (1, 3), (0, 3)])
+def test_fallback_thresholds_mapped_or_3d_is_measured(monkeypatch, geometry, dim):
     model = learned.load(learned.CHEB_WEIGHTS)
-    s = fake_solver(geometry=1)
+    s = fake_solver(geometry=geometry, dim=dim)
     calls = []
 
     def measured(solver):

@@ -343,3 +343,33 @@ def test_schedule_in_3d_cuts_cycles():
     assert st["converged"] and 2 * st["cycles"] < plain["cycles"]
     assert s.div_norm(U) < 1e-10
     s.close()
+
+
+def test_learned_schedule_3d_measures_its_threshold():
+    """The network is trained on 2D problems and its inputs carry no
+    dimension, so a 3D batch runs it with fallback thresholds measured on the
+    batch (the fixed damping's worst cycle ratio).  The FP32-refined solve
+    then converges to the fixed damping's solution, in no more cycles."""
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    from paper_1705_09282_amd import learned
+    print("\n[case] 3D 8^3 k=1 L=3, sigma 1 and 1e3, learned schedule", flush=True)
+    B = BatchSolver(3, 8, 3, 1, [1.0, 1.0], [1.0, 1e3], precision=1, max_cycles=200).bind()
+    F = torch.tensor(B.manufactured_rhs(), device="cuda")
+    U = torch.zeros_like(F)
+    plain = B.solve(F, U)
+    Up = host(U)
+    thr = learned.measured_worst_plain(B)
+    learned.apply_chebyshev(B)
+    U.zero_()
+    st = B.solve(F, U)
+    got = host(U)
+    n, nv = B.n, B.sizes()["n_vel"]
+    print(f"[3d] thresholds {thr.round(3)}; cycles plain {[x['cycles'] for x in plain]} learned "
+          f"{[x['cycles'] for x in st]} fallback {[x['fallback'] for x in st]}", flush=True)
+    assert ((thr > 0) & (thr < 1)).all()
+    for p in range(2):
+        assert st[p]["converged"] and st[p]["cycles"] <= plain[p]["cycles"]
+        sl = slice(p * n, p * n + nv)
+        assert np.linalg.norm(got[sl] - Up[sl]) <= 1e-6 * np.linalg.norm(Up[sl])
+    assert B.div_norm(U).max() < 1e-10
+    B.close()

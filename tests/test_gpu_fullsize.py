@@ -112,6 +112,39 @@ def test_oseen2d_full_size_learned_vs_fixed():
     B.close()
 
 
+
+def test_oseen2d_full_size_fp32_learned_constant_damping():
+    """The learned-damping Oseen workload as the benchmark runs it: the twelve
+    128^2 problems as one batch, autotuned, FP32 V-cycles inside FP64
+    refinement with the network's constant dampings and steps.  Every problem
+    converges without a fallback, ||div u|| stays at rounding, and the answers
+    of the smallest and largest |a|h/nu meet the tolerance with the oracle's
+    matrix."""
+    from paper_1705_09282_amd import learned
+    from paper_1705_09282_amd.dfmg import BatchSolver
+    probs = [workloads.oseen2d(nu, peh) for nu in workloads.OSEEN2D_NUS for peh in workloads.OSEEN2D_PEH]
+    print("\n[case] oseen2d 128^2 batch, FP32 refinement, learned constant damping", flush=True)
+    B = BatchSolver(2, 128, 6, 2, [p["nu"] for p in probs], [p["sigma"] for p in probs], [p["c"] for p in probs],
+                    precision=1, max_cycles=200).bind()
+    B.autotune(reps=5)
+    learned.apply(B)
+    F = torch.tensor(B.manufactured_rhs(), device="cuda")
+    U = torch.zeros_like(F)
+    st = B.solve(F, U, tol=1e-8)
+    div = B.div_norm(U)
+    print(f"[oseen fp32] cycles {[s['cycles'] for s in st]} fallback {[s['fallback'] for s in st]} "
+          f"max div {div.max():.1e}", flush=True)
+    assert all(s["converged"] and not s["fallback"] for s in st)
+    assert div.max() < 1e-10
+    n = B.n
+    for i in (0, len(probs) - 1):
+        K, Fo = oracle_system(probs[i])
+        Ui = U[i * n:(i + 1) * n].cpu().numpy()
+        res = np.linalg.norm(Fo - K @ Ui) / np.linalg.norm(Fo)
+        print(f"[oseen fp32] problem {i} oracle residual {res:.2e}", flush=True)
+        assert res < 1.05e-8
+    B.close()
+
 def test_streamed_residual_at_1024():
     """Levels whose operator values far exceed the Infinity Cache load them
     non-temporally (one lane per row): the FP64 residual of the 1024^2, k=2

@@ -60,6 +60,7 @@ struct LevelData {
     T *P_v = nullptr, *R_v = nullptr;  // shared by the batch
     T *P_ev = nullptr, *R_ev = nullptr;  // fixed-width forms (when stored)
     T *mval = nullptr;  // multiplicative sweep: the operator rows in lane order (FP64 only)
+    T *msoa = nullptr;  // the small subdomains' inverses interleaved (levels with per-subdomain inverses)
 };
 
 struct DevLevel {
@@ -72,6 +73,7 @@ struct DevLevel {
     int32_t *P_eci = nullptr, *R_eci = nullptr, *inv_ell = nullptr, *inv4_ell = nullptr;
     int32_t *mlane = nullptr;  // lane table of the multiplicative sweep
     int32_t *mstride = nullptr;  // its per-workgroup entry strides
+    bool soa = false;  // the small subdomains' inverses also stored interleaved (msoa)
     int4 *bmesh = nullptr;
     // per problem (form 4): small-subdomain and remaining-subdomain tables
     int4 *sinfo = nullptr;
@@ -232,6 +234,16 @@ void plan(dfmg_ctx *c, Arena &A) {
         v.sM = 0;
         for (const Hierarchy &Q : c->P) v.sM = std::max(v.sM, (int64_t)Q.lv[l].M.size());
         take_level(A, v, np, v.d, l == 0, h);
+        // levels whose inverses are mostly per subdomain (advection, mapped
+        // domains): the small subdomains' inverses also interleaved, so that
+        // a wavefront's loads of them coalesce
+        if (l > 0) {
+            int64_t ncls = 0;
+            for (const Hierarchy &Q : c->P) ncls = std::max(ncls, Q.lv[l].n_class);
+            v.soa = !h.small_list.empty() && 2 * ncls > h.n_patch;
+        }
+        const int64_t nsoa = (int64_t)kSmallPatch * kSmallPatch * (int64_t)h.small_list.size();
+        if (v.soa) v.d.msoa = A.take<double>((size_t)nsoa * np);
         // the multiplicative sweep's rows in lane order (every smoothed level:
         // 42.9 -> 35.8 ms per solve of the 256^2 four-problem batch)
         if (c->mult() && l > 0) {
@@ -242,6 +254,7 @@ void plan(dfmg_ctx *c, Arena &A) {
         }
         if (c->mixed()) {
             take_level(A, v, np, v.f, l == 0, h);
+            if (v.soa) v.f.msoa = A.take<float>((size_t)nsoa * np);
             v.npsi = h.n_psi;
             v.psi = A.take<double>((size_t)h.n_psi * np);
             if (l == 0) {
@@ -438,6 +451,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop,
     a.ent_info = v.ent_info;
     a.delta = v.data<T>().delta;
     a.M = v.data<T>().M;
+    a.msoa = v.soa ? v.data<T>().msoa : nullptr;
     a.r = r;
     a.U = U;
     a.eta = dm.eta ? dm.eta : c->eta + l;
@@ -1490,6 +1504,22 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                 }
                 up(v.ent_info + p * v.nent, info, s);
                 HIPCHK(hipStreamSynchronize(s));  // info is reused for the next problem
+            }
+            if (v.soa) {
+                const size_t ns = h.small_list.size(), kk = (size_t)kSmallPatch * kSmallPatch;
+                std::vector<double> ms(kk * ns);
+                for (int p = 0; p < np; ++p) {
+                    const HostLevel &hp = c->P[p].lv[l];
+                    std::fill(ms.begin(), ms.end(), 0.0);
+                    for (size_t q = 0; q < ns; ++q) {
+                        const int32_t i = h.small_list[q];
+                        if (h.pptr[i + 1] - h.pptr[i] != kSmallPatch) continue;  // read from M instead
+                        for (size_t e = 0; e < kk; ++e) ms[e * ns + q] = hp.M[hp.moff[i] + e];
+                    }
+                    up(v.d.msoa + p * kk * ns, ms, s);
+                    if (c->mixed()) up32(v.f.msoa + p * kk * ns, ms, s);
+                    HIPCHK(hipStreamSynchronize(s));  // ms is refilled for the next problem
+                }
             }
         }
         up(c->eta, c->eta_host, s);

@@ -85,6 +85,11 @@ struct PatchArgsT {
     const int4 *ent_info;  // per problem (stride nent): (M row offset, subdomain start, size, 0)
     T *delta;           // per problem (stride nent): per-entry local corrections
     const T *M;         // per problem (stride sM)
+    // form 4, levels whose inverses are mostly per subdomain: those of the
+    // small subdomains interleaved, entry (row, c) of small subdomain q at
+    // (row * kSmallPatch + c) * nsmall + q, per problem (stride
+    // kSmallPatch^2 * nsmall); nullptr elsewhere
+    const T *msoa;
     const T *r;
     T *U;               // per problem (stride svec)
     const double *eta;  // per problem (stride seta)

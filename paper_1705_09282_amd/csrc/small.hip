@@ -88,12 +88,25 @@ __global__ __launch_bounds__(BS) void k_patch_solve_small(PatchArgsT<T> a, int n
 #pragma unroll
                 for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
         } else if (nn == kSmallPatch) {
+            if (a.msoa) {
+                // per-subdomain inverses, interleaved: each load coalesces
+                const T *ms = a.msoa + (int64_t)prob * kSmallPatch * kSmallPatch * a.nsmall + q;
 #pragma unroll
-            for (int row = 0; row < kSmallPatch; ++row) {
-                T acc = 0;
+                for (int row = 0; row < kSmallPatch; ++row) {
+                    T acc = 0;
 #pragma unroll
-                for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
-                out[row] = acc;
+                    for (int c = 0; c < kSmallPatch; ++c)
+                        acc = fma(ms[(int64_t)(row * kSmallPatch + c) * a.nsmall], rv[c], acc);
+                    out[row] = acc;
+                }
+            } else {
+#pragma unroll
+                for (int row = 0; row < kSmallPatch; ++row) {
+                    T acc = 0;
+#pragma unroll
+                    for (int c = 0; c < kSmallPatch; ++c) acc = fma(m[row * kSmallPatch + c], rv[c], acc);
+                    out[row] = acc;
+                }
             }
             if (store)
 #pragma unroll

@@ -85,6 +85,7 @@ struct DevLevel {
     // potential form of the FP32 cycle (precision 1, 2D)
     double *psi = nullptr, *Ps_v = nullptr;  // psi per problem (FP64: see PatchArgsT)
     float *beta = nullptr, *Q = nullptr;     // per problem
+    float *qsoa = nullptr;  // the small subdomains' potential rows interleaved (with msoa)
     int32_t *qoff = nullptr, *qptr = nullptr, *beta_row = nullptr, *beta_patch = nullptr, *bigbeta = nullptr,
             *qinv_ptr = nullptr, *qinv_pos = nullptr, *Ps_rp = nullptr, *Ps_ci = nullptr;
     int32_t *qinv_ell = nullptr, *Ps_eci = nullptr;
@@ -265,6 +266,7 @@ void plan(dfmg_ctx *c, Arena &A) {
                 for (const Hierarchy &Q : c->P) v.sQ = std::max(v.sQ, (int64_t)Q.lv[l].Q.size());
                 v.beta = A.take<float>((size_t)v.nbeta * np);
                 v.Q = A.take<float>((size_t)v.sQ * np);
+                if (v.soa) v.qsoa = A.take<float>((size_t)kSmallPatch * h.small_list.size() * np);
                 v.Ps_v = A.take<double>(h.Ps_v.size());
                 v.qoff = A.take<int32_t>(h.qoff.size() * np);
                 v.qptr = A.take<int32_t>(h.qptr.size());
@@ -483,6 +485,7 @@ void schwarz(dfmg_ctx *c, int l, const T *r, T *U, bool assign, const int *stop,
         a.psi = v.psi;
         a.beta = reinterpret_cast<T *>(v.beta);
         a.Q = reinterpret_cast<const T *>(v.Q);
+        a.qsoa = v.soa ? reinterpret_cast<const T *>(v.qsoa) : nullptr;
         a.sQ = v.sQ;
         a.nbeta = v.nbeta;
         a.npsi = (int)v.npsi;
@@ -1401,6 +1404,21 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                         up(v.beta_row + p * v.nbeta, c->P[p].lv[l].beta_row, s);
                     }
                     HIPCHK(hipStreamSynchronize(s));
+                    if (v.soa) {
+                        // the single potential row of each full small subdomain, interleaved
+                        const size_t ns = h.small_list.size();
+                        std::vector<double> qs((size_t)kSmallPatch * ns);
+                        for (int p = 0; p < np; ++p) {
+                            const HostLevel &hp = c->P[p].lv[l];
+                            std::fill(qs.begin(), qs.end(), 0.0);
+                            for (size_t q = 0; q < ns; ++q) {
+                                const int32_t i = h.small_list[q];
+                                if (h.pptr[i + 1] - h.pptr[i] != kSmallPatch) continue;  // read from Q instead
+                                for (int e = 0; e < kSmallPatch; ++e) qs[(size_t)e * ns + q] = hp.Q[hp.qoff[i] + e];
+                            }
+                            up32(v.qsoa + p * kSmallPatch * ns, qs, s);  // synchronous
+                        }
+                    }
                     up(v.Ps_v, h.Ps_v, s);
                     up(v.qptr, h.qptr, s);
                     up(v.beta_patch, h.beta_patch, s);

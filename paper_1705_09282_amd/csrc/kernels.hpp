@@ -90,6 +90,10 @@ struct PatchArgsT {
     // (row * kSmallPatch + c) * nsmall + q, per problem (stride
     // kSmallPatch^2 * nsmall); nullptr elsewhere
     const T *msoa;
+    // with msoa in the FP32 cycle: the single potential row of each full
+    // small subdomain, entry c of subdomain q at c * nsmall + q, per problem
+    // (stride kSmallPatch * nsmall)
+    const T *qsoa;
     const T *r;
     T *U;               // per problem (stride svec)
     const double *eta;  // per problem (stride seta)

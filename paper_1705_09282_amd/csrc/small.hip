@@ -130,6 +130,14 @@ __global__ __launch_bounds__(BS) void k_patch_solve_small(PatchArgsT<T> a, int n
                     qdone = true;
                 }
             }
+            if (!qdone && a.qsoa && nn == kSmallPatch) {
+                // per-subdomain maps, interleaved (the order of small_row)
+                const T *qs = a.qsoa + (int64_t)prob * kSmallPatch * a.nsmall + q;
+                v = 0;
+#pragma unroll
+                for (int c = 0; c < kSmallPatch; ++c) v = fma(qs[(int64_t)c * a.nsmall], rv[c], v);
+                qdone = true;
+            }
             if (!qdone) v = small_row(a.Q + prob * a.sQ + si.z, nn, rv);
             if (store) a.beta[prob * a.nbeta + si.w] = v;
         }

@@ -486,9 +486,10 @@ def main():
                     help="only the HBM-resident residual leg (1024^2, one problem)")
     ap.add_argument("--no-hbm-leg", action="store_true", help="skip the HBM-resident residual leg")
     ap.add_argument("--no-paper-legs", action="store_true", help="skip the paper's Oseen problems (context legs)")
-    ap.add_argument("--only", choices=("timed", "multiplicative"), default=None,
-                    help="build and time one path only (for kernel traces): the timed path, or the multiplicative "
-                         "FP64 V(1,2) batch; prints its ms per step and tuning")
+    ap.add_argument("--only", choices=("timed", "multiplicative", "mixed"), default=None,
+                    help="build and time one path only (for kernel traces): the timed path, the multiplicative "
+                         "FP64 V(1,2) batch, or the mixed 256-problem batch with FP32 refinement and the learned "
+                         "schedule; prints its ms per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver runs each problem on a "
@@ -565,6 +566,22 @@ def main():
 
     if args.roofline_hbm_only:
         print(json.dumps({"roofline_hbm": roofline_hbm(dev, reps=200)}), flush=True)
+        return
+
+    if args.only == "mixed":
+        from paper_1705_09282_amd.dfmg import MultiSolver
+        probs = workloads.batch2d()
+        m = MultiSolver([(p["d"], p["N"], p["L"], p["k"]) for p in probs], [p["nu"] for p in probs],
+                        [p["sigma"] for p in probs], [p["c"] for p in probs], precision=1).bind(dev)
+        m.autotune()
+        learned.apply_chebyshev(m)
+        F = torch.tensor(m.manufactured_rhs(), device=dev)
+        U = torch.zeros_like(F)
+        T, st = run(m, F, U)
+        print(json.dumps({"path": "mixed", "ms_per_step": 1e3 * T / args.steps, "mesh_groups": m.n_groups,
+                          "cycles_max": max(x["cycles"] for x in st), "steps": args.steps,
+                          "warmup": args.warmup}), flush=True)
+        m.close()
         return
 
     if args.only:

@@ -1524,19 +1524,27 @@ int dfmg_bind(dfmg_ctx *c, void *ws, size_t bytes, void *stream) {
                 HIPCHK(hipStreamSynchronize(s));  // info is reused for the next problem
             }
             if (v.soa) {
+                // chunks of W coefficients of a row (16 bytes: W = 2 in FP64, 4 in
+                // FP32), chunk e / W of subdomain q at ((e / W) * ns + q) * W
                 const size_t ns = h.small_list.size(), kk = (size_t)kSmallPatch * kSmallPatch;
                 std::vector<double> ms(kk * ns);
-                for (int p = 0; p < np; ++p) {
-                    const HostLevel &hp = c->P[p].lv[l];
+                auto fill = [&](const HostLevel &hp, size_t W) {
                     std::fill(ms.begin(), ms.end(), 0.0);
                     for (size_t q = 0; q < ns; ++q) {
                         const int32_t i = h.small_list[q];
                         if (h.pptr[i + 1] - h.pptr[i] != kSmallPatch) continue;  // read from M instead
-                        for (size_t e = 0; e < kk; ++e) ms[e * ns + q] = hp.M[hp.moff[i] + e];
+                        for (size_t e = 0; e < kk; ++e) ms[((e / W) * ns + q) * W + e % W] = hp.M[hp.moff[i] + e];
                     }
+                };
+                for (int p = 0; p < np; ++p) {
+                    const HostLevel &hp = c->P[p].lv[l];
+                    fill(hp, 2);
                     up(v.d.msoa + p * kk * ns, ms, s);
-                    if (c->mixed()) up32(v.f.msoa + p * kk * ns, ms, s);
-                    HIPCHK(hipStreamSynchronize(s));  // ms is refilled for the next problem
+                    HIPCHK(hipStreamSynchronize(s));  // ms is refilled
+                    if (c->mixed()) {
+                        fill(hp, 4);
+                        up32(v.f.msoa + p * kk * ns, ms, s);  // synchronous
+                    }
                 }
             }
         }

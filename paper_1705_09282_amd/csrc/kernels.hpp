@@ -86,9 +86,10 @@ struct PatchArgsT {
     T *delta;           // per problem (stride nent): per-entry local corrections
     const T *M;         // per problem (stride sM)
     // form 4, levels whose inverses are mostly per subdomain: those of the
-    // small subdomains interleaved, entry (row, c) of small subdomain q at
-    // (row * kSmallPatch + c) * nsmall + q, per problem (stride
-    // kSmallPatch^2 * nsmall); nullptr elsewhere
+    // small subdomains interleaved in 16-byte chunks (W = 16 / sizeof(T)
+    // coefficients), entry e = row * kSmallPatch + c of small subdomain q at
+    // ((e / W) * nsmall + q) * W + e % W, per problem (stride kSmallPatch^2 *
+    // nsmall); nullptr elsewhere
     const T *msoa;
     // with msoa in the FP32 cycle: the single potential row of each full
     // small subdomain, entry c of subdomain q at c * nsmall + q, per problem

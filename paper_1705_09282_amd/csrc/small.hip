@@ -89,14 +89,27 @@ __global__ __launch_bounds__(BS) void k_patch_solve_small(PatchArgsT<T> a, int n
                 for (int row = 0; row < kSmallPatch; ++row) delta[(int64_t)row * a.nsmall + q] = out[row];
         } else if (nn == kSmallPatch) {
             if (a.msoa) {
-                // per-subdomain inverses, interleaved: each load coalesces
-                const T *ms = a.msoa + (int64_t)prob * kSmallPatch * kSmallPatch * a.nsmall + q;
+                // per-subdomain inverses, interleaved in 16-byte chunks (W
+                // consecutive coefficients of a row): each load coalesces
+                constexpr int W = 16 / (int)sizeof(T), NCH = kSmallPatch / W;
+                const T *ms = a.msoa + (int64_t)prob * kSmallPatch * kSmallPatch * a.nsmall + (int64_t)q * W;
 #pragma unroll
                 for (int row = 0; row < kSmallPatch; ++row) {
                     T acc = 0;
 #pragma unroll
-                    for (int c = 0; c < kSmallPatch; ++c)
-                        acc = fma(ms[(int64_t)(row * kSmallPatch + c) * a.nsmall], rv[c], acc);
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        const T *p4 = ms + (int64_t)(row * NCH + ch) * a.nsmall * W;
+                        T v[W];
+                        if constexpr (W == 4) {
+                            const float4 x = *reinterpret_cast<const float4 *>(p4);
+                            v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+                        } else {
+                            const double2 x = *reinterpret_cast<const double2 *>(p4);
+                            v[0] = x.x, v[1] = x.y;
+                        }
+#pragma unroll
+                        for (int j = 0; j < W; ++j) acc = fma(v[j], rv[ch * W + j], acc);
+                    }
                     out[row] = acc;
                 }
             } else {
